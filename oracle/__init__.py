@@ -1,0 +1,208 @@
+"""FP64 CPU oracle for visual-sphere perspective-map rasterization.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg are the only callers.  The arithmetic lives in
+``vsr_oracle.c`` (plain C, double precision, one pixel x one triangle at a
+time); this module compiles it with gcc and marshals numpy arrays.  It
+imports nothing from the HIP library and the HIP library imports nothing
+from here.
+
+Per-pixel flags returned by :func:`render`:
+  FLAG_EDGE    a triangle whose depth is within 1e-5 of the winner's (or
+               that could be hit from behind) passes within 1e-6 rad of one
+               of its edge planes: the id there may legitimately differ in
+               FP32.
+  FLAG_DEPTH   best and second-best covered depths differ by <= 2e-5 * r.
+  FLAG_INVALID the pixel has no view direction (outside the projection).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "vsr_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+NO_HIT = 0xFFFFFFFF
+FLAG_EDGE, FLAG_DEPTH, FLAG_INVALID = 1, 2, 4
+
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm", "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _View(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("aov", ctypes.c_int32),
+                ("k", ctypes.c_double), ("l", ctypes.c_double), ("s", ctypes.c_double),
+                ("omega_deg", ctypes.c_double), ("rot", ctypes.c_double * 9)]
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            lib = ctypes.CDLL(_LIB)
+            dp = ctypes.POINTER(ctypes.c_double)
+            lib.orc_limits.argtypes = [dp, dp, dp, dp]
+            lib.orc_view_coord.argtypes = [ctypes.c_int32] * 5 + [dp, dp]
+            lib.orc_direction.argtypes = [ctypes.c_double] * 6 + [dp]
+            lib.orc_direction.restype = ctypes.c_int
+            lib.orc_pixel_direction.argtypes = [ctypes.POINTER(_View), ctypes.c_int32, ctypes.c_int32, dp]
+            lib.orc_pixel_direction.restype = ctypes.c_int
+            lib.orc_map.argtypes = [ctypes.POINTER(_View), ctypes.c_void_p, ctypes.c_void_p]
+            lib.orc_inverse.argtypes = [dp] + [ctypes.c_double] * 4 + [dp, dp]
+            lib.orc_triangle.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, dp]
+            lib.orc_cap.argtypes = [dp, dp, dp, dp]
+            lib.orc_render.argtypes = [ctypes.POINTER(_View), ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int32]
+            lib.orc_render.restype = ctypes.c_int
+            lib.orc_pair.argtypes = [ctypes.POINTER(_View), ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_int64, ctypes.c_int64, dp]
+            _lib = lib
+    return _lib
+
+
+def _cview(view) -> _View:
+    v = _View()
+    v.width, v.height, v.aov = int(view.width), int(view.height), int(view.aov)
+    v.k, v.l, v.s, v.omega_deg = float(view.k), float(view.l), float(view.s), float(view.omega_deg)
+    for i, r in enumerate(view.rot):
+        v.rot[i] = float(r)
+    return v
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def limits(k: float, l: float, s: float, omega_deg: float):
+    """Section 2.1.1 parameter limits: returns (k, l, s, omega_deg) clamped."""
+    lib = _load()
+    a = [ctypes.c_double(float(x)) for x in (k, l, s, omega_deg)]
+    lib.orc_limits(*[ctypes.byref(x) for x in a])
+    return tuple(x.value for x in a)
+
+
+def view_coord(i: int, j: int, width: int, height: int, aov: int = 0):
+    lib = _load()
+    x, y = ctypes.c_double(), ctypes.c_double()
+    lib.orc_view_coord(i, j, width, height, aov, ctypes.byref(x), ctypes.byref(y))
+    return x.value, y.value
+
+
+def direction(x: float, y: float, k: float, l: float, s: float, omega_deg: float):
+    """Section 2.1.2 for already-limited parameters: (unit vector, valid)."""
+    lib = _load()
+    out = np.zeros(3)
+    ok = lib.orc_direction(x, y, k, l, s, omega_deg, _dp(out))
+    return out, bool(ok)
+
+
+def inverse(v: Sequence[float], k: float, l: float, s: float, omega_deg: float):
+    """Section 2.1.3 for already-limited parameters: camera vector -> (x, y)."""
+    lib = _load()
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    x, y = ctypes.c_double(), ctypes.c_double()
+    lib.orc_inverse(_dp(vv), k, l, s, omega_deg, ctypes.byref(x), ctypes.byref(y))
+    return x.value, y.value
+
+
+def perspective_map(view):
+    """World-space map: (float64[H, W, 3], bool[H, W] valid)."""
+    lib = _load()
+    d = np.zeros((view.height, view.width, 3), dtype=np.float64)
+    ok = np.zeros((view.height, view.width), dtype=np.uint8)
+    cv = _cview(view)
+    lib.orc_map(ctypes.byref(cv), d.ctypes.data, ok.ctypes.data)
+    return d, ok.astype(bool)
+
+
+def triangle(tris: np.ndarray, t: int) -> dict:
+    """Per-triangle quantities of sections 1.1 and 1.1.4 for triangle t."""
+    lib = _load()
+    tris = np.ascontiguousarray(tris, dtype=np.float32)
+    out = np.zeros(14)
+    lib.orc_triangle(tris.ctypes.data, tris.shape[1], t, _dp(out))
+    return {"n": out[0:9].reshape(3, 3), "N": out[9:12], "d": out[12], "live": bool(out[13])}
+
+
+def cap(a, b, c):
+    """Section 1.1.2 smallest circle: (S_hat[3], |S|)."""
+    lib = _load()
+    arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (a, b, c)]
+    out = np.zeros(4)
+    lib.orc_cap(_dp(arr[0]), _dp(arr[1]), _dp(arr[2]), _dp(out))
+    return out[:3].copy(), float(out[3])
+
+
+@dataclass
+class RenderResult:
+    id: np.ndarray       # uint32, NO_HIT where nothing is covered
+    depth: np.ndarray    # float64, +inf where nothing is covered
+    depth2: np.ndarray   # float64 second-nearest covered depth
+    cover: np.ndarray    # uint32 number of covering triangles
+    flags: np.ndarray    # uint8 FLAG_* bits
+
+
+def render(view, tris: np.ndarray, pixels: Optional[np.ndarray] = None,
+           threads: Optional[int] = None) -> RenderResult:
+    """Brute-force FP64 render of the listed flat pixel indices (j*W+i), or
+    of the whole frame (arrays shaped [H, W]) when ``pixels`` is None."""
+    lib = _load()
+    tris = np.ascontiguousarray(tris, dtype=np.float32)
+    assert tris.ndim == 2 and tris.shape[0] == 9
+    ntri = tris.shape[1]
+    if pixels is None:
+        n = view.width * view.height
+        pix_ptr = None
+    else:
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        n = pixels.shape[0]
+        pix_ptr = pixels.ctypes.data
+    ids = np.empty(n, dtype=np.uint32)
+    depth = np.empty(n, dtype=np.float64)
+    depth2 = np.empty(n, dtype=np.float64)
+    cover = np.empty(n, dtype=np.uint32)
+    flags = np.empty(n, dtype=np.uint8)
+    threads = threads or os.cpu_count() or 1
+    cv = _cview(view)
+    rc = lib.orc_render(ctypes.byref(cv), tris.ctypes.data, ntri, pix_ptr, n, ids.ctypes.data,
+                        depth.ctypes.data, depth2.ctypes.data, cover.ctypes.data, flags.ctypes.data,
+                        int(threads))
+    if rc != 0:
+        raise MemoryError("oracle render failed")
+    res = RenderResult(ids, depth, depth2, cover, flags)
+    if pixels is None:
+        for f in ("id", "depth", "depth2", "cover", "flags"):
+            setattr(res, f, getattr(res, f).reshape(view.height, view.width))
+    return res
+
+
+def pair(view, tris: np.ndarray, t: int, p: int):
+    """(oriented edge values[3], r, pixel valid) of one pixel-triangle pair."""
+    lib = _load()
+    tris = np.ascontiguousarray(tris, dtype=np.float32)
+    out = np.zeros(5)
+    cv = _cview(view)
+    lib.orc_pair(ctypes.byref(cv), tris.ctypes.data, tris.shape[1], int(t), int(p), _dp(out))
+    return out[0:3].copy(), float(out[3]), bool(out[4])

@@ -1,0 +1,437 @@
+/*
+ * FP64 reference oracle for visual-sphere perspective-map rasterization.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or constant with the HIP library and never calls it.
+ *
+ * Every quantity is computed in double precision straight from the paper's
+ * definitions, one pixel and one triangle at a time, with no binning,
+ * blocking or reordering:
+ *
+ *   map      Fober, "Perspective picture from Visual Sphere", section 2
+ *            (remark on normalising texture coordinates per angle-of-view
+ *            type), 2.1.1 (parameter limits) and 2.1.2 (2D->3D transform).
+ *   coverage section 1.1 (dot products of the map vector with the three
+ *            normalised edge cross products, min of step) and 1.1.1 (binary
+ *            step: 1 iff g > 0).
+ *   depth    section 1.1.4 (hard normal N=(A-B)x(C-B); r = A.N / G.N).
+ *   resolve  section 1.4 (depth-pass test: the nearest r wins).
+ *
+ * Readings where the paper is silent or inconsistent (all documented in the
+ * design notes):
+ *   - R = sqrt(x^2 + l*y^2) as in the 2D->3D equation (the inverse in 2.1.3
+ *     uses the same form).
+ *   - pixel (i, j) samples texture coordinate ((i+1/2)/W, (j+1/2)/H); camera
+ *     frame +x right, +y down (row index), +z forward.
+ *   - at R = 0 the factor sin(theta)/R takes its limit.
+ *   - for k < 0 a pixel with |sin(k*Omega/2)*R| > 1 has no direction
+ *     (invalid, never covered).
+ *   - triangle winding is arbitrary: the three edge tests are multiplied by
+ *     sigma = sign(det[A,B,C]); det = 0 covers nothing.
+ *   - ties in depth go to the lower triangle id; no hit gives id 0xFFFFFFFF
+ *     and depth +inf.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_NO_HIT 0xFFFFFFFFu
+#define ORC_FLAG_EDGE 1u    /* within the 1e-6 rad band of a competing edge */
+#define ORC_FLAG_DEPTH 2u   /* best and second-best depth within 2e-5 rel.  */
+#define ORC_FLAG_INVALID 4u /* pixel has no view direction                   */
+
+typedef struct {
+    int32_t width, height, aov;
+    double k, l, s, omega_deg;
+    double rot[9]; /* camera -> world, row-major */
+} orc_view;
+
+static const double ORC_PI = 3.14159265358979323846;
+
+/* ---------------------------------------------------------------------- */
+/* Section 2.1.1: clamp k to [-1,1], l to [0,1], s to [4/5,1] and the angle of
+ * view (degrees) to [1, Omega_max] with Omega_max = (k>0 ? 179 : 180) /
+ * max(|k|, 1/2). */
+void orc_limits(double *k, double *l, double *s, double *omega_deg)
+{
+    double kk = *k < -1.0 ? -1.0 : (*k > 1.0 ? 1.0 : *k);
+    double ll = *l < 0.0 ? 0.0 : (*l > 1.0 ? 1.0 : *l);
+    double ss = *s < 0.8 ? 0.8 : (*s > 1.0 ? 1.0 : *s);
+    double ak = fabs(kk) > 0.5 ? fabs(kk) : 0.5;
+    double om_max = (kk > 0.0 ? 179.0 : 180.0) / ak;
+    double om = *omega_deg < 1.0 ? 1.0 : (*omega_deg > om_max ? om_max : *omega_deg);
+    *k = kk;
+    *l = ll;
+    *s = ss;
+    *omega_deg = om;
+}
+
+/* Section 2, remark on 2D coordinates: centre the texture coordinate and
+ * scale it by the aspect ratio a = W/H according to the angle-of-view type.
+ * aov: 0 horizontal, 1 diagonal, 2 vertical, 3 horizontal 4x3. */
+void orc_view_coord(int32_t i, int32_t j, int32_t width, int32_t height, int32_t aov,
+                    double *x, double *y)
+{
+    double fs = (i + 0.5) / (double)width;
+    double ft = (j + 0.5) / (double)height;
+    double a = (double)width / (double)height;
+    double cx = 2.0 * fs - 1.0, cy = 2.0 * ft - 1.0;
+    switch (aov) {
+    case 1: { /* diagonal: [a, 1] / sqrt(1 + a^2) */
+        double q = sqrt(1.0 + a * a);
+        *x = cx * a / q;
+        *y = cy / q;
+        break;
+    }
+    case 2: /* vertical: [a, 1] */
+        *x = cx * a;
+        *y = cy;
+        break;
+    case 3: /* horizontal 4x3: [a, 1] / (4/3) */
+        *x = cx * a / (4.0 / 3.0);
+        *y = cy / (4.0 / 3.0);
+        break;
+    default: /* horizontal: [1, 1/a] */
+        *x = cx;
+        *y = cy / a;
+        break;
+    }
+}
+
+/* Section 2.1.2: view coordinates (x, y) -> unit direction in the camera
+ * frame.  Parameters must already be limited.  Returns 1 when the pixel has
+ * a direction, 0 when it falls outside the projection's domain (then out is
+ * the zero vector). */
+int orc_direction(double x, double y, double k, double l, double s, double omega_deg,
+                  double out[3])
+{
+    double half = 0.5 * omega_deg * ORC_PI / 180.0; /* Omega/2 in radians */
+    double R = sqrt(x * x + l * y * y);
+    double theta, sin_over_R;
+    double c = l * (1.0 - s) + s; /* anamorphic divisor of the y component */
+    if (k > 0.0) {
+        theta = atan(tan(k * half) * R) / k;
+    } else if (k < 0.0) {
+        double q = sin(k * half) * R;
+        if (q < -1.0 || q > 1.0) {
+            out[0] = out[1] = out[2] = 0.0;
+            return 0;
+        }
+        theta = asin(q) / k;
+    } else {
+        theta = half * R;
+    }
+    if (R > 0.0) {
+        sin_over_R = sin(theta) / R;
+    } else { /* limit of sin(theta(R))/R as R -> 0 */
+        if (k > 0.0)
+            sin_over_R = tan(k * half) / k;
+        else if (k < 0.0)
+            sin_over_R = sin(k * half) / k;
+        else
+            sin_over_R = half;
+    }
+    double v0 = x * sin_over_R;
+    double v1 = y * sin_over_R / c;
+    double v2 = cos(theta);
+    double n = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    out[0] = v0 / n;
+    out[1] = v1 / n;
+    out[2] = v2 / n;
+    return 1;
+}
+
+/* Pixel (i, j) of a view -> world-space unit direction (camera direction
+ * rotated by view->rot).  Limits of section 2.1.1 are applied first. */
+int orc_pixel_direction(const orc_view *v, int32_t i, int32_t j, double g[3])
+{
+    double k = v->k, l = v->l, s = v->s, om = v->omega_deg;
+    double x, y, cam[3];
+    orc_limits(&k, &l, &s, &om);
+    orc_view_coord(i, j, v->width, v->height, v->aov, &x, &y);
+    int ok = orc_direction(x, y, k, l, s, om, cam);
+    for (int r = 0; r < 3; ++r)
+        g[r] = v->rot[3 * r + 0] * cam[0] + v->rot[3 * r + 1] * cam[1] + v->rot[3 * r + 2] * cam[2];
+    return ok;
+}
+
+/* Whole map: dirs[(j*W+i)*3 + c], valid[j*W+i]. */
+void orc_map(const orc_view *v, double *dirs, uint8_t *valid)
+{
+    for (int32_t j = 0; j < v->height; ++j)
+        for (int32_t i = 0; i < v->width; ++i) {
+            int64_t p = (int64_t)j * v->width + i;
+            valid[p] = (uint8_t)orc_pixel_direction(v, i, j, dirs + 3 * p);
+        }
+}
+
+/* Section 2.1.3: camera-frame unit vector -> view coordinates (x, y).
+ * The paper states it as the reverse of 2.1.2; it is exact when
+ * l*(1-s)+s = 1.  Parameters must already be limited. */
+void orc_inverse(const double v[3], double k, double l, double s, double omega_deg,
+                 double *x, double *y)
+{
+    double half = 0.5 * omega_deg * ORC_PI / 180.0;
+    double theta = acos(v[2] / sqrt(v[0] * v[0] + l * v[1] * v[1] + v[2] * v[2]));
+    double R;
+    if (k > 0.0)
+        R = tan(k * theta) / tan(k * half);
+    else if (k < 0.0)
+        R = sin(k * theta) / sin(k * half);
+    else
+        R = theta / half;
+    double q = sqrt(v[0] * v[0] + l * v[1] * v[1]);
+    double f = q > 0.0 ? R / q : 0.0;
+    *x = v[0] * f;
+    *y = v[1] * f * (l * (1.0 - s) + s);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Per-triangle quantities.                                                */
+
+static void cross3(const double a[3], const double b[3], double o[3])
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+typedef struct {
+    double n[3][3]; /* sigma * normalised A x B, B x C, C x A (section 1.1)  */
+    double N[3];    /* hard normal (A-B) x (C-B) (section 1.1.4)             */
+    double d;       /* A . N                                                 */
+    int live;       /* 0 when det[A,B,C] = 0: covers nothing                 */
+} orc_tri;
+
+static void load_vertex(const float *soa, int64_t ntri, int64_t t, int v, double out[3])
+{
+    out[0] = (double)soa[(3 * v + 0) * ntri + t];
+    out[1] = (double)soa[(3 * v + 1) * ntri + t];
+    out[2] = (double)soa[(3 * v + 2) * ntri + t];
+}
+
+static void tri_prepare(const float *soa, int64_t ntri, int64_t t, orc_tri *o)
+{
+    double A[3], B[3], C[3], AB[3], BC[3], CA[3], BxC[3], AmB[3], CmB[3];
+    load_vertex(soa, ntri, t, 0, A);
+    load_vertex(soa, ntri, t, 1, B);
+    load_vertex(soa, ntri, t, 2, C);
+    cross3(A, B, AB);
+    cross3(B, C, BC);
+    cross3(C, A, CA);
+    cross3(B, C, BxC);
+    double det = dot3(A, BxC);
+    for (int r = 0; r < 3; ++r) {
+        AmB[r] = A[r] - B[r];
+        CmB[r] = C[r] - B[r];
+    }
+    cross3(AmB, CmB, o->N);
+    o->d = dot3(A, o->N);
+    o->live = det != 0.0;
+    double sigma = det > 0.0 ? 1.0 : -1.0;
+    const double *e[3] = {AB, BC, CA};
+    for (int i = 0; i < 3; ++i) {
+        double len = sqrt(dot3(e[i], e[i]));
+        if (len == 0.0)
+            o->live = 0;
+        for (int r = 0; r < 3; ++r)
+            o->n[i][r] = len > 0.0 ? sigma * e[i][r] / len : 0.0;
+    }
+}
+
+/* Exported for tests: the prepared quantities of triangle t.
+ * out[0..8] oriented unit edge normals, out[9..11] N, out[12] d, out[13] live. */
+void orc_triangle(const float *soa, int64_t ntri, int64_t t, double out[14])
+{
+    orc_tri o;
+    tri_prepare(soa, ntri, t, &o);
+    for (int i = 0; i < 3; ++i)
+        for (int r = 0; r < 3; ++r)
+            out[3 * i + r] = o.n[i][r];
+    out[9] = o.N[0];
+    out[10] = o.N[1];
+    out[11] = o.N[2];
+    out[12] = o.d;
+    out[13] = o.live;
+}
+
+/* Section 1.1.2: smallest circle around the sphere-projected vertices.
+ * Circumcentre from barycentric weights a^2(b^2+c^2-a^2) ...; when a weight
+ * is <= 0 the triangle is obtuse there and the midpoint of the opposite edge
+ * is used.  out = (S_hat, |S|); |S| is the cosine of the cap's radius. */
+void orc_cap(const double A[3], const double B[3], const double C[3], double out[4])
+{
+    double a[3], b[3], c[3], S[3];
+    double la = sqrt(dot3(A, A)), lb = sqrt(dot3(B, B)), lc = sqrt(dot3(C, C));
+    for (int r = 0; r < 3; ++r) {
+        a[r] = A[r] / la;
+        b[r] = B[r] / lb;
+        c[r] = C[r] / lc;
+    }
+    double d_bc[3], d_ca[3], d_ab[3];
+    for (int r = 0; r < 3; ++r) {
+        d_bc[r] = b[r] - c[r];
+        d_ca[r] = c[r] - a[r];
+        d_ab[r] = a[r] - b[r];
+    }
+    double a2 = dot3(d_bc, d_bc), b2 = dot3(d_ca, d_ca), c2 = dot3(d_ab, d_ab);
+    double ws = a2 * (b2 + c2 - a2);
+    double wt = b2 * (c2 + a2 - b2);
+    double wp = c2 * (a2 + b2 - c2);
+    if (ws <= 0.0) {
+        for (int r = 0; r < 3; ++r) S[r] = 0.5 * (b[r] + c[r]);
+    } else if (wt <= 0.0) {
+        for (int r = 0; r < 3; ++r) S[r] = 0.5 * (c[r] + a[r]);
+    } else if (wp <= 0.0) {
+        for (int r = 0; r < 3; ++r) S[r] = 0.5 * (a[r] + b[r]);
+    } else {
+        double w = ws + wt + wp;
+        for (int r = 0; r < 3; ++r) S[r] = (ws * a[r] + wt * b[r] + wp * c[r]) / w;
+    }
+    double len = sqrt(dot3(S, S));
+    out[0] = S[0] / len;
+    out[1] = S[1] / len;
+    out[2] = S[2] / len;
+    out[3] = len;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Brute-force render: every listed pixel against every triangle.           */
+
+typedef struct {
+    const orc_view *v;
+    const orc_tri *tris;
+    int64_t ntri;
+    const int64_t *pix; /* NULL: all pixels in row-major order */
+    int64_t npix;
+    uint32_t *id;
+    double *depth;
+    double *depth2;
+    uint32_t *cover;
+    uint8_t *flags;
+    int64_t begin, end; /* first pixel and stride */
+} orc_job;
+
+/* sin(1e-6): half-width of the edge band in which FP32 and FP64 coverage may
+ * legitimately differ. */
+static const double BAND = 9.999999999998333e-07;
+
+static void render_pixel(const orc_job *jb, int64_t q)
+{
+    int64_t p = jb->pix ? jb->pix[q] : q;
+    int32_t i = (int32_t)(p % jb->v->width), j = (int32_t)(p / jb->v->width);
+    double g[3];
+    int ok = orc_pixel_direction(jb->v, i, j, g);
+    uint32_t best_id = ORC_NO_HIT, count = 0;
+    double best = INFINITY, second = INFINITY;
+    double band_min = INFINITY; /* nearest depth of a triangle in the band */
+    int band_any = 0;           /* some band triangle with non-positive r  */
+    if (ok) {
+        for (int64_t t = 0; t < jb->ntri; ++t) {
+            const orc_tri *tr = &jb->tris[t];
+            if (!tr->live)
+                continue;
+            double e0 = dot3(tr->n[0], g), e1 = dot3(tr->n[1], g), e2 = dot3(tr->n[2], g);
+            double gn = dot3(g, tr->N);
+            double r = tr->d / gn;
+            if (e0 > 0.0 && e1 > 0.0 && e2 > 0.0) { /* bstep on all three edges */
+                ++count;
+                if (r < best || (r == best && (uint32_t)t < best_id)) {
+                    second = best;
+                    best = r;
+                    best_id = (uint32_t)t;
+                } else if (r < second) {
+                    second = r;
+                }
+            }
+            double m0 = fabs(e0), m1 = fabs(e1), m2 = fabs(e2);
+            double mn = m0 < m1 ? (m0 < m2 ? m0 : m2) : (m1 < m2 ? m1 : m2);
+            if (mn < BAND && e0 > -BAND && e1 > -BAND && e2 > -BAND) {
+                if (r > 0.0 && gn != 0.0) {
+                    if (r < band_min)
+                        band_min = r;
+                } else {
+                    band_any = 1;
+                }
+            }
+        }
+    }
+    uint8_t f = 0;
+    if (!ok)
+        f |= ORC_FLAG_INVALID;
+    if (band_any || (band_min < INFINITY && (best_id == ORC_NO_HIT || band_min <= best * (1.0 + 1e-5))))
+        f |= ORC_FLAG_EDGE;
+    if (best_id != ORC_NO_HIT && second < INFINITY && second - best <= 2e-5 * best)
+        f |= ORC_FLAG_DEPTH;
+    jb->id[q] = best_id;
+    if (jb->depth) jb->depth[q] = best;
+    if (jb->depth2) jb->depth2[q] = second;
+    if (jb->cover) jb->cover[q] = count;
+    if (jb->flags) jb->flags[q] = f;
+}
+
+static void *render_range(void *arg)
+{
+    orc_job *jb = (orc_job *)arg;
+    for (int64_t q = jb->begin; q < jb->npix; q += jb->end)
+        render_pixel(jb, q);
+    return NULL;
+}
+
+/* Render the listed pixels (pix = NULL: the whole W*H frame, row-major).
+ * Outputs are indexed like pix; depth2, cover and flags may be NULL.
+ * Returns 0 on success, -1 on allocation failure. */
+int orc_render(const orc_view *v, const float *xyz_soa, int64_t ntri, const int64_t *pix,
+               int64_t npix, uint32_t *id, double *depth, double *depth2, uint32_t *cover,
+               uint8_t *flags, int32_t nthreads)
+{
+    if (!pix)
+        npix = (int64_t)v->width * v->height;
+    orc_tri *tris = (orc_tri *)malloc(sizeof(orc_tri) * (size_t)(ntri > 0 ? ntri : 1));
+    if (!tris)
+        return -1;
+    for (int64_t t = 0; t < ntri; ++t)
+        tri_prepare(xyz_soa, ntri, t, &tris[t]);
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    pthread_t th[256];
+    orc_job jobs[256];
+    /* thread w renders pixels w, w + nthreads, w + 2*nthreads, ... */
+    for (int w = 0; w < nthreads; ++w) {
+        orc_job jb = {v, tris, ntri, pix, npix, id, depth, depth2, cover, flags, w, nthreads};
+        jobs[w] = jb;
+    }
+    for (int w = 1; w < nthreads; ++w)
+        pthread_create(&th[w], NULL, render_range, &jobs[w]);
+    render_range(&jobs[0]);
+    for (int w = 1; w < nthreads; ++w)
+        pthread_join(th[w], NULL);
+    free(tris);
+    return 0;
+}
+
+/* One (pixel, triangle) pair: out[0..2] oriented edge values n_i . g,
+ * out[3] r = d / (g . N), out[4] pixel valid. */
+void orc_pair(const orc_view *v, const float *xyz_soa, int64_t ntri, int64_t t, int64_t p,
+              double out[5])
+{
+    orc_tri tr;
+    double g[3];
+    tri_prepare(xyz_soa, ntri, t, &tr);
+    int ok = orc_pixel_direction(v, (int32_t)(p % v->width), (int32_t)(p / v->width), g);
+    out[0] = dot3(tr.n[0], g);
+    out[1] = dot3(tr.n[1], g);
+    out[2] = dot3(tr.n[2], g);
+    out[3] = tr.d / dot3(g, tr.N);
+    out[4] = ok;
+}
