@@ -1,0 +1,196 @@
+/*
+ * vsr — visual-sphere perspective-map rasterization on AMD Instinct MI355X
+ * (gfx950).  C ABI of libvsr.so.
+ *
+ * The method (J. M. Fober, "Perspective picture from Visual Sphere: a new
+ * approach to image rasterization"): every pixel of a picture owns a unit
+ * view direction G taken from a perspective vector map (section 2.1.2,
+ * Universal Perspective model with parameters k, l, s and angle of view
+ * Omega).  A triangle ABC seen from the projection origin O covers the
+ * pixel when G lies on the inner side of the three great-circle planes
+ * through O that contain its edges, i.e. when G.(AxB), G.(BxC), G.(CxA) all
+ * pass the binary step (sections 1.1 and 1.1.1).  The covered fragment's
+ * depth is the ray-plane distance r = A.N / G.N with N the triangle's hard
+ * normal (section 1.1.4), and the nearest depth wins (depth-pass test,
+ * section 1.4).
+ *
+ * Conventions shared by every call
+ *   - All buffer pointers are DEVICE pointers owned by the caller.  The
+ *     library never allocates or frees device memory and keeps no device
+ *     state between calls.  Buffer sizes come from the vsr_*_bytes()
+ *     functions; buffers must be 256-byte aligned.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Every call only enqueues work on it and returns; results are ready
+ *     when the stream is synchronised.
+ *   - Return value: VSR_OK (0) or a negative VSR_E_* code; on error nothing
+ *     has been enqueued and vsr_last_error() describes the cause (the text
+ *     is per thread).  No C++ exception crosses this ABI.
+ *   - Output images are row-major, top row first: pixel (i, j) (column i,
+ *     row j) is element j*width + i.
+ *   - Triangle ids are column indices of the input vertex array.
+ *   - Calls on distinct streams with distinct buffers may run concurrently.
+ */
+#ifndef VSR_H
+#define VSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define VSR_OK 0
+#define VSR_E_ARG (-1)   /* null pointer, bad size or dimension, misaligned   */
+#define VSR_E_SPACE (-2) /* a buffer is smaller than its vsr_*_bytes() size    */
+#define VSR_E_RANGE (-3) /* view parameters outside the limits (VSR_STRICT)    */
+#define VSR_E_HIP (-4)   /* the HIP runtime refused a launch                   */
+
+/* map storage formats */
+#define VSR_MAP_F32 0   /* three float planes (x, y, z): 12 bytes per pixel   */
+#define VSR_MAP_OCT16 1 /* octahedral unit vector, two fp16: 4 bytes per pixel */
+
+/* vsr_build_map flags */
+#define VSR_STRICT 1u /* reject parameters outside the limits instead of clamping */
+
+/* angle-of-view types (section 2, remark on normalising 2D coordinates) */
+#define VSR_AOV_HORIZONTAL 0
+#define VSR_AOV_DIAGONAL 1
+#define VSR_AOV_VERTICAL 2
+#define VSR_AOV_HORIZONTAL_4X3 3
+
+/* vsr_bin flags */
+#define VSR_BIN_ALL 1u /* list every live triangle in every tile (no culling) */
+
+#define VSR_NO_HIT 0xFFFFFFFFu /* tri_id of a pixel that nothing covers */
+
+/* Edge of the square pixel tiles that maps, bins and the rasterizer use. */
+#define VSR_TILE 8
+
+/* One view request (host memory).
+ *   width, height  picture size in pixels, 1..32768 each.
+ *   aov            VSR_AOV_* angle-of-view type.
+ *   k, l, s        Universal Perspective projection type, cylindricity and
+ *                  anamorphic correction (section 2.1.1).
+ *   omega_deg      angle of view in degrees.
+ *   rot            camera->world rotation, row-major 3x3; the camera looks
+ *                  along +z with +x right and +y down the picture. */
+typedef struct {
+    int32_t width, height, aov, reserved;
+    float k, l, s, omega_deg;
+    float rot[9];
+} vsr_view;
+
+/* ------------------------------------------------------------- sizing */
+
+/* Bytes of a perspective map of a width x height view in format fmt
+ * (VSR_MAP_*), including its per-tile bounding caps.  <0 on bad input. */
+int64_t vsr_map_bytes(int32_t width, int32_t height, int32_t fmt);
+
+/* Bytes of the setup buffer for ntri triangles (records, bounding caps,
+ * direction index and the scratch space the setup sorts use).  <0 on bad
+ * input. */
+int64_t vsr_setup_bytes(int64_t ntri);
+
+/* Bytes of the bin buffer of a width x height view with lists of at most
+ * bin_depth triangles per tile (1..8192).  <0 on bad input. */
+int64_t vsr_bin_bytes(int32_t width, int32_t height, int32_t bin_depth);
+
+/* ------------------------------------------------------------ pipeline */
+
+/* Step 1 — perspective vector map (sections 2, 2.1.1, 2.1.2).
+ * Applies the parameter limits of section 2.1.1 (or, with VSR_STRICT,
+ * returns VSR_E_RANGE when a parameter is outside them), computes the unit
+ * world direction of every pixel centre ((i+1/2)/W, (j+1/2)/H), and the
+ * bounding cap of every tile.  Pixels outside the projection's domain
+ * (k < 0 with |sin(k*Omega/2)*R| > 1) get no direction and are never
+ * covered.
+ *   v           view (host).
+ *   fmt         VSR_MAP_F32 or VSR_MAP_OCT16.
+ *   map         device buffer of vsr_map_bytes(width, height, fmt) bytes.
+ *   v_effective optional host output: the view after clamping. */
+int vsr_build_map(const vsr_view* v, int32_t fmt, uint32_t flags, void* map, int64_t map_bytes,
+                  vsr_view* v_effective, void* stream);
+
+/* Copy a map's directions out to a row-major device array
+ * out[(j*width + i)*3 + c] (float; all zero for a pixel without a direction),
+ * decoding VSR_MAP_OCT16.  For inspection and tests; not on the hot path. */
+int vsr_map_unpack(const vsr_view* v, int32_t fmt, const void* map, float* out, void* stream);
+
+/* Step 2 — per-triangle setup (sections 1.1, 1.1.2, 1.1.4).
+ *   xyz     device float[9][ntri] structure of arrays: rows ax, ay, az, bx,
+ *           by, bz, cx, cy, cz; vertices relative to the projection origin.
+ *   setup   device buffer of vsr_setup_bytes(ntri) bytes; it receives the
+ *           oriented unit edge-plane normals, the oriented unit plane normal
+ *           and plane distance, a bounding cap (section 1.1.2) and a depth
+ *           lower bound per triangle, sorted nearest first, plus a
+ *           multi-level cube-map index of the caps.
+ * Triangles whose plane passes through O (det[A,B,C] = 0 in FP32, to a
+ * relative 1e-7) cover nothing.  The setup depends only on the vertices, so
+ * one setup serves every view rendered from the same origin. */
+int vsr_setup_tris(const float* xyz, int64_t ntri, void* setup, int64_t setup_bytes, void* stream);
+
+/* Step 3 — conservative binning (the coarse "once per region" test of
+ * section 1.1.3, made conservative).  For every tile of the map it lists
+ * the triangles whose bounding cap meets the tile's cap and whose three edge
+ * planes do not exclude the whole tile, nearest first.  A tile with more
+ * than bin_depth candidates is marked overflowed; vsr_raster then gathers
+ * its candidates itself, so overflow costs time, never pixels.
+ *   v, fmt, map  the map built by vsr_build_map for this view.
+ *   setup, ntri  the setup buffer of vsr_setup_tris.
+ *   bins         device buffer of vsr_bin_bytes(width, height, bin_depth). */
+int vsr_bin(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
+            int32_t bin_depth, uint32_t flags, void* bins, int64_t bin_bytes, void* stream);
+
+/* Step 4 — rasterization with depth test (sections 1.1, 1.1.1, 1.1.4, 1.4).
+ * Every pixel tests its direction against the edge planes of every listed
+ * triangle (strict > 0), takes r = d / (G.N) for covered ones and keeps the
+ * smallest (r, triangle id) pair.
+ *   tri_id  device uint32[height][width]; VSR_NO_HIT where nothing covers.
+ *   depth   device float[height][width]; +inf where nothing covers.  Depth
+ *           is the distance along the unit view direction, not z. */
+int vsr_raster(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
+               const void* bins, int32_t bin_depth, uint32_t* tri_id, float* depth, void* stream);
+
+/* ------------------------------------------------------------- batches */
+
+/* One view of a batch (host memory).  setup/ntri name a resident scene
+ * prepared by vsr_setup_tris; the outputs are caller-owned device images. */
+typedef struct {
+    vsr_view view;
+    const void* setup;
+    int64_t ntri;
+    uint32_t* tri_id;
+    float* depth;
+} vsr_job;
+
+/* Bytes of the workspace vsr_submit needs for these jobs. */
+int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t bin_depth);
+
+/* Step 5 — many views in one pass: builds every job's map, bins and
+ * rasterizes all jobs' tiles with one launch per stage (persistent work
+ * queue over (job, tile) items), so views of different sizes and
+ * parameters share the GPU.  Each job's output is identical, bit for bit,
+ * to rendering it alone with vsr_build_map / vsr_bin / vsr_raster at the
+ * same fmt and bin_depth.
+ *   jobs       host array of njobs jobs (1..4096).
+ *   workspace  device buffer of vsr_submit_bytes(jobs, njobs, fmt,
+ *              bin_depth) bytes; it holds the maps, bins and job table. */
+int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t bin_depth, void* workspace,
+               int64_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------- diagnostics */
+
+/* Host call after the stream has synchronised: number of overflowed tiles
+ * recorded in a bin buffer (or submit workspace).  Reads device memory with
+ * a blocking copy.  Returns VSR_OK or an error code. */
+int vsr_bin_overflow(const void* bins_or_ws, int32_t is_workspace, int64_t* overflowed_tiles);
+
+const char* vsr_strerror(int code);
+const char* vsr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VSR_H */

@@ -158,6 +158,20 @@ int orc_pixel_direction(const orc_view *v, int32_t i, int32_t j, double g[3])
     return ok;
 }
 
+/* 1 when pixel (i, j) lies within 1e-6 of the edge of the projection's
+ * domain (k < 0 and |sin(k*Omega/2)*R| within 1e-6 of 1): there the pixel
+ * may have a direction in one precision and none in another. */
+int orc_domain_edge(const orc_view *v, int32_t i, int32_t j)
+{
+    double k = v->k, l = v->l, s = v->s, om = v->omega_deg, x, y;
+    orc_limits(&k, &l, &s, &om);
+    if (!(k < 0.0))
+        return 0;
+    orc_view_coord(i, j, v->width, v->height, v->aov, &x, &y);
+    double q = sin(k * 0.5 * om * ORC_PI / 180.0) * sqrt(x * x + l * y * y);
+    return fabs(fabs(q) - 1.0) < 1e-6;
+}
+
 /* Whole map: dirs[(j*W+i)*3 + c], valid[j*W+i]. */
 void orc_map(const orc_view *v, double *dirs, uint8_t *valid)
 {
@@ -367,6 +381,8 @@ static void render_pixel(const orc_job *jb, int64_t q)
     uint8_t f = 0;
     if (!ok)
         f |= ORC_FLAG_INVALID;
+    if (orc_domain_edge(jb->v, i, j))
+        f |= ORC_FLAG_EDGE;
     if (band_any || (band_min < INFINITY && (best_id == ORC_NO_HIT || band_min <= best * (1.0 + 1e-5))))
         f |= ORC_FLAG_EDGE;
     if (best_id != ORC_NO_HIT && second < INFINITY && second - best <= 2e-5 * best)

@@ -1,0 +1,252 @@
+// C ABI of libvsr: argument checks, per-view constants, launches.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#pragma once
+#include <stdarg.h>
+
+#include "map.hpp"
+#include "raster.hpp"
+#include "setup.hpp"
+#include "submit.hpp"
+
+using namespace vsr;
+
+static thread_local char g_err[512] = "";
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+static int hip_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return VSR_OK;
+    return fail(VSR_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+static const int32_t kMaxDim = 32768;
+static const int32_t kMaxDepth = 8192;
+
+// Section 2.1.1 limits, in double precision on float inputs.
+static void limit_params(double& k, double& l, double& s, double& om) {
+    k = k < -1.0 ? -1.0 : (k > 1.0 ? 1.0 : k);
+    l = l < 0.0 ? 0.0 : (l > 1.0 ? 1.0 : l);
+    s = s < 0.8 ? 0.8 : (s > 1.0 ? 1.0 : s);
+    double om_max = (k > 0.0 ? 179.0 : 180.0) / fmax(fabs(k), 0.5);
+    om = om < 1.0 ? 1.0 : (om > om_max ? om_max : om);
+}
+
+namespace vsr {
+// Fills the per-view constants; returns VSR_OK or an error code.
+int make_map_params(const vsr_view* v, int32_t fmt, uint32_t flags, MapParams* P, vsr_view* eff) {
+    if (!v) return fail(VSR_E_ARG, "view is NULL");
+    if (v->width < 1 || v->height < 1 || v->width > kMaxDim || v->height > kMaxDim)
+        return fail(VSR_E_ARG, "view size %dx%d outside 1..%d", v->width, v->height, kMaxDim);
+    if (v->aov < 0 || v->aov > 3) return fail(VSR_E_ARG, "unknown angle-of-view type %d", v->aov);
+    if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return fail(VSR_E_ARG, "unknown map format %d", fmt);
+    double k = v->k, l = v->l, s = v->s, om = v->omega_deg;
+    if (!(isfinite(k) && isfinite(l) && isfinite(s) && isfinite(om)))
+        return fail(VSR_E_ARG, "non-finite view parameter");
+    for (int q = 0; q < 9; ++q)
+        if (!isfinite(v->rot[q])) return fail(VSR_E_ARG, "non-finite rotation");
+    double k0 = k, l0 = l, s0 = s, om0 = om;
+    limit_params(k, l, s, om);
+    if ((flags & VSR_STRICT) && (k != k0 || l != l0 || s != s0 || om != om0))
+        return fail(VSR_E_RANGE, "parameters (k=%g l=%g s=%g omega=%g) outside the limits", k0, l0, s0, om0);
+    MapLayout L = map_layout(v->width, v->height, fmt);
+    P->W = v->width;
+    P->H = v->height;
+    P->aov = v->aov;
+    P->fmt = fmt;
+    P->ntx = L.ntx;
+    P->nty = L.nty;
+    const double pi = 3.14159265358979323846;
+    double half = 0.5 * om * pi / 180.0;
+    P->kind = k > 0.0 ? 1 : (k < 0.0 ? -1 : 0);
+    P->k = float(k);
+    P->half = float(half);
+    P->kt = float(k > 0.0 ? tan(k * half) : (k < 0.0 ? sin(k * half) : 0.0));
+    P->sig0 = float(k > 0.0 ? tan(k * half) / k : (k < 0.0 ? sin(k * half) / k : half));
+    P->l = float(l);
+    P->c = float(l * (1.0 - s) + s);
+    double W = v->width, H = v->height;
+    switch (v->aov) {
+    case VSR_AOV_DIAGONAL:  // x = cx*a/sqrt(1+a^2) = (2i+1-W)/hypot(W,H)
+        P->xmul = 1;
+        P->xden = P->yden = float(sqrt(W * W + H * H));
+        break;
+    case VSR_AOV_VERTICAL:  // x = cx*a = (2i+1-W)/H
+        P->xmul = 1;
+        P->xden = P->yden = float(H);
+        break;
+    case VSR_AOV_HORIZONTAL_4X3:  // x = cx*a*3/4 = 3(2i+1-W)/(4H)
+        P->xmul = 3;
+        P->xden = P->yden = float(4.0 * H);
+        break;
+    default:  // horizontal: x = cx, y = cy/a = (2j+1-H)/W
+        P->xmul = 1;
+        P->xden = P->yden = float(W);
+        break;
+    }
+    for (int q = 0; q < 9; ++q) P->rot[q] = v->rot[q];
+    if (eff) {
+        *eff = *v;
+        eff->k = float(k);
+        eff->l = float(l);
+        eff->s = float(s);
+        eff->omega_deg = float(om);
+    }
+    return VSR_OK;
+}
+}  // namespace vsr
+
+extern "C" {
+
+int64_t vsr_map_bytes(int32_t width, int32_t height, int32_t fmt) {
+    if (width < 1 || height < 1 || width > kMaxDim || height > kMaxDim) return VSR_E_ARG;
+    if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return VSR_E_ARG;
+    return map_layout(width, height, fmt).bytes;
+}
+
+int64_t vsr_setup_bytes(int64_t ntri) {
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return VSR_E_ARG;
+    return setup_layout(ntri).bytes;
+}
+
+int64_t vsr_bin_bytes(int32_t width, int32_t height, int32_t bin_depth) {
+    if (width < 1 || height < 1 || width > kMaxDim || height > kMaxDim) return VSR_E_ARG;
+    if (bin_depth < 1 || bin_depth > kMaxDepth) return VSR_E_ARG;
+    return bin_layout(width, height, bin_depth).bytes;
+}
+
+int vsr_build_map(const vsr_view* v, int32_t fmt, uint32_t flags, void* map, int64_t map_bytes, vsr_view* v_eff,
+                  void* stream) {
+    MapParams P;
+    int rc = make_map_params(v, fmt, flags, &P, v_eff);
+    if (rc != VSR_OK) return rc;
+    if (!map || !aligned(map)) return fail(VSR_E_ARG, "map buffer NULL or not 256-byte aligned");
+    int64_t need = map_layout(v->width, v->height, fmt).bytes;
+    if (map_bytes < need) return fail(VSR_E_SPACE, "map buffer %lld < %lld bytes", (long long)map_bytes, (long long)need);
+    return hip_status(launch_build_map(P, map, hipStream_t(stream)), "vsr_build_map");
+}
+
+int vsr_map_unpack(const vsr_view* v, int32_t fmt, const void* map, float* out, void* stream) {
+    if (!v) return fail(VSR_E_ARG, "view is NULL");
+    if (v->width < 1 || v->height < 1 || v->width > kMaxDim || v->height > kMaxDim)
+        return fail(VSR_E_ARG, "view size %dx%d outside 1..%d", v->width, v->height, kMaxDim);
+    if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return fail(VSR_E_ARG, "unknown map format %d", fmt);
+    if (!map || !aligned(map) || !out || (reinterpret_cast<uintptr_t>(out) & 3u))
+        return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    return hip_status(launch_map_unpack(map, v->width, v->height, fmt, out, hipStream_t(stream)), "vsr_map_unpack");
+}
+
+int vsr_setup_tris(const float* xyz, int64_t ntri, void* setup, int64_t setup_bytes, void* stream) {
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri %lld out of range", (long long)ntri);
+    if ((ntri > 0 && !xyz) || !setup || !aligned(setup)) return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if ((reinterpret_cast<uintptr_t>(xyz) & 3u) != 0) return fail(VSR_E_ARG, "vertex array not 4-byte aligned");
+    int64_t need = setup_layout(ntri).bytes;
+    if (setup_bytes < need)
+        return fail(VSR_E_SPACE, "setup buffer %lld < %lld bytes", (long long)setup_bytes, (long long)need);
+    return hip_status(launch_setup(xyz, ntri, setup, hipStream_t(stream)), "vsr_setup_tris");
+}
+
+static int check_view_buffers(const vsr_view* v, int32_t fmt) {
+    if (!v) return fail(VSR_E_ARG, "view is NULL");
+    if (v->width < 1 || v->height < 1 || v->width > kMaxDim || v->height > kMaxDim)
+        return fail(VSR_E_ARG, "view size %dx%d outside 1..%d", v->width, v->height, kMaxDim);
+    if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return fail(VSR_E_ARG, "unknown map format %d", fmt);
+    return VSR_OK;
+}
+
+int vsr_bin(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri, int32_t bin_depth,
+            uint32_t flags, void* bins, int64_t bin_bytes, void* stream) {
+    int rc = check_view_buffers(v, fmt);
+    if (rc != VSR_OK) return rc;
+    if (!map || !setup || !bins || !aligned(map) || !aligned(setup) || !aligned(bins))
+        return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri out of range");
+    if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
+    int64_t need = bin_layout(v->width, v->height, bin_depth).bytes;
+    if (bin_bytes < need) return fail(VSR_E_SPACE, "bin buffer %lld < %lld bytes", (long long)bin_bytes, (long long)need);
+    return hip_status(launch_bin(map, v->width, v->height, fmt, setup, ntri, bin_depth, (flags & VSR_BIN_ALL) != 0,
+                                 bins, hipStream_t(stream)),
+                      "vsr_bin");
+}
+
+int vsr_raster(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri, const void* bins,
+               int32_t bin_depth, uint32_t* tri_id, float* depth, void* stream) {
+    int rc = check_view_buffers(v, fmt);
+    if (rc != VSR_OK) return rc;
+    if (!map || !setup || !bins || !tri_id || !depth || !aligned(map) || !aligned(setup) || !aligned(bins))
+        return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if ((reinterpret_cast<uintptr_t>(tri_id) & 3u) || (reinterpret_cast<uintptr_t>(depth) & 3u))
+        return fail(VSR_E_ARG, "output not 4-byte aligned");
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri out of range");
+    if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
+    return hip_status(launch_raster(map, v->width, v->height, fmt, setup, ntri, bins, bin_depth, tri_id, depth,
+                                    hipStream_t(stream)),
+                      "vsr_raster");
+}
+
+int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t bin_depth) {
+    if (!jobs || njobs < 1 || njobs > 4096) return VSR_E_ARG;
+    if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return VSR_E_ARG;
+    if (bin_depth < 1 || bin_depth > kMaxDepth) return VSR_E_ARG;
+    for (int32_t q = 0; q < njobs; ++q) {
+        const vsr_view& v = jobs[q].view;
+        if (v.width < 1 || v.height < 1 || v.width > kMaxDim || v.height > kMaxDim) return VSR_E_ARG;
+    }
+    return submit_bytes(jobs, njobs, fmt, bin_depth);
+}
+
+int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t bin_depth, void* workspace, int64_t ws_bytes,
+               void* stream) {
+    if (!jobs || njobs < 1 || njobs > 4096) return fail(VSR_E_ARG, "njobs %d outside 1..4096", njobs);
+    if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
+    if (!workspace || !aligned(workspace)) return fail(VSR_E_ARG, "workspace NULL or misaligned");
+    for (int32_t q = 0; q < njobs; ++q) {
+        const vsr_job& J = jobs[q];
+        MapParams P;
+        int rc = make_map_params(&J.view, fmt, 0, &P, nullptr);
+        if (rc != VSR_OK) return rc;
+        if (!J.setup || !aligned(J.setup) || !J.tri_id || !J.depth || J.ntri < 0 || J.ntri > (int64_t(1) << 31))
+            return fail(VSR_E_ARG, "job %d: bad scene or output pointer", q);
+        if ((reinterpret_cast<uintptr_t>(J.tri_id) & 3u) || (reinterpret_cast<uintptr_t>(J.depth) & 3u))
+            return fail(VSR_E_ARG, "job %d: output not 4-byte aligned", q);
+    }
+    int64_t need = submit_bytes(jobs, njobs, fmt, bin_depth);
+    if (ws_bytes < need) return fail(VSR_E_SPACE, "workspace %lld < %lld bytes", (long long)ws_bytes, (long long)need);
+    return hip_status(launch_submit(jobs, njobs, fmt, bin_depth, workspace, hipStream_t(stream)), "vsr_submit");
+}
+
+int vsr_bin_overflow(const void* bins_or_ws, int32_t is_workspace, int64_t* overflowed_tiles) {
+    (void)is_workspace;  // both keep the overflow counter in their first word
+    if (!bins_or_ws || !overflowed_tiles) return fail(VSR_E_ARG, "NULL argument");
+    uint32_t w = 0;
+    hipError_t e = hipMemcpy(&w, bins_or_ws, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_status(e, "vsr_bin_overflow");
+    *overflowed_tiles = w;
+    return VSR_OK;
+}
+
+const char* vsr_strerror(int code) {
+    switch (code) {
+    case VSR_OK: return "ok";
+    case VSR_E_ARG: return "invalid argument";
+    case VSR_E_SPACE: return "buffer too small";
+    case VSR_E_RANGE: return "view parameters outside the limits";
+    case VSR_E_HIP: return "HIP runtime error";
+    default: return "unknown error";
+    }
+}
+
+const char* vsr_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Perspective vector map (Universal Perspective model) and per-tile caps.
+//
+// One wavefront per 8x8 tile, one lane per pixel.  Each lane turns its pixel
+// centre into view coordinates (angle-of-view normalisation, section 2),
+// applies the 2D->3D transform of section 2.1.2 in FP32 with the accurate
+// device math library, rotates the direction into the world frame and
+// stores it tile-major (x, y and z planes, or one octahedral fp16 pair).
+// The wave then reduces the tile's bounding cap: the normalised mean
+// direction and the largest chord to it, widened by a safety margin.
+#pragma once
+#include "vsr_internal.h"
+
+namespace vsr {
+
+// Unit camera direction of pixel (i, j); false when the pixel is outside
+// the projection's domain.
+__device__ inline bool pixel_direction(const MapParams& P, int i, int j, float3& out) {
+    float x = float((2 * i + 1 - P.W) * P.xmul) / P.xden;
+    float y = float((2 * j + 1 - P.H) * P.xmul) / P.yden;
+    float R = sqrtf(fmaf(x, x, P.l * (y * y)));
+    float theta;
+    if (P.kind > 0) {
+        theta = atanf(P.kt * R) / P.k;
+    } else if (P.kind < 0) {
+        float q = P.kt * R;
+        if (q > 1.0f || q < -1.0f) return false;
+        theta = asinf(q) / P.k;
+    } else {
+        theta = P.half * R;
+    }
+    float sn, cs;
+    sincosf(theta, &sn, &cs);
+    float sig = R > 0.0f ? sn / R : P.sig0;
+    float v0 = x * sig, v1 = (y * sig) / P.c, v2 = cs;
+    float inv = 1.0f / sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
+    v0 *= inv;
+    v1 *= inv;
+    v2 *= inv;
+    out = f3(fmaf(P.rot[2], v2, fmaf(P.rot[1], v1, P.rot[0] * v0)),
+             fmaf(P.rot[5], v2, fmaf(P.rot[4], v1, P.rot[3] * v0)),
+             fmaf(P.rot[8], v2, fmaf(P.rot[7], v1, P.rot[6] * v0)));
+    return true;
+}
+
+// Cap of the directions held by the lanes with ok=true (wave-uniform result).
+__device__ inline void tile_cap(float3 g, bool ok, float4& c0, float4& c1) {
+    uint64_t m = __ballot(ok);
+    if (m == 0) {
+        c0 = make_float4(0.f, 0.f, 1.f, 0.f);
+        c1 = make_float4(1.f, 0.f, kCapEmpty, 0.f);
+        return;
+    }
+    float sx = wave_sum(ok ? g.x : 0.f), sy = wave_sum(ok ? g.y : 0.f), sz = wave_sum(ok ? g.z : 0.f);
+    float len = sqrtf(sx * sx + sy * sy + sz * sz);
+    float n = (float)__popcll(m);
+    if (!(len > 1e-3f * n)) {  // directions spread all round: no useful cap
+        c0 = make_float4(0.f, 0.f, 1.f, 1.f);
+        c1 = make_float4(0.f, 1.f, kCapWide, 0.f);
+        return;
+    }
+    float3 c = f3(sx / len, sy / len, sz / len);
+    float3 d = sub3(g, c);
+    float ch2 = wave_max(ok ? d.x * d.x + d.y * d.y + d.z * d.z : 0.f);
+    float rho = 2.0f * asinf(fminf(1.0f, 0.5f * sqrtf(ch2)));
+    rho = rho * (1.0f + kCapRelMargin) + kCapAbsMargin;
+    if (!(rho < kHalfPi)) {
+        c0 = make_float4(c.x, c.y, c.z, 1.f);
+        c1 = make_float4(0.f, 1.f, kCapWide, 0.f);
+        return;
+    }
+    float sh, chh;
+    sincosf(0.5f * rho, &sh, &chh);
+    c0 = make_float4(c.x, c.y, c.z, sh);
+    c1 = make_float4(chh, sinf(rho), 0.f, 0.f);
+}
+
+__device__ inline void build_map_tile(const MapParams& P, void* map, int64_t ntiles, int64_t tile, int lane) {
+    int tx = int(tile % P.ntx), ty = int(tile / P.ntx);
+    int i = tx * kTile + (lane & (kTile - 1)), j = ty * kTile + (lane >> 3);
+    float3 g = f3(0.f, 0.f, 0.f);
+    bool ok = false;
+    if (i < P.W && j < P.H) ok = pixel_direction(P, i, j, g);
+    if (!ok) g = f3(0.f, 0.f, 0.f);
+    int64_t q = tile * kTilePix + lane;
+    if (P.fmt == VSR_MAP_OCT16) {
+        uint32_t w = ok ? oct_encode(g) : kOctInvalid;
+        reinterpret_cast<uint32_t*>(map)[q] = w;
+        g = oct_decode(w);  // the cap must bound what the rasterizer reads
+        ok = (w != kOctInvalid);
+    } else {
+        float* p = reinterpret_cast<float*>(map);
+        int64_t plane = ntiles * kTilePix;
+        p[q] = g.x;
+        p[plane + q] = g.y;
+        p[2 * plane + q] = g.z;
+    }
+    float4 c0, c1;
+    tile_cap(g, ok, c0, c1);
+    if (lane == 0) {
+        MapLayout L = map_layout(P.W, P.H, P.fmt);
+        float4* caps = reinterpret_cast<float4*>(reinterpret_cast<char*>(map) + L.caps_off);
+        caps[2 * tile] = c0;
+        caps[2 * tile + 1] = c1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_build_map(MapParams P, void* map, int64_t ntiles) {
+    int lane = threadIdx.x & 63;
+    int64_t tile = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;
+    build_map_tile(P, map, ntiles, tile, lane);
+}
+
+__global__ __launch_bounds__(256) void k_map_unpack(const void* map, int32_t fmt, int64_t ntiles, int32_t ntx,
+                                                    int32_t W, int32_t H, float* out) {
+    int lane = threadIdx.x & 63;
+    int64_t tile = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;
+    int tx = int(tile % ntx), ty = int(tile / ntx);
+    int i = tx * kTile + (lane & (kTile - 1)), j = ty * kTile + (lane >> 3);
+    if (i >= W || j >= H) return;
+    float3 g = load_dir(map, fmt, ntiles, tile, lane);
+    int64_t o = (int64_t(j) * W + i) * 3;
+    out[o] = g.x;
+    out[o + 1] = g.y;
+    out[o + 2] = g.z;
+}
+
+hipError_t launch_map_unpack(const void* map, int32_t W, int32_t H, int32_t fmt, float* out, hipStream_t st) {
+    MapLayout L = map_layout(W, H, fmt);
+    hipLaunchKernelGGL(k_map_unpack, dim3(unsigned((L.ntiles + 3) / 4)), dim3(256), 0, st, map, fmt, L.ntiles, L.ntx,
+                       W, H, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_map(const MapParams& P, void* map, hipStream_t stream) {
+    MapLayout L = map_layout(P.W, P.H, P.fmt);
+    int64_t blocks = (L.ntiles + 3) / 4;
+    hipLaunchKernelGGL(k_build_map, dim3(unsigned(blocks)), dim3(256), 0, stream, P, map, L.ntiles);
+    return hipGetLastError();
+}
+
+}  // namespace vsr

@@ -1,0 +1,329 @@
+// Per-triangle setup, nearest-first ordering and the cube-map cap index.
+//
+// k_setup_tris (one thread per triangle, coalesced SoA vertex reads):
+//   - the three edge-plane normals A x B, B x C, C x A of section 1.1,
+//     each computed from the edge's endpoints in a canonical (lexicographic)
+//     order as P x (Q - P) and negated when the order was swapped, so the two
+//     triangles sharing an edge get exactly opposite normals;
+//   - orientation: the normals are multiplied by sigma = sign(det[A,B,C]) so
+//     that either winding covers the inside of its cone, never its antipode;
+//   - the hard normal N = (A-B) x (C-B) and d = A.N of section 1.1.4, stored
+//     as a unit normal facing away from O and the plane's distance from O;
+//   - a depth lower bound (the plane distance, rounded down) for the
+//     front-to-back early exit of the rasterizer;
+//   - the smallest-circle cap of section 1.1.2 (bounding cap of the
+//     spherical triangle) and the cube-map cell of its centre at the level
+//     matching its radius.
+// Then a stable LSD radix sort orders triangles by depth lower bound (ties
+// keep id order), records are permuted into that order, and a second
+// stable radix sort groups them by cell so that every cell's list is itself
+// nearest first.  cell_start[b] is the first entry of bucket b.
+#pragma once
+#include "vsr_internal.h"
+
+namespace vsr {
+
+__device__ inline bool vless(float3 a, float3 b) {
+    if (a.x != b.x) return a.x < b.x;
+    if (a.y != b.y) return a.y < b.y;
+    return a.z < b.z;
+}
+
+// Edge-plane normal of edge P->Q, antisymmetric bit for bit: n(P,Q) = -n(Q,P).
+__device__ inline float3 edge_normal(float3 P, float3 Q) {
+    if (vless(P, Q)) return cross3(P, sub3(Q, P));
+    float3 n = cross3(Q, sub3(P, Q));
+    return f3(-n.x, -n.y, -n.z);
+}
+
+// Cube-map cell of a unit direction at level L.
+__device__ inline uint32_t cell_of(float3 s, int L) {
+    float ax = fabsf(s.x), ay = fabsf(s.y), az = fabsf(s.z);
+    int a;
+    float major;
+    if (ax >= ay && ax >= az) {
+        a = 0;
+        major = s.x;
+    } else if (ay >= az) {
+        a = 1;
+        major = s.y;
+    } else {
+        a = 2;
+        major = s.z;
+    }
+    int face = 2 * a + (major < 0.0f ? 1 : 0);
+    float comp[3] = {s.x, s.y, s.z};
+    float am = fabsf(major);
+    float u = comp[(a + 1) % 3] / am, v = comp[(a + 2) % 3] / am;
+    int M = 1 << L;
+    int iu = min(M - 1, max(0, int(floorf((u + 1.0f) * 0.5f * M))));
+    int iv = min(M - 1, max(0, int(floorf((v + 1.0f) * 0.5f * M))));
+    return uint32_t(level_base(L) + int64_t(face) * M * M + int64_t(iv) * M + iu);
+}
+
+__global__ __launch_bounds__(256) void k_setup_tris(const float* __restrict__ xyz, int64_t n,
+                                                    float4* __restrict__ rec_id, float4* __restrict__ cap_id,
+                                                    uint32_t* __restrict__ key, uint32_t* __restrict__ val,
+                                                    uint32_t* __restrict__ bucket) {
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    float3 A = f3(xyz[0 * n + t], xyz[1 * n + t], xyz[2 * n + t]);
+    float3 B = f3(xyz[3 * n + t], xyz[4 * n + t], xyz[5 * n + t]);
+    float3 C = f3(xyz[6 * n + t], xyz[7 * n + t], xyz[8 * n + t]);
+
+    float3 N = cross3(sub3(A, B), sub3(C, B));
+    float d = dot3(A, N);
+    float lenN = sqrtf(dot3(N, N));
+    float lenA = sqrtf(dot3(A, A));
+    float3 e0 = edge_normal(A, B), e1 = edge_normal(B, C), e2 = edge_normal(C, A);
+    float l0 = dot3(e0, e0), l1 = dot3(e1, e1), l2 = dot3(e2, e2);
+    // det[A,B,C] = -A.N: cull when the plane passes (to FP32 accuracy) through O
+    bool live = fabsf(d) > 1e-7f * lenA * lenN && l0 > 0.0f && l1 > 0.0f && l2 > 0.0f;
+
+    float4 r0, r1, r2, r3, c0, c1;
+    uint32_t bkt = uint32_t(kNumBuckets);
+    float lb = __int_as_float(0x7F800000);  // +inf: sorted last
+    if (live) {
+        float sigma = d < 0.0f ? 1.0f : -1.0f;  // sign(det[A,B,C])
+        float s0 = sigma / sqrtf(l0), s1 = sigma / sqrtf(l1), s2 = sigma / sqrtf(l2);
+        float sn = (d > 0.0f ? 1.0f : -1.0f) / lenN;
+        float dist = fabsf(d) / lenN;
+        lb = dist * (1.0f - 1.0f / 65536.0f);
+        r0 = make_float4(e0.x * s0, e0.y * s0, e0.z * s0, N.x * sn);
+        r1 = make_float4(e1.x * s1, e1.y * s1, e1.z * s1, N.y * sn);
+        r2 = make_float4(e2.x * s2, e2.y * s2, e2.z * s2, N.z * sn);
+        r3 = make_float4(dist, lb, __uint_as_float(uint32_t(t)), 0.0f);
+
+        // Smallest circle around the sphere-projected vertices (section 1.1.2).
+        float3 a = scale3(A, 1.0f / lenA);
+        float3 b = scale3(B, 1.0f / sqrtf(dot3(B, B)));
+        float3 c = scale3(C, 1.0f / sqrtf(dot3(C, C)));
+        float3 dbc = sub3(b, c), dca = sub3(c, a), dab = sub3(a, b);
+        float a2 = dot3(dbc, dbc), b2 = dot3(dca, dca), c2 = dot3(dab, dab);
+        float ws = a2 * (b2 + c2 - a2), wt = b2 * (c2 + a2 - b2), wp = c2 * (a2 + b2 - c2);
+        float3 S;
+        if (ws <= 0.0f)
+            S = scale3(add3(b, c), 0.5f);
+        else if (wt <= 0.0f)
+            S = scale3(add3(c, a), 0.5f);
+        else if (wp <= 0.0f)
+            S = scale3(add3(a, b), 0.5f);
+        else
+            S = scale3(add3(add3(scale3(a, ws), scale3(b, wt)), scale3(c, wp)), 1.0f / (ws + wt + wp));
+        float sl = sqrtf(dot3(S, S));
+        bool wide = !(sl > 1e-6f);
+        float rho = kPi;
+        if (!wide) {
+            S = scale3(S, 1.0f / sl);
+            // radius from the actual vertex chords, robust to rounding in S
+            float3 da = sub3(a, S), db = sub3(b, S), dc = sub3(c, S);
+            float ch2 = fmaxf(dot3(da, da), fmaxf(dot3(db, db), dot3(dc, dc)));
+            rho = 2.0f * asinf(fminf(1.0f, 0.5f * sqrtf(ch2)));
+            rho = rho * (1.0f + kCapRelMargin) + kCapAbsMargin;
+            wide = !(rho < kHalfPi);
+        }
+        int L = 0;
+        if (!wide) {
+            float sh, chh;
+            sincosf(0.5f * rho, &sh, &chh);
+            c0 = make_float4(S.x, S.y, S.z, sh);
+            c1 = make_float4(chh, sinf(rho), 0.0f, rho);
+            // finest level whose cell radius bound (pi/4)/2^L still covers rho
+            while (L < kMaxLevel && rho <= kQuarterPi / float(1 << (L + 1))) ++L;
+            if (rho > kQuarterPi) L = 0;
+            bkt = cell_of(S, L);
+        } else {
+            c0 = make_float4(0.0f, 0.0f, 1.0f, 1.0f);
+            c1 = make_float4(0.0f, 1.0f, kCapWide, kPi);
+            bkt = uint32_t(level_base(0));  // level 0, face 0: every tile looks at level 0
+        }
+    } else {
+        r0 = r1 = r2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        r3 = make_float4(0.0f, lb, __uint_as_float(uint32_t(t)), 0.0f);
+        c0 = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
+        c1 = make_float4(1.0f, 0.0f, kCapEmpty, 0.0f);
+    }
+    rec_id[4 * t + 0] = r0;
+    rec_id[4 * t + 1] = r1;
+    rec_id[4 * t + 2] = r2;
+    rec_id[4 * t + 3] = r3;
+    cap_id[2 * t + 0] = c0;
+    cap_id[2 * t + 1] = c1;
+    key[t] = __float_as_uint(lb);  // non-negative floats sort like their bits
+    val[t] = uint32_t(t);
+    bucket[t] = bkt;
+}
+
+// ------------------------------------------------ stable LSD radix sort --
+// Blocks of kSortBlock consecutive keys; per pass: per-block digit
+// histogram, one exclusive scan over (digit, block), stable scatter.
+
+__global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                          uint32_t* __restrict__ hist, int64_t nblocks) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = int64_t(blockIdx.x) * kSortBlock;
+    for (int r = 0; r < kSortItems; ++r) {
+        int64_t i = base + r * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of `total` counters by one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ a, int64_t total) {
+    __shared__ uint32_t part[1024];
+    int64_t per = (total + 1023) / 1024;
+    int64_t b = int64_t(threadIdx.x) * per, e = min(total, b + per);
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += a[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        uint32_t v = threadIdx.x >= unsigned(o) ? part[threadIdx.x - o] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0u;
+    for (int64_t i = b; i < e; ++i) {
+        uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                             const uint32_t* __restrict__ vin,
+                                                             uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                             int64_t n, int shift, const uint32_t* __restrict__ offs,
+                                                             int64_t nblocks) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kSortThreads / 64][256];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    run[tid] = offs[int64_t(tid) * nblocks + blockIdx.x];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t base = int64_t(blockIdx.x) * kSortBlock;
+    for (int r = 0; r < kSortItems; ++r) {
+        for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+        int64_t i = base + r * kSortThreads + tid;
+        bool valid = i < n;
+        uint32_t k = valid ? kin[i] : 0u, v = valid ? vin[i] : 0u;
+        uint32_t dg = (k >> shift) & 255u;
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            uint64_t m = __ballot((dg >> bit) & 1u);
+            same &= ((dg >> bit) & 1u) ? m : ~m;
+        }
+        uint32_t rank = (uint32_t)__popcll(same & lt);
+        if (valid && rank == 0) wcnt[wave][dg] = (uint32_t)__popcll(same);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[dg] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][dg];
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < kSortThreads / 64; ++w) add += wcnt[w][tid];
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+// Sort (key, val) pairs of length n on `bits` low key bits (multiple of 8).
+// Returns which buffer pair holds the result: false = (ka, va), true = (kb, vb).
+static hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, uint32_t* hist, int64_t n,
+                             int bits, bool* in_b, hipStream_t st) {
+    int64_t nb = (n + kSortBlock - 1) / kSortBlock;
+    bool b = false;
+    for (int shift = 0; shift < bits; shift += 8) {
+        uint32_t *ki = b ? kb : ka, *vi = b ? vb : va, *ko = b ? ka : kb, *vo = b ? va : vb;
+        hipLaunchKernelGGL(k_rs_hist, dim3(unsigned(nb)), dim3(kSortThreads), 0, st, ki, n, shift, hist, nb);
+        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, hist, 256 * nb);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(unsigned(nb)), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n, shift,
+                           hist, nb);
+        b = !b;
+    }
+    *in_b = b;
+    return hipGetLastError();
+}
+
+// Permute records and caps into nearest-first order; prepare the cell sort.
+__global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ order_ids, int64_t n,
+                                                 const float4* __restrict__ rec_id, const float4* __restrict__ cap_id,
+                                                 const uint32_t* __restrict__ bucket, float4* __restrict__ rec,
+                                                 float4* __restrict__ cap, uint32_t* __restrict__ order,
+                                                 uint32_t* __restrict__ key2, uint32_t* __restrict__ val2) {
+    int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    uint32_t id = order_ids[r];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rec[4 * r + q] = rec_id[4 * int64_t(id) + q];
+    cap[2 * r + 0] = cap_id[2 * int64_t(id) + 0];
+    cap[2 * r + 1] = cap_id[2 * int64_t(id) + 1];
+    order[r] = id;
+    key2[r] = bucket[id];
+    val2[r] = uint32_t(r);
+}
+
+// cell_start[b] = first position whose bucket is >= b (lower bound).
+__global__ __launch_bounds__(256) void k_cell_start(const uint32_t* __restrict__ sorted_bucket, int64_t n,
+                                                    uint32_t* __restrict__ cell_start) {
+    int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b > kNumBuckets) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (int64_t(sorted_bucket[mid]) < b)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    cell_start[b] = uint32_t(lo);
+}
+
+hipError_t launch_setup(const float* xyz, int64_t n, void* setup, hipStream_t st) {
+    SetupLayout L = setup_layout(n);
+    char* base = reinterpret_cast<char*>(setup);
+    auto U = [&](int64_t off) { return reinterpret_cast<uint32_t*>(base + off); };
+    auto F4 = [&](int64_t off) { return reinterpret_cast<float4*>(base + off); };
+    if (n > 0) {
+        unsigned blocks = unsigned((n + 255) / 256);
+        hipLaunchKernelGGL(k_setup_tris, dim3(blocks), dim3(256), 0, st, xyz, n, F4(L.rec_id_off), F4(L.cap_id_off),
+                           U(L.key_a_off), U(L.val_a_off), U(L.bucket_off));
+        bool in_b = false;
+        hipError_t e = radix_sort(U(L.key_a_off), U(L.val_a_off), U(L.key_b_off), U(L.val_b_off), U(L.hist_off), n,
+                                  32, &in_b, st);
+        if (e != hipSuccess) return e;
+        uint32_t* ids = in_b ? U(L.val_b_off) : U(L.val_a_off);
+        // the cell sort writes into the pair not holding ids
+        uint32_t* k2 = in_b ? U(L.key_a_off) : U(L.key_b_off);
+        uint32_t* v2 = in_b ? U(L.val_a_off) : U(L.val_b_off);
+        hipLaunchKernelGGL(k_permute, dim3(blocks), dim3(256), 0, st, ids, n, F4(L.rec_id_off), F4(L.cap_id_off),
+                           U(L.bucket_off), F4(L.rec_off), F4(L.cap_off), U(L.order_off), k2, v2);
+        // ids are no longer needed: the other pair is free scratch
+        uint32_t* k3 = in_b ? U(L.key_b_off) : U(L.key_a_off);
+        uint32_t* v3 = in_b ? U(L.val_b_off) : U(L.val_a_off);
+        bool in3 = false;
+        e = radix_sort(k2, v2, k3, v3, U(L.hist_off), n, 24, &in3, st);
+        if (e != hipSuccess) return e;
+        uint32_t* sk = in3 ? k3 : k2;
+        uint32_t* sv = in3 ? v3 : v2;
+        e = hipMemcpyAsync(U(L.cell_list_off), sv, size_t(n) * 4, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_cell_start, dim3(unsigned((kNumBuckets + 1 + 255) / 256)), dim3(256), 0, st, sk, n,
+                           U(L.cell_start_off));
+    } else {
+        hipLaunchKernelGGL(k_cell_start, dim3(unsigned((kNumBuckets + 1 + 255) / 256)), dim3(256), 0, st,
+                           U(L.key_a_off), int64_t(0), U(L.cell_start_off));
+    }
+    return hipGetLastError();
+}
+
+}  // namespace vsr

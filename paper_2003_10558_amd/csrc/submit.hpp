@@ -1,0 +1,168 @@
+// Batched views: one launch per stage over the (job, tile) items of all jobs.
+//
+// The job table lives in the workspace; it is written by a small kernel whose
+// arguments carry the descriptors (no host-memory copy, so a caller may
+// capture the whole submit in a HIP graph).  Each stage kernel maps its
+// global tile index to (job, local tile) with a wave-uniform binary search
+// over the jobs' tile offsets and then runs exactly the per-tile device
+// function of the single-view path, which is why a batched job's output is
+// bit-identical to rendering that view alone.
+
+#pragma once
+#include "map.hpp"
+#include "raster.hpp"
+
+namespace vsr {
+
+int make_map_params(const vsr_view* v, int32_t fmt, uint32_t flags, MapParams* P, vsr_view* eff);
+
+struct JobDesc {
+    MapParams P;
+    void* map;
+    void* bins;
+    const void* setup;
+    int64_t ntri;
+    uint32_t* tri_id;
+    float* depth;
+    int64_t tile_off;  // first global tile of this job
+    int64_t ntiles;
+};
+
+constexpr int kJobChunk = 8;
+struct JobChunk {
+    JobDesc d[kJobChunk];
+    int32_t first, count;
+};
+
+__global__ void k_write_jobs(JobChunk c, JobDesc* table) {
+    int q = threadIdx.x;
+    if (q < c.count) table[c.first + q] = c.d[q];
+}
+
+struct WsLayout {
+    int64_t table_off, data_off, bytes;
+};
+
+static WsLayout ws_layout(int32_t njobs) {
+    WsLayout w;
+    w.table_off = 256;
+    w.data_off = w.table_off + align256(int64_t(njobs) * int64_t(sizeof(JobDesc)));
+    w.bytes = w.data_off;
+    return w;
+}
+
+int64_t submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t depth) {
+    int64_t b = ws_layout(njobs).bytes;
+    for (int32_t q = 0; q < njobs; ++q) {
+        b += map_layout(jobs[q].view.width, jobs[q].view.height, fmt).bytes;
+        b += bin_layout(jobs[q].view.width, jobs[q].view.height, depth).bytes;
+    }
+    return b;
+}
+
+__device__ inline int find_job(const JobDesc* __restrict__ T, int njobs, int64_t t) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (T[mid].tile_off <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_submit_map(const JobDesc* __restrict__ T, int njobs, int64_t total) {
+    int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    int64_t t = int64_t(blockIdx.x) * 4 + w;
+    if (t >= total) return;
+    int jb = find_job(T, njobs, t);
+    const JobDesc& J = T[jb];
+    build_map_tile(J.P, J.map, J.ntiles, t - J.tile_off, threadIdx.x & 63);
+}
+
+__global__ __launch_bounds__(64) void k_submit_bin(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
+                                                   int32_t depth, int32_t lds_cap, uint32_t* status) {
+    extern __shared__ uint32_t lst[];
+    int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    int jb = find_job(T, njobs, t);
+    const JobDesc& J = T[jb];
+    BinArgs A;
+    A.map = J.map;
+    A.ntiles = J.ntiles;
+    A.fmt = fmt;
+    A.depth = depth;
+    A.lds_cap = lds_cap;
+    A.all = 0;
+    A.setup = J.setup;
+    A.n = J.ntri;
+    A.bins = J.bins;
+    A.status = status;
+    bin_tile(A, t - J.tile_off, threadIdx.x, lst);
+}
+
+__global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
+                                                       int32_t depth, int64_t total) {
+    int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    int64_t t = xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
+    if (t >= total) return;
+    int jb = find_job(T, njobs, t);
+    const JobDesc& J = T[jb];
+    RasterArgs A;
+    A.map = J.map;
+    A.ntiles = J.ntiles;
+    A.fmt = fmt;
+    A.depth = depth;
+    A.W = J.P.W;
+    A.H = J.P.H;
+    A.ntx = J.P.ntx;
+    A.pad = 0;
+    A.setup = J.setup;
+    A.n = J.ntri;
+    A.bins = J.bins;
+    A.tri_id = J.tri_id;
+    A.out_depth = J.depth;
+    raster_tile(A, t - J.tile_off, threadIdx.x & 63);
+}
+
+hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t depth, void* ws, hipStream_t st) {
+    WsLayout W = ws_layout(njobs);
+    char* base = reinterpret_cast<char*>(ws);
+    JobDesc* table = reinterpret_cast<JobDesc*>(base + W.table_off);
+    int64_t off = W.data_off, tiles = 0;
+    JobChunk chunk;
+    chunk.first = 0;
+    chunk.count = 0;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ws), int64_t(64));
+    for (int32_t q = 0; q < njobs; ++q) {
+        JobDesc& D = chunk.d[chunk.count];
+        make_map_params(&jobs[q].view, fmt, 0, &D.P, nullptr);
+        MapLayout ML = map_layout(D.P.W, D.P.H, fmt);
+        BinLayout BL = bin_layout(D.P.W, D.P.H, depth);
+        D.map = base + off;
+        off += ML.bytes;
+        D.bins = base + off;
+        off += BL.bytes;
+        D.setup = jobs[q].setup;
+        D.ntri = jobs[q].ntri;
+        D.tri_id = jobs[q].tri_id;
+        D.depth = jobs[q].depth;
+        D.tile_off = tiles;
+        D.ntiles = ML.ntiles;
+        tiles += ML.ntiles;
+        if (++chunk.count == kJobChunk || q == njobs - 1) {
+            hipLaunchKernelGGL(k_write_jobs, dim3(1), dim3(kJobChunk), 0, st, chunk, table);
+            chunk.first = q + 1;
+            chunk.count = 0;
+        }
+    }
+    hipLaunchKernelGGL(k_submit_map, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, tiles);
+    int32_t cap = bin_lds_cap(depth);
+    hipLaunchKernelGGL(k_submit_bin, dim3(unsigned(tiles)), dim3(64), size_t(cap) * 4, st, table, njobs, fmt, depth,
+                       cap, reinterpret_cast<uint32_t*>(ws));
+    hipLaunchKernelGGL(k_submit_raster, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, fmt, depth,
+                       tiles);
+    return hipGetLastError();
+}
+
+}  // namespace vsr

@@ -1,0 +1,244 @@
+// Internal layouts and device helpers of libvsr (gfx950).
+//
+// Build flags matter for this file: everything is compiled with
+// -ffp-contract=off so that a*b - c*d is two rounded products and one
+// rounded difference.  That makes the edge-plane normal of a shared edge
+// exactly the negation of its neighbour's (watertight coverage); fused
+// multiply-adds are written explicitly with fmaf() where wanted.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vsr.h"
+
+namespace vsr {
+
+constexpr int kTile = VSR_TILE;              // tile edge in pixels
+constexpr int kTilePix = kTile * kTile;      // 64 = one wavefront
+constexpr int kLevels = 9;                   // cube-map index levels 0..8
+constexpr int kMaxLevel = kLevels - 1;
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kQuarterPi = 0.785398163397448310f;
+constexpr float kHalfPi = 1.57079632679489662f;
+constexpr uint32_t kNoHit = VSR_NO_HIT;
+// Initial z-buffer key: depth +inf in the high word, id NO_HIT in the low word.
+constexpr uint64_t kKeyEmpty = (uint64_t(0x7F800000u) << 32) | uint64_t(kNoHit);
+
+// Cap margins (radians).  The FP32 coverage test can differ from the exact
+// spherical triangle by ~1e-7 rad; caps are widened far beyond that so that
+// binning never rejects a (tile, triangle) pair the rasterizer would cover.
+constexpr float kCapAbsMargin = 2e-5f;
+constexpr float kCapRelMargin = 1e-6f;
+
+__host__ __device__ constexpr int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+// Cells of level L: 6 faces of M x M, M = 2^L.  Buckets of all levels are
+// numbered consecutively; bucket kNumBuckets collects culled triangles.
+__host__ __device__ constexpr int64_t level_base(int L) { return 6 * (((int64_t(1) << (2 * L)) - 1) / 3); }
+constexpr int64_t kNumBuckets = level_base(kLevels);
+
+// --------------------------------------------------------------- map ----
+struct MapLayout {
+    int32_t ntx, nty;
+    int64_t ntiles;
+    int64_t plane_bytes;  // all pixel data
+    int64_t caps_off;     // float4 x 2 per tile
+    int64_t bytes;
+};
+
+__host__ __device__ inline MapLayout map_layout(int32_t w, int32_t h, int32_t fmt) {
+    MapLayout m;
+    m.ntx = (w + kTile - 1) / kTile;
+    m.nty = (h + kTile - 1) / kTile;
+    m.ntiles = int64_t(m.ntx) * m.nty;
+    m.plane_bytes = m.ntiles * kTilePix * (fmt == VSR_MAP_OCT16 ? 4 : 12);
+    m.caps_off = align256(m.plane_bytes);
+    m.bytes = m.caps_off + align256(m.ntiles * 32);
+    return m;
+}
+
+// Per-view constants of the map generator, computed on the host in double
+// precision and rounded once to float.
+struct MapParams {
+    int32_t W, H, aov, fmt;
+    int32_t ntx, nty;
+    int32_t kind;       // +1: k > 0, 0: k == 0, -1: k < 0
+    int32_t xmul;       // x = (2i+1-W) * xmul / xden, y = (2j+1-H) * xmul / yden
+    float xden, yden;
+    float k;            // projection type k (divisor of the arc functions)
+    float half;         // Omega / 2 in radians
+    float kt;           // tan(k*Omega/2) (k>0) or sin(k*Omega/2) (k<0)
+    float sig0;         // limit of sin(theta)/R at R = 0
+    float l;            // cylindricity
+    float c;            // anamorphic divisor l*(1-s)+s
+    float rot[9];
+};
+
+// ------------------------------------------------------------- setup ----
+struct SetupLayout {
+    int64_t n;
+    int64_t nblocks;    // radix-sort blocks
+    int64_t rec_off, cap_off, cell_list_off, cell_start_off, order_off;
+    int64_t rec_id_off, cap_id_off, key_a_off, val_a_off, key_b_off, val_b_off, bucket_off, hist_off;
+    int64_t bytes;
+};
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortBlock = kSortThreads * kSortItems;  // 2048 keys per block
+
+__host__ __device__ inline SetupLayout setup_layout(int64_t n) {
+    SetupLayout s;
+    s.n = n;
+    s.nblocks = (n + kSortBlock - 1) / kSortBlock;
+    int64_t o = 256;
+    s.rec_off = o;        o += align256(n * 64);
+    s.cap_off = o;        o += align256(n * 32);
+    s.cell_list_off = o;  o += align256(n * 4);
+    s.cell_start_off = o; o += align256((kNumBuckets + 1) * 4);
+    s.order_off = o;      o += align256(n * 4);
+    s.rec_id_off = o;     o += align256(n * 64);
+    s.cap_id_off = o;     o += align256(n * 32);
+    s.key_a_off = o;      o += align256(n * 4);
+    s.val_a_off = o;      o += align256(n * 4);
+    s.key_b_off = o;      o += align256(n * 4);
+    s.val_b_off = o;      o += align256(n * 4);
+    s.bucket_off = o;     o += align256(n * 4);
+    s.hist_off = o;       o += align256(256 * (s.nblocks > 0 ? s.nblocks : 1) * 4);
+    s.bytes = o;
+    return s;
+}
+
+// --------------------------------------------------------------- bins ---
+struct BinLayout {
+    int64_t ntiles;
+    int64_t counts_off;
+    int64_t lists_off;
+    int64_t bytes;
+};
+
+__host__ __device__ inline BinLayout bin_layout(int32_t w, int32_t h, int32_t depth) {
+    MapLayout m = map_layout(w, h, VSR_MAP_F32);
+    BinLayout b;
+    b.ntiles = m.ntiles;
+    b.counts_off = 256;  // first 256 bytes: status words (overflowed tile count)
+    b.lists_off = b.counts_off + align256(m.ntiles * 4);
+    b.bytes = b.lists_off + align256(m.ntiles * int64_t(depth) * 4);
+    return b;
+}
+
+// ------------------------------------------------------ device helpers --
+__device__ inline float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
+__device__ inline float3 sub3(float3 a, float3 b) { return f3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ inline float3 add3(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ inline float3 scale3(float3 a, float s) { return f3(a.x * s, a.y * s, a.z * s); }
+__device__ inline float dot3(float3 a, float3 b) { return fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)); }
+// Cross product with separately rounded products (no contraction).
+__device__ inline float3 cross3(float3 a, float3 b) {
+    return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+// Wave-wide reductions (64 lanes).
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// Octahedral unit-vector encoding (two fp16).  The all-ones word marks a
+// pixel without a direction.
+constexpr uint32_t kOctInvalid = 0xFFFFFFFFu;
+
+__device__ inline uint32_t oct_encode(float3 g) {
+    float s = fabsf(g.x) + fabsf(g.y) + fabsf(g.z);
+    if (!(s > 0.0f)) return kOctInvalid;
+    float x = g.x / s, y = g.y / s;
+    if (g.z < 0.0f) {
+        float ox = (1.0f - fabsf(y)) * (x >= 0.0f ? 1.0f : -1.0f);
+        float oy = (1.0f - fabsf(x)) * (y >= 0.0f ? 1.0f : -1.0f);
+        x = ox;
+        y = oy;
+    }
+    _Float16 hx = (_Float16)x, hy = (_Float16)y;
+    uint16_t bx, by;
+    __builtin_memcpy(&bx, &hx, 2);
+    __builtin_memcpy(&by, &hy, 2);
+    return uint32_t(bx) | (uint32_t(by) << 16);
+}
+
+__device__ inline float3 oct_decode(uint32_t w) {
+    if (w == kOctInvalid) return f3(0.0f, 0.0f, 0.0f);
+    uint16_t bx = uint16_t(w & 0xFFFFu), by = uint16_t(w >> 16);
+    _Float16 hx, hy;
+    __builtin_memcpy(&hx, &bx, 2);
+    __builtin_memcpy(&hy, &by, 2);
+    float x = (float)hx, y = (float)hy;
+    float z = 1.0f - fabsf(x) - fabsf(y);
+    if (z < 0.0f) {
+        float ox = (1.0f - fabsf(y)) * (x >= 0.0f ? 1.0f : -1.0f);
+        float oy = (1.0f - fabsf(x)) * (y >= 0.0f ? 1.0f : -1.0f);
+        x = ox;
+        y = oy;
+    }
+    float inv = 1.0f / sqrtf(fmaf(x, x, fmaf(y, y, z * z)));
+    return f3(x * inv, y * inv, z * inv);
+}
+
+// Tile caps of a map buffer (2 x float4 per tile, after the pixel planes).
+__host__ __device__ inline const float4* map_caps(const void* map, int64_t ntiles, int32_t fmt) {
+    return reinterpret_cast<const float4*>(reinterpret_cast<const char*>(map) +
+                                           align256(ntiles * kTilePix * (fmt == VSR_MAP_OCT16 ? 4 : 12)));
+}
+
+// Load the direction of pixel `lane` of tile `tile`.
+__device__ inline float3 load_dir(const void* map, int32_t fmt, int64_t ntiles, int64_t tile, int lane) {
+    if (fmt == VSR_MAP_OCT16) {
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(map);
+        return oct_decode(p[tile * kTilePix + lane]);
+    }
+    const float* p = reinterpret_cast<const float*>(map);
+    int64_t plane = ntiles * kTilePix;
+    int64_t q = tile * kTilePix + lane;
+    return f3(p[q], p[plane + q], p[2 * plane + q]);
+}
+
+// Tile cap record: c0 = (centre.xyz, sin(rho/2)), c1 = (cos(rho/2), sin(rho), flags, 0)
+constexpr float kCapWide = 1.0f;   // cap radius >= pi/2: no culling possible
+constexpr float kCapEmpty = 2.0f;  // no pixel with a direction
+// Triangle cap record: same layout; flags kCapWide when the cap is useless.
+
+// Conservative test: may triangle (cap tc0/tc1, oriented unit edge normals
+// n0..n2) cover any pixel of the tile (cap c0/c1)?  Never returns false for
+// a pair the rasterizer's FP32 test could cover.
+__device__ inline bool tile_may_see(float4 c0, float4 c1, float4 t0, float4 t1, float3 n0, float3 n1,
+                                    float3 n2) {
+    if (c1.z == kCapEmpty) return false;
+    if (c1.z == kCapWide) return true;
+    if (t1.z != kCapWide) {
+        float dx = c0.x - t0.x, dy = c0.y - t0.y, dz = c0.z - t0.z;
+        float chord2 = dx * dx + dy * dy + dz * dz;
+        // sin((rho_tile + rho_tri)/2) by the angle-sum identity
+        float s = c0.w * t1.x + c1.x * t0.w;
+        if (chord2 > 4.0f * s * s * (1.0f + 1e-6f) + 1e-12f) return false;
+    }
+    float3 c = f3(c0.x, c0.y, c0.z);
+    float lim = -c1.y - 1e-6f;
+    if (dot3(n0, c) < lim || dot3(n1, c) < lim || dot3(n2, c) < lim) return false;
+    return true;
+}
+
+}  // namespace vsr

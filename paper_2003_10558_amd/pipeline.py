@@ -1,0 +1,92 @@
+"""Device-memory plumbing around the C ABI: resident scenes and view buffers.
+
+Nothing here computes any part of the method; it allocates the buffers the
+vsr_* calls need (torch tensors on the GPU) and chains the calls.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import vsr
+
+DEFAULT_BIN_DEPTH = 1024
+
+
+def _buffer(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+class Scene:
+    """Triangles resident on the GPU with their setup (vsr_setup_tris)."""
+
+    def __init__(self, xyz: np.ndarray | torch.Tensor, device="cuda", stream=None):
+        if isinstance(xyz, np.ndarray):
+            xyz = torch.from_numpy(np.ascontiguousarray(xyz, dtype=np.float32))
+        self.xyz = xyz.to(device=device, dtype=torch.float32).contiguous()
+        assert self.xyz.dim() == 2 and self.xyz.shape[0] == 9
+        self.ntri = int(self.xyz.shape[1])
+        self.device = self.xyz.device
+        self.setup = _buffer(vsr.vsr_setup_bytes(self.ntri), self.device)
+        self.refresh(stream)
+
+    def refresh(self, stream=None) -> None:
+        """Re-run the per-triangle setup (e.g. after the vertices moved)."""
+        vsr.vsr_setup_tris(self.xyz, self.setup, stream)
+
+
+@dataclass
+class Frame:
+    tri_id: torch.Tensor   # uint32 as int32 storage, [H, W]
+    depth: torch.Tensor    # float32 [H, W]
+    map: torch.Tensor
+    bins: torch.Tensor
+    view_eff: object
+
+
+def alloc_outputs(view, device) -> Tuple[torch.Tensor, torch.Tensor]:
+    ids = torch.empty((view.height, view.width), dtype=torch.int32, device=device)
+    dep = torch.empty((view.height, view.width), dtype=torch.float32, device=device)
+    return ids, dep
+
+
+def render(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, bin_depth: int = DEFAULT_BIN_DEPTH,
+           bin_flags: int = 0, stream=None, frame: Optional[Frame] = None) -> Frame:
+    """build_map -> bin -> raster for one view (plain per-view path)."""
+    dev = scene.device
+    if frame is None:
+        ids, dep = alloc_outputs(view, dev)
+        frame = Frame(ids, dep, _buffer(vsr.vsr_map_bytes(view.width, view.height, fmt), dev),
+                      _buffer(vsr.vsr_bin_bytes(view.width, view.height, bin_depth), dev), None)
+    frame.view_eff = vsr.vsr_build_map(view, fmt, 0, frame.map, stream)
+    vsr.vsr_bin(view, fmt, frame.map, scene.setup, scene.ntri, bin_depth, bin_flags, frame.bins, stream)
+    vsr.vsr_raster(view, fmt, frame.map, scene.setup, scene.ntri, frame.bins, bin_depth, frame.tri_id,
+                   frame.depth, stream)
+    return frame
+
+
+class Batch:
+    """Workspace + outputs for vsr_submit over a fixed list of (scene, view)."""
+
+    def __init__(self, items: Sequence[Tuple[Scene, object]], fmt: int = vsr.VSR_MAP_F32,
+                 bin_depth: int = DEFAULT_BIN_DEPTH):
+        assert len(items) > 0
+        self.items = list(items)
+        self.fmt, self.bin_depth = fmt, bin_depth
+        dev = items[0][0].device
+        self.outputs = [alloc_outputs(v, dev) for _, v in self.items]
+        self.jobs = vsr.make_jobs([(v, s.setup, s.ntri, o[0], o[1])
+                                   for (s, v), o in zip(self.items, self.outputs)])
+        self.workspace = _buffer(vsr.vsr_submit_bytes(self.jobs, fmt, bin_depth), dev)
+
+    def submit(self, stream=None) -> List[Tuple[torch.Tensor, torch.Tensor]]:
+        vsr.vsr_submit(self.jobs, self.fmt, self.bin_depth, self.workspace, stream)
+        return self.outputs
+
+
+def ids_u32(t: torch.Tensor) -> np.ndarray:
+    """Device int32 id image -> host uint32 array."""
+    return t.cpu().numpy().view(np.uint32)

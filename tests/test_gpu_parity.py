@@ -1,0 +1,232 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Run on an MI355X: python -u -m pytest -m gpu -x -v tests/
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2003_10558_amd import pipeline, vsr
+    oracle.build(force=False)
+    return torch, pipeline, vsr
+
+
+def _gpu_map(gpu, view, fmt=0):
+    torch, pipeline, vsr = gpu
+    buf = torch.empty(vsr.vsr_map_bytes(view.width, view.height, fmt), dtype=torch.uint8, device="cuda")
+    eff = vsr.vsr_build_map(view, fmt, 0, buf)
+    out = torch.empty((view.height, view.width, 3), dtype=torch.float32, device="cuda")
+    vsr.vsr_map_unpack(view, fmt, buf, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64), eff
+
+
+def _angle(a, b):
+    """Angle between unit vectors, robust for tiny angles."""
+    c = np.linalg.norm(np.cross(a, b), axis=-1)
+    d = np.einsum("...i,...i->...", a, b)
+    return np.arctan2(c, d)
+
+
+MAP_VIEWS = [
+    ("small", synth.view_small()),
+    ("1080p_k1", synth.views_1080p_sweep()[0]),
+    ("1080p_k0.5", synth.views_1080p_sweep()[1]),
+    ("1080p_k0", synth.views_1080p_sweep()[2]),
+    ("1080p_k-0.5", synth.views_1080p_sweep()[3]),
+    ("diag", synth.View(333, 121, -0.8, 0.3, 0.9, 150.0, synth.AOV_DIAGONAL, synth.yaw_pitch_rotation(0.4, 1.0))),
+    ("vert", synth.View(100, 300, 0.7, 0.0, 0.8, 100.0, synth.AOV_VERTICAL, synth.yaw_pitch_rotation(2.0, -0.5))),
+    ("4x3", synth.View(161, 97, -1.0, 1.0, 1.0, 180.0, synth.AOV_HORIZONTAL_4X3)),
+    ("wide360", synth.View(200, 100, 0.0, 0.4, 0.85, 360.0, 0, synth.yaw_pitch_rotation(5.0, 0.2))),
+]
+
+
+@pytest.mark.parametrize("name,view", MAP_VIEWS, ids=[n for n, _ in MAP_VIEWS])
+def test_map_matches_oracle(gpu, name, view):
+    _say(f"[map] {name} {view.width}x{view.height} k={view.k}")
+    g, eff = _gpu_map(gpu, view)
+    ref, ok = oracle.perspective_map(view)
+    k, l, s, om = oracle.limits(view.k, view.l, view.s, view.omega_deg)
+    assert (eff.k, eff.omega_deg) == pytest.approx((k, om), rel=1e-6)
+    gok = np.any(g != 0, axis=-1)
+    # validity agrees except within 1e-6 of the domain edge
+    diff = gok != ok
+    if diff.any():
+        js, is_ = np.nonzero(diff)
+        for j, i in zip(js[:50], is_[:50]):
+            assert oracle.render(view, np.zeros((9, 0), np.float32), np.array([j * view.width + i])).flags[0] & 1
+    both = gok & ok
+    err = _angle(g[both], ref[both])
+    _say(f"[map] {name}: max angular error {err.max():.3e} rad, p99 {np.quantile(err, 0.99):.3e}")
+    assert err.max() < 1e-6
+    assert np.all(np.abs(np.linalg.norm(g[both], axis=-1) - 1) < 1e-6)
+
+
+def _render(gpu, tris, view, fmt=0, depth=1024, flags=0):
+    torch, pipeline, vsr = gpu
+    scene = pipeline.Scene(tris)
+    fr = pipeline.render(scene, view, fmt=fmt, bin_depth=depth, bin_flags=flags)
+    torch.cuda.synchronize()
+    return pipeline.ids_u32(fr.tri_id), fr.depth.cpu().numpy(), vsr.vsr_bin_overflow(fr.bins)
+
+
+def test_small_full_frame(gpu):
+    view, tris = synth.view_small(), synth.scene_small()
+    _say("[raster] 256x256 full frame vs oracle")
+    ids, dep, ovf = _render(gpu, tris, view)
+    ref = oracle.render(view, tris)
+    st = compare(view, tris, ids, dep, ref)
+    _say("[raster] " + st.line() + " " + "; ".join(st.notes))
+    assert st.ok(), st.notes
+    assert ovf == 0
+
+
+def test_binning_is_exact(gpu):
+    """Real bins give the same bits as every triangle in every tile."""
+    for name, view, tris in [("small", synth.view_small(), synth.scene_small()),
+                             ("rot", synth.View(200, 150, -0.4, 0.3, 0.9, 300.0, 0, synth.yaw_pitch_rotation(1.0, 0.3)),
+                              synth.scene(1500, 17))]:
+        _say(f"[bin-exact] {name}")
+        a_ids, a_dep, _ = _render(gpu, tris, view)
+        b_ids, b_dep, ovf = _render(gpu, tris, view, depth=4096, flags=1)
+        assert ovf == 0
+        assert np.array_equal(a_ids, b_ids)
+        assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
+
+
+RAGGED = [
+    (1, 1, 0), (7, 5, 0), (8, 8, 1), (9, 9, 2), (37, 23, 3), (129, 65, 0), (255, 257, 1),
+]
+
+
+@pytest.mark.parametrize("w,h,aov", RAGGED)
+def test_ragged_sizes(gpu, w, h, aov):
+    rng = np.random.default_rng(w * 1000 + h)
+    view = synth.View(w, h, float(rng.uniform(-1, 1)), float(rng.uniform(0, 1)), float(rng.uniform(0.8, 1)),
+                      float(rng.uniform(60, 360)), aov, synth.yaw_pitch_rotation(rng.uniform(0, 6), rng.uniform(-1, 1)))
+    tris = synth.scene(400, w + h)
+    _say(f"[ragged] {w}x{h} aov={aov} k={view.k:.3f}")
+    ids, dep, _ = _render(gpu, tris, view)
+    st = compare(view, tris, ids, dep, oracle.render(view, tris))
+    _say("[ragged] " + st.line())
+    assert st.ok(), st.notes
+
+
+def test_empty_and_degenerate(gpu):
+    view = synth.View(64, 48, 0.2, 0.5, 0.9, 200.0)
+    _say("[edge] empty scene")
+    ids, dep, _ = _render(gpu, np.zeros((9, 0), np.float32), view)
+    assert np.all(ids == 0xFFFFFFFF) and np.all(np.isinf(dep))
+    _say("[edge] degenerate triangles")
+    t1 = [1, 0, 0, 0, 1, 0, 1, 1, 0]          # plane through O
+    t2 = [1, 2, 3, 1, 2, 3, -1, 0, 2]         # two equal vertices
+    t3 = [0, 0, 5, 0, 0, 5, 0, 0, 5]          # a point
+    t4 = [-50, -40, 3, 60, -30, 3, 0, 70, 3]  # big, in front
+    tris = np.ascontiguousarray(np.array([t1, t2, t3, t4], dtype=np.float32).T)
+    ids, dep, _ = _render(gpu, tris, view)
+    ref = oracle.render(view, tris)
+    st = compare(view, tris, ids, dep, ref)
+    assert st.ok(), st.notes
+    assert set(np.unique(ids)) <= {3, 0xFFFFFFFF}
+
+
+def test_winding_and_antipode(gpu):
+    """Both windings cover the same pixels and nothing at the antipode."""
+    view = synth.View(128, 64, 0.0, 1.0, 1.0, 360.0)
+    tri = np.array([[-1, -1, 5, 1, -1, 5, 0, 1, 5]], dtype=np.float32).T
+    rev = tri[[0, 1, 2, 6, 7, 8, 3, 4, 5]]
+    a, da, _ = _render(gpu, np.ascontiguousarray(tri), view)
+    b, db, _ = _render(gpu, np.ascontiguousarray(rev), view)
+    ref = oracle.render(view, tri)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a != 0xFFFFFFFF, ref.id != 0xFFFFFFFF)
+
+
+def test_overflow_falls_back(gpu):
+    """A tiny bin depth overflows; the rasterizer gathers itself: same bits."""
+    view, tris = synth.view_small(), synth.scene_small()
+    _say("[overflow] depth 4 vs 1024")
+    a_ids, a_dep, ovf_a = _render(gpu, tris, view, depth=1024)
+    b_ids, b_dep, ovf_b = _render(gpu, tris, view, depth=4)
+    assert ovf_a == 0 and ovf_b > 0
+    assert np.array_equal(a_ids, b_ids)
+    assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
+
+
+def test_submit_matches_single_views(gpu):
+    torch, pipeline, vsr = gpu
+    tris = synth.scene(3000, 23)
+    scene = pipeline.Scene(tris)
+    views = synth.random_views(6, 99, resolutions=((96, 64), (130, 70), (64, 64)))
+    _say("[submit] 6 mixed views vs single")
+    batch = pipeline.Batch([(scene, v) for v in views])
+    outs = batch.submit()
+    torch.cuda.synchronize()
+    for v, (ids_t, dep_t) in zip(views, outs):
+        fr = pipeline.render(scene, v)
+        torch.cuda.synchronize()
+        assert np.array_equal(pipeline.ids_u32(ids_t), pipeline.ids_u32(fr.tri_id))
+        assert np.array_equal(dep_t.cpu().numpy().view(np.uint32), fr.depth.cpu().numpy().view(np.uint32))
+    # and against the oracle for one of them
+    v = views[0]
+    st = compare(v, tris, pipeline.ids_u32(outs[0][0]), outs[0][1].cpu().numpy(), oracle.render(v, tris))
+    assert st.ok(), st.notes
+
+
+def test_oct16_tier_small(gpu):
+    """Octahedral fp16 map: angular error and coverage mismatch vs FP64."""
+    view, tris = synth.view_small(), synth.scene_small()
+    g16, _ = _gpu_map(gpu, view, fmt=1)
+    ref, ok = oracle.perspective_map(view)
+    err = _angle(g16[ok], ref[ok])
+    ids, dep, _ = _render(gpu, tris, view, fmt=1)
+    rr = oracle.render(view, tris)
+    mism = float(np.mean(ids != rr.id))
+    _say(f"[oct16] angular error mean {err.mean():.2e} max {err.max():.2e}; id mismatch fraction {mism:.4f}")
+    assert err.max() < 2e-3
+    assert mism < 0.05
+
+
+@pytest.mark.parametrize("q", [0, 1, 2, 3])
+def test_1080p_1m_sampled(gpu, q):
+    """1920x1080 view of 1M small triangles + radius-100 icosphere, sampled
+    pixels (64 random 16x16 tiles + random pixels) against the oracle."""
+    torch, pipeline, vsr = gpu
+    view = synth.views_1080p_sweep()[q]
+    tris = _scene_1m()
+    _say(f"[1080p] k={view.k} omega={view.omega_deg}")
+    ids, dep, ovf = _render(gpu, tris, view)
+    pix = synth.pixel_sample(view.width, view.height, seed=100 + q, n_tiles=8, n_pixels=2048)
+    ref = oracle.render(view, tris, pix)
+    st = compare(view, tris, ids, dep, ref, pix)
+    _say(f"[1080p] k={view.k}: " + st.line() + f" overflow={ovf} " + "; ".join(st.notes))
+    assert st.ok(), st.notes
+
+
+_SCENE_1M = None
+
+
+def _scene_1m():
+    global _SCENE_1M
+    if _SCENE_1M is None:
+        _SCENE_1M = synth.scene_1m()
+    return _SCENE_1M
