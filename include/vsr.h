@@ -152,6 +152,16 @@ int vsr_bin(const vsr_view* v, int32_t fmt, const void* map, const void* setup, 
 int vsr_raster(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
                const void* bins, int32_t bin_depth, uint32_t* tri_id, float* depth, void* stream);
 
+/* Instrumented vsr_raster (same images) that also counts, into the device
+ * array stats[4] of uint64: executed pixel-triangle tests (pixels with a
+ * direction x triangles processed), covered fragments processed, triangles
+ * processed, tiles.  With no_early_exit != 0 every listed triangle is
+ * processed, so stats[1] is then the number of covered (pixel, triangle)
+ * pairs of the frame.  For measurement; slower than vsr_raster. */
+int vsr_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
+                     const void* bins, int32_t bin_depth, uint32_t* tri_id, float* depth, uint64_t* stats,
+                     int32_t no_early_exit, void* stream);
+
 /* ------------------------------------------------------------- batches */
 
 /* One view of a batch (host memory).  setup/ntri name a resident scene

@@ -72,7 +72,9 @@ int make_map_params(const vsr_view* v, int32_t fmt, uint32_t flags, MapParams* P
     P->kind = k > 0.0 ? 1 : (k < 0.0 ? -1 : 0);
     P->k = float(k);
     P->half = float(half);
-    P->kt = float(k > 0.0 ? tan(k * half) : (k < 0.0 ? sin(k * half) : 0.0));
+    double kt = k > 0.0 ? tan(k * half) : (k < 0.0 ? sin(k * half) : 0.0);
+    P->kt = float(kt);
+    P->kt_lo = float(kt - double(P->kt));
     P->sig0 = float(k > 0.0 ? tan(k * half) / k : (k < 0.0 ? sin(k * half) / k : half));
     P->l = float(l);
     P->c = float(l * (1.0 - s) + s);
@@ -94,6 +96,12 @@ int make_map_params(const vsr_view* v, int32_t fmt, uint32_t flags, MapParams* P
         P->xmul = 1;
         P->xden = P->yden = float(W);
         break;
+    }
+    P->xden_lo = float(0.0);
+    P->yden_lo = float(0.0);
+    if (v->aov == VSR_AOV_DIAGONAL) {
+        double hyp = sqrt(W * W + H * H);
+        P->xden_lo = P->yden_lo = float(hyp - double(P->xden));
     }
     for (int q = 0; q < 9; ++q) P->rot[q] = v->rot[q];
     if (eff) {
@@ -193,6 +201,21 @@ int vsr_raster(const vsr_view* v, int32_t fmt, const void* map, const void* setu
     return hip_status(launch_raster(map, v->width, v->height, fmt, setup, ntri, bins, bin_depth, tri_id, depth,
                                     hipStream_t(stream)),
                       "vsr_raster");
+}
+
+int vsr_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
+                     const void* bins, int32_t bin_depth, uint32_t* tri_id, float* depth, uint64_t* stats,
+                     int32_t no_early_exit, void* stream) {
+    int rc = check_view_buffers(v, fmt);
+    if (rc != VSR_OK) return rc;
+    if (!map || !setup || !bins || !tri_id || !depth || !stats || !aligned(map) || !aligned(setup) || !aligned(bins))
+        return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if ((reinterpret_cast<uintptr_t>(stats) & 7u) != 0) return fail(VSR_E_ARG, "stats not 8-byte aligned");
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri out of range");
+    if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
+    return hip_status(launch_raster(map, v->width, v->height, fmt, setup, ntri, bins, bin_depth, tri_id, depth,
+                                    hipStream_t(stream), reinterpret_cast<unsigned long long*>(stats), no_early_exit),
+                      "vsr_raster_stats");
 }
 
 int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t bin_depth) {

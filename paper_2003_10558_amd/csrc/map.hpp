@@ -12,19 +12,57 @@
 
 namespace vsr {
 
+// Double-float helpers (value = hi + lo, |lo| <= ulp(hi)/2).
+__device__ inline void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// asin(q) for |q| <= 1 given q = qh + ql in double-float.  Near |q| = 1 asin
+// is ill-conditioned (the rim of sine-type projections); there it is taken
+// as pi/2 - 2 asin(sqrt((1-|q|)/2)) with 1-|q| formed exactly.
+__device__ inline float asin_df(float qh, float ql) {
+    float ah = fabsf(qh), al = qh < 0.0f ? -ql : ql;
+    float a;
+    if (ah <= 0.5f) {
+        a = asinf(ah + al);
+    } else {
+        float t = (1.0f - ah) - al;  // 1 - ah is exact for ah in [0.5, 1]
+        a = kHalfPi - 2.0f * asinf(sqrtf(fmaxf(0.0f, 0.5f * t)));
+    }
+    return qh < 0.0f ? -a : a;
+}
+
 // Unit camera direction of pixel (i, j); false when the pixel is outside
 // the projection's domain.
 __device__ inline bool pixel_direction(const MapParams& P, int i, int j, float3& out) {
-    float x = float((2 * i + 1 - P.W) * P.xmul) / P.xden;
-    float y = float((2 * j + 1 - P.H) * P.xmul) / P.yden;
+    float nx = float((2 * i + 1 - P.W) * P.xmul), ny = float((2 * j + 1 - P.H) * P.xmul);
+    float x = nx / P.xden;
+    float y = ny / P.yden;
     float R = sqrtf(fmaf(x, x, P.l * (y * y)));
     float theta;
     if (P.kind > 0) {
         theta = atanf(P.kt * R) / P.k;
     } else if (P.kind < 0) {
-        float q = P.kt * R;
-        if (q > 1.0f || q < -1.0f) return false;
-        theta = asinf(q) / P.k;
+        // sin(k Omega/2) R in double-float: x, y, R^2, R and the product
+        float xl = (fmaf(-x, P.xden, nx) - x * P.xden_lo) / P.xden;
+        float yl = (fmaf(-y, P.yden, ny) - y * P.yden_lo) / P.yden;
+        float xx = x * x, xxe = fmaf(x, x, -xx) + 2.0f * x * xl;
+        float yy = y * y, yye = fmaf(y, y, -yy) + 2.0f * y * yl;
+        float ly = P.l * yy, lye = fmaf(P.l, yy, -ly) + P.l * yye;
+        float Xh, Xe;
+        two_sum(xx, ly, Xh, Xe);
+        Xe += xxe + lye;
+        float Rh = sqrtf(Xh);
+        float Rl = Rh > 0.0f ? (fmaf(-Rh, Rh, Xh) + Xe) / (2.0f * Rh) : 0.0f;
+        float qh = P.kt * Rh;
+        float ql = fmaf(P.kt, Rh, -qh) + P.kt * Rl + P.kt_lo * Rh;
+        float s, e;
+        two_sum(qh, ql, s, e);
+        if (fabsf(s) > 1.0f || (fabsf(s) == 1.0f && (s > 0.0f ? e > 0.0f : e < 0.0f))) return false;
+        theta = asin_df(s, e) / P.k;
+        R = Rh;
     } else {
         theta = P.half * R;
     }

@@ -238,9 +238,12 @@ struct RasterArgs {
     const void* bins;
     uint32_t* tri_id;
     float* out_depth;
+    unsigned long long* stats;  // instrumented variant only: tests, covered, triangles, tiles
+    int32_t no_early_exit;      // instrumented variant only: process whole lists
 };
 
-__device__ inline void raster_one(const float4* __restrict__ rec, uint32_t rank, float3 g, uint64_t& best) {
+// One triangle against the lane's pixel; returns whether it covers it.
+__device__ inline bool raster_one(const float4* __restrict__ rec, uint32_t rank, float3 g, uint64_t& best) {
     const float4* r = rec + 4 * int64_t(rank);
     float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
     float e0 = fmaf(r0.z, g.z, fmaf(r0.y, g.y, r0.x * g.x));
@@ -252,10 +255,13 @@ __device__ inline void raster_one(const float4* __restrict__ rec, uint32_t rank,
             float rr = r3.x * __builtin_amdgcn_rcpf(dn);
             uint64_t key = (uint64_t(__float_as_uint(rr)) << 32) | uint64_t(__float_as_uint(r3.z));
             best = key < best ? key : best;
+            return true;
         }
     }
+    return false;
 }
 
+template <bool kStats>
 __device__ inline void raster_tile(const RasterArgs& A, int64_t tile, int lane) {
     const float4* caps = map_caps(A.map, A.ntiles, A.fmt);
     SceneView S = scene_view(A.setup, A.n);
@@ -270,18 +276,23 @@ __device__ inline void raster_tile(const RasterArgs& A, int64_t tile, int lane) 
     bool has_dir = inside && (g.x != 0.0f || g.y != 0.0f || g.z != 0.0f);
     uint64_t best = kKeyEmpty;
     uint32_t count = counts[tile];
+    unsigned long long n_tri = 0, n_cov = 0;
     if (count <= uint32_t(A.depth)) {
         const uint32_t* lst = lists + tile * A.depth;
         for (uint32_t k = 0; k < count; ++k) {
             uint32_t rank = lst[k];
-            if ((k & 7u) == 0u) {
+            if ((k & 7u) == 0u && !(kStats && A.no_early_exit)) {
                 // nearest-first early exit: every pixel already beats the
                 // next triangle's depth lower bound
-                uint32_t worst = wave_max_u32(has_dir ? uint32_t(best >> 32) : 0u);
+                uint32_t worst = __builtin_amdgcn_readfirstlane(wave_max_u32(has_dir ? uint32_t(best >> 32) : 0u));
                 float lb = S.rec[4 * int64_t(rank) + 3].y;
                 if (lb > __uint_as_float(worst)) break;
             }
-            raster_one(S.rec, rank, g, best);
+            bool cov = raster_one(S.rec, rank, g, best);
+            if (kStats) {
+                n_tri += 1;
+                n_cov += __popcll(__ballot(cov));
+            }
         }
     } else {
         float4 tc0 = caps[2 * tile], tc1 = caps[2 * tile + 1];
@@ -292,9 +303,19 @@ __device__ inline void raster_tile(const RasterArgs& A, int64_t tile, int lane) 
                 int q = __ffsll((unsigned long long)m) - 1;
                 m &= m - 1;
                 uint32_t rk = uint32_t(__builtin_amdgcn_readlane(int(rank), q));
-                raster_one(S.rec, rk, g, best);
+                bool cov = raster_one(S.rec, rk, g, best);
+                if (kStats) {
+                    n_tri += 1;
+                    n_cov += __popcll(__ballot(cov));
+                }
             }
         });
+    }
+    if (kStats && lane == 0) {
+        atomicAdd(&A.stats[0], n_tri * (unsigned long long)__popcll(__ballot(has_dir)));
+        atomicAdd(&A.stats[1], n_cov);
+        atomicAdd(&A.stats[2], n_tri);
+        atomicAdd(&A.stats[3], 1ull);
     }
     if (inside) {
         int64_t o = int64_t(j) * A.W + i;
@@ -303,11 +324,12 @@ __device__ inline void raster_tile(const RasterArgs& A, int64_t tile, int lane) 
     }
 }
 
+template <bool kStats>
 __global__ __launch_bounds__(256) void k_raster(RasterArgs A) {
     int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
     if (tile >= A.ntiles) return;
-    raster_tile(A, tile, threadIdx.x & 63);
+    raster_tile<kStats>(A, tile, threadIdx.x & 63);
 }
 
 // ------------------------------------------------------------ launchers --
@@ -337,7 +359,8 @@ hipError_t launch_bin(const void* map, int32_t W, int32_t H, int32_t fmt, const 
 }
 
 hipError_t launch_raster(const void* map, int32_t W, int32_t H, int32_t fmt, const void* setup, int64_t n,
-                         const void* bins, int32_t depth, uint32_t* tri_id, float* out_depth, hipStream_t st) {
+                         const void* bins, int32_t depth, uint32_t* tri_id, float* out_depth, hipStream_t st,
+                         unsigned long long* stats = nullptr, int32_t no_early_exit = 0) {
     MapLayout ML = map_layout(W, H, fmt);
     RasterArgs A;
     A.map = map;
@@ -353,8 +376,15 @@ hipError_t launch_raster(const void* map, int32_t W, int32_t H, int32_t fmt, con
     A.bins = bins;
     A.tri_id = tri_id;
     A.out_depth = out_depth;
+    A.stats = stats;
+    A.no_early_exit = no_early_exit;
     int64_t blocks = (ML.ntiles + 3) / 4;
-    hipLaunchKernelGGL(k_raster, dim3(unsigned(blocks)), dim3(256), 0, st, A);
+    if (stats) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(stats), int64_t(8));
+        hipLaunchKernelGGL(k_raster<true>, dim3(unsigned(blocks)), dim3(256), 0, st, A);
+    } else {
+        hipLaunchKernelGGL(k_raster<false>, dim3(unsigned(blocks)), dim3(256), 0, st, A);
+    }
     return hipGetLastError();
 }
 

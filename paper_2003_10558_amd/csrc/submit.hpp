@@ -122,7 +122,9 @@ __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict
     A.bins = J.bins;
     A.tri_id = J.tri_id;
     A.out_depth = J.depth;
-    raster_tile(A, t - J.tile_off, threadIdx.x & 63);
+    A.stats = nullptr;
+    A.no_early_exit = 0;
+    raster_tile<false>(A, t - J.tile_off, threadIdx.x & 63);
 }
 
 hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t depth, void* ws, hipStream_t st) {

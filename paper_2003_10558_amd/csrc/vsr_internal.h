@@ -65,10 +65,12 @@ struct MapParams {
     int32_t ntx, nty;
     int32_t kind;       // +1: k > 0, 0: k == 0, -1: k < 0
     int32_t xmul;       // x = (2i+1-W) * xmul / xden, y = (2j+1-H) * xmul / yden
-    float xden, yden;
+    float xden, yden;   // denominators (rounded) ...
+    float xden_lo, yden_lo;  // ... and their rounding residuals
     float k;            // projection type k (divisor of the arc functions)
     float half;         // Omega / 2 in radians
     float kt;           // tan(k*Omega/2) (k>0) or sin(k*Omega/2) (k<0)
+    float kt_lo;        // rounding residual of kt
     float sig0;         // limit of sin(theta)/R at R = 0
     float l;            // cylindricity
     float c;            // anamorphic divisor l*(1-s)+s

@@ -58,6 +58,8 @@ _lib.vsr_map_unpack.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _vp]
 _lib.vsr_setup_tris.argtypes = [_vp, _i64, _vp, _i64, _vp]
 _lib.vsr_bin.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _i32, _u32, _vp, _i64, _vp]
 _lib.vsr_raster.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp]
+_lib.vsr_raster_stats.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _i32,
+                                  _vp]
 _lib.vsr_submit_bytes.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32]
 _lib.vsr_submit_bytes.restype = _i64
 _lib.vsr_submit.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _vp, _i64, _vp]
@@ -65,11 +67,11 @@ _lib.vsr_bin_overflow.argtypes = [_vp, _i32, ctypes.POINTER(_i64)]
 _lib.vsr_strerror.argtypes = [ctypes.c_int]
 _lib.vsr_strerror.restype = ctypes.c_char_p
 _lib.vsr_last_error.restype = ctypes.c_char_p
-for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_raster", "vsr_submit", "vsr_bin_overflow"):
+for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_raster", "vsr_raster_stats", "vsr_submit", "vsr_bin_overflow"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin",
-           "vsr_raster", "vsr_submit_bytes", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
+           "vsr_raster", "vsr_raster_stats", "vsr_submit_bytes", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
 
 
 def _check(rc: int) -> None:
@@ -149,6 +151,13 @@ def vsr_raster(view, fmt: int, map_buf, setup_buf, ntri: int, bins, bin_depth: i
     v = make_view(view)
     _check(_lib.vsr_raster(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), ntri, _ptr(bins), bin_depth,
                            _ptr(tri_id), _ptr(depth), _stream(stream)))
+
+
+def vsr_raster_stats(view, fmt: int, map_buf, setup_buf, ntri: int, bins, bin_depth: int, tri_id, depth, stats,
+                     no_early_exit: bool = False, stream=None) -> None:
+    v = make_view(view)
+    _check(_lib.vsr_raster_stats(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), ntri, _ptr(bins), bin_depth,
+                                 _ptr(tri_id), _ptr(depth), _ptr(stats), int(bool(no_early_exit)), _stream(stream)))
 
 
 def make_jobs(jobs: Sequence[tuple]):
