@@ -146,82 +146,302 @@ __device__ inline int64_t xcd_remap(int64_t b, int64_t nb) {
 }
 
 // ---------------------------------------------------------------- bin ---
+// One 256-thread workgroup per 16x16 super-tile (2x2 tiles; wave w owns tile
+// w).  The super-tile's cap bounds its four tile caps; the cell rectangles
+// of that cap are gathered once, and each candidate is tested against the
+// super cap and then against each of the four tile caps.  Survivors are
+// appended to the tiles' LDS lists, which are sorted (nearest first) and
+// written out.
+constexpr int kSupTiles = 4;
+
 struct BinArgs {
     const void* map;
     int64_t ntiles;
     int32_t fmt, depth, lds_cap, all;
+    int32_t ntx, nty;
     const void* setup;
     int64_t n;
     void* bins;
     uint32_t* status;  // overflowed-tile counter
 };
 
-__device__ inline void bin_tile(const BinArgs& A, int64_t tile, int lane, uint32_t* lst) {
+__device__ inline float4 empty_cap0() { return make_float4(0.f, 0.f, 1.f, 0.f); }
+__device__ inline float4 empty_cap1() { return make_float4(1.f, 0.f, kCapEmpty, 0.f); }
+
+// May a triangle (binning record a + unit edge normals) cover a pixel of
+// the tile with cap (c0, c1)?  Conservative, like tile_may_see.
+__device__ inline bool sub_may_see(float4 c0, float4 c1, float4 a, float3 n0, float3 n1, float3 n2) {
+    if (c1.z == kCapEmpty) return false;
+    if (c1.z == kCapWide) return true;
+    if (a.w < kBinWide) {
+        float dx = c0.x - a.x, dy = c0.y - a.y, dz = c0.z - a.z;
+        float chord2 = dx * dx + dy * dy + dz * dz;
+        float ch_t = sqrtf(fmaxf(0.0f, 1.0f - a.w * a.w));
+        float sm = c0.w * ch_t + c1.x * a.w;  // sin((rho_tile + rho_tri)/2)
+        if (chord2 > 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f) return false;
+    }
+    float3 c = f3(c0.x, c0.y, c0.z);
+    float lim = -c1.y - 1e-6f;
+    return !(dot3(n0, c) < lim || dot3(n1, c) < lim || dot3(n2, c) < lim);
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wsum, uint32_t& total) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wsum[w] = x;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int q = 0; q < w; ++q) base += s_wsum[q];
+    total = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+    __syncthreads();
+    return base + x - v;
+}
+
+__device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
+    extern __shared__ uint32_t lists[];  // kSupTiles x lds_cap
+    __shared__ float4 s_cap[kSupTiles][2];
+    __shared__ int s_rect[64][4];
+    __shared__ uint32_t s_ppre[65];
+    __shared__ uint32_t s_rb[256], s_pre[256], s_wsum[4], s_cnt[kSupTiles];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nsx = (A.ntx + 1) / 2;
+    const int sx = int(sidx % nsx), sy = int(sidx / nsx);
+    const int tx = 2 * sx + (w & 1), ty = 2 * sy + (w >> 1);
+    const bool present = tx < A.ntx && ty < A.nty;
+    const int64_t tile = int64_t(ty) * A.ntx + tx;
     const float4* caps = map_caps(A.map, A.ntiles, A.fmt);
-    float4 tc0 = caps[2 * tile], tc1 = caps[2 * tile + 1];
+    if (lane == 0) {
+        s_cap[w][0] = present ? caps[2 * tile] : empty_cap0();
+        s_cap[w][1] = present ? caps[2 * tile + 1] : empty_cap1();
+    }
+    if (tid < kSupTiles) s_cnt[tid] = 0;
+    __syncthreads();
+
+    float4 sc0[kSupTiles], sc1[kSupTiles];
+#pragma unroll
+    for (int q = 0; q < kSupTiles; ++q) {
+        sc0[q] = s_cap[q][0];
+        sc1[q] = s_cap[q][1];
+    }
+    // super-tile cap: bounds the four tile caps
+    bool any = false, wide = false;
+    float3 sum = f3(0.f, 0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < kSupTiles; ++q) {
+        if (sc1[q].z == kCapEmpty) continue;
+        any = true;
+        if (sc1[q].z == kCapWide) wide = true;
+        sum = add3(sum, f3(sc0[q].x, sc0[q].y, sc0[q].z));
+    }
+    float3 cs = f3(0.f, 0.f, 1.f);
+    float rho_s = kPi;
+    if (any && !wide) {
+        float len = sqrtf(dot3(sum, sum));
+        if (len > 1e-3f) {
+            cs = scale3(sum, 1.0f / len);
+            rho_s = 0.0f;
+#pragma unroll
+            for (int q = 0; q < kSupTiles; ++q) {
+                if (sc1[q].z == kCapEmpty) continue;
+                float3 d = sub3(cs, f3(sc0[q].x, sc0[q].y, sc0[q].z));
+                float ang = 2.0f * asinf(fminf(1.0f, 0.5f * sqrtf(dot3(d, d))));
+                rho_s = fmaxf(rho_s, ang + 2.0f * asinf(fminf(1.0f, sc0[q].w)));
+            }
+            rho_s = rho_s * (1.0f + kCapRelMargin) + 1e-6f;
+        }
+        if (!(rho_s < kHalfPi)) wide = true;
+    }
+    float sh_s = 1.0f, ch_s = 0.0f;
+    if (!wide) sincosf(0.5f * rho_s, &sh_s, &ch_s);
+
     SceneView S = scene_view(A.setup, A.n);
-    char* bb = reinterpret_cast<char*>(A.bins);
-    uint32_t* counts = reinterpret_cast<uint32_t*>(bb + 256);
-    uint32_t* lists = reinterpret_cast<uint32_t*>(bb + 256 + align256(A.ntiles * 4));
-    uint32_t count = 0;
-    const uint32_t cap_n = uint32_t(A.lds_cap);
-    auto push = [&](uint32_t rank, bool pass) {
-        uint64_t m = __ballot(pass);
-        uint32_t pos = count + __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
-        if (pass && pos < cap_n) lst[pos] = rank;
-        count += uint32_t(__popcll(m));
-    };
-    if (A.all) {
-        if (tc1.z != kCapEmpty) {
-            for (int64_t k = 0; k < A.n; k += 64) {
-                int64_t idx = k + lane;
-                bool valid = idx < A.n;
-                bool pass = valid && S.cap[2 * idx + 1].z != kCapEmpty;
-                push(uint32_t(idx), pass);
+    const float4* binrec =
+        reinterpret_cast<const float4*>(reinterpret_cast<const char*>(A.setup) + setup_layout(A.n).binrec_off);
+    const uint32_t lcap = uint32_t(A.lds_cap);
+
+    auto append = [&](uint32_t mask, uint32_t rank) {
+#pragma unroll
+        for (int q = 0; q < kSupTiles; ++q) {
+            if (mask & (1u << q)) {
+                uint32_t pos = atomicAdd(&s_cnt[q], 1u);
+                if (pos < lcap) lists[q * lcap + pos] = rank;
             }
         }
-    } else {
-        gather_candidates(S, tc0, tc1, lane, [&](uint32_t rank, bool valid) {
-            bool pass = valid && candidate_test(S, rank, tc0, tc1);
-            push(rank, pass);
-        });
+    };
+
+    if (any && A.all) {
+        uint32_t live_mask = 0;
+#pragma unroll
+        for (int q = 0; q < kSupTiles; ++q)
+            if (sc1[q].z != kCapEmpty) live_mask |= 1u << q;
+        for (int64_t k0 = 0; k0 < A.n; k0 += 256) {
+            int64_t r = k0 + tid;
+            if (r < A.n && S.cap[2 * r + 1].z != kCapEmpty) append(live_mask, uint32_t(r));
+        }
+    } else if (any) {
+        // (level, face) rectangles: lane p of wave 0 handles level p/6, face p%6
+        if (tid < 64) {
+            int iu0 = 1, iu1 = 0, iv0 = 1, iv1 = 0;
+            if (tid < 6 * kLevels) {
+                int L = tid / 6, face = tid % 6, M = 1 << L;
+                int64_t fb = level_base(L) + int64_t(face) * M * M;
+                if (S.cell_start[fb] != S.cell_start[fb + int64_t(M) * M]) {
+                    float RL = (L == 0) ? kHalfPi : kQuarterPi / float(M);
+                    float alpha = (wide ? kPi : rho_s) + RL + 1e-5f;
+                    if (!face_cells(cs, alpha, face, M, iu0, iu1, iv0, iv1)) {
+                        iu0 = 1;
+                        iu1 = 0;
+                    }
+                }
+            }
+            s_rect[tid][0] = iu0;
+            s_rect[tid][1] = iu1;
+            s_rect[tid][2] = iv0;
+            s_rect[tid][3] = iv1;
+            // prefix of row counts over the pairs
+            uint32_t nr = (iu0 <= iu1) ? uint32_t(iv1 - iv0 + 1) : 0u, x = nr;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                uint32_t y = __shfl_up(x, o, 64);
+                if (tid >= o) x += y;
+            }
+            s_ppre[tid] = x - nr;
+            if (tid == 63) s_ppre[64] = x;
+        }
+        __syncthreads();
+        const uint32_t nrows_all = s_ppre[64];
+        // all rows of all pairs, 256 at a time: one contiguous run each
+        for (uint32_t rb = 0; rb < nrows_all; rb += 256) {
+            const uint32_t nb = min(256u, nrows_all - rb);
+            uint32_t len = 0;
+            if (uint32_t(tid) < nb) {
+                uint32_t r = rb + tid;
+                int lo = 0, hi = 63;  // pair holding row r: last p with s_ppre[p] <= r
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (s_ppre[mid] <= r)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                const int L = lo / 6, face = lo % 6, M = 1 << L;
+                const int64_t row = level_base(L) + int64_t(face) * M * M +
+                                    int64_t(s_rect[lo][2] + int(r - s_ppre[lo])) * M;
+                uint32_t b = S.cell_start[row + s_rect[lo][0]], e = S.cell_start[row + s_rect[lo][1] + 1];
+                s_rb[tid] = b;
+                len = e - b;
+            }
+            uint32_t total;
+            uint32_t pre = block_exclusive_scan(len, s_wsum, total);
+            s_pre[tid] = pre;
+            __syncthreads();
+            // candidates, two per thread per pass so their loads overlap
+            for (uint32_t k0 = 0; k0 < total; k0 += 512) {
+                float4 a[2];
+                int64_t idx[2];
+                bool valid[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    uint32_t k = k0 + uint32_t(h * 256 + tid);
+                    valid[h] = k < total;
+                    idx[h] = 0;
+                    if (valid[h]) {
+                        int lo = 0, hi = int(nb) - 1;  // row holding candidate k
+                        while (lo < hi) {
+                            int mid = (lo + hi + 1) >> 1;
+                            if (s_pre[mid] <= k)
+                                lo = mid;
+                            else
+                                hi = mid - 1;
+                        }
+                        idx[h] = int64_t(s_rb[lo]) + (k - s_pre[lo]);
+                        a[h] = binrec[4 * idx[h]];
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (!valid[h]) continue;
+                    bool pass = true;
+                    if (!wide && a[h].w < kBinWide) {
+                        float dx = cs.x - a[h].x, dy = cs.y - a[h].y, dz = cs.z - a[h].z;
+                        float chord2 = dx * dx + dy * dy + dz * dz;
+                        float ch_t = sqrtf(fmaxf(0.0f, 1.0f - a[h].w * a[h].w));
+                        float sm = sh_s * ch_t + ch_s * a[h].w;
+                        pass = chord2 <= 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f;
+                    }
+                    if (pass) {
+                        const float4* br = binrec + 4 * idx[h];
+                        float4 b4 = br[1], c4 = br[2], d4 = br[3];
+                        float3 n0 = f3(b4.x, b4.y, b4.z), n1 = f3(c4.x, c4.y, c4.z), n2 = f3(d4.x, d4.y, d4.z);
+                        uint32_t mask = 0;
+#pragma unroll
+                        for (int q = 0; q < kSupTiles; ++q)
+                            if (sub_may_see(sc0[q], sc1[q], a[h], n0, n1, n2)) mask |= 1u << q;
+                        if (mask) append(mask, __float_as_uint(b4.w));
+                    }
+                }
+            }
+            __syncthreads();
+        }
     }
     __syncthreads();
-    if (count <= uint32_t(A.depth)) {
-        // bitonic sort of the first count entries, padded to a power of two
-        uint32_t np = 1;
-        while (np < count) np <<= 1;
-        for (uint32_t i = count + lane; i < np; i += 64) lst[i] = 0xFFFFFFFFu;
-        __syncthreads();
-        for (uint32_t k = 2; k <= np; k <<= 1) {
-            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                for (uint32_t i = lane; i < np; i += 64) {
+
+    // sort every tile's list (same network size in all waves: barriers are
+    // block-wide), then write it out
+    const uint32_t depth = uint32_t(A.depth);
+    uint32_t npmax = 1;
+#pragma unroll
+    for (int q = 0; q < kSupTiles; ++q) {
+        uint32_t c = s_cnt[q];
+        if (c <= depth)
+            while (npmax < c) npmax <<= 1;
+    }
+    const uint32_t cnt = s_cnt[w];
+    const bool keep = present && cnt <= depth;
+    uint32_t* my = lists + w * lcap;
+    if (keep)
+        for (uint32_t i = cnt + lane; i < npmax; i += 64) my[i] = 0xFFFFFFFFu;
+    __syncthreads();
+    for (uint32_t k = 2; k <= npmax; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            if (keep) {
+                for (uint32_t i = lane; i < npmax; i += 64) {
                     uint32_t l = i ^ j;
                     if (l > i) {
-                        uint32_t a = lst[i], b = lst[l];
+                        uint32_t x = my[i], y = my[l];
                         bool up = (i & k) == 0;
-                        if ((a > b) == up) {
-                            lst[i] = b;
-                            lst[l] = a;
+                        if ((x > y) == up) {
+                            my[i] = y;
+                            my[l] = x;
                         }
                     }
                 }
-                __syncthreads();
             }
+            __syncthreads();
         }
-        uint32_t* out = lists + tile * A.depth;
-        for (uint32_t i = lane; i < count; i += 64) out[i] = lst[i];
-    } else if (lane == 0) {
-        atomicAdd(A.status, 1u);  // overflowed tiles
     }
-    if (lane == 0) counts[tile] = count;
+    if (present) {
+        char* bb = reinterpret_cast<char*>(A.bins);
+        uint32_t* counts = reinterpret_cast<uint32_t*>(bb + 256);
+        uint32_t* out = reinterpret_cast<uint32_t*>(bb + 256 + align256(A.ntiles * 4)) + tile * A.depth;
+        if (keep)
+            for (uint32_t i = lane; i < cnt; i += 64) out[i] = my[i];
+        if (lane == 0) {
+            counts[tile] = cnt;
+            if (!keep) atomicAdd(A.status, 1u);
+        }
+    }
 }
 
-__global__ __launch_bounds__(64) void k_bin(BinArgs A) {
-    extern __shared__ uint32_t lst[];
-    int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    bin_tile(A, tile, threadIdx.x, lst);
-}
+__global__ __launch_bounds__(256) void k_bin(BinArgs A) { bin_super(A, xcd_remap(blockIdx.x, gridDim.x)); }
 
 __global__ __launch_bounds__(64) void k_zero_u32(uint32_t* p, int64_t n) {
     int64_t i = int64_t(blockIdx.x) * 64 + threadIdx.x;
@@ -242,10 +462,9 @@ struct RasterArgs {
     int32_t no_early_exit;      // instrumented variant only: process whole lists
 };
 
-// One triangle against the lane's pixel; returns whether it covers it.
-__device__ inline bool raster_one(const float4* __restrict__ rec, uint32_t rank, float3 g, uint64_t& best) {
-    const float4* r = rec + 4 * int64_t(rank);
-    float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+// One triangle (record r0..r3) against the lane's pixel; returns whether it
+// covers it.
+__device__ inline bool raster_rec(float4 r0, float4 r1, float4 r2, float4 r3, float3 g, uint64_t& best) {
     float e0 = fmaf(r0.z, g.z, fmaf(r0.y, g.y, r0.x * g.x));
     float e1 = fmaf(r1.z, g.z, fmaf(r1.y, g.y, r1.x * g.x));
     float e2 = fmaf(r2.z, g.z, fmaf(r2.y, g.y, r2.x * g.x));
@@ -259,6 +478,11 @@ __device__ inline bool raster_one(const float4* __restrict__ rec, uint32_t rank,
         }
     }
     return false;
+}
+
+__device__ inline bool raster_one(const float4* __restrict__ rec, uint32_t rank, float3 g, uint64_t& best) {
+    const float4* r = rec + 4 * int64_t(rank);
+    return raster_rec(r[0], r[1], r[2], r[3], g, best);
 }
 
 template <bool kStats>
@@ -278,21 +502,57 @@ __device__ inline void raster_tile(const RasterArgs& A, int64_t tile, int lane) 
     uint32_t count = counts[tile];
     unsigned long long n_tri = 0, n_cov = 0;
     if (count <= uint32_t(A.depth)) {
+        // Records are fetched 16 at a time: lane l loads float4 (l & 3) of
+        // triangle (l >> 2) of the group, one vector load for the whole
+        // wave, staged in LDS and read back as broadcasts.  The next group's
+        // records and the group after's ranks are in flight meanwhile.
+        __shared__ float4 s_stage[4][64];
+        float4* stg = s_stage[threadIdx.x >> 6];
         const uint32_t* lst = lists + tile * A.depth;
-        for (uint32_t k = 0; k < count; ++k) {
-            uint32_t rank = lst[k];
-            if ((k & 7u) == 0u && !(kStats && A.no_early_exit)) {
-                // nearest-first early exit: every pixel already beats the
-                // next triangle's depth lower bound
-                uint32_t worst = __builtin_amdgcn_readfirstlane(wave_max_u32(has_dir ? uint32_t(best >> 32) : 0u));
-                float lb = S.rec[4 * int64_t(rank) + 3].y;
-                if (lb > __uint_as_float(worst)) break;
+        const float4* rec = S.rec;
+        const uint32_t ngroups = (count + 15u) >> 4;
+        const uint32_t sub = uint32_t(lane) >> 2, part = uint32_t(lane) & 3u;
+        uint32_t rk = sub < count ? lst[sub] : 0u;
+        float4 v = rec[4 * int64_t(rk) + part];
+        rk = 16u + sub < count ? lst[16u + sub] : 0u;
+        bool done = false;
+        for (uint32_t gi = 0; gi < ngroups && !done; ++gi) {
+            stg[lane] = v;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (gi + 1 < ngroups) v = rec[4 * int64_t(rk) + part];
+            if (gi + 2 < ngroups) {
+                uint32_t e = (gi + 2) * 16u + sub;
+                rk = e < count ? lst[e] : 0u;
             }
-            bool cov = raster_one(S.rec, rank, g, best);
-            if (kStats) {
-                n_tri += 1;
-                n_cov += __popcll(__ballot(cov));
+            const uint32_t nt = min(16u, count - gi * 16u);
+            for (uint32_t t8 = 0; t8 < nt; t8 += 8) {
+                if (!(kStats && A.no_early_exit)) {
+                    // nearest-first early exit: every pixel already beats this
+                    // triangle's depth lower bound (and so every later one's)
+                    float lb = __builtin_amdgcn_readfirstlane(stg[4 * t8 + 3].y);
+                    uint32_t worst = wave_max_u32_dpp(has_dir ? uint32_t(best >> 32) : 0u);
+                    if (lb > __uint_as_float(worst)) {
+                        done = true;
+                        break;
+                    }
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < 8; ++u) {
+                    const uint32_t t = t8 + u;
+                    if (t < nt) {
+                        float4 c0 = stg[4 * t], c1 = stg[4 * t + 1], c2 = stg[4 * t + 2], c3 = stg[4 * t + 3];
+                        bool cov = raster_rec(c0, c1, c2, c3, g, best);
+                        if (kStats) {
+                            n_tri += 1;
+                            n_cov += __popcll(__ballot(cov));
+                        }
+                    }
+                }
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
     } else {
         float4 tc0 = caps[2 * tile], tc1 = caps[2 * tile + 1];
@@ -311,8 +571,9 @@ __device__ inline void raster_tile(const RasterArgs& A, int64_t tile, int lane) 
             }
         });
     }
+    unsigned long long npix = kStats ? (unsigned long long)__popcll(__ballot(has_dir)) : 0ull;
     if (kStats && lane == 0) {
-        atomicAdd(&A.stats[0], n_tri * (unsigned long long)__popcll(__ballot(has_dir)));
+        atomicAdd(&A.stats[0], n_tri * npix);
         atomicAdd(&A.stats[1], n_cov);
         atomicAdd(&A.stats[2], n_tri);
         atomicAdd(&A.stats[3], 1ull);
@@ -335,9 +596,11 @@ __global__ __launch_bounds__(256) void k_raster(RasterArgs A) {
 // ------------------------------------------------------------ launchers --
 int32_t bin_lds_cap(int32_t depth) {
     int32_t c = 64;
-    while (c < depth + 1) c <<= 1;  // room for depth+1 entries detects overflow
+    while (c < depth) c <<= 1;
     return c;
 }
+
+int64_t bin_grid(int32_t ntx, int32_t nty) { return int64_t((ntx + 1) / 2) * ((nty + 1) / 2); }
 
 hipError_t launch_bin(const void* map, int32_t W, int32_t H, int32_t fmt, const void* setup, int64_t n, int32_t depth,
                       bool all, void* bins, hipStream_t st) {
@@ -349,12 +612,15 @@ hipError_t launch_bin(const void* map, int32_t W, int32_t H, int32_t fmt, const 
     A.depth = depth;
     A.lds_cap = bin_lds_cap(depth);
     A.all = all ? 1 : 0;
+    A.ntx = ML.ntx;
+    A.nty = ML.nty;
     A.setup = setup;
     A.n = n;
     A.bins = bins;
     A.status = reinterpret_cast<uint32_t*>(bins);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(bins), int64_t(64));
-    hipLaunchKernelGGL(k_bin, dim3(unsigned(ML.ntiles)), dim3(64), size_t(A.lds_cap) * 4, st, A);
+    hipLaunchKernelGGL(k_bin, dim3(unsigned(bin_grid(ML.ntx, ML.nty))), dim3(256),
+                       size_t(kSupTiles) * A.lds_cap * 4, st, A);
     return hipGetLastError();
 }
 

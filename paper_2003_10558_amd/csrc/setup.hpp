@@ -172,16 +172,19 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t* __rest
     hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of `total` counters by one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ a, int64_t total) {
-    __shared__ uint32_t part[1024];
-    int64_t per = (total + 1023) / 1024;
-    int64_t b = int64_t(threadIdx.x) * per, e = min(total, b + per);
+// Exclusive scan of one digit's row of per-block counts (one workgroup per
+// digit); the row total goes to tot[digit].
+__global__ __launch_bounds__(256) void k_rs_scan_rows(uint32_t* __restrict__ hist, int64_t nblocks,
+                                                      uint32_t* __restrict__ tot) {
+    __shared__ uint32_t part[256];
+    uint32_t* a = hist + int64_t(blockIdx.x) * nblocks;
+    int64_t per = (nblocks + 255) / 256;
+    int64_t b = int64_t(threadIdx.x) * per, e = min(nblocks, b + per);
     uint32_t s = 0;
     for (int64_t i = b; i < e; ++i) s += a[i];
     part[threadIdx.x] = s;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
+    for (int o = 1; o < 256; o <<= 1) {
         uint32_t v = threadIdx.x >= unsigned(o) ? part[threadIdx.x - o] : 0u;
         __syncthreads();
         part[threadIdx.x] += v;
@@ -193,17 +196,32 @@ __global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ a, int6
         a[i] = run;
         run += v;
     }
+    if (threadIdx.x == 255) tot[blockIdx.x] = part[255];
+}
+
+// Exclusive scan of the 256 digit totals, in place.
+__global__ __launch_bounds__(256) void k_rs_scan_tot(uint32_t* __restrict__ tot) {
+    __shared__ uint32_t part[256];
+    part[threadIdx.x] = tot[threadIdx.x];
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        uint32_t v = threadIdx.x >= unsigned(o) ? part[threadIdx.x - o] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    tot[threadIdx.x] = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0u;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                              const uint32_t* __restrict__ vin,
                                                              uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              int64_t n, int shift, const uint32_t* __restrict__ offs,
-                                                             int64_t nblocks) {
+                                                             int64_t nblocks, const uint32_t* __restrict__ base_of) {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[kSortThreads / 64][256];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    run[tid] = offs[int64_t(tid) * nblocks + blockIdx.x];
+    run[tid] = base_of[tid] + offs[int64_t(tid) * nblocks + blockIdx.x];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int64_t base = int64_t(blockIdx.x) * kSortBlock;
     for (int r = 0; r < kSortItems; ++r) {
@@ -244,10 +262,12 @@ static hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t*
     bool b = false;
     for (int shift = 0; shift < bits; shift += 8) {
         uint32_t *ki = b ? kb : ka, *vi = b ? vb : va, *ko = b ? ka : kb, *vo = b ? va : vb;
+        uint32_t* tot = hist + 256 * nb;
         hipLaunchKernelGGL(k_rs_hist, dim3(unsigned(nb)), dim3(kSortThreads), 0, st, ki, n, shift, hist, nb);
-        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, hist, 256 * nb);
+        hipLaunchKernelGGL(k_rs_scan_rows, dim3(256), dim3(256), 0, st, hist, nb, tot);
+        hipLaunchKernelGGL(k_rs_scan_tot, dim3(1), dim3(256), 0, st, tot);
         hipLaunchKernelGGL(k_rs_scatter, dim3(unsigned(nb)), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n, shift,
-                           hist, nb);
+                           hist, nb, tot);
         b = !b;
     }
     *in_b = b;
@@ -270,6 +290,24 @@ __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ or
     order[r] = id;
     key2[r] = bucket[id];
     val2[r] = uint32_t(r);
+}
+
+// Cell-ordered copies: cell_list[k] = rank of the k-th entry and its
+// binning record (cap + edge normals).
+__global__ __launch_bounds__(256) void k_cell_records(const uint32_t* __restrict__ ranks, int64_t n,
+                                                      const float4* __restrict__ rec, const float4* __restrict__ cap,
+                                                      uint32_t* __restrict__ cell_list, float4* __restrict__ binrec) {
+    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t r = ranks[k];
+    cell_list[k] = r;
+    float4 c0 = cap[2 * int64_t(r)], c1 = cap[2 * int64_t(r) + 1];
+    float4 r0 = rec[4 * int64_t(r)], r1 = rec[4 * int64_t(r) + 1], r2 = rec[4 * int64_t(r) + 2];
+    float sh = (c1.z == kCapWide) ? kBinWide : c0.w;
+    binrec[4 * k + 0] = make_float4(c0.x, c0.y, c0.z, sh);
+    binrec[4 * k + 1] = make_float4(r0.x, r0.y, r0.z, __uint_as_float(r));
+    binrec[4 * k + 2] = make_float4(r1.x, r1.y, r1.z, 0.0f);
+    binrec[4 * k + 3] = make_float4(r2.x, r2.y, r2.z, 0.0f);
 }
 
 // cell_start[b] = first position whose bucket is >= b (lower bound).
@@ -315,8 +353,8 @@ hipError_t launch_setup(const float* xyz, int64_t n, void* setup, hipStream_t st
         if (e != hipSuccess) return e;
         uint32_t* sk = in3 ? k3 : k2;
         uint32_t* sv = in3 ? v3 : v2;
-        e = hipMemcpyAsync(U(L.cell_list_off), sv, size_t(n) * 4, hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_cell_records, dim3(blocks), dim3(256), 0, st, sv, n, F4(L.rec_off), F4(L.cap_off),
+                           U(L.cell_list_off), F4(L.binrec_off));
         hipLaunchKernelGGL(k_cell_start, dim3(unsigned((kNumBuckets + 1 + 255) / 256)), dim3(256), 0, st, sk, n,
                            U(L.cell_start_off));
     } else {

@@ -26,6 +26,8 @@ struct JobDesc {
     float* depth;
     int64_t tile_off;  // first global tile of this job
     int64_t ntiles;
+    int64_t stile_off;  // first global super-tile (binning) of this job
+    int32_t ntx, nty;
 };
 
 constexpr int kJobChunk = 8;
@@ -72,20 +74,22 @@ __device__ inline int find_job(const JobDesc* __restrict__ T, int njobs, int64_t
     return lo;
 }
 
-__global__ __launch_bounds__(256) void k_submit_map(const JobDesc* __restrict__ T, int njobs, int64_t total) {
-    int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    int64_t t = int64_t(blockIdx.x) * 4 + w;
-    if (t >= total) return;
-    int jb = find_job(T, njobs, t);
-    const JobDesc& J = T[jb];
-    build_map_tile(J.P, J.map, J.ntiles, t - J.tile_off, threadIdx.x & 63);
+__device__ inline int find_job_super(const JobDesc* __restrict__ T, int njobs, int64_t t) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (T[mid].stile_off <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
 }
 
-__global__ __launch_bounds__(64) void k_submit_bin(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
-                                                   int32_t depth, int32_t lds_cap, uint32_t* status) {
-    extern __shared__ uint32_t lst[];
+__global__ __launch_bounds__(256) void k_submit_bin(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
+                                                    int32_t depth, int32_t lds_cap, uint32_t* status) {
     int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    int jb = find_job(T, njobs, t);
+    int jb = find_job_super(T, njobs, t);
     const JobDesc& J = T[jb];
     BinArgs A;
     A.map = J.map;
@@ -94,11 +98,22 @@ __global__ __launch_bounds__(64) void k_submit_bin(const JobDesc* __restrict__ T
     A.depth = depth;
     A.lds_cap = lds_cap;
     A.all = 0;
+    A.ntx = J.ntx;
+    A.nty = J.nty;
     A.setup = J.setup;
     A.n = J.ntri;
     A.bins = J.bins;
     A.status = status;
-    bin_tile(A, t - J.tile_off, threadIdx.x, lst);
+    bin_super(A, t - J.stile_off);
+}
+
+__global__ __launch_bounds__(256) void k_submit_map(const JobDesc* __restrict__ T, int njobs, int64_t total) {
+    int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    int64_t t = int64_t(blockIdx.x) * 4 + w;
+    if (t >= total) return;
+    int jb = find_job(T, njobs, t);
+    const JobDesc& J = T[jb];
+    build_map_tile(J.P, J.map, J.ntiles, t - J.tile_off, threadIdx.x & 63);
 }
 
 __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
@@ -132,6 +147,7 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
     char* base = reinterpret_cast<char*>(ws);
     JobDesc* table = reinterpret_cast<JobDesc*>(base + W.table_off);
     int64_t off = W.data_off, tiles = 0;
+    int64_t stiles = 0;
     JobChunk chunk;
     chunk.first = 0;
     chunk.count = 0;
@@ -145,6 +161,10 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
         off += ML.bytes;
         D.bins = base + off;
         off += BL.bytes;
+        D.ntx = ML.ntx;
+        D.nty = ML.nty;
+        D.stile_off = stiles;
+        stiles += bin_grid(ML.ntx, ML.nty);
         D.setup = jobs[q].setup;
         D.ntri = jobs[q].ntri;
         D.tri_id = jobs[q].tri_id;
@@ -160,8 +180,8 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
     }
     hipLaunchKernelGGL(k_submit_map, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, tiles);
     int32_t cap = bin_lds_cap(depth);
-    hipLaunchKernelGGL(k_submit_bin, dim3(unsigned(tiles)), dim3(64), size_t(cap) * 4, st, table, njobs, fmt, depth,
-                       cap, reinterpret_cast<uint32_t*>(ws));
+    hipLaunchKernelGGL(k_submit_bin, dim3(unsigned(stiles)), dim3(256), size_t(kSupTiles) * cap * 4, st, table, njobs,
+                       fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
     hipLaunchKernelGGL(k_submit_raster, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, fmt, depth,
                        tiles);
     return hipGetLastError();

@@ -81,7 +81,7 @@ struct MapParams {
 struct SetupLayout {
     int64_t n;
     int64_t nblocks;    // radix-sort blocks
-    int64_t rec_off, cap_off, cell_list_off, cell_start_off, order_off;
+    int64_t rec_off, cap_off, cell_list_off, cell_start_off, order_off, binrec_off;
     int64_t rec_id_off, cap_id_off, key_a_off, val_a_off, key_b_off, val_b_off, bucket_off, hist_off;
     int64_t bytes;
 };
@@ -100,6 +100,7 @@ __host__ __device__ inline SetupLayout setup_layout(int64_t n) {
     s.cell_list_off = o;  o += align256(n * 4);
     s.cell_start_off = o; o += align256((kNumBuckets + 1) * 4);
     s.order_off = o;      o += align256(n * 4);
+    s.binrec_off = o;     o += align256(n * 64);
     s.rec_id_off = o;     o += align256(n * 64);
     s.cap_id_off = o;     o += align256(n * 32);
     s.key_a_off = o;      o += align256(n * 4);
@@ -107,7 +108,7 @@ __host__ __device__ inline SetupLayout setup_layout(int64_t n) {
     s.key_b_off = o;      o += align256(n * 4);
     s.val_b_off = o;      o += align256(n * 4);
     s.bucket_off = o;     o += align256(n * 4);
-    s.hist_off = o;       o += align256(256 * (s.nblocks > 0 ? s.nblocks : 1) * 4);
+    s.hist_off = o;       o += align256((256 * (s.nblocks > 0 ? s.nblocks : 1) + 256) * 4);
     s.bytes = o;
     return s;
 }
@@ -159,6 +160,23 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
         v = w > v ? w : v;
     }
     return v;
+}
+
+// Wave-wide maximum of unsigned values with DPP row shifts and row
+// broadcasts; lanes that a DPP step does not feed read 0 (the identity).
+// Lane 63 ends with the maximum, returned to every lane as a scalar.
+template <int kCtrl, int kRowMask, bool kBound>
+__device__ inline uint32_t dpp_max_step(uint32_t v) {
+    return max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xF, kBound));
+}
+__device__ inline uint32_t wave_max_u32_dpp(uint32_t v) {
+    v = dpp_max_step<0x111, 0xF, true>(v);   // row_shr:1
+    v = dpp_max_step<0x112, 0xF, true>(v);   // row_shr:2
+    v = dpp_max_step<0x114, 0xF, true>(v);   // row_shr:4
+    v = dpp_max_step<0x118, 0xF, true>(v);   // row_shr:8
+    v = dpp_max_step<0x142, 0xA, false>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_max_step<0x143, 0xC, false>(v);  // row_bcast:31 into rows 2 and 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // Octahedral unit-vector encoding (two fp16).  The all-ones word marks a
@@ -217,6 +235,13 @@ __device__ inline float3 load_dir(const void* map, int32_t fmt, int64_t ntiles, 
     int64_t q = tile * kTilePix + lane;
     return f3(p[q], p[plane + q], p[2 * plane + q]);
 }
+
+// Binning record of a triangle, stored in cell order (entry k belongs to
+// cell_list[k]) so that a run of cells streams as coalesced 64-byte loads:
+//   a = (cap centre xyz, sin(rho/2), or kBinWide for a useless cap)
+//   b = (n0 xyz, rank bits), c = (n1 xyz, 0), d = (n2 xyz, 0)
+// with n_i the oriented unit edge-plane normals.
+constexpr float kBinWide = 2.0f;
 
 // Tile cap record: c0 = (centre.xyz, sin(rho/2)), c1 = (cos(rho/2), sin(rho), flags, 0)
 constexpr float kCapWide = 1.0f;   // cap radius >= pi/2: no culling possible
