@@ -12,19 +12,19 @@
 // streamed 64 candidates at a time, one per lane, through the conservative
 // cap and edge-plane test; survivors are compacted with ballot + mbcnt.
 //
-// Binning keeps the survivors in LDS, sorts them (they are triangle ranks,
-// i.e. nearest-first order) with a bitonic network and writes the tile's
-// list.
+// Binning keeps the survivors in LDS and writes each tile's list ordered by
+// depth bucket (triangle ranks are nearest-first; a bucket is a run of
+// consecutive ranks) with a counting sort.
 //
 // Rasterization: each lane owns one pixel direction g and a 64-bit z-buffer
-// key (depth bits << 32 | triangle id).  For every listed triangle, read
-// with wave-uniform scalar loads, the lane forms the three oriented
-// edge-plane values n_i . g (section 1.1); all three > 0 is the binary step
-// of section 1.1.1.  Covered lanes take r = d / (g . N) (section 1.1.4) and
-// keep the smaller key (depth-pass test, section 1.4; ties to the lower id).
-// Lists are nearest first: once every pixel of the tile holds a depth below
-// the next triangle's depth lower bound, no later triangle can win and the
-// wave stops.
+// key (depth bits << 32 | triangle id).  For every listed triangle, staged
+// through LDS and read as wave-wide broadcasts, the lane forms the three
+// oriented edge-plane values n_i . g (section 1.1); all three > 0 is the
+// binary step of section 1.1.1.  Covered lanes take r = d / (g . N)
+// (section 1.1.4) and keep the smaller key (depth-pass test, section 1.4;
+// ties to the lower id).  Lists are in bucket order: once every pixel of the
+// tile holds a depth below the lower bound of the current bucket, no later
+// triangle can win and the wave stops.
 #pragma once
 #include "vsr_internal.h"
 
@@ -150,8 +150,8 @@ __device__ inline int64_t xcd_remap(int64_t b, int64_t nb) {
 // w).  The super-tile's cap bounds its four tile caps; the cell rectangles
 // of that cap are gathered once, and each candidate is tested against the
 // super cap and then against each of the four tile caps.  Survivors are
-// appended to the tiles' LDS lists, which are sorted (nearest first) and
-// written out.
+// appended to the tiles' LDS lists, which are ordered by depth bucket
+// (nearest first) and written out.
 constexpr int kSupTiles = 4;
 
 struct BinArgs {
@@ -208,6 +208,8 @@ __device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
     __shared__ float4 s_cap[kSupTiles][2];
     __shared__ int s_rect[64][4];
     __shared__ uint32_t s_ppre[65];
+    __shared__ float4 s_sup[2];
+    __shared__ uint32_t s_bk[kSupTiles][kDepthBuckets];
     __shared__ uint32_t s_rb[256], s_pre[256], s_wsum[4], s_cnt[kSupTiles];
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -231,36 +233,43 @@ __device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
         sc0[q] = s_cap[q][0];
         sc1[q] = s_cap[q][1];
     }
-    // super-tile cap: bounds the four tile caps
-    bool any = false, wide = false;
-    float3 sum = f3(0.f, 0.f, 0.f);
-#pragma unroll
-    for (int q = 0; q < kSupTiles; ++q) {
-        if (sc1[q].z == kCapEmpty) continue;
-        any = true;
-        if (sc1[q].z == kCapWide) wide = true;
-        sum = add3(sum, f3(sc0[q].x, sc0[q].y, sc0[q].z));
-    }
-    float3 cs = f3(0.f, 0.f, 1.f);
-    float rho_s = kPi;
-    if (any && !wide) {
-        float len = sqrtf(dot3(sum, sum));
-        if (len > 1e-3f) {
-            cs = scale3(sum, 1.0f / len);
-            rho_s = 0.0f;
-#pragma unroll
-            for (int q = 0; q < kSupTiles; ++q) {
-                if (sc1[q].z == kCapEmpty) continue;
-                float3 d = sub3(cs, f3(sc0[q].x, sc0[q].y, sc0[q].z));
-                float ang = 2.0f * asinf(fminf(1.0f, 0.5f * sqrtf(dot3(d, d))));
-                rho_s = fmaxf(rho_s, ang + 2.0f * asinf(fminf(1.0f, sc0[q].w)));
-            }
-            rho_s = rho_s * (1.0f + kCapRelMargin) + 1e-6f;
+    // super-tile cap: bounds the four tile caps (computed once, shared)
+    if (tid == 0) {
+        bool any0 = false, wide0 = false;
+        float3 sum = f3(0.f, 0.f, 0.f);
+        for (int q = 0; q < kSupTiles; ++q) {
+            if (sc1[q].z == kCapEmpty) continue;
+            any0 = true;
+            if (sc1[q].z == kCapWide) wide0 = true;
+            sum = add3(sum, f3(sc0[q].x, sc0[q].y, sc0[q].z));
         }
-        if (!(rho_s < kHalfPi)) wide = true;
+        float3 c = f3(0.f, 0.f, 1.f);
+        float rho = kPi;
+        if (any0 && !wide0) {
+            float len = sqrtf(dot3(sum, sum));
+            if (len > 1e-3f) {
+                c = scale3(sum, 1.0f / len);
+                rho = 0.0f;
+                for (int q = 0; q < kSupTiles; ++q) {
+                    if (sc1[q].z == kCapEmpty) continue;
+                    float3 d = sub3(c, f3(sc0[q].x, sc0[q].y, sc0[q].z));
+                    float ang = 2.0f * asinf(fminf(1.0f, 0.5f * sqrtf(dot3(d, d))));
+                    rho = fmaxf(rho, ang + 2.0f * asinf(fminf(1.0f, sc0[q].w)));
+                }
+                rho = rho * (1.0f + kCapRelMargin) + 1e-6f;
+            }
+            if (!(rho < kHalfPi)) wide0 = true;
+        }
+        float sh = 1.0f, ch = 0.0f;
+        if (!wide0) sincosf(0.5f * rho, &sh, &ch);
+        s_sup[0] = make_float4(c.x, c.y, c.z, rho);
+        s_sup[1] = make_float4(sh, ch, any0 ? 1.0f : 0.0f, wide0 ? 1.0f : 0.0f);
     }
-    float sh_s = 1.0f, ch_s = 0.0f;
-    if (!wide) sincosf(0.5f * rho_s, &sh_s, &ch_s);
+    __syncthreads();
+    const float4 sup0 = s_sup[0], sup1 = s_sup[1];
+    const float3 cs = f3(sup0.x, sup0.y, sup0.z);
+    const float rho_s = sup0.w, sh_s = sup1.x, ch_s = sup1.y;
+    const bool any = sup1.z != 0.0f, wide = sup1.w != 0.0f;
 
     SceneView S = scene_view(A.setup, A.n);
     const float4* binrec =
@@ -394,46 +403,52 @@ __device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
     }
     __syncthreads();
 
-    // sort every tile's list (same network size in all waves: barriers are
-    // block-wide), then write it out
+    // Order every tile's list by depth bucket (nearest first) with a
+    // counting sort, scattering straight into the output list.
     const uint32_t depth = uint32_t(A.depth);
-    uint32_t npmax = 1;
-#pragma unroll
-    for (int q = 0; q < kSupTiles; ++q) {
-        uint32_t c = s_cnt[q];
-        if (c <= depth)
-            while (npmax < c) npmax <<= 1;
-    }
     const uint32_t cnt = s_cnt[w];
     const bool keep = present && cnt <= depth;
-    uint32_t* my = lists + w * lcap;
-    if (keep)
-        for (uint32_t i = cnt + lane; i < npmax; i += 64) my[i] = 0xFFFFFFFFu;
-    __syncthreads();
-    for (uint32_t k = 2; k <= npmax; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            if (keep) {
-                for (uint32_t i = lane; i < npmax; i += 64) {
-                    uint32_t l = i ^ j;
-                    if (l > i) {
-                        uint32_t x = my[i], y = my[l];
-                        bool up = (i & k) == 0;
-                        if ((x > y) == up) {
-                            my[i] = y;
-                            my[l] = x;
-                        }
-                    }
-                }
-            }
-            __syncthreads();
+    const uint32_t* my = lists + w * lcap;
+    uint32_t* bk = s_bk[w];
+    const int shift = bucket_shift(A.n);
+    char* bb = reinterpret_cast<char*>(A.bins);
+    uint32_t* out = reinterpret_cast<uint32_t*>(bb + 256 + align256(A.ntiles * 4)) + tile * A.depth;
+    if (keep) {
+        for (int q = lane; q < kDepthBuckets; q += 64) bk[q] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t i = lane; i < cnt; i += 64) atomicAdd(&bk[my[i] >> shift], 1u);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // exclusive scan of the 256 bucket counts: 4 per lane
+        uint32_t c4[4], run = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c4[q] = bk[4 * lane + q];
+            run += c4[q];
+        }
+        uint32_t x = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        uint32_t base = x - run;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            bk[4 * lane + q] = base;
+            base += c4[q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t i = lane; i < cnt; i += 64) {
+            uint32_t r = my[i];
+            out[atomicAdd(&bk[r >> shift], 1u)] = r;
         }
     }
     if (present) {
-        char* bb = reinterpret_cast<char*>(A.bins);
         uint32_t* counts = reinterpret_cast<uint32_t*>(bb + 256);
-        uint32_t* out = reinterpret_cast<uint32_t*>(bb + 256 + align256(A.ntiles * 4)) + tile * A.depth;
-        if (keep)
-            for (uint32_t i = lane; i < cnt; i += 64) out[i] = my[i];
         if (lane == 0) {
             counts[tile] = cnt;
             if (!keep) atomicAdd(A.status, 1u);
@@ -529,9 +544,10 @@ __device__ inline void raster_tile(const RasterArgs& A, int64_t tile, int lane) 
             const uint32_t nt = min(16u, count - gi * 16u);
             for (uint32_t t8 = 0; t8 < nt; t8 += 8) {
                 if (!(kStats && A.no_early_exit)) {
-                    // nearest-first early exit: every pixel already beats this
-                    // triangle's depth lower bound (and so every later one's)
-                    float lb = __builtin_amdgcn_readfirstlane(stg[4 * t8 + 3].y);
+                    // nearest-first early exit: every pixel already beats the
+                    // depth lower bound of this triangle's bucket, which bounds
+                    // every triangle still to come
+                    float lb = __builtin_amdgcn_readfirstlane(stg[4 * t8 + 3].w);
                     uint32_t worst = wave_max_u32_dpp(has_dir ? uint32_t(best >> 32) : 0u);
                     if (lb > __uint_as_float(worst)) {
                         done = true;

@@ -292,6 +292,17 @@ __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ or
     val2[r] = uint32_t(r);
 }
 
+// Depth buckets: ranks are grouped into 2^bucket_shift(n) consecutive ranks
+// (at most 256 buckets).  Every record's fourth word of r3 receives the depth
+// lower bound of the first rank of its bucket, which bounds the lower bound
+// of every triangle in that bucket and in all later ones.
+__global__ __launch_bounds__(256) void k_bucket_lb(float4* __restrict__ rec, int64_t n, int shift) {
+    int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int64_t first = (r >> shift) << shift;
+    rec[4 * r + 3].w = rec[4 * first + 3].y;
+}
+
 // Cell-ordered copies: cell_list[k] = rank of the k-th entry and its
 // binning record (cap + edge normals).
 __global__ __launch_bounds__(256) void k_cell_records(const uint32_t* __restrict__ ranks, int64_t n,
@@ -345,6 +356,7 @@ hipError_t launch_setup(const float* xyz, int64_t n, void* setup, hipStream_t st
         uint32_t* v2 = in_b ? U(L.val_a_off) : U(L.val_b_off);
         hipLaunchKernelGGL(k_permute, dim3(blocks), dim3(256), 0, st, ids, n, F4(L.rec_id_off), F4(L.cap_id_off),
                            U(L.bucket_off), F4(L.rec_off), F4(L.cap_off), U(L.order_off), k2, v2);
+        hipLaunchKernelGGL(k_bucket_lb, dim3(blocks), dim3(256), 0, st, F4(L.rec_off), n, bucket_shift(n));
         // ids are no longer needed: the other pair is free scratch
         uint32_t* k3 = in_b ? U(L.key_b_off) : U(L.key_a_off);
         uint32_t* v3 = in_b ? U(L.val_b_off) : U(L.val_a_off);

@@ -113,6 +113,14 @@ __host__ __device__ inline SetupLayout setup_layout(int64_t n) {
     return s;
 }
 
+// Depth buckets of the nearest-first order: bucket of rank r is r >> shift.
+constexpr int kDepthBuckets = 256;
+__host__ __device__ inline int bucket_shift(int64_t n) {
+    int s = 0;
+    while ((int64_t(kDepthBuckets) << s) < n) ++s;
+    return s;
+}
+
 // --------------------------------------------------------------- bins ---
 struct BinLayout {
     int64_t ntiles;
