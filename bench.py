@@ -110,6 +110,20 @@ def main():
     log(f"plain: {plain_ms:.3f} ms/view (p50 {np.percentile(lat, 50):.3f}, p99 {np.percentile(lat, 99):.3f}), "
         f"raster {np.mean(rast):.3f} ms, overflowed tiles {overflow}")
 
+    # ---------------- single-view fused path (vsr_build_map + vsr_render)
+    ffr = pipeline.render_fused(scene, views[0], fmt=fmt)
+    torch.cuda.synchronize()
+    fl = []
+    for v in views[:n_plain]:
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        pipeline.render_fused(scene, v, fmt=fmt, frame=ffr)
+        e1.record(stream)
+        e1.synchronize()
+        fl.append(e0.elapsed_time(e1))
+    fused_ms = float(np.mean(fl))
+    log(f"fused single view: {fused_ms:.3f} ms/view")
+
     # ---------------- fragment counts (instrumented raster, one view per k)
     stats = torch.zeros(4, dtype=torch.int64, device=dev)
     F_all, F_proc, tests_proc = [], [], []
@@ -130,7 +144,7 @@ def main():
         f"tests executed: {tests_proc}")
 
     # ---------------- batched: setup + one submit of all views per step
-    batch = pipeline.Batch([(scene, v) for v in views], fmt=fmt, bin_depth=depth)
+    batch = pipeline.Batch([(scene, v) for v in views], fmt=fmt, mode=vsr.VSR_SUBMIT_BINNED, bin_depth=depth)
     for _ in range(args.warmup):
         scene.refresh()
         batch.submit()
@@ -149,7 +163,6 @@ def main():
     views_per_s = len(views) / (step_ms / 1e3)
     log(f"batched step (setup + {len(views)} views): {step_ms:.3f} ms -> {views_per_s:.1f} views/s "
         f"(wall {wall:.3f}s for {args.steps} steps)")
-    ws_overflow = vsr.vsr_bin_overflow(batch.workspace, True)
 
     # batched without setup, and setup alone
     e0, e1 = ev(), ev()
@@ -167,6 +180,19 @@ def main():
     torch.cuda.synchronize()
     setup_ms = e0.elapsed_time(e1) / args.steps
     log(f"submit only: {submit_ms:.3f} ms ({len(views) / submit_ms * 1e3:.1f} views/s); setup {setup_ms:.3f} ms")
+    # the fused depth-sliced batch on the same views
+    fbatch = pipeline.Batch([(scene, v) for v in views], fmt=fmt, mode=vsr.VSR_SUBMIT_FUSED)
+    fbatch.submit()
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    for _ in range(max(1, args.steps // 2)):
+        fbatch.submit()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fsubmit_ms = e0.elapsed_time(e1) / max(1, args.steps // 2)
+    log(f"fused submit: {fsubmit_ms:.3f} ms ({len(views) / fsubmit_ms * 1e3:.1f} views/s)")
+    del fbatch
 
     # ---------------- roofline of the rasterizer (dominant kernel)
     t_r = float(np.mean(rast)) * 1e-3
@@ -226,7 +252,9 @@ def main():
         "covered_fragments_per_frame": F_mean,
         "processed_fragments_per_frame": float(np.mean(F_proc)),
         "executed_tests_per_frame": float(np.mean(tests_proc)),
-        "overflowed_tiles": {"plain": overflow, "batched": ws_overflow},
+        "overflowed_tiles_plain": overflow,
+        "fused_fps": 1e3 / fused_ms,
+        "batched_fused_fps": len(views) / fsubmit_ms * 1e3,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -162,6 +162,19 @@ int vsr_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const void
                      const void* bins, int32_t bin_depth, uint32_t* tri_id, float* depth, uint64_t* stats,
                      int32_t no_early_exit, void* stream);
 
+/* Steps 3+4 fused for one view: bytes of the scratch buffer vsr_render
+ * needs for a width x height view. */
+int64_t vsr_render_bytes(int32_t width, int32_t height);
+
+/* Steps 3+4 fused, depth-sliced (same images as vsr_bin + vsr_raster, bit
+ * for bit).  Triangles are visited nearest-first in slices; a 16x16 block of
+ * pixels gathers a slice's candidates into on-chip lists, rasterizes them,
+ * and stops as soon as every pixel is nearer than the next slice can be, so
+ * occluded geometry is never gathered.
+ *   scratch  device buffer of vsr_render_bytes(width, height) bytes. */
+int vsr_render(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri, void* scratch,
+               int64_t scratch_bytes, uint32_t* tri_id, float* depth, void* stream);
+
 /* ------------------------------------------------------------- batches */
 
 /* One view of a batch (host memory).  setup/ntri name a resident scene
@@ -174,19 +187,27 @@ typedef struct {
     float* depth;
 } vsr_job;
 
-/* Bytes of the workspace vsr_submit needs for these jobs. */
-int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t bin_depth);
+/* vsr_submit modes */
+#define VSR_SUBMIT_BINNED 0 /* all maps, then vsr_bin and vsr_raster work over all jobs (bin_depth used) */
+#define VSR_SUBMIT_FUSED 1  /* all maps, then vsr_render work over all jobs (dense, deep scenes)         */
 
-/* Step 5 — many views in one pass: builds every job's map, bins and
- * rasterizes all jobs' tiles with one launch per stage (persistent work
- * queue over (job, tile) items), so views of different sizes and
- * parameters share the GPU.  Each job's output is identical, bit for bit,
- * to rendering it alone with vsr_build_map / vsr_bin / vsr_raster at the
- * same fmt and bin_depth.
+/* Bytes of the workspace vsr_submit needs for these jobs, mode and depth. */
+int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth);
+
+/* Step 5 — many views in one pass: one launch builds every job's map, then
+ * one launch per remaining stage covers the pixel blocks of all jobs, so
+ * views of different sizes, parameters and scenes share the GPU.  mode
+ * VSR_SUBMIT_BINNED bins (bin_depth: 1..8192) and rasterizes; mode
+ * VSR_SUBMIT_FUSED runs the fused depth-sliced renderer (bin_depth
+ * ignored).  Each job's images are identical, bit for bit, to rendering it
+ * alone with vsr_build_map + vsr_bin + vsr_raster or vsr_render at the same
+ * fmt.  No host-to-device copy is issued, so the call can be captured in a
+ * HIP graph.  Overflowed tiles of the binned mode are counted in the first
+ * word of the workspace (vsr_bin_overflow).
  *   jobs       host array of njobs jobs (1..4096).
- *   workspace  device buffer of vsr_submit_bytes(jobs, njobs, fmt,
- *              bin_depth) bytes; it holds the maps, bins and job table. */
-int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t bin_depth, void* workspace,
+ *   workspace  device buffer of vsr_submit_bytes(...) bytes holding the job
+ *              table, the maps and the bins or list scratch. */
+int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth, void* workspace,
                int64_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------- diagnostics */

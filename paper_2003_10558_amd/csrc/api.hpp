@@ -6,6 +6,8 @@
 #pragma once
 #include <stdarg.h>
 
+#include "bin.hpp"
+#include "fused.hpp"
 #include "map.hpp"
 #include "raster.hpp"
 #include "setup.hpp"
@@ -218,21 +220,46 @@ int vsr_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const void
                       "vsr_raster_stats");
 }
 
-int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t bin_depth) {
+int64_t vsr_render_bytes(int32_t width, int32_t height) {
+    if (width < 1 || height < 1 || width > kMaxDim || height > kMaxDim) return VSR_E_ARG;
+    return fused_scratch_bytes(width, height);
+}
+
+int vsr_render(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri, void* scratch,
+               int64_t scratch_bytes, uint32_t* tri_id, float* depth, void* stream) {
+    int rc = check_view_buffers(v, fmt);
+    if (rc != VSR_OK) return rc;
+    if (!map || !setup || !scratch || !tri_id || !depth || !aligned(map) || !aligned(setup) || !aligned(scratch))
+        return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if ((reinterpret_cast<uintptr_t>(tri_id) & 3u) || (reinterpret_cast<uintptr_t>(depth) & 3u))
+        return fail(VSR_E_ARG, "output not 4-byte aligned");
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri out of range");
+    int64_t need = fused_scratch_bytes(v->width, v->height);
+    if (scratch_bytes < need)
+        return fail(VSR_E_SPACE, "scratch %lld < %lld bytes", (long long)scratch_bytes, (long long)need);
+    return hip_status(launch_fused(map, v->width, v->height, fmt, setup, ntri, scratch, tri_id, depth,
+                                   hipStream_t(stream)),
+                      "vsr_render");
+}
+
+int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth) {
     if (!jobs || njobs < 1 || njobs > 4096) return VSR_E_ARG;
     if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return VSR_E_ARG;
-    if (bin_depth < 1 || bin_depth > kMaxDepth) return VSR_E_ARG;
+    if (mode != VSR_SUBMIT_BINNED && mode != VSR_SUBMIT_FUSED) return VSR_E_ARG;
+    if (mode == VSR_SUBMIT_BINNED && (bin_depth < 1 || bin_depth > kMaxDepth)) return VSR_E_ARG;
     for (int32_t q = 0; q < njobs; ++q) {
         const vsr_view& v = jobs[q].view;
         if (v.width < 1 || v.height < 1 || v.width > kMaxDim || v.height > kMaxDim) return VSR_E_ARG;
     }
-    return submit_bytes(jobs, njobs, fmt, bin_depth);
+    return submit_bytes(jobs, njobs, fmt, mode, bin_depth);
 }
 
-int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t bin_depth, void* workspace, int64_t ws_bytes,
-               void* stream) {
+int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth, void* workspace,
+               int64_t ws_bytes, void* stream) {
     if (!jobs || njobs < 1 || njobs > 4096) return fail(VSR_E_ARG, "njobs %d outside 1..4096", njobs);
-    if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
+    if (mode != VSR_SUBMIT_BINNED && mode != VSR_SUBMIT_FUSED) return fail(VSR_E_ARG, "unknown submit mode %d", mode);
+    if (mode == VSR_SUBMIT_BINNED && (bin_depth < 1 || bin_depth > kMaxDepth))
+        return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
     if (!workspace || !aligned(workspace)) return fail(VSR_E_ARG, "workspace NULL or misaligned");
     for (int32_t q = 0; q < njobs; ++q) {
         const vsr_job& J = jobs[q];
@@ -244,9 +271,9 @@ int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t bin_dept
         if ((reinterpret_cast<uintptr_t>(J.tri_id) & 3u) || (reinterpret_cast<uintptr_t>(J.depth) & 3u))
             return fail(VSR_E_ARG, "job %d: output not 4-byte aligned", q);
     }
-    int64_t need = submit_bytes(jobs, njobs, fmt, bin_depth);
+    int64_t need = submit_bytes(jobs, njobs, fmt, mode, bin_depth);
     if (ws_bytes < need) return fail(VSR_E_SPACE, "workspace %lld < %lld bytes", (long long)ws_bytes, (long long)need);
-    return hip_status(launch_submit(jobs, njobs, fmt, bin_depth, workspace, hipStream_t(stream)), "vsr_submit");
+    return hip_status(launch_submit(jobs, njobs, fmt, mode, bin_depth, workspace, hipStream_t(stream)), "vsr_submit");
 }
 
 int vsr_bin_overflow(const void* bins_or_ws, int32_t is_workspace, int64_t* overflowed_tiles) {

@@ -16,8 +16,10 @@
 //     matching its radius.
 // Then a stable LSD radix sort orders triangles by depth lower bound (ties
 // keep id order), records are permuted into that order, and a second
-// stable radix sort groups them by cell so that every cell's list is itself
-// nearest first.  cell_start[b] is the first entry of bucket b.
+// stable radix sort groups them by (depth slice, cell) so that every cell's
+// list is itself nearest first.  cell_start[key] is the first entry of
+// index key `key`; face_count[s][level*6+face] counts a slice's triangles
+// on one cube face of one level.
 #pragma once
 #include "vsr_internal.h"
 
@@ -288,7 +290,9 @@ __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ or
     cap[2 * r + 0] = cap_id[2 * int64_t(id) + 0];
     cap[2 * r + 1] = cap_id[2 * int64_t(id) + 1];
     order[r] = id;
-    key2[r] = bucket[id];
+    uint32_t b = bucket[id];
+    key2[r] = b == uint32_t(kNumBuckets) ? uint32_t(kIndexKeys)
+                                         : uint32_t(int64_t(slice_of(n, r)) * kNumBuckets + b);
     val2[r] = uint32_t(r);
 }
 
@@ -321,11 +325,11 @@ __global__ __launch_bounds__(256) void k_cell_records(const uint32_t* __restrict
     binrec[4 * k + 3] = make_float4(r2.x, r2.y, r2.z, 0.0f);
 }
 
-// cell_start[b] = first position whose bucket is >= b (lower bound).
+// cell_start[b] = first position whose index key is >= b (lower bound).
 __global__ __launch_bounds__(256) void k_cell_start(const uint32_t* __restrict__ sorted_bucket, int64_t n,
                                                     uint32_t* __restrict__ cell_start) {
     int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (b > kNumBuckets) return;
+    if (b > kIndexKeys) return;
     int64_t lo = 0, hi = n;
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
@@ -335,6 +339,19 @@ __global__ __launch_bounds__(256) void k_cell_start(const uint32_t* __restrict__
             hi = mid;
     }
     cell_start[b] = uint32_t(lo);
+}
+
+// Triangles of slice s on cube face `face` of level L (p = L*6 + face).
+__global__ __launch_bounds__(64) void k_face_count(const uint32_t* __restrict__ cell_start,
+                                                   uint32_t* __restrict__ face_count) {
+    int s = blockIdx.x, p = threadIdx.x;
+    uint32_t c = 0;
+    if (p < 6 * kLevels) {
+        int L = p / 6, face = p % 6, M = 1 << L;
+        int64_t fb = int64_t(s) * kNumBuckets + level_base(L) + int64_t(face) * M * M;
+        c = cell_start[fb + int64_t(M) * M] - cell_start[fb];
+    }
+    face_count[s * 64 + p] = c;
 }
 
 hipError_t launch_setup(const float* xyz, int64_t n, void* setup, hipStream_t st) {
@@ -367,12 +384,13 @@ hipError_t launch_setup(const float* xyz, int64_t n, void* setup, hipStream_t st
         uint32_t* sv = in3 ? v3 : v2;
         hipLaunchKernelGGL(k_cell_records, dim3(blocks), dim3(256), 0, st, sv, n, F4(L.rec_off), F4(L.cap_off),
                            U(L.cell_list_off), F4(L.binrec_off));
-        hipLaunchKernelGGL(k_cell_start, dim3(unsigned((kNumBuckets + 1 + 255) / 256)), dim3(256), 0, st, sk, n,
+        hipLaunchKernelGGL(k_cell_start, dim3(unsigned((kIndexKeys + 1 + 255) / 256)), dim3(256), 0, st, sk, n,
                            U(L.cell_start_off));
     } else {
-        hipLaunchKernelGGL(k_cell_start, dim3(unsigned((kNumBuckets + 1 + 255) / 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_cell_start, dim3(unsigned((kIndexKeys + 1 + 255) / 256)), dim3(256), 0, st,
                            U(L.key_a_off), int64_t(0), U(L.cell_start_off));
     }
+    hipLaunchKernelGGL(k_face_count, dim3(kSlices), dim3(64), 0, st, U(L.cell_start_off), U(L.face_count_off));
     return hipGetLastError();
 }
 

@@ -1,16 +1,19 @@
-// Batched views: one launch per stage over the (job, tile) items of all jobs.
+// Batched views: one launch per stage for any number of jobs — all maps,
+// then either the binner over all jobs' 16x16 super-tiles and the
+// rasterizer over all their 8x8 tiles (VSR_SUBMIT_BINNED), or the fused
+// depth-sliced bin + raster over all super-tiles (VSR_SUBMIT_FUSED).
 //
 // The job table lives in the workspace; it is written by a small kernel whose
 // arguments carry the descriptors (no host-memory copy, so a caller may
-// capture the whole submit in a HIP graph).  Each stage kernel maps its
-// global tile index to (job, local tile) with a wave-uniform binary search
-// over the jobs' tile offsets and then runs exactly the per-tile device
-// function of the single-view path, which is why a batched job's output is
-// bit-identical to rendering that view alone.
+// capture the whole submit in a HIP graph).  Each kernel maps its global
+// tile (or super-tile) index to (job, local index) with a uniform binary
+// search over the jobs' offsets and runs the per-tile device function of the
+// single-view path, so a batched job's images are bit-identical to
+// rendering that view alone.
 
 #pragma once
+#include "fused.hpp"
 #include "map.hpp"
-#include "raster.hpp"
 
 namespace vsr {
 
@@ -53,11 +56,15 @@ static WsLayout ws_layout(int32_t njobs) {
     return w;
 }
 
-int64_t submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t depth) {
+inline int64_t job_scratch_bytes(int32_t W, int32_t H, int32_t mode, int32_t depth) {
+    return mode == VSR_SUBMIT_FUSED ? fused_scratch_bytes(W, H) : bin_layout(W, H, depth).bytes;
+}
+
+int64_t submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth) {
     int64_t b = ws_layout(njobs).bytes;
     for (int32_t q = 0; q < njobs; ++q) {
         b += map_layout(jobs[q].view.width, jobs[q].view.height, fmt).bytes;
-        b += bin_layout(jobs[q].view.width, jobs[q].view.height, depth).bytes;
+        b += job_scratch_bytes(jobs[q].view.width, jobs[q].view.height, mode, depth);
     }
     return b;
 }
@@ -107,15 +114,6 @@ __global__ __launch_bounds__(256) void k_submit_bin(const JobDesc* __restrict__ 
     bin_super(A, t - J.stile_off);
 }
 
-__global__ __launch_bounds__(256) void k_submit_map(const JobDesc* __restrict__ T, int njobs, int64_t total) {
-    int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    int64_t t = int64_t(blockIdx.x) * 4 + w;
-    if (t >= total) return;
-    int jb = find_job(T, njobs, t);
-    const JobDesc& J = T[jb];
-    build_map_tile(J.P, J.map, J.ntiles, t - J.tile_off, threadIdx.x & 63);
-}
-
 __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
                                                        int32_t depth, int64_t total) {
     int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -142,7 +140,38 @@ __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict
     raster_tile<false>(A, t - J.tile_off, threadIdx.x & 63);
 }
 
-hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t depth, void* ws, hipStream_t st) {
+__global__ __launch_bounds__(256) void k_submit_fused(const JobDesc* __restrict__ T, int njobs, int32_t fmt) {
+    int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    int jb = find_job_super(T, njobs, t);
+    const JobDesc& J = T[jb];
+    FusedArgs A;
+    A.map = J.map;
+    A.ntiles = J.ntiles;
+    A.fmt = fmt;
+    A.W = J.P.W;
+    A.H = J.P.H;
+    A.ntx = J.ntx;
+    A.nty = J.nty;
+    A.pad = 0;
+    A.setup = J.setup;
+    A.n = J.ntri;
+    A.scratch = reinterpret_cast<uint32_t*>(J.bins);
+    A.tri_id = J.tri_id;
+    A.depth = J.depth;
+    fused_super(A, t - J.stile_off);
+}
+
+__global__ __launch_bounds__(256) void k_submit_map(const JobDesc* __restrict__ T, int njobs, int64_t total) {
+    int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    int64_t t = int64_t(blockIdx.x) * 4 + w;
+    if (t >= total) return;
+    int jb = find_job(T, njobs, t);
+    const JobDesc& J = T[jb];
+    build_map_tile(J.P, J.map, J.ntiles, t - J.tile_off, threadIdx.x & 63);
+}
+
+hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth, void* ws,
+                         hipStream_t st) {
     WsLayout W = ws_layout(njobs);
     char* base = reinterpret_cast<char*>(ws);
     JobDesc* table = reinterpret_cast<JobDesc*>(base + W.table_off);
@@ -156,11 +185,10 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
         JobDesc& D = chunk.d[chunk.count];
         make_map_params(&jobs[q].view, fmt, 0, &D.P, nullptr);
         MapLayout ML = map_layout(D.P.W, D.P.H, fmt);
-        BinLayout BL = bin_layout(D.P.W, D.P.H, depth);
         D.map = base + off;
         off += ML.bytes;
         D.bins = base + off;
-        off += BL.bytes;
+        off += job_scratch_bytes(D.P.W, D.P.H, mode, depth);
         D.ntx = ML.ntx;
         D.nty = ML.nty;
         D.stile_off = stiles;
@@ -179,11 +207,15 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
         }
     }
     hipLaunchKernelGGL(k_submit_map, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, tiles);
-    int32_t cap = bin_lds_cap(depth);
-    hipLaunchKernelGGL(k_submit_bin, dim3(unsigned(stiles)), dim3(256), size_t(kSupTiles) * cap * 4, st, table, njobs,
-                       fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
-    hipLaunchKernelGGL(k_submit_raster, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, fmt, depth,
-                       tiles);
+    if (mode == VSR_SUBMIT_FUSED) {
+        hipLaunchKernelGGL(k_submit_fused, dim3(unsigned(stiles)), dim3(256), 0, st, table, njobs, fmt);
+    } else {
+        int32_t cap = bin_lds_cap(depth);
+        hipLaunchKernelGGL(k_submit_bin, dim3(unsigned(stiles)), dim3(256), size_t(kSupTiles) * cap * 4, st, table,
+                           njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
+        hipLaunchKernelGGL(k_submit_raster, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, fmt,
+                           depth, tiles);
+    }
     return hipGetLastError();
 }
 

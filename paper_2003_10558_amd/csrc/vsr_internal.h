@@ -33,10 +33,27 @@ constexpr float kCapRelMargin = 1e-6f;
 
 __host__ __device__ constexpr int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
-// Cells of level L: 6 faces of M x M, M = 2^L.  Buckets of all levels are
-// numbered consecutively; bucket kNumBuckets collects culled triangles.
+// Cells of level L: 6 faces of M x M, M = 2^L.  Cells of all levels are
+// numbered consecutively; cell kNumBuckets marks culled triangles.
 __host__ __device__ constexpr int64_t level_base(int L) { return 6 * (((int64_t(1) << (2 * L)) - 1) / 3); }
 constexpr int64_t kNumBuckets = level_base(kLevels);
+
+// Depth slices of the nearest-first order: slice s holds ranks
+// [slice_begin(s), slice_begin(s+1)) with boundaries at n/64, n/16, n/4.
+// The cap index is built per slice: index key = s * kNumBuckets + cell,
+// culled triangles get kIndexKeys.
+constexpr int kSlices = 4;
+constexpr int64_t kIndexKeys = int64_t(kSlices) * kNumBuckets;
+__host__ __device__ inline int64_t slice_begin(int64_t n, int s) {
+    if (s <= 0) return 0;
+    if (s >= kSlices) return n;
+    return n >> (2 * (kSlices - s));
+}
+__host__ __device__ inline int slice_of(int64_t n, int64_t rank) {
+    int s = 0;
+    while (s + 1 < kSlices && slice_begin(n, s + 1) <= rank) ++s;
+    return s;
+}
 
 // --------------------------------------------------------------- map ----
 struct MapLayout {
@@ -81,7 +98,7 @@ struct MapParams {
 struct SetupLayout {
     int64_t n;
     int64_t nblocks;    // radix-sort blocks
-    int64_t rec_off, cap_off, cell_list_off, cell_start_off, order_off, binrec_off;
+    int64_t rec_off, cap_off, cell_list_off, cell_start_off, order_off, binrec_off, face_count_off;
     int64_t rec_id_off, cap_id_off, key_a_off, val_a_off, key_b_off, val_b_off, bucket_off, hist_off;
     int64_t bytes;
 };
@@ -98,7 +115,8 @@ __host__ __device__ inline SetupLayout setup_layout(int64_t n) {
     s.rec_off = o;        o += align256(n * 64);
     s.cap_off = o;        o += align256(n * 32);
     s.cell_list_off = o;  o += align256(n * 4);
-    s.cell_start_off = o; o += align256((kNumBuckets + 1) * 4);
+    s.cell_start_off = o; o += align256((kIndexKeys + 1) * 4);
+    s.face_count_off = o; o += align256(int64_t(kSlices) * 64 * 4);
     s.order_off = o;      o += align256(n * 4);
     s.binrec_off = o;     o += align256(n * 64);
     s.rec_id_off = o;     o += align256(n * 64);

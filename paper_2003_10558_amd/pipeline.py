@@ -68,22 +68,35 @@ def render(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, bin_depth: int = DEFA
     return frame
 
 
+def render_fused(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, stream=None,
+                 frame: Optional[Frame] = None) -> Frame:
+    """build_map -> fused depth-sliced bin + raster (vsr_render) for one view."""
+    dev = scene.device
+    if frame is None:
+        ids, dep = alloc_outputs(view, dev)
+        frame = Frame(ids, dep, _buffer(vsr.vsr_map_bytes(view.width, view.height, fmt), dev),
+                      _buffer(vsr.vsr_render_bytes(view.width, view.height), dev), None)
+    frame.view_eff = vsr.vsr_build_map(view, fmt, 0, frame.map, stream)
+    vsr.vsr_render(view, fmt, frame.map, scene.setup, scene.ntri, frame.bins, frame.tri_id, frame.depth, stream)
+    return frame
+
+
 class Batch:
     """Workspace + outputs for vsr_submit over a fixed list of (scene, view)."""
 
     def __init__(self, items: Sequence[Tuple[Scene, object]], fmt: int = vsr.VSR_MAP_F32,
-                 bin_depth: int = DEFAULT_BIN_DEPTH):
+                 mode: int = vsr.VSR_SUBMIT_BINNED, bin_depth: int = DEFAULT_BIN_DEPTH):
         assert len(items) > 0
         self.items = list(items)
-        self.fmt, self.bin_depth = fmt, bin_depth
+        self.fmt, self.mode, self.bin_depth = fmt, mode, bin_depth
         dev = items[0][0].device
         self.outputs = [alloc_outputs(v, dev) for _, v in self.items]
         self.jobs = vsr.make_jobs([(v, s.setup, s.ntri, o[0], o[1])
                                    for (s, v), o in zip(self.items, self.outputs)])
-        self.workspace = _buffer(vsr.vsr_submit_bytes(self.jobs, fmt, bin_depth), dev)
+        self.workspace = _buffer(vsr.vsr_submit_bytes(self.jobs, fmt, mode, bin_depth), dev)
 
     def submit(self, stream=None) -> List[Tuple[torch.Tensor, torch.Tensor]]:
-        vsr.vsr_submit(self.jobs, self.fmt, self.bin_depth, self.workspace, stream)
+        vsr.vsr_submit(self.jobs, self.fmt, self.mode, self.bin_depth, self.workspace, stream)
         return self.outputs
 
 

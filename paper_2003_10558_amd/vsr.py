@@ -20,6 +20,7 @@ VSR_MAP_F32, VSR_MAP_OCT16 = 0, 1
 VSR_STRICT = 1
 VSR_BIN_ALL = 1
 VSR_NO_HIT = 0xFFFFFFFF
+VSR_SUBMIT_BINNED, VSR_SUBMIT_FUSED = 0, 1
 VSR_TILE = 8
 VSR_AOV_HORIZONTAL, VSR_AOV_DIAGONAL, VSR_AOV_VERTICAL, VSR_AOV_HORIZONTAL_4X3 = 0, 1, 2, 3
 
@@ -60,18 +61,21 @@ _lib.vsr_bin.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _i32, _
 _lib.vsr_raster.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp]
 _lib.vsr_raster_stats.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _i32,
                                   _vp]
-_lib.vsr_submit_bytes.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32]
+_lib.vsr_render_bytes.argtypes = [_i32, _i32]
+_lib.vsr_render_bytes.restype = _i64
+_lib.vsr_render.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp]
+_lib.vsr_submit_bytes.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32]
 _lib.vsr_submit_bytes.restype = _i64
-_lib.vsr_submit.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _vp, _i64, _vp]
+_lib.vsr_submit.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32, _vp, _i64, _vp]
 _lib.vsr_bin_overflow.argtypes = [_vp, _i32, ctypes.POINTER(_i64)]
 _lib.vsr_strerror.argtypes = [ctypes.c_int]
 _lib.vsr_strerror.restype = ctypes.c_char_p
 _lib.vsr_last_error.restype = ctypes.c_char_p
-for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_raster", "vsr_raster_stats", "vsr_submit", "vsr_bin_overflow"):
+for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_raster", "vsr_raster_stats", "vsr_render", "vsr_submit", "vsr_bin_overflow"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin",
-           "vsr_raster", "vsr_raster_stats", "vsr_submit_bytes", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
+           "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_submit_bytes", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
 
 
 def _check(rc: int) -> None:
@@ -172,12 +176,23 @@ def make_jobs(jobs: Sequence[tuple]):
     return arr
 
 
-def vsr_submit_bytes(jobs, fmt: int, bin_depth: int) -> int:
-    return _size(_lib.vsr_submit_bytes(jobs, len(jobs), fmt, bin_depth), "vsr_submit_bytes")
+def vsr_render_bytes(width: int, height: int) -> int:
+    return _size(_lib.vsr_render_bytes(width, height), "vsr_render_bytes")
 
 
-def vsr_submit(jobs, fmt: int, bin_depth: int, workspace, stream=None) -> None:
-    _check(_lib.vsr_submit(jobs, len(jobs), fmt, bin_depth, _ptr(workspace), _nbytes(workspace), _stream(stream)))
+def vsr_render(view, fmt: int, map_buf, setup_buf, ntri: int, scratch, tri_id, depth, stream=None) -> None:
+    v = make_view(view)
+    _check(_lib.vsr_render(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), ntri, _ptr(scratch),
+                           _nbytes(scratch), _ptr(tri_id), _ptr(depth), _stream(stream)))
+
+
+def vsr_submit_bytes(jobs, fmt: int, mode: int = 0, bin_depth: int = 1024) -> int:
+    return _size(_lib.vsr_submit_bytes(jobs, len(jobs), fmt, mode, bin_depth), "vsr_submit_bytes")
+
+
+def vsr_submit(jobs, fmt: int, mode: int, bin_depth: int, workspace, stream=None) -> None:
+    _check(_lib.vsr_submit(jobs, len(jobs), fmt, mode, bin_depth, _ptr(workspace), _nbytes(workspace),
+                           _stream(stream)))
 
 
 def vsr_bin_overflow(bins_or_ws, is_workspace: bool = False) -> int:

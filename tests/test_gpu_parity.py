@@ -172,13 +172,14 @@ def test_overflow_falls_back(gpu):
     assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
 
 
-def test_submit_matches_single_views(gpu):
+@pytest.mark.parametrize("mode", [0, 1], ids=["binned", "fused"])
+def test_submit_matches_single_views(gpu, mode):
     torch, pipeline, vsr = gpu
     tris = synth.scene(3000, 23)
     scene = pipeline.Scene(tris)
     views = synth.random_views(6, 99, resolutions=((96, 64), (130, 70), (64, 64)))
-    _say("[submit] 6 mixed views vs single")
-    batch = pipeline.Batch([(scene, v) for v in views])
+    _say(f"[submit] 6 mixed views vs single, mode {mode}")
+    batch = pipeline.Batch([(scene, v) for v in views], mode=mode)
     outs = batch.submit()
     torch.cuda.synchronize()
     for v, (ids_t, dep_t) in zip(views, outs):
@@ -190,6 +191,40 @@ def test_submit_matches_single_views(gpu):
     v = views[0]
     st = compare(v, tris, pipeline.ids_u32(outs[0][0]), outs[0][1].cpu().numpy(), oracle.render(v, tris))
     assert st.ok(), st.notes
+
+
+def _render_fused(gpu, tris, view, fmt=0):
+    torch, pipeline, vsr = gpu
+    scene = pipeline.Scene(tris)
+    fr = pipeline.render_fused(scene, view, fmt=fmt)
+    torch.cuda.synchronize()
+    return pipeline.ids_u32(fr.tri_id), fr.depth.cpu().numpy()
+
+
+FUSED_CASES = [
+    ("small", synth.view_small(), lambda: synth.scene_small()),
+    ("rot", synth.View(200, 150, -0.4, 0.3, 0.9, 300.0, 0, synth.yaw_pitch_rotation(1.0, 0.3)),
+     lambda: synth.scene(1500, 17)),
+    ("ragged", synth.View(37, 23, 0.7, 0.2, 0.95, 200.0, 3, synth.yaw_pitch_rotation(4.0, -0.8)),
+     lambda: synth.scene(300, 5)),
+    ("dense", synth.View(160, 96, 0.1, 0.8, 0.9, 250.0, 0, synth.yaw_pitch_rotation(0.2, 0.1)),
+     lambda: synth.scene(60000, 29)),
+    ("empty", synth.View(40, 30, 0.0, 1.0, 1.0, 90.0), lambda: np.zeros((9, 0), np.float32)),
+]
+
+
+@pytest.mark.parametrize("name,view,make", FUSED_CASES, ids=[c[0] for c in FUSED_CASES])
+def test_fused_matches_plain(gpu, name, view, make):
+    """vsr_render (depth-sliced, fused) gives the same bits as bin + raster."""
+    tris = make()
+    _say(f"[fused] {name} {view.width}x{view.height} T={tris.shape[1]}")
+    a_ids, a_dep, _ = _render(gpu, tris, view, depth=4096)
+    b_ids, b_dep = _render_fused(gpu, tris, view)
+    assert np.array_equal(a_ids, b_ids)
+    assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
+    if tris.shape[1] <= 5000:
+        st = compare(view, tris, b_ids, b_dep, oracle.render(view, tris))
+        assert st.ok(), st.notes
 
 
 def test_oct16_tier_small(gpu):

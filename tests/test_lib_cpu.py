@@ -115,10 +115,19 @@ def test_submit_argument_errors(vsr):
     jobs[0].view = vsr.make_view(synth.View(64, 32, 0.3, 0.5, 0.9, 120.0))
     jobs[0].setup = 0
     with pytest.raises(vsr.VsrError) as e:
-        vsr.vsr_submit(jobs, 0, 64, _FakeBuf(256, 10 ** 9), stream=0)
+        vsr.vsr_submit(jobs, 0, 0, 64, _FakeBuf(256, 10 ** 9), stream=0)
     assert e.value.code == vsr.VSR_E_ARG
     jobs[0].setup, jobs[0].tri_id, jobs[0].depth, jobs[0].ntri = 512, 1024, 2048, 10
-    need = vsr.vsr_submit_bytes(jobs, 0, 64)
+    for mode in (vsr.VSR_SUBMIT_BINNED, vsr.VSR_SUBMIT_FUSED):
+        need = vsr.vsr_submit_bytes(jobs, 0, mode, 64)
+        with pytest.raises(vsr.VsrError) as e:
+            vsr.vsr_submit(jobs, 0, mode, 64, _FakeBuf(256, need - 1), stream=0)
+        assert e.value.code == vsr.VSR_E_SPACE
     with pytest.raises(vsr.VsrError) as e:
-        vsr.vsr_submit(jobs, 0, 64, _FakeBuf(256, need - 1), stream=0)
+        vsr.vsr_submit(jobs, 0, 7, 64, _FakeBuf(256, 10 ** 9), stream=0)
+    assert e.value.code == vsr.VSR_E_ARG
+    v = synth.View(64, 32, 0.3, 0.5, 0.9, 120.0)
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.vsr_render(v, 0, _FakeBuf(256, 1), _FakeBuf(512, 1), 10, _FakeBuf(768, 16), _FakeBuf(1024, 1),
+                       _FakeBuf(2048, 1), stream=0)
     assert e.value.code == vsr.VSR_E_SPACE
