@@ -93,7 +93,7 @@ int64_t vsr_map_bytes(int32_t width, int32_t height, int32_t fmt);
 int64_t vsr_setup_bytes(int64_t ntri);
 
 /* Bytes of the bin buffer of a width x height view with lists of at most
- * bin_depth triangles per tile (1..8192).  <0 on bad input. */
+ * bin_depth triangles per tile (1..2048).  <0 on bad input. */
 int64_t vsr_bin_bytes(int32_t width, int32_t height, int32_t bin_depth);
 
 /* ------------------------------------------------------------ pipeline */
@@ -197,7 +197,7 @@ int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
 /* Step 5 — many views in one pass: one launch builds every job's map, then
  * one launch per remaining stage covers the pixel blocks of all jobs, so
  * views of different sizes, parameters and scenes share the GPU.  mode
- * VSR_SUBMIT_BINNED bins (bin_depth: 1..8192) and rasterizes; mode
+ * VSR_SUBMIT_BINNED bins (bin_depth: 1..2048) and rasterizes; mode
  * VSR_SUBMIT_FUSED runs the fused depth-sliced renderer (bin_depth
  * ignored).  Each job's images are identical, bit for bit, to rendering it
  * alone with vsr_build_map + vsr_bin + vsr_raster or vsr_render at the same

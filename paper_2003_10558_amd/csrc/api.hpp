@@ -34,7 +34,7 @@ static int hip_status(hipError_t e, const char* what) {
 static bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
 static const int32_t kMaxDim = 32768;
-static const int32_t kMaxDepth = 8192;
+static const int32_t kMaxDepth = 2048;  // four lists of this many entries fit in LDS
 
 // Section 2.1.1 limits, in double precision on float inputs.
 static void limit_params(double& k, double& l, double& s, double& om) {

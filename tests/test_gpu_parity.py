@@ -104,10 +104,10 @@ def test_binning_is_exact(gpu):
     """Real bins give the same bits as every triangle in every tile."""
     for name, view, tris in [("small", synth.view_small(), synth.scene_small()),
                              ("rot", synth.View(200, 150, -0.4, 0.3, 0.9, 300.0, 0, synth.yaw_pitch_rotation(1.0, 0.3)),
-                              synth.scene(1500, 17))]:
+                              synth.scene(700, 17))]:
         _say(f"[bin-exact] {name}")
         a_ids, a_dep, _ = _render(gpu, tris, view)
-        b_ids, b_dep, ovf = _render(gpu, tris, view, depth=4096, flags=1)
+        b_ids, b_dep, ovf = _render(gpu, tris, view, depth=2048, flags=1)
         assert ovf == 0
         assert np.array_equal(a_ids, b_ids)
         assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
@@ -218,7 +218,7 @@ def test_fused_matches_plain(gpu, name, view, make):
     """vsr_render (depth-sliced, fused) gives the same bits as bin + raster."""
     tris = make()
     _say(f"[fused] {name} {view.width}x{view.height} T={tris.shape[1]}")
-    a_ids, a_dep, _ = _render(gpu, tris, view, depth=4096)
+    a_ids, a_dep, _ = _render(gpu, tris, view, depth=2048)
     b_ids, b_dep = _render_fused(gpu, tris, view)
     assert np.array_equal(a_ids, b_ids)
     assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))

@@ -49,7 +49,7 @@ def test_sizes(vsr):
     with pytest.raises(vsr.VsrError):
         vsr.vsr_bin_bytes(16, 16, 0)
     with pytest.raises(vsr.VsrError):
-        vsr.vsr_bin_bytes(16, 16, 9000)
+        vsr.vsr_bin_bytes(16, 16, 3000)
     with pytest.raises(vsr.VsrError):
         vsr.vsr_setup_bytes(-1)
 
