@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: no CPU leg, fewer passes")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU split of this "
@@ -194,6 +197,33 @@ def main():
     log(f"fused submit: {fsubmit_ms:.3f} ms ({len(views) / fsubmit_ms * 1e3:.1f} views/s)")
     del fbatch
 
+    # ---------------- serving: Poisson arrivals over three resident scenes
+    serve_stats = None
+    if args.serve_seconds > 0 and not args.profile:
+        from paper_2003_10558_amd import serve
+        t0 = time.time()
+        sc_np = synth.serve_scenes()
+        sc = [pipeline.Scene(t, device=dev) for t in sc_np]
+        torch.cuda.synchronize()
+        log(f"serving scenes {[t.shape[1] for t in sc_np]} ready in {time.time() - t0:.1f}s")
+        reqs = serve.make_requests(len(sc), rate_hz=args.serve_rate, duration_s=args.serve_seconds,
+                                   seed=synth.SERVE_ARRIVAL_SEED, view_seed=synth.SERVE_ARRIVAL_SEED + 100,
+                                   resolutions=synth.SERVE_RESOLUTIONS)
+        srv = serve.Server(sc, streams=3, max_batch=32, hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)),
+                           mode_for_scene=lambda s: (vsr.VSR_SUBMIT_FUSED, depth))
+        warm = serve.make_requests(len(sc), rate_hz=200.0, duration_s=0.1, seed=99, view_seed=98,
+                                   resolutions=synth.SERVE_RESOLUTIONS)
+        srv.run(warm)
+        st = srv.run(reqs)
+        serve_stats = st.as_dict()
+        serve_stats.update({"rate_hz": args.serve_rate, "duration_s": args.serve_seconds,
+                            "scenes": [int(t.shape[1]) for t in sc_np],
+                            "resolutions": [list(r) for r in synth.SERVE_RESOLUTIONS]})
+        log(f"serving: offered {st.offered} at {args.serve_rate:.0f}/s for {args.serve_seconds}s: completed "
+            f"{st.completed}, dropped {st.dropped}, {st.views_per_s:.1f} views/s, p50 {st.p50_ms:.1f} ms, "
+            f"p99 {st.p99_ms:.1f} ms, mean batch {st.mean_batch:.1f}")
+        del sc, srv
+
     # ---------------- roofline of the rasterizer (dominant kernel)
     t_r = float(np.mean(rast)) * 1e-3
     achieved = OPS_PER_FRAGMENT * F_mean / t_r
@@ -255,6 +285,7 @@ def main():
         "overflowed_tiles_plain": overflow,
         "fused_fps": 1e3 / fused_ms,
         "batched_fused_fps": len(views) / fsubmit_ms * 1e3,
+        "serving": serve_stats,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
