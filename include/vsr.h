@@ -210,6 +210,21 @@ int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
 int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth, void* workspace,
                int64_t ws_bytes, void* stream);
 
+/* Graph-friendly batches.  A caller that replays one captured vsr_submit
+ * with new view parameters (same sizes, same scenes' triangle counts) writes
+ * the job table itself between replays:
+ *   vsr_submit_table() fills host_table (vsr_submit_table_bytes(njobs)
+ *   bytes) with the table vsr_submit would write for these jobs and this
+ *   workspace; the caller copies it to workspace + vsr_submit_table_offset()
+ *   on its stream and launches (or replays a capture of) vsr_submit with
+ *   mode | VSR_SUBMIT_TABLE_READY, which then reads the table instead of
+ *   writing it. */
+#define VSR_SUBMIT_TABLE_READY 0x100
+int64_t vsr_submit_table_bytes(int32_t njobs);
+int64_t vsr_submit_table_offset(void);
+int vsr_submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth,
+                     const void* workspace, void* host_table, int64_t host_table_bytes);
+
 /* ---------------------------------------------------------- diagnostics */
 
 /* Host call after the stream has synchronised: number of overflowed tiles

@@ -254,8 +254,31 @@ int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
     return submit_bytes(jobs, njobs, fmt, mode, bin_depth);
 }
 
+int64_t vsr_submit_table_bytes(int32_t njobs) {
+    if (njobs < 1 || njobs > 4096) return VSR_E_ARG;
+    return submit_table_bytes(njobs);
+}
+
+int64_t vsr_submit_table_offset(void) { return submit_table_offset(); }
+
+int vsr_submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth,
+                     const void* workspace, void* host_table, int64_t host_table_bytes) {
+    if (!jobs || njobs < 1 || njobs > 4096) return fail(VSR_E_ARG, "njobs %d outside 1..4096", njobs);
+    if (!workspace || !aligned(workspace) || !host_table) return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if (host_table_bytes < submit_table_bytes(njobs)) return fail(VSR_E_SPACE, "host table too small");
+    for (int32_t q = 0; q < njobs; ++q) {
+        MapParams P;
+        int rc = make_map_params(&jobs[q].view, fmt, 0, &P, nullptr);
+        if (rc != VSR_OK) return rc;
+    }
+    submit_table(jobs, njobs, fmt, mode, bin_depth, const_cast<void*>(workspace), host_table);
+    return VSR_OK;
+}
+
 int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth, void* workspace,
                int64_t ws_bytes, void* stream) {
+    const bool table_ready = (mode & VSR_SUBMIT_TABLE_READY) != 0;
+    mode &= ~VSR_SUBMIT_TABLE_READY;
     if (!jobs || njobs < 1 || njobs > 4096) return fail(VSR_E_ARG, "njobs %d outside 1..4096", njobs);
     if (mode != VSR_SUBMIT_BINNED && mode != VSR_SUBMIT_FUSED) return fail(VSR_E_ARG, "unknown submit mode %d", mode);
     if (mode == VSR_SUBMIT_BINNED && (bin_depth < 1 || bin_depth > kMaxDepth))
@@ -273,7 +296,8 @@ int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, in
     }
     int64_t need = submit_bytes(jobs, njobs, fmt, mode, bin_depth);
     if (ws_bytes < need) return fail(VSR_E_SPACE, "workspace %lld < %lld bytes", (long long)ws_bytes, (long long)need);
-    return hip_status(launch_submit(jobs, njobs, fmt, mode, bin_depth, workspace, hipStream_t(stream)), "vsr_submit");
+    return hip_status(launch_submit(jobs, njobs, fmt, mode, bin_depth, workspace, table_ready, hipStream_t(stream)),
+                      "vsr_submit");
 }
 
 int vsr_bin_overflow(const void* bins_or_ws, int32_t is_workspace, int64_t* overflowed_tiles) {

@@ -12,6 +12,9 @@
 // rendering that view alone.
 
 #pragma once
+#include <algorithm>
+#include <vector>
+
 #include "fused.hpp"
 #include "map.hpp"
 
@@ -170,19 +173,15 @@ __global__ __launch_bounds__(256) void k_submit_map(const JobDesc* __restrict__ 
     build_map_tile(J.P, J.map, J.ntiles, t - J.tile_off, threadIdx.x & 63);
 }
 
-hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth, void* ws,
-                         hipStream_t st) {
+// Job descriptors of a submit, in workspace order; returns the number of
+// tiles and super-tiles through the pointers.
+static void build_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth, void* ws,
+                        JobDesc* out, int64_t* n_tiles, int64_t* n_stiles) {
     WsLayout W = ws_layout(njobs);
     char* base = reinterpret_cast<char*>(ws);
-    JobDesc* table = reinterpret_cast<JobDesc*>(base + W.table_off);
-    int64_t off = W.data_off, tiles = 0;
-    int64_t stiles = 0;
-    JobChunk chunk;
-    chunk.first = 0;
-    chunk.count = 0;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ws), int64_t(64));
+    int64_t off = W.data_off, tiles = 0, stiles = 0;
     for (int32_t q = 0; q < njobs; ++q) {
-        JobDesc& D = chunk.d[chunk.count];
+        JobDesc& D = out[q];
         make_map_params(&jobs[q].view, fmt, 0, &D.P, nullptr);
         MapLayout ML = map_layout(D.P.W, D.P.H, fmt);
         D.map = base + off;
@@ -200,10 +199,39 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
         D.tile_off = tiles;
         D.ntiles = ML.ntiles;
         tiles += ML.ntiles;
-        if (++chunk.count == kJobChunk || q == njobs - 1) {
+    }
+    *n_tiles = tiles;
+    *n_stiles = stiles;
+}
+
+int64_t submit_table_bytes(int32_t njobs) { return int64_t(njobs) * int64_t(sizeof(JobDesc)); }
+
+// Host image of the job table that vsr_submit would write into `ws`.
+void submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth, void* ws,
+                  void* host) {
+    int64_t t, s;
+    build_table(jobs, njobs, fmt, mode, depth, ws, reinterpret_cast<JobDesc*>(host), &t, &s);
+}
+
+int64_t submit_table_offset() { return ws_layout(1).table_off; }
+
+hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth, void* ws,
+                         bool table_ready, hipStream_t st) {
+    WsLayout W = ws_layout(njobs);
+    char* base = reinterpret_cast<char*>(ws);
+    JobDesc* table = reinterpret_cast<JobDesc*>(base + W.table_off);
+    std::vector<JobDesc> host(njobs);
+    int64_t tiles = 0, stiles = 0;
+    build_table(jobs, njobs, fmt, mode, depth, ws, host.data(), &tiles, &stiles);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ws), int64_t(64));
+    if (!table_ready) {
+        // descriptors travel as kernel arguments: no host-memory copy
+        for (int32_t first = 0; first < njobs; first += kJobChunk) {
+            JobChunk chunk;
+            chunk.first = first;
+            chunk.count = std::min(kJobChunk, njobs - first);
+            for (int q = 0; q < chunk.count; ++q) chunk.d[q] = host[first + q];
             hipLaunchKernelGGL(k_write_jobs, dim3(1), dim3(kJobChunk), 0, st, chunk, table);
-            chunk.first = q + 1;
-            chunk.count = 0;
         }
     }
     hipLaunchKernelGGL(k_submit_map, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, tiles);

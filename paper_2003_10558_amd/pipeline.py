@@ -100,6 +100,53 @@ class Batch:
         return self.outputs
 
 
+class GraphBatch:
+    """A batch captured once in a HIP graph and replayed with new view
+    parameters.  Shapes (view sizes, scenes) are fixed at capture; between
+    replays set_views() rewrites the job table in device memory with one
+    host-to-device copy on the capture stream."""
+
+    def __init__(self, items: Sequence[Tuple[Scene, object]], fmt: int = vsr.VSR_MAP_F32,
+                 mode: int = vsr.VSR_SUBMIT_BINNED, bin_depth: int = DEFAULT_BIN_DEPTH, stream=None):
+        self.batch = Batch(items, fmt=fmt, mode=mode, bin_depth=bin_depth)
+        self.stream = stream or torch.cuda.Stream(device=self.batch.workspace.device)
+        nb = vsr.vsr_submit_table_bytes(len(self.batch.jobs))
+        off = vsr.vsr_submit_table_offset()
+        self.table_host = torch.empty(nb, dtype=torch.uint8, pin_memory=True)
+        self.table_dev = self.batch.workspace[off:off + nb]
+        self.set_views([v for _, v in items])
+        self.stream.synchronize()
+        # warm-up launch outside the capture, then capture
+        with torch.cuda.stream(self.stream):
+            self._launch()
+        self.stream.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=self.stream):
+            self._launch()
+
+    def _launch(self):
+        b = self.batch
+        vsr.vsr_submit(b.jobs, b.fmt, b.mode | vsr.VSR_SUBMIT_TABLE_READY, b.bin_depth, b.workspace,
+                       torch.cuda.current_stream())
+
+    def set_views(self, views: Sequence[object]) -> None:
+        b = self.batch
+        assert len(views) == len(b.jobs)
+        for q, v in enumerate(views):
+            old = b.jobs[q].view
+            assert (int(v.width), int(v.height)) == (old.width, old.height), "view sizes are fixed at capture"
+            b.jobs[q].view = vsr.make_view(v)
+        self.stream.synchronize()  # the previous replay may still read the table
+        vsr.vsr_submit_table(b.jobs, b.fmt, b.mode, b.bin_depth, b.workspace, self.table_host)
+        with torch.cuda.stream(self.stream):
+            self.table_dev.copy_(self.table_host, non_blocking=True)
+
+    def replay(self) -> List[Tuple[torch.Tensor, torch.Tensor]]:
+        with torch.cuda.stream(self.stream):
+            self.graph.replay()
+        return self.batch.outputs
+
+
 def ids_u32(t: torch.Tensor) -> np.ndarray:
     """Device int32 id image -> host uint32 array."""
     return t.cpu().numpy().view(np.uint32)

@@ -21,6 +21,7 @@ VSR_STRICT = 1
 VSR_BIN_ALL = 1
 VSR_NO_HIT = 0xFFFFFFFF
 VSR_SUBMIT_BINNED, VSR_SUBMIT_FUSED = 0, 1
+VSR_SUBMIT_TABLE_READY = 0x100
 VSR_TILE = 8
 VSR_AOV_HORIZONTAL, VSR_AOV_DIAGONAL, VSR_AOV_VERTICAL, VSR_AOV_HORIZONTAL_4X3 = 0, 1, 2, 3
 
@@ -67,15 +68,22 @@ _lib.vsr_render.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp,
 _lib.vsr_submit_bytes.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32]
 _lib.vsr_submit_bytes.restype = _i64
 _lib.vsr_submit.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32, _vp, _i64, _vp]
+_lib.vsr_submit_table_bytes.argtypes = [_i32]
+_lib.vsr_submit_table_bytes.restype = _i64
+_lib.vsr_submit_table_offset.argtypes = []
+_lib.vsr_submit_table_offset.restype = _i64
+_lib.vsr_submit_table.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32, _vp, _vp, _i64]
 _lib.vsr_bin_overflow.argtypes = [_vp, _i32, ctypes.POINTER(_i64)]
 _lib.vsr_strerror.argtypes = [ctypes.c_int]
 _lib.vsr_strerror.restype = ctypes.c_char_p
 _lib.vsr_last_error.restype = ctypes.c_char_p
-for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_raster", "vsr_raster_stats", "vsr_render", "vsr_submit", "vsr_bin_overflow"):
+for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_raster", "vsr_raster_stats", "vsr_render", "vsr_submit", "vsr_submit_table",
+           "vsr_bin_overflow"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin",
-           "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_submit_bytes", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
+           "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_submit_bytes",
+           "vsr_submit_table_bytes", "vsr_submit_table_offset", "vsr_submit_table", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
 
 
 def _check(rc: int) -> None:
@@ -193,6 +201,21 @@ def vsr_submit_bytes(jobs, fmt: int, mode: int = 0, bin_depth: int = 1024) -> in
 def vsr_submit(jobs, fmt: int, mode: int, bin_depth: int, workspace, stream=None) -> None:
     _check(_lib.vsr_submit(jobs, len(jobs), fmt, mode, bin_depth, _ptr(workspace), _nbytes(workspace),
                            _stream(stream)))
+
+
+def vsr_submit_table_bytes(njobs: int) -> int:
+    return _size(_lib.vsr_submit_table_bytes(njobs), "vsr_submit_table_bytes")
+
+
+def vsr_submit_table_offset() -> int:
+    return int(_lib.vsr_submit_table_offset())
+
+
+def vsr_submit_table(jobs, fmt: int, mode: int, bin_depth: int, workspace, host_table) -> None:
+    """host_table: a host (CPU) uint8 tensor or numpy array."""
+    ptr = host_table.data_ptr() if hasattr(host_table, "data_ptr") else host_table.ctypes.data
+    n = host_table.numel() if hasattr(host_table, "numel") else host_table.nbytes
+    _check(_lib.vsr_submit_table(jobs, len(jobs), fmt, mode, bin_depth, _ptr(workspace), ptr, n))
 
 
 def vsr_bin_overflow(bins_or_ws, is_workspace: bool = False) -> int:
