@@ -47,36 +47,68 @@ __device__ inline SceneView scene_view(const void* setup, int64_t n) {
 
 // Longitude range of a cap (centre with components p along the measured
 // axis, q along the face normal, r along the rotation axis; radius alpha),
-// intersected with the face's [-pi/4, pi/4].  False when empty.
+// intersected with the face's [-pi/4, pi/4], as u = tan(longitude).  False
+// when empty.  General, for caps that reach the face's plane.
 __device__ inline bool lon_range(float p, float q, float r, float alpha, float& lo, float& hi) {
     float lam = atan2f(p, q);
     float beta = asinf(fminf(1.0f, fmaxf(-1.0f, r)));
     if (fabsf(beta) + alpha >= kHalfPi) {
-        lo = -kQuarterPi;
-        hi = kQuarterPi;
+        lo = -1.0f;
+        hi = 1.0f;
         return true;
     }
     float dl = asinf(fminf(1.0f, sinf(alpha) / cosf(beta))) + 1e-5f;
-    lo = fmaxf(lam - dl, -kQuarterPi);
-    hi = fminf(lam + dl, kQuarterPi);
+    float a = fmaxf(lam - dl, -kQuarterPi), b = fminf(lam + dl, kQuarterPi);
+    if (a > b) return false;
+    lo = tanf(a);
+    hi = tanf(b);
+    return true;
+}
+
+// Range of u = p_u / p_a over a cap (centre c, sa = sine of its radius)
+// lying wholly in the half-space p_a > 0 (ca > sa), clipped to [-1, 1]; the
+// extremes are where a plane p_u = u p_a through O is tangent to the cap:
+// (cu - u ca)^2 = sa^2 (1 + u^2).  False when the range misses [-1, 1].
+__device__ inline bool tangent_range(float ca, float cu, float sa, float& lo, float& hi) {
+    const float den = ca * ca - sa * sa;
+    const float root = sa * sqrtf(fmaxf(0.0f, ca * ca + cu * cu - sa * sa));
+    const float mid = ca * cu;
+    const float u1 = (mid - root) / den, u2 = (mid + root) / den;
+    lo = fmaxf(u1 - 1e-5f * (1.0f + fabsf(u1)), -1.0f);
+    hi = fminf(u2 + 1e-5f * (1.0f + fabsf(u2)), 1.0f);
     return lo <= hi;
 }
 
-__device__ inline int cell_index(float angle, int M) {
-    float u = tanf(angle);
+__device__ inline int cell_index(float u, int M) {
     return min(M - 1, max(0, int(floorf((u + 1.0f) * 0.5f * M))));
 }
+
+// Angle from a cube face's centre axis to its corners, acos(1/sqrt(3)), plus
+// a margin: the face lies inside the cap of this radius around its axis.
+constexpr float kFaceRadius = 0.95533f;
 
 // Cell rectangle [iu0, iu1] x [iv0, iv1] of cube face `face` at M x M cells
 // that contains every direction within alpha of c on that face.
 __device__ inline bool face_cells(float3 c, float alpha, int face, int M, int& iu0, int& iu1, int& iv0, int& iv1) {
-    int a = face >> 1;
-    float sg = (face & 1) ? -1.0f : 1.0f;
-    float comp[3] = {c.x, c.y, c.z};
-    float ca = comp[a] * sg, cu = comp[(a + 1) % 3], cv = comp[(a + 2) % 3];
+    if (!(alpha < kHalfPi)) {
+        iu0 = iv0 = 0;
+        iu1 = iv1 = M - 1;
+        return true;
+    }
+    const int a = face >> 1;
+    const float sg = (face & 1) ? -1.0f : 1.0f;
+    const float comp[3] = {c.x, c.y, c.z};
+    const float ca = comp[a] * sg, cu = comp[(a + 1) % 3], cv = comp[(a + 2) % 3];
+    if (alpha + kFaceRadius < kPi && ca < cosf(alpha + kFaceRadius + 1e-5f)) return false;
     float ulo, uhi, vlo, vhi;
-    if (!lon_range(cu, ca, cv, alpha, ulo, uhi)) return false;
-    if (!lon_range(cv, ca, cu, alpha, vlo, vhi)) return false;
+    const float sa = sinf(alpha);
+    if (ca > sa * (1.0f + 1e-5f) + 1e-6f) {
+        if (!tangent_range(ca, cu, sa, ulo, uhi)) return false;
+        if (!tangent_range(ca, cv, sa, vlo, vhi)) return false;
+    } else {
+        if (!lon_range(cu, ca, cv, alpha, ulo, uhi)) return false;
+        if (!lon_range(cv, ca, cu, alpha, vlo, vhi)) return false;
+    }
     iu0 = cell_index(ulo, M);
     iu1 = cell_index(uhi, M);
     iv0 = cell_index(vlo, M);

@@ -113,6 +113,20 @@ def test_binning_is_exact(gpu):
         assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
 
 
+@pytest.mark.parametrize("seed", list(range(6)))
+def test_binning_is_exact_random_views(gpu, seed):
+    """Random lenses up to 360 degrees, random orientation: culling never
+    drops a triangle the rasterizer covers (bit-identical to no culling)."""
+    views = synth.random_views(4, 500 + seed, resolutions=((200, 150), (96, 96), (311, 97)))
+    tris = synth.scene(700, 600 + seed)
+    for v in views:
+        a_ids, a_dep, _ = _render(gpu, tris, v)
+        b_ids, b_dep, ovf = _render(gpu, tris, v, depth=2048, flags=1)
+        assert ovf == 0
+        assert np.array_equal(a_ids, b_ids), (v.k, v.omega_deg)
+        assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
+
+
 RAGGED = [
     (1, 1, 0), (7, 5, 0), (8, 8, 1), (9, 9, 2), (37, 23, 3), (129, 65, 0), (255, 257, 1),
 ]
