@@ -29,7 +29,7 @@ __device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
     int64_t tile;
     int tx, ty;
     const bool present = super_tile_of(sidx, w, A.ntx, A.nty, tile, tx, ty);
-    super_setup(sh, map_caps(A.map, A.ntiles, A.fmt), present, tile);
+    super_setup(sh, map_caps(A.map, A.ntiles, A.fmt), scene_view(A.setup, A.n).face_count, present, tile);
     const bool any = sh.sup[1].z != 0.0f;
     const SceneView S = scene_view(A.setup, A.n);
     const uint32_t lcap = uint32_t(A.lds_cap);

@@ -86,6 +86,41 @@ __device__ inline int cell_index(float u, int M) {
 // Angle from a cube face's centre axis to its corners, acos(1/sqrt(3)), plus
 // a margin: the face lies inside the cap of this radius around its axis.
 constexpr float kFaceRadius = 0.95533f;
+constexpr float kCosFace = 0.5773390f;  // cos(kFaceRadius) = 0.57733934..., rounded down
+constexpr float kSinFace = 0.8165046f;  // sin(kFaceRadius) = 0.81650431..., rounded up
+
+// face_cells with the cap radius given by its sine and cosine (sa, ca_):
+// no transcendental on the common path.
+__device__ inline bool face_cells_sc(float3 c, float sa, float ca_, int face, int M, int& iu0, int& iu1, int& iv0,
+                                     int& iv1) {
+    if (!(ca_ > 0.0f)) {  // radius >= pi/2
+        iu0 = iv0 = 0;
+        iu1 = iv1 = M - 1;
+        return true;
+    }
+    const int a = face >> 1;
+    const float sg = (face & 1) ? -1.0f : 1.0f;
+    const float comp[3] = {c.x, c.y, c.z};
+    const float cax = comp[a] * sg, cu = comp[(a + 1) % 3], cv = comp[(a + 2) % 3];
+    // reject faces outside the cap of radius alpha + kFaceRadius around c
+    const float cf = ca_ * kCosFace - sa * kSinFace;  // cos(alpha + face radius)
+    const float sf = sa * kCosFace + ca_ * kSinFace;
+    if (sf > 0.0f && cax < cf - 1e-6f) return false;
+    float ulo, uhi, vlo, vhi;
+    if (cax > sa * (1.0f + 1e-5f) + 1e-6f) {
+        if (!tangent_range(cax, cu, sa, ulo, uhi)) return false;
+        if (!tangent_range(cax, cv, sa, vlo, vhi)) return false;
+    } else {
+        const float alpha = atan2f(sa, ca_);
+        if (!lon_range(cu, cax, cv, alpha, ulo, uhi)) return false;
+        if (!lon_range(cv, cax, cu, alpha, vlo, vhi)) return false;
+    }
+    iu0 = cell_index(ulo, M);
+    iu1 = cell_index(uhi, M);
+    iv0 = cell_index(vlo, M);
+    iv1 = cell_index(vhi, M);
+    return true;
+}
 
 // Cell rectangle [iu0, iu1] x [iv0, iv1] of cube face `face` at M x M cells
 // that contains every direction within alpha of c on that face.
@@ -203,8 +238,10 @@ struct SuperShared {
     uint32_t rb[256], pre[256], wsum[4];
     uint32_t cnt[kSupTiles];
     uint32_t flag[kSupTiles];
+    uint32_t fc[kSlices * 64];  // per-slice (level, face) triangle counts
     uint32_t bk[kSupTiles][kDepthBuckets];
 };
+static_assert(kSlices * 64 == 256, "one face count per thread of the 256-thread block");
 
 // Exclusive scan of one value per thread over a 256-thread block.
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wsum, uint32_t& total) {
@@ -234,14 +271,19 @@ __device__ inline bool super_tile_of(int64_t sidx, int w, int ntx, int nty, int6
     return tx < ntx && ty < nty;
 }
 
-// Loads the four tile caps, computes the super-tile cap and the cell
-// rectangles of every (level, face).  All threads of the block call it.
-__device__ inline void super_setup(SuperShared& sh, const float4* caps, bool present, int64_t tile) {
+// Loads the four tile caps and the per-slice face counts, computes the
+// super-tile cap and the cell rectangles of every (level, face).  All
+// threads of the block call it.  Angles are never formed: caps carry
+// sin and cos of their half radius, and radii add through the angle-sum
+// identities.
+__device__ inline void super_setup(SuperShared& sh, const float4* caps, const uint32_t* face_count, bool present,
+                                   int64_t tile) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (lane == 0) {
         sh.cap[w][0] = present ? caps[2 * tile] : empty_cap0();
         sh.cap[w][1] = present ? caps[2 * tile + 1] : empty_cap1();
     }
+    sh.fc[tid] = face_count[tid];  // kSlices * 64 == 256 entries
     if (tid < kSupTiles) {
         sh.cnt[tid] = 0;
         sh.flag[tid] = 0;
@@ -258,26 +300,42 @@ __device__ inline void super_setup(SuperShared& sh, const float4* caps, bool pre
             sum = add3(sum, f3(c0.x, c0.y, c0.z));
         }
         float3 c = f3(0.f, 0.f, 1.f);
-        float rho = kPi;
+        float sh_ = 1.0f, ch_ = 0.0f;  // sin, cos of half the super-cap radius
         if (any0 && !wide0) {
             float len = sqrtf(dot3(sum, sum));
             if (len > 1e-3f) {
                 c = scale3(sum, 1.0f / len);
-                rho = 0.0f;
+                sh_ = 0.0f;
+                ch_ = 1.0f;
                 for (int q = 0; q < kSupTiles; ++q) {
                     float4 c0 = sh.cap[q][0], c1 = sh.cap[q][1];
                     if (c1.z == kCapEmpty) continue;
+                    // half-angle between the centres from the chord, plus the
+                    // tile's half radius: sin/cos of the sum
                     float3 d = sub3(c, f3(c0.x, c0.y, c0.z));
-                    float ang = 2.0f * asinf(fminf(1.0f, 0.5f * sqrtf(dot3(d, d))));
-                    rho = fmaxf(rho, ang + 2.0f * asinf(fminf(1.0f, c0.w)));
+                    float st = fminf(1.0f, 0.5f * sqrtf(dot3(d, d)));
+                    float ct = sqrtf(fmaxf(0.0f, 1.0f - st * st));
+                    float sq = st * c1.x + ct * c0.w, cq = ct * c1.x - st * c0.w;
+                    if (!(cq > 0.0f)) {
+                        wide0 = true;
+                    } else if (sq > sh_) {
+                        sh_ = sq;
+                        ch_ = cq;
+                    }
                 }
-                rho = rho * (1.0f + kCapRelMargin) + 1e-6f;
+                // margin: grow the half radius by a relative 1e-6 and 1e-7 rad
+                sh_ = sh_ * (1.0f + 1e-6f) + 1e-7f;
+                ch_ = sqrtf(fmaxf(0.0f, 1.0f - sh_ * sh_));
+            } else {
+                wide0 = true;
             }
-            if (!(rho < kHalfPi)) wide0 = true;
+            if (!(sh_ < 0.70710678f)) wide0 = true;  // radius >= pi/2
         }
-        float sh_ = 1.0f, ch_ = 0.0f;
-        if (!wide0) sincosf(0.5f * rho, &sh_, &ch_);
-        sh.sup[0] = make_float4(c.x, c.y, c.z, rho);
+        if (wide0) {
+            sh_ = 1.0f;
+            ch_ = 0.0f;
+        }
+        sh.sup[0] = make_float4(c.x, c.y, c.z, sh_);
         sh.sup[1] = make_float4(sh_, ch_, any0 ? 1.0f : 0.0f, wide0 ? 1.0f : 0.0f);
     }
     __syncthreads();
@@ -285,12 +343,21 @@ __device__ inline void super_setup(SuperShared& sh, const float4* caps, bool pre
         const float4 sup0 = sh.sup[0], sup1 = sh.sup[1];
         int iu0 = 1, iu1 = 0, iv0 = 1, iv1 = 0;
         if (tid < 6 * kLevels && sup1.z != 0.0f) {
-            int L = tid / 6, face = tid % 6, M = 1 << L;
-            float RL = (L == 0) ? kHalfPi : kQuarterPi / float(M);
-            float alpha = (sup1.w != 0.0f ? kPi : sup0.w) + RL + 1e-5f;
-            if (!face_cells(f3(sup0.x, sup0.y, sup0.z), alpha, face, M, iu0, iu1, iv0, iv1)) {
-                iu0 = 1;
-                iu1 = 0;
+            const int L = tid / 6, face = tid % 6, M = 1 << L;
+            const float RL = ((L == 0) ? kHalfPi : kQuarterPi / float(M)) + 1e-5f;
+            if (sup1.w != 0.0f) {
+                iu0 = iv0 = 0;
+                iu1 = iv1 = M - 1;
+            } else {
+                // alpha = super radius + R_L: sin and cos from the sum identities
+                const float srho = 2.0f * sup1.x * sup1.y, crho = 1.0f - 2.0f * sup1.x * sup1.x;
+                float sR, cR;
+                sincosf(RL, &sR, &cR);
+                const float sa = srho * cR + crho * sR, ca = crho * cR - srho * sR;
+                if (!face_cells_sc(f3(sup0.x, sup0.y, sup0.z), sa, ca, face, M, iu0, iu1, iv0, iv1)) {
+                    iu0 = 1;
+                    iu1 = 0;
+                }
             }
         }
         sh.rect[tid][0] = iu0;
@@ -323,7 +390,7 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
         uint32_t nr = 0;
         for (int s = s0; s < s1; ++s) {
             sh.spre[tid][s - s0] = nr;
-            if (rows && S.face_count[s * 64 + tid] != 0) nr += rows;
+            if (rows && sh.fc[s * 64 + tid] != 0) nr += rows;
         }
         sh.spre[tid][s1 - s0] = nr;
         uint32_t x = nr;
