@@ -26,7 +26,8 @@ struct SceneView {
     const float4* cap;         // 2 x float4 per triangle, rank order
     const uint32_t* cell_list; // ranks sorted by (slice, cell)
     const uint32_t* cell_start;
-    const float4* binrec;      // cell-ordered binning records
+    const float4* bincap;      // cell-ordered caps: centre, sine of half radius (kBinWide: wide)
+    const float4* binnrm;      // cell-ordered unit edge normals (3 per triangle; rank in .w of the first)
     const uint32_t* face_count;
     int64_t n;
 };
@@ -39,44 +40,45 @@ __device__ inline SceneView scene_view(const void* setup, int64_t n) {
     s.cap = reinterpret_cast<const float4*>(b + L.cap_off);
     s.cell_list = reinterpret_cast<const uint32_t*>(b + L.cell_list_off);
     s.cell_start = reinterpret_cast<const uint32_t*>(b + L.cell_start_off);
-    s.binrec = reinterpret_cast<const float4*>(b + L.binrec_off);
+    s.bincap = reinterpret_cast<const float4*>(b + L.bincap_off);
+    s.binnrm = reinterpret_cast<const float4*>(b + L.binnrm_off);
     s.face_count = reinterpret_cast<const uint32_t*>(b + L.face_count_off);
     s.n = n;
     return s;
 }
 
-// Longitude range of a cap (centre with components p along the measured
-// axis, q along the face normal, r along the rotation axis; radius alpha),
-// intersected with the face's [-pi/4, pi/4], as u = tan(longitude).  False
-// when empty.  General, for caps that reach the face's plane.
-__device__ inline bool lon_range(float p, float q, float r, float alpha, float& lo, float& hi) {
-    float lam = atan2f(p, q);
-    float beta = asinf(fminf(1.0f, fmaxf(-1.0f, r)));
-    if (fabsf(beta) + alpha >= kHalfPi) {
-        lo = -1.0f;
-        hi = 1.0f;
-        return true;
+// Range of u = p_u / p_a, clipped to [-1, 1], over the directions p of a cap
+// that lie on the cube face with axis a.  The cap has centre components ca
+// (along a) and cu (along u) and radius alpha < pi/2 with sine sa.  Such a p
+// lies on the plane through O on which p_u = u p_a; the centre is then within
+// alpha of that plane, |cu - u ca| <= sa sqrt(1 + u^2), i.e.
+//   f(u) = (ca^2 - sa^2) u^2 - 2 ca cu u + cu^2 - sa^2 <= 0.
+// The hull of {u in [-1, 1] : f(u) <= 0}, evaluated in FP64 so that rounding
+// stays far below the cap margins; false when empty.
+__device__ inline bool axis_range(float ca_f, float cu_f, float sa_f, float& lo, float& hi) {
+    const double ca = ca_f, cu = cu_f, sa = sa_f;
+    const double den = ca * ca - sa * sa;
+    const double disc = ca * ca + cu * cu - sa * sa;  // discriminant of f / (4 sa^2)
+    double a = -1.0, b = 1.0;
+    if (disc > 0.0 && fabs(den) > 1e-8) {
+        const double root = sa * sqrt(disc), mid = ca * cu;
+        double r1 = (mid - root) / den, r2 = (mid + root) / den;
+        if (den > 0.0) {  // f <= 0 between the roots r1 <= r2
+            a = fmax(r1 - 1e-7 * (1.0 + fabs(r1)), -1.0);
+            b = fmin(r2 + 1e-7 * (1.0 + fabs(r2)), 1.0);
+            if (a > b) return false;
+        } else {  // f <= 0 outside (r2, r1)
+            r2 += 1e-7 * (1.0 + fabs(r2));
+            r1 -= 1e-7 * (1.0 + fabs(r1));
+            const bool left = r2 >= -1.0, right = r1 <= 1.0;
+            if (!left && !right) return false;
+            if (!right) b = fmin(r2, 1.0);
+            if (!left) a = fmax(r1, -1.0);
+        }
     }
-    float dl = asinf(fminf(1.0f, sinf(alpha) / cosf(beta))) + 1e-5f;
-    float a = fmaxf(lam - dl, -kQuarterPi), b = fminf(lam + dl, kQuarterPi);
-    if (a > b) return false;
-    lo = tanf(a);
-    hi = tanf(b);
+    lo = float(a);
+    hi = float(b);
     return true;
-}
-
-// Range of u = p_u / p_a over a cap (centre c, sa = sine of its radius)
-// lying wholly in the half-space p_a > 0 (ca > sa), clipped to [-1, 1]; the
-// extremes are where a plane p_u = u p_a through O is tangent to the cap:
-// (cu - u ca)^2 = sa^2 (1 + u^2).  False when the range misses [-1, 1].
-__device__ inline bool tangent_range(float ca, float cu, float sa, float& lo, float& hi) {
-    const float den = ca * ca - sa * sa;
-    const float root = sa * sqrtf(fmaxf(0.0f, ca * ca + cu * cu - sa * sa));
-    const float mid = ca * cu;
-    const float u1 = (mid - root) / den, u2 = (mid + root) / den;
-    lo = fmaxf(u1 - 1e-5f * (1.0f + fabsf(u1)), -1.0f);
-    hi = fminf(u2 + 1e-5f * (1.0f + fabsf(u2)), 1.0f);
-    return lo <= hi;
 }
 
 __device__ inline int cell_index(float u, int M) {
@@ -107,14 +109,7 @@ __device__ inline bool face_cells_sc(float3 c, float sa, float ca_, int face, in
     const float sf = sa * kCosFace + ca_ * kSinFace;
     if (sf > 0.0f && cax < cf - 1e-6f) return false;
     float ulo, uhi, vlo, vhi;
-    if (cax > sa * (1.0f + 1e-5f) + 1e-6f) {
-        if (!tangent_range(cax, cu, sa, ulo, uhi)) return false;
-        if (!tangent_range(cax, cv, sa, vlo, vhi)) return false;
-    } else {
-        const float alpha = atan2f(sa, ca_);
-        if (!lon_range(cu, cax, cv, alpha, ulo, uhi)) return false;
-        if (!lon_range(cv, cax, cu, alpha, vlo, vhi)) return false;
-    }
+    if (!axis_range(cax, cu, sa, ulo, uhi) || !axis_range(cax, cv, sa, vlo, vhi)) return false;
     iu0 = cell_index(ulo, M);
     iu1 = cell_index(uhi, M);
     iv0 = cell_index(vlo, M);
@@ -130,25 +125,9 @@ __device__ inline bool face_cells(float3 c, float alpha, int face, int M, int& i
         iu1 = iv1 = M - 1;
         return true;
     }
-    const int a = face >> 1;
-    const float sg = (face & 1) ? -1.0f : 1.0f;
-    const float comp[3] = {c.x, c.y, c.z};
-    const float ca = comp[a] * sg, cu = comp[(a + 1) % 3], cv = comp[(a + 2) % 3];
-    if (alpha + kFaceRadius < kPi && ca < cosf(alpha + kFaceRadius + 1e-5f)) return false;
-    float ulo, uhi, vlo, vhi;
-    const float sa = sinf(alpha);
-    if (ca > sa * (1.0f + 1e-5f) + 1e-6f) {
-        if (!tangent_range(ca, cu, sa, ulo, uhi)) return false;
-        if (!tangent_range(ca, cv, sa, vlo, vhi)) return false;
-    } else {
-        if (!lon_range(cu, ca, cv, alpha, ulo, uhi)) return false;
-        if (!lon_range(cv, ca, cu, alpha, vlo, vhi)) return false;
-    }
-    iu0 = cell_index(ulo, M);
-    iu1 = cell_index(uhi, M);
-    iv0 = cell_index(vlo, M);
-    iv1 = cell_index(vhi, M);
-    return true;
+    float sa, ca;
+    sincosf(alpha, &sa, &ca);
+    return face_cells_sc(c, sa, ca, face, M, iu0, iu1, iv0, iv1);
 }
 
 __device__ inline int64_t xcd_remap(int64_t b, int64_t nb) {
@@ -228,6 +207,8 @@ __device__ inline bool candidate_test(const SceneView& S, uint32_t rank, float4 
 // ------------------------------------------- one workgroup, 4 tiles -----
 
 constexpr int kSupTiles = 4;
+constexpr int kGatherPer = 4;                    // candidates per thread per gather block
+constexpr int kGatherBlock = 256 * kGatherPer;   // one block's candidates; also the survivor list size
 
 struct SuperShared {
     float4 cap[kSupTiles][2];
@@ -238,10 +219,12 @@ struct SuperShared {
     uint32_t rb[256], pre[256], wsum[4];
     uint32_t cnt[kSupTiles];
     uint32_t flag[kSupTiles];
+    uint32_t npass;
     uint32_t fc[kSlices * 64];  // per-slice (level, face) triangle counts
     uint32_t bk[kSupTiles][kDepthBuckets];
 };
 static_assert(kSlices * 64 == 256, "one face count per thread of the 256-thread block");
+static_assert(kSupTiles * kDepthBuckets >= kGatherBlock, "survivor list fits in the bucket counters");
 
 // Exclusive scan of one value per thread over a 256-thread block.
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wsum, uint32_t& total) {
@@ -410,6 +393,7 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
         tc1[q] = sh.cap[q][1];
     }
     const uint32_t nrows_all = sh.ppre[64];
+    uint32_t* const pass_list = &sh.bk[0][0];  // free while gathering
     for (uint32_t rb = 0; rb < nrows_all; rb += 256) {
         const uint32_t nb = min(256u, nrows_all - rb);
         uint32_t len = 0;
@@ -436,40 +420,68 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
         uint32_t total;
         uint32_t pre = block_exclusive_scan(len, sh.wsum, total);
         sh.pre[tid] = pre;
+        if (tid == 0) sh.npass = 0;
         __syncthreads();
-        for (uint32_t k0 = 0; k0 < total; k0 += 256) {
-            uint32_t k = k0 + uint32_t(tid);
-            if (k < total) {
-                int lo = 0, hi = int(nb) - 1;  // row holding candidate k
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (sh.pre[mid] <= k)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
+        for (uint32_t k0 = 0; k0 < total; k0 += kGatherBlock) {
+            // stage 1: the super-tile cap test on up to kGatherPer candidates
+            // per thread, their loads all in flight together; survivors are
+            // compacted into pass_list
+            uint32_t pos[kGatherPer];
+            float4 a[kGatherPer];
+#pragma unroll
+            for (int u = 0; u < kGatherPer; ++u) {
+                const uint32_t k = k0 + uint32_t(u * 256 + tid);
+                pos[u] = 0xFFFFFFFFu;
+                if (k < total) {
+                    int lo = 0, hi = int(nb) - 1;  // row holding candidate k
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (sh.pre[mid] <= k)
+                            lo = mid;
+                        else
+                            hi = mid - 1;
+                    }
+                    pos[u] = sh.rb[lo] + (k - sh.pre[lo]);
                 }
-                const float4* br = S.binrec + 4 * (int64_t(sh.rb[lo]) + (k - sh.pre[lo]));
-                float4 a = br[0];
+            }
+#pragma unroll
+            for (int u = 0; u < kGatherPer; ++u)
+                a[u] = (pos[u] != 0xFFFFFFFFu) ? S.bincap[pos[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < kGatherPer; ++u) {
+                if (pos[u] == 0xFFFFFFFFu) continue;
                 bool pass = true;
-                if (!wide && a.w < kBinWide) {
-                    float dx = cs.x - a.x, dy = cs.y - a.y, dz = cs.z - a.z;
+                if (!wide && a[u].w < kBinWide) {
+                    float dx = cs.x - a[u].x, dy = cs.y - a[u].y, dz = cs.z - a[u].z;
                     float chord2 = dx * dx + dy * dy + dz * dz;
-                    float ch_t = sqrtf(fmaxf(0.0f, 1.0f - a.w * a.w));
-                    float sm = sh_s * ch_t + ch_s * a.w;
+                    float ch_t = sqrtf(fmaxf(0.0f, 1.0f - a[u].w * a[u].w));
+                    float sm = sh_s * ch_t + ch_s * a[u].w;
                     pass = chord2 <= 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f;
                 }
-                if (pass) {
-                    float4 b4 = br[1], c4 = br[2], d4 = br[3];
+                if (pass) pass_list[atomicAdd(&sh.npass, 1u)] = pos[u];
+            }
+            __syncthreads();
+            const uint32_t npass = sh.npass;
+            __syncthreads();
+            if (tid == 0) sh.npass = 0;  // next block's count; ordered by the syncs below
+            // stage 2: edge-plane tests of the survivors against the four tiles
+            for (uint32_t c0 = 0; c0 < npass; c0 += 256) {
+                if (c0 + uint32_t(tid) < npass) {
+                    const uint32_t p = pass_list[c0 + tid];
+                    const float4 a4 = S.bincap[p];
+                    const float4 b4 = S.binnrm[3 * int64_t(p)], c4 = S.binnrm[3 * int64_t(p) + 1],
+                                 d4 = S.binnrm[3 * int64_t(p) + 2];
                     float3 n0 = f3(b4.x, b4.y, b4.z), n1 = f3(c4.x, c4.y, c4.z), n2 = f3(d4.x, d4.y, d4.z);
                     uint32_t mask = 0;
 #pragma unroll
                     for (int q = 0; q < kSupTiles; ++q)
                         if ((live_mask >> q) & 1u)
-                            if (sub_may_see(tc0[q], tc1[q], a, n0, n1, n2)) mask |= 1u << q;
+                            if (sub_may_see(tc0[q], tc1[q], a4, n0, n1, n2)) mask |= 1u << q;
                     if (mask) append(mask, __float_as_uint(b4.w));
                 }
+                chunk_end();
             }
-            chunk_end();
+            __syncthreads();
         }
         __syncthreads();
     }

@@ -311,7 +311,8 @@ __global__ __launch_bounds__(256) void k_bucket_lb(float4* __restrict__ rec, int
 // binning record (cap + edge normals).
 __global__ __launch_bounds__(256) void k_cell_records(const uint32_t* __restrict__ ranks, int64_t n,
                                                       const float4* __restrict__ rec, const float4* __restrict__ cap,
-                                                      uint32_t* __restrict__ cell_list, float4* __restrict__ binrec) {
+                                                      uint32_t* __restrict__ cell_list, float4* __restrict__ bincap,
+                                                      float4* __restrict__ binnrm) {
     int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
     uint32_t r = ranks[k];
@@ -319,10 +320,10 @@ __global__ __launch_bounds__(256) void k_cell_records(const uint32_t* __restrict
     float4 c0 = cap[2 * int64_t(r)], c1 = cap[2 * int64_t(r) + 1];
     float4 r0 = rec[4 * int64_t(r)], r1 = rec[4 * int64_t(r) + 1], r2 = rec[4 * int64_t(r) + 2];
     float sh = (c1.z == kCapWide) ? kBinWide : c0.w;
-    binrec[4 * k + 0] = make_float4(c0.x, c0.y, c0.z, sh);
-    binrec[4 * k + 1] = make_float4(r0.x, r0.y, r0.z, __uint_as_float(r));
-    binrec[4 * k + 2] = make_float4(r1.x, r1.y, r1.z, 0.0f);
-    binrec[4 * k + 3] = make_float4(r2.x, r2.y, r2.z, 0.0f);
+    bincap[k] = make_float4(c0.x, c0.y, c0.z, sh);
+    binnrm[3 * k + 0] = make_float4(r0.x, r0.y, r0.z, __uint_as_float(r));
+    binnrm[3 * k + 1] = make_float4(r1.x, r1.y, r1.z, 0.0f);
+    binnrm[3 * k + 2] = make_float4(r2.x, r2.y, r2.z, 0.0f);
 }
 
 // cell_start[b] = first position whose index key is >= b (lower bound).
@@ -383,7 +384,7 @@ hipError_t launch_setup(const float* xyz, int64_t n, void* setup, hipStream_t st
         uint32_t* sk = in3 ? k3 : k2;
         uint32_t* sv = in3 ? v3 : v2;
         hipLaunchKernelGGL(k_cell_records, dim3(blocks), dim3(256), 0, st, sv, n, F4(L.rec_off), F4(L.cap_off),
-                           U(L.cell_list_off), F4(L.binrec_off));
+                           U(L.cell_list_off), F4(L.bincap_off), F4(L.binnrm_off));
         hipLaunchKernelGGL(k_cell_start, dim3(unsigned((kIndexKeys + 1 + 255) / 256)), dim3(256), 0, st, sk, n,
                            U(L.cell_start_off));
     } else {
