@@ -16,6 +16,7 @@ kernel time, against the FP32 VALU peak), and the FP64 CPU oracle timed on a
 bounded pixel sample on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --summarize DIR...   (rocprofv3 CSV output -> text summary)
 """
 import argparse
 import json
@@ -30,13 +31,108 @@ sys.path.insert(0, ROOT)
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: non-packed FP32 VALU
 PEAK_HBM = 8.0e12
 OPS_PER_FRAGMENT = 20                        # 3 edge dots (9) + min3 + cmp + g.N (3) + rcp + mul + cmp64 + 2 sel
+BIN_BYTES_PER_TRI = 64                       # cap (16 B) + three edge normals (48 B), read once
+BIN_BYTES_PER_TILE = 36                      # tile cap (32 B) read, list length (4 B) written
+CALIB_BYTES = 256 << 20                      # copy-like calibration kernel of the profiled run
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def source_hash() -> str:
+    """Hash of the kernel sources: counters taken from other sources are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2003_10558_amd", "csrc")
+    for f in sorted(os.listdir(csrc)) + ["../../include/vsr.h"]:
+        if f.endswith((".hip", ".hpp", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE summary, scaled by the calibration kernel; None when the
+    summary is missing or was taken on other kernel sources."""
+    path = os.path.join(PROFILES, "traffic_1080p_1m.txt")
+    if not os.path.exists(path):
+        return None
+    src, calib, rows = None, None, {}
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "source":
+            src = f[1]
+        elif f[0] == "calib":
+            calib = dict(zip(f[2::2], map(float, f[3::2])))
+        elif f[0] == "kernel":
+            rows[f[1]] = dict(zip(f[2::2], map(float, f[3::2])))
+    key = "vsr::" + kernel
+    if src != source_hash() or calib is None or key not in rows:
+        return None
+    r = rows[key]
+    fetch = r["fetch_kib"] * 1024 / calib["fetch_factor"]
+    write = r["write_kib"] * 1024 / calib["write_factor"]
+    return {"bytes": fetch + write, "fetch_bytes": fetch, "write_bytes": write, "source": src,
+            "counters": "FETCH_SIZE, WRITE_SIZE per dispatch / calibration factor"}
+
+
+def summarize(dirs):
+    """Reduce rocprofv3 CSV output (kernel_stats and counter_collection
+    files under `dirs`) to the text summaries kept under profiles/."""
+    import csv
+    import glob
+    stats, counters = [], {}
+    for d in dirs:
+        stats += glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                name = row["Kernel_Name"].split("(")[0].replace("void ", "").strip()
+                key = (name, row["Counter_Name"])
+                counters.setdefault(key, {}).setdefault(row.get("Dispatch_Id", ""), 0.0)
+                counters[key][row.get("Dispatch_Id", "")] += float(row["Counter_Value"])
+    print(f"source {source_hash()}")
+    for f in stats:
+        rows = list(csv.DictReader(open(f)))
+        print(f"# {'kernel':60s} {'calls':>6s} {'total_us':>11s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} "
+              f"{'pct':>6s}")
+        for r in rows:
+            name = r["Name"].split("(")[0].replace("void ", "").strip()[:60]
+            print(f"stat {name:60s} {int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e3:11.1f} "
+                  f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:10.2f} "
+                  f"{float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}")
+    if counters:
+        names = sorted({k[0] for k in counters})
+        cnames = sorted({k[1] for k in counters})
+        mean = {k: sum(v.values()) / len(v) for k, v in counters.items()}
+        cal = [n for n in names if "neg_kernel" in n]
+        if cal and (cal[0], "FETCH_SIZE") in mean and (cal[0], "WRITE_SIZE") in mean:
+            ff = max(counters[(cal[0], "FETCH_SIZE")].values()) * 1024 / CALIB_BYTES
+            wf = max(counters[(cal[0], "WRITE_SIZE")].values()) * 1024 / CALIB_BYTES
+            print(f"calib {cal[0].split('<')[0]} bytes {CALIB_BYTES} fetch_factor {ff:.4f} write_factor {wf:.4f}")
+        for n in names:
+            if not n.startswith("vsr::"):
+                continue
+            vals = " ".join(f"{c.lower() if c in ('FETCH_SIZE', 'WRITE_SIZE') else c} {mean[(n, c)]:.6g}"
+                            for c in cnames if (n, c) in mean)
+            vals = vals.replace("fetch_size", "fetch_kib").replace("write_size", "write_kib")
+            nd = max(len(counters[(n, c)]) for c in cnames if (n, c) in counters)
+            if (n, "SQ_INSTS_VALU") in mean and (n, "GRBM_GUI_ACTIVE") in mean:
+                # wave-level VALU issue slots: one per CU per cycle; the GRBM
+                # busy count is summed over the 8 XCDs
+                util = mean[(n, "SQ_INSTS_VALU")] / (256 * mean[(n, "GRBM_GUI_ACTIVE")] / 8)
+                vals += f" valu_issue_util {util:.3f}"
+            print(f"kernel {n.replace(' ', '')} dispatches {nd} {vals}")
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize":
+        summarize(sys.argv[2:])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -52,8 +148,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU split of this "
-              f"workload is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); a multi-GPU split of this "
+              f"workload is not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -67,6 +163,16 @@ def main():
     torch.cuda.set_device(dev)
     fmt = vsr.VSR_MAP_F32 if args.fmt == "f32" else vsr.VSR_MAP_OCT16
     depth = args.bin_depth
+
+    if args.profile:
+        # copy-like calibration kernel of known size (reads and writes
+        # CALIB_BYTES once) for scaling the HBM traffic counters
+        src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     t0 = time.time()
     tris = synth.scene_1m()
@@ -93,12 +199,14 @@ def main():
     frame = pipeline.render(scene, views[0], fmt=fmt, bin_depth=depth)
     torch.cuda.synchronize()
     n_plain = len(views) if not args.profile else 8
-    lat, rast = [], []
+    lat, rast, binl, entries = [], [], [], []
+    ntiles = ((views[0].width + 7) // 8) * ((views[0].height + 7) // 8)
     for rep in range(2):
         for v in views[:n_plain]:
-            e0, e1, e2 = ev(), ev(), ev()
+            e0, ea, e1, e2 = ev(), ev(), ev(), ev()
             e0.record(stream)
             frame.view_eff = vsr.vsr_build_map(v, fmt, 0, frame.map)
+            ea.record(stream)
             vsr.vsr_bin(v, fmt, frame.map, scene.setup, scene.ntri, depth, 0, frame.bins)
             e1.record(stream)
             vsr.vsr_raster(v, fmt, frame.map, scene.setup, scene.ntri, frame.bins, depth, frame.tri_id, frame.depth)
@@ -106,12 +214,16 @@ def main():
             e2.synchronize()
             if rep == 1:
                 lat.append(e0.elapsed_time(e2))
+                binl.append(ea.elapsed_time(e1))
                 rast.append(e1.elapsed_time(e2))
+                # bin list entries written (per-tile counts follow the 256-byte header)
+                entries.append(int(frame.bins[256:256 + 4 * ntiles].view(torch.int32).sum().item()))
     overflow = vsr.vsr_bin_overflow(frame.bins)
     lat = np.array(lat)
     plain_ms = float(lat.mean())
     log(f"plain: {plain_ms:.3f} ms/view (p50 {np.percentile(lat, 50):.3f}, p99 {np.percentile(lat, 99):.3f}), "
-        f"raster {np.mean(rast):.3f} ms, overflowed tiles {overflow}")
+        f"bin {np.mean(binl):.3f} ms, raster {np.mean(rast):.3f} ms, list entries {np.mean(entries):.0f}, "
+        f"overflowed tiles {overflow}")
 
     # ---------------- single-view fused path (vsr_build_map + vsr_render)
     ffr = pipeline.render_fused(scene, views[0], fmt=fmt)
@@ -224,13 +336,30 @@ def main():
             f"p99 {st.p99_ms:.1f} ms, mean batch {st.mean_batch:.1f}")
         del sc, srv
 
-    # ---------------- roofline of the rasterizer (dominant kernel)
+    # ---------------- rooflines
+    # dominant kernel of the step: the binner (HBM-bound ideal: read every
+    # triangle's 64-byte bin record and every tile cap once, write the lists)
+    t_b = float(np.mean(binl)) * 1e-3
+    bin_bytes = BIN_BYTES_PER_TRI * tris.shape[1] + BIN_BYTES_PER_TILE * ntiles + 4 * float(np.mean(entries))
+    roofline = {"bound": "hbm", "achieved": bin_bytes / t_b / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": bin_bytes / t_b / PEAK_HBM, "traffic": traffic_from_profiles("k_bin"),
+                "kernel": "k_bin", "kernel_ms": t_b * 1e3, "algorithmic_bytes": bin_bytes,
+                "list_entries": float(np.mean(entries))}
+    # the rasterizer against the VALU peak: lane-ops per covered fragment
     t_r = float(np.mean(rast)) * 1e-3
     achieved = OPS_PER_FRAGMENT * F_mean / t_r
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
-                "unit": "T lane-ops/s", "frac": achieved / PEAK_VALU_LANE_OPS, "traffic": None,
-                "kernel": "k_raster", "kernel_ms": t_r * 1e3, "fragments_per_launch": F_mean,
-                "ops_per_fragment": OPS_PER_FRAGMENT}
+    roofline_raster = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
+                       "unit": "T lane-ops/s", "frac": achieved / PEAK_VALU_LANE_OPS,
+                       "traffic": traffic_from_profiles("k_raster<false>"), "kernel": "k_raster",
+                       "kernel_ms": t_r * 1e3, "fragments_per_launch": F_mean, "ops_per_fragment": OPS_PER_FRAGMENT}
+    # the whole batched step per view: covered-fragment work and frame bytes
+    per_view_s = submit_ms * 1e-3 / len(views)
+    frame_bytes = (12 if fmt == vsr.VSR_MAP_F32 else 4) * 2073600 + 68 * tris.shape[1] + 8 * 2073600
+    roofline_step = {"valu_frac": OPS_PER_FRAGMENT * F_mean / per_view_s / PEAK_VALU_LANE_OPS,
+                     "hbm_frac": frame_bytes / per_view_s / PEAK_HBM, "per_view_us": per_view_s * 1e6}
+    log(f"roofline: k_bin {roofline['achieved']:.0f} GB/s ({roofline['frac']:.3f} of HBM), k_raster "
+        f"{roofline_raster['achieved']:.2f} T lane-ops/s ({roofline_raster['frac']:.3f} of VALU), step per view "
+        f"{roofline_step['valu_frac']:.3f} VALU / {roofline_step['hbm_frac']:.3f} HBM")
 
     # ---------------- CPU baseline: the FP64 oracle on a bounded sample
     cpu = None
@@ -287,6 +416,8 @@ def main():
         "batched_fused_fps": len(views) / fsubmit_ms * 1e3,
         "serving": serve_stats,
         "roofline": roofline,
+        "roofline_raster": roofline_raster,
+        "roofline_step": roofline_step,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
