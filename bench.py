@@ -5,8 +5,10 @@ scene (+ enclosing radius-100 icosphere) on one MI355X.
 One step = the whole hot path over one batch: per-triangle setup of the
 resident scene (vsr_setup_tris) followed by one vsr_submit of `--views`
 1080p views (k in {1, 0.5, 0, -0.5} x yaw/pitch orientations), i.e. map
-generation, binning and rasterization of every view.  `value` is views per
-second over the timed steps (inputs resident in HBM).
+generation (once per distinct lens: the map is camera-frame), binning and
+rasterization of every view.  `value` is views per second over the timed
+steps (inputs resident in HBM).  The same batch with a distinct lens per
+view (64 maps per step) is reported beside it.
 
 Also reported: the plain per-view form (vsr_build_map -> vsr_bin ->
 vsr_raster, one view at a time) and its per-view latency percentiles, the
@@ -295,6 +297,23 @@ def main():
     torch.cuda.synchronize()
     setup_ms = e0.elapsed_time(e1) / args.steps
     log(f"submit only: {submit_ms:.3f} ms ({len(views) / submit_ms * 1e3:.1f} views/s); setup {setup_ms:.3f} ms")
+    # the same step with every view on its own lens (no map shared)
+    dviews = [synth.View(v.width, v.height, v.k + 1e-3 * (q + 1), v.l, v.s, v.omega_deg, v.aov, v.rot)
+              for q, v in enumerate(views)]
+    dbatch = pipeline.Batch([(scene, v) for v in dviews], fmt=fmt, mode=vsr.VSR_SUBMIT_BINNED, bin_depth=depth)
+    dbatch.submit()
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    for _ in range(args.steps):
+        dbatch.submit()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dsubmit_ms = e0.elapsed_time(e1) / args.steps
+    n_lens = len({(v.width, v.height, v.aov, v.k, v.l, v.s, v.omega_deg) for v in views})
+    log(f"submit, {len(views)} distinct lenses: {dsubmit_ms:.3f} ms ({len(views) / dsubmit_ms * 1e3:.1f} views/s); "
+        f"the benchmark batch shares {n_lens} lens maps")
+    del dbatch
     # the fused depth-sliced batch on the same views
     fbatch = pipeline.Batch([(scene, v) for v in views], fmt=fmt, mode=vsr.VSR_SUBMIT_FUSED)
     fbatch.submit()
@@ -405,6 +424,8 @@ def main():
                    "step": "vsr_setup_tris + vsr_submit(all views)"},
         "batched_fps_with_setup": views_per_s,
         "batched_fps": len(views) / submit_ms * 1e3,
+        "batched_fps_distinct_lenses": len(views) / dsubmit_ms * 1e3,
+        "lens_maps_per_step": n_lens,
         "plain_fps": 1e3 / plain_ms,
         "plain_view_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "setup_ms": setup_ms,

@@ -147,15 +147,6 @@ int vsr_build_map(const vsr_view* v, int32_t fmt, uint32_t flags, void* map, int
     return hip_status(launch_build_map(P, map, hipStream_t(stream)), "vsr_build_map");
 }
 
-int vsr_map_unpack(const vsr_view* v, int32_t fmt, const void* map, float* out, void* stream) {
-    if (!v) return fail(VSR_E_ARG, "view is NULL");
-    if (v->width < 1 || v->height < 1 || v->width > kMaxDim || v->height > kMaxDim)
-        return fail(VSR_E_ARG, "view size %dx%d outside 1..%d", v->width, v->height, kMaxDim);
-    if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return fail(VSR_E_ARG, "unknown map format %d", fmt);
-    if (!map || !aligned(map) || !out || (reinterpret_cast<uintptr_t>(out) & 3u))
-        return fail(VSR_E_ARG, "NULL or misaligned buffer");
-    return hip_status(launch_map_unpack(map, v->width, v->height, fmt, out, hipStream_t(stream)), "vsr_map_unpack");
-}
 
 int vsr_setup_tris(const float* xyz, int64_t ntri, void* setup, int64_t setup_bytes, void* stream) {
     if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri %lld out of range", (long long)ntri);
@@ -172,7 +163,18 @@ static int check_view_buffers(const vsr_view* v, int32_t fmt) {
     if (v->width < 1 || v->height < 1 || v->width > kMaxDim || v->height > kMaxDim)
         return fail(VSR_E_ARG, "view size %dx%d outside 1..%d", v->width, v->height, kMaxDim);
     if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return fail(VSR_E_ARG, "unknown map format %d", fmt);
+    for (int q = 0; q < 9; ++q)
+        if (!isfinite(v->rot[q])) return fail(VSR_E_ARG, "non-finite rotation");
     return VSR_OK;
+}
+
+int vsr_map_unpack(const vsr_view* v, int32_t fmt, const void* map, float* out, void* stream) {
+    int rc = check_view_buffers(v, fmt);
+    if (rc != VSR_OK) return rc;
+    if (!map || !aligned(map) || !out || (reinterpret_cast<uintptr_t>(out) & 3u))
+        return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    return hip_status(launch_map_unpack(map, v->width, v->height, fmt, rot_of(v->rot), out, hipStream_t(stream)),
+                      "vsr_map_unpack");
 }
 
 int vsr_bin(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri, int32_t bin_depth,
@@ -185,8 +187,8 @@ int vsr_bin(const vsr_view* v, int32_t fmt, const void* map, const void* setup, 
     if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
     int64_t need = bin_layout(v->width, v->height, bin_depth).bytes;
     if (bin_bytes < need) return fail(VSR_E_SPACE, "bin buffer %lld < %lld bytes", (long long)bin_bytes, (long long)need);
-    return hip_status(launch_bin(map, v->width, v->height, fmt, setup, ntri, bin_depth, (flags & VSR_BIN_ALL) != 0,
-                                 bins, hipStream_t(stream)),
+    return hip_status(launch_bin(map, v->width, v->height, fmt, rot_of(v->rot), setup, ntri, bin_depth,
+                                 (flags & VSR_BIN_ALL) != 0, bins, hipStream_t(stream)),
                       "vsr_bin");
 }
 
@@ -200,8 +202,8 @@ int vsr_raster(const vsr_view* v, int32_t fmt, const void* map, const void* setu
         return fail(VSR_E_ARG, "output not 4-byte aligned");
     if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri out of range");
     if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
-    return hip_status(launch_raster(map, v->width, v->height, fmt, setup, ntri, bins, bin_depth, tri_id, depth,
-                                    hipStream_t(stream)),
+    return hip_status(launch_raster(map, v->width, v->height, fmt, rot_of(v->rot), setup, ntri, bins, bin_depth,
+                                    tri_id, depth, hipStream_t(stream)),
                       "vsr_raster");
 }
 
@@ -215,8 +217,9 @@ int vsr_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const void
     if ((reinterpret_cast<uintptr_t>(stats) & 7u) != 0) return fail(VSR_E_ARG, "stats not 8-byte aligned");
     if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri out of range");
     if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
-    return hip_status(launch_raster(map, v->width, v->height, fmt, setup, ntri, bins, bin_depth, tri_id, depth,
-                                    hipStream_t(stream), reinterpret_cast<unsigned long long*>(stats), no_early_exit),
+    return hip_status(launch_raster(map, v->width, v->height, fmt, rot_of(v->rot), setup, ntri, bins, bin_depth,
+                                    tri_id, depth, hipStream_t(stream), reinterpret_cast<unsigned long long*>(stats),
+                                    no_early_exit),
                       "vsr_raster_stats");
 }
 
@@ -237,8 +240,8 @@ int vsr_render(const vsr_view* v, int32_t fmt, const void* map, const void* setu
     int64_t need = fused_scratch_bytes(v->width, v->height);
     if (scratch_bytes < need)
         return fail(VSR_E_SPACE, "scratch %lld < %lld bytes", (long long)scratch_bytes, (long long)need);
-    return hip_status(launch_fused(map, v->width, v->height, fmt, setup, ntri, scratch, tri_id, depth,
-                                   hipStream_t(stream)),
+    return hip_status(launch_fused(map, v->width, v->height, fmt, rot_of(v->rot), setup, ntri, scratch, tri_id,
+                                   depth, hipStream_t(stream)),
                       "vsr_render");
 }
 

@@ -19,6 +19,7 @@ struct BinArgs {
     int64_t n;
     void* bins;
     uint32_t* status;  // overflowed-tile counter
+    Rot rot;           // camera -> world
 };
 
 __device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
@@ -29,7 +30,7 @@ __device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
     int64_t tile;
     int tx, ty;
     const bool present = super_tile_of(sidx, w, A.ntx, A.nty, tile, tx, ty);
-    super_setup(sh, map_caps(A.map, A.ntiles, A.fmt), scene_view(A.setup, A.n).face_count, present, tile);
+    super_setup(sh, map_caps(A.map, A.ntiles, A.fmt), A.rot, scene_view(A.setup, A.n).face_count, present, tile);
     const bool any = sh.sup[1].z != 0.0f;
     const SceneView S = scene_view(A.setup, A.n);
     const uint32_t lcap = uint32_t(A.lds_cap);
@@ -85,8 +86,8 @@ inline int32_t bin_lds_cap(int32_t depth) {
 
 inline int64_t bin_grid(int32_t ntx, int32_t nty) { return int64_t((ntx + 1) / 2) * ((nty + 1) / 2); }
 
-hipError_t launch_bin(const void* map, int32_t W, int32_t H, int32_t fmt, const void* setup, int64_t n, int32_t depth,
-                      bool all, void* bins, hipStream_t st) {
+hipError_t launch_bin(const void* map, int32_t W, int32_t H, int32_t fmt, const Rot& R, const void* setup, int64_t n,
+                      int32_t depth, bool all, void* bins, hipStream_t st) {
     MapLayout ML = map_layout(W, H, fmt);
     BinArgs A;
     A.map = map;
@@ -101,6 +102,7 @@ hipError_t launch_bin(const void* map, int32_t W, int32_t H, int32_t fmt, const 
     A.n = n;
     A.bins = bins;
     A.status = reinterpret_cast<uint32_t*>(bins);
+    A.rot = R;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(bins), int64_t(64));
     hipLaunchKernelGGL(k_bin, dim3(unsigned(bin_grid(ML.ntx, ML.nty))), dim3(256),
                        size_t(kSupTiles) * A.lds_cap * 4, st, A);

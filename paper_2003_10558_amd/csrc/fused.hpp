@@ -32,6 +32,7 @@ struct FusedArgs {
     uint32_t* scratch;  // kFusedCap ranks per tile (bucket-ordered lists)
     uint32_t* tri_id;
     float* depth;
+    Rot rot;            // camera -> world
 };
 
 __device__ inline void fused_super(const FusedArgs& A, int64_t sidx) {
@@ -43,13 +44,13 @@ __device__ inline void fused_super(const FusedArgs& A, int64_t sidx) {
     int64_t tile;
     int tx, ty;
     const bool present = super_tile_of(sidx, w, A.ntx, A.nty, tile, tx, ty);
-    super_setup(sh, map_caps(A.map, A.ntiles, A.fmt), scene_view(A.setup, A.n).face_count, present, tile);
+    super_setup(sh, map_caps(A.map, A.ntiles, A.fmt), A.rot, scene_view(A.setup, A.n).face_count, present, tile);
     const SceneView S = scene_view(A.setup, A.n);
 
     const int i = tx * kTile + (lane & (kTile - 1)), j = ty * kTile + (lane >> 3);
     const bool inside = present && i < A.W && j < A.H;
     float3 g = f3(0.f, 0.f, 0.f);
-    if (present) g = load_dir(A.map, A.fmt, A.ntiles, tile, lane);
+    if (present) g = load_dir(A.map, A.fmt, A.ntiles, tile, lane, A.rot);
     const bool has_dir = inside && (g.x != 0.0f || g.y != 0.0f || g.z != 0.0f);
     uint64_t best = kKeyEmpty;
     bool done = !present || sh.cap[w][1].z == kCapEmpty || A.n == 0;
@@ -125,7 +126,7 @@ inline int64_t fused_scratch_bytes(int32_t W, int32_t H) {
     return align256(map_layout(W, H, VSR_MAP_F32).ntiles * int64_t(kFusedCap) * 4);
 }
 
-hipError_t launch_fused(const void* map, int32_t W, int32_t H, int32_t fmt, const void* setup, int64_t n,
+hipError_t launch_fused(const void* map, int32_t W, int32_t H, int32_t fmt, const Rot& R, const void* setup, int64_t n,
                         void* scratch, uint32_t* tri_id, float* depth, hipStream_t st) {
     MapLayout ML = map_layout(W, H, fmt);
     FusedArgs A;
@@ -142,6 +143,7 @@ hipError_t launch_fused(const void* map, int32_t W, int32_t H, int32_t fmt, cons
     A.scratch = reinterpret_cast<uint32_t*>(scratch);
     A.tri_id = tri_id;
     A.depth = depth;
+    A.rot = R;
     hipLaunchKernelGGL(k_fused, dim3(unsigned(bin_grid(ML.ntx, ML.nty))), dim3(256), 0, st, A);
     return hipGetLastError();
 }

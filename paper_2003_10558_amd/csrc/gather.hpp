@@ -138,16 +138,19 @@ __device__ inline int64_t xcd_remap(int64_t b, int64_t nb) {
 __device__ inline float4 empty_cap0() { return make_float4(0.f, 0.f, 1.f, 0.f); }
 __device__ inline float4 empty_cap1() { return make_float4(1.f, 0.f, kCapEmpty, 0.f); }
 
-// May a triangle (binning record a + unit edge normals) cover a pixel of
-// the tile with cap (c0, c1)?  Never false for a pair the rasterizer's FP32
-// test could cover.
-__device__ inline bool sub_may_see(float4 c0, float4 c1, float4 a, float3 n0, float3 n1, float3 n2) {
+// Cosine of a binning cap's half radius from its sine.  The hardware square
+// root (about 1 ulp) is ample: the cap tests carry a relative margin of 1e-6.
+__device__ inline float bin_cos_half(float4 a) { return __builtin_amdgcn_sqrtf(fmaxf(0.0f, 1.0f - a.w * a.w)); }
+
+// May a triangle (binning record a, ch_t = bin_cos_half(a), unit edge
+// normals) cover a pixel of the tile with cap (c0, c1)?  Never false for a
+// pair the rasterizer's FP32 test could cover.
+__device__ inline bool sub_may_see(float4 c0, float4 c1, float4 a, float ch_t, float3 n0, float3 n1, float3 n2) {
     if (c1.z == kCapEmpty) return false;
     if (c1.z == kCapWide) return true;
     if (a.w < kBinWide) {
         float dx = c0.x - a.x, dy = c0.y - a.y, dz = c0.z - a.z;
         float chord2 = dx * dx + dy * dy + dz * dz;
-        float ch_t = sqrtf(fmaxf(0.0f, 1.0f - a.w * a.w));
         float sm = c0.w * ch_t + c1.x * a.w;  // sin((rho_tile + rho_tri)/2)
         if (chord2 > 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f) return false;
     }
@@ -254,17 +257,20 @@ __device__ inline bool super_tile_of(int64_t sidx, int w, int ntx, int nty, int6
     return tx < ntx && ty < nty;
 }
 
-// Loads the four tile caps and the per-slice face counts, computes the
+// Loads the four tile caps (rotated to the world frame) and the per-slice
+// face counts, computes the
 // super-tile cap and the cell rectangles of every (level, face).  All
 // threads of the block call it.  Angles are never formed: caps carry
 // sin and cos of their half radius, and radii add through the angle-sum
 // identities.
-__device__ inline void super_setup(SuperShared& sh, const float4* caps, const uint32_t* face_count, bool present,
-                                   int64_t tile) {
+__device__ inline void super_setup(SuperShared& sh, const float4* caps, const Rot& R, const uint32_t* face_count,
+                                   bool present, int64_t tile) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (lane == 0) {
-        sh.cap[w][0] = present ? caps[2 * tile] : empty_cap0();
-        sh.cap[w][1] = present ? caps[2 * tile + 1] : empty_cap1();
+        float4 c0 = empty_cap0(), c1 = empty_cap1();
+        if (present) load_tile_cap(caps, tile, R, c0, c1);
+        sh.cap[w][0] = c0;
+        sh.cap[w][1] = c1;
     }
     sh.fc[tid] = face_count[tid];  // kSlices * 64 == 256 entries
     if (tid < kSupTiles) {
@@ -454,8 +460,7 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
                 if (!wide && a[u].w < kBinWide) {
                     float dx = cs.x - a[u].x, dy = cs.y - a[u].y, dz = cs.z - a[u].z;
                     float chord2 = dx * dx + dy * dy + dz * dz;
-                    float ch_t = sqrtf(fmaxf(0.0f, 1.0f - a[u].w * a[u].w));
-                    float sm = sh_s * ch_t + ch_s * a[u].w;
+                    float sm = sh_s * bin_cos_half(a[u]) + ch_s * a[u].w;
                     pass = chord2 <= 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f;
                 }
                 if (pass) pass_list[atomicAdd(&sh.npass, 1u)] = pos[u];
@@ -472,11 +477,12 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
                     const float4 b4 = S.binnrm[3 * int64_t(p)], c4 = S.binnrm[3 * int64_t(p) + 1],
                                  d4 = S.binnrm[3 * int64_t(p) + 2];
                     float3 n0 = f3(b4.x, b4.y, b4.z), n1 = f3(c4.x, c4.y, c4.z), n2 = f3(d4.x, d4.y, d4.z);
+                    const float ch_t = bin_cos_half(a4);
                     uint32_t mask = 0;
 #pragma unroll
                     for (int q = 0; q < kSupTiles; ++q)
                         if ((live_mask >> q) & 1u)
-                            if (sub_may_see(tc0[q], tc1[q], a4, n0, n1, n2)) mask |= 1u << q;
+                            if (sub_may_see(tc0[q], tc1[q], a4, ch_t, n0, n1, n2)) mask |= 1u << q;
                     if (mask) append(mask, __float_as_uint(b4.w));
                 }
                 chunk_end();

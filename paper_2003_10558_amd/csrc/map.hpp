@@ -3,10 +3,15 @@
 // One wavefront per 8x8 tile, one lane per pixel.  Each lane turns its pixel
 // centre into view coordinates (angle-of-view normalisation, section 2),
 // applies the 2D->3D transform of section 2.1.2 in FP32 with the accurate
-// device math library, rotates the direction into the world frame and
-// stores it tile-major (x, y and z planes, or one octahedral fp16 pair).
-// The wave then reduces the tile's bounding cap: the normalised mean
-// direction and the largest chord to it, widened by a safety margin.
+// device math library and stores the camera-frame direction tile-major (x, y
+// and z planes, or one octahedral fp16 pair).  The wave then reduces the
+// tile's bounding cap: the normalised mean direction and the largest chord
+// to it, widened by a safety margin.
+//
+// The map depends only on the lens (size, angle of view, k, l, s, Omega): as
+// in the paper, where the vector map is computed once and kept as a texture,
+// one map serves every orientation.  Consumers rotate directions and cap
+// centres into the world frame as they load them (load_dir, load_tile_cap).
 #pragma once
 #include "vsr_internal.h"
 
@@ -71,12 +76,7 @@ __device__ inline bool pixel_direction(const MapParams& P, int i, int j, float3&
     float sig = R > 0.0f ? sn / R : P.sig0;
     float v0 = x * sig, v1 = (y * sig) / P.c, v2 = cs;
     float inv = 1.0f / sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
-    v0 *= inv;
-    v1 *= inv;
-    v2 *= inv;
-    out = f3(fmaf(P.rot[2], v2, fmaf(P.rot[1], v1, P.rot[0] * v0)),
-             fmaf(P.rot[5], v2, fmaf(P.rot[4], v1, P.rot[3] * v0)),
-             fmaf(P.rot[8], v2, fmaf(P.rot[7], v1, P.rot[6] * v0)));
+    out = f3(v0 * inv, v1 * inv, v2 * inv);
     return true;
 }
 
@@ -150,24 +150,25 @@ __global__ __launch_bounds__(256) void k_build_map(MapParams P, void* map, int64
 }
 
 __global__ __launch_bounds__(256) void k_map_unpack(const void* map, int32_t fmt, int64_t ntiles, int32_t ntx,
-                                                    int32_t W, int32_t H, float* out) {
+                                                    int32_t W, int32_t H, Rot R, float* out) {
     int lane = threadIdx.x & 63;
     int64_t tile = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (tile >= ntiles) return;
     int tx = int(tile % ntx), ty = int(tile / ntx);
     int i = tx * kTile + (lane & (kTile - 1)), j = ty * kTile + (lane >> 3);
     if (i >= W || j >= H) return;
-    float3 g = load_dir(map, fmt, ntiles, tile, lane);
+    float3 g = load_dir(map, fmt, ntiles, tile, lane, R);
     int64_t o = (int64_t(j) * W + i) * 3;
     out[o] = g.x;
     out[o + 1] = g.y;
     out[o + 2] = g.z;
 }
 
-hipError_t launch_map_unpack(const void* map, int32_t W, int32_t H, int32_t fmt, float* out, hipStream_t st) {
+hipError_t launch_map_unpack(const void* map, int32_t W, int32_t H, int32_t fmt, const Rot& R, float* out,
+                             hipStream_t st) {
     MapLayout L = map_layout(W, H, fmt);
     hipLaunchKernelGGL(k_map_unpack, dim3(unsigned((L.ntiles + 3) / 4)), dim3(256), 0, st, map, fmt, L.ntiles, L.ntx,
-                       W, H, out);
+                       W, H, R, out);
     return hipGetLastError();
 }
 

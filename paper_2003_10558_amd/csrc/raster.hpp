@@ -30,6 +30,7 @@ struct RasterArgs {
     float* out_depth;
     unsigned long long* stats;  // instrumented variant only: tests, covered, triangles, tiles
     int32_t no_early_exit;      // instrumented variant only: process whole lists
+    Rot rot;                    // camera -> world
 };
 
 // One triangle (record r0..r3) against the lane's pixel; returns whether it
@@ -122,7 +123,7 @@ __device__ inline void raster_tile(const RasterArgs& A, int64_t tile, int lane) 
     int tx = int(tile % A.ntx), ty = int(tile / A.ntx);
     int i = tx * kTile + (lane & (kTile - 1)), j = ty * kTile + (lane >> 3);
     bool inside = i < A.W && j < A.H;
-    float3 g = load_dir(A.map, A.fmt, A.ntiles, tile, lane);
+    float3 g = load_dir(A.map, A.fmt, A.ntiles, tile, lane, A.rot);
     bool has_dir = inside && (g.x != 0.0f || g.y != 0.0f || g.z != 0.0f);
     uint64_t best = kKeyEmpty;
     uint32_t count = counts[tile];
@@ -132,7 +133,8 @@ __device__ inline void raster_tile(const RasterArgs& A, int64_t tile, int lane) 
         raster_list<kStats>(lists + tile * A.depth, count, S.rec, g, has_dir, best, s_stage[threadIdx.x >> 6],
                             !(kStats && A.no_early_exit), n_tri, n_cov);
     } else {
-        float4 tc0 = caps[2 * tile], tc1 = caps[2 * tile + 1];
+        float4 tc0, tc1;
+        load_tile_cap(caps, tile, A.rot, tc0, tc1);
         gather_candidates(S, tc0, tc1, lane, [&](uint32_t rank, bool valid) {
             bool pass = valid && candidate_test(S, rank, tc0, tc1);
             uint64_t m = __ballot(pass);
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(256) void k_raster(RasterArgs A) {
     raster_tile<kStats>(A, tile, threadIdx.x & 63);
 }
 
-hipError_t launch_raster(const void* map, int32_t W, int32_t H, int32_t fmt, const void* setup, int64_t n,
+hipError_t launch_raster(const void* map, int32_t W, int32_t H, int32_t fmt, const Rot& R, const void* setup, int64_t n,
                          const void* bins, int32_t depth, uint32_t* tri_id, float* out_depth, hipStream_t st,
                          unsigned long long* stats = nullptr, int32_t no_early_exit = 0) {
     MapLayout ML = map_layout(W, H, fmt);
@@ -190,6 +192,7 @@ hipError_t launch_raster(const void* map, int32_t W, int32_t H, int32_t fmt, con
     A.out_depth = out_depth;
     A.stats = stats;
     A.no_early_exit = no_early_exit;
+    A.rot = R;
     int64_t blocks = (ML.ntiles + 3) / 4;
     if (stats) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(stats), int64_t(8));

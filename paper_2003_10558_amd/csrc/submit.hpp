@@ -3,6 +3,10 @@
 // rasterizer over all their 8x8 tiles (VSR_SUBMIT_BINNED), or the fused
 // depth-sliced bin + raster over all super-tiles (VSR_SUBMIT_FUSED).
 //
+// Maps are camera-frame, so jobs whose lens (size, angle of view and
+// effective k, l, s, Omega) is the same share one map, built once per
+// submit; every job applies its own rotation.
+//
 // The job table lives in the workspace; it is written by a small kernel whose
 // arguments carry the descriptors (no host-memory copy, so a caller may
 // capture the whole submit in a HIP graph).  Each kernel maps its global
@@ -13,6 +17,9 @@
 
 #pragma once
 #include <algorithm>
+#include <array>
+#include <cstring>
+#include <map>
 #include <vector>
 
 #include "fused.hpp"
@@ -33,7 +40,10 @@ struct JobDesc {
     int64_t tile_off;  // first global tile of this job
     int64_t ntiles;
     int64_t stile_off;  // first global super-tile (binning) of this job
+    int64_t mtile_off;  // first global map tile of this job's map (if it builds it)
     int32_t ntx, nty;
+    int32_t map_owner;  // 1: this job builds the map it uses
+    int32_t pad;
 };
 
 constexpr int kJobChunk = 8;
@@ -114,6 +124,7 @@ __global__ __launch_bounds__(256) void k_submit_bin(const JobDesc* __restrict__ 
     A.n = J.ntri;
     A.bins = J.bins;
     A.status = status;
+    A.rot = rot_of(J.P.rot);
     bin_super(A, t - J.stile_off);
 }
 
@@ -140,6 +151,7 @@ __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict
     A.out_depth = J.depth;
     A.stats = nullptr;
     A.no_early_exit = 0;
+    A.rot = rot_of(J.P.rot);
     raster_tile<false>(A, t - J.tile_off, threadIdx.x & 63);
 }
 
@@ -161,31 +173,68 @@ __global__ __launch_bounds__(256) void k_submit_fused(const JobDesc* __restrict_
     A.scratch = reinterpret_cast<uint32_t*>(J.bins);
     A.tri_id = J.tri_id;
     A.depth = J.depth;
+    A.rot = rot_of(J.P.rot);
     fused_super(A, t - J.stile_off);
+}
+
+// Map tiles of the jobs that own a map: job ranges [mtile_off, mtile_off +
+// ntiles) for owners, empty for sharers (whose offset equals the next
+// job's, so the last job with mtile_off <= t is always the owner of t).
+__device__ inline int find_map_job(const JobDesc* __restrict__ T, int njobs, int64_t t) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (T[mid].mtile_off <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
 }
 
 __global__ __launch_bounds__(256) void k_submit_map(const JobDesc* __restrict__ T, int njobs, int64_t total) {
     int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     int64_t t = int64_t(blockIdx.x) * 4 + w;
     if (t >= total) return;
-    int jb = find_job(T, njobs, t);
+    int jb = find_map_job(T, njobs, t);
     const JobDesc& J = T[jb];
-    build_map_tile(J.P, J.map, J.ntiles, t - J.tile_off, threadIdx.x & 63);
+    build_map_tile(J.P, J.map, J.ntiles, t - J.mtile_off, threadIdx.x & 63);
 }
 
 // Job descriptors of a submit, in workspace order; returns the number of
-// tiles and super-tiles through the pointers.
+// tiles, super-tiles and map tiles through the pointers.  With share_maps,
+// jobs with the same lens use the first such job's map.
 static void build_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth, void* ws,
-                        JobDesc* out, int64_t* n_tiles, int64_t* n_stiles) {
+                        bool share_maps, JobDesc* out, int64_t* n_tiles, int64_t* n_stiles, int64_t* n_mtiles) {
     WsLayout W = ws_layout(njobs);
     char* base = reinterpret_cast<char*>(ws);
-    int64_t off = W.data_off, tiles = 0, stiles = 0;
+    int64_t off = W.data_off, tiles = 0, stiles = 0, mtiles = 0;
+    std::map<std::array<uint32_t, 7>, int32_t> lens;
+    auto bits = [](float f) {
+        uint32_t u;
+        memcpy(&u, &f, 4);
+        return u;
+    };
     for (int32_t q = 0; q < njobs; ++q) {
         JobDesc& D = out[q];
-        make_map_params(&jobs[q].view, fmt, 0, &D.P, nullptr);
+        vsr_view eff;
+        make_map_params(&jobs[q].view, fmt, 0, &D.P, &eff);
         MapLayout ML = map_layout(D.P.W, D.P.H, fmt);
-        D.map = base + off;
-        off += ML.bytes;
+        const std::array<uint32_t, 7> key = {uint32_t(eff.width), uint32_t(eff.height), uint32_t(eff.aov),
+                                             bits(eff.k), bits(eff.l), bits(eff.s), bits(eff.omega_deg)};
+        auto it = share_maps ? lens.find(key) : lens.end();
+        D.mtile_off = mtiles;
+        if (it != lens.end()) {
+            D.map = out[it->second].map;
+            D.map_owner = 0;
+        } else {
+            D.map = base + off;
+            off += ML.bytes;
+            D.map_owner = 1;
+            mtiles += ML.ntiles;
+            if (share_maps) lens.emplace(key, q);
+        }
+        D.pad = 0;
         D.bins = base + off;
         off += job_scratch_bytes(D.P.W, D.P.H, mode, depth);
         D.ntx = ML.ntx;
@@ -202,6 +251,7 @@ static void build_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t
     }
     *n_tiles = tiles;
     *n_stiles = stiles;
+    *n_mtiles = mtiles;
 }
 
 int64_t submit_table_bytes(int32_t njobs) { return int64_t(njobs) * int64_t(sizeof(JobDesc)); }
@@ -209,8 +259,8 @@ int64_t submit_table_bytes(int32_t njobs) { return int64_t(njobs) * int64_t(size
 // Host image of the job table that vsr_submit would write into `ws`.
 void submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth, void* ws,
                   void* host) {
-    int64_t t, s;
-    build_table(jobs, njobs, fmt, mode, depth, ws, reinterpret_cast<JobDesc*>(host), &t, &s);
+    int64_t t, s, m;
+    build_table(jobs, njobs, fmt, mode, depth, ws, false, reinterpret_cast<JobDesc*>(host), &t, &s, &m);
 }
 
 int64_t submit_table_offset() { return ws_layout(1).table_off; }
@@ -221,8 +271,10 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
     char* base = reinterpret_cast<char*>(ws);
     JobDesc* table = reinterpret_cast<JobDesc*>(base + W.table_off);
     std::vector<JobDesc> host(njobs);
-    int64_t tiles = 0, stiles = 0;
-    build_table(jobs, njobs, fmt, mode, depth, ws, host.data(), &tiles, &stiles);
+    int64_t tiles = 0, stiles = 0, mtiles = 0;
+    // a prewritten table (graph replays) never shares maps, so the grids
+    // sized here fit any table written for jobs of the same sizes
+    build_table(jobs, njobs, fmt, mode, depth, ws, !table_ready, host.data(), &tiles, &stiles, &mtiles);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ws), int64_t(64));
     if (!table_ready) {
         // descriptors travel as kernel arguments: no host-memory copy
@@ -234,7 +286,7 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
             hipLaunchKernelGGL(k_write_jobs, dim3(1), dim3(kJobChunk), 0, st, chunk, table);
         }
     }
-    hipLaunchKernelGGL(k_submit_map, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, tiles);
+    hipLaunchKernelGGL(k_submit_map, dim3(unsigned((mtiles + 3) / 4)), dim3(256), 0, st, table, njobs, mtiles);
     if (mode == VSR_SUBMIT_FUSED) {
         hipLaunchKernelGGL(k_submit_fused, dim3(unsigned(stiles)), dim3(256), 0, st, table, njobs, fmt);
     } else {

@@ -251,8 +251,28 @@ __host__ __device__ inline const float4* map_caps(const void* map, int64_t ntile
                                            align256(ntiles * kTilePix * (fmt == VSR_MAP_OCT16 ? 4 : 12)));
 }
 
-// Load the direction of pixel `lane` of tile `tile`.
-__device__ inline float3 load_dir(const void* map, int32_t fmt, int64_t ntiles, int64_t tile, int lane) {
+// Camera -> world rotation of a view (row-major), applied to the camera-frame
+// map: the map depends only on the lens (size, AOV, k, l, s, Omega), so one
+// map serves every orientation.
+struct Rot {
+    float m[9];
+};
+
+__host__ __device__ inline Rot rot_of(const float* r) {
+    Rot R;
+    for (int q = 0; q < 9; ++q) R.m[q] = r[q];
+    return R;
+}
+
+// World direction of a camera-frame direction (fixed FP32 operation order).
+__device__ inline float3 rotate_dir(const Rot& R, float3 v) {
+    return f3(fmaf(R.m[2], v.z, fmaf(R.m[1], v.y, R.m[0] * v.x)),
+              fmaf(R.m[5], v.z, fmaf(R.m[4], v.y, R.m[3] * v.x)),
+              fmaf(R.m[8], v.z, fmaf(R.m[7], v.y, R.m[6] * v.x)));
+}
+
+// Load the camera-frame direction of pixel `lane` of tile `tile`.
+__device__ inline float3 load_dir_cam(const void* map, int32_t fmt, int64_t ntiles, int64_t tile, int lane) {
     if (fmt == VSR_MAP_OCT16) {
         const uint32_t* p = reinterpret_cast<const uint32_t*>(map);
         return oct_decode(p[tile * kTilePix + lane]);
@@ -261,6 +281,22 @@ __device__ inline float3 load_dir(const void* map, int32_t fmt, int64_t ntiles, 
     int64_t plane = ntiles * kTilePix;
     int64_t q = tile * kTilePix + lane;
     return f3(p[q], p[plane + q], p[2 * plane + q]);
+}
+
+// World direction of pixel `lane` of tile `tile` (zero: no direction).
+__device__ inline float3 load_dir(const void* map, int32_t fmt, int64_t ntiles, int64_t tile, int lane,
+                                  const Rot& R) {
+    return rotate_dir(R, load_dir_cam(map, fmt, ntiles, tile, lane));
+}
+
+// World-frame cap of tile `tile`: the camera-frame centre rotated.  The
+// rotation's FP32 rounding (a few 1e-7 rad) is far inside the cap margin
+// (2e-5 rad), so the cap still bounds every rotated pixel direction.
+__device__ inline void load_tile_cap(const float4* caps, int64_t tile, const Rot& R, float4& c0, float4& c1) {
+    c0 = caps[2 * tile];
+    c1 = caps[2 * tile + 1];
+    const float3 c = rotate_dir(R, f3(c0.x, c0.y, c0.z));
+    c0 = make_float4(c.x, c.y, c.z, c0.w);
 }
 
 // Binning record of a triangle, stored in cell order (entry k belongs to

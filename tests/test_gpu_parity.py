@@ -207,6 +207,63 @@ def test_submit_matches_single_views(gpu, mode):
     assert st.ok(), st.notes
 
 
+def _same_lens(view, yaw, pitch):
+    return synth.View(view.width, view.height, view.k, view.l, view.s, view.omega_deg, view.aov,
+                      synth.yaw_pitch_rotation(yaw, pitch))
+
+
+@pytest.mark.parametrize("fmt", [0, 1], ids=["f32", "oct16"])
+def test_map_is_orientation_free(gpu, fmt):
+    """The map holds camera-frame directions: views that differ only in
+    orientation build byte-identical maps, and a view rendered with another
+    orientation's map equals rendering it with its own."""
+    torch, pipeline, vsr = gpu
+    tris = synth.scene(2500, 31)
+    scene = pipeline.Scene(tris)
+    base = synth.View(150, 90, -0.3, 0.7, 0.8, 230.0, 0)
+    va, vb = _same_lens(base, 0.3, 0.2), _same_lens(base, 2.5, -0.9)
+    fa = pipeline.render(scene, va, fmt=fmt)
+    fb = pipeline.render(scene, vb, fmt=fmt)
+    torch.cuda.synchronize()
+    ntiles = ((base.width + 7) // 8) * ((base.height + 7) // 8)
+    plane = ntiles * 64 * (12 if fmt == 0 else 4)
+    caps = (plane + 255) // 256 * 256
+    for lo, hi in ((0, plane), (caps, caps + 32 * ntiles)):  # directions, tile caps (not the padding)
+        assert torch.equal(fa.map[lo:hi], fb.map[lo:hi])
+    # render vb through va's map
+    ids = torch.empty_like(fb.tri_id)
+    dep = torch.empty_like(fb.depth)
+    vsr.vsr_bin(vb, fmt, fa.map, scene.setup, scene.ntri, 1024, 0, fa.bins)
+    vsr.vsr_raster(vb, fmt, fa.map, scene.setup, scene.ntri, fa.bins, 1024, ids, dep)
+    torch.cuda.synchronize()
+    assert torch.equal(ids, fb.tri_id)
+    assert np.array_equal(dep.cpu().numpy().view(np.uint32), fb.depth.cpu().numpy().view(np.uint32))
+    if fmt == 0:
+        st = compare(vb, tris, pipeline.ids_u32(ids), dep.cpu().numpy(), oracle.render(vb, tris))
+        _say("[map-orient] " + st.line())
+        assert st.ok(), st.notes
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["binned", "fused"])
+def test_submit_shares_lens_maps(gpu, mode):
+    """A batch whose views repeat lenses in several orientations (maps built
+    once per lens) renders every view exactly as alone."""
+    torch, pipeline, vsr = gpu
+    tris = synth.scene(3000, 37)
+    scene = pipeline.Scene(tris)
+    lenses = [synth.View(120, 80, 0.6, 0.5, 1.0, 160.0, 0), synth.View(96, 96, -0.5, 0.2, 0.7, 280.0, 1)]
+    views = [_same_lens(lenses[q % 2], 0.7 * q, 0.25 * (q % 3) - 0.25) for q in range(7)]
+    batch = pipeline.Batch([(scene, v) for v in views], mode=mode)
+    outs = batch.submit()
+    torch.cuda.synchronize()
+    _say(f"[submit-lens] {len(views)} views over 2 lenses, mode {mode}")
+    for v, (ids_t, dep_t) in zip(views, outs):
+        fr = pipeline.render(scene, v)
+        torch.cuda.synchronize()
+        assert np.array_equal(pipeline.ids_u32(ids_t), pipeline.ids_u32(fr.tri_id))
+        assert np.array_equal(dep_t.cpu().numpy().view(np.uint32), fr.depth.cpu().numpy().view(np.uint32))
+
+
 def _render_fused(gpu, tris, view, fmt=0):
     torch, pipeline, vsr = gpu
     scene = pipeline.Scene(tris)
