@@ -30,7 +30,8 @@ __device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
     int64_t tile;
     int tx, ty;
     const bool present = super_tile_of(sidx, w, A.ntx, A.nty, tile, tx, ty);
-    super_setup(sh, map_caps(A.map, A.ntiles, A.fmt), A.rot, scene_view(A.setup, A.n).face_count, present, tile);
+    super_setup(sh, map_caps(A.map, A.ntiles, A.fmt), map_sups(A.map, A.ntiles, A.fmt), A.rot,
+                scene_view(A.setup, A.n).face_count, present, tile, sidx);
     const bool any = sh.sup[1].z != 0.0f;
     const SceneView S = scene_view(A.setup, A.n);
     const uint32_t lcap = uint32_t(A.lds_cap);

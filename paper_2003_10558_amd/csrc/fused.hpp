@@ -44,7 +44,8 @@ __device__ inline void fused_super(const FusedArgs& A, int64_t sidx) {
     int64_t tile;
     int tx, ty;
     const bool present = super_tile_of(sidx, w, A.ntx, A.nty, tile, tx, ty);
-    super_setup(sh, map_caps(A.map, A.ntiles, A.fmt), A.rot, scene_view(A.setup, A.n).face_count, present, tile);
+    super_setup(sh, map_caps(A.map, A.ntiles, A.fmt), map_sups(A.map, A.ntiles, A.fmt), A.rot,
+                scene_view(A.setup, A.n).face_count, present, tile, sidx);
     const SceneView S = scene_view(A.setup, A.n);
 
     const int i = tx * kTile + (lane & (kTile - 1)), j = ty * kTile + (lane >> 3);

@@ -247,24 +247,13 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wsum, ui
     return base + x - v;
 }
 
-// Tile of wave w in super-tile sidx (2x2 tiles); false when outside the map.
-__device__ inline bool super_tile_of(int64_t sidx, int w, int ntx, int nty, int64_t& tile, int& tx, int& ty) {
-    const int nsx = (ntx + 1) / 2;
-    const int sx = int(sidx % nsx), sy = int(sidx / nsx);
-    tx = 2 * sx + (w & 1);
-    ty = 2 * sy + (w >> 1);
-    tile = int64_t(ty) * ntx + tx;
-    return tx < ntx && ty < nty;
-}
-
-// Loads the four tile caps (rotated to the world frame) and the per-slice
-// face counts, computes the
-// super-tile cap and the cell rectangles of every (level, face).  All
-// threads of the block call it.  Angles are never formed: caps carry
-// sin and cos of their half radius, and radii add through the angle-sum
-// identities.
-__device__ inline void super_setup(SuperShared& sh, const float4* caps, const Rot& R, const uint32_t* face_count,
-                                   bool present, int64_t tile) {
+// Loads the four tile caps and the super-tile cap (rotated to the world
+// frame) and the per-slice face counts, and computes the cell rectangles of
+// every (level, face).  All threads of the block call it.  Angles are never
+// formed: caps carry sin and cos of their half radius, and radii add
+// through the angle-sum identities.
+__device__ inline void super_setup(SuperShared& sh, const float4* caps, const float4* sups, const Rot& R,
+                                   const uint32_t* face_count, bool present, int64_t tile, int64_t sidx) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (lane == 0) {
         float4 c0 = empty_cap0(), c1 = empty_cap1();
@@ -272,60 +261,16 @@ __device__ inline void super_setup(SuperShared& sh, const float4* caps, const Ro
         sh.cap[w][0] = c0;
         sh.cap[w][1] = c1;
     }
+    if (tid == 64) {
+        float4 s0, s1;
+        load_tile_cap(sups, sidx, R, s0, s1);
+        sh.sup[0] = s0;
+        sh.sup[1] = s1;
+    }
     sh.fc[tid] = face_count[tid];  // kSlices * 64 == 256 entries
     if (tid < kSupTiles) {
         sh.cnt[tid] = 0;
         sh.flag[tid] = 0;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        bool any0 = false, wide0 = false;
-        float3 sum = f3(0.f, 0.f, 0.f);
-        for (int q = 0; q < kSupTiles; ++q) {
-            float4 c0 = sh.cap[q][0], c1 = sh.cap[q][1];
-            if (c1.z == kCapEmpty) continue;
-            any0 = true;
-            if (c1.z == kCapWide) wide0 = true;
-            sum = add3(sum, f3(c0.x, c0.y, c0.z));
-        }
-        float3 c = f3(0.f, 0.f, 1.f);
-        float sh_ = 1.0f, ch_ = 0.0f;  // sin, cos of half the super-cap radius
-        if (any0 && !wide0) {
-            float len = sqrtf(dot3(sum, sum));
-            if (len > 1e-3f) {
-                c = scale3(sum, 1.0f / len);
-                sh_ = 0.0f;
-                ch_ = 1.0f;
-                for (int q = 0; q < kSupTiles; ++q) {
-                    float4 c0 = sh.cap[q][0], c1 = sh.cap[q][1];
-                    if (c1.z == kCapEmpty) continue;
-                    // half-angle between the centres from the chord, plus the
-                    // tile's half radius: sin/cos of the sum
-                    float3 d = sub3(c, f3(c0.x, c0.y, c0.z));
-                    float st = fminf(1.0f, 0.5f * sqrtf(dot3(d, d)));
-                    float ct = sqrtf(fmaxf(0.0f, 1.0f - st * st));
-                    float sq = st * c1.x + ct * c0.w, cq = ct * c1.x - st * c0.w;
-                    if (!(cq > 0.0f)) {
-                        wide0 = true;
-                    } else if (sq > sh_) {
-                        sh_ = sq;
-                        ch_ = cq;
-                    }
-                }
-                // margin: grow the half radius by a relative 1e-6 and 1e-7 rad
-                sh_ = sh_ * (1.0f + 1e-6f) + 1e-7f;
-                ch_ = sqrtf(fmaxf(0.0f, 1.0f - sh_ * sh_));
-            } else {
-                wide0 = true;
-            }
-            if (!(sh_ < 0.70710678f)) wide0 = true;  // radius >= pi/2
-        }
-        if (wide0) {
-            sh_ = 1.0f;
-            ch_ = 0.0f;
-        }
-        sh.sup[0] = make_float4(c.x, c.y, c.z, sh_);
-        sh.sup[1] = make_float4(sh_, ch_, any0 ? 1.0f : 0.0f, wide0 ? 1.0f : 0.0f);
     }
     __syncthreads();
     if (tid < 64) {

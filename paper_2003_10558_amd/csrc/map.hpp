@@ -8,6 +8,9 @@
 // tile's bounding cap: the normalised mean direction and the largest chord
 // to it, widened by a safety margin.
 //
+// Each 16x16 super-tile also gets a cap bounding its four tile caps (used by
+// the binner).
+//
 // The map depends only on the lens (size, angle of view, k, l, s, Omega): as
 // in the paper, where the vector map is computed once and kept as a texture,
 // one map serves every orientation.  Consumers rotate directions and cap
@@ -112,7 +115,9 @@ __device__ inline void tile_cap(float3 g, bool ok, float4& c0, float4& c1) {
     c1 = make_float4(chh, sinf(rho), 0.f, 0.f);
 }
 
-__device__ inline void build_map_tile(const MapParams& P, void* map, int64_t ntiles, int64_t tile, int lane) {
+// Directions and cap of one tile (one wave); the cap is also returned.
+__device__ inline void build_map_tile(const MapParams& P, void* map, int64_t ntiles, int64_t tile, int lane,
+                                      float4& c0, float4& c1) {
     int tx = int(tile % P.ntx), ty = int(tile / P.ntx);
     int i = tx * kTile + (lane & (kTile - 1)), j = ty * kTile + (lane >> 3);
     float3 g = f3(0.f, 0.f, 0.f);
@@ -132,7 +137,6 @@ __device__ inline void build_map_tile(const MapParams& P, void* map, int64_t nti
         p[plane + q] = g.y;
         p[2 * plane + q] = g.z;
     }
-    float4 c0, c1;
     tile_cap(g, ok, c0, c1);
     if (lane == 0) {
         MapLayout L = map_layout(P.W, P.H, P.fmt);
@@ -142,11 +146,32 @@ __device__ inline void build_map_tile(const MapParams& P, void* map, int64_t nti
     }
 }
 
+// One 256-thread block per 16x16 super-tile: wave w builds tile w of the
+// 2x2, then one thread bounds the four tile caps by the super-tile cap.
+__device__ inline void build_map_super(const MapParams& P, void* map, int64_t ntiles, int64_t sidx) {
+    __shared__ float4 s_cap[4][2];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    int64_t tile;
+    int tx, ty;
+    float4 c0 = make_float4(0.f, 0.f, 1.f, 0.f), c1 = make_float4(1.f, 0.f, kCapEmpty, 0.f);
+    if (super_tile_of(sidx, w, P.ntx, P.nty, tile, tx, ty)) build_map_tile(P, map, ntiles, tile, lane, c0, c1);
+    if (lane == 0) {
+        s_cap[w][0] = c0;
+        s_cap[w][1] = c1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float4 sup0, sup1;
+        super_cap_of(s_cap, sup0, sup1);
+        float4* sups = const_cast<float4*>(map_sups(map, ntiles, P.fmt));
+        sups[2 * sidx] = sup0;
+        sups[2 * sidx + 1] = sup1;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_build_map(MapParams P, void* map, int64_t ntiles) {
-    int lane = threadIdx.x & 63;
-    int64_t tile = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-    if (tile >= ntiles) return;
-    build_map_tile(P, map, ntiles, tile, lane);
+    build_map_super(P, map, ntiles, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_map_unpack(const void* map, int32_t fmt, int64_t ntiles, int32_t ntx,
@@ -174,8 +199,7 @@ hipError_t launch_map_unpack(const void* map, int32_t W, int32_t H, int32_t fmt,
 
 hipError_t launch_build_map(const MapParams& P, void* map, hipStream_t stream) {
     MapLayout L = map_layout(P.W, P.H, P.fmt);
-    int64_t blocks = (L.ntiles + 3) / 4;
-    hipLaunchKernelGGL(k_build_map, dim3(unsigned(blocks)), dim3(256), 0, stream, P, map, L.ntiles);
+    hipLaunchKernelGGL(k_build_map, dim3(unsigned(L.nsup)), dim3(256), 0, stream, P, map, L.ntiles);
     return hipGetLastError();
 }
 

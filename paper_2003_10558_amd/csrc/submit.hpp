@@ -40,7 +40,7 @@ struct JobDesc {
     int64_t tile_off;  // first global tile of this job
     int64_t ntiles;
     int64_t stile_off;  // first global super-tile (binning) of this job
-    int64_t mtile_off;  // first global map tile of this job's map (if it builds it)
+    int64_t msup_off;   // first global map super-tile of this job's map (if it builds it)
     int32_t ntx, nty;
     int32_t map_owner;  // 1: this job builds the map it uses
     int32_t pad;
@@ -177,14 +177,14 @@ __global__ __launch_bounds__(256) void k_submit_fused(const JobDesc* __restrict_
     fused_super(A, t - J.stile_off);
 }
 
-// Map tiles of the jobs that own a map: job ranges [mtile_off, mtile_off +
-// ntiles) for owners, empty for sharers (whose offset equals the next
-// job's, so the last job with mtile_off <= t is always the owner of t).
+// Map super-tiles of the jobs that own a map: job ranges [msup_off,
+// msup_off + nsup) for owners, empty for sharers (whose offset equals the
+// next job's, so the last job with msup_off <= t is always the owner of t).
 __device__ inline int find_map_job(const JobDesc* __restrict__ T, int njobs, int64_t t) {
     int lo = 0, hi = njobs - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (T[mid].mtile_off <= t)
+        if (T[mid].msup_off <= t)
             lo = mid;
         else
             hi = mid - 1;
@@ -192,17 +192,15 @@ __device__ inline int find_map_job(const JobDesc* __restrict__ T, int njobs, int
     return lo;
 }
 
-__global__ __launch_bounds__(256) void k_submit_map(const JobDesc* __restrict__ T, int njobs, int64_t total) {
-    int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    int64_t t = int64_t(blockIdx.x) * 4 + w;
-    if (t >= total) return;
-    int jb = find_map_job(T, njobs, t);
+__global__ __launch_bounds__(256) void k_submit_map(const JobDesc* __restrict__ T, int njobs) {
+    const int64_t t = blockIdx.x;
+    const int jb = find_map_job(T, njobs, t);
     const JobDesc& J = T[jb];
-    build_map_tile(J.P, J.map, J.ntiles, t - J.mtile_off, threadIdx.x & 63);
+    build_map_super(J.P, J.map, J.ntiles, t - J.msup_off);
 }
 
 // Job descriptors of a submit, in workspace order; returns the number of
-// tiles, super-tiles and map tiles through the pointers.  With share_maps,
+// tiles, super-tiles and map super-tiles through the pointers.  With share_maps,
 // jobs with the same lens use the first such job's map.
 static void build_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth, void* ws,
                         bool share_maps, JobDesc* out, int64_t* n_tiles, int64_t* n_stiles, int64_t* n_mtiles) {
@@ -223,7 +221,7 @@ static void build_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t
         const std::array<uint32_t, 7> key = {uint32_t(eff.width), uint32_t(eff.height), uint32_t(eff.aov),
                                              bits(eff.k), bits(eff.l), bits(eff.s), bits(eff.omega_deg)};
         auto it = share_maps ? lens.find(key) : lens.end();
-        D.mtile_off = mtiles;
+        D.msup_off = mtiles;
         if (it != lens.end()) {
             D.map = out[it->second].map;
             D.map_owner = 0;
@@ -231,7 +229,7 @@ static void build_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t
             D.map = base + off;
             off += ML.bytes;
             D.map_owner = 1;
-            mtiles += ML.ntiles;
+            mtiles += ML.nsup;
             if (share_maps) lens.emplace(key, q);
         }
         D.pad = 0;
@@ -286,7 +284,7 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
             hipLaunchKernelGGL(k_write_jobs, dim3(1), dim3(kJobChunk), 0, st, chunk, table);
         }
     }
-    hipLaunchKernelGGL(k_submit_map, dim3(unsigned((mtiles + 3) / 4)), dim3(256), 0, st, table, njobs, mtiles);
+    if (mtiles > 0) hipLaunchKernelGGL(k_submit_map, dim3(unsigned(mtiles)), dim3(256), 0, st, table, njobs);
     if (mode == VSR_SUBMIT_FUSED) {
         hipLaunchKernelGGL(k_submit_fused, dim3(unsigned(stiles)), dim3(256), 0, st, table, njobs, fmt);
     } else {

@@ -59,8 +59,10 @@ __host__ __device__ inline int slice_of(int64_t n, int64_t rank) {
 struct MapLayout {
     int32_t ntx, nty;
     int64_t ntiles;
+    int64_t nsup;         // 16x16 super-tiles (2x2 tiles), row-major over ((ntx+1)/2) x ((nty+1)/2)
     int64_t plane_bytes;  // all pixel data
     int64_t caps_off;     // float4 x 2 per tile
+    int64_t sups_off;     // float4 x 2 per super-tile
     int64_t bytes;
 };
 
@@ -69,9 +71,11 @@ __host__ __device__ inline MapLayout map_layout(int32_t w, int32_t h, int32_t fm
     m.ntx = (w + kTile - 1) / kTile;
     m.nty = (h + kTile - 1) / kTile;
     m.ntiles = int64_t(m.ntx) * m.nty;
+    m.nsup = int64_t((m.ntx + 1) / 2) * ((m.nty + 1) / 2);
     m.plane_bytes = m.ntiles * kTilePix * (fmt == VSR_MAP_OCT16 ? 4 : 12);
     m.caps_off = align256(m.plane_bytes);
-    m.bytes = m.caps_off + align256(m.ntiles * 32);
+    m.sups_off = m.caps_off + align256(m.ntiles * 32);
+    m.bytes = m.sups_off + align256(m.nsup * 32);
     return m;
 }
 
@@ -251,6 +255,13 @@ __host__ __device__ inline const float4* map_caps(const void* map, int64_t ntile
                                            align256(ntiles * kTilePix * (fmt == VSR_MAP_OCT16 ? 4 : 12)));
 }
 
+// Super-tile caps of a map buffer (2 x float4 per 16x16 super-tile, after
+// the tile caps).
+__host__ __device__ inline const float4* map_sups(const void* map, int64_t ntiles, int32_t fmt) {
+    return reinterpret_cast<const float4*>(reinterpret_cast<const char*>(map_caps(map, ntiles, fmt)) +
+                                           align256(ntiles * 32));
+}
+
 // Camera -> world rotation of a view (row-major), applied to the camera-frame
 // map: the map depends only on the lens (size, AOV, k, l, s, Omega), so one
 // map serves every orientation.
@@ -299,6 +310,17 @@ __device__ inline void load_tile_cap(const float4* caps, int64_t tile, const Rot
     c0 = make_float4(c.x, c.y, c.z, c0.w);
 }
 
+// Tile of wave w (0..3) in super-tile sidx (2x2 tiles, row-major over
+// ((ntx+1)/2) columns); false when outside the map.
+__host__ __device__ inline bool super_tile_of(int64_t sidx, int w, int ntx, int nty, int64_t& tile, int& tx, int& ty) {
+    const int nsx = (ntx + 1) / 2;
+    const int sx = int(sidx % nsx), sy = int(sidx / nsx);
+    tx = 2 * sx + (w & 1);
+    ty = 2 * sy + (w >> 1);
+    tile = int64_t(ty) * ntx + tx;
+    return tx < ntx && ty < nty;
+}
+
 // Binning record of a triangle, stored in cell order (entry k belongs to
 // cell_list[k]) so that a run of cells streams as coalesced 64-byte loads:
 //   a = (cap centre xyz, sin(rho/2), or kBinWide for a useless cap)
@@ -329,6 +351,61 @@ __device__ inline bool tile_may_see(float4 c0, float4 c1, float4 t0, float4 t1, 
     float lim = -c1.y - 1e-6f;
     if (dot3(n0, c) < lim || dot3(n1, c) < lim || dot3(n2, c) < lim) return false;
     return true;
+}
+
+// Cap of a 16x16 super-tile bounding its four tile caps, written as
+//   sup0 = (centre, sin of half the radius), sup1 = (same sine, its cosine,
+//   1 if any tile has a direction, 1 if the cap is wide (radius >= pi/2)).
+// Angles are never formed: half radii add through the angle-sum identities
+// on the half-chord between centres.  The margin (1e-6 relative, 1e-6
+// absolute on the half-radius sine) also covers the rotation of the centres
+// into the world frame, which is applied after this (the tile caps carry
+// 2e-5 rad over their pixels, so pixels stay well inside).
+__device__ inline void super_cap_of(const float4 (&cap)[4][2], float4& sup0, float4& sup1) {
+    bool any0 = false, wide0 = false;
+    float3 sum = f3(0.f, 0.f, 0.f);
+    for (int q = 0; q < 4; ++q) {
+        const float4 c0 = cap[q][0], c1 = cap[q][1];
+        if (c1.z == kCapEmpty) continue;
+        any0 = true;
+        if (c1.z == kCapWide) wide0 = true;
+        sum = add3(sum, f3(c0.x, c0.y, c0.z));
+    }
+    float3 c = f3(0.f, 0.f, 1.f);
+    float sh_ = 1.0f, ch_ = 0.0f;
+    if (any0 && !wide0) {
+        const float len = sqrtf(dot3(sum, sum));
+        if (len > 1e-3f) {
+            c = scale3(sum, 1.0f / len);
+            sh_ = 0.0f;
+            ch_ = 1.0f;
+            for (int q = 0; q < 4; ++q) {
+                const float4 c0 = cap[q][0], c1 = cap[q][1];
+                if (c1.z == kCapEmpty) continue;
+                const float3 d = sub3(c, f3(c0.x, c0.y, c0.z));
+                const float st = fminf(1.0f, 0.5f * sqrtf(dot3(d, d)));
+                const float ct = sqrtf(fmaxf(0.0f, 1.0f - st * st));
+                const float sq = st * c1.x + ct * c0.w, cq = ct * c1.x - st * c0.w;
+                if (!(cq > 0.0f)) {
+                    wide0 = true;
+                } else if (sq > sh_) {
+                    sh_ = sq;
+                    ch_ = cq;
+                }
+            }
+            sh_ = sh_ * (1.0f + 1e-6f) + 1e-6f;
+            ch_ = sqrtf(fmaxf(0.0f, 1.0f - sh_ * sh_));
+        } else {
+            wide0 = true;
+        }
+        if (!(sh_ < 0.70710678f)) wide0 = true;  // radius >= pi/2
+    }
+    if (wide0) {
+        sh_ = 1.0f;
+        ch_ = 0.0f;
+    }
+    sup0 = make_float4(c.x, c.y, c.z, sh_);
+    sup1 = make_float4(sh_, ch_, any0 ? 1.0f : 0.0f, wide0 ? 1.0f : 0.0f);
 }
 
 }  // namespace vsr
