@@ -140,7 +140,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--views", type=int, default=64)
-    ap.add_argument("--bin-depth", type=int, default=1024)
+    ap.add_argument("--bin-depth", type=int, default=256)
     ap.add_argument("--fmt", choices=["f32", "oct16"], default="f32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")

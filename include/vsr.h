@@ -61,6 +61,13 @@ extern "C" {
 
 /* vsr_bin flags */
 #define VSR_BIN_ALL 1u /* list every live triangle in every tile (no culling) */
+/* Workgroup shape of the binner (the lists are the same either way):
+ * candidates gathered once per 32x32-pixel block of 4x4 tiles, or once per
+ * 16x16 super-tile of 2x2 tiles.  Neither flag: blocks when the list
+ * capacity (bin_depth rounded up to a power of two, at least 64) is at most
+ * 256 and the launch has at least 8192 blocks, super-tiles otherwise. */
+#define VSR_BIN_BLOCKS 2u
+#define VSR_BIN_SUPERTILES 4u
 
 #define VSR_NO_HIT 0xFFFFFFFFu /* tri_id of a pixel that nothing covers */
 
@@ -220,6 +227,10 @@ int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, in
  *   mode | VSR_SUBMIT_TABLE_READY, which then reads the table instead of
  *   writing it. */
 #define VSR_SUBMIT_TABLE_READY 0x100
+/* Binner shape of a binned submit (see VSR_BIN_BLOCKS); neither: automatic
+ * over the blocks of all jobs. */
+#define VSR_SUBMIT_BIN_BLOCKS 0x200
+#define VSR_SUBMIT_BIN_SUPERTILES 0x400
 int64_t vsr_submit_table_bytes(int32_t njobs);
 int64_t vsr_submit_table_offset(void);
 int vsr_submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth,

@@ -187,8 +187,10 @@ int vsr_bin(const vsr_view* v, int32_t fmt, const void* map, const void* setup, 
     if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
     int64_t need = bin_layout(v->width, v->height, bin_depth).bytes;
     if (bin_bytes < need) return fail(VSR_E_SPACE, "bin buffer %lld < %lld bytes", (long long)bin_bytes, (long long)need);
-    return hip_status(launch_bin(map, v->width, v->height, fmt, rot_of(v->rot), setup, ntri, bin_depth,
-                                 (flags & VSR_BIN_ALL) != 0, bins, hipStream_t(stream)),
+    if ((flags & VSR_BIN_BLOCKS) && (flags & VSR_BIN_SUPERTILES))
+        return fail(VSR_E_ARG, "VSR_BIN_BLOCKS and VSR_BIN_SUPERTILES together");
+    return hip_status(launch_bin(map, v->width, v->height, fmt, rot_of(v->rot), setup, ntri, bin_depth, flags, bins,
+                                 hipStream_t(stream)),
                       "vsr_bin");
 }
 
@@ -248,6 +250,7 @@ int vsr_render(const vsr_view* v, int32_t fmt, const void* map, const void* setu
 int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth) {
     if (!jobs || njobs < 1 || njobs > 4096) return VSR_E_ARG;
     if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return VSR_E_ARG;
+    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES);
     if (mode != VSR_SUBMIT_BINNED && mode != VSR_SUBMIT_FUSED) return VSR_E_ARG;
     if (mode == VSR_SUBMIT_BINNED && (bin_depth < 1 || bin_depth > kMaxDepth)) return VSR_E_ARG;
     for (int32_t q = 0; q < njobs; ++q) {
@@ -269,6 +272,7 @@ int vsr_submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mo
     if (!jobs || njobs < 1 || njobs > 4096) return fail(VSR_E_ARG, "njobs %d outside 1..4096", njobs);
     if (!workspace || !aligned(workspace) || !host_table) return fail(VSR_E_ARG, "NULL or misaligned buffer");
     if (host_table_bytes < submit_table_bytes(njobs)) return fail(VSR_E_SPACE, "host table too small");
+    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES);
     for (int32_t q = 0; q < njobs; ++q) {
         MapParams P;
         int rc = make_map_params(&jobs[q].view, fmt, 0, &P, nullptr);
@@ -281,7 +285,12 @@ int vsr_submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mo
 int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth, void* workspace,
                int64_t ws_bytes, void* stream) {
     const bool table_ready = (mode & VSR_SUBMIT_TABLE_READY) != 0;
-    mode &= ~VSR_SUBMIT_TABLE_READY;
+    uint32_t shape = 0;
+    if (mode & VSR_SUBMIT_BIN_BLOCKS) shape |= VSR_BIN_BLOCKS;
+    if (mode & VSR_SUBMIT_BIN_SUPERTILES) shape |= VSR_BIN_SUPERTILES;
+    if (shape == (VSR_BIN_BLOCKS | VSR_BIN_SUPERTILES))
+        return fail(VSR_E_ARG, "VSR_SUBMIT_BIN_BLOCKS and VSR_SUBMIT_BIN_SUPERTILES together");
+    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES);
     if (!jobs || njobs < 1 || njobs > 4096) return fail(VSR_E_ARG, "njobs %d outside 1..4096", njobs);
     if (mode != VSR_SUBMIT_BINNED && mode != VSR_SUBMIT_FUSED) return fail(VSR_E_ARG, "unknown submit mode %d", mode);
     if (mode == VSR_SUBMIT_BINNED && (bin_depth < 1 || bin_depth > kMaxDepth))
@@ -299,7 +308,8 @@ int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, in
     }
     int64_t need = submit_bytes(jobs, njobs, fmt, mode, bin_depth);
     if (ws_bytes < need) return fail(VSR_E_SPACE, "workspace %lld < %lld bytes", (long long)ws_bytes, (long long)need);
-    return hip_status(launch_submit(jobs, njobs, fmt, mode, bin_depth, workspace, table_ready, hipStream_t(stream)),
+    return hip_status(
+        launch_submit(jobs, njobs, fmt, mode, bin_depth, workspace, table_ready, shape, hipStream_t(stream)),
                       "vsr_submit");
 }
 

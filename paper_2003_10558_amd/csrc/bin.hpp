@@ -1,10 +1,17 @@
 // Conservative binning (vsr_bin): per 8x8 tile, the triangles that may
 // cover one of its pixels, in depth-bucket order.
 //
-// One 256-thread workgroup per 16x16 super-tile (2x2 tiles; wave w owns tile
-// w): the super-tile cap is gathered once per depth slice (gather.hpp),
-// survivors are appended to the four tiles' LDS lists with LDS atomics, and
-// each wave writes its list with a counting sort by depth bucket.
+// Two workgroup shapes share the gathering code (gather.hpp):
+//   bin_block  one 256-thread workgroup per 32x32 block (4x4 tiles, wave w
+//              owns the 2x2 tiles of quadrant w).  The block cap gathers the
+//              candidates once; each survivor is tested against the four
+//              quadrant (super-tile) caps and then the tiles of the
+//              quadrants it may meet.  Used when the LDS lists (16 x the
+//              list capacity) stay small.
+//   bin_super  one 256-thread workgroup per 16x16 super-tile (2x2 tiles,
+//              wave w owns tile w), for deep lists.
+// Survivors are appended to the tiles' LDS lists with LDS atomics, and each
+// wave writes its tiles' lists with a counting sort by depth bucket.
 #pragma once
 #include "gather.hpp"
 
@@ -55,7 +62,23 @@ __device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
             if (r < A.n && S.cap[2 * r + 1].z != kCapEmpty) append(live_mask, uint32_t(r));
         }
     } else if (any) {
-        gather_slices(sh, S, 0, kSlices, live_mask, append, [] {});
+        float4 tc0[kSupTiles], tc1[kSupTiles];
+#pragma unroll
+        for (int q = 0; q < kSupTiles; ++q) {
+            tc0[q] = sh.cap[q][0];
+            tc1[q] = sh.cap[q][1];
+        }
+        auto visit = [&](bool valid, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t rank) {
+            uint32_t mask = 0;
+            if (valid) {
+#pragma unroll
+                for (int q = 0; q < kSupTiles; ++q)
+                    if ((live_mask >> q) & 1u)
+                        if (sub_may_see(tc0[q], tc1[q], a, ch_t, n0, n1, n2)) mask |= 1u << q;
+            }
+            if (mask) append(mask, rank);
+        };
+        gather_slices(sh, S, 0, kSlices, visit, [] {});
     }
     __syncthreads();
 
@@ -74,6 +97,148 @@ __device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
 
 __global__ __launch_bounds__(256) void k_bin(BinArgs A) { bin_super(A, xcd_remap(blockIdx.x, gridDim.x)); }
 
+// ------------------------------------------------ 32x32 blocks ----------
+
+constexpr int kBlkTiles = 16;
+
+struct BlockShared {
+    SuperShared g;                // gathering state; g.sup = block cap
+    float4 tcap[kBlkTiles][2];    // tile caps, tile 4q + (2 dy + dx) of quadrant q
+    float4 qcap[4][2];            // quadrant (super-tile) caps, super-tile layout
+    uint32_t tcnt[kBlkTiles];
+};
+
+// Tile (tx, ty) of slot t (quadrant t >> 2) of block b; false outside the map.
+__device__ inline bool block_tile_of(int64_t b, int t, int ntx, int nty, int64_t& tile) {
+    const int nbx = (ntx + 3) / 4;
+    const int bx = int(b % nbx), by = int(b / nbx);
+    const int q = t >> 2, d = t & 3;
+    const int tx = 4 * bx + 2 * (q & 1) + (d & 1), ty = 4 * by + 2 * (q >> 1) + (d >> 1);
+    tile = int64_t(ty) * ntx + tx;
+    return tx < ntx && ty < nty;
+}
+
+// May a triangle meet a pixel of the super-tile with cap (s0, s1) (super-tile
+// layout)?  Same conservative tests as sub_may_see.
+__device__ inline bool quad_may_see(float4 s0, float4 s1, float4 a, float ch_t, float3 n0, float3 n1, float3 n2) {
+    if (s1.z == 0.0f) return false;  // no pixel with a direction
+    if (s1.w != 0.0f) return true;   // wide
+    if (a.w < kBinWide) {
+        float dx = s0.x - a.x, dy = s0.y - a.y, dz = s0.z - a.z;
+        float chord2 = dx * dx + dy * dy + dz * dz;
+        float sm = s0.w * ch_t + s1.y * a.w;
+        if (chord2 > 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f) return false;
+    }
+    float3 c = f3(s0.x, s0.y, s0.z);
+    float lim = -2.0f * s1.x * s1.y - 1e-6f;  // -sin(rho)
+    return !(dot3(n0, c) < lim || dot3(n1, c) < lim || dot3(n2, c) < lim);
+}
+
+__device__ inline void bin_block(const BinArgs& A, int64_t b) {
+    extern __shared__ uint32_t lists[];  // kBlkTiles x lds_cap
+    __shared__ BlockShared sh;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const SceneView S = scene_view(A.setup, A.n);
+    const uint32_t lcap = uint32_t(A.lds_cap);
+    const int nsx = (A.ntx + 1) / 2, nsy = (A.nty + 1) / 2, nbx = (A.ntx + 3) / 4;
+    if (tid < kBlkTiles) {
+        int64_t tile;
+        float4 c0 = empty_cap0(), c1 = empty_cap1();
+        if (block_tile_of(b, tid, A.ntx, A.nty, tile)) load_tile_cap(map_caps(A.map, A.ntiles, A.fmt), tile, A.rot, c0, c1);
+        sh.tcap[tid][0] = c0;
+        sh.tcap[tid][1] = c1;
+        sh.tcnt[tid] = 0;
+    } else if (tid < kBlkTiles + 4) {
+        const int q = tid - kBlkTiles;
+        const int sx = 2 * int(b % nbx) + (q & 1), sy = 2 * int(b / nbx) + (q >> 1);
+        float4 s0 = make_float4(0.f, 0.f, 1.f, 1.f), s1 = make_float4(1.f, 0.f, 0.f, 0.f);  // no pixel
+        if (sx < nsx && sy < nsy) load_tile_cap(map_sups(A.map, A.ntiles, A.fmt), int64_t(sy) * nsx + sx, A.rot, s0, s1);
+        sh.qcap[q][0] = s0;
+        sh.qcap[q][1] = s1;
+    } else if (tid == kBlkTiles + 4) {
+        float4 s0, s1;
+        load_tile_cap(map_blks(A.map, A.ntiles, A.fmt, A.ntx, A.nty), b, A.rot, s0, s1);
+        sh.g.sup[0] = s0;
+        sh.g.sup[1] = s1;
+    }
+    sh.g.fc[tid] = S.face_count[tid];
+    __syncthreads();
+    setup_rects(sh.g);
+    const bool any = sh.g.sup[1].z != 0.0f;
+
+    auto append = [&](uint32_t mask, uint32_t rank) {
+        while (mask) {
+            const int t = __ffs(mask) - 1;
+            mask &= mask - 1;
+            const uint32_t pos = atomicAdd(&sh.tcnt[t], 1u);
+            if (pos < lcap) lists[t * lcap + pos] = rank;
+        }
+    };
+    if (any && A.all) {
+        uint32_t live = 0;
+        for (int t = 0; t < kBlkTiles; ++t)
+            if (sh.tcap[t][1].z != kCapEmpty) live |= 1u << t;
+        for (int64_t k0 = 0; k0 < A.n; k0 += 256) {
+            int64_t r = k0 + tid;
+            if (r < A.n && S.cap[2 * r + 1].z != kCapEmpty) append(live, uint32_t(r));
+        }
+    } else if (any) {
+        auto visit = [&](bool valid, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t rank) {
+            uint32_t mask = 0;
+            if (valid) {
+                // caps are read from LDS in the loops (not unrolled, so they
+                // are not hoisted into registers)
+#pragma unroll 1
+                for (int q = 0; q < 4; ++q) {
+                    if (!quad_may_see(sh.qcap[q][0], sh.qcap[q][1], a, ch_t, n0, n1, n2)) continue;
+#pragma unroll 1
+                    for (int d = 0; d < 4; ++d) {
+                        const int t = 4 * q + d;
+                        if (sub_may_see(sh.tcap[t][0], sh.tcap[t][1], a, ch_t, n0, n1, n2)) mask |= 1u << t;
+                    }
+                }
+            }
+            append(mask, rank);
+        };
+        gather_slices(sh.g, S, 0, kSlices, visit, [] {});
+    }
+    __syncthreads();
+
+    // wave w writes the lists of quadrant w's tiles
+    char* bb = reinterpret_cast<char*>(A.bins);
+    const int shift = bucket_shift(A.n);
+    for (int d = 0; d < 4; ++d) {
+        const int t = 4 * w + d;
+        int64_t tile;
+        if (!block_tile_of(b, t, A.ntx, A.nty, tile)) continue;
+        const uint32_t cnt = sh.tcnt[t];
+        const bool keep = cnt <= uint32_t(A.depth);
+        if (keep) {
+            uint32_t* out = reinterpret_cast<uint32_t*>(bb + 256 + align256(A.ntiles * 4)) + tile * A.depth;
+            bucket_sort_wave(lists + t * lcap, cnt, sh.g.bk[w], shift, out);
+        }
+        if (lane == 0) {
+            reinterpret_cast<uint32_t*>(bb + 256)[tile] = cnt;
+            if (!keep) atomicAdd(A.status, 1u);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bin_block(BinArgs A) { bin_block(A, xcd_remap(blockIdx.x, gridDim.x)); }
+
+// Automatic binner shape: 32x32 blocks for list capacities up to
+// kBlockMaxCap and launches of at least kBlockMinGrid blocks (a single small
+// view leaves too few workgroups for the longer block-sized ones).
+constexpr int32_t kBlockMaxCap = 256;
+constexpr int64_t kBlockMinGrid = 8192;
+
+inline bool use_blocks(int32_t lds_cap, int64_t nblk, uint32_t flags) {
+    if (flags & VSR_BIN_BLOCKS) return true;
+    if (flags & VSR_BIN_SUPERTILES) return false;
+    return lds_cap <= kBlockMaxCap && nblk >= kBlockMinGrid;
+}
+
 __global__ __launch_bounds__(64) void k_zero_u32(uint32_t* p, int64_t n) {
     int64_t i = int64_t(blockIdx.x) * 64 + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -88,7 +253,7 @@ inline int32_t bin_lds_cap(int32_t depth) {
 inline int64_t bin_grid(int32_t ntx, int32_t nty) { return int64_t((ntx + 1) / 2) * ((nty + 1) / 2); }
 
 hipError_t launch_bin(const void* map, int32_t W, int32_t H, int32_t fmt, const Rot& R, const void* setup, int64_t n,
-                      int32_t depth, bool all, void* bins, hipStream_t st) {
+                      int32_t depth, uint32_t flags, void* bins, hipStream_t st) {
     MapLayout ML = map_layout(W, H, fmt);
     BinArgs A;
     A.map = map;
@@ -96,7 +261,7 @@ hipError_t launch_bin(const void* map, int32_t W, int32_t H, int32_t fmt, const 
     A.fmt = fmt;
     A.depth = depth;
     A.lds_cap = bin_lds_cap(depth);
-    A.all = all ? 1 : 0;
+    A.all = (flags & VSR_BIN_ALL) ? 1 : 0;
     A.ntx = ML.ntx;
     A.nty = ML.nty;
     A.setup = setup;
@@ -105,8 +270,11 @@ hipError_t launch_bin(const void* map, int32_t W, int32_t H, int32_t fmt, const 
     A.status = reinterpret_cast<uint32_t*>(bins);
     A.rot = R;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(bins), int64_t(64));
-    hipLaunchKernelGGL(k_bin, dim3(unsigned(bin_grid(ML.ntx, ML.nty))), dim3(256),
-                       size_t(kSupTiles) * A.lds_cap * 4, st, A);
+    if (use_blocks(A.lds_cap, ML.nblk, flags))
+        hipLaunchKernelGGL(k_bin_block, dim3(unsigned(ML.nblk)), dim3(256), size_t(kBlkTiles) * A.lds_cap * 4, st, A);
+    else
+        hipLaunchKernelGGL(k_bin, dim3(unsigned(bin_grid(ML.ntx, ML.nty))), dim3(256),
+                           size_t(kSupTiles) * A.lds_cap * 4, st, A);
     return hipGetLastError();
 }
 

@@ -59,6 +59,12 @@ __device__ inline void fused_super(const FusedArgs& A, int64_t sidx) {
     __syncthreads();
 
     unsigned long long n_tri = 0, n_cov = 0;  // unused counters of raster_list
+    float4 tc0[kSupTiles], tc1[kSupTiles];
+#pragma unroll
+    for (int q = 0; q < kSupTiles; ++q) {
+        tc0[q] = sh.cap[q][0];
+        tc1[q] = sh.cap[q][1];
+    }
     float4* stg = stage[w];
     uint32_t* my = lists[w];
     uint32_t* scr = A.scratch + (present ? tile : 0) * kFusedCap;
@@ -90,7 +96,17 @@ __device__ inline void fused_super(const FusedArgs& A, int64_t sidx) {
             }
             __syncthreads();
         };
-        gather_slices(sh, S, s0, s1, live, append, chunk_end);
+        auto visit = [&](bool valid, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t rank) {
+            uint32_t mask = 0;
+            if (valid) {
+#pragma unroll
+                for (int q = 0; q < kSupTiles; ++q)
+                    if ((live >> q) & 1u)
+                        if (sub_may_see(tc0[q], tc1[q], a, ch_t, n0, n1, n2)) mask |= 1u << q;
+            }
+            if (mask) append(mask, rank);
+        };
+        gather_slices(sh, S, s0, s1, visit, chunk_end);
         const uint32_t c = sh.cnt[w];
         if (!done && c > 0) {
             bucket_sort_wave(my, c, sh.bk[w], shift, scr);

@@ -247,32 +247,12 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wsum, ui
     return base + x - v;
 }
 
-// Loads the four tile caps and the super-tile cap (rotated to the world
-// frame) and the per-slice face counts, and computes the cell rectangles of
-// every (level, face).  All threads of the block call it.  Angles are never
-// formed: caps carry sin and cos of their half radius, and radii add
-// through the angle-sum identities.
-__device__ inline void super_setup(SuperShared& sh, const float4* caps, const float4* sups, const Rot& R,
-                                   const uint32_t* face_count, bool present, int64_t tile, int64_t sidx) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (lane == 0) {
-        float4 c0 = empty_cap0(), c1 = empty_cap1();
-        if (present) load_tile_cap(caps, tile, R, c0, c1);
-        sh.cap[w][0] = c0;
-        sh.cap[w][1] = c1;
-    }
-    if (tid == 64) {
-        float4 s0, s1;
-        load_tile_cap(sups, sidx, R, s0, s1);
-        sh.sup[0] = s0;
-        sh.sup[1] = s1;
-    }
-    sh.fc[tid] = face_count[tid];  // kSlices * 64 == 256 entries
-    if (tid < kSupTiles) {
-        sh.cnt[tid] = 0;
-        sh.flag[tid] = 0;
-    }
-    __syncthreads();
+// Cell rectangles of every (level, face) for the gathering cap sh.sup, and
+// the per-slice face counts.  All threads of the block call it after sh.sup
+// is set (and visible).  Angles are never formed: caps carry sin and cos of
+// their half radius, and radii add through the angle-sum identities.
+__device__ inline void setup_rects(SuperShared& sh) {
+    const int tid = threadIdx.x;
     if (tid < 64) {
         const float4 sup0 = sh.sup[0], sup1 = sh.sup[1];
         int iu0 = 1, iu1 = 0, iv0 = 1, iv1 = 0;
@@ -302,16 +282,46 @@ __device__ inline void super_setup(SuperShared& sh, const float4* caps, const fl
     __syncthreads();
 }
 
-// Streams the candidates of depth slices [s0, s1) through the super-tile
-// tests.  The rows of every (level, face, slice) are flattened into one
-// list so that their cell ranges load and scan in one pass.
-// append(mask, rank) receives every survivor with the set of tiles (bits of
-// live_mask) it may cover; chunk_end() runs after every 256 candidates, by
+
+// Loads the four tile caps and the super-tile cap (rotated to the world
+// frame) and the per-slice face counts, then the cell rectangles.  All
+// threads of the block call it.
+__device__ inline void super_setup(SuperShared& sh, const float4* caps, const float4* sups, const Rot& R,
+                                   const uint32_t* face_count, bool present, int64_t tile, int64_t sidx) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (lane == 0) {
+        float4 c0 = empty_cap0(), c1 = empty_cap1();
+        if (present) load_tile_cap(caps, tile, R, c0, c1);
+        sh.cap[w][0] = c0;
+        sh.cap[w][1] = c1;
+    }
+    if (tid == 64) {
+        float4 s0, s1;
+        load_tile_cap(sups, sidx, R, s0, s1);
+        sh.sup[0] = s0;
+        sh.sup[1] = s1;
+    }
+    sh.fc[tid] = face_count[tid];  // kSlices * 64 == 256 entries
+    if (tid < kSupTiles) {
+        sh.cnt[tid] = 0;
+        sh.flag[tid] = 0;
+    }
+    __syncthreads();
+    setup_rects(sh);
+}
+
+// Streams the candidates of depth slices [s0, s1) through the test against
+// the gathering cap sh.sup.  The rows of every (level, face, slice) are
+// flattened into one list so that their cell ranges load and scan in one
+// pass.  visit(valid, a, ch_t, n0, n1, n2, rank) is called by every thread
+// for each 256 survivors (valid false on idle threads), with the survivor's
+// binning record a, bin_cos_half(a), unit edge normals and rank; it tests
+// the caller's tiles and appends.  chunk_end() runs after each such call, by
 // all threads (a point where the caller may synchronise).  All threads of
 // the block call this with the same arguments.
-template <typename Append, typename ChunkEnd>
-__device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0, int s1, uint32_t live_mask,
-                                     Append&& append, ChunkEnd&& chunk_end) {
+template <typename Visit, typename ChunkEnd>
+__device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0, int s1, Visit&& visit,
+                                     ChunkEnd&& chunk_end) {
     const int tid = threadIdx.x;
     const float4 sup0 = sh.sup[0], sup1 = sh.sup[1];
     const float3 cs = f3(sup0.x, sup0.y, sup0.z);
@@ -337,12 +347,6 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
         if (tid == 63) sh.ppre[64] = x;
     }
     __syncthreads();
-    float4 tc0[kSupTiles], tc1[kSupTiles];
-#pragma unroll
-    for (int q = 0; q < kSupTiles; ++q) {
-        tc0[q] = sh.cap[q][0];
-        tc1[q] = sh.cap[q][1];
-    }
     const uint32_t nrows_all = sh.ppre[64];
     uint32_t* const pass_list = &sh.bk[0][0];  // free while gathering
     for (uint32_t rb = 0; rb < nrows_all; rb += 256) {
@@ -414,22 +418,19 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
             const uint32_t npass = sh.npass;
             __syncthreads();
             if (tid == 0) sh.npass = 0;  // next block's count; ordered by the syncs below
-            // stage 2: edge-plane tests of the survivors against the four tiles
+            // stage 2: the caller's tile tests on the survivors
             for (uint32_t c0 = 0; c0 < npass; c0 += 256) {
-                if (c0 + uint32_t(tid) < npass) {
+                const bool valid = c0 + uint32_t(tid) < npass;
+                float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f), b4 = a4, c4 = a4, d4 = a4;
+                if (valid) {
                     const uint32_t p = pass_list[c0 + tid];
-                    const float4 a4 = S.bincap[p];
-                    const float4 b4 = S.binnrm[3 * int64_t(p)], c4 = S.binnrm[3 * int64_t(p) + 1],
-                                 d4 = S.binnrm[3 * int64_t(p) + 2];
-                    float3 n0 = f3(b4.x, b4.y, b4.z), n1 = f3(c4.x, c4.y, c4.z), n2 = f3(d4.x, d4.y, d4.z);
-                    const float ch_t = bin_cos_half(a4);
-                    uint32_t mask = 0;
-#pragma unroll
-                    for (int q = 0; q < kSupTiles; ++q)
-                        if ((live_mask >> q) & 1u)
-                            if (sub_may_see(tc0[q], tc1[q], a4, ch_t, n0, n1, n2)) mask |= 1u << q;
-                    if (mask) append(mask, __float_as_uint(b4.w));
+                    a4 = S.bincap[p];
+                    b4 = S.binnrm[3 * int64_t(p)];
+                    c4 = S.binnrm[3 * int64_t(p) + 1];
+                    d4 = S.binnrm[3 * int64_t(p) + 2];
                 }
+                visit(valid, a4, bin_cos_half(a4), f3(b4.x, b4.y, b4.z), f3(c4.x, c4.y, c4.z), f3(d4.x, d4.y, d4.z),
+                      __float_as_uint(b4.w));
                 chunk_end();
             }
             __syncthreads();

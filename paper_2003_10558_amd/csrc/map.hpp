@@ -8,8 +8,9 @@
 // tile's bounding cap: the normalised mean direction and the largest chord
 // to it, widened by a safety margin.
 //
-// Each 16x16 super-tile also gets a cap bounding its four tile caps (used by
-// the binner).
+// Each 16x16 super-tile also gets a cap bounding its four tile caps, and
+// each 32x32 block one bounding its four super-tile caps (used by the
+// binner).
 //
 // The map depends only on the lens (size, angle of view, k, l, s, Omega): as
 // in the paper, where the vector map is computed once and kept as a texture,
@@ -174,6 +175,36 @@ __global__ __launch_bounds__(256) void k_build_map(MapParams P, void* map, int64
     build_map_super(P, map, ntiles, blockIdx.x);
 }
 
+// Cap of 32x32 block b (2x2 super-tiles) from its super-tile caps; one
+// thread per block, after the map kernel.
+__device__ inline void block_cap(void* map, int64_t ntiles, int32_t fmt, int32_t ntx, int32_t nty, int64_t b) {
+    const int nsx = (ntx + 1) / 2, nsy = (nty + 1) / 2, nbx = (ntx + 3) / 4;
+    const int bx = int(b % nbx), by = int(b / nbx);
+    const float4* sups = map_sups(map, ntiles, fmt);
+    float4 ch[4][2];
+    for (int q = 0; q < 4; ++q) {
+        const int sx = 2 * bx + (q & 1), sy = 2 * by + (q >> 1);
+        if (sx < nsx && sy < nsy) {
+            const int64_t si = int64_t(sy) * nsx + sx;
+            sup_as_child(sups[2 * si], sups[2 * si + 1], ch[q][0], ch[q][1]);
+        } else {
+            ch[q][0] = make_float4(0.f, 0.f, 1.f, 0.f);
+            ch[q][1] = make_float4(1.f, 0.f, kCapEmpty, 0.f);
+        }
+    }
+    float4 b0, b1;
+    super_cap_of(ch, b0, b1);
+    float4* blks = const_cast<float4*>(map_blks(map, ntiles, fmt, ntx, nty));
+    blks[2 * b] = b0;
+    blks[2 * b + 1] = b1;
+}
+
+__global__ __launch_bounds__(64) void k_block_caps(void* map, int64_t ntiles, int32_t fmt, int32_t ntx, int32_t nty,
+                                                   int64_t nblk) {
+    const int64_t b = int64_t(blockIdx.x) * 64 + threadIdx.x;
+    if (b < nblk) block_cap(map, ntiles, fmt, ntx, nty, b);
+}
+
 __global__ __launch_bounds__(256) void k_map_unpack(const void* map, int32_t fmt, int64_t ntiles, int32_t ntx,
                                                     int32_t W, int32_t H, Rot R, float* out) {
     int lane = threadIdx.x & 63;
@@ -200,6 +231,8 @@ hipError_t launch_map_unpack(const void* map, int32_t W, int32_t H, int32_t fmt,
 hipError_t launch_build_map(const MapParams& P, void* map, hipStream_t stream) {
     MapLayout L = map_layout(P.W, P.H, P.fmt);
     hipLaunchKernelGGL(k_build_map, dim3(unsigned(L.nsup)), dim3(256), 0, stream, P, map, L.ntiles);
+    hipLaunchKernelGGL(k_block_caps, dim3(unsigned((L.nblk + 63) / 64)), dim3(64), 0, stream, map, L.ntiles, P.fmt,
+                       L.ntx, L.nty, L.nblk);
     return hipGetLastError();
 }
 

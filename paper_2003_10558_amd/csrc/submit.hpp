@@ -41,6 +41,8 @@ struct JobDesc {
     int64_t ntiles;
     int64_t stile_off;  // first global super-tile (binning) of this job
     int64_t msup_off;   // first global map super-tile of this job's map (if it builds it)
+    int64_t mblk_off;   // first global map block of this job's map (if it builds it)
+    int64_t blk_off;    // first global 32x32 block (binning) of this job
     int32_t ntx, nty;
     int32_t map_owner;  // 1: this job builds the map it uses
     int32_t pad;
@@ -104,6 +106,51 @@ __device__ inline int find_job_super(const JobDesc* __restrict__ T, int njobs, i
             hi = mid - 1;
     }
     return lo;
+}
+
+// Last job whose range offset (member Off) is <= t.  Jobs with empty
+// ranges share the next job's offset and are never returned for t < total.
+template <int64_t JobDesc::*Off>
+__device__ inline int find_off(const JobDesc* __restrict__ T, int njobs, int64_t t) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (T[mid].*Off <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_submit_bin_block(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
+                                                          int32_t depth, int32_t lds_cap, uint32_t* status) {
+    int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    int jb = find_off<&JobDesc::blk_off>(T, njobs, t);
+    const JobDesc& J = T[jb];
+    BinArgs A;
+    A.map = J.map;
+    A.ntiles = J.ntiles;
+    A.fmt = fmt;
+    A.depth = depth;
+    A.lds_cap = lds_cap;
+    A.all = 0;
+    A.ntx = J.ntx;
+    A.nty = J.nty;
+    A.setup = J.setup;
+    A.n = J.ntri;
+    A.bins = J.bins;
+    A.status = status;
+    A.rot = rot_of(J.P.rot);
+    bin_block(A, t - J.blk_off);
+}
+
+__global__ __launch_bounds__(64) void k_submit_block_caps(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
+                                                          int64_t total) {
+    const int64_t t = int64_t(blockIdx.x) * 64 + threadIdx.x;
+    if (t >= total) return;
+    const JobDesc& J = T[find_off<&JobDesc::mblk_off>(T, njobs, t)];
+    block_cap(J.map, J.ntiles, fmt, J.ntx, J.nty, t - J.mblk_off);
 }
 
 __global__ __launch_bounds__(256) void k_submit_bin(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
@@ -203,10 +250,11 @@ __global__ __launch_bounds__(256) void k_submit_map(const JobDesc* __restrict__ 
 // tiles, super-tiles and map super-tiles through the pointers.  With share_maps,
 // jobs with the same lens use the first such job's map.
 static void build_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth, void* ws,
-                        bool share_maps, JobDesc* out, int64_t* n_tiles, int64_t* n_stiles, int64_t* n_mtiles) {
+                        bool share_maps, JobDesc* out, int64_t* n_tiles, int64_t* n_stiles, int64_t* n_mtiles,
+                        int64_t* n_blks, int64_t* n_mblks) {
     WsLayout W = ws_layout(njobs);
     char* base = reinterpret_cast<char*>(ws);
-    int64_t off = W.data_off, tiles = 0, stiles = 0, mtiles = 0;
+    int64_t off = W.data_off, tiles = 0, stiles = 0, mtiles = 0, blks = 0, mblks = 0;
     std::map<std::array<uint32_t, 7>, int32_t> lens;
     auto bits = [](float f) {
         uint32_t u;
@@ -222,6 +270,7 @@ static void build_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t
                                              bits(eff.k), bits(eff.l), bits(eff.s), bits(eff.omega_deg)};
         auto it = share_maps ? lens.find(key) : lens.end();
         D.msup_off = mtiles;
+        D.mblk_off = mblks;
         if (it != lens.end()) {
             D.map = out[it->second].map;
             D.map_owner = 0;
@@ -230,6 +279,7 @@ static void build_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t
             off += ML.bytes;
             D.map_owner = 1;
             mtiles += ML.nsup;
+            mblks += ML.nblk;
             if (share_maps) lens.emplace(key, q);
         }
         D.pad = 0;
@@ -239,6 +289,8 @@ static void build_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t
         D.nty = ML.nty;
         D.stile_off = stiles;
         stiles += bin_grid(ML.ntx, ML.nty);
+        D.blk_off = blks;
+        blks += ML.nblk;
         D.setup = jobs[q].setup;
         D.ntri = jobs[q].ntri;
         D.tri_id = jobs[q].tri_id;
@@ -250,6 +302,8 @@ static void build_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t
     *n_tiles = tiles;
     *n_stiles = stiles;
     *n_mtiles = mtiles;
+    *n_blks = blks;
+    *n_mblks = mblks;
 }
 
 int64_t submit_table_bytes(int32_t njobs) { return int64_t(njobs) * int64_t(sizeof(JobDesc)); }
@@ -257,22 +311,23 @@ int64_t submit_table_bytes(int32_t njobs) { return int64_t(njobs) * int64_t(size
 // Host image of the job table that vsr_submit would write into `ws`.
 void submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth, void* ws,
                   void* host) {
-    int64_t t, s, m;
-    build_table(jobs, njobs, fmt, mode, depth, ws, false, reinterpret_cast<JobDesc*>(host), &t, &s, &m);
+    int64_t t, s, m, b, mb;
+    build_table(jobs, njobs, fmt, mode, depth, ws, false, reinterpret_cast<JobDesc*>(host), &t, &s, &m, &b, &mb);
 }
 
 int64_t submit_table_offset() { return ws_layout(1).table_off; }
 
 hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth, void* ws,
-                         bool table_ready, hipStream_t st) {
+                         bool table_ready, uint32_t shape, hipStream_t st) {
     WsLayout W = ws_layout(njobs);
     char* base = reinterpret_cast<char*>(ws);
     JobDesc* table = reinterpret_cast<JobDesc*>(base + W.table_off);
     std::vector<JobDesc> host(njobs);
-    int64_t tiles = 0, stiles = 0, mtiles = 0;
+    int64_t tiles = 0, stiles = 0, mtiles = 0, blks = 0, mblks = 0;
     // a prewritten table (graph replays) never shares maps, so the grids
     // sized here fit any table written for jobs of the same sizes
-    build_table(jobs, njobs, fmt, mode, depth, ws, !table_ready, host.data(), &tiles, &stiles, &mtiles);
+    build_table(jobs, njobs, fmt, mode, depth, ws, !table_ready, host.data(), &tiles, &stiles, &mtiles, &blks,
+                &mblks);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ws), int64_t(64));
     if (!table_ready) {
         // descriptors travel as kernel arguments: no host-memory copy
@@ -285,12 +340,19 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
         }
     }
     if (mtiles > 0) hipLaunchKernelGGL(k_submit_map, dim3(unsigned(mtiles)), dim3(256), 0, st, table, njobs);
+    if (mblks > 0)
+        hipLaunchKernelGGL(k_submit_block_caps, dim3(unsigned((mblks + 63) / 64)), dim3(64), 0, st, table, njobs, fmt,
+                           mblks);
     if (mode == VSR_SUBMIT_FUSED) {
         hipLaunchKernelGGL(k_submit_fused, dim3(unsigned(stiles)), dim3(256), 0, st, table, njobs, fmt);
     } else {
         int32_t cap = bin_lds_cap(depth);
-        hipLaunchKernelGGL(k_submit_bin, dim3(unsigned(stiles)), dim3(256), size_t(kSupTiles) * cap * 4, st, table,
-                           njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
+        if (use_blocks(cap, blks, shape))
+            hipLaunchKernelGGL(k_submit_bin_block, dim3(unsigned(blks)), dim3(256), size_t(kBlkTiles) * cap * 4, st,
+                               table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
+        else
+            hipLaunchKernelGGL(k_submit_bin, dim3(unsigned(stiles)), dim3(256), size_t(kSupTiles) * cap * 4, st,
+                               table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
         hipLaunchKernelGGL(k_submit_raster, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, fmt,
                            depth, tiles);
     }

@@ -60,9 +60,11 @@ struct MapLayout {
     int32_t ntx, nty;
     int64_t ntiles;
     int64_t nsup;         // 16x16 super-tiles (2x2 tiles), row-major over ((ntx+1)/2) x ((nty+1)/2)
+    int64_t nblk;         // 32x32 blocks (4x4 tiles), row-major over ((ntx+3)/4) x ((nty+3)/4)
     int64_t plane_bytes;  // all pixel data
     int64_t caps_off;     // float4 x 2 per tile
     int64_t sups_off;     // float4 x 2 per super-tile
+    int64_t blks_off;     // float4 x 2 per block
     int64_t bytes;
 };
 
@@ -74,8 +76,10 @@ __host__ __device__ inline MapLayout map_layout(int32_t w, int32_t h, int32_t fm
     m.nsup = int64_t((m.ntx + 1) / 2) * ((m.nty + 1) / 2);
     m.plane_bytes = m.ntiles * kTilePix * (fmt == VSR_MAP_OCT16 ? 4 : 12);
     m.caps_off = align256(m.plane_bytes);
+    m.nblk = int64_t((m.ntx + 3) / 4) * ((m.nty + 3) / 4);
     m.sups_off = m.caps_off + align256(m.ntiles * 32);
-    m.bytes = m.sups_off + align256(m.nsup * 32);
+    m.blks_off = m.sups_off + align256(m.nsup * 32);
+    m.bytes = m.blks_off + align256(m.nblk * 32);
     return m;
 }
 
@@ -262,6 +266,15 @@ __host__ __device__ inline const float4* map_sups(const void* map, int64_t ntile
                                            align256(ntiles * 32));
 }
 
+// Block caps of a map buffer (2 x float4 per 32x32 block, after the
+// super-tile caps).
+__host__ __device__ inline const float4* map_blks(const void* map, int64_t ntiles, int32_t fmt, int32_t ntx,
+                                                  int32_t nty) {
+    const int64_t nsup = int64_t((ntx + 1) / 2) * ((nty + 1) / 2);
+    return reinterpret_cast<const float4*>(reinterpret_cast<const char*>(map_sups(map, ntiles, fmt)) +
+                                           align256(nsup * 32));
+}
+
 // Camera -> world rotation of a view (row-major), applied to the camera-frame
 // map: the map depends only on the lens (size, AOV, k, l, s, Omega), so one
 // map serves every orientation.
@@ -406,6 +419,14 @@ __device__ inline void super_cap_of(const float4 (&cap)[4][2], float4& sup0, flo
     }
     sup0 = make_float4(c.x, c.y, c.z, sh_);
     sup1 = make_float4(sh_, ch_, any0 ? 1.0f : 0.0f, wide0 ? 1.0f : 0.0f);
+}
+
+// A super-tile cap (sup0, sup1 as written by super_cap_of) in the tile-cap
+// layout that super_cap_of reads for its children.
+__device__ inline void sup_as_child(float4 sup0, float4 sup1, float4& c0, float4& c1) {
+    c0 = sup0;
+    const float flag = sup1.z == 0.0f ? kCapEmpty : (sup1.w != 0.0f ? kCapWide : 0.0f);
+    c1 = make_float4(sup1.y, 2.0f * sup1.x * sup1.y, flag, 0.0f);
 }
 
 }  // namespace vsr

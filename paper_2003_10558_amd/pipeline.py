@@ -13,7 +13,7 @@ import torch
 
 from . import vsr
 
-DEFAULT_BIN_DEPTH = 1024
+DEFAULT_BIN_DEPTH = 256
 
 
 def _buffer(nbytes: int, device) -> torch.Tensor:

@@ -19,9 +19,11 @@ VSR_OK, VSR_E_ARG, VSR_E_SPACE, VSR_E_RANGE, VSR_E_HIP = 0, -1, -2, -3, -4
 VSR_MAP_F32, VSR_MAP_OCT16 = 0, 1
 VSR_STRICT = 1
 VSR_BIN_ALL = 1
+VSR_BIN_BLOCKS, VSR_BIN_SUPERTILES = 2, 4
 VSR_NO_HIT = 0xFFFFFFFF
 VSR_SUBMIT_BINNED, VSR_SUBMIT_FUSED = 0, 1
 VSR_SUBMIT_TABLE_READY = 0x100
+VSR_SUBMIT_BIN_BLOCKS, VSR_SUBMIT_BIN_SUPERTILES = 0x200, 0x400
 VSR_TILE = 8
 VSR_AOV_HORIZONTAL, VSR_AOV_DIAGONAL, VSR_AOV_VERTICAL, VSR_AOV_HORIZONTAL_4X3 = 0, 1, 2, 3
 

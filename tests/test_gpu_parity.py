@@ -106,11 +106,12 @@ def test_binning_is_exact(gpu):
                              ("rot", synth.View(200, 150, -0.4, 0.3, 0.9, 300.0, 0, synth.yaw_pitch_rotation(1.0, 0.3)),
                               synth.scene(700, 17))]:
         _say(f"[bin-exact] {name}")
-        a_ids, a_dep, _ = _render(gpu, tris, view)
         b_ids, b_dep, ovf = _render(gpu, tris, view, depth=2048, flags=1)
         assert ovf == 0
-        assert np.array_equal(a_ids, b_ids)
-        assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
+        for depth, shape in ((1024, 0), (256, 2), (256, 4)):  # automatic, 32x32 blocks, 16x16 super-tiles
+            a_ids, a_dep, _ = _render(gpu, tris, view, depth=depth, flags=shape)
+            assert np.array_equal(a_ids, b_ids), shape
+            assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32)), shape
 
 
 @pytest.mark.parametrize("seed", list(range(6)))
@@ -120,11 +121,12 @@ def test_binning_is_exact_random_views(gpu, seed):
     views = synth.random_views(4, 500 + seed, resolutions=((200, 150), (96, 96), (311, 97)))
     tris = synth.scene(700, 600 + seed)
     for v in views:
-        a_ids, a_dep, _ = _render(gpu, tris, v)
         b_ids, b_dep, ovf = _render(gpu, tris, v, depth=2048, flags=1)
         assert ovf == 0
-        assert np.array_equal(a_ids, b_ids), (v.k, v.omega_deg)
-        assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
+        for shape in (2, 4):  # 32x32 blocks, 16x16 super-tiles
+            a_ids, a_dep, _ = _render(gpu, tris, v, depth=256, flags=shape)
+            assert np.array_equal(a_ids, b_ids), (v.k, v.omega_deg, shape)
+            assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
 
 
 RAGGED = [
@@ -186,7 +188,7 @@ def test_overflow_falls_back(gpu):
     assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
 
 
-@pytest.mark.parametrize("mode", [0, 1], ids=["binned", "fused"])
+@pytest.mark.parametrize("mode", [0x200, 0x400, 1], ids=["binned-blocks", "binned-supertiles", "fused"])
 def test_submit_matches_single_views(gpu, mode):
     torch, pipeline, vsr = gpu
     tris = synth.scene(3000, 23)
@@ -233,8 +235,9 @@ def test_map_is_orientation_free(gpu, fmt):
     # render vb through va's map
     ids = torch.empty_like(fb.tri_id)
     dep = torch.empty_like(fb.depth)
-    vsr.vsr_bin(vb, fmt, fa.map, scene.setup, scene.ntri, 1024, 0, fa.bins)
-    vsr.vsr_raster(vb, fmt, fa.map, scene.setup, scene.ntri, fa.bins, 1024, ids, dep)
+    depth = pipeline.DEFAULT_BIN_DEPTH
+    vsr.vsr_bin(vb, fmt, fa.map, scene.setup, scene.ntri, depth, 0, fa.bins)
+    vsr.vsr_raster(vb, fmt, fa.map, scene.setup, scene.ntri, fa.bins, depth, ids, dep)
     torch.cuda.synchronize()
     assert torch.equal(ids, fb.tri_id)
     assert np.array_equal(dep.cpu().numpy().view(np.uint32), fb.depth.cpu().numpy().view(np.uint32))
@@ -244,7 +247,7 @@ def test_map_is_orientation_free(gpu, fmt):
         assert st.ok(), st.notes
 
 
-@pytest.mark.parametrize("mode", [0, 1], ids=["binned", "fused"])
+@pytest.mark.parametrize("mode", [0x200, 0x400, 1], ids=["binned-blocks", "binned-supertiles", "fused"])
 def test_submit_shares_lens_maps(gpu, mode):
     """A batch whose views repeat lenses in several orientations (maps built
     once per lens) renders every view exactly as alone."""

@@ -35,9 +35,10 @@ def test_exports_every_declared_symbol(vsr):
 
 
 def test_sizes(vsr):
-    # 256x256: 1024 tiles of 64 pixels, 12 B/px, + 32 B of cap per tile
-    assert vsr.vsr_map_bytes(256, 256, vsr.VSR_MAP_F32) == 1024 * 64 * 12 + 1024 * 32 + 256 * 32
-    assert vsr.vsr_map_bytes(256, 256, vsr.VSR_MAP_OCT16) == 1024 * 64 * 4 + 1024 * 32 + 256 * 32
+    # 256x256: 1024 tiles of 64 pixels, 12 B/px, + 32 B of cap per tile, per
+    # 16x16 super-tile (256) and per 32x32 block (64)
+    assert vsr.vsr_map_bytes(256, 256, vsr.VSR_MAP_F32) == 1024 * 64 * 12 + 1024 * 32 + 256 * 32 + 64 * 32
+    assert vsr.vsr_map_bytes(256, 256, vsr.VSR_MAP_OCT16) == 1024 * 64 * 4 + 1024 * 32 + 256 * 32 + 64 * 32
     # ragged: 9x9 -> 2x2 tiles
     assert vsr.vsr_map_bytes(9, 9, vsr.VSR_MAP_F32) >= 4 * 64 * 12 + 4 * 32
     assert vsr.vsr_bin_bytes(16, 16, 100) >= 256 + 4 * 4 + 4 * 100 * 4
