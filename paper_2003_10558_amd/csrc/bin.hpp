@@ -78,7 +78,10 @@ __device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
             }
             if (mask) append(mask, rank);
         };
-        gather_slices(sh, S, 0, kSlices, visit, [] {});
+        gather_slices(sh, S, 0, kSlices, [&](const uint32_t* chunk, uint32_t n) {
+            const bool valid = uint32_t(threadIdx.x) < n;
+            visit_record(S, valid, valid ? chunk[threadIdx.x] : 0u, visit);
+        }, [] {});
     }
     __syncthreads();
 
@@ -106,6 +109,8 @@ struct BlockShared {
     float4 tcap[kBlkTiles][2];    // tile caps, tile 4q + (2 dy + dx) of quadrant q
     float4 qcap[4][2];            // quadrant (super-tile) caps, super-tile layout
     uint32_t tcnt[kBlkTiles];
+    uint32_t qn[4];               // survivors of the current chunk that may meet quadrant q ...
+    uint32_t ql[4][256];          // ... and their cell-ordered positions
 };
 
 // Tile (tx, ty) of slot t (quadrant t >> 2) of block b; false outside the map.
@@ -184,24 +189,57 @@ __device__ inline void bin_block(const BinArgs& A, int64_t b) {
             if (r < A.n && S.cap[2 * r + 1].z != kCapEmpty) append(live, uint32_t(r));
         }
     } else if (any) {
-        auto visit = [&](bool valid, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t rank) {
-            uint32_t mask = 0;
-            if (valid) {
-                // caps are read from LDS in the loops (not unrolled, so they
-                // are not hoisted into registers)
-#pragma unroll 1
-                for (int q = 0; q < 4; ++q) {
-                    if (!quad_may_see(sh.qcap[q][0], sh.qcap[q][1], a, ch_t, n0, n1, n2)) continue;
-#pragma unroll 1
-                    for (int d = 0; d < 4; ++d) {
-                        const int t = 4 * q + d;
-                        if (sub_may_see(sh.tcap[t][0], sh.tcap[t][1], a, ch_t, n0, n1, n2)) mask |= 1u << t;
-                    }
-                }
+        // Each chunk of survivors: every thread tests one survivor against
+        // the four quadrant caps and files it in the lists of the quadrants
+        // it may meet; then wave w tests quadrant w's list against its four
+        // tiles.  A wave owns its tiles' counters, so it appends with ballots.
+        if (tid < 4) sh.qn[tid] = 0;
+        __syncthreads();
+        auto visit_chunk = [&](const uint32_t* chunk, uint32_t n) {
+            if (uint32_t(tid) < n) {
+                const uint32_t p = chunk[tid];
+                visit_record(S, true, p, [&](bool, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (quad_may_see(sh.qcap[q][0], sh.qcap[q][1], a, ch_t, n0, n1, n2))
+                            sh.ql[q][atomicAdd(&sh.qn[q], 1u)] = p;
+                });
             }
-            append(mask, rank);
+            __syncthreads();
+            const uint32_t m = sh.qn[w];
+            float4 tc0[4], tc1[4];
+            uint32_t tn[4];  // the wave's tile counts, kept identical in every lane
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                tc0[d] = sh.tcap[4 * w + d][0];
+                tc1[d] = sh.tcap[4 * w + d][1];
+                tn[d] = sh.tcnt[4 * w + d];
+            }
+            for (uint32_t i0 = 0; i0 < m; i0 += 64) {
+                const bool v = i0 + uint32_t(lane) < m;
+                visit_record(S, v, v ? sh.ql[w][i0 + lane] : 0u,
+                             [&](bool valid, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t rank) {
+#pragma unroll
+                                 for (int d = 0; d < 4; ++d) {
+                                     const int t = 4 * w + d;
+                                     const bool on = valid && sub_may_see(tc0[d], tc1[d], a, ch_t, n0, n1, n2);
+                                     const uint64_t bal = __ballot(on);
+                                     const uint32_t pos = tn[d] + __builtin_amdgcn_mbcnt_hi(
+                                                                      uint32_t(bal >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
+                                     if (on && pos < lcap) lists[t * lcap + pos] = rank;
+                                     tn[d] += uint32_t(__popcll(bal));
+                                 }
+                             });
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int d = 0; d < 4; ++d) sh.tcnt[4 * w + d] = tn[d];
+                sh.qn[w] = 0;  // read by this wave only; the next chunk starts after a barrier
+            }
+            __syncthreads();
         };
-        gather_slices(sh.g, S, 0, kSlices, visit, [] {});
+        gather_slices(sh.g, S, 0, kSlices, visit_chunk, [] {});
     }
     __syncthreads();
 

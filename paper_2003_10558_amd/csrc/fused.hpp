@@ -106,7 +106,10 @@ __device__ inline void fused_super(const FusedArgs& A, int64_t sidx) {
             }
             if (mask) append(mask, rank);
         };
-        gather_slices(sh, S, s0, s1, visit, chunk_end);
+        gather_slices(sh, S, s0, s1, [&](const uint32_t* chunk, uint32_t n) {
+            const bool valid = uint32_t(threadIdx.x) < n;
+            visit_record(S, valid, valid ? chunk[threadIdx.x] : 0u, visit);
+        }, chunk_end);
         const uint32_t c = sh.cnt[w];
         if (!done && c > 0) {
             bucket_sort_wave(my, c, sh.bk[w], shift, scr);

@@ -310,17 +310,31 @@ __device__ inline void super_setup(SuperShared& sh, const float4* caps, const fl
     setup_rects(sh);
 }
 
+// Binning record of survivor `p` (cell-ordered position) for thread-level
+// tests: visit(valid, a, bin_cos_half(a), n0, n1, n2, rank).
+template <typename Visit>
+__device__ inline void visit_record(const SceneView& S, bool valid, uint32_t p, Visit&& visit) {
+    float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f), b4 = a4, c4 = a4, d4 = a4;
+    if (valid) {
+        a4 = S.bincap[p];
+        b4 = S.binnrm[3 * int64_t(p)];
+        c4 = S.binnrm[3 * int64_t(p) + 1];
+        d4 = S.binnrm[3 * int64_t(p) + 2];
+    }
+    visit(valid, a4, bin_cos_half(a4), f3(b4.x, b4.y, b4.z), f3(c4.x, c4.y, c4.z), f3(d4.x, d4.y, d4.z),
+          __float_as_uint(b4.w));
+}
+
 // Streams the candidates of depth slices [s0, s1) through the test against
 // the gathering cap sh.sup.  The rows of every (level, face, slice) are
 // flattened into one list so that their cell ranges load and scan in one
-// pass.  visit(valid, a, ch_t, n0, n1, n2, rank) is called by every thread
-// for each 256 survivors (valid false on idle threads), with the survivor's
-// binning record a, bin_cos_half(a), unit edge normals and rank; it tests
-// the caller's tiles and appends.  chunk_end() runs after each such call, by
-// all threads (a point where the caller may synchronise).  All threads of
-// the block call this with the same arguments.
-template <typename Visit, typename ChunkEnd>
-__device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0, int s1, Visit&& visit,
+// pass.  visit_chunk(list, n) is called by every thread for each chunk of
+// at most 256 survivors (cell-ordered positions list[0..n)); it tests the
+// caller's tiles and appends.  chunk_end() runs after each such call, by all
+// threads (a point where the caller may synchronise).  All threads of the
+// block call this with the same arguments.
+template <typename VisitChunk, typename ChunkEnd>
+__device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0, int s1, VisitChunk&& visit_chunk,
                                      ChunkEnd&& chunk_end) {
     const int tid = threadIdx.x;
     const float4 sup0 = sh.sup[0], sup1 = sh.sup[1];
@@ -420,17 +434,7 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
             if (tid == 0) sh.npass = 0;  // next block's count; ordered by the syncs below
             // stage 2: the caller's tile tests on the survivors
             for (uint32_t c0 = 0; c0 < npass; c0 += 256) {
-                const bool valid = c0 + uint32_t(tid) < npass;
-                float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f), b4 = a4, c4 = a4, d4 = a4;
-                if (valid) {
-                    const uint32_t p = pass_list[c0 + tid];
-                    a4 = S.bincap[p];
-                    b4 = S.binnrm[3 * int64_t(p)];
-                    c4 = S.binnrm[3 * int64_t(p) + 1];
-                    d4 = S.binnrm[3 * int64_t(p) + 2];
-                }
-                visit(valid, a4, bin_cos_half(a4), f3(b4.x, b4.y, b4.z), f3(c4.x, c4.y, c4.z), f3(d4.x, d4.y, d4.z),
-                      __float_as_uint(b4.w));
+                visit_chunk(pass_list + c0, min(256u, npass - c0));
                 chunk_end();
             }
             __syncthreads();
