@@ -76,6 +76,9 @@ def _load():
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_int32]
             lib.orc_render.restype = ctypes.c_int
+            lib.orc_fragments.argtypes = [ctypes.POINTER(_View), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int64, dp, dp]
             lib.orc_pair.argtypes = [ctypes.POINTER(_View), ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_int64, ctypes.c_int64, dp]
             _lib = lib
@@ -206,3 +209,24 @@ def pair(view, tris: np.ndarray, t: int, p: int):
     cv = _cview(view)
     lib.orc_pair(ctypes.byref(cv), tris.ctypes.data, tris.shape[1], int(t), int(p), _dp(out))
     return out[0:3].copy(), float(out[3]), bool(out[4])
+
+
+def fragments(view, tris: np.ndarray, attr: np.ndarray, pixels: np.ndarray, ids: np.ndarray,
+              normalize3: bool = False):
+    """Section 1.1.4 fragment data of the listed pixels with winners ``ids``:
+    (b [n, 3] barycentric weights of A, B, C; f [n, nattr] interpolated
+    vertex data, attr shaped [3, nattr, T])."""
+    lib = _load()
+    tris = np.ascontiguousarray(tris, dtype=np.float32)
+    attr = np.ascontiguousarray(attr, dtype=np.float32)
+    assert attr.ndim == 3 and attr.shape[0] == 3 and attr.shape[2] == tris.shape[1]
+    nattr = attr.shape[1]
+    pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    n = pixels.shape[0]
+    b = np.zeros((n, 3))
+    f = np.zeros((n, max(nattr, 1)))
+    cv = _cview(view)
+    lib.orc_fragments(ctypes.byref(cv), tris.ctypes.data, tris.shape[1], attr.ctypes.data, nattr,
+                      int(bool(normalize3)), pixels.ctypes.data, ids.ctypes.data, n, _dp(b), _dp(f))
+    return b, f[:, :nattr]

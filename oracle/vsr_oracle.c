@@ -17,6 +17,9 @@
  *            step: 1 iff g > 0).
  *   depth    section 1.1.4 (hard normal N=(A-B)x(C-B); r = A.N / G.N).
  *   resolve  section 1.4 (depth-pass test: the nearest r wins).
+ *   fragment section 1.1.4, second half (barycentric vector of the
+ *            intersection point from triple products with the hard normal;
+ *            vertex data interpolated with it).
  *
  * Readings where the paper is silent or inconsistent (all documented in the
  * design notes):
@@ -450,4 +453,76 @@ void orc_pair(const orc_view *v, const float *xyz_soa, int64_t ntri, int64_t t, 
     out[2] = dot3(tr.n[2], g);
     out[3] = tr.d / dot3(g, tr.N);
     out[4] = ok;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Section 1.1.4, fragment data.  For pixel p and triangle t (its winner),
+ * the intersection point P = r G with r = A.N / G.N, the barycentric vector
+ *   b_s = ((C-P) x (B-P)) . N / (N . N)
+ *   b_t = ((A-P) x (C-P)) . N / (N . N)
+ *   b_p = ((B-P) x (A-P)) . N / (N . N)
+ * (weights of A, B, C) and the vertex data interpolated with it,
+ *   f = b_s A_f + b_t B_f + b_p C_f,
+ * the first three components normalised when normalize3 (the normal pass).
+ * attr holds [3 vertices][nattr][ntri] floats.  A pixel without direction,
+ * t = NO_HIT, a degenerate triangle or G parallel to its plane gives b = 0
+ * and f = 0. */
+static void fragment_one(const orc_view *v, const float *xyz, int64_t ntri, const float *attr, int32_t nattr,
+                         int32_t normalize3, int64_t p, uint32_t t, double b[3], double *f)
+{
+    b[0] = b[1] = b[2] = 0.0;
+    for (int32_t k = 0; k < nattr; ++k)
+        f[k] = 0.0;
+    double g[3];
+    if (t == ORC_NO_HIT || (int64_t)t >= ntri)
+        return;
+    if (!orc_pixel_direction(v, (int32_t)(p % v->width), (int32_t)(p / v->width), g))
+        return;
+    double A[3], B[3], C[3], AmB[3], CmB[3], N[3];
+    load_vertex(xyz, ntri, t, 0, A);
+    load_vertex(xyz, ntri, t, 1, B);
+    load_vertex(xyz, ntri, t, 2, C);
+    for (int r = 0; r < 3; ++r) {
+        AmB[r] = A[r] - B[r];
+        CmB[r] = C[r] - B[r];
+    }
+    cross3(AmB, CmB, N);
+    double nn = dot3(N, N), gn = dot3(g, N);
+    if (nn == 0.0 || gn == 0.0)
+        return;
+    double r = dot3(A, N) / gn;
+    double Pa[3], Pb[3], Pc[3], x[3];
+    for (int q = 0; q < 3; ++q) {
+        Pa[q] = A[q] - r * g[q];
+        Pb[q] = B[q] - r * g[q];
+        Pc[q] = C[q] - r * g[q];
+    }
+    cross3(Pc, Pb, x);
+    b[0] = dot3(x, N) / nn;
+    cross3(Pa, Pc, x);
+    b[1] = dot3(x, N) / nn;
+    cross3(Pb, Pa, x);
+    b[2] = dot3(x, N) / nn;
+    for (int32_t k = 0; k < nattr; ++k) {
+        double fa = attr[(0 * (int64_t)nattr + k) * ntri + t];
+        double fb = attr[(1 * (int64_t)nattr + k) * ntri + t];
+        double fc = attr[(2 * (int64_t)nattr + k) * ntri + t];
+        f[k] = b[0] * fa + b[1] * fb + b[2] * fc;
+    }
+    if (normalize3 && nattr >= 3) {
+        double len = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+        if (len > 0.0)
+            for (int q = 0; q < 3; ++q)
+                f[q] /= len;
+    }
+}
+
+/* Fragment data of the listed pixels (flat indices j*W+i) with winners
+ * ids[q]: out_b[3q..3q+2], out_f[nattr*q ..]. */
+void orc_fragments(const orc_view *v, const float *xyz, int64_t ntri, const float *attr, int32_t nattr,
+                   int32_t normalize3, const int64_t *pix, const uint32_t *ids, int64_t npix, double *out_b,
+                   double *out_f)
+{
+    for (int64_t q = 0; q < npix; ++q)
+        fragment_one(v, xyz, ntri, attr, nattr, normalize3, pix[q], ids[q], out_b + 3 * q, out_f + nattr * q);
 }

@@ -251,6 +251,23 @@ def serve_scenes() -> List[np.ndarray]:
 # Pixel samples for parity at full size
 # ----------------------------------------------------------------------------
 
+def vertex_attributes(n_tri: int, seed: int) -> np.ndarray:
+    """Per-vertex data ``float32[3, 5, T]`` (vertex, attribute, triangle):
+    attributes 0..2 a unit normal per vertex (a random direction per
+    triangle plus a per-vertex random offset of 0.3, renormalised), 3..4 a
+    texture coordinate uniform in [0, 1]^2."""
+    rng = np.random.default_rng(seed)
+    base = rng.normal(size=(n_tri, 3))
+    base /= np.linalg.norm(base, axis=1, keepdims=True)
+    out = np.empty((3, 5, n_tri), dtype=np.float64)
+    for v in range(3):
+        nv = base + 0.3 * rng.normal(size=(n_tri, 3))
+        nv /= np.linalg.norm(nv, axis=1, keepdims=True)
+        out[v, 0:3] = nv.T
+        out[v, 3:5] = rng.uniform(0.0, 1.0, size=(2, n_tri))
+    return out.astype(np.float32)
+
+
 def pixel_sample(width: int, height: int, seed: int, n_tiles: int = 64, tile: int = 16,
                  n_pixels: int = 16384) -> np.ndarray:
     """Sorted unique flat pixel indices (j*W+i): every pixel of ``n_tiles``

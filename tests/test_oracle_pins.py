@@ -382,3 +382,61 @@ def test_smallest_circle_cap_contains_spherical_triangle(oracle_lib):
         inner = w @ np.stack(units)
         inner /= np.linalg.norm(inner, axis=1, keepdims=True)
         assert np.all(inner @ S >= cosr - 1e-12)
+
+
+# -------------------------------------------------------- fragment data --
+
+def test_fragment_barycentrics_match_linear_solve(oracle_lib):
+    """Section 1.1.4 fragment data against LAPACK: with [A B C] w = g, the
+    ray meets the plane at P = g / sum(w) = sum(w_i V_i) / sum(w), so the
+    barycentric weights are w / sum(w); an attribute that is an affine
+    function of position interpolates to its value at P; the normal pass is
+    unit length."""
+    tris = synth.scene(60, 41)
+    view = synth.View(96, 72, 0.3, 0.6, 0.9, 260.0, 0, synth.yaw_pitch_rotation(0.4, 0.2))
+    res = oracle_lib.render(view, tris)
+    pix = np.flatnonzero(res.id.reshape(-1) != 0xFFFFFFFF)
+    ids = res.id.reshape(-1)[pix]
+    rng = np.random.default_rng(5)
+    T = tris.shape[1]
+    verts = tris.astype(np.float64).reshape(3, 3, T)            # [vertex, xyz, t]
+    M, c = rng.normal(size=(2, 3)), rng.normal(size=2)
+    aff = np.einsum("kx,vxt->vkt", M, verts) + c[None, :, None]  # affine in position
+    attr = np.concatenate([synth.vertex_attributes(T, 7).astype(np.float64), aff], axis=1)
+    b, f = oracle_lib.fragments(view, tris, attr.astype(np.float32), pix, ids, normalize3=True)
+    b2, f2 = oracle_lib.fragments(view, tris, aff.astype(np.float32), pix, ids)
+    dirs, ok = oracle_lib.perspective_map(view)
+    flat = dirs.reshape(-1, 3)
+    a32 = aff.astype(np.float32).astype(np.float64)
+    for q in range(0, len(pix), 7):
+        t, g = int(ids[q]), flat[pix[q]]
+        w = _solve_weights(tris[:, t], g)
+        assert np.allclose(b[q], w / w.sum(), rtol=1e-9, atol=1e-9), (q, b[q], w / w.sum())
+        assert b[q].sum() == pytest.approx(1.0, abs=1e-11)
+        assert b[q].min() > -1e-11                      # covered: inside the triangle
+        P = g / w.sum()
+        assert np.allclose(b[q] @ verts[:, :, t], P, rtol=1e-9, atol=1e-9)
+        exp = a32[:, :, t].T @ b[q]                      # same weights on the float32 data
+        assert np.allclose(f2[q], exp, rtol=1e-9, atol=1e-9)
+        assert np.allclose(f2[q], M @ P + c, rtol=1e-5, atol=1e-5)  # float32 rounding of the data
+        assert np.linalg.norm(f[q, 0:3]) == pytest.approx(1.0, abs=1e-12)
+    assert len(pix) > 2000
+
+
+def test_fragment_at_a_vertex_is_that_vertex(oracle_lib):
+    """A pixel looking straight at vertex A gets b = (1, 0, 0) and A's data."""
+    view = synth.View(64, 48, -0.2, 0.8, 0.9, 200.0, 0)
+    dirs, ok = oracle_lib.perspective_map(view)
+    p = 23 * 64 + 40
+    g = dirs.reshape(-1, 3)[p]
+    A = 7.0 * g
+    B = A + np.array([1.0, 0.2, 0.1])
+    C = A + np.array([0.1, 1.0, 0.3])
+    tris = np.concatenate([A, B, C]).reshape(9, 1).astype(np.float32)
+    attr = synth.vertex_attributes(1, 3)
+    b, f = oracle_lib.fragments(view, tris, attr, np.array([p]), np.array([0], dtype=np.uint32))
+    assert np.allclose(b[0], [1.0, 0.0, 0.0], atol=1e-6)
+    assert np.allclose(f[0], attr[0, :, 0], atol=1e-6)
+    # no hit, or a pixel without direction: zeros
+    b, f = oracle_lib.fragments(view, tris, attr, np.array([p]), np.array([0xFFFFFFFF], dtype=np.uint32))
+    assert not b.any() and not f.any()
