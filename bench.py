@@ -227,6 +227,30 @@ def main():
         f"bin {np.mean(binl):.3f} ms, raster {np.mean(rast):.3f} ms, list entries {np.mean(entries):.0f}, "
         f"overflowed tiles {overflow}")
 
+    # ---------------- fragment data (section 1.1.4) of the last plain frame
+    vattr = torch.from_numpy(synth.vertex_attributes(tris.shape[1], 21)).to(dev)
+    bary_t = torch.empty((3, views[0].height, views[0].width), dtype=torch.float32, device=dev)
+    attr_t = torch.empty((5, views[0].height, views[0].width), dtype=torch.float32, device=dev)
+    rl = []
+    for rep in range(4):
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        vsr.vsr_resolve(v, fmt, frame.map, scene.xyz, scene.ntri, frame.tri_id, vattr, 5,
+                        vsr.VSR_RESOLVE_NORMALIZE3, bary_t, attr_t)
+        e1.record(stream)
+        e1.synchronize()
+        if rep:
+            rl.append(e0.elapsed_time(e1))
+    resolve_ms = float(np.mean(rl))
+    ids_now = frame.tri_id.reshape(-1)
+    winners = int(torch.unique(ids_now[ids_now != -1]).numel())
+    P = views[0].width * views[0].height
+    map_px = 12 if fmt == vsr.VSR_MAP_F32 else 4
+    resolve_bytes = P * (map_px + 4 + 4 * (3 + 5)) + winners * (36 + 3 * 5 * 4)
+    log(f"resolve (barycentrics + 5 interpolated components): {resolve_ms:.3f} ms, {winners} distinct winners, "
+        f"{resolve_bytes / resolve_ms / 1e6:.0f} GB/s algorithmic")
+    del bary_t, attr_t
+
     # ---------------- single-view fused path (vsr_build_map + vsr_render)
     ffr = pipeline.render_fused(scene, views[0], fmt=fmt)
     torch.cuda.synchronize()
@@ -371,6 +395,13 @@ def main():
                        "unit": "T lane-ops/s", "frac": achieved / PEAK_VALU_LANE_OPS,
                        "traffic": traffic_from_profiles("k_raster<false>"), "kernel": "k_raster",
                        "kernel_ms": t_r * 1e3, "fragments_per_launch": F_mean, "ops_per_fragment": OPS_PER_FRAGMENT}
+    # fragment data: HBM-bound (map, ids and outputs per pixel, the winners'
+    # vertices and data once each)
+    roofline_resolve = {"bound": "hbm", "achieved": resolve_bytes / (resolve_ms * 1e-3) / 1e9,
+                        "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                        "frac": resolve_bytes / (resolve_ms * 1e-3) / PEAK_HBM,
+                        "traffic": traffic_from_profiles("k_resolve"), "kernel": "k_resolve",
+                        "kernel_ms": resolve_ms, "algorithmic_bytes": resolve_bytes, "winners": winners}
     # the whole batched step per view: covered-fragment work and frame bytes
     per_view_s = submit_ms * 1e-3 / len(views)
     frame_bytes = (12 if fmt == vsr.VSR_MAP_F32 else 4) * 2073600 + 68 * tris.shape[1] + 8 * 2073600
@@ -439,6 +470,8 @@ def main():
         "roofline": roofline,
         "roofline_raster": roofline_raster,
         "roofline_step": roofline_step,
+        "roofline_resolve": roofline_resolve,
+        "resolve_ms": resolve_ms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

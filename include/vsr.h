@@ -182,6 +182,30 @@ int64_t vsr_render_bytes(int32_t width, int32_t height);
 int vsr_render(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri, void* scratch,
                int64_t scratch_bytes, uint32_t* tri_id, float* depth, void* stream);
 
+/* Step 6 — fragment data from barycentric coordinates (section 1.1.4,
+ * second half).  For every pixel whose tri_id names a triangle: the
+ * barycentric weights (b_A, b_B, b_C) of the point where the pixel's ray
+ * meets that triangle's plane (they sum to 1, all >= 0 inside), and per
+ * vertex data interpolated with them, f = b_A A_f + b_B B_f + b_C C_f
+ * (perspective-correct: the weights are those of the 3D point).  With
+ * VSR_RESOLVE_NORMALIZE3 the first three data components are normalised
+ * (the normal pass).  Pixels with no hit, no direction, or a ray parallel
+ * to the plane get zeros.
+ *   v, fmt, map  the view and its map (any map of the same lens).
+ *   xyz, ntri    the device triangle array given to vsr_setup_tris
+ *                (float[9][ntri]).
+ *   tri_id       device uint32[height][width] from vsr_raster / vsr_render.
+ *   vattr        device float[3][nattr][ntri]: data of vertex v (0=A, 1=B,
+ *                2=C), component k, triangle t at (v*nattr + k)*ntri + t;
+ *                may be NULL when nattr == 0.  nattr: 0..64.
+ *   bary         device float[3][height][width] or NULL.
+ *   attr         device float[nattr][height][width] or NULL.
+ * Returns VSR_E_ARG for bad sizes or pointers, or NORMALIZE3 with nattr < 3. */
+#define VSR_RESOLVE_NORMALIZE3 1u
+int vsr_resolve(const vsr_view* v, int32_t fmt, const void* map, const float* xyz, int64_t ntri,
+                const uint32_t* tri_id, const float* vattr, int32_t nattr, uint32_t flags, float* bary, float* attr,
+                void* stream);
+
 /* ------------------------------------------------------------- batches */
 
 /* One view of a batch (host memory).  setup/ntri name a resident scene

@@ -10,6 +10,7 @@
 #include "fused.hpp"
 #include "map.hpp"
 #include "raster.hpp"
+#include "resolve.hpp"
 #include "setup.hpp"
 #include "submit.hpp"
 
@@ -245,6 +246,28 @@ int vsr_render(const vsr_view* v, int32_t fmt, const void* map, const void* setu
     return hip_status(launch_fused(map, v->width, v->height, fmt, rot_of(v->rot), setup, ntri, scratch, tri_id,
                                    depth, hipStream_t(stream)),
                       "vsr_render");
+}
+
+int vsr_resolve(const vsr_view* v, int32_t fmt, const void* map, const float* xyz, int64_t ntri,
+                const uint32_t* tri_id, const float* vattr, int32_t nattr, uint32_t flags, float* bary, float* attr,
+                void* stream) {
+    int rc = check_view_buffers(v, fmt);
+    if (rc != VSR_OK) return rc;
+    if (!map || !aligned(map) || !tri_id || (ntri > 0 && !xyz)) return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri out of range");
+    if (nattr < 0 || nattr > 64) return fail(VSR_E_ARG, "nattr %d outside 0..64", nattr);
+    if (nattr > 0 && ntri > 0 && !vattr) return fail(VSR_E_ARG, "vattr is NULL");
+    if ((flags & VSR_RESOLVE_NORMALIZE3) && nattr < 3) return fail(VSR_E_ARG, "NORMALIZE3 needs nattr >= 3");
+    if ((flags & ~VSR_RESOLVE_NORMALIZE3) != 0) return fail(VSR_E_ARG, "unknown flags 0x%x", flags);
+    const uintptr_t mis = reinterpret_cast<uintptr_t>(xyz) | reinterpret_cast<uintptr_t>(tri_id) |
+                          reinterpret_cast<uintptr_t>(vattr) | reinterpret_cast<uintptr_t>(bary) |
+                          reinterpret_cast<uintptr_t>(attr);
+    if (mis & 3u) return fail(VSR_E_ARG, "buffer not 4-byte aligned");
+    if (!bary && !attr) return VSR_OK;
+    return hip_status(launch_resolve(map, v->width, v->height, fmt, rot_of(v->rot), xyz, ntri, tri_id, vattr, nattr,
+                                     (flags & VSR_RESOLVE_NORMALIZE3) != 0, bary, nattr > 0 ? attr : nullptr,
+                                     hipStream_t(stream)),
+                      "vsr_resolve");
 }
 
 int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth) {

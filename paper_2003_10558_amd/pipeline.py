@@ -81,6 +81,24 @@ def render_fused(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, stream=None,
     return frame
 
 
+def resolve(scene: Scene, view, frame: Frame, vattr: Optional[torch.Tensor] = None, normalize3: bool = False,
+            fmt: int = vsr.VSR_MAP_F32, stream=None) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+    """Fragment data of a rendered frame: barycentric weights [3, H, W] and,
+    with per-vertex data ``vattr`` [3, K, T], the interpolated data [K, H, W]
+    (the first three normalised when ``normalize3``)."""
+    dev = scene.device
+    bary = torch.empty((3, view.height, view.width), dtype=torch.float32, device=dev)
+    nattr = 0 if vattr is None else int(vattr.shape[1])
+    attr = None
+    if nattr:
+        vattr = vattr.to(device=dev, dtype=torch.float32).contiguous()
+        assert vattr.shape == (3, nattr, scene.ntri)
+        attr = torch.empty((nattr, view.height, view.width), dtype=torch.float32, device=dev)
+    vsr.vsr_resolve(view, fmt, frame.map, scene.xyz, scene.ntri, frame.tri_id, vattr, nattr,
+                    vsr.VSR_RESOLVE_NORMALIZE3 if normalize3 else 0, bary, attr, stream)
+    return bary, attr
+
+
 class Batch:
     """Workspace + outputs for vsr_submit over a fixed list of (scene, view)."""
 

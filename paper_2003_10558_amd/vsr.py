@@ -25,6 +25,7 @@ VSR_SUBMIT_BINNED, VSR_SUBMIT_FUSED = 0, 1
 VSR_SUBMIT_TABLE_READY = 0x100
 VSR_SUBMIT_BIN_BLOCKS, VSR_SUBMIT_BIN_SUPERTILES = 0x200, 0x400
 VSR_TILE = 8
+VSR_RESOLVE_NORMALIZE3 = 1
 VSR_AOV_HORIZONTAL, VSR_AOV_DIAGONAL, VSR_AOV_VERTICAL, VSR_AOV_HORIZONTAL_4X3 = 0, 1, 2, 3
 
 if not os.path.exists(LIB_PATH):
@@ -67,6 +68,7 @@ _lib.vsr_raster_stats.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64
 _lib.vsr_render_bytes.argtypes = [_i32, _i32]
 _lib.vsr_render_bytes.restype = _i64
 _lib.vsr_render.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp]
+_lib.vsr_resolve.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _vp, _i32, _u32, _vp, _vp, _vp]
 _lib.vsr_submit_bytes.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32]
 _lib.vsr_submit_bytes.restype = _i64
 _lib.vsr_submit.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32, _vp, _i64, _vp]
@@ -84,7 +86,7 @@ for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin",
-           "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_submit_bytes",
+           "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_resolve", "vsr_submit_bytes",
            "vsr_submit_table_bytes", "vsr_submit_table_offset", "vsr_submit_table", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
 
 
@@ -194,6 +196,13 @@ def vsr_render(view, fmt: int, map_buf, setup_buf, ntri: int, scratch, tri_id, d
     v = make_view(view)
     _check(_lib.vsr_render(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), ntri, _ptr(scratch),
                            _nbytes(scratch), _ptr(tri_id), _ptr(depth), _stream(stream)))
+
+
+def vsr_resolve(view, fmt: int, map_buf, xyz, ntri: int, tri_id, vattr, nattr: int, flags: int, bary, attr,
+                stream=None) -> None:
+    v = make_view(view)
+    _check(_lib.vsr_resolve(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(xyz), ntri, _ptr(tri_id), _ptr(vattr), nattr,
+                            flags, _ptr(bary), _ptr(attr), _stream(stream)))
 
 
 def vsr_submit_bytes(jobs, fmt: int, mode: int = 0, bin_depth: int = 1024) -> int:

@@ -1,0 +1,109 @@
+"""GPU parity of the fragment-data step (section 1.1.4, vsr_resolve).
+
+The GPU's barycentric weights and interpolated vertex data are compared with
+the FP64 oracle (the paper's triple-product form) at pixels where both
+agree on the winner.  The tolerance is derived per pixel: the weights of a
+ray-plane point are a ratio b_A = G.(B x C) / G.N' (N' = (B-A) x (C-A)),
+whose error from a direction error dG (the FP32 map: below 1e-6 rad) and
+from FP32 products (about 32 ulp of the magnitudes involved) is bounded by
+(1e-6 + 32 * 2^-24) * M / |G.N'| with M the largest |P| |Q - P| over the
+triangle's edges; data error follows through the weights.
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+EPS32 = 2.0 ** -24
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2003_10558_amd import pipeline, vsr
+    oracle.build(force=False)
+    return torch, pipeline, vsr
+
+
+def _dirs(view, pix):
+    out = np.zeros((len(pix), 3))
+    for q, p in enumerate(pix):
+        x, y = oracle.view_coord(int(p) % view.width, int(p) // view.width, view.width, view.height, view.aov)
+        k, l, s, om = oracle.limits(view.k, view.l, view.s, view.omega_deg)
+        g, ok = oracle.direction(x, y, k, l, s, om)
+        out[q] = view.rot_matrix() @ g if ok else 0.0
+    return out
+
+
+def _check(gpu, view, tris, pix, seed, tag):
+    torch, pipeline, vsr = gpu
+    scene = pipeline.Scene(tris)
+    fr = pipeline.render(scene, view)
+    T = tris.shape[1]
+    attr_np = synth.vertex_attributes(T, seed)
+    bary, attr = pipeline.resolve(scene, view, fr, torch.from_numpy(attr_np), normalize3=True)
+    torch.cuda.synchronize()
+    ids = pipeline.ids_u32(fr.tri_id).reshape(-1)
+    b_gpu = bary.cpu().numpy().reshape(3, -1)
+    f_gpu = attr.cpu().numpy().reshape(attr_np.shape[1], -1)
+    # pixels without a hit get zeros
+    miss = ids == 0xFFFFFFFF
+    assert not b_gpu[:, miss].any() and not f_gpu[:, miss].any()
+    ref = oracle.render(view, tris, pix)
+    sel = pix[(ids[pix] == ref.id) & (ref.id != 0xFFFFFFFF)]
+    t = ids[sel]
+    b_ref, f_ref = oracle.fragments(view, tris, attr_np, sel, t, normalize3=True)
+    _, f_raw = oracle.fragments(view, tris, attr_np[:, 0:3], sel, t)   # the normal before normalising
+    g = _dirs(view, sel)
+    V = tris.astype(np.float64).reshape(3, 3, T)[:, :, t]                # [vertex, xyz, n]
+    A, B, C = V[0].T, V[1].T, V[2].T
+    Np = np.cross(B - A, C - A)
+    s = np.abs(np.einsum("ij,ij->i", g, Np))
+    M = np.max(np.stack([np.linalg.norm(B, axis=1) * np.linalg.norm(C - B, axis=1),
+                         np.linalg.norm(C, axis=1) * np.linalg.norm(A - C, axis=1),
+                         np.linalg.norm(A, axis=1) * np.linalg.norm(B - A, axis=1)]), axis=0)
+    tol_b = (1e-6 + 32 * EPS32) * M / s + 1e-6
+    db = np.abs(b_gpu[:, sel].T - b_ref).max(axis=1)
+    a = np.abs(attr_np[:, :, t]).sum(axis=0).T                          # [n, K] sum over vertices
+    tol_f = tol_b[:, None] * a + 8 * EPS32 * a
+    tol_f[:, 0:3] /= np.maximum(np.linalg.norm(f_raw, axis=1), 1e-6)[:, None] / 2.0
+    df = np.abs(f_gpu[:, sel].T - f_ref)
+    ratio_b, ratio_f = (db / tol_b).max(), (df / tol_f).max()
+    _say(f"[resolve-{tag}] {len(sel)} pixels: max |db| {db.max():.2e} (median tol {np.median(tol_b):.1e}), "
+         f"max |df| {df.max():.2e}; worst error/tolerance b {ratio_b:.3f} f {ratio_f:.3f}")
+    assert len(sel) > 100
+    assert ratio_b <= 1.0 and ratio_f <= 1.0
+    assert np.abs(b_gpu[:, sel].sum(axis=0) - 1.0).max() < 1e-5
+
+
+def test_resolve_small_full_frame(gpu):
+    view = synth.view_small()
+    tris = synth.scene_small()
+    pix = np.arange(view.width * view.height)
+    _check(gpu, view, tris, pix, 11, "small")
+
+
+def test_resolve_rotated_wide(gpu):
+    view = synth.View(200, 150, -0.4, 0.3, 0.9, 300.0, 0, synth.yaw_pitch_rotation(1.0, 0.3))
+    tris = synth.scene(1500, 19)
+    pix = synth.pixel_sample(view.width, view.height, seed=12, n_tiles=8, n_pixels=4000)
+    _check(gpu, view, tris, pix, 13, "rot")
+
+
+def test_resolve_1080p_1m_sampled(gpu):
+    view = synth.views_1080p_sweep()[1]
+    tris = synth.scene_1m()
+    pix = synth.pixel_sample(view.width, view.height, seed=14, n_tiles=2, n_pixels=1024)
+    _check(gpu, view, tris, pix, 15, "1080p")

@@ -132,3 +132,24 @@ def test_submit_argument_errors(vsr):
         vsr.vsr_render(v, 0, _FakeBuf(256, 1), _FakeBuf(512, 1), 10, _FakeBuf(768, 16), _FakeBuf(1024, 1),
                        _FakeBuf(2048, 1), stream=0)
     assert e.value.code == vsr.VSR_E_SPACE
+
+
+def test_resolve_argument_errors(vsr):
+    v = synth.View(64, 32, 0.3, 0.5, 0.9, 120.0)
+    cases = [
+        dict(nattr=-1),                                   # nattr out of range
+        dict(nattr=65),
+        dict(nattr=2, flags=vsr.VSR_RESOLVE_NORMALIZE3),  # normal pass needs 3 components
+        dict(flags=8),                                    # unknown flag
+        dict(vattr=None),                                 # data missing for nattr > 0
+        dict(map_buf=None),
+        dict(bary=_FakeBuf(4098, 1)),                     # misaligned
+    ]
+    for c in cases:
+        a = dict(map_buf=_FakeBuf(256, 1), xyz=_FakeBuf(512, 1), ntri=10, tri_id=_FakeBuf(1024, 1),
+                 vattr=_FakeBuf(2048, 1), nattr=3, flags=0, bary=_FakeBuf(4096, 1), attr=_FakeBuf(8192, 1))
+        a.update(c)
+        with pytest.raises(vsr.VsrError) as e:
+            vsr.vsr_resolve(v, 0, a["map_buf"], a["xyz"], a["ntri"], a["tri_id"], a["vattr"], a["nattr"],
+                            a["flags"], a["bary"], a["attr"], stream=0)
+        assert e.value.code == vsr.VSR_E_ARG, c
