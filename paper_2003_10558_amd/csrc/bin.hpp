@@ -167,7 +167,7 @@ __device__ inline void bin_block(const BinArgs& A, int64_t b) {
         sh.g.sup[0] = s0;
         sh.g.sup[1] = s1;
     }
-    sh.g.fc[tid] = S.face_count[tid];
+    for (int q = tid; q < kSlices * 64; q += 256) sh.g.fc[q] = S.face_count[q];
     __syncthreads();
     setup_rects(sh.g);
     const bool any = sh.g.sup[1].z != 0.0f;

@@ -19,8 +19,7 @@
 namespace vsr {
 
 constexpr int kFusedCap = 1024;                // LDS list entries per tile
-constexpr int kFusedSteps = 4;
-__constant__ const int kFusedStep[kFusedSteps + 1] = {0, 1, 2, 3, kSlices};
+constexpr int kFusedSteps = kSlices;  // one depth slice per step
 constexpr uint32_t kFlushAt = kFusedCap - 256;  // a chunk adds <= 256 per tile
 
 struct FusedArgs {
@@ -72,7 +71,7 @@ __device__ inline void fused_super(const FusedArgs& A, int64_t sidx) {
 
     // slice groups visited in turn
     for (int step = 0; step < kFusedSteps; ++step) {
-        const int s0 = kFusedStep[step], s1 = kFusedStep[step + 1];
+        const int s0 = step, s1 = step + 1;
         uint32_t live = 0;
 #pragma unroll
         for (int q = 0; q < kSupTiles; ++q)

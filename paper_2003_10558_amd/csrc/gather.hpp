@@ -226,7 +226,6 @@ struct SuperShared {
     uint32_t fc[kSlices * 64];  // per-slice (level, face) triangle counts
     uint32_t bk[kSupTiles][kDepthBuckets];
 };
-static_assert(kSlices * 64 == 256, "one face count per thread of the 256-thread block");
 static_assert(kSupTiles * kDepthBuckets >= kGatherBlock, "survivor list fits in the bucket counters");
 
 // Exclusive scan of one value per thread over a 256-thread block.
@@ -301,7 +300,7 @@ __device__ inline void super_setup(SuperShared& sh, const float4* caps, const fl
         sh.sup[0] = s0;
         sh.sup[1] = s1;
     }
-    sh.fc[tid] = face_count[tid];  // kSlices * 64 == 256 entries
+    for (int q = tid; q < kSlices * 64; q += 256) sh.fc[q] = face_count[q];
     if (tid < kSupTiles) {
         sh.cnt[tid] = 0;
         sh.flag[tid] = 0;

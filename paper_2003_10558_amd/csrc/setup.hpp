@@ -9,8 +9,7 @@
 //     that either winding covers the inside of its cone, never its antipode;
 //   - the hard normal N = (A-B) x (C-B) and d = A.N of section 1.1.4, stored
 //     as a unit normal facing away from O and the plane's distance from O;
-//   - a depth lower bound (the plane distance, rounded down) for the
-//     front-to-back early exit of the rasterizer;
+//   - a depth lower bound for the front-to-back early exit (depth_lb);
 //   - the smallest-circle cap of section 1.1.2 (bounding cap of the
 //     spherical triangle) and the cube-map cell of its centre at the level
 //     matching its radius.
@@ -63,6 +62,99 @@ __device__ inline uint32_t cell_of(float3 s, int L) {
     return uint32_t(level_base(L) + int64_t(face) * M * M + int64_t(iv) * M + iu);
 }
 
+// ---------------------------------------------- depth lower bound ------
+// A bound lb <= every FP32 depth the rasterizer can compute for this
+// triangle, so that nearest-first processing may stop once every pixel is
+// nearer than the next triangle's lb.  The plane distance d alone is one
+// (r = d / (G.N) >= d), but for a triangle seen at an angle the rays that
+// cover it meet its plane much further out: r >= d / cos(theta), theta the
+// angle from the plane normal to the nearest direction of the triangle's
+// cone.  Evaluated in FP64 from the values the rasterizer uses:
+//   - covered directions satisfy the stored FP32 edge tests, so they lie in
+//     the exact vertex cone dilated by eta_i per edge (the stored normal's
+//     deviation from the exact one plus the FP32 dot-product rounding, 8
+//     ulp); near a corner of angle alpha the dilation reaches
+//     eta / sin(alpha / 2), doubled for margin;
+//   - the FP32 depth d * rcp(G.N) is at least (1 - 3 ulp) r / (1 + 8 ulp r/d)
+//     (G.N carries at most 8 ulp of absolute rounding, |G| <= 1 + 2e-6);
+// and the result is widened by 1e-5 and rounded down to FP32.  Never below
+// the plane-distance bound d (1 - 2^-16).
+__device__ inline double dnorm3(double x, double y, double z) { return sqrt(x * x + y * y + z * z); }
+
+struct D3 {
+    double x, y, z;
+};
+__device__ inline D3 d3(float3 v) { return D3{double(v.x), double(v.y), double(v.z)}; }
+__device__ inline D3 dsub(D3 a, D3 b) { return D3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline D3 dscale(D3 a, double s) { return D3{a.x * s, a.y * s, a.z * s}; }
+__device__ inline double ddot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline D3 dcross(D3 a, D3 b) { return D3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+__device__ inline double dlen(D3 a) { return dnorm3(a.x, a.y, a.z); }
+__device__ inline D3 dunit(D3 a) { return dscale(a, 1.0 / dlen(a)); }
+
+// Angle from unit p to the minor arc between unit directions u and v.
+__device__ inline double arc_distance(D3 p, D3 u, D3 v) {
+    D3 n = dcross(u, v);
+    const double ln = dlen(n);
+    double best = fmin(acos(fmin(1.0, fmax(-1.0, ddot(p, u)))), acos(fmin(1.0, fmax(-1.0, ddot(p, v)))));
+    if (ln > 0.0) {
+        n = dscale(n, 1.0 / ln);
+        const double sp = ddot(p, n);
+        const D3 q = dsub(p, dscale(n, sp));  // projection onto the arc's great circle
+        if (ddot(dcross(u, q), n) >= 0.0 && ddot(dcross(q, v), n) >= 0.0)
+            best = fmin(best, asin(fmin(1.0, fabs(sp))));
+    }
+    return best;
+}
+
+__device__ inline float depth_lb(float3 A, float3 B, float3 C, float4 r0, float4 r1, float4 r2, float dist,
+                                 float sigma) {
+    const float base = dist * (1.0f - 1.0f / 65536.0f);
+    const double eps = 1.0 / 16777216.0;
+    const D3 a = dunit(d3(A)), b = dunit(d3(B)), c = dunit(d3(C));
+    // exact unit edge normals of the vertex cone, oriented inward
+    const D3 stored[3] = {D3{r0.x, r0.y, r0.z}, D3{r1.x, r1.y, r1.z}, D3{r2.x, r2.y, r2.z}};
+    const D3 ex[3] = {dcross(d3(A), d3(B)), dcross(d3(B), d3(C)), dcross(d3(C), d3(A))};
+    double eta = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double l = dlen(ex[i]);
+        if (!(l > 0.0)) return base;
+        const D3 e = dscale(ex[i], double(sigma) / l);
+        eta = fmax(eta, dlen(dsub(stored[i], e)) + 8.0 * eps * (1.0 + dlen(stored[i])));
+    }
+    // smallest spherical angle of the triangle
+    const D3 v[3] = {a, b, c};
+    double smin = 1.0;
+    for (int i = 0; i < 3; ++i) {
+        const D3 p = v[i], q = v[(i + 1) % 3], r = v[(i + 2) % 3];
+        D3 tq = dsub(q, dscale(p, ddot(q, p))), tr = dsub(r, dscale(p, ddot(r, p)));
+        const double lq = dlen(tq), lr = dlen(tr);
+        if (!(lq > 0.0 && lr > 0.0)) return base;
+        const double ca = fmin(1.0, fmax(-1.0, ddot(tq, tr) / (lq * lr)));
+        smin = fmin(smin, sqrt(fmax(0.0, 0.5 * (1.0 - ca))));  // sin(alpha/2)
+    }
+    if (!(smin > 1e-9)) return base;
+    const double eta_eff = 2.0 * eta / smin;
+    // angle from the stored plane normal to the cone
+    const D3 nh = D3{r0.w, r1.w, r2.w};
+    const double lnh = dlen(nh);
+    const D3 u = dscale(nh, 1.0 / lnh);
+    double theta = 0.0;
+    bool inside = true;
+    for (int i = 0; i < 3; ++i)
+        if (ddot(dscale(ex[i], double(sigma)), u) < 0.0) inside = false;
+    if (!inside) theta = fmin(arc_distance(u, a, b), fmin(arc_distance(u, b, c), arc_distance(u, c, a)));
+    theta = fmax(0.0, theta - eta_eff);
+    if (!(theta < 1.5)) theta = 1.5;  // keep cos well away from 0; still a valid bound
+    const double dd = double(dist);
+    const double L = dd / (lnh * (1.0 + 2e-6) * cos(theta));
+    double lb = (1.0 - 3.0 * eps) * L / (1.0 + 8.0 * eps * L / dd);
+    lb *= 1.0 - 1e-5;
+    float f = float(lb);
+    if (double(f) > lb) f = __uint_as_float(__float_as_uint(f) - 1u);  // round down
+    return fmaxf(f, base);
+}
+
 __global__ __launch_bounds__(256) void k_setup_tris(const float* __restrict__ xyz, int64_t n,
                                                     float4* __restrict__ rec_id, float4* __restrict__ cap_id,
                                                     uint32_t* __restrict__ key, uint32_t* __restrict__ val,
@@ -90,10 +182,10 @@ __global__ __launch_bounds__(256) void k_setup_tris(const float* __restrict__ xy
         float s0 = sigma / sqrtf(l0), s1 = sigma / sqrtf(l1), s2 = sigma / sqrtf(l2);
         float sn = (d > 0.0f ? 1.0f : -1.0f) / lenN;
         float dist = fabsf(d) / lenN;
-        lb = dist * (1.0f - 1.0f / 65536.0f);
         r0 = make_float4(e0.x * s0, e0.y * s0, e0.z * s0, N.x * sn);
         r1 = make_float4(e1.x * s1, e1.y * s1, e1.z * s1, N.y * sn);
         r2 = make_float4(e2.x * s2, e2.y * s2, e2.z * s2, N.z * sn);
+        lb = depth_lb(A, B, C, r0, r1, r2, dist, sigma);
         r3 = make_float4(dist, lb, __uint_as_float(uint32_t(t)), 0.0f);
 
         // Smallest circle around the sphere-projected vertices (section 1.1.2).
