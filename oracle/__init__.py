@@ -76,6 +76,12 @@ def _load():
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_int32]
             lib.orc_render.restype = ctypes.c_int
+            lib.orc_delta.argtypes = [ctypes.POINTER(_View), ctypes.c_int32, ctypes.c_int32]
+            lib.orc_delta.restype = ctypes.c_double
+            lib.orc_aa_render.argtypes = [ctypes.POINTER(_View), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_int64, dp, dp, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int32]
+            lib.orc_aa_render.restype = ctypes.c_int
             lib.orc_fragments.argtypes = [ctypes.POINTER(_View), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_int64, dp, dp]
@@ -230,3 +236,48 @@ def fragments(view, tris: np.ndarray, attr: np.ndarray, pixels: np.ndarray, ids:
     lib.orc_fragments(ctypes.byref(cv), tris.ctypes.data, tris.shape[1], attr.ctypes.data, nattr,
                       int(bool(normalize3)), pixels.ctypes.data, ids.ctypes.data, n, _dp(b), _dp(f))
     return b, f[:, :nattr]
+
+
+def delta(view, i: int, j: int) -> float:
+    """Section 1.1.1 global delta of pixel (i, j): 1 / max_c fwidth(G_c) of
+    the camera-frame map (central differences, one-sided at borders)."""
+    lib = _load()
+    cv = _cview(view)
+    return float(lib.orc_delta(ctypes.byref(cv), int(i), int(j)))
+
+
+@dataclass
+class AAResult:
+    cov: np.ndarray      # float64 coverage in [0, 1]
+    depth: np.ndarray    # float64 depth pass: sum of clipped mask x depth
+    dom: np.ndarray      # uint32 id with the largest clipped mask, NO_HIT if none
+    margin: np.ndarray   # largest clipped mask minus the second largest
+    gap: np.ndarray      # smallest relative depth step between fragments taken
+
+
+def aa_render(view, tris: np.ndarray, pixels: Optional[np.ndarray] = None,
+              threads: Optional[int] = None) -> AAResult:
+    """Aliasing-free render (sections 1.1.1, 1.1.2, 1.4) of the listed flat
+    pixel indices, or of the whole frame ([H, W] arrays) when ``pixels`` is
+    None."""
+    lib = _load()
+    tris = np.ascontiguousarray(tris, dtype=np.float32)
+    ntri = tris.shape[1]
+    if pixels is None:
+        n, pix_ptr = view.width * view.height, None
+    else:
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        n, pix_ptr = pixels.shape[0], pixels.ctypes.data
+    cov, depth = np.empty(n), np.empty(n)
+    dom = np.empty(n, dtype=np.uint32)
+    aux = np.empty((n, 2))
+    cv = _cview(view)
+    rc = lib.orc_aa_render(ctypes.byref(cv), tris.ctypes.data, ntri, pix_ptr, n, _dp(cov), _dp(depth),
+                           dom.ctypes.data, aux.ctypes.data, int(threads or os.cpu_count() or 1))
+    if rc != 0:
+        raise MemoryError("oracle aa render failed")
+    res = AAResult(cov, depth, dom, aux[:, 0].copy(), aux[:, 1].copy())
+    if pixels is None:
+        for f in ("cov", "depth", "dom", "margin", "gap"):
+            setattr(res, f, getattr(res, f).reshape(view.height, view.width))
+    return res

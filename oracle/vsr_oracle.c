@@ -17,6 +17,9 @@
  *            step: 1 iff g > 0).
  *   depth    section 1.1.4 (hard normal N=(A-B)x(C-B); r = A.N / G.N).
  *   resolve  section 1.4 (depth-pass test: the nearest r wins).
+ *   aa       sections 1.1.1 (pixel step with the map's global delta), 1.1.2
+ *            (miter mask of the smallest circle) and 1.4 (front-to-back
+ *            combination of clipped fragment masks).
  *   fragment section 1.1.4, second half (barycentric vector of the
  *            intersection point from triple products with the hard normal;
  *            vertex data interpolated with it).
@@ -525,4 +528,250 @@ void orc_fragments(const orc_view *v, const float *xyz, int64_t ntri, const floa
 {
     for (int64_t q = 0; q < npix; ++q)
         fragment_one(v, xyz, ntri, attr, nattr, normalize3, pix[q], ids[q], out_b + 3 * q, out_f + nattr * q);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Aliasing-free coverage: section 1.1.1 (pixel step with the map's global
+ * delta), 1.1.2 (miter mask from the smallest circle) and 1.4 (front-to-back
+ * combination of fragment masks).                                          */
+
+/* Camera-frame direction of pixel (i, j) (the map before rotation). */
+static int cam_direction(const orc_view *v, int32_t i, int32_t j, double g[3])
+{
+    double k = v->k, l = v->l, s = v->s, om = v->omega_deg, x, y;
+    orc_limits(&k, &l, &s, &om);
+    orc_view_coord(i, j, v->width, v->height, v->aov, &x, &y);
+    return orc_direction(x, y, k, l, s, om, g);
+}
+
+/* Derivative of the camera-frame map along one pixel axis at (i, j):
+ * central difference of the two neighbours, one-sided where a neighbour is
+ * outside the picture or has no direction, 0 when neither has one. */
+static void map_derivative(const orc_view *v, int32_t i, int32_t j, int32_t di, int32_t dj, const double g0[3],
+                           double out[3])
+{
+    double gp[3], gm[3];
+    int32_t ip = i + di, jp = j + dj, im = i - di, jm = j - dj;
+    int okp = ip >= 0 && ip < v->width && jp >= 0 && jp < v->height && cam_direction(v, ip, jp, gp);
+    int okm = im >= 0 && im < v->width && jm >= 0 && jm < v->height && cam_direction(v, im, jm, gm);
+    for (int c = 0; c < 3; ++c) {
+        if (okp && okm)
+            out[c] = 0.5 * (gp[c] - gm[c]);
+        else if (okp)
+            out[c] = gp[c] - g0[c];
+        else if (okm)
+            out[c] = g0[c] - gm[c];
+        else
+            out[c] = 0.0;
+    }
+}
+
+/* Section 1.1.1 global delta of pixel (i, j): the reciprocal of the largest
+ * component of fwidth(G) = |dG/di| + |dG/dj| of the camera-frame map.
+ * 0 for a pixel without direction; +inf when the map does not vary. */
+double orc_delta(const orc_view *v, int32_t i, int32_t j)
+{
+    double g[3], di[3], dj[3];
+    if (!cam_direction(v, i, j, g))
+        return 0.0;
+    map_derivative(v, i, j, 1, 0, g, di);
+    map_derivative(v, i, j, 0, 1, g, dj);
+    double m = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double f = fabs(di[c]) + fabs(dj[c]);
+        if (f > m)
+            m = f;
+    }
+    return m > 0.0 ? 1.0 / m : INFINITY;
+}
+
+/* gpstep of section 1.1.1: clamp(delta * g + 1/2, 0, 1). */
+static double gpstep(double g, double delta)
+{
+    double x = delta * g + 0.5;
+    return x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+}
+
+typedef struct {
+    double r, m;
+    uint32_t id;
+} orc_frag;
+
+static int frag_cmp(const void *a, const void *b)
+{
+    const orc_frag *x = (const orc_frag *)a, *y = (const orc_frag *)b;
+    if (x->r != y->r)
+        return x->r < y->r ? -1 : 1;
+    return x->id < y->id ? -1 : (x->id > y->id ? 1 : 0);
+}
+
+typedef struct {
+    const orc_view *v;
+    const orc_tri *tris;
+    const double *caps; /* 4 per triangle: S_hat, |S| (section 1.1.2) */
+    int64_t ntri;
+    const int64_t *pix;
+    int64_t npix;
+    double *cov, *depth;
+    uint32_t *dom;
+    double *aux; /* optional, 2 per pixel: see orc_aa_render */
+    int64_t begin, stride;
+} orc_aa_job;
+
+/* Fragment mask of a triangle at direction g (sections 1.1.1-1.1.2): the
+ * smallest pixel step over the three edges and the miter circle.  The edge
+ * values n_i . g have unit gradient on the sphere at the edge; the miter
+ * value S_hat . g - |S| has gradient sin(rho) at the rim (|S| = cos rho), so
+ * it is divided by sin(rho) before the global delta scales it.  With the
+ * per-fragment derivative of the section's equation the division changes
+ * nothing (pstep is scale-free); with the global delta it keeps the miter's
+ * slope one pixel wide like the edges'.  A degenerate circle (no finite
+ * centre, or rho = 0) omits the miter, as the section allows. */
+static double aa_mask(const orc_tri *tr, const double *cap, const double g[3], double delta)
+{
+    double m = 1.0;
+    for (int i = 0; i < 3; ++i) {
+        double s = gpstep(dot3(tr->n[i], g), delta);
+        if (s < m)
+            m = s;
+    }
+    if (isfinite(cap[0]) && isfinite(cap[1]) && isfinite(cap[2]) && isfinite(cap[3])) {
+        double sr2 = 1.0 - cap[3] * cap[3];
+        if (sr2 > 0.0) {
+            double s = gpstep((dot3(cap, g) - cap[3]) / sqrt(sr2), delta);
+            if (s < m)
+                m = s;
+        }
+    }
+    return m;
+}
+
+static void aa_pixel(const orc_aa_job *jb, int64_t q)
+{
+    int64_t p = jb->pix ? jb->pix[q] : q;
+    int32_t i = (int32_t)(p % jb->v->width), j = (int32_t)(p / jb->v->width);
+    double g[3];
+    double m_b = 0.0, r_b = 0.0, best = 0.0, second = 0.0, gap = INFINITY;
+    uint32_t dom = ORC_NO_HIT;
+    if (orc_pixel_direction(jb->v, i, j, g)) {
+        double delta = orc_delta(jb->v, i, j);
+        int64_t cap_n = 16, n = 0;
+        orc_frag *fr = (orc_frag *)malloc(sizeof(orc_frag) * (size_t)cap_n);
+        for (int64_t t = 0; fr && t < jb->ntri; ++t) {
+            const orc_tri *tr = &jb->tris[t];
+            if (!tr->live)
+                continue;
+            double m = aa_mask(tr, jb->caps + 4 * t, g, delta);
+            double gn = dot3(g, tr->N);
+            if (!(m > 0.0) || gn == 0.0)
+                continue;
+            double r = tr->d / gn;
+            if (!(r > 0.0))
+                continue;
+            if (n == cap_n) {
+                cap_n *= 2;
+                orc_frag *nf = (orc_frag *)realloc(fr, sizeof(orc_frag) * (size_t)cap_n);
+                if (!nf) {
+                    free(fr);
+                    fr = NULL;
+                    break;
+                }
+                fr = nf;
+            }
+            fr[n].r = r;
+            fr[n].m = m;
+            fr[n].id = (uint32_t)t;
+            ++n;
+        }
+        if (fr) {
+            qsort(fr, (size_t)n, sizeof(orc_frag), frag_cmp);
+            /* section 1.4: front to back, each mask clipped by what is
+             * already covered, data weighted by the clipped mask */
+            int64_t k = 0;
+            for (; k < n && m_b < 1.0; ++k) {
+                double mfc = fr[k].m < 1.0 - m_b ? fr[k].m : 1.0 - m_b;
+                m_b += mfc;
+                r_b += mfc * fr[k].r;
+                if (mfc > best) {
+                    second = best;
+                    best = mfc;
+                    dom = fr[k].id;
+                } else if (mfc > second) {
+                    second = mfc;
+                }
+            }
+            /* smallest relative depth step among the fragments used and the
+             * first one left out: below rounding, their order is arbitrary */
+            for (int64_t q = 1; q <= k && q < n; ++q) {
+                double g = (fr[q].r - fr[q - 1].r) / fr[q].r;
+                if (g < gap)
+                    gap = g;
+            }
+            free(fr);
+        }
+    }
+    jb->cov[q] = m_b;
+    jb->depth[q] = r_b;
+    jb->dom[q] = dom;
+    if (jb->aux) {
+        jb->aux[2 * q] = best - second;
+        jb->aux[2 * q + 1] = gap;
+    }
+}
+
+static void *aa_range(void *arg)
+{
+    orc_aa_job *jb = (orc_aa_job *)arg;
+    for (int64_t q = jb->begin; q < jb->npix; q += jb->stride)
+        aa_pixel(jb, q);
+    return NULL;
+}
+
+/* Anti-aliased render of the listed pixels (pix = NULL: whole frame):
+ * coverage m in [0, 1], depth pass sum(m_fc * r) and the id with the largest
+ * clipped mask (NO_HIT when nothing covers; on equal clipped masks the
+ * nearer fragment).  aux (optional, 2 per pixel) receives the margin of the
+ * largest clipped mask over the second largest and the smallest relative
+ * depth step between consecutive fragments taken (+inf if none): where
+ * either is at rounding level, another dominant id is as correct.  Returns
+ * -1 on allocation failure. */
+int orc_aa_render(const orc_view *v, const float *xyz_soa, int64_t ntri, const int64_t *pix, int64_t npix,
+                  double *cov, double *depth, uint32_t *dom, double *aux, int32_t nthreads)
+{
+    if (!pix)
+        npix = (int64_t)v->width * v->height;
+    orc_tri *tris = (orc_tri *)malloc(sizeof(orc_tri) * (size_t)(ntri > 0 ? ntri : 1));
+    double *caps = (double *)malloc(sizeof(double) * 4 * (size_t)(ntri > 0 ? ntri : 1));
+    if (!tris || !caps) {
+        free(tris);
+        free(caps);
+        return -1;
+    }
+    for (int64_t t = 0; t < ntri; ++t) {
+        double A[3], B[3], C[3];
+        tri_prepare(xyz_soa, ntri, t, &tris[t]);
+        load_vertex(xyz_soa, ntri, t, 0, A);
+        load_vertex(xyz_soa, ntri, t, 1, B);
+        load_vertex(xyz_soa, ntri, t, 2, C);
+        if (tris[t].live)
+            orc_cap(A, B, C, caps + 4 * t);
+    }
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    pthread_t th[256];
+    orc_aa_job jobs[256];
+    for (int w = 0; w < nthreads; ++w) {
+        orc_aa_job jb = {v, tris, caps, ntri, pix, npix, cov, depth, dom, aux, w, nthreads};
+        jobs[w] = jb;
+    }
+    for (int w = 1; w < nthreads; ++w)
+        pthread_create(&th[w], NULL, aa_range, &jobs[w]);
+    aa_range(&jobs[0]);
+    for (int w = 1; w < nthreads; ++w)
+        pthread_join(th[w], NULL);
+    free(tris);
+    free(caps);
+    return 0;
 }
