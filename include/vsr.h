@@ -52,6 +52,7 @@ extern "C" {
 
 /* vsr_build_map flags */
 #define VSR_STRICT 1u /* reject parameters outside the limits instead of clamping */
+#define VSR_MAP_AA 2u /* also store the global delta and widen the caps: see vsr_aa_raster */
 
 /* angle-of-view types (section 2, remark on normalising 2D coordinates) */
 #define VSR_AOV_HORIZONTAL 0
@@ -205,6 +206,52 @@ int vsr_render(const vsr_view* v, int32_t fmt, const void* map, const void* setu
 int vsr_resolve(const vsr_view* v, int32_t fmt, const void* map, const float* xyz, int64_t ntri,
                 const uint32_t* tri_id, const float* vattr, int32_t nattr, uint32_t flags, float* bary, float* attr,
                 void* stream);
+
+/* Step 7 — aliasing-free coverage (sections 1.1.1, 1.1.2, 1.4).
+ *
+ * Bytes of a map built with VSR_MAP_AA: the map of vsr_map_bytes followed by
+ * one float per pixel (the global delta).  <0 on bad input. */
+int64_t vsr_aa_map_bytes(int32_t width, int32_t height, int32_t fmt);
+
+/* Anti-aliased coverage and front-to-back combination.  Per pixel and
+ * triangle the fragment mask is
+ *   m = min(gpstep(n_0.G), gpstep(n_1.G), gpstep(n_2.G), gpstep(miter)),
+ *   gpstep(x) = clamp(delta*x + 1/2, 0, 1)      (section 1.1.1)
+ * with n_i the oriented unit edge-plane normals, delta the pixel's global
+ * delta (1 / largest component of fwidth of the camera-frame map, by
+ * central differences), and miter = (S.G - |S|)/sin(rho) for the smallest
+ * circle (S, rho) of section 1.1.2 (divided by sin rho so that its slope is
+ * one pixel wide like the edges').  Fragments with m > 0 whose plane is in
+ * front (r = d/(G.N) > 0) are combined nearest first by (r, id), as in
+ * section 1.4: m_fc = min(m, 1 - m_b), m_b += m_fc, depth += m_fc * r.
+ *   map          built by vsr_build_map with VSR_MAP_AA into a buffer of
+ *                vsr_aa_map_bytes(width, height, fmt) bytes; its tile caps
+ *                are widened by the pixel step's fringe, so vsr_bin on it
+ *                lists every triangle whose mask is non-zero in a tile.
+ *   setup, ntri  from vsr_setup_tris; bins, bin_depth from vsr_bin on map
+ *                (an overflowed tile gathers its own candidates).
+ *   coverage     device float[height][width]: m_b in [0, 1] (0: no hit or
+ *                no direction).
+ *   depth_pass   device float[height][width]: sum of m_fc * r (the depth
+ *                pass, not divided by the coverage).
+ *   dominant     device uint32[height][width]: the triangle with the largest
+ *                clipped share m_fc (ties: the nearer), VSR_NO_HIT if none.
+ *   lost         optional device uint32 (may be NULL): receives the number
+ *                of pixels that met more than 8 fragments before their masks
+ *                saturated; only those pixels can differ from the exact
+ *                combination.
+ * A map built without VSR_MAP_AA gives undefined images (no delta plane). */
+int vsr_aa_raster(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri, const void* bins,
+                  int32_t bin_depth, float* coverage, float* depth_pass, uint32_t* dominant, uint32_t* lost,
+                  void* stream);
+
+/* Instrumented vsr_aa_raster (same images) that also counts, into the device
+ * array stats[4] of uint64: pixel-triangle mask evaluations (pixels with a
+ * direction x triangles tested), fragments inserted, triangles skipped by
+ * the wave's saturation-depth test, tiles.  For measurement. */
+int vsr_aa_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
+                        const void* bins, int32_t bin_depth, float* coverage, float* depth_pass, uint32_t* dominant,
+                        uint32_t* lost, uint64_t* stats, void* stream);
 
 /* ------------------------------------------------------------- batches */
 

@@ -253,6 +253,9 @@ class AAResult:
     dom: np.ndarray      # uint32 id with the largest clipped mask, NO_HIT if none
     margin: np.ndarray   # largest clipped mask minus the second largest
     gap: np.ndarray      # smallest relative depth step between fragments taken
+    n_near: np.ndarray   # fragments taken + the first left out
+    sum_r: np.ndarray    # their summed depth
+    sum_rg: np.ndarray   # their summed depth / cos(ray, plane normal)
 
 
 def aa_render(view, tris: np.ndarray, pixels: Optional[np.ndarray] = None,
@@ -270,14 +273,14 @@ def aa_render(view, tris: np.ndarray, pixels: Optional[np.ndarray] = None,
         n, pix_ptr = pixels.shape[0], pixels.ctypes.data
     cov, depth = np.empty(n), np.empty(n)
     dom = np.empty(n, dtype=np.uint32)
-    aux = np.empty((n, 2))
+    aux = np.empty((n, 5))
     cv = _cview(view)
     rc = lib.orc_aa_render(ctypes.byref(cv), tris.ctypes.data, ntri, pix_ptr, n, _dp(cov), _dp(depth),
                            dom.ctypes.data, aux.ctypes.data, int(threads or os.cpu_count() or 1))
     if rc != 0:
         raise MemoryError("oracle aa render failed")
-    res = AAResult(cov, depth, dom, aux[:, 0].copy(), aux[:, 1].copy())
+    res = AAResult(cov, depth, dom, *(aux[:, c].copy() for c in range(5)))
     if pixels is None:
-        for f in ("cov", "depth", "dom", "margin", "gap"):
+        for f in ("cov", "depth", "dom", "margin", "gap", "n_near", "sum_r", "sum_rg"):
             setattr(res, f, getattr(res, f).reshape(view.height, view.width))
     return res

@@ -585,15 +585,20 @@ double orc_delta(const orc_view *v, int32_t i, int32_t j)
     return m > 0.0 ? 1.0 / m : INFINITY;
 }
 
-/* gpstep of section 1.1.1: clamp(delta * g + 1/2, 0, 1). */
+/* gpstep of section 1.1.1: clamp(delta * g + 1/2, 0, 1).  With an infinite
+ * delta (a picture of one pixel: the map does not vary) it is the binary
+ * step, and a value exactly on the edge counts as outside, as the strict
+ * binary step does. */
 static double gpstep(double g, double delta)
 {
     double x = delta * g + 0.5;
-    return x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+    return x > 0.0 ? (x < 1.0 ? x : 1.0) : 0.0;
 }
 
+#define ORC_AA_AUX 5
+
 typedef struct {
-    double r, m;
+    double r, m, gn;
     uint32_t id;
 } orc_frag;
 
@@ -614,7 +619,7 @@ typedef struct {
     int64_t npix;
     double *cov, *depth;
     uint32_t *dom;
-    double *aux; /* optional, 2 per pixel: see orc_aa_render */
+    double *aux; /* optional, ORC_AA_AUX per pixel: see orc_aa_render */
     int64_t begin, stride;
 } orc_aa_job;
 
@@ -626,7 +631,9 @@ typedef struct {
  * per-fragment derivative of the section's equation the division changes
  * nothing (pstep is scale-free); with the global delta it keeps the miter's
  * slope one pixel wide like the edges'.  A degenerate circle (no finite
- * centre, or rho = 0) omits the miter, as the section allows. */
+ * centre, rho = 0, or a circle plane within 1e-6 of O: the projected
+ * vertices on one great circle, to rounding) omits the miter, as the
+ * section allows. */
 static double aa_mask(const orc_tri *tr, const double *cap, const double g[3], double delta)
 {
     double m = 1.0;
@@ -635,7 +642,7 @@ static double aa_mask(const orc_tri *tr, const double *cap, const double g[3], d
         if (s < m)
             m = s;
     }
-    if (isfinite(cap[0]) && isfinite(cap[1]) && isfinite(cap[2]) && isfinite(cap[3])) {
+    if (isfinite(cap[0]) && isfinite(cap[1]) && isfinite(cap[2]) && isfinite(cap[3]) && cap[3] > 1e-6) {
         double sr2 = 1.0 - cap[3] * cap[3];
         if (sr2 > 0.0) {
             double s = gpstep((dot3(cap, g) - cap[3]) / sqrt(sr2), delta);
@@ -652,6 +659,7 @@ static void aa_pixel(const orc_aa_job *jb, int64_t q)
     int32_t i = (int32_t)(p % jb->v->width), j = (int32_t)(p / jb->v->width);
     double g[3];
     double m_b = 0.0, r_b = 0.0, best = 0.0, second = 0.0, gap = INFINITY;
+    double n_near = 0.0, sum_r = 0.0, sum_rg = 0.0;
     uint32_t dom = ORC_NO_HIT;
     if (orc_pixel_direction(jb->v, i, j, g)) {
         double delta = orc_delta(jb->v, i, j);
@@ -680,6 +688,7 @@ static void aa_pixel(const orc_aa_job *jb, int64_t q)
             }
             fr[n].r = r;
             fr[n].m = m;
+            fr[n].gn = fabs(gn) / sqrt(dot3(tr->N, tr->N));
             fr[n].id = (uint32_t)t;
             ++n;
         }
@@ -700,12 +709,19 @@ static void aa_pixel(const orc_aa_job *jb, int64_t q)
                     second = mfc;
                 }
             }
-            /* smallest relative depth step among the fragments used and the
-             * first one left out: below rounding, their order is arbitrary */
-            for (int64_t q = 1; q <= k && q < n; ++q) {
-                double g = (fr[q].r - fr[q - 1].r) / fr[q].r;
-                if (g < gap)
-                    gap = g;
+            /* conditioning over the fragments taken and the first one left
+             * out: smallest relative depth step (below rounding their order
+             * is arbitrary), their number, sum of depths and of depth over
+             * the cosine between ray and plane normal */
+            for (int64_t f = 0; f <= k && f < n; ++f) {
+                if (f > 0) {
+                    double step = (fr[f].r - fr[f - 1].r) / fr[f].r;
+                    if (step < gap)
+                        gap = step;
+                }
+                n_near += 1.0;
+                sum_r += fr[f].r;
+                sum_rg += fr[f].r / fr[f].gn;
             }
             free(fr);
         }
@@ -714,8 +730,12 @@ static void aa_pixel(const orc_aa_job *jb, int64_t q)
     jb->depth[q] = r_b;
     jb->dom[q] = dom;
     if (jb->aux) {
-        jb->aux[2 * q] = best - second;
-        jb->aux[2 * q + 1] = gap;
+        double *a = jb->aux + ORC_AA_AUX * q;
+        a[0] = best - second;
+        a[1] = gap;
+        a[2] = n_near;
+        a[3] = sum_r;
+        a[4] = sum_rg;
     }
 }
 
@@ -730,11 +750,14 @@ static void *aa_range(void *arg)
 /* Anti-aliased render of the listed pixels (pix = NULL: whole frame):
  * coverage m in [0, 1], depth pass sum(m_fc * r) and the id with the largest
  * clipped mask (NO_HIT when nothing covers; on equal clipped masks the
- * nearer fragment).  aux (optional, 2 per pixel) receives the margin of the
- * largest clipped mask over the second largest and the smallest relative
- * depth step between consecutive fragments taken (+inf if none): where
- * either is at rounding level, another dominant id is as correct.  Returns
- * -1 on allocation failure. */
+ * nearer fragment).  aux (optional, ORC_AA_AUX per pixel) receives, for a
+ * tolerance model of a lower-precision implementation: the margin of the
+ * largest clipped mask over the second largest; the smallest relative depth
+ * step between consecutive fragments among those taken and the first one
+ * left out (+inf if none; where either is at rounding level another
+ * dominant id is as correct); the number of those fragments, the sum of
+ * their depths r, and the sum of r / cos(ray, plane normal).  Returns -1 on
+ * allocation failure. */
 int orc_aa_render(const orc_view *v, const float *xyz_soa, int64_t ntri, const int64_t *pix, int64_t npix,
                   double *cov, double *depth, uint32_t *dom, double *aux, int32_t nthreads)
 {

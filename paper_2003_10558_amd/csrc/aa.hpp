@@ -1,0 +1,331 @@
+// Aliasing-free coverage: pixel step with the global delta (section 1.1.1),
+// miter mask (section 1.1.2) and front-to-back combination of clipped
+// fragment masks (section 1.4).
+//
+// One 64-lane wavefront per 8x8 tile of a map built with VSR_MAP_AA, whose
+// tile caps are widened by the pixel step's fringe so that the ordinary
+// binner lists every triangle that touches a tile.  Each lane owns one
+// pixel direction g and its delta, and for every listed triangle forms
+//   m = min(gpstep(n_0.g), gpstep(n_1.g), gpstep(n_2.g), gpstep(miter)),
+//   gpstep(x) = clamp(delta*x + 1/2, 0, 1),
+// the miter value being (S.g - cos rho)/sin rho written through the chord
+// |g - S| (no cancellation for small circles).  Fragments with m > 0 and
+// the plane in front (r = d/(g.N) > 0) enter a per-lane list sorted by
+// (r, id) that keeps the nearest ones up to the point where their masks
+// saturate the pixel (m^b reaches 1); anything behind that point gets a
+// zero share and is dropped.  At the end the list is combined front to
+// back: m^fc = min(m^f, 1 - m^b), m^b += m^fc, depth pass += m^fc r, and the
+// dominant id is the fragment with the largest share.  A pixel whose list
+// overflows before saturating is counted (its result may be inexact).
+//
+// Records are staged through LDS eight triangles at a time (lane l loads
+// word (l & 7) of triangle l >> 3: four record words and two cap words; the
+// lane holding the cap's second word turns the rim into the two constants
+// of the miter value).  A triangle whose plane cannot come nearer, anywhere
+// in the tile, than the saturation depth of every pixel is skipped by the
+// whole wave.
+#pragma once
+#include "raster.hpp"
+
+namespace vsr {
+
+constexpr int kAAFrags = 8;  // fragments kept per pixel before saturation
+
+struct AAArgs {
+    const void* map;
+    int64_t ntiles;
+    int32_t fmt, depth, W, H, ntx;
+    const void* setup;
+    int64_t n;
+    const void* bins;
+    float* cov;
+    float* dpass;
+    uint32_t* dom;
+    uint32_t* lost;                 // pixels whose list overflowed unsaturated
+    unsigned long long* stats;      // optional: tests, fragments inserted, triangles skipped, tiles
+    Rot rot;
+};
+
+__device__ inline bool frag_less(float ra, uint32_t ia, float rb, uint32_t ib) {
+    return ra < rb || (ra == rb && ia < ib);
+}
+
+struct FragList {
+    float r[kAAFrags], m[kAAFrags];
+    uint32_t id[kAAFrags];
+    int cnt;
+    float rsat;      // depth of the fragment that saturates the pixel, +inf if none
+    uint32_t idsat;
+    bool lost;
+
+    __device__ inline void init() {
+        cnt = 0;
+        rsat = __int_as_float(0x7F800000);
+        idsat = kNoHit;
+        lost = false;
+    }
+
+    __device__ inline void insert(float rr, uint32_t ii, float mm) {
+        if (!frag_less(rr, ii, rsat, idsat)) return;  // behind the saturated prefix: zero share
+        float cr = rr, cm = mm;
+        uint32_t ci = ii;
+#pragma unroll
+        for (int k = 0; k < kAAFrags; ++k) {
+            if (k < cnt) {
+                if (frag_less(cr, ci, r[k], id[k])) {
+                    float tr = r[k], tm = m[k];
+                    uint32_t ti = id[k];
+                    r[k] = cr;
+                    m[k] = cm;
+                    id[k] = ci;
+                    cr = tr;
+                    cm = tm;
+                    ci = ti;
+                }
+            } else if (k == cnt) {
+                r[k] = cr;
+                m[k] = cm;
+                id[k] = ci;
+            }
+        }
+        const bool dropped = (cnt == kAAFrags);
+        if (!dropped) ++cnt;
+        // saturation point: first fragment whose mask fills what is left
+        float mb = 0.0f;
+        int keep = cnt;
+#pragma unroll
+        for (int k = 0; k < kAAFrags; ++k) {
+            if (k < keep) {
+                if (m[k] >= 1.0f - mb) {
+                    rsat = r[k];
+                    idsat = id[k];
+                    keep = k + 1;
+                } else {
+                    mb += m[k];
+                }
+            }
+        }
+        cnt = keep;
+        if (dropped && rsat == __int_as_float(0x7F800000)) lost = true;
+    }
+
+    __device__ inline void combine(float& mb, float& rb, uint32_t& dom) const {
+        mb = 0.0f;
+        rb = 0.0f;
+        dom = kNoHit;
+        float best = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kAAFrags; ++k) {
+            if (k < cnt) {
+                float mfc = fminf(m[k], 1.0f - mb);
+                mb += mfc;
+                rb = fmaf(mfc, r[k], rb);
+                if (mfc > best) {
+                    best = mfc;
+                    dom = id[k];
+                }
+            }
+        }
+    }
+};
+
+__device__ inline float gpstep(float x, float delta) { return fminf(fmaxf(fmaf(delta, x, 0.5f), 0.0f), 1.0f); }
+
+// Miter constants from the rim's half-angle sine sh: the value
+// (S.g - cos rho)/sin rho = (2 sh^2 - |g-S|^2/2)/(2 sh ch) = a - |g-S|^2 b.
+// sh = 0 (degenerate circle): no miter (a = +inf).
+__device__ inline float2 miter_consts(float sh) {
+    if (!(sh > 0.0f)) return make_float2(__int_as_float(0x7F800000), 0.0f);
+    float ch = sqrtf(fmaxf(0.0f, 1.0f - sh * sh));
+    return make_float2(sh / ch, 0.25f / (sh * ch));
+}
+
+// One triangle against the lane's pixel.  c0 = (S, -), c1 = (a, b, -, -).
+__device__ inline bool aa_rec(float4 r0, float4 r1, float4 r2, float4 r3, float4 c0, float4 c1, float3 g, float delta,
+                              FragList& L) {
+    float e0 = fmaf(r0.z, g.z, fmaf(r0.y, g.y, r0.x * g.x));
+    float e1 = fmaf(r1.z, g.z, fmaf(r1.y, g.y, r1.x * g.x));
+    float e2 = fmaf(r2.z, g.z, fmaf(r2.y, g.y, r2.x * g.x));
+    float dx = g.x - c0.x, dy = g.y - c0.y, dz = g.z - c0.z;
+    float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    float mv = fmaf(-q, c1.y, c1.x);
+    float m = fminf(fminf(gpstep(e0, delta), gpstep(e1, delta)), fminf(gpstep(e2, delta), gpstep(mv, delta)));
+    if (m > 0.0f) {
+        float dn = fmaf(r2.w, g.z, fmaf(r1.w, g.y, r0.w * g.x));
+        if (dn > 0.0f) {
+            L.insert(r3.x / dn, __float_as_uint(r3.z), m);
+            return true;
+        }
+    }
+    return false;
+}
+
+// Nearest distance at which a triangle's plane (unit normal N facing away
+// from O, distance d) can be met by a ray of the tile cap (centre c,
+// cos/sin of the radius cr/sr; wide: any ray): r = d/(g.N) >= d/cos(angle).
+__device__ inline float plane_min_depth(float3 N, float d, float3 c, float cr, float sr, bool wide) {
+    if (wide) return d;
+    float ca = dot3(c, N);
+    if (ca >= cr) return d;
+    float sa = sqrtf(fmaxf(0.0f, 1.0f - ca * ca));
+    float cm = fmaf(ca, cr, sa * sr);  // cos(angle(c, N) - radius)
+    return cm > 0.0f ? d / cm : __int_as_float(0x7F800000);
+}
+
+template <bool kStats>
+__device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* stg) {
+    const float4* caps = map_caps(A.map, A.ntiles, A.fmt);
+    SceneView S = scene_view(A.setup, A.n);
+    const char* bb = reinterpret_cast<const char*>(A.bins);
+    const uint32_t* counts = reinterpret_cast<const uint32_t*>(bb + 256);
+    const uint32_t* lists = reinterpret_cast<const uint32_t*>(bb + 256 + align256(A.ntiles * 4));
+    const float* dplane =
+        reinterpret_cast<const float*>(reinterpret_cast<const char*>(A.map) + aa_delta_off(A.W, A.H, A.fmt));
+
+    int tx = int(tile % A.ntx), ty = int(tile / A.ntx);
+    int i = tx * kTile + (lane & (kTile - 1)), j = ty * kTile + (lane >> 3);
+    bool inside = i < A.W && j < A.H;
+    float3 g = load_dir(A.map, A.fmt, A.ntiles, tile, lane, A.rot);
+    float delta = dplane[tile * kTilePix + lane];
+    bool has_dir = inside && delta > 0.0f;
+    FragList L;
+    L.init();
+    if (!has_dir) L.rsat = 0.0f;  // nothing can cover it
+
+    float4 tc0, tc1;
+    load_tile_cap(caps, tile, A.rot, tc0, tc1);
+    const float3 tcen = f3(tc0.x, tc0.y, tc0.z);
+    const float tcr = fmaf(-2.0f * tc0.w, tc0.w, 1.0f), tsr = tc1.y;
+    const bool twide = tc1.z == kCapWide;
+    unsigned long long n_test = 0, n_frag = 0, n_skip = 0;
+
+    auto visit = [&](float4 r0, float4 r1, float4 r2, float4 r3, float4 c0, float4 c1, float rmax) {
+        // rmax: largest saturation depth over the wave (wave-uniform)
+        if (rmax < __int_as_float(0x7F800000)) {
+            float rmin = plane_min_depth(f3(r0.w, r1.w, r2.w), r3.x, tcen, tcr, tsr, twide);
+            if (rmin * (1.0f - 1e-4f) > rmax) {
+                if (kStats) ++n_skip;
+                return;
+            }
+        }
+        bool f = has_dir && aa_rec(r0, r1, r2, r3, c0, c1, g, delta, L);
+        if (kStats) {
+            ++n_test;
+            n_frag += __popcll(__ballot(f));
+        }
+    };
+
+    const uint32_t count = counts[tile];
+    if (count <= uint32_t(A.depth)) {
+        const uint32_t* lst = lists + tile * A.depth;
+        const uint32_t sub = uint32_t(lane) >> 3, part = uint32_t(lane) & 7u;
+        const uint32_t ngroups = (count + 7u) >> 3;
+        for (uint32_t gi = 0; gi < ngroups; ++gi) {
+            const uint32_t e = gi * 8u + sub;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (e < count) {
+                const uint32_t rk = lst[e];
+                if (part < 4u) {
+                    v = S.rec[4 * int64_t(rk) + part];
+                } else if (part < 6u) {
+                    v = S.cap[2 * int64_t(rk) + (part - 4u)];
+                    if (part == 5u) {
+                        float2 mc = miter_consts(v.w);
+                        v = make_float4(mc.x, mc.y, 0.f, 0.f);
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            stg[lane] = v;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            float rmax = __uint_as_float(wave_max_u32_dpp(__float_as_uint(L.rsat)));
+            const uint32_t nt = min(8u, count - gi * 8u);
+            for (uint32_t t = 0; t < nt; ++t) {
+                const float4* w = stg + 8 * t;
+                visit(w[0], w[1], w[2], w[3], w[4], w[5], rmax);
+            }
+        }
+    } else {
+        gather_candidates(S, tc0, tc1, lane, [&](uint32_t rank, bool valid) {
+            bool pass = valid && candidate_test(S, rank, tc0, tc1);
+            uint64_t msk = __ballot(pass);
+            while (msk) {
+                int qb = __ffsll((unsigned long long)msk) - 1;
+                msk &= msk - 1;
+                uint32_t rk = uint32_t(__builtin_amdgcn_readlane(int(rank), qb));
+                const float4* r = S.rec + 4 * int64_t(rk);
+                float4 c1 = S.cap[2 * int64_t(rk) + 1];
+                float2 mc = miter_consts(c1.w);
+                float rmax = __uint_as_float(wave_max_u32_dpp(__float_as_uint(L.rsat)));
+                visit(r[0], r[1], r[2], r[3], S.cap[2 * int64_t(rk)], make_float4(mc.x, mc.y, 0.f, 0.f), rmax);
+            }
+        });
+    }
+
+    float mb, rb;
+    uint32_t dm;
+    L.combine(mb, rb, dm);
+    if (inside) {
+        int64_t o = int64_t(j) * A.W + i;
+        A.cov[o] = mb;
+        A.dpass[o] = rb;
+        A.dom[o] = dm;
+    }
+    if (A.lost) {
+        uint32_t c = uint32_t(__popcll(__ballot(L.lost)));
+        if (lane == 0 && c) atomicAdd(A.lost, c);
+    }
+    if (kStats && lane == 0) {
+        unsigned long long npix = (unsigned long long)__popcll(__ballot(has_dir));
+        atomicAdd(&A.stats[0], n_test * npix);
+        atomicAdd(&A.stats[1], n_frag);
+        atomicAdd(&A.stats[2], n_skip);
+        atomicAdd(&A.stats[3], 1ull);
+    }
+}
+
+template <bool kStats>
+__global__ __launch_bounds__(256) void k_aa_raster(AAArgs A) {
+    __shared__ float4 s_stage[4][64];
+    int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
+    if (tile >= A.ntiles) return;
+    aa_tile<kStats>(A, tile, threadIdx.x & 63, s_stage[w]);
+}
+
+hipError_t launch_aa_raster(const void* map, int32_t W, int32_t H, int32_t fmt, const Rot& R, const void* setup,
+                            int64_t n, const void* bins, int32_t depth, float* cov, float* dpass, uint32_t* dom,
+                            uint32_t* lost, unsigned long long* stats, hipStream_t st) {
+    MapLayout ML = map_layout(W, H, fmt);
+    AAArgs A;
+    A.map = map;
+    A.ntiles = ML.ntiles;
+    A.fmt = fmt;
+    A.depth = depth;
+    A.W = W;
+    A.H = H;
+    A.ntx = ML.ntx;
+    A.setup = setup;
+    A.n = n;
+    A.bins = bins;
+    A.cov = cov;
+    A.dpass = dpass;
+    A.dom = dom;
+    A.lost = lost;
+    A.stats = stats;
+    A.rot = R;
+    int64_t blocks = (ML.ntiles + 3) / 4;
+    if (lost) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, lost, int64_t(1));
+    if (stats) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(stats), int64_t(8));
+        hipLaunchKernelGGL(k_aa_raster<true>, dim3(unsigned(blocks)), dim3(256), 0, st, A);
+    } else {
+        hipLaunchKernelGGL(k_aa_raster<false>, dim3(unsigned(blocks)), dim3(256), 0, st, A);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace vsr

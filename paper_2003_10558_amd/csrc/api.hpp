@@ -6,6 +6,7 @@
 #pragma once
 #include <stdarg.h>
 
+#include "aa.hpp"
 #include "bin.hpp"
 #include "fused.hpp"
 #include "map.hpp"
@@ -143,9 +144,17 @@ int vsr_build_map(const vsr_view* v, int32_t fmt, uint32_t flags, void* map, int
     int rc = make_map_params(v, fmt, flags, &P, v_eff);
     if (rc != VSR_OK) return rc;
     if (!map || !aligned(map)) return fail(VSR_E_ARG, "map buffer NULL or not 256-byte aligned");
-    int64_t need = map_layout(v->width, v->height, fmt).bytes;
+    if ((flags & ~(VSR_STRICT | VSR_MAP_AA)) != 0) return fail(VSR_E_ARG, "unknown flags 0x%x", flags);
+    const bool aa = (flags & VSR_MAP_AA) != 0;
+    int64_t need = aa ? aa_map_bytes(v->width, v->height, fmt) : map_layout(v->width, v->height, fmt).bytes;
     if (map_bytes < need) return fail(VSR_E_SPACE, "map buffer %lld < %lld bytes", (long long)map_bytes, (long long)need);
-    return hip_status(launch_build_map(P, map, hipStream_t(stream)), "vsr_build_map");
+    return hip_status(launch_build_map(P, map, aa, hipStream_t(stream)), "vsr_build_map");
+}
+
+int64_t vsr_aa_map_bytes(int32_t width, int32_t height, int32_t fmt) {
+    if (width < 1 || height < 1 || width > kMaxDim || height > kMaxDim) return VSR_E_ARG;
+    if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return VSR_E_ARG;
+    return aa_map_bytes(width, height, fmt);
 }
 
 
@@ -224,6 +233,41 @@ int vsr_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const void
                                     tri_id, depth, hipStream_t(stream), reinterpret_cast<unsigned long long*>(stats),
                                     no_early_exit),
                       "vsr_raster_stats");
+}
+
+static int aa_raster_common(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
+                            const void* bins, int32_t bin_depth, float* coverage, float* depth_pass,
+                            uint32_t* dominant, uint32_t* lost, uint64_t* stats, void* stream, const char* what) {
+    int rc = check_view_buffers(v, fmt);
+    if (rc != VSR_OK) return rc;
+    if (!map || !setup || !bins || !coverage || !depth_pass || !dominant || !aligned(map) || !aligned(setup) ||
+        !aligned(bins))
+        return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    const uintptr_t mis = reinterpret_cast<uintptr_t>(coverage) | reinterpret_cast<uintptr_t>(depth_pass) |
+                          reinterpret_cast<uintptr_t>(dominant) | reinterpret_cast<uintptr_t>(lost);
+    if (mis & 3u) return fail(VSR_E_ARG, "output not 4-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(stats) & 7u) != 0) return fail(VSR_E_ARG, "stats not 8-byte aligned");
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri out of range");
+    if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
+    return hip_status(launch_aa_raster(map, v->width, v->height, fmt, rot_of(v->rot), setup, ntri, bins, bin_depth,
+                                       coverage, depth_pass, dominant, lost,
+                                       reinterpret_cast<unsigned long long*>(stats), hipStream_t(stream)),
+                      what);
+}
+
+int vsr_aa_raster(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri, const void* bins,
+                  int32_t bin_depth, float* coverage, float* depth_pass, uint32_t* dominant, uint32_t* lost,
+                  void* stream) {
+    return aa_raster_common(v, fmt, map, setup, ntri, bins, bin_depth, coverage, depth_pass, dominant, lost, nullptr,
+                            stream, "vsr_aa_raster");
+}
+
+int vsr_aa_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
+                        const void* bins, int32_t bin_depth, float* coverage, float* depth_pass, uint32_t* dominant,
+                        uint32_t* lost, uint64_t* stats, void* stream) {
+    if (!stats) return fail(VSR_E_ARG, "stats is NULL");
+    return aa_raster_common(v, fmt, map, setup, ntri, bins, bin_depth, coverage, depth_pass, dominant, lost, stats,
+                            stream, "vsr_aa_raster_stats");
 }
 
 int64_t vsr_render_bytes(int32_t width, int32_t height) {

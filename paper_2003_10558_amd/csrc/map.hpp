@@ -84,6 +84,44 @@ __device__ inline bool pixel_direction(const MapParams& P, int i, int j, float3&
     return true;
 }
 
+// Derivative of the camera-frame map along one pixel axis at (i, j): central
+// difference of the two neighbours, one-sided where a neighbour is outside
+// the picture or has no direction, zero when neither has one.
+__device__ inline float3 map_derivative(const MapParams& P, int i, int j, int di, int dj, float3 g) {
+    float3 gp, gm;
+    const int ip = i + di, jp = j + dj, im = i - di, jm = j - dj;
+    bool okp = ip < P.W && jp < P.H && pixel_direction(P, ip, jp, gp);
+    bool okm = im >= 0 && jm >= 0 && pixel_direction(P, im, jm, gm);
+    if (okp && okm) return f3(0.5f * (gp.x - gm.x), 0.5f * (gp.y - gm.y), 0.5f * (gp.z - gm.z));
+    if (okp) return sub3(gp, g);
+    if (okm) return sub3(g, gm);
+    return f3(0.f, 0.f, 0.f);
+}
+
+// Section 1.1.1 global delta: the reciprocal of the largest component of
+// fwidth(G) = |dG/di| + |dG/dj| (+inf when the map does not vary).
+__device__ inline float pixel_delta(const MapParams& P, int i, int j, float3 g) {
+    float3 a = map_derivative(P, i, j, 1, 0, g), b = map_derivative(P, i, j, 0, 1, g);
+    float f = fmaxf(fabsf(a.x) + fabsf(b.x), fmaxf(fabsf(a.y) + fabsf(b.y), fabsf(a.z) + fabsf(b.z)));
+    return f > 0.0f ? 1.0f / f : __int_as_float(0x7F800000);
+}
+
+// Widens a tile cap by beta radians (a cap reaching pi/2 becomes wide).
+__device__ inline void dilate_cap(float4& c0, float4& c1, float beta) {
+    if (c1.z == kCapEmpty || c1.z == kCapWide) return;
+    float rho = 2.0f * asinf(fminf(1.0f, c0.w)) + beta;
+    if (!(rho < kHalfPi)) {
+        c0.w = 1.f;
+        c1 = make_float4(0.f, 1.f, kCapWide, 0.f);
+        return;
+    }
+    float sh, chh;
+    sincosf(0.5f * rho, &sh, &chh);
+    c0.w = sh;
+    c1.x = chh;
+    c1.y = sinf(rho);
+}
+
 // Cap of the directions held by the lanes with ok=true (wave-uniform result).
 __device__ inline void tile_cap(float3 g, bool ok, float4& c0, float4& c1) {
     uint64_t m = __ballot(ok);
@@ -117,6 +155,12 @@ __device__ inline void tile_cap(float3 g, bool ok, float4& c0, float4& c1) {
 }
 
 // Directions and cap of one tile (one wave); the cap is also returned.
+// With kAA the lane also stores its pixel's global delta, and the tile cap
+// is widened by the fringe the pixel step adds outside an edge: a pixel is
+// touched by a triangle when every edge value exceeds -1/(2 delta) (and the
+// miter value, whose cap grows by no more for radii up to pi/2), i.e. within
+// asin(1/(2 delta)) of each edge's half-sphere.
+template <bool kAA>
 __device__ inline void build_map_tile(const MapParams& P, void* map, int64_t ntiles, int64_t tile, int lane,
                                       float4& c0, float4& c1) {
     int tx = int(tile % P.ntx), ty = int(tile / P.ntx);
@@ -126,6 +170,13 @@ __device__ inline void build_map_tile(const MapParams& P, void* map, int64_t nti
     if (i < P.W && j < P.H) ok = pixel_direction(P, i, j, g);
     if (!ok) g = f3(0.f, 0.f, 0.f);
     int64_t q = tile * kTilePix + lane;
+    float fringe = 0.0f;
+    if (kAA) {
+        float delta = ok ? pixel_delta(P, i, j, g) : 0.0f;
+        float* dplane = reinterpret_cast<float*>(reinterpret_cast<char*>(map) + aa_delta_off(P.W, P.H, P.fmt));
+        dplane[q] = delta;
+        fringe = wave_max(ok ? 0.5f / delta : 0.0f);
+    }
     if (P.fmt == VSR_MAP_OCT16) {
         uint32_t w = ok ? oct_encode(g) : kOctInvalid;
         reinterpret_cast<uint32_t*>(map)[q] = w;
@@ -139,6 +190,7 @@ __device__ inline void build_map_tile(const MapParams& P, void* map, int64_t nti
         p[2 * plane + q] = g.z;
     }
     tile_cap(g, ok, c0, c1);
+    if (kAA) dilate_cap(c0, c1, asinf(fminf(1.0f, fringe)) * (1.0f + 1e-3f) + 1e-6f);
     if (lane == 0) {
         MapLayout L = map_layout(P.W, P.H, P.fmt);
         float4* caps = reinterpret_cast<float4*>(reinterpret_cast<char*>(map) + L.caps_off);
@@ -149,6 +201,7 @@ __device__ inline void build_map_tile(const MapParams& P, void* map, int64_t nti
 
 // One 256-thread block per 16x16 super-tile: wave w builds tile w of the
 // 2x2, then one thread bounds the four tile caps by the super-tile cap.
+template <bool kAA = false>
 __device__ inline void build_map_super(const MapParams& P, void* map, int64_t ntiles, int64_t sidx) {
     __shared__ float4 s_cap[4][2];
     const int lane = threadIdx.x & 63;
@@ -156,7 +209,7 @@ __device__ inline void build_map_super(const MapParams& P, void* map, int64_t nt
     int64_t tile;
     int tx, ty;
     float4 c0 = make_float4(0.f, 0.f, 1.f, 0.f), c1 = make_float4(1.f, 0.f, kCapEmpty, 0.f);
-    if (super_tile_of(sidx, w, P.ntx, P.nty, tile, tx, ty)) build_map_tile(P, map, ntiles, tile, lane, c0, c1);
+    if (super_tile_of(sidx, w, P.ntx, P.nty, tile, tx, ty)) build_map_tile<kAA>(P, map, ntiles, tile, lane, c0, c1);
     if (lane == 0) {
         s_cap[w][0] = c0;
         s_cap[w][1] = c1;
@@ -171,8 +224,9 @@ __device__ inline void build_map_super(const MapParams& P, void* map, int64_t nt
     }
 }
 
+template <bool kAA>
 __global__ __launch_bounds__(256) void k_build_map(MapParams P, void* map, int64_t ntiles) {
-    build_map_super(P, map, ntiles, blockIdx.x);
+    build_map_super<kAA>(P, map, ntiles, blockIdx.x);
 }
 
 // Cap of 32x32 block b (2x2 super-tiles) from its super-tile caps; one
@@ -228,9 +282,12 @@ hipError_t launch_map_unpack(const void* map, int32_t W, int32_t H, int32_t fmt,
     return hipGetLastError();
 }
 
-hipError_t launch_build_map(const MapParams& P, void* map, hipStream_t stream) {
+hipError_t launch_build_map(const MapParams& P, void* map, bool aa, hipStream_t stream) {
     MapLayout L = map_layout(P.W, P.H, P.fmt);
-    hipLaunchKernelGGL(k_build_map, dim3(unsigned(L.nsup)), dim3(256), 0, stream, P, map, L.ntiles);
+    if (aa)
+        hipLaunchKernelGGL(k_build_map<true>, dim3(unsigned(L.nsup)), dim3(256), 0, stream, P, map, L.ntiles);
+    else
+        hipLaunchKernelGGL(k_build_map<false>, dim3(unsigned(L.nsup)), dim3(256), 0, stream, P, map, L.ntiles);
     hipLaunchKernelGGL(k_block_caps, dim3(unsigned((L.nblk + 63) / 64)), dim3(64), 0, stream, map, L.ntiles, P.fmt,
                        L.ntx, L.nty, L.nblk);
     return hipGetLastError();

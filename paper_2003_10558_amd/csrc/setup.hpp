@@ -205,14 +205,16 @@ __global__ __launch_bounds__(256) void k_setup_tris(const float* __restrict__ xy
         else
             S = scale3(add3(add3(scale3(a, ws), scale3(b, wt)), scale3(c, wp)), 1.0f / (ws + wt + wp));
         float sl = sqrtf(dot3(S, S));
-        bool wide = !(sl > 1e-6f);
-        float rho = kPi;
+        const bool degenerate = !(sl > 1e-6f);  // plane of the unit vertices through O
+        bool wide = degenerate;
+        float rho = kPi, sh_rim = 0.0f;
         if (!wide) {
             S = scale3(S, 1.0f / sl);
             // radius from the actual vertex chords, robust to rounding in S
             float3 da = sub3(a, S), db = sub3(b, S), dc = sub3(c, S);
             float ch2 = fmaxf(dot3(da, da), fmaxf(dot3(db, db), dot3(dc, dc)));
-            rho = 2.0f * asinf(fminf(1.0f, 0.5f * sqrtf(ch2)));
+            sh_rim = fminf(1.0f, 0.5f * sqrtf(ch2));  // sine of half the exact radius (miter rim)
+            rho = 2.0f * asinf(sh_rim);
             rho = rho * (1.0f + kCapRelMargin) + kCapAbsMargin;
             wide = !(rho < kHalfPi);
         }
@@ -221,14 +223,15 @@ __global__ __launch_bounds__(256) void k_setup_tris(const float* __restrict__ xy
             float sh, chh;
             sincosf(0.5f * rho, &sh, &chh);
             c0 = make_float4(S.x, S.y, S.z, sh);
-            c1 = make_float4(chh, sinf(rho), 0.0f, rho);
+            c1 = make_float4(chh, sinf(rho), 0.0f, sh_rim);
             // finest level whose cell radius bound (pi/4)/2^L still covers rho
             while (L < kMaxLevel && rho <= kQuarterPi / float(1 << (L + 1))) ++L;
             if (rho > kQuarterPi) L = 0;
             bkt = cell_of(S, L);
         } else {
-            c0 = make_float4(0.0f, 0.0f, 1.0f, 1.0f);
-            c1 = make_float4(0.0f, 1.0f, kCapWide, kPi);
+            // no culling; the centre and rim still define the miter unless degenerate
+            c0 = degenerate ? make_float4(0.0f, 0.0f, 1.0f, 1.0f) : make_float4(S.x, S.y, S.z, 1.0f);
+            c1 = make_float4(0.0f, 1.0f, kCapWide, sh_rim);
             bkt = uint32_t(level_base(0));  // level 0, face 0: every tile looks at level 0
         }
     } else {

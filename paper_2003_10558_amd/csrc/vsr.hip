@@ -3,5 +3,7 @@
 //   setup.hpp   per-triangle setup, ordering, cap index (step 2)
 //   raster.hpp  conservative binning + rasterizer       (steps 3, 4)
 //   submit.hpp  batched views                           (step 5)
+//   resolve.hpp fragment data from barycentrics         (section 1.1.4)
+//   aa.hpp      aliasing-free coverage                  (sections 1.1.1, 1.1.2, 1.4)
 //   api.hpp     C ABI (include/vsr.h)
 #include "api.hpp"

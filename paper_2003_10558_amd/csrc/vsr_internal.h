@@ -83,6 +83,15 @@ __host__ __device__ inline MapLayout map_layout(int32_t w, int32_t h, int32_t fm
     return m;
 }
 
+// Map with anti-aliasing data (built with VSR_MAP_AA): the plain layout,
+// then one float per pixel, tile-major like the directions, holding the
+// section 1.1.1 global delta (0 for a pixel without direction).
+__host__ __device__ inline int64_t aa_delta_off(int32_t w, int32_t h, int32_t fmt) { return map_layout(w, h, fmt).bytes; }
+__host__ __device__ inline int64_t aa_map_bytes(int32_t w, int32_t h, int32_t fmt) {
+    MapLayout m = map_layout(w, h, fmt);
+    return m.bytes + align256(m.ntiles * kTilePix * 4);
+}
+
 // Per-view constants of the map generator, computed on the host in double
 // precision and rounded once to float.
 struct MapParams {
@@ -344,7 +353,11 @@ constexpr float kBinWide = 2.0f;
 // Tile cap record: c0 = (centre.xyz, sin(rho/2)), c1 = (cos(rho/2), sin(rho), flags, 0)
 constexpr float kCapWide = 1.0f;   // cap radius >= pi/2: no culling possible
 constexpr float kCapEmpty = 2.0f;  // no pixel with a direction
-// Triangle cap record: same layout; flags kCapWide when the cap is useless.
+// Triangle cap record: same layout, widened by the FP32 margins; flags
+// kCapWide when the cap is useless for culling.  Its fourth word c1.w holds
+// the sine of half the exact (unwidened) radius of the section 1.1.2
+// smallest circle, whose centre is c0.xyz also for wide caps; 0 when the
+// circle is degenerate (no miter).
 
 // Conservative test: may triangle (cap tc0/tc1, oriented unit edge normals
 // n0..n2) cover any pixel of the tile (cap c0/c1)?  Never returns false for

@@ -99,6 +99,41 @@ def resolve(scene: Scene, view, frame: Frame, vattr: Optional[torch.Tensor] = No
     return bary, attr
 
 
+@dataclass
+class AAFrame:
+    coverage: torch.Tensor    # float32 [H, W], m_b in [0, 1]
+    depth_pass: torch.Tensor  # float32 [H, W], sum of m_fc * r
+    dominant: torch.Tensor    # uint32 as int32 storage, [H, W]
+    lost: torch.Tensor        # int32 [1]: pixels whose fragment list overflowed
+    map: torch.Tensor
+    bins: torch.Tensor
+    view_eff: object
+
+
+def render_aa(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, bin_depth: int = DEFAULT_BIN_DEPTH,
+              bin_flags: int = 0, stream=None, frame: Optional[AAFrame] = None,
+              stats: Optional[torch.Tensor] = None) -> AAFrame:
+    """Aliasing-free frame: build_map (VSR_MAP_AA) -> bin -> vsr_aa_raster."""
+    dev = scene.device
+    H, W = view.height, view.width
+    if frame is None:
+        frame = AAFrame(torch.empty((H, W), dtype=torch.float32, device=dev),
+                        torch.empty((H, W), dtype=torch.float32, device=dev),
+                        torch.empty((H, W), dtype=torch.int32, device=dev),
+                        torch.empty(1, dtype=torch.int32, device=dev),
+                        _buffer(vsr.vsr_aa_map_bytes(W, H, fmt), dev),
+                        _buffer(vsr.vsr_bin_bytes(W, H, bin_depth), dev), None)
+    frame.view_eff = vsr.vsr_build_map(view, fmt, vsr.VSR_MAP_AA, frame.map, stream)
+    vsr.vsr_bin(view, fmt, frame.map, scene.setup, scene.ntri, bin_depth, bin_flags, frame.bins, stream)
+    if stats is None:
+        vsr.vsr_aa_raster(view, fmt, frame.map, scene.setup, scene.ntri, frame.bins, bin_depth, frame.coverage,
+                          frame.depth_pass, frame.dominant, frame.lost, stream)
+    else:
+        vsr.vsr_aa_raster_stats(view, fmt, frame.map, scene.setup, scene.ntri, frame.bins, bin_depth,
+                                frame.coverage, frame.depth_pass, frame.dominant, frame.lost, stats, stream)
+    return frame
+
+
 class Batch:
     """Workspace + outputs for vsr_submit over a fixed list of (scene, view)."""
 

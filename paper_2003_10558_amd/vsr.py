@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libvsr.so")
 VSR_OK, VSR_E_ARG, VSR_E_SPACE, VSR_E_RANGE, VSR_E_HIP = 0, -1, -2, -3, -4
 VSR_MAP_F32, VSR_MAP_OCT16 = 0, 1
 VSR_STRICT = 1
+VSR_MAP_AA = 2
 VSR_BIN_ALL = 1
 VSR_BIN_BLOCKS, VSR_BIN_SUPERTILES = 2, 4
 VSR_NO_HIT = 0xFFFFFFFF
@@ -69,6 +70,11 @@ _lib.vsr_render_bytes.argtypes = [_i32, _i32]
 _lib.vsr_render_bytes.restype = _i64
 _lib.vsr_render.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp]
 _lib.vsr_resolve.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _vp, _i32, _u32, _vp, _vp, _vp]
+_lib.vsr_aa_map_bytes.argtypes = [_i32, _i32, _i32]
+_lib.vsr_aa_map_bytes.restype = _i64
+_lib.vsr_aa_raster.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp, _vp]
+_lib.vsr_aa_raster_stats.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp,
+                                     _vp, _vp]
 _lib.vsr_submit_bytes.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32]
 _lib.vsr_submit_bytes.restype = _i64
 _lib.vsr_submit.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32, _vp, _i64, _vp]
@@ -86,7 +92,8 @@ for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin",
-           "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_resolve", "vsr_submit_bytes",
+           "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_resolve", "vsr_aa_map_bytes",
+           "vsr_aa_raster", "vsr_aa_raster_stats", "vsr_submit_bytes",
            "vsr_submit_table_bytes", "vsr_submit_table_offset", "vsr_submit_table", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
 
 
@@ -203,6 +210,25 @@ def vsr_resolve(view, fmt: int, map_buf, xyz, ntri: int, tri_id, vattr, nattr: i
     v = make_view(view)
     _check(_lib.vsr_resolve(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(xyz), ntri, _ptr(tri_id), _ptr(vattr), nattr,
                             flags, _ptr(bary), _ptr(attr), _stream(stream)))
+
+
+def vsr_aa_map_bytes(width: int, height: int, fmt: int = VSR_MAP_F32) -> int:
+    return _size(_lib.vsr_aa_map_bytes(width, height, fmt), "vsr_aa_map_bytes")
+
+
+def vsr_aa_raster(view, fmt: int, map_buf, setup_buf, ntri: int, bins, bin_depth: int, coverage, depth_pass,
+                  dominant, lost=None, stream=None) -> None:
+    v = make_view(view)
+    _check(_lib.vsr_aa_raster(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), ntri, _ptr(bins), bin_depth,
+                              _ptr(coverage), _ptr(depth_pass), _ptr(dominant), _ptr(lost), _stream(stream)))
+
+
+def vsr_aa_raster_stats(view, fmt: int, map_buf, setup_buf, ntri: int, bins, bin_depth: int, coverage, depth_pass,
+                        dominant, lost, stats, stream=None) -> None:
+    v = make_view(view)
+    _check(_lib.vsr_aa_raster_stats(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), ntri, _ptr(bins),
+                                    bin_depth, _ptr(coverage), _ptr(depth_pass), _ptr(dominant), _ptr(lost),
+                                    _ptr(stats), _stream(stream)))
 
 
 def vsr_submit_bytes(jobs, fmt: int, mode: int = 0, bin_depth: int = 1024) -> int:

@@ -153,3 +153,35 @@ def test_resolve_argument_errors(vsr):
             vsr.vsr_resolve(v, 0, a["map_buf"], a["xyz"], a["ntri"], a["tri_id"], a["vattr"], a["nattr"],
                             a["flags"], a["bary"], a["attr"], stream=0)
         assert e.value.code == vsr.VSR_E_ARG, c
+
+
+def test_aa_sizes_and_argument_errors(vsr):
+    # the AA map appends one float of global delta per pixel to the map
+    for w, h, fmt in [(256, 256, 0), (9, 9, 1), (1920, 1080, 0)]:
+        plain = vsr.vsr_map_bytes(w, h, fmt)
+        tiles = ((w + 7) // 8) * ((h + 7) // 8)
+        assert vsr.vsr_aa_map_bytes(w, h, fmt) == plain + (tiles * 64 * 4 + 255) // 256 * 256
+    with pytest.raises(vsr.VsrError):
+        vsr.vsr_aa_map_bytes(0, 5, 0)
+    v = synth.View(64, 32, 0.3, 0.5, 0.9, 120.0)
+    # a plain-sized buffer is too small for an AA map; unknown flags refused
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.vsr_build_map(v, 0, vsr.VSR_MAP_AA, _FakeBuf(256, vsr.vsr_map_bytes(64, 32, 0)), stream=0)
+    assert e.value.code == vsr.VSR_E_SPACE
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.vsr_build_map(v, 0, 8, _FakeBuf(256, 10 ** 8), stream=0)
+    assert e.value.code == vsr.VSR_E_ARG
+    ok = dict(map_buf=_FakeBuf(256, 1), setup=_FakeBuf(512, 1), ntri=10, bins=_FakeBuf(768, 1), depth=64,
+              cov=_FakeBuf(1024, 1), dp=_FakeBuf(2048, 1), dom=_FakeBuf(4096, 1), lost=None)
+    for c in [dict(map_buf=None), dict(cov=None), dict(dom=_FakeBuf(4098, 1)), dict(lost=_FakeBuf(8194, 1)),
+              dict(depth=0), dict(ntri=-1), dict(bins=_FakeBuf(770, 1))]:
+        a = dict(ok)
+        a.update(c)
+        with pytest.raises(vsr.VsrError) as e:
+            vsr.vsr_aa_raster(v, 0, a["map_buf"], a["setup"], a["ntri"], a["bins"], a["depth"], a["cov"], a["dp"],
+                              a["dom"], a["lost"], stream=0)
+        assert e.value.code == vsr.VSR_E_ARG, c
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.vsr_aa_raster_stats(v, 0, ok["map_buf"], ok["setup"], 10, ok["bins"], 64, ok["cov"], ok["dp"],
+                                ok["dom"], None, None, stream=0)
+    assert e.value.code == vsr.VSR_E_ARG
