@@ -14,8 +14,10 @@ Also reported: the plain per-view form (vsr_build_map -> vsr_bin ->
 vsr_raster, one view at a time) and its per-view latency percentiles, the
 batched form without the setup, the setup alone, the rasterizer's roofline
 (algorithmic lane-ops per covered fragment x covered fragments / measured
-kernel time, against the FP32 VALU peak), and the FP64 CPU oracle timed on a
-bounded pixel sample on the host cores.
+kernel time, against the FP32 VALU peak), the aliasing-free variant
+(vsr_build_map with VSR_MAP_AA -> vsr_bin -> vsr_aa_raster) per view with its
+own VALU roofline, the fragment-data step, and the FP64 CPU oracle timed on
+a bounded pixel sample on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --summarize DIR...   (rocprofv3 CSV output -> text summary)
@@ -32,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: non-packed FP32 VALU
 PEAK_HBM = 8.0e12
+OPS_PER_AA_FRAGMENT = 36                     # 3 edge dots (9) + chord (6) + miter (1) + 4 steps (12) + 3 min + cmp + g.N (3) + div
 OPS_PER_FRAGMENT = 20                        # 3 edge dots (9) + min3 + cmp + g.N (3) + rcp + mul + cmp64 + 2 sel
 BIN_BYTES_PER_TRI = 64                       # cap (16 B) + three edge normals (48 B), read once
 BIN_BYTES_PER_TILE = 36                      # tile cap (32 B) read, list length (4 B) written
@@ -251,6 +254,47 @@ def main():
         f"{resolve_bytes / resolve_ms / 1e6:.0f} GB/s algorithmic")
     del bary_t, attr_t
 
+    # ---------------- aliasing-free coverage (sections 1.1.1, 1.1.2, 1.4), plain per-view path
+    aaf = pipeline.render_aa(scene, views[0], fmt=fmt, bin_depth=depth)
+    torch.cuda.synchronize()
+    n_aa = 16 if not args.profile else 4
+    aa_lat, aa_bin, aa_rast, aa_map = [], [], [], []
+    for rep in range(2):
+        for v in views[:n_aa]:
+            e0, ea, e1, e2 = ev(), ev(), ev(), ev()
+            e0.record(stream)
+            vsr.vsr_build_map(v, fmt, vsr.VSR_MAP_AA, aaf.map)
+            ea.record(stream)
+            vsr.vsr_bin(v, fmt, aaf.map, scene.setup, scene.ntri, depth, 0, aaf.bins)
+            e1.record(stream)
+            vsr.vsr_aa_raster(v, fmt, aaf.map, scene.setup, scene.ntri, aaf.bins, depth, aaf.coverage,
+                              aaf.depth_pass, aaf.dominant, aaf.lost)
+            e2.record(stream)
+            e2.synchronize()
+            if rep == 1:
+                aa_lat.append(e0.elapsed_time(e2))
+                aa_map.append(e0.elapsed_time(ea))
+                aa_bin.append(ea.elapsed_time(e1))
+                aa_rast.append(e1.elapsed_time(e2))
+    aa_lost = int(aaf.lost.item())
+    aa_ms = float(np.mean(aa_lat))
+    aa_stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    F_aa, F_aa_proc, aa_tests, aa_skipped = [], [], [], []
+    for q in range(4):
+        v = views[q]
+        pipeline.render_aa(scene, v, fmt=fmt, bin_depth=depth, frame=aaf, stats=aa_stats, no_skip=True)
+        torch.cuda.synchronize()
+        F_aa.append(int(aa_stats[1].item()))
+        pipeline.render_aa(scene, v, fmt=fmt, bin_depth=depth, frame=aaf, stats=aa_stats)
+        torch.cuda.synchronize()
+        F_aa_proc.append(int(aa_stats[1].item()))
+        aa_tests.append(int(aa_stats[0].item()))
+        aa_skipped.append(int(aa_stats[2].item()))
+    F_aa_mean = float(np.mean(F_aa))
+    log(f"aa: {aa_ms:.3f} ms/view (map {np.mean(aa_map):.3f}, bin {np.mean(aa_bin):.3f}, raster "
+        f"{np.mean(aa_rast):.3f}), lost pixels {aa_lost}; fragments per frame (all depths) {F_aa}, found with "
+        f"skipping {F_aa_proc}, mask evaluations {aa_tests}, triangles skipped {aa_skipped}")
+
     # ---------------- single-view fused path (vsr_build_map + vsr_render)
     ffr = pipeline.render_fused(scene, views[0], fmt=fmt)
     torch.cuda.synchronize()
@@ -402,11 +446,20 @@ def main():
                         "frac": resolve_bytes / (resolve_ms * 1e-3) / PEAK_HBM,
                         "traffic": traffic_from_profiles("k_resolve"), "kernel": "k_resolve",
                         "kernel_ms": resolve_ms, "algorithmic_bytes": resolve_bytes, "winners": winners}
+    # aliasing-free raster against the VALU peak: lane-ops per fragment (all depths)
+    t_aa = float(np.mean(aa_rast)) * 1e-3
+    achieved_aa = OPS_PER_AA_FRAGMENT * F_aa_mean / t_aa
+    roofline_aa = {"bound": "alu", "achieved": achieved_aa / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
+                   "unit": "T lane-ops/s", "frac": achieved_aa / PEAK_VALU_LANE_OPS,
+                   "traffic": traffic_from_profiles("k_aa_raster<false>"), "kernel": "k_aa_raster",
+                   "kernel_ms": t_aa * 1e3, "fragments_per_launch": F_aa_mean,
+                   "ops_per_fragment": OPS_PER_AA_FRAGMENT}
     # the whole batched step per view: covered-fragment work and frame bytes
     per_view_s = submit_ms * 1e-3 / len(views)
     frame_bytes = (12 if fmt == vsr.VSR_MAP_F32 else 4) * 2073600 + 68 * tris.shape[1] + 8 * 2073600
     roofline_step = {"valu_frac": OPS_PER_FRAGMENT * F_mean / per_view_s / PEAK_VALU_LANE_OPS,
                      "hbm_frac": frame_bytes / per_view_s / PEAK_HBM, "per_view_us": per_view_s * 1e6}
+    log(f"roofline: k_aa_raster {roofline_aa['achieved']:.2f} T lane-ops/s ({roofline_aa['frac']:.3f} of VALU)")
     log(f"roofline: k_bin {roofline['achieved']:.0f} GB/s ({roofline['frac']:.3f} of HBM), k_raster "
         f"{roofline_raster['achieved']:.2f} T lane-ops/s ({roofline_raster['frac']:.3f} of VALU), step per view "
         f"{roofline_step['valu_frac']:.3f} VALU / {roofline_step['hbm_frac']:.3f} HBM")
@@ -472,6 +525,11 @@ def main():
         "roofline_step": roofline_step,
         "roofline_resolve": roofline_resolve,
         "resolve_ms": resolve_ms,
+        "aa": {"fps": 1e3 / aa_ms, "ms_per_view": aa_ms, "map_ms": float(np.mean(aa_map)),
+               "bin_ms": float(np.mean(aa_bin)), "raster_ms": float(np.mean(aa_rast)), "lost_pixels": aa_lost,
+               "fragments_per_frame": F_aa_mean, "fragments_found_with_skipping": float(np.mean(F_aa_proc)),
+               "mask_evaluations": float(np.mean(aa_tests)), "triangles_skipped": float(np.mean(aa_skipped))},
+        "roofline_aa": roofline_aa,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -247,11 +247,14 @@ int vsr_aa_raster(const vsr_view* v, int32_t fmt, const void* map, const void* s
 
 /* Instrumented vsr_aa_raster (same images) that also counts, into the device
  * array stats[4] of uint64: pixel-triangle mask evaluations (pixels with a
- * direction x triangles tested), fragments inserted, triangles skipped by
- * the wave's saturation-depth test, tiles.  For measurement. */
+ * direction x triangles tested), fragments (m > 0, plane in front) found,
+ * triangles skipped by the wave's saturation-depth test, tiles.  With
+ * no_skip != 0 every listed triangle is tested, so stats[1] is then the
+ * number of (pixel, triangle) fragments of the frame at all depths.  For
+ * measurement; slower than vsr_aa_raster. */
 int vsr_aa_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
                         const void* bins, int32_t bin_depth, float* coverage, float* depth_pass, uint32_t* dominant,
-                        uint32_t* lost, uint64_t* stats, void* stream);
+                        uint32_t* lost, uint64_t* stats, int32_t no_skip, void* stream);
 
 /* ------------------------------------------------------------- batches */
 

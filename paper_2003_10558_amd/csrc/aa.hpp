@@ -21,9 +21,9 @@
 // Records are staged through LDS eight triangles at a time (lane l loads
 // word (l & 7) of triangle l >> 3: four record words and two cap words; the
 // lane holding the cap's second word turns the rim into the two constants
-// of the miter value).  A triangle whose plane cannot come nearer, anywhere
-// in the tile, than the saturation depth of every pixel is skipped by the
-// whole wave.
+// of the miter value, and the seventh lane decides whether the triangle can
+// matter at all: one whose plane cannot come nearer, anywhere in the tile,
+// than the saturation depth of every pixel is skipped by the whole wave).
 #pragma once
 #include "raster.hpp"
 
@@ -43,6 +43,7 @@ struct AAArgs {
     uint32_t* dom;
     uint32_t* lost;                 // pixels whose list overflowed unsaturated
     unsigned long long* stats;      // optional: tests, fragments inserted, triangles skipped, tiles
+    int32_t no_skip;                // instrumented variant only: test every listed triangle
     Rot rot;
 };
 
@@ -65,6 +66,8 @@ struct FragList {
         lost = false;
     }
 
+    // The loops are unrolled with constant indices (the list stays in
+    // registers); a step that no lane of the wave needs is branched over.
     __device__ inline void insert(float rr, uint32_t ii, float mm) {
         if (!frag_less(rr, ii, rsat, idsat)) return;  // behind the saturated prefix: zero share
         float cr = rr, cm = mm;
@@ -129,6 +132,15 @@ struct FragList {
     }
 };
 
+// Bits 6, 14, ..., 62 of a ballot (lane 8t + 6 of each triangle's group of
+// eight lanes) packed into bits 0..7.
+__device__ inline uint32_t pack_group_bits(uint64_t b) {
+    uint32_t out = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) out |= uint32_t((b >> (8 * t + 6)) & 1ull) << t;
+    return out;
+}
+
 __device__ inline float gpstep(float x, float delta) { return fminf(fmaxf(fmaf(delta, x, 0.5f), 0.0f), 1.0f); }
 
 // Miter constants from the rim's half-angle sine sh: the value
@@ -140,7 +152,8 @@ __device__ inline float2 miter_consts(float sh) {
     return make_float2(sh / ch, 0.25f / (sh * ch));
 }
 
-// One triangle against the lane's pixel.  c0 = (S, -), c1 = (a, b, -, -).
+// One triangle against the lane's pixel: inserts its fragment, if any.
+// c0 = (S, -), c1 = (a, b, -, -).
 __device__ inline bool aa_rec(float4 r0, float4 r1, float4 r2, float4 r3, float4 c0, float4 c1, float3 g, float delta,
                               FragList& L) {
     float e0 = fmaf(r0.z, g.z, fmaf(r0.y, g.y, r0.x * g.x));
@@ -153,7 +166,7 @@ __device__ inline bool aa_rec(float4 r0, float4 r1, float4 r2, float4 r3, float4
     if (m > 0.0f) {
         float dn = fmaf(r2.w, g.z, fmaf(r1.w, g.y, r0.w * g.x));
         if (dn > 0.0f) {
-            L.insert(r3.x / dn, __float_as_uint(r3.z), m);
+            L.insert(r3.x * __builtin_amdgcn_rcpf(dn), __float_as_uint(r3.z), m);
             return true;
         }
     }
@@ -168,7 +181,7 @@ __device__ inline float plane_min_depth(float3 N, float d, float3 c, float cr, f
     float ca = dot3(c, N);
     if (ca >= cr) return d;
     float sa = sqrtf(fmaxf(0.0f, 1.0f - ca * ca));
-    float cm = fmaf(ca, cr, sa * sr);  // cos(angle(c, N) - radius)
+    float cm = fmaf(ca, cr, sa * sr) + 1e-6f;  // cos(angle(c, N) - radius), plus FP32 slack
     return cm > 0.0f ? d / cm : __int_as_float(0x7F800000);
 }
 
@@ -199,15 +212,15 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
     const bool twide = tc1.z == kCapWide;
     unsigned long long n_test = 0, n_frag = 0, n_skip = 0;
 
-    auto visit = [&](float4 r0, float4 r1, float4 r2, float4 r3, float4 c0, float4 c1, float rmax) {
-        // rmax: largest saturation depth over the wave (wave-uniform)
-        if (rmax < __int_as_float(0x7F800000)) {
-            float rmin = plane_min_depth(f3(r0.w, r1.w, r2.w), r3.x, tcen, tcr, tsr, twide);
-            if (rmin * (1.0f - 1e-4f) > rmax) {
-                if (kStats) ++n_skip;
-                return;
-            }
-        }
+    const bool may_skip = !(kStats && A.no_skip);
+    // May a triangle be skipped by the whole wave?  rmax: largest saturation
+    // depth over the wave's pixels (taken before the triangle's group, so at
+    // least the current one).
+    auto skippable = [&](float3 N, float d, float rmax) {
+        if (!may_skip || !(rmax < __int_as_float(0x7F800000))) return false;
+        return plane_min_depth(N, d, tcen, tcr, tsr, twide) * (1.0f - 1e-4f) > rmax;
+    };
+    auto visit = [&](float4 r0, float4 r1, float4 r2, float4 r3, float4 c0, float4 c1) {
         bool f = has_dir && aa_rec(r0, r1, r2, r3, c0, c1, g, delta, L);
         if (kStats) {
             ++n_test;
@@ -220,32 +233,51 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
         const uint32_t* lst = lists + tile * A.depth;
         const uint32_t sub = uint32_t(lane) >> 3, part = uint32_t(lane) & 7u;
         const uint32_t ngroups = (count + 7u) >> 3;
-        for (uint32_t gi = 0; gi < ngroups; ++gi) {
-            const uint32_t e = gi * 8u + sub;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        // this lane's word of triangle `sub` of a group: record words 0..3,
+        // cap words 4..5, and for lane 6 the plane (N, d) of the skip test
+        auto fetch = [&](uint32_t e) {
+            float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
             if (e < count) {
                 const uint32_t rk = lst[e];
+                const float4* rec = S.rec + 4 * int64_t(rk);
                 if (part < 4u) {
-                    v = S.rec[4 * int64_t(rk) + part];
+                    w = rec[part];
                 } else if (part < 6u) {
-                    v = S.cap[2 * int64_t(rk) + (part - 4u)];
-                    if (part == 5u) {
-                        float2 mc = miter_consts(v.w);
-                        v = make_float4(mc.x, mc.y, 0.f, 0.f);
-                    }
+                    w = S.cap[2 * int64_t(rk) + (part - 4u)];
+                } else if (part == 6u) {
+                    const float* rw = reinterpret_cast<const float*>(rec);
+                    w = make_float4(rw[3], rw[7], rw[11], rw[12]);
                 }
             }
+            return w;
+        };
+        float4 v = fetch(sub);  // group 0; the next group is fetched while one is tested
+        for (uint32_t gi = 0; gi < ngroups; ++gi) {
+            const float rmax = __uint_as_float(wave_max_u32_dpp(__float_as_uint(L.rsat)));
+            const bool present = gi * 8u + sub < count;
+            bool live = present;
+            float4 st = v;
+            if (part == 5u) {
+                float2 mc = miter_consts(v.w);
+                st = make_float4(mc.x, mc.y, 0.f, 0.f);
+            } else if (part == 6u && present) {
+                // this lane decides for the whole wave whether the triangle can matter
+                live = !skippable(f3(v.x, v.y, v.z), v.w, rmax);
+            }
+            // bit t: triangle t of the group is to be tested
+            const uint32_t todo = pack_group_bits(__ballot(live && part == 6u));
+            if (kStats) n_skip += uint32_t(__popc(pack_group_bits(__ballot(present && part == 6u)))) -
+                                  uint32_t(__popc(todo));
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            stg[lane] = v;
+            stg[lane] = st;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            float rmax = __uint_as_float(wave_max_u32_dpp(__float_as_uint(L.rsat)));
-            const uint32_t nt = min(8u, count - gi * 8u);
-            for (uint32_t t = 0; t < nt; ++t) {
-                const float4* w = stg + 8 * t;
-                visit(w[0], w[1], w[2], w[3], w[4], w[5], rmax);
+            if (gi + 1 < ngroups) v = fetch((gi + 1) * 8u + sub);
+            for (uint32_t m = todo; m; m &= m - 1) {
+                const float4* w = stg + 8 * uint32_t(__ffs(m) - 1);
+                visit(w[0], w[1], w[2], w[3], w[4], w[5]);
             }
         }
     } else {
@@ -259,8 +291,13 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
                 const float4* r = S.rec + 4 * int64_t(rk);
                 float4 c1 = S.cap[2 * int64_t(rk) + 1];
                 float2 mc = miter_consts(c1.w);
+                float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
                 float rmax = __uint_as_float(wave_max_u32_dpp(__float_as_uint(L.rsat)));
-                visit(r[0], r[1], r[2], r[3], S.cap[2 * int64_t(rk)], make_float4(mc.x, mc.y, 0.f, 0.f), rmax);
+                if (skippable(f3(r0.w, r1.w, r2.w), r3.x, rmax)) {
+                    if (kStats) ++n_skip;
+                    continue;
+                }
+                visit(r0, r1, r2, r3, S.cap[2 * int64_t(rk)], make_float4(mc.x, mc.y, 0.f, 0.f));
             }
         });
     }
@@ -278,8 +315,8 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
         uint32_t c = uint32_t(__popcll(__ballot(L.lost)));
         if (lane == 0 && c) atomicAdd(A.lost, c);
     }
+    const unsigned long long npix = kStats ? (unsigned long long)__popcll(__ballot(has_dir)) : 0ull;
     if (kStats && lane == 0) {
-        unsigned long long npix = (unsigned long long)__popcll(__ballot(has_dir));
         atomicAdd(&A.stats[0], n_test * npix);
         atomicAdd(&A.stats[1], n_frag);
         atomicAdd(&A.stats[2], n_skip);
@@ -298,7 +335,7 @@ __global__ __launch_bounds__(256) void k_aa_raster(AAArgs A) {
 
 hipError_t launch_aa_raster(const void* map, int32_t W, int32_t H, int32_t fmt, const Rot& R, const void* setup,
                             int64_t n, const void* bins, int32_t depth, float* cov, float* dpass, uint32_t* dom,
-                            uint32_t* lost, unsigned long long* stats, hipStream_t st) {
+                            uint32_t* lost, unsigned long long* stats, int32_t no_skip, hipStream_t st) {
     MapLayout ML = map_layout(W, H, fmt);
     AAArgs A;
     A.map = map;
@@ -316,6 +353,7 @@ hipError_t launch_aa_raster(const void* map, int32_t W, int32_t H, int32_t fmt, 
     A.dom = dom;
     A.lost = lost;
     A.stats = stats;
+    A.no_skip = no_skip;
     A.rot = R;
     int64_t blocks = (ML.ntiles + 3) / 4;
     if (lost) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, lost, int64_t(1));

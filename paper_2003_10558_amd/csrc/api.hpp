@@ -237,7 +237,8 @@ int vsr_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const void
 
 static int aa_raster_common(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
                             const void* bins, int32_t bin_depth, float* coverage, float* depth_pass,
-                            uint32_t* dominant, uint32_t* lost, uint64_t* stats, void* stream, const char* what) {
+                            uint32_t* dominant, uint32_t* lost, uint64_t* stats, int32_t no_skip, void* stream,
+                            const char* what) {
     int rc = check_view_buffers(v, fmt);
     if (rc != VSR_OK) return rc;
     if (!map || !setup || !bins || !coverage || !depth_pass || !dominant || !aligned(map) || !aligned(setup) ||
@@ -251,7 +252,7 @@ static int aa_raster_common(const vsr_view* v, int32_t fmt, const void* map, con
     if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
     return hip_status(launch_aa_raster(map, v->width, v->height, fmt, rot_of(v->rot), setup, ntri, bins, bin_depth,
                                        coverage, depth_pass, dominant, lost,
-                                       reinterpret_cast<unsigned long long*>(stats), hipStream_t(stream)),
+                                       reinterpret_cast<unsigned long long*>(stats), no_skip, hipStream_t(stream)),
                       what);
 }
 
@@ -259,15 +260,15 @@ int vsr_aa_raster(const vsr_view* v, int32_t fmt, const void* map, const void* s
                   int32_t bin_depth, float* coverage, float* depth_pass, uint32_t* dominant, uint32_t* lost,
                   void* stream) {
     return aa_raster_common(v, fmt, map, setup, ntri, bins, bin_depth, coverage, depth_pass, dominant, lost, nullptr,
-                            stream, "vsr_aa_raster");
+                            0, stream, "vsr_aa_raster");
 }
 
 int vsr_aa_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
                         const void* bins, int32_t bin_depth, float* coverage, float* depth_pass, uint32_t* dominant,
-                        uint32_t* lost, uint64_t* stats, void* stream) {
+                        uint32_t* lost, uint64_t* stats, int32_t no_skip, void* stream) {
     if (!stats) return fail(VSR_E_ARG, "stats is NULL");
     return aa_raster_common(v, fmt, map, setup, ntri, bins, bin_depth, coverage, depth_pass, dominant, lost, stats,
-                            stream, "vsr_aa_raster_stats");
+                            no_skip, stream, "vsr_aa_raster_stats");
 }
 
 int64_t vsr_render_bytes(int32_t width, int32_t height) {

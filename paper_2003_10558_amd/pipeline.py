@@ -112,7 +112,7 @@ class AAFrame:
 
 def render_aa(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, bin_depth: int = DEFAULT_BIN_DEPTH,
               bin_flags: int = 0, stream=None, frame: Optional[AAFrame] = None,
-              stats: Optional[torch.Tensor] = None) -> AAFrame:
+              stats: Optional[torch.Tensor] = None, no_skip: bool = False) -> AAFrame:
     """Aliasing-free frame: build_map (VSR_MAP_AA) -> bin -> vsr_aa_raster."""
     dev = scene.device
     H, W = view.height, view.width
@@ -130,7 +130,8 @@ def render_aa(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, bin_depth: int = D
                           frame.depth_pass, frame.dominant, frame.lost, stream)
     else:
         vsr.vsr_aa_raster_stats(view, fmt, frame.map, scene.setup, scene.ntri, frame.bins, bin_depth,
-                                frame.coverage, frame.depth_pass, frame.dominant, frame.lost, stats, stream)
+                                frame.coverage, frame.depth_pass, frame.dominant, frame.lost, stats, no_skip,
+                                stream)
     return frame
 
 

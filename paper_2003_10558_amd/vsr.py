@@ -74,7 +74,7 @@ _lib.vsr_aa_map_bytes.argtypes = [_i32, _i32, _i32]
 _lib.vsr_aa_map_bytes.restype = _i64
 _lib.vsr_aa_raster.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp, _vp]
 _lib.vsr_aa_raster_stats.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp,
-                                     _vp, _vp]
+                                     _vp, _i32, _vp]
 _lib.vsr_submit_bytes.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32]
 _lib.vsr_submit_bytes.restype = _i64
 _lib.vsr_submit.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32, _vp, _i64, _vp]
@@ -224,11 +224,11 @@ def vsr_aa_raster(view, fmt: int, map_buf, setup_buf, ntri: int, bins, bin_depth
 
 
 def vsr_aa_raster_stats(view, fmt: int, map_buf, setup_buf, ntri: int, bins, bin_depth: int, coverage, depth_pass,
-                        dominant, lost, stats, stream=None) -> None:
+                        dominant, lost, stats, no_skip: bool = False, stream=None) -> None:
     v = make_view(view)
     _check(_lib.vsr_aa_raster_stats(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), ntri, _ptr(bins),
                                     bin_depth, _ptr(coverage), _ptr(depth_pass), _ptr(dominant), _ptr(lost),
-                                    _ptr(stats), _stream(stream)))
+                                    _ptr(stats), int(bool(no_skip)), _stream(stream)))
 
 
 def vsr_submit_bytes(jobs, fmt: int, mode: int = 0, bin_depth: int = 1024) -> int:
