@@ -50,7 +50,8 @@ def build(force: bool = True) -> str:
 class _View(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("aov", ctypes.c_int32),
                 ("k", ctypes.c_double), ("l", ctypes.c_double), ("s", ctypes.c_double),
-                ("omega_deg", ctypes.c_double), ("rot", ctypes.c_double * 9)]
+                ("omega_deg", ctypes.c_double), ("rot", ctypes.c_double * 9),
+                ("lens", ctypes.c_int32), ("lens_n", ctypes.c_int32), ("lp", ctypes.c_double * 8)]
 
 
 def _load():
@@ -76,6 +77,9 @@ def _load():
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_int32]
             lib.orc_render.restype = ctypes.c_int
+            lib.orc_lens_direction.argtypes = [ctypes.POINTER(_View), ctypes.c_double, ctypes.c_double, dp,
+                                               ctypes.POINTER(ctypes.c_int32)]
+            lib.orc_lens_direction.restype = ctypes.c_int
             lib.orc_delta.argtypes = [ctypes.POINTER(_View), ctypes.c_int32, ctypes.c_int32]
             lib.orc_delta.restype = ctypes.c_double
             lib.orc_aa_render.argtypes = [ctypes.POINTER(_View), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
@@ -97,6 +101,10 @@ def _cview(view) -> _View:
     v.k, v.l, v.s, v.omega_deg = float(view.k), float(view.l), float(view.s), float(view.omega_deg)
     for i, r in enumerate(view.rot):
         v.rot[i] = float(r)
+    v.lens = int(getattr(view, "lens", 0))
+    v.lens_n = int(getattr(view, "lens_n", 1))
+    for i, x in enumerate(tuple(getattr(view, "lens_p", ()))[:8]):
+        v.lp[i] = float(x)
     return v
 
 
@@ -236,6 +244,18 @@ def fragments(view, tris: np.ndarray, attr: np.ndarray, pixels: np.ndarray, ids:
     lib.orc_fragments(ctypes.byref(cv), tris.ctypes.data, tris.shape[1], attr.ctypes.data, nattr,
                       int(bool(normalize3)), pixels.ctypes.data, ids.ctypes.data, n, _dp(b), _dp(f))
     return b, f[:, :nattr]
+
+
+def lens_direction(view, fs: float, ft: float):
+    """Camera-frame direction of texture coordinate (fs, ft) for the view's
+    map generator (section 2.1 or 2.2): (unit vector, has direction,
+    picture segment)."""
+    lib = _load()
+    cv = _cview(view)
+    out = np.zeros(3)
+    seg = ctypes.c_int32(0)
+    ok = lib.orc_lens_direction(ctypes.byref(cv), float(fs), float(ft), _dp(out), ctypes.byref(seg))
+    return out, bool(ok), int(seg.value)
 
 
 def delta(view, i: int, j: int) -> float:

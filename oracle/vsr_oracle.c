@@ -17,6 +17,10 @@
  *            step: 1 iff g > 0).
  *   depth    section 1.1.4 (hard normal N=(A-B)x(C-B); r = A.N / G.N).
  *   resolve  section 1.4 (depth-pass test: the nearest r wins).
+ *   lens     sections 2.2.2, 2.2.4, 2.2.7-2.2.9 (curved panorama,
+ *            equirectangular, cube, screen array and VR maps) and 2.3
+ *            (Brown-Conrady distortion of the Universal map's view
+ *            coordinates).
  *   aa       sections 1.1.1 (pixel step with the map's global delta), 1.1.2
  *            (miter mask of the smallest circle) and 1.4 (front-to-back
  *            combination of clipped fragment masks).
@@ -49,10 +53,25 @@
 #define ORC_FLAG_DEPTH 2u   /* best and second-best depth within 2e-5 rel.  */
 #define ORC_FLAG_INVALID 4u /* pixel has no view direction                   */
 
+/* Map generators: the Universal Perspective of section 2.1 (with the
+ * Brown-Conrady distortion of section 2.3 when any coefficient is non-zero)
+ * and the maps of section 2.2: equirectangular (2.2.4), cube (2.2.7),
+ * multiple-screen array (2.2.8), virtual reality (2.2.9) and curved
+ * panorama (2.2.2). */
+#define ORC_LENS_UNIVERSAL 0
+#define ORC_LENS_EQUIRECT 1
+#define ORC_LENS_CUBE 2
+#define ORC_LENS_SCREENS 3
+#define ORC_LENS_VR 4
+#define ORC_LENS_PANORAMA 5
+
 typedef struct {
     int32_t width, height, aov;
     double k, l, s, omega_deg;
-    double rot[9]; /* camera -> world, row-major */
+    double rot[9];  /* camera -> world, row-major */
+    int32_t lens;   /* ORC_LENS_* */
+    int32_t lens_n; /* screen array: number of screens */
+    double lp[8];   /* lens parameters, see orc_lens_direction */
 } orc_view;
 
 static const double ORC_PI = 3.14159265358979323846;
@@ -75,14 +94,12 @@ void orc_limits(double *k, double *l, double *s, double *omega_deg)
     *omega_deg = om;
 }
 
-/* Section 2, remark on 2D coordinates: centre the texture coordinate and
- * scale it by the aspect ratio a = W/H according to the angle-of-view type.
- * aov: 0 horizontal, 1 diagonal, 2 vertical, 3 horizontal 4x3. */
-void orc_view_coord(int32_t i, int32_t j, int32_t width, int32_t height, int32_t aov,
-                    double *x, double *y)
+/* Section 2, remark on 2D coordinates: centre the texture coordinate
+ * (fs, ft) in [0,1]^2 and scale it by the aspect ratio a = W/H according to
+ * the angle-of-view type.  aov: 0 horizontal, 1 diagonal, 2 vertical,
+ * 3 horizontal 4x3. */
+static void view_coord_f(double fs, double ft, int32_t width, int32_t height, int32_t aov, double *x, double *y)
 {
-    double fs = (i + 0.5) / (double)width;
-    double ft = (j + 0.5) / (double)height;
     double a = (double)width / (double)height;
     double cx = 2.0 * fs - 1.0, cy = 2.0 * ft - 1.0;
     switch (aov) {
@@ -105,6 +122,13 @@ void orc_view_coord(int32_t i, int32_t j, int32_t width, int32_t height, int32_t
         *y = cy / a;
         break;
     }
+}
+
+/* The same for the centre of pixel (i, j): ((i + 1/2)/W, (j + 1/2)/H). */
+void orc_view_coord(int32_t i, int32_t j, int32_t width, int32_t height, int32_t aov,
+                    double *x, double *y)
+{
+    view_coord_f((i + 0.5) / (double)width, (j + 0.5) / (double)height, width, height, aov, x, y);
 }
 
 /* Section 2.1.2: view coordinates (x, y) -> unit direction in the camera
@@ -150,15 +174,148 @@ int orc_direction(double x, double y, double k, double l, double s, double omega
     return 1;
 }
 
+static void normalize3(double v[3])
+{
+    double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] /= n;
+    v[1] /= n;
+    v[2] /= n;
+}
+
+/* Section 2.3 Brown-Conrady distortion of view coordinates (x, y):
+ * radial (1 + k1 r^2 + k2 r^4), thin prism (p . f) f and decentering q r^2,
+ * with c = (k1, k2, p1, p2, q1, q2). */
+static void lens_distort(const double *c, double *x, double *y)
+{
+    double r2 = *x * *x + *y * *y;
+    double radial = 1.0 + c[0] * r2 + c[1] * r2 * r2;
+    double prism = c[2] * *x + c[3] * *y;
+    double nx = *x * radial + prism * *x + c[4] * r2;
+    double ny = *y * radial + prism * *y + c[5] * r2;
+    *x = nx;
+    *y = ny;
+}
+
+/* Camera-frame unit direction of texture coordinate (fs, ft) for the view's
+ * map generator; *seg receives the picture segment the coordinate belongs
+ * to (cube face, screen, eye; 0 for one-piece maps).  Returns 0 (zero
+ * direction) where the generator gives none.  Lens parameters lp[]:
+ *   UNIVERSAL  (k1, k2, p1, p2, q1, q2) distortion of the view coordinates
+ *              (all zero: none), then section 2.1.2 with the view's k, l, s,
+ *              Omega after the section 2.1.1 limits;
+ *   EQUIRECT   none: longitude pi(2fs - 1), polar angle pi ft from -y;
+ *   CUBE       none: six 90-degree faces side by side, face floor(6 fs);
+ *   SCREENS    lp[0] = one screen's horizontal angle of view (degrees),
+ *              lens_n screens side by side, each turned about y by its
+ *              index times that angle;
+ *   VR         lp[0] = vertical angle of view (degrees), lp[1] = IPD d in
+ *              screen widths, lp[2], lp[3] = radial coefficients k1, k2;
+ *   PANORAMA   lp[0] = horizontal angle of view (degrees) of a cylinder of
+ *              unit radius whose height follows from the aspect ratio. */
+int orc_lens_direction(const orc_view *v, double fs, double ft, double out[3], int32_t *seg)
+{
+    const double a = (double)v->width / (double)v->height;
+    const double *p = v->lp;
+    *seg = 0;
+    switch (v->lens) {
+    case ORC_LENS_EQUIRECT: { /* section 2.2.4, equirectangular */
+        double lon = ORC_PI * (2.0 * fs - 1.0), pol = ORC_PI * ft;
+        out[0] = sin(lon) * sin(pol);
+        out[1] = -cos(pol);
+        out[2] = cos(lon) * sin(pol);
+        return 1;
+    }
+    case ORC_LENS_CUBE: { /* section 2.2.7, cube mapping */
+        int face = (int)floor(6.0 * fs);
+        if (face > 5)
+            face = 5;
+        if (face < 0)
+            face = 0;
+        double u[3] = {6.0 * fs - face - 0.5, ft - 0.5, 0.5};
+        normalize3(u);
+        /* rows of each face's rotation; face 3 (absent from the printed
+         * cases) is the identity: the forward face */
+        static const double M[6][3][3] = {
+            {{0, 0, 1}, {-1, 0, 0}, {0, -1, 0}},  /* +x */
+            {{0, 0, -1}, {1, 0, 0}, {0, -1, 0}},  /* -x */
+            {{1, 0, 0}, {0, -1, 0}, {0, 0, -1}},  /* -z */
+            {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}},    /* +z */
+            {{1, 0, 0}, {0, 0, 1}, {0, -1, 0}},   /* +y */
+            {{-1, 0, 0}, {0, 0, -1}, {0, -1, 0}}, /* -y */
+        };
+        for (int r = 0; r < 3; ++r)
+            out[r] = M[face][r][0] * u[0] + M[face][r][1] * u[1] + M[face][r][2] * u[2];
+        *seg = face;
+        return 1;
+    }
+    case ORC_LENS_SCREENS: { /* section 2.2.8, multiple-screen array */
+        int n = v->lens_n < 1 ? 1 : v->lens_n;
+        int s = (int)floor(n * fs);
+        if (s > n - 1)
+            s = n - 1;
+        if (s < 0)
+            s = 0;
+        double om = p[0] * ORC_PI / 180.0;
+        double phi = (s + 0.5 * (1 - n)) * om;
+        double u[3] = {2.0 * (n * fs - s) - 1.0, (2.0 * ft - 1.0) * n / a, 1.0 / tan(0.5 * om)};
+        normalize3(u);
+        out[0] = cos(phi) * u[0] + sin(phi) * u[2];
+        out[1] = u[1];
+        out[2] = -sin(phi) * u[0] + cos(phi) * u[2];
+        *seg = s;
+        return 1;
+    }
+    case ORC_LENS_VR: { /* section 2.2.9, virtual reality */
+        double eye = fs > 0.5 ? 1.0 : (fs < 0.5 ? -1.0 : 0.0);
+        double t = 2.0 * fs;
+        double x = (2.0 * (t - floor(t)) - 1.0 + eye * (1.0 - 2.0 * p[1])) * 0.5 * a;
+        double y = 2.0 * ft - 1.0;
+        double R2 = x * x + y * y, den = 1.0 + p[2] + p[3];
+        if (den == 0.0) {
+            out[0] = out[1] = out[2] = 0.0;
+            return 0;
+        }
+        double f = (1.0 + p[2] * R2 + p[3] * R2 * R2) / den;
+        out[0] = x * f;
+        out[1] = y * f;
+        out[2] = 1.0 / tan(0.5 * p[0] * ORC_PI / 180.0);
+        normalize3(out);
+        *seg = eye > 0.0 ? 1 : 0;
+        return 1;
+    }
+    case ORC_LENS_PANORAMA: { /* section 2.2.2, curved panorama */
+        double om = p[0] * ORC_PI / 180.0;
+        double x = om * (fs - 0.5), y = (om / a) * (ft - 0.5);
+        out[0] = sin(x);
+        out[1] = y;
+        out[2] = cos(x);
+        normalize3(out);
+        return 1;
+    }
+    default: { /* section 2.1 Universal Perspective */
+        double k = v->k, l = v->l, s = v->s, om = v->omega_deg, x, y;
+        orc_limits(&k, &l, &s, &om);
+        view_coord_f(fs, ft, v->width, v->height, v->aov, &x, &y);
+        if (p[0] != 0.0 || p[1] != 0.0 || p[2] != 0.0 || p[3] != 0.0 || p[4] != 0.0 || p[5] != 0.0)
+            lens_distort(p, &x, &y);
+        return orc_direction(x, y, k, l, s, om, out);
+    }
+    }
+}
+
+/* Camera-frame direction and segment of the centre of pixel (i, j). */
+int orc_cam_pixel(const orc_view *v, int32_t i, int32_t j, double cam[3], int32_t *seg)
+{
+    return orc_lens_direction(v, (i + 0.5) / (double)v->width, (j + 0.5) / (double)v->height, cam, seg);
+}
+
 /* Pixel (i, j) of a view -> world-space unit direction (camera direction
- * rotated by view->rot).  Limits of section 2.1.1 are applied first. */
+ * rotated by view->rot). */
 int orc_pixel_direction(const orc_view *v, int32_t i, int32_t j, double g[3])
 {
-    double k = v->k, l = v->l, s = v->s, om = v->omega_deg;
-    double x, y, cam[3];
-    orc_limits(&k, &l, &s, &om);
-    orc_view_coord(i, j, v->width, v->height, v->aov, &x, &y);
-    int ok = orc_direction(x, y, k, l, s, om, cam);
+    double cam[3];
+    int32_t seg;
+    int ok = orc_cam_pixel(v, i, j, cam, &seg);
     for (int r = 0; r < 3; ++r)
         g[r] = v->rot[3 * r + 0] * cam[0] + v->rot[3 * r + 1] * cam[1] + v->rot[3 * r + 2] * cam[2];
     return ok;
@@ -171,9 +328,12 @@ int orc_domain_edge(const orc_view *v, int32_t i, int32_t j)
 {
     double k = v->k, l = v->l, s = v->s, om = v->omega_deg, x, y;
     orc_limits(&k, &l, &s, &om);
-    if (!(k < 0.0))
+    if (v->lens != ORC_LENS_UNIVERSAL || !(k < 0.0))
         return 0;
     orc_view_coord(i, j, v->width, v->height, v->aov, &x, &y);
+    if (v->lp[0] != 0.0 || v->lp[1] != 0.0 || v->lp[2] != 0.0 || v->lp[3] != 0.0 || v->lp[4] != 0.0 ||
+        v->lp[5] != 0.0)
+        lens_distort(v->lp, &x, &y);
     double q = sin(k * 0.5 * om * ORC_PI / 180.0) * sqrt(x * x + l * y * y);
     return fabs(fabs(q) - 1.0) < 1e-6;
 }
@@ -535,25 +695,27 @@ void orc_fragments(const orc_view *v, const float *xyz, int64_t ntri, const floa
  * delta), 1.1.2 (miter mask from the smallest circle) and 1.4 (front-to-back
  * combination of fragment masks).                                          */
 
-/* Camera-frame direction of pixel (i, j) (the map before rotation). */
-static int cam_direction(const orc_view *v, int32_t i, int32_t j, double g[3])
+/* Camera-frame direction of pixel (i, j) (the map before rotation) if it
+ * has one and lies in segment seg0 (the neighbour rule of orc_delta). */
+static int cam_neighbour(const orc_view *v, int32_t i, int32_t j, int32_t seg0, double g[3])
 {
-    double k = v->k, l = v->l, s = v->s, om = v->omega_deg, x, y;
-    orc_limits(&k, &l, &s, &om);
-    orc_view_coord(i, j, v->width, v->height, v->aov, &x, &y);
-    return orc_direction(x, y, k, l, s, om, g);
+    int32_t seg;
+    if (i < 0 || i >= v->width || j < 0 || j >= v->height)
+        return 0;
+    return orc_cam_pixel(v, i, j, g, &seg) && seg == seg0;
 }
 
 /* Derivative of the camera-frame map along one pixel axis at (i, j):
  * central difference of the two neighbours, one-sided where a neighbour is
- * outside the picture or has no direction, 0 when neither has one. */
-static void map_derivative(const orc_view *v, int32_t i, int32_t j, int32_t di, int32_t dj, const double g0[3],
-                           double out[3])
+ * outside the picture, has no direction or lies in another segment of the
+ * picture (another cube face, screen or eye: not adjacent on the sphere),
+ * 0 when neither neighbour counts. */
+static void map_derivative(const orc_view *v, int32_t i, int32_t j, int32_t seg0, int32_t di, int32_t dj,
+                           const double g0[3], double out[3])
 {
     double gp[3], gm[3];
-    int32_t ip = i + di, jp = j + dj, im = i - di, jm = j - dj;
-    int okp = ip >= 0 && ip < v->width && jp >= 0 && jp < v->height && cam_direction(v, ip, jp, gp);
-    int okm = im >= 0 && im < v->width && jm >= 0 && jm < v->height && cam_direction(v, im, jm, gm);
+    int okp = cam_neighbour(v, i + di, j + dj, seg0, gp);
+    int okm = cam_neighbour(v, i - di, j - dj, seg0, gm);
     for (int c = 0; c < 3; ++c) {
         if (okp && okm)
             out[c] = 0.5 * (gp[c] - gm[c]);
@@ -572,10 +734,11 @@ static void map_derivative(const orc_view *v, int32_t i, int32_t j, int32_t di, 
 double orc_delta(const orc_view *v, int32_t i, int32_t j)
 {
     double g[3], di[3], dj[3];
-    if (!cam_direction(v, i, j, g))
+    int32_t seg;
+    if (!orc_cam_pixel(v, i, j, g, &seg))
         return 0.0;
-    map_derivative(v, i, j, 1, 0, g, di);
-    map_derivative(v, i, j, 0, 1, g, dj);
+    map_derivative(v, i, j, seg, 1, 0, g, di);
+    map_derivative(v, i, j, seg, 0, 1, g, dj);
     double m = 0.0;
     for (int c = 0; c < 3; ++c) {
         double f = fabs(di[c]) + fabs(dj[c]);

@@ -26,10 +26,15 @@ import numpy as np
 AOV_HORIZONTAL, AOV_DIAGONAL, AOV_VERTICAL, AOV_HORIZONTAL_4X3 = 0, 1, 2, 3
 
 
+LENS_UNIVERSAL, LENS_EQUIRECT, LENS_CUBE, LENS_SCREENS, LENS_VR, LENS_PANORAMA = 0, 1, 2, 3, 4, 5
+
+
 @dataclasses.dataclass
 class View:
-    """Universal Perspective view request (camera frame: +x right, +y down,
-    +z forward; ``rot`` is the row-major camera->world rotation)."""
+    """View request (camera frame: +x right, +y down, +z forward; ``rot`` is
+    the row-major camera->world rotation).  ``lens`` selects the map
+    generator (LENS_*; k, l, s, omega_deg and aov belong to the Universal
+    Perspective one), ``lens_n`` and ``lens_p`` are its parameters."""
 
     width: int
     height: int
@@ -39,6 +44,9 @@ class View:
     omega_deg: float
     aov: int = AOV_HORIZONTAL
     rot: Tuple[float, ...] = (1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0)
+    lens: int = LENS_UNIVERSAL
+    lens_n: int = 1
+    lens_p: Tuple[float, ...] = ()
 
     def rot_matrix(self) -> np.ndarray:
         return np.asarray(self.rot, dtype=np.float64).reshape(3, 3)
