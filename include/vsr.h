@@ -120,6 +120,45 @@ int64_t vsr_bin_bytes(int32_t width, int32_t height, int32_t bin_depth);
 int vsr_build_map(const vsr_view* v, int32_t fmt, uint32_t flags, void* map, int64_t map_bytes,
                   vsr_view* v_effective, void* stream);
 
+/* Other map generators (sections 2.2.2, 2.2.4, 2.2.7-2.2.9) and lens
+ * distortion (section 2.3).  A vsr_lens picks the generator; the view's
+ * width, height and rotation always apply, its k, l, s, omega_deg and aov
+ * only to VSR_LENS_UNIVERSAL.  Parameters (p[]):
+ *   VSR_LENS_UNIVERSAL  p[0..5] = k1, k2, p1, p2, q1, q2: Brown-Conrady
+ *                       distortion (radial, thin prism, decentering) of the
+ *                       view coordinates before the 2D->3D transform; all
+ *                       zero = vsr_build_map.
+ *   VSR_LENS_EQUIRECT   none: longitude pi (2fs - 1) across, polar angle
+ *                       pi ft from straight up down the picture.
+ *   VSR_LENS_CUBE       none: six 90-degree faces side by side (face
+ *                       floor(6 fs): +x, -x, -z, +z, +y, -y).
+ *   VSR_LENS_SCREENS    n = screens (1..64), p[0] = one screen's horizontal
+ *                       angle of view in degrees (0, 180); screen s is
+ *                       turned about the vertical axis by (s - (n-1)/2) p[0].
+ *   VSR_LENS_VR         p[0] = vertical angle of view (0, 180) degrees,
+ *                       p[1] = interpupillary distance in screen widths,
+ *                       p[2], p[3] = radial lens coefficients k1, k2 (the
+ *                       factor (1 + k1 R^2 + k2 R^4)/(1 + k1 + k2);
+ *                       1 + k1 + k2 = 0 is refused); left eye on the left.
+ *   VSR_LENS_PANORAMA   p[0] = horizontal angle of view (0, 360] degrees of
+ *                       a unit cylinder; its height follows from W/H.
+ * The map has the same layout as vsr_build_map's (flags: VSR_STRICT for the
+ * Universal parameters, VSR_MAP_AA), and every later step takes it
+ * unchanged.  VSR_E_ARG for an unknown type or parameters outside the
+ * ranges above. */
+#define VSR_LENS_UNIVERSAL 0
+#define VSR_LENS_EQUIRECT 1
+#define VSR_LENS_CUBE 2
+#define VSR_LENS_SCREENS 3
+#define VSR_LENS_VR 4
+#define VSR_LENS_PANORAMA 5
+typedef struct {
+    int32_t type, n;
+    float p[8];
+} vsr_lens;
+int vsr_build_map_lens(const vsr_view* v, const vsr_lens* lens, int32_t fmt, uint32_t flags, void* map,
+                       int64_t map_bytes, vsr_view* v_effective, void* stream);
+
 /* Copy a map's directions out to a row-major device array
  * out[(j*width + i)*3 + c] (float; all zero for a pixel without a direction),
  * decoding VSR_MAP_OCT16.  For inspection and tests; not on the hot path. */

@@ -108,12 +108,71 @@ int make_map_params(const vsr_view* v, int32_t fmt, uint32_t flags, MapParams* P
         P->xden_lo = P->yden_lo = float(hyp - double(P->xden));
     }
     for (int q = 0; q < 9; ++q) P->rot[q] = v->rot[q];
+    P->lens = VSR_LENS_UNIVERSAL;
+    P->lens_n = 1;
+    P->distort = 0;
+    P->pad_ = 0;
+    for (int q = 0; q < 8; ++q) P->lp[q] = 0.0f;
     if (eff) {
         *eff = *v;
         eff->k = float(k);
         eff->l = float(l);
         eff->s = float(s);
         eff->omega_deg = float(om);
+    }
+    return VSR_OK;
+}
+// Generator constants of a vsr_lens (on top of make_map_params, whose
+// Universal Perspective part the other generators ignore).
+int make_lens_params(const vsr_lens* lens, MapParams* P) {
+    if (!lens) return fail(VSR_E_ARG, "lens is NULL");
+    for (int q = 0; q < 8; ++q)
+        if (!isfinite(lens->p[q])) return fail(VSR_E_ARG, "non-finite lens parameter");
+    const double pi = 3.14159265358979323846;
+    const double W = P->W, H = P->H;
+    P->lens = lens->type;
+    switch (lens->type) {
+    case VSR_LENS_UNIVERSAL: {
+        bool any = false;
+        for (int q = 0; q < 6; ++q) {
+            P->lp[q] = lens->p[q];
+            any = any || lens->p[q] != 0.0f;
+        }
+        P->distort = any ? 1 : 0;
+        break;
+    }
+    case VSR_LENS_EQUIRECT:
+    case VSR_LENS_CUBE:
+        break;
+    case VSR_LENS_SCREENS: {
+        if (lens->n < 1 || lens->n > 64) return fail(VSR_E_ARG, "screen count %d outside 1..64", lens->n);
+        double om = lens->p[0];
+        if (!(om > 0.0 && om < 180.0)) return fail(VSR_E_ARG, "screen angle of view %g outside (0, 180)", om);
+        P->lens_n = lens->n;
+        P->lp[0] = float(1.0 / tan(0.5 * om * pi / 180.0));
+        P->lp[1] = float(0.5 * om * pi / 180.0);
+        break;
+    }
+    case VSR_LENS_VR: {
+        double om = lens->p[0], d = lens->p[1], k1 = lens->p[2], k2 = lens->p[3];
+        if (!(om > 0.0 && om < 180.0)) return fail(VSR_E_ARG, "vertical angle of view %g outside (0, 180)", om);
+        if (!(fabs(1.0 + k1 + k2) > 1e-6)) return fail(VSR_E_ARG, "1 + k1 + k2 is zero");
+        P->lp[0] = float(1.0 / tan(0.5 * om * pi / 180.0));
+        P->lp[1] = float(1.0 - 2.0 * d);
+        P->lp[2] = float(k1);
+        P->lp[3] = float(k2);
+        P->lp[4] = float(1.0 / (1.0 + k1 + k2));
+        P->lp[5] = float(0.5 * W / H);
+        break;
+    }
+    case VSR_LENS_PANORAMA: {
+        double om = lens->p[0];
+        if (!(om > 0.0 && om <= 360.0)) return fail(VSR_E_ARG, "panorama angle of view %g outside (0, 360]", om);
+        P->lp[0] = float(om * pi / 180.0 / (2.0 * W));
+        break;
+    }
+    default:
+        return fail(VSR_E_ARG, "unknown lens type %d", lens->type);
     }
     return VSR_OK;
 }
@@ -149,6 +208,24 @@ int vsr_build_map(const vsr_view* v, int32_t fmt, uint32_t flags, void* map, int
     int64_t need = aa ? aa_map_bytes(v->width, v->height, fmt) : map_layout(v->width, v->height, fmt).bytes;
     if (map_bytes < need) return fail(VSR_E_SPACE, "map buffer %lld < %lld bytes", (long long)map_bytes, (long long)need);
     return hip_status(launch_build_map(P, map, aa, hipStream_t(stream)), "vsr_build_map");
+}
+
+int vsr_build_map_lens(const vsr_view* v, const vsr_lens* lens, int32_t fmt, uint32_t flags, void* map,
+                       int64_t map_bytes, vsr_view* v_eff, void* stream) {
+    MapParams P;
+    // the Universal Perspective parameters are limited (and checked under
+    // VSR_STRICT) only when that generator is used
+    const uint32_t base_flags = (lens && lens->type != VSR_LENS_UNIVERSAL) ? (flags & ~VSR_STRICT) : flags;
+    int rc = make_map_params(v, fmt, base_flags, &P, v_eff);
+    if (rc != VSR_OK) return rc;
+    rc = make_lens_params(lens, &P);
+    if (rc != VSR_OK) return rc;
+    if (!map || !aligned(map)) return fail(VSR_E_ARG, "map buffer NULL or not 256-byte aligned");
+    if ((flags & ~(VSR_STRICT | VSR_MAP_AA)) != 0) return fail(VSR_E_ARG, "unknown flags 0x%x", flags);
+    const bool aa = (flags & VSR_MAP_AA) != 0;
+    int64_t need = aa ? aa_map_bytes(v->width, v->height, fmt) : map_layout(v->width, v->height, fmt).bytes;
+    if (map_bytes < need) return fail(VSR_E_SPACE, "map buffer %lld < %lld bytes", (long long)map_bytes, (long long)need);
+    return hip_status(launch_build_map(P, map, aa, hipStream_t(stream)), "vsr_build_map_lens");
 }
 
 int64_t vsr_aa_map_bytes(int32_t width, int32_t height, int32_t fmt) {

@@ -1,4 +1,5 @@
-// Perspective vector map (Universal Perspective model) and per-tile caps.
+// Perspective vector map (Universal Perspective model, or one of the other
+// generators of section 2.2) and per-tile caps.
 //
 // One wavefront per 8x8 tile, one lane per pixel.  Each lane turns its pixel
 // centre into view coordinates (angle-of-view normalisation, section 2),
@@ -43,20 +44,35 @@ __device__ inline float asin_df(float qh, float ql) {
     return qh < 0.0f ? -a : a;
 }
 
-// Unit camera direction of pixel (i, j); false when the pixel is outside
-// the projection's domain.
-__device__ inline bool pixel_direction(const MapParams& P, int i, int j, float3& out) {
+// Section 2.3 Brown-Conrady distortion of view coordinates: radial
+// (1 + k1 r^2 + k2 r^4), thin prism (p . f) f, decentering q r^2;
+// c = (k1, k2, p1, p2, q1, q2).
+__device__ inline void lens_distort(const float* c, float& x, float& y) {
+    float r2 = fmaf(x, x, y * y);
+    float radial = fmaf(r2, fmaf(c[1], r2, c[0]), 1.0f);
+    float prism = fmaf(c[2], x, c[3] * y);
+    float nx = fmaf(x, radial, fmaf(prism, x, c[4] * r2));
+    float ny = fmaf(y, radial, fmaf(prism, y, c[5] * r2));
+    x = nx;
+    y = ny;
+}
+
+// Universal Perspective (section 2.1.2) camera direction of pixel (i, j);
+// false when the pixel is outside the projection's domain.
+__device__ inline bool universal_direction(const MapParams& P, int i, int j, float3& out) {
     float nx = float((2 * i + 1 - P.W) * P.xmul), ny = float((2 * j + 1 - P.H) * P.xmul);
     float x = nx / P.xden;
     float y = ny / P.yden;
+    if (P.distort) lens_distort(P.lp, x, y);
     float R = sqrtf(fmaf(x, x, P.l * (y * y)));
     float theta;
     if (P.kind > 0) {
         theta = atanf(P.kt * R) / P.k;
     } else if (P.kind < 0) {
         // sin(k Omega/2) R in double-float: x, y, R^2, R and the product
-        float xl = (fmaf(-x, P.xden, nx) - x * P.xden_lo) / P.xden;
-        float yl = (fmaf(-y, P.yden, ny) - y * P.yden_lo) / P.yden;
+        // (the rounding residuals of x and y are known only undistorted)
+        float xl = P.distort ? 0.0f : (fmaf(-x, P.xden, nx) - x * P.xden_lo) / P.xden;
+        float yl = P.distort ? 0.0f : (fmaf(-y, P.yden, ny) - y * P.yden_lo) / P.yden;
         float xx = x * x, xxe = fmaf(x, x, -xx) + 2.0f * x * xl;
         float yy = y * y, yye = fmaf(y, y, -yy) + 2.0f * y * yl;
         float ly = P.l * yy, lye = fmaf(P.l, yy, -ly) + P.l * yye;
@@ -84,14 +100,93 @@ __device__ inline bool pixel_direction(const MapParams& P, int i, int j, float3&
     return true;
 }
 
+__device__ inline float3 normalized(float x, float y, float z) {
+    float inv = 1.0f / sqrtf(fmaf(x, x, fmaf(y, y, z * z)));
+    return f3(x * inv, y * inv, z * inv);
+}
+
+// Picture segment of pixel (i, j): cube face, screen or eye (0 for the
+// one-piece maps).  Texture coordinates are ratios of integers, so the
+// segment index is exact integer arithmetic.
+__device__ inline int pixel_segment(const MapParams& P, int i) {
+    switch (P.lens) {
+    case VSR_LENS_CUBE: return min(5, (3 * (2 * i + 1)) / P.W);
+    case VSR_LENS_SCREENS: return min(P.lens_n - 1, (P.lens_n * (2 * i + 1)) / (2 * P.W));
+    case VSR_LENS_VR: return 2 * i + 1 > P.W ? 1 : 0;
+    default: return 0;
+    }
+}
+
+// Camera direction of pixel (i, j) for the view's map generator (section
+// 2.1.2, or the maps of section 2.2); false when the pixel has none.
+__device__ inline bool pixel_direction(const MapParams& P, int i, int j, float3& out) {
+    switch (P.lens) {
+    case VSR_LENS_EQUIRECT: {  // section 2.2.4: longitude pi (2fs - 1), polar angle pi ft from -y
+        float sl, cl, sp, cp;
+        sincospif(float(2 * i + 1 - P.W) / float(P.W), &sl, &cl);
+        sincospif(float(2 * j + 1) / float(2 * P.H), &sp, &cp);
+        out = f3(sl * sp, -cp, cl * sp);
+        return true;
+    }
+    case VSR_LENS_CUBE: {  // section 2.2.7: six 90-degree faces side by side
+        const int face = pixel_segment(P, i);
+        // face-local (fract(6 fs) - 1/2, ft - 1/2, 1/2), numerators exact
+        float u = float(2 * (3 * (2 * i + 1) - P.W * face) - P.W) / float(2 * P.W);
+        float v = float(2 * j + 1 - P.H) / float(2 * P.H);
+        float3 d = normalized(u, v, 0.5f);
+        switch (face) {  // rows of the face rotation; face 3 is the forward face
+        case 0: out = f3(d.z, -d.x, -d.y); break;
+        case 1: out = f3(-d.z, d.x, -d.y); break;
+        case 2: out = f3(d.x, -d.y, -d.z); break;
+        case 3: out = d; break;
+        case 4: out = f3(d.x, d.z, -d.y); break;
+        default: out = f3(-d.x, -d.z, -d.y); break;
+        }
+        return true;
+    }
+    case VSR_LENS_SCREENS: {  // section 2.2.8: n flat screens, screen s turned about y
+        const int n = P.lens_n, s = pixel_segment(P, i);
+        float u = float(n * (2 * i + 1) - 2 * P.W * s - P.W) / float(P.W);
+        float v = float(n * (2 * j + 1 - P.H)) / float(P.W);
+        float3 d = normalized(u, v, P.lp[0]);
+        float sn, cs;
+        sincosf(float(2 * s + 1 - n) * P.lp[1], &sn, &cs);
+        out = f3(fmaf(cs, d.x, sn * d.z), d.y, fmaf(-sn, d.x, cs * d.z));
+        return true;
+    }
+    case VSR_LENS_VR: {  // section 2.2.9: two eyes, IPD offset, radial lens distortion
+        const int t = 2 * i + 1;
+        const float eye = t > P.W ? 1.0f : (t < P.W ? -1.0f : 0.0f);
+        float x = (float(2 * (t % P.W) - P.W) / float(P.W) + eye * P.lp[1]) * P.lp[5];
+        float y = float(2 * j + 1 - P.H) / float(P.H);
+        float R2 = fmaf(x, x, y * y);
+        float f = fmaf(R2, fmaf(P.lp[3], R2, P.lp[2]), 1.0f) * P.lp[4];
+        out = normalized(x * f, y * f, P.lp[0]);
+        return true;
+    }
+    case VSR_LENS_PANORAMA: {  // section 2.2.2: unit cylinder, height from the aspect ratio
+        float x = float(2 * i + 1 - P.W) * P.lp[0], y = float(2 * j + 1 - P.H) * P.lp[0];
+        float sn, cs;
+        sincosf(x, &sn, &cs);
+        out = normalized(sn, y, cs);
+        return true;
+    }
+    default:
+        return universal_direction(P, i, j, out);
+    }
+}
+
 // Derivative of the camera-frame map along one pixel axis at (i, j): central
 // difference of the two neighbours, one-sided where a neighbour is outside
-// the picture or has no direction, zero when neither has one.
+// the picture, has no direction or lies in another segment of the picture
+// (cube face, screen, eye: not adjacent on the sphere), zero when neither
+// counts.
 __device__ inline float3 map_derivative(const MapParams& P, int i, int j, int di, int dj, float3 g) {
     float3 gp, gm;
     const int ip = i + di, jp = j + dj, im = i - di, jm = j - dj;
-    bool okp = ip < P.W && jp < P.H && pixel_direction(P, ip, jp, gp);
-    bool okm = im >= 0 && jm >= 0 && pixel_direction(P, im, jm, gm);
+    const int seg = pixel_segment(P, i);
+    bool okp = ip < P.W && jp < P.H && pixel_segment(P, ip) == seg && pixel_direction(P, ip, jp, gp);
+    bool okm = im >= 0 && jm >= 0 && pixel_segment(P, im) == seg && pixel_direction(P, im, jm, gm);
     if (okp && okm) return f3(0.5f * (gp.x - gm.x), 0.5f * (gp.y - gm.y), 0.5f * (gp.z - gm.z));
     if (okp) return sub3(gp, g);
     if (okm) return sub3(g, gm);

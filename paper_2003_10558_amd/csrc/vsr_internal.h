@@ -109,6 +109,11 @@ struct MapParams {
     float l;            // cylindricity
     float c;            // anamorphic divisor l*(1-s)+s
     float rot[9];
+    int32_t lens;       // map generator, VSR_LENS_*
+    int32_t lens_n;     // screen array: number of screens
+    int32_t distort;    // Universal: Brown-Conrady coefficients not all zero
+    int32_t pad_;
+    float lp[8];        // generator constants (set by the host, see make_map_params)
 };
 
 // ------------------------------------------------------------- setup ----

@@ -20,6 +20,14 @@ def _buffer(nbytes: int, device) -> torch.Tensor:
     return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
 
 
+def build_map(view, fmt: int, flags: int, map_buf, stream=None):
+    """vsr_build_map, or vsr_build_map_lens when the view names another
+    generator or a lens distortion."""
+    if vsr.has_lens(view):
+        return vsr.vsr_build_map_lens(view, fmt, flags, map_buf, stream)
+    return vsr.vsr_build_map(view, fmt, flags, map_buf, stream)
+
+
 class Scene:
     """Triangles resident on the GPU with their setup (vsr_setup_tris)."""
 
@@ -61,7 +69,7 @@ def render(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, bin_depth: int = DEFA
         ids, dep = alloc_outputs(view, dev)
         frame = Frame(ids, dep, _buffer(vsr.vsr_map_bytes(view.width, view.height, fmt), dev),
                       _buffer(vsr.vsr_bin_bytes(view.width, view.height, bin_depth), dev), None)
-    frame.view_eff = vsr.vsr_build_map(view, fmt, 0, frame.map, stream)
+    frame.view_eff = build_map(view, fmt, 0, frame.map, stream)
     vsr.vsr_bin(view, fmt, frame.map, scene.setup, scene.ntri, bin_depth, bin_flags, frame.bins, stream)
     vsr.vsr_raster(view, fmt, frame.map, scene.setup, scene.ntri, frame.bins, bin_depth, frame.tri_id,
                    frame.depth, stream)
@@ -76,7 +84,7 @@ def render_fused(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, stream=None,
         ids, dep = alloc_outputs(view, dev)
         frame = Frame(ids, dep, _buffer(vsr.vsr_map_bytes(view.width, view.height, fmt), dev),
                       _buffer(vsr.vsr_render_bytes(view.width, view.height), dev), None)
-    frame.view_eff = vsr.vsr_build_map(view, fmt, 0, frame.map, stream)
+    frame.view_eff = build_map(view, fmt, 0, frame.map, stream)
     vsr.vsr_render(view, fmt, frame.map, scene.setup, scene.ntri, frame.bins, frame.tri_id, frame.depth, stream)
     return frame
 
@@ -123,7 +131,7 @@ def render_aa(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, bin_depth: int = D
                         torch.empty(1, dtype=torch.int32, device=dev),
                         _buffer(vsr.vsr_aa_map_bytes(W, H, fmt), dev),
                         _buffer(vsr.vsr_bin_bytes(W, H, bin_depth), dev), None)
-    frame.view_eff = vsr.vsr_build_map(view, fmt, vsr.VSR_MAP_AA, frame.map, stream)
+    frame.view_eff = build_map(view, fmt, vsr.VSR_MAP_AA, frame.map, stream)
     vsr.vsr_bin(view, fmt, frame.map, scene.setup, scene.ntri, bin_depth, bin_flags, frame.bins, stream)
     if stats is None:
         vsr.vsr_aa_raster(view, fmt, frame.map, scene.setup, scene.ntri, frame.bins, bin_depth, frame.coverage,
@@ -141,6 +149,9 @@ class Batch:
     def __init__(self, items: Sequence[Tuple[Scene, object]], fmt: int = vsr.VSR_MAP_F32,
                  mode: int = vsr.VSR_SUBMIT_BINNED, bin_depth: int = DEFAULT_BIN_DEPTH):
         assert len(items) > 0
+        if any(vsr.has_lens(v) for _, v in items):
+            raise ValueError("vsr_submit takes Universal Perspective views only; render other generators with "
+                             "render() / render_aa()")
         self.items = list(items)
         self.fmt, self.mode, self.bin_depth = fmt, mode, bin_depth
         dev = items[0][0].device

@@ -19,6 +19,7 @@ VSR_OK, VSR_E_ARG, VSR_E_SPACE, VSR_E_RANGE, VSR_E_HIP = 0, -1, -2, -3, -4
 VSR_MAP_F32, VSR_MAP_OCT16 = 0, 1
 VSR_STRICT = 1
 VSR_MAP_AA = 2
+VSR_LENS_UNIVERSAL, VSR_LENS_EQUIRECT, VSR_LENS_CUBE, VSR_LENS_SCREENS, VSR_LENS_VR, VSR_LENS_PANORAMA = range(6)
 VSR_BIN_ALL = 1
 VSR_BIN_BLOCKS, VSR_BIN_SUPERTILES = 2, 4
 VSR_NO_HIT = 0xFFFFFFFF
@@ -47,6 +48,10 @@ class vsr_view(ctypes.Structure):
                 ("s", ctypes.c_float), ("omega_deg", ctypes.c_float), ("rot", ctypes.c_float * 9)]
 
 
+class vsr_lens(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("n", ctypes.c_int32), ("p", ctypes.c_float * 8)]
+
+
 class vsr_job(ctypes.Structure):
     _fields_ = [("view", vsr_view), ("setup", ctypes.c_void_p), ("ntri", ctypes.c_int64),
                 ("tri_id", ctypes.c_void_p), ("depth", ctypes.c_void_p)]
@@ -60,6 +65,8 @@ _lib.vsr_setup_bytes.restype = _i64
 _lib.vsr_bin_bytes.argtypes = [_i32, _i32, _i32]
 _lib.vsr_bin_bytes.restype = _i64
 _lib.vsr_build_map.argtypes = [ctypes.POINTER(vsr_view), _i32, _u32, _vp, _i64, ctypes.POINTER(vsr_view), _vp]
+_lib.vsr_build_map_lens.argtypes = [ctypes.POINTER(vsr_view), ctypes.POINTER(vsr_lens), _i32, _u32, _vp, _i64,
+                                    ctypes.POINTER(vsr_view), _vp]
 _lib.vsr_map_unpack.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _vp]
 _lib.vsr_setup_tris.argtypes = [_vp, _i64, _vp, _i64, _vp]
 _lib.vsr_bin.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _i32, _u32, _vp, _i64, _vp]
@@ -91,7 +98,7 @@ for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_
            "vsr_bin_overflow"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin",
+EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map", "vsr_build_map_lens", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin",
            "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_resolve", "vsr_aa_map_bytes",
            "vsr_aa_raster", "vsr_aa_raster_stats", "vsr_submit_bytes",
            "vsr_submit_table_bytes", "vsr_submit_table_offset", "vsr_submit_table", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
@@ -150,6 +157,31 @@ def vsr_build_map(view, fmt: int, flags: int, map_buf, stream=None) -> vsr_view:
     eff = vsr_view()
     _check(_lib.vsr_build_map(ctypes.byref(v), fmt, flags, _ptr(map_buf), _nbytes(map_buf), ctypes.byref(eff),
                               _stream(stream)))
+    return eff
+
+
+def make_lens(view) -> vsr_lens:
+    """vsr_lens from a view's optional ``lens``, ``lens_n`` and ``lens_p``."""
+    ln = vsr_lens()
+    ln.type = int(getattr(view, "lens", VSR_LENS_UNIVERSAL))
+    ln.n = int(getattr(view, "lens_n", 1))
+    for q, x in enumerate(tuple(getattr(view, "lens_p", ()))[:8]):
+        ln.p[q] = float(x)
+    return ln
+
+
+def has_lens(view) -> bool:
+    """True when the view asks for another generator or lens distortion."""
+    return int(getattr(view, "lens", VSR_LENS_UNIVERSAL)) != VSR_LENS_UNIVERSAL or any(
+        float(x) != 0.0 for x in tuple(getattr(view, "lens_p", ())))
+
+
+def vsr_build_map_lens(view, fmt: int, flags: int, map_buf, stream=None) -> vsr_view:
+    v = make_view(view)
+    ln = make_lens(view)
+    eff = vsr_view()
+    _check(_lib.vsr_build_map_lens(ctypes.byref(v), ctypes.byref(ln), fmt, flags, _ptr(map_buf), _nbytes(map_buf),
+                                   ctypes.byref(eff), _stream(stream)))
     return eff
 
 

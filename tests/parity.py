@@ -138,7 +138,6 @@ def compare(view, tris: np.ndarray, gpu_ids: np.ndarray, gpu_depth: np.ndarray, 
 
 
 def _pixel_dir(view, p: int) -> np.ndarray:
-    x, y = oracle.view_coord(p % view.width, p // view.width, view.width, view.height, view.aov)
-    k, l, s, om = oracle.limits(view.k, view.l, view.s, view.omega_deg)
-    g, _ = oracle.direction(x, y, k, l, s, om)
+    i, j = p % view.width, p // view.width
+    g, _, _ = oracle.lens_direction(view, (i + 0.5) / view.width, (j + 0.5) / view.height)
     return view.rot_matrix() @ g

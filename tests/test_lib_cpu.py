@@ -183,5 +183,26 @@ def test_aa_sizes_and_argument_errors(vsr):
         assert e.value.code == vsr.VSR_E_ARG, c
     with pytest.raises(vsr.VsrError) as e:
         vsr.vsr_aa_raster_stats(v, 0, ok["map_buf"], ok["setup"], 10, ok["bins"], 64, ok["cov"], ok["dp"],
-                                ok["dom"], None, None, stream=0)
+                                ok["dom"], None, None, False, stream=0)
     assert e.value.code == vsr.VSR_E_ARG
+
+
+def test_lens_argument_errors(vsr):
+    v = synth.View(64, 32, 0.3, 0.5, 0.9, 120.0)
+    buf = _FakeBuf(256, 10 ** 8)
+    for lens, n, p in [(9, 1, ()), (-1, 1, ()), (vsr.VSR_LENS_SCREENS, 0, (60.0,)), (vsr.VSR_LENS_SCREENS, 65, (60.0,)),
+                       (vsr.VSR_LENS_SCREENS, 2, (0.0,)), (vsr.VSR_LENS_VR, 1, (90.0, 0.5, -0.5, -0.5)),
+                       (vsr.VSR_LENS_VR, 1, (180.0, 0.5, 0.0, 0.0)), (vsr.VSR_LENS_PANORAMA, 1, (361.0,)),
+                       (vsr.VSR_LENS_UNIVERSAL, 1, (float("nan"),))]:
+        lv = synth.View(64, 32, 0.3, 0.5, 0.9, 120.0, lens=lens, lens_n=n, lens_p=p)
+        with pytest.raises(vsr.VsrError) as e:
+            vsr.vsr_build_map_lens(lv, 0, 0, buf, stream=0)
+        assert e.value.code == vsr.VSR_E_ARG, (lens, n, p)
+    # NULL lens
+    with pytest.raises(vsr.VsrError) as e:
+        vsr._check(vsr._lib.vsr_build_map_lens(ctypes.byref(vsr.make_view(v)), None, 0, 0, 256, 10 ** 8, None, 0))
+    assert e.value.code == vsr.VSR_E_ARG
+    # batches take Universal views only
+    from paper_2003_10558_amd import pipeline
+    with pytest.raises(ValueError):
+        pipeline.Batch([(None, synth.View(64, 32, 0, 0, 1, 90, lens=vsr.VSR_LENS_EQUIRECT))])
