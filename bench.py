@@ -295,6 +295,46 @@ def main():
         f"{np.mean(aa_rast):.3f}), lost pixels {aa_lost}; fragments per frame (all depths) {F_aa}, found with "
         f"skipping {F_aa_proc}, mask evaluations {aa_tests}, triangles skipped {aa_skipped}")
 
+    # ---------------- other map generators (sections 2.2, 2.3), plain per-view path
+    lens_views = {
+        "equirect_2048x1024": synth.View(2048, 1024, 0, 0, 1, 90, 0, views[1].rot, lens=vsr.VSR_LENS_EQUIRECT),
+        "cube_3456x576": synth.View(3456, 576, 0, 0, 1, 90, 0, views[1].rot, lens=vsr.VSR_LENS_CUBE),
+        "screens3_1920x1080": synth.View(1920, 1080, 0, 0, 1, 90, 0, views[1].rot, lens=vsr.VSR_LENS_SCREENS,
+                                         lens_n=3, lens_p=(60.0,)),
+        "vr_1920x1080": synth.View(1920, 1080, 0, 0, 1, 90, 0, views[1].rot, lens=vsr.VSR_LENS_VR,
+                                   lens_p=(100.0, 0.42, 0.22, 0.05)),
+        "panorama_1920x1080": synth.View(1920, 1080, 0, 0, 1, 90, 0, views[1].rot, lens=vsr.VSR_LENS_PANORAMA,
+                                         lens_p=(270.0,)),
+        "distorted_k0.5_1920x1080": synth.View(1920, 1080, 0.5, 0.5, 1.0, 180.0, 0, views[1].rot,
+                                               lens_p=(0.12, -0.03, 0.01, -0.01, 0.005, -0.005)),
+    }
+    lens_stats = {}
+    for name, lv in lens_views.items():
+        lf = pipeline.render(scene, lv, fmt=fmt, bin_depth=depth)
+        torch.cuda.synchronize()
+        tm, tb, tr = [], [], []
+        for rep in range(3 if not args.profile else 2):
+            e0, ea, e1, e2 = ev(), ev(), ev(), ev()
+            e0.record(stream)
+            pipeline.build_map(lv, fmt, 0, lf.map)
+            ea.record(stream)
+            vsr.vsr_bin(lv, fmt, lf.map, scene.setup, scene.ntri, depth, 0, lf.bins)
+            e1.record(stream)
+            vsr.vsr_raster(lv, fmt, lf.map, scene.setup, scene.ntri, lf.bins, depth, lf.tri_id, lf.depth)
+            e2.record(stream)
+            e2.synchronize()
+            if rep:
+                tm.append(e0.elapsed_time(ea))
+                tb.append(ea.elapsed_time(e1))
+                tr.append(e1.elapsed_time(e2))
+        npx = lv.width * lv.height
+        lens_stats[name] = {"map_ms": float(np.mean(tm)), "bin_ms": float(np.mean(tb)), "raster_ms": float(np.mean(tr)),
+                            "fps": 1e3 / (np.mean(tm) + np.mean(tb) + np.mean(tr)), "pixels": npx,
+                            "overflowed_tiles": vsr.vsr_bin_overflow(lf.bins)}
+        log(f"lens {name}: map {np.mean(tm):.3f} ms, bin {np.mean(tb):.3f} ms, raster {np.mean(tr):.3f} ms "
+            f"-> {lens_stats[name]['fps']:.0f} frames/s")
+        del lf
+
     # ---------------- single-view fused path (vsr_build_map + vsr_render)
     ffr = pipeline.render_fused(scene, views[0], fmt=fmt)
     torch.cuda.synchronize()
@@ -530,6 +570,7 @@ def main():
                "fragments_per_frame": F_aa_mean, "fragments_found_with_skipping": float(np.mean(F_aa_proc)),
                "mask_evaluations": float(np.mean(aa_tests)), "triangles_skipped": float(np.mean(aa_skipped))},
         "roofline_aa": roofline_aa,
+        "lenses": lens_stats,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
