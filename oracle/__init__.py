@@ -80,6 +80,13 @@ def _load():
             lib.orc_lens_direction.argtypes = [ctypes.POINTER(_View), ctypes.c_double, ctypes.c_double, dp,
                                                ctypes.POINTER(ctypes.c_int32)]
             lib.orc_lens_direction.restype = ctypes.c_int
+            lib.orc_wireframe.argtypes = [ctypes.POINTER(_View), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_int64, dp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+            lib.orc_wireframe.restype = ctypes.c_int
+            lib.orc_particles.argtypes = [ctypes.POINTER(_View), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_int64, dp, dp, dp, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int32]
+            lib.orc_particles.restype = ctypes.c_int
             lib.orc_delta.argtypes = [ctypes.POINTER(_View), ctypes.c_int32, ctypes.c_int32]
             lib.orc_delta.restype = ctypes.c_double
             lib.orc_aa_render.argtypes = [ctypes.POINTER(_View), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
@@ -303,4 +310,76 @@ def aa_render(view, tris: np.ndarray, pixels: Optional[np.ndarray] = None,
     if pixels is None:
         for f in ("cov", "depth", "dom", "margin", "gap", "n_near", "sum_r", "sum_rg"):
             setattr(res, f, getattr(res, f).reshape(view.height, view.width))
+    return res
+
+
+@dataclass
+class WireResult:
+    cov: np.ndarray      # float64 largest line mask over the triangles' sides
+    dom: np.ndarray      # uint32 triangle of that side (ties: lower id), NO_HIT if none
+    second: np.ndarray   # largest mask of any other triangle
+
+
+def wireframe(view, tris: np.ndarray, pixels: Optional[np.ndarray] = None,
+              threads: Optional[int] = None) -> WireResult:
+    """Aliasing-free wire frame of the triangles' sides (section 1.2)."""
+    lib = _load()
+    tris = np.ascontiguousarray(tris, dtype=np.float32)
+    if pixels is None:
+        n, pix_ptr = view.width * view.height, None
+    else:
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        n, pix_ptr = pixels.shape[0], pixels.ctypes.data
+    cov, second = np.empty(n), np.empty(n)
+    dom = np.empty(n, dtype=np.uint32)
+    cv = _cview(view)
+    rc = lib.orc_wireframe(ctypes.byref(cv), tris.ctypes.data, tris.shape[1], pix_ptr, n, _dp(cov),
+                           dom.ctypes.data, second.ctypes.data, int(threads or os.cpu_count() or 1))
+    if rc != 0:
+        raise MemoryError("oracle wireframe failed")
+    res = WireResult(cov, dom, second)
+    if pixels is None:
+        for f in ("cov", "dom", "second"):
+            setattr(res, f, getattr(res, f).reshape(view.height, view.width))
+    return res
+
+
+@dataclass
+class ParticleResult:
+    cov: np.ndarray
+    depth: np.ndarray    # depth pass
+    uv: np.ndarray       # texture-coordinate pass [..., 2]
+    dom: np.ndarray
+    margin: np.ndarray
+    gap: np.ndarray
+    n_near: np.ndarray
+    sum_r: np.ndarray
+
+
+def particles(view, pr: np.ndarray, pixels: Optional[np.ndarray] = None,
+              threads: Optional[int] = None) -> ParticleResult:
+    """Aliasing-free particles (section 1.3) combined front to back (1.4);
+    pr = float32[4, n] (x, y, z, radius)."""
+    lib = _load()
+    pr = np.ascontiguousarray(pr, dtype=np.float32)
+    if pixels is None:
+        n, pix_ptr = view.width * view.height, None
+    else:
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        n, pix_ptr = pixels.shape[0], pixels.ctypes.data
+    cov, depth = np.empty(n), np.empty(n)
+    uv = np.empty((n, 2))
+    dom = np.empty(n, dtype=np.uint32)
+    aux = np.empty((n, 4))
+    cv = _cview(view)
+    rc = lib.orc_particles(ctypes.byref(cv), pr.ctypes.data, pr.shape[1], pix_ptr, n, _dp(cov), _dp(depth),
+                           _dp(uv), dom.ctypes.data, aux.ctypes.data, int(threads or os.cpu_count() or 1))
+    if rc != 0:
+        raise MemoryError("oracle particles failed")
+    res = ParticleResult(cov, depth, uv, dom, *(aux[:, c].copy() for c in range(4)))
+    if pixels is None:
+        H, W = view.height, view.width
+        for f in ("cov", "depth", "dom", "margin", "gap", "n_near", "sum_r"):
+            setattr(res, f, getattr(res, f).reshape(H, W))
+        res.uv = res.uv.reshape(H, W, 2)
     return res

@@ -21,6 +21,10 @@
  *            equirectangular, cube, screen array and VR maps) and 2.3
  *            (Brown-Conrady distortion of the Universal map's view
  *            coordinates).
+ *   wire     section 1.2 (line step of a segment's great circle limited by
+ *            the cap around the segment) for the sides of the triangles.
+ *   particle section 1.3 (cap of a sphere seen from O, texture coordinates
+ *            on the particle's plane), combined as in section 1.4.
  *   aa       sections 1.1.1 (pixel step with the map's global delta), 1.1.2
  *            (miter mask of the smallest circle) and 1.4 (front-to-back
  *            combination of clipped fragment masks).
@@ -959,5 +963,333 @@ int orc_aa_render(const orc_view *v, const float *xyz_soa, int64_t ntri, const i
         pthread_join(th[w], NULL);
     free(tris);
     free(caps);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Wire-frame line segments (section 1.2) and procedural particles
+ * (section 1.3), aliasing-free, with the global delta of section 1.1.1.    */
+
+typedef struct {
+    void (*fn)(void *ctx, int64_t q);
+    void *ctx;
+    int64_t n, begin, stride;
+} orc_par;
+
+static void *par_range(void *arg)
+{
+    orc_par *p = (orc_par *)arg;
+    for (int64_t q = p->begin; q < p->n; q += p->stride)
+        p->fn(p->ctx, q);
+    return NULL;
+}
+
+static void par_for(int64_t n, int32_t nthreads, void (*fn)(void *, int64_t), void *ctx)
+{
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    pthread_t th[256];
+    orc_par jobs[256];
+    for (int w = 0; w < nthreads; ++w) {
+        orc_par p = {fn, ctx, n, w, nthreads};
+        jobs[w] = p;
+    }
+    for (int w = 1; w < nthreads; ++w)
+        pthread_create(&th[w], NULL, par_range, &jobs[w]);
+    par_range(&jobs[0]);
+    for (int w = 1; w < nthreads; ++w)
+        pthread_join(th[w], NULL);
+}
+
+/* One line segment P->Q on the sphere: the unit normal of its great circle
+ * and the cap around it (centre L_hat = normalised mean of the unit end
+ * points, cos of the radius |L|).  Returns 0 when the great circle is
+ * undefined (P and Q on one line through O). */
+typedef struct {
+    double n[3], L[3], cos_r, sin_r;
+} orc_seg;
+
+static int seg_prepare(const double P[3], const double Q[3], orc_seg *s)
+{
+    double p[3], q[3], c[3];
+    double lp = sqrt(dot3(P, P)), lq = sqrt(dot3(Q, Q));
+    if (!(lp > 0.0) || !(lq > 0.0))
+        return 0;
+    for (int r = 0; r < 3; ++r) {
+        p[r] = P[r] / lp;
+        q[r] = Q[r] / lq;
+    }
+    cross3(p, q, c);
+    double ln = sqrt(dot3(c, c));
+    if (!(ln > 0.0))
+        return 0;
+    double L[3] = {0.5 * (p[0] + q[0]), 0.5 * (p[1] + q[1]), 0.5 * (p[2] + q[2])};
+    double ll = sqrt(dot3(L, L));
+    if (!(ll > 0.0))
+        return 0;
+    for (int r = 0; r < 3; ++r) {
+        s->n[r] = c[r] / ln;
+        s->L[r] = L[r] / ll;
+    }
+    s->cos_r = ll;
+    s->sin_r = sqrt(1.0 - ll * ll > 0.0 ? 1.0 - ll * ll : 0.0);
+    return 1;
+}
+
+/* Line mask of a segment at direction g: the pixel-smooth line step of the
+ * great circle, 1 - min(|n.g| delta, 1), limited by the pixel step of the
+ * cap around the segment (its value divided by sin of the radius, as for
+ * the miter mask). */
+static double seg_mask(const orc_seg *s, const double g[3], double delta)
+{
+    double h = fabs(dot3(s->n, g)) * delta;
+    h = h < 1.0 ? 1.0 - h : 0.0;
+    if (!(h > 0.0))
+        return 0.0;
+    if (s->sin_r > 0.0) {
+        double c = gpstep((dot3(s->L, g) - s->cos_r) / s->sin_r, delta);
+        if (c < h)
+            h = c;
+    }
+    return h;
+}
+
+typedef struct {
+    const orc_view *v;
+    const float *xyz;
+    int64_t ntri;
+    const orc_seg *segs; /* 3 per triangle */
+    const uint8_t *seg_ok;
+    const int64_t *pix;
+    double *cov;
+    uint32_t *dom;
+    double *second; /* optional: second largest value among other triangles */
+} orc_wire_job;
+
+static void wire_pixel(void *ctx, int64_t q)
+{
+    const orc_wire_job *jb = (const orc_wire_job *)ctx;
+    int64_t p = jb->pix ? jb->pix[q] : q;
+    int32_t i = (int32_t)(p % jb->v->width), j = (int32_t)(p / jb->v->width);
+    double g[3], best = 0.0, second = 0.0;
+    uint32_t dom = ORC_NO_HIT;
+    if (orc_pixel_direction(jb->v, i, j, g)) {
+        double delta = orc_delta(jb->v, i, j);
+        for (int64_t t = 0; t < jb->ntri; ++t) {
+            double mt = 0.0;
+            for (int e = 0; e < 3; ++e)
+                if (jb->seg_ok[3 * t + e]) {
+                    double m = seg_mask(&jb->segs[3 * t + e], g, delta);
+                    if (m > mt)
+                        mt = m;
+                }
+            if (mt > best) {
+                second = best;
+                best = mt;
+                dom = (uint32_t)t;
+            } else if (mt > second) {
+                second = mt;
+            }
+        }
+    }
+    jb->cov[q] = best;
+    jb->dom[q] = dom;
+    if (jb->second)
+        jb->second[q] = second;
+}
+
+/* Wire frame of the live triangles' sides (segments AB, BC, CA): per pixel
+ * the largest line mask over all sides and the triangle it belongs to (ties:
+ * the lower id; NO_HIT when every mask is 0); `second` (optional) receives
+ * the largest mask of any other triangle.  Returns -1 on allocation
+ * failure. */
+int orc_wireframe(const orc_view *v, const float *xyz_soa, int64_t ntri, const int64_t *pix, int64_t npix,
+                  double *cov, uint32_t *dom, double *second, int32_t nthreads)
+{
+    if (!pix)
+        npix = (int64_t)v->width * v->height;
+    size_t m = (size_t)(ntri > 0 ? ntri : 1);
+    orc_seg *segs = (orc_seg *)malloc(sizeof(orc_seg) * 3 * m);
+    uint8_t *ok = (uint8_t *)malloc(3 * m);
+    if (!segs || !ok) {
+        free(segs);
+        free(ok);
+        return -1;
+    }
+    for (int64_t t = 0; t < ntri; ++t) {
+        double V[3][3];
+        orc_tri tr;
+        tri_prepare(xyz_soa, ntri, t, &tr);
+        for (int c = 0; c < 3; ++c)
+            load_vertex(xyz_soa, ntri, t, c, V[c]);
+        for (int e = 0; e < 3; ++e)
+            ok[3 * t + e] = (uint8_t)(tr.live && seg_prepare(V[e], V[(e + 1) % 3], &segs[3 * t + e]));
+    }
+    orc_wire_job jb = {v, xyz_soa, ntri, segs, ok, pix, cov, dom, second};
+    par_for(npix, nthreads, wire_pixel, &jb);
+    free(segs);
+    free(ok);
+    return 0;
+}
+
+/* Particles: position P (from O) and radius r, P.P > r^2 > 0. */
+typedef struct {
+    double P[3], dist, cos_r, sin_r, X[3], Y[3], scale;
+    int live;
+} orc_part;
+
+static void part_prepare(const float *pr, int64_t n, int64_t k, orc_part *o)
+{
+    double P[3] = {pr[0 * n + k], pr[1 * n + k], pr[2 * n + k]}, r = pr[3 * n + k];
+    double d = sqrt(dot3(P, P));
+    o->live = r > 0.0 && d > r;
+    if (!o->live)
+        return;
+    for (int c = 0; c < 3; ++c)
+        o->P[c] = P[c] / d;
+    o->dist = d;
+    o->sin_r = r / d;
+    o->cos_r = sqrt(1.0 - o->sin_r * o->sin_r);
+    /* texture axes: X = |(P_z, 0, -P_x)| (x axis when P is vertical), Y = X x P_hat */
+    double xl = sqrt(P[2] * P[2] + P[0] * P[0]);
+    if (xl > 0.0) {
+        o->X[0] = P[2] / xl;
+        o->X[1] = 0.0;
+        o->X[2] = -P[0] / xl;
+    } else {
+        o->X[0] = 1.0;
+        o->X[1] = 0.0;
+        o->X[2] = 0.0;
+    }
+    cross3(o->X, o->P, o->Y);
+    o->scale = d / (2.0 * r);
+}
+
+typedef struct {
+    const orc_view *v;
+    const orc_part *parts;
+    int64_t n;
+    const int64_t *pix;
+    double *cov, *depth, *uv;
+    uint32_t *dom;
+    double *aux;
+} orc_part_job;
+
+typedef struct {
+    double r, m, u, w;
+    uint32_t id;
+} orc_pfrag;
+
+static int pfrag_cmp(const void *a, const void *b)
+{
+    const orc_pfrag *x = (const orc_pfrag *)a, *y = (const orc_pfrag *)b;
+    if (x->r != y->r)
+        return x->r < y->r ? -1 : 1;
+    return x->id < y->id ? -1 : (x->id > y->id ? 1 : 0);
+}
+
+static void part_pixel(void *ctx, int64_t q)
+{
+    const orc_part_job *jb = (const orc_part_job *)ctx;
+    int64_t p = jb->pix ? jb->pix[q] : q;
+    int32_t i = (int32_t)(p % jb->v->width), j = (int32_t)(p / jb->v->width);
+    double g[3], m_b = 0.0, r_b = 0.0, u_b = 0.0, w_b = 0.0, best = 0.0, second = 0.0, gap = INFINITY;
+    double n_near = 0.0, sum_r = 0.0;
+    uint32_t dom = ORC_NO_HIT;
+    if (orc_pixel_direction(jb->v, i, j, g)) {
+        double delta = orc_delta(jb->v, i, j);
+        int64_t cap_n = 16, n = 0;
+        orc_pfrag *fr = (orc_pfrag *)malloc(sizeof(orc_pfrag) * (size_t)cap_n);
+        for (int64_t k = 0; fr && k < jb->n; ++k) {
+            const orc_part *pt = &jb->parts[k];
+            if (!pt->live)
+                continue;
+            double gp = dot3(g, pt->P);
+            double m = gpstep((gp - pt->cos_r) / pt->sin_r, delta);
+            if (!(m > 0.0) || !(gp > 0.0))
+                continue;
+            if (n == cap_n) {
+                cap_n *= 2;
+                orc_pfrag *nf = (orc_pfrag *)realloc(fr, sizeof(orc_pfrag) * (size_t)cap_n);
+                if (!nf) {
+                    free(fr);
+                    fr = NULL;
+                    break;
+                }
+                fr = nf;
+            }
+            fr[n].r = pt->dist / gp; /* where the ray meets the particle's plane */
+            fr[n].m = m;
+            fr[n].u = dot3(g, pt->X) * pt->scale + 0.5;
+            fr[n].w = dot3(g, pt->Y) * pt->scale + 0.5;
+            fr[n].id = (uint32_t)k;
+            ++n;
+        }
+        if (fr) {
+            qsort(fr, (size_t)n, sizeof(orc_pfrag), pfrag_cmp);
+            int64_t k = 0;
+            for (; k < n && m_b < 1.0; ++k) { /* section 1.4, texture coordinates as a pass too */
+                double mfc = fr[k].m < 1.0 - m_b ? fr[k].m : 1.0 - m_b;
+                m_b += mfc;
+                r_b += mfc * fr[k].r;
+                u_b += mfc * fr[k].u;
+                w_b += mfc * fr[k].w;
+                if (mfc > best) {
+                    second = best;
+                    best = mfc;
+                    dom = fr[k].id;
+                } else if (mfc > second) {
+                    second = mfc;
+                }
+            }
+            for (int64_t f = 0; f <= k && f < n; ++f) {
+                if (f > 0) {
+                    double step = (fr[f].r - fr[f - 1].r) / fr[f].r;
+                    if (step < gap)
+                        gap = step;
+                }
+                n_near += 1.0;
+                sum_r += fr[f].r;
+            }
+            free(fr);
+        }
+    }
+    jb->cov[q] = m_b;
+    jb->depth[q] = r_b;
+    jb->uv[2 * q] = u_b;
+    jb->uv[2 * q + 1] = w_b;
+    jb->dom[q] = dom;
+    if (jb->aux) {
+        double *a = jb->aux + 4 * q;
+        a[0] = best - second;
+        a[1] = gap;
+        a[2] = n_near;
+        a[3] = sum_r;
+    }
+}
+
+/* Particles (pr = float[4][n]: x, y, z, radius), section 1.3 mask with the
+ * pixel step of section 1.1.1 (the cap value divided by sin of its radius,
+ * like the miter mask), combined front to back by the depth where the ray
+ * meets the particle's plane (through P, normal P_hat) as in section 1.4:
+ * coverage, depth pass, texture-coordinate pass (2 per pixel) and dominant
+ * id.  aux (optional, 4 per pixel): share margin, smallest relative depth
+ * step, fragments taken + 1, their summed depth.  Particles with r <= 0 or
+ * the camera inside are skipped.  Returns -1 on allocation failure. */
+int orc_particles(const orc_view *v, const float *pr, int64_t n, const int64_t *pix, int64_t npix, double *cov,
+                  double *depth, double *uv, uint32_t *dom, double *aux, int32_t nthreads)
+{
+    if (!pix)
+        npix = (int64_t)v->width * v->height;
+    orc_part *parts = (orc_part *)malloc(sizeof(orc_part) * (size_t)(n > 0 ? n : 1));
+    if (!parts)
+        return -1;
+    for (int64_t k = 0; k < n; ++k)
+        part_prepare(pr, n, k, &parts[k]);
+    orc_part_job jb = {v, parts, n, pix, cov, depth, uv, dom, aux};
+    par_for(npix, nthreads, part_pixel, &jb);
+    free(parts);
     return 0;
 }
