@@ -52,7 +52,8 @@ extern "C" {
 
 /* vsr_build_map flags */
 #define VSR_STRICT 1u /* reject parameters outside the limits instead of clamping */
-#define VSR_MAP_AA 2u /* also store the global delta and widen the caps: see vsr_aa_raster */
+#define VSR_MAP_AA 2u       /* also store the global delta and widen the caps: see vsr_aa_raster   */
+#define VSR_MAP_AA_LINES 4u /* VSR_MAP_AA with caps widened for wire frames: see vsr_aa_wireframe */
 
 /* angle-of-view types (section 2, remark on normalising 2D coordinates) */
 #define VSR_AOV_HORIZONTAL 0
@@ -294,6 +295,57 @@ int vsr_aa_raster(const vsr_view* v, int32_t fmt, const void* map, const void* s
 int vsr_aa_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
                         const void* bins, int32_t bin_depth, float* coverage, float* depth_pass, uint32_t* dominant,
                         uint32_t* lost, uint64_t* stats, int32_t no_skip, void* stream);
+
+/* Step 8 — wire frame of the triangles' sides (section 1.2), aliasing-free.
+ * Per pixel and side P->Q of every listed live triangle: the line step of
+ * the side's great circle with the global delta, h = 1 - min(|n.G| delta, 1)
+ * (a strip one pixel wide each way), limited by the pixel step of the cap
+ * around the segment (centre |P_hat + Q_hat|, cos of the radius
+ * |(P_hat + Q_hat)/2|; value divided by sin of the radius).  Lines do not
+ * hide each other: coverage is the largest mask over all sides and dominant
+ * the triangle of that side (ties: the lower id; VSR_NO_HIT where nothing
+ * draws).
+ *   map          built with VSR_MAP_AA_LINES (caps widened by 5/4 pixel:
+ *                a side draws up to sqrt(5)/2 pixel from its segment);
+ *                bins from vsr_bin on that map and the triangles' setup.
+ *   xyz, ntri    the vertex array given to vsr_setup_tris.
+ *   coverage     device float[height][width]; dominant uint32[height][width]. */
+int vsr_aa_wireframe(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const float* xyz,
+                     int64_t ntri, const void* bins, int32_t bin_depth, float* coverage, uint32_t* dominant,
+                     void* stream);
+/* Instrumented vsr_aa_wireframe: stats[4] of uint64 receive (pixels with a
+ * direction x triangles tested, (pixel, triangle) pairs with a mask > 0, 0,
+ * tiles). */
+int vsr_aa_wireframe_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const float* xyz,
+                           int64_t ntri, const void* bins, int32_t bin_depth, float* coverage, uint32_t* dominant,
+                           uint64_t* stats, void* stream);
+
+/* Step 9 — procedural particles (section 1.3), aliasing-free, combined
+ * front to back (section 1.4).
+ * vsr_setup_particles prepares n spheres pr = device float[4][n] (rows x, y,
+ * z, radius; positions relative to O) into a setup buffer of
+ * vsr_setup_bytes(n) bytes, in the same layout as triangles (vsr_bin bins
+ * them unchanged; vsr_raster draws nothing for them).  A particle with
+ * radius <= 0 or containing O is skipped. */
+int vsr_setup_particles(const float* pr, int64_t n, void* setup, int64_t setup_bytes, void* stream);
+/* Per pixel and particle: mask = pixel step of (G.P_hat - cos rho)/sin rho,
+ * sin rho = r/|P| (the sphere's silhouette cone); depth where the ray meets
+ * the particle's plane (through P, normal P_hat), |P| / (G.P_hat); texture
+ * coordinates (G.X, G.Y) |P|/(2r) + 1/2 with X = |(P_z, 0, -P_x)| (the x
+ * axis for a vertical P) and Y = X x P_hat.  Fragments are combined nearest
+ * first by (depth, id) as in vsr_aa_raster; the texture coordinates as a
+ * pass like the depth (section 1.4).
+ *   map          built with VSR_MAP_AA; bins from vsr_bin on it and the
+ *                particles' setup.
+ *   uv           optional device float[2][height][width] (u plane, then v).
+ *   other outputs and lost as in vsr_aa_raster. */
+int vsr_aa_particles(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t n, const void* bins,
+                     int32_t bin_depth, float* coverage, float* depth_pass, float* uv, uint32_t* dominant,
+                     uint32_t* lost, void* stream);
+/* Instrumented vsr_aa_particles (stats as in vsr_aa_raster_stats). */
+int vsr_aa_particles_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t n,
+                           const void* bins, int32_t bin_depth, float* coverage, float* depth_pass, float* uv,
+                           uint32_t* dominant, uint32_t* lost, uint64_t* stats, int32_t no_skip, void* stream);
 
 /* ------------------------------------------------------------- batches */
 

@@ -41,6 +41,7 @@ struct AAArgs {
     float* cov;
     float* dpass;
     uint32_t* dom;
+    float* uv;                      // particles: texture-coordinate pass, 2 planes
     uint32_t* lost;                 // pixels whose list overflowed unsaturated
     unsigned long long* stats;      // optional: tests, fragments inserted, triangles skipped, tiles
     int32_t no_skip;                // instrumented variant only: test every listed triangle
@@ -51,9 +52,13 @@ __device__ inline bool frag_less(float ra, uint32_t ia, float rb, uint32_t ib) {
     return ra < rb || (ra == rb && ia < ib);
 }
 
+// Per-lane fragment list; with kUV each fragment also carries texture
+// coordinates (particles), combined like the depth (section 1.4).
+template <bool kUV>
 struct FragList {
     float r[kAAFrags], m[kAAFrags];
     uint32_t id[kAAFrags];
+    float u[kUV ? kAAFrags : 1], w[kUV ? kAAFrags : 1];
     int cnt;
     float rsat;      // depth of the fragment that saturates the pixel, +inf if none
     uint32_t idsat;
@@ -68,9 +73,9 @@ struct FragList {
 
     // The loops are unrolled with constant indices (the list stays in
     // registers); a step that no lane of the wave needs is branched over.
-    __device__ inline void insert(float rr, uint32_t ii, float mm) {
+    __device__ inline void insert(float rr, uint32_t ii, float mm, float uu = 0.0f, float ww = 0.0f) {
         if (!frag_less(rr, ii, rsat, idsat)) return;  // behind the saturated prefix: zero share
-        float cr = rr, cm = mm;
+        float cr = rr, cm = mm, cu = uu, cw = ww;
         uint32_t ci = ii;
 #pragma unroll
         for (int k = 0; k < kAAFrags; ++k) {
@@ -84,11 +89,22 @@ struct FragList {
                     cr = tr;
                     cm = tm;
                     ci = ti;
+                    if (kUV) {
+                        float tu = u[k], tw = w[k];
+                        u[k] = cu;
+                        w[k] = cw;
+                        cu = tu;
+                        cw = tw;
+                    }
                 }
             } else if (k == cnt) {
                 r[k] = cr;
                 m[k] = cm;
                 id[k] = ci;
+                if (kUV) {
+                    u[k] = cu;
+                    w[k] = cw;
+                }
             }
         }
         const bool dropped = (cnt == kAAFrags);
@@ -112,9 +128,11 @@ struct FragList {
         if (dropped && rsat == __int_as_float(0x7F800000)) lost = true;
     }
 
-    __device__ inline void combine(float& mb, float& rb, uint32_t& dom) const {
+    __device__ inline void combine(float& mb, float& rb, float& ub, float& wb, uint32_t& dom) const {
         mb = 0.0f;
         rb = 0.0f;
+        ub = 0.0f;
+        wb = 0.0f;
         dom = kNoHit;
         float best = 0.0f;
 #pragma unroll
@@ -123,6 +141,10 @@ struct FragList {
                 float mfc = fminf(m[k], 1.0f - mb);
                 mb += mfc;
                 rb = fmaf(mfc, r[k], rb);
+                if (kUV) {
+                    ub = fmaf(mfc, u[k], ub);
+                    wb = fmaf(mfc, w[k], wb);
+                }
                 if (mfc > best) {
                     best = mfc;
                     dom = id[k];
@@ -155,7 +177,7 @@ __device__ inline float2 miter_consts(float sh) {
 // One triangle against the lane's pixel: inserts its fragment, if any.
 // c0 = (S, -), c1 = (a, b, -, -).
 __device__ inline bool aa_rec(float4 r0, float4 r1, float4 r2, float4 r3, float4 c0, float4 c1, float3 g, float delta,
-                              FragList& L) {
+                              FragList<false>& L) {
     float e0 = fmaf(r0.z, g.z, fmaf(r0.y, g.y, r0.x * g.x));
     float e1 = fmaf(r1.z, g.z, fmaf(r1.y, g.y, r1.x * g.x));
     float e2 = fmaf(r2.z, g.z, fmaf(r2.y, g.y, r2.x * g.x));
@@ -167,6 +189,38 @@ __device__ inline bool aa_rec(float4 r0, float4 r1, float4 r2, float4 r3, float4
         float dn = fmaf(r2.w, g.z, fmaf(r1.w, g.y, r0.w * g.x));
         if (dn > 0.0f) {
             L.insert(r3.x * __builtin_amdgcn_rcpf(dn), __float_as_uint(r3.z), m);
+            return true;
+        }
+    }
+    return false;
+}
+
+// Texture axes of a particle seen along P_hat (section 1.3): X = |(P_z, 0,
+// -P_x)| (the x axis when P is vertical) and the scale |P|/(2r) =
+// 1/(2 sin rho) from the rim's half-angle sine sh.
+__device__ inline float4 particle_axes(float3 Ph, float sh) {
+    float xl = sqrtf(fmaf(Ph.z, Ph.z, Ph.x * Ph.x));
+    float3 X = xl > 0.0f ? f3(Ph.z / xl, 0.0f, -Ph.x / xl) : f3(1.0f, 0.0f, 0.0f);
+    float ch = sqrtf(fmaxf(0.0f, 1.0f - sh * sh));
+    return make_float4(X.x, X.y, X.z, 0.25f / (sh * ch));
+}
+
+// One particle against the lane's pixel: the cap value (S = P_hat) through
+// the miter constants c1 = (a, b), depth on the particle's plane, texture
+// coordinates from the axes ax = (X, scale).
+__device__ inline bool part_rec(float4 r0, float4 r1, float4 r2, float4 r3, float4 c0, float4 c1, float4 ax, float3 g,
+                                float delta, FragList<true>& L) {
+    float dx = g.x - c0.x, dy = g.y - c0.y, dz = g.z - c0.z;
+    float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    float m = gpstep(fmaf(-q, c1.y, c1.x), delta);
+    if (m > 0.0f) {
+        const float3 N = f3(r0.w, r1.w, r2.w);
+        float dn = fmaf(N.z, g.z, fmaf(N.y, g.y, N.x * g.x));
+        if (dn > 0.0f) {
+            const float3 X = f3(ax.x, ax.y, ax.z);
+            const float3 Y = cross3(X, N);
+            float u = fmaf(dot3(g, X), ax.w, 0.5f), w = fmaf(dot3(g, Y), ax.w, 0.5f);
+            L.insert(r3.x * __builtin_amdgcn_rcpf(dn), __float_as_uint(r3.z), m, u, w);
             return true;
         }
     }
@@ -185,8 +239,11 @@ __device__ inline float plane_min_depth(float3 N, float d, float3 c, float cr, f
     return cm > 0.0f ? d / cm : __int_as_float(0x7F800000);
 }
 
-template <bool kStats>
+constexpr int kPrimTriangles = 0, kPrimParticles = 1;
+
+template <bool kStats, int kPrim>
 __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* stg) {
+    constexpr bool kPart = kPrim == kPrimParticles;
     const float4* caps = map_caps(A.map, A.ntiles, A.fmt);
     SceneView S = scene_view(A.setup, A.n);
     const char* bb = reinterpret_cast<const char*>(A.bins);
@@ -201,7 +258,7 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
     float3 g = load_dir(A.map, A.fmt, A.ntiles, tile, lane, A.rot);
     float delta = dplane[tile * kTilePix + lane];
     bool has_dir = inside && delta > 0.0f;
-    FragList L;
+    FragList<kPart> L;
     L.init();
     if (!has_dir) L.rsat = 0.0f;  // nothing can cover it
 
@@ -220,8 +277,12 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
         if (!may_skip || !(rmax < __int_as_float(0x7F800000))) return false;
         return plane_min_depth(N, d, tcen, tcr, tsr, twide) * (1.0f - 1e-4f) > rmax;
     };
-    auto visit = [&](float4 r0, float4 r1, float4 r2, float4 r3, float4 c0, float4 c1) {
-        bool f = has_dir && aa_rec(r0, r1, r2, r3, c0, c1, g, delta, L);
+    auto visit = [&](float4 r0, float4 r1, float4 r2, float4 r3, float4 c0, float4 c1, float4 ax) {
+        bool f;
+        if constexpr (kPart)
+            f = has_dir && part_rec(r0, r1, r2, r3, c0, c1, ax, g, delta, L);
+        else
+            f = has_dir && aa_rec(r0, r1, r2, r3, c0, c1, g, delta, L);
         if (kStats) {
             ++n_test;
             n_frag += __popcll(__ballot(f));
@@ -234,7 +295,8 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
         const uint32_t sub = uint32_t(lane) >> 3, part = uint32_t(lane) & 7u;
         const uint32_t ngroups = (count + 7u) >> 3;
         // this lane's word of triangle `sub` of a group: record words 0..3,
-        // cap words 4..5, and for lane 6 the plane (N, d) of the skip test
+        // cap words 4..5, for lane 6 the plane (N, d) of the skip test, and
+        // for particles lane 7 the plane normal and the rim (texture axes)
         auto fetch = [&](uint32_t e) {
             float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
             if (e < count) {
@@ -247,6 +309,9 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
                 } else if (part == 6u) {
                     const float* rw = reinterpret_cast<const float*>(rec);
                     w = make_float4(rw[3], rw[7], rw[11], rw[12]);
+                } else if (kPart) {
+                    const float* rw = reinterpret_cast<const float*>(rec);
+                    w = make_float4(rw[3], rw[7], rw[11], S.cap[2 * int64_t(rk) + 1].w);
                 }
             }
             return w;
@@ -263,6 +328,8 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
             } else if (part == 6u && present) {
                 // this lane decides for the whole wave whether the triangle can matter
                 live = !skippable(f3(v.x, v.y, v.z), v.w, rmax);
+            } else if (kPart && part == 7u && present) {
+                st = particle_axes(f3(v.x, v.y, v.z), v.w);
             }
             // bit t: triangle t of the group is to be tested
             const uint32_t todo = pack_group_bits(__ballot(live && part == 6u));
@@ -277,7 +344,7 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
             if (gi + 1 < ngroups) v = fetch((gi + 1) * 8u + sub);
             for (uint32_t m = todo; m; m &= m - 1) {
                 const float4* w = stg + 8 * uint32_t(__ffs(m) - 1);
-                visit(w[0], w[1], w[2], w[3], w[4], w[5]);
+                visit(w[0], w[1], w[2], w[3], w[4], w[5], w[7]);
             }
         }
     } else {
@@ -297,19 +364,25 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
                     if (kStats) ++n_skip;
                     continue;
                 }
-                visit(r0, r1, r2, r3, S.cap[2 * int64_t(rk)], make_float4(mc.x, mc.y, 0.f, 0.f));
+                float4 ax = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (kPart) ax = particle_axes(f3(r0.w, r1.w, r2.w), c1.w);
+                visit(r0, r1, r2, r3, S.cap[2 * int64_t(rk)], make_float4(mc.x, mc.y, 0.f, 0.f), ax);
             }
         });
     }
 
-    float mb, rb;
+    float mb, rb, ub, wb;
     uint32_t dm;
-    L.combine(mb, rb, dm);
+    L.combine(mb, rb, ub, wb, dm);
     if (inside) {
         int64_t o = int64_t(j) * A.W + i;
         A.cov[o] = mb;
         A.dpass[o] = rb;
         A.dom[o] = dm;
+        if (kPart && A.uv) {
+            A.uv[o] = ub;
+            A.uv[int64_t(A.W) * A.H + o] = wb;
+        }
     }
     if (A.lost) {
         uint32_t c = uint32_t(__popcll(__ballot(L.lost)));
@@ -324,18 +397,21 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
     }
 }
 
-template <bool kStats>
+template <bool kStats, int kPrim>
 __global__ __launch_bounds__(256) void k_aa_raster(AAArgs A) {
     __shared__ float4 s_stage[4][64];
     int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
     if (tile >= A.ntiles) return;
-    aa_tile<kStats>(A, tile, threadIdx.x & 63, s_stage[w]);
+    aa_tile<kStats, kPrim>(A, tile, threadIdx.x & 63, s_stage[w]);
 }
 
+// prim: kPrimTriangles (setup of vsr_setup_tris) or kPrimParticles (setup
+// of vsr_setup_particles; uv receives the texture-coordinate pass).
 hipError_t launch_aa_raster(const void* map, int32_t W, int32_t H, int32_t fmt, const Rot& R, const void* setup,
                             int64_t n, const void* bins, int32_t depth, float* cov, float* dpass, uint32_t* dom,
-                            uint32_t* lost, unsigned long long* stats, int32_t no_skip, hipStream_t st) {
+                            uint32_t* lost, unsigned long long* stats, int32_t no_skip, hipStream_t st,
+                            int prim = kPrimTriangles, float* uv = nullptr) {
     MapLayout ML = map_layout(W, H, fmt);
     AAArgs A;
     A.map = map;
@@ -351,17 +427,25 @@ hipError_t launch_aa_raster(const void* map, int32_t W, int32_t H, int32_t fmt, 
     A.cov = cov;
     A.dpass = dpass;
     A.dom = dom;
+    A.uv = uv;
     A.lost = lost;
     A.stats = stats;
     A.no_skip = no_skip;
     A.rot = R;
     int64_t blocks = (ML.ntiles + 3) / 4;
     if (lost) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, lost, int64_t(1));
-    if (stats) {
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(stats), int64_t(8));
-        hipLaunchKernelGGL(k_aa_raster<true>, dim3(unsigned(blocks)), dim3(256), 0, st, A);
+    if (stats) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(stats), int64_t(8));
+    const dim3 grid = dim3(unsigned(blocks)), block = dim3(256);
+    if (prim == kPrimParticles) {
+        if (stats)
+            hipLaunchKernelGGL((k_aa_raster<true, kPrimParticles>), grid, block, 0, st, A);
+        else
+            hipLaunchKernelGGL((k_aa_raster<false, kPrimParticles>), grid, block, 0, st, A);
     } else {
-        hipLaunchKernelGGL(k_aa_raster<false>, dim3(unsigned(blocks)), dim3(256), 0, st, A);
+        if (stats)
+            hipLaunchKernelGGL((k_aa_raster<true, kPrimTriangles>), grid, block, 0, st, A);
+        else
+            hipLaunchKernelGGL((k_aa_raster<false, kPrimTriangles>), grid, block, 0, st, A);
     }
     return hipGetLastError();
 }

@@ -14,6 +14,7 @@
 #include "resolve.hpp"
 #include "setup.hpp"
 #include "submit.hpp"
+#include "wire.hpp"
 
 using namespace vsr;
 
@@ -111,7 +112,7 @@ int make_map_params(const vsr_view* v, int32_t fmt, uint32_t flags, MapParams* P
     P->lens = VSR_LENS_UNIVERSAL;
     P->lens_n = 1;
     P->distort = 0;
-    P->pad_ = 0;
+    P->fringe = 0.5f;
     for (int q = 0; q < 8; ++q) P->lp[q] = 0.0f;
     if (eff) {
         *eff = *v;
@@ -203,8 +204,9 @@ int vsr_build_map(const vsr_view* v, int32_t fmt, uint32_t flags, void* map, int
     int rc = make_map_params(v, fmt, flags, &P, v_eff);
     if (rc != VSR_OK) return rc;
     if (!map || !aligned(map)) return fail(VSR_E_ARG, "map buffer NULL or not 256-byte aligned");
-    if ((flags & ~(VSR_STRICT | VSR_MAP_AA)) != 0) return fail(VSR_E_ARG, "unknown flags 0x%x", flags);
-    const bool aa = (flags & VSR_MAP_AA) != 0;
+    if ((flags & ~(VSR_STRICT | VSR_MAP_AA | VSR_MAP_AA_LINES)) != 0) return fail(VSR_E_ARG, "unknown flags 0x%x", flags);
+    const bool aa = (flags & (VSR_MAP_AA | VSR_MAP_AA_LINES)) != 0;
+    if (flags & VSR_MAP_AA_LINES) P.fringe = 1.25f;
     int64_t need = aa ? aa_map_bytes(v->width, v->height, fmt) : map_layout(v->width, v->height, fmt).bytes;
     if (map_bytes < need) return fail(VSR_E_SPACE, "map buffer %lld < %lld bytes", (long long)map_bytes, (long long)need);
     return hip_status(launch_build_map(P, map, aa, hipStream_t(stream)), "vsr_build_map");
@@ -221,8 +223,9 @@ int vsr_build_map_lens(const vsr_view* v, const vsr_lens* lens, int32_t fmt, uin
     rc = make_lens_params(lens, &P);
     if (rc != VSR_OK) return rc;
     if (!map || !aligned(map)) return fail(VSR_E_ARG, "map buffer NULL or not 256-byte aligned");
-    if ((flags & ~(VSR_STRICT | VSR_MAP_AA)) != 0) return fail(VSR_E_ARG, "unknown flags 0x%x", flags);
-    const bool aa = (flags & VSR_MAP_AA) != 0;
+    if ((flags & ~(VSR_STRICT | VSR_MAP_AA | VSR_MAP_AA_LINES)) != 0) return fail(VSR_E_ARG, "unknown flags 0x%x", flags);
+    const bool aa = (flags & (VSR_MAP_AA | VSR_MAP_AA_LINES)) != 0;
+    if (flags & VSR_MAP_AA_LINES) P.fringe = 1.25f;
     int64_t need = aa ? aa_map_bytes(v->width, v->height, fmt) : map_layout(v->width, v->height, fmt).bytes;
     if (map_bytes < need) return fail(VSR_E_SPACE, "map buffer %lld < %lld bytes", (long long)map_bytes, (long long)need);
     return hip_status(launch_build_map(P, map, aa, hipStream_t(stream)), "vsr_build_map_lens");
@@ -346,6 +349,89 @@ int vsr_aa_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const v
     if (!stats) return fail(VSR_E_ARG, "stats is NULL");
     return aa_raster_common(v, fmt, map, setup, ntri, bins, bin_depth, coverage, depth_pass, dominant, lost, stats,
                             no_skip, stream, "vsr_aa_raster_stats");
+}
+
+int vsr_setup_particles(const float* pr, int64_t n, void* setup, int64_t setup_bytes, void* stream) {
+    if (n < 0 || n > (int64_t(1) << 31)) return fail(VSR_E_ARG, "n %lld out of range", (long long)n);
+    if ((n > 0 && !pr) || !setup || !aligned(setup)) return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if ((reinterpret_cast<uintptr_t>(pr) & 3u) != 0) return fail(VSR_E_ARG, "particle array not 4-byte aligned");
+    int64_t need = setup_layout(n).bytes;
+    if (setup_bytes < need)
+        return fail(VSR_E_SPACE, "setup buffer %lld < %lld bytes", (long long)setup_bytes, (long long)need);
+    return hip_status(launch_setup_particles(pr, n, setup, hipStream_t(stream)), "vsr_setup_particles");
+}
+
+static int aa_particles_common(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t n,
+                               const void* bins, int32_t bin_depth, float* coverage, float* depth_pass, float* uv,
+                               uint32_t* dominant, uint32_t* lost, uint64_t* stats, int32_t no_skip, void* stream,
+                               const char* what) {
+    int rc = check_view_buffers(v, fmt);
+    if (rc != VSR_OK) return rc;
+    if (!map || !setup || !bins || !coverage || !depth_pass || !dominant || !aligned(map) || !aligned(setup) ||
+        !aligned(bins))
+        return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    const uintptr_t mis = reinterpret_cast<uintptr_t>(coverage) | reinterpret_cast<uintptr_t>(depth_pass) |
+                          reinterpret_cast<uintptr_t>(dominant) | reinterpret_cast<uintptr_t>(lost) |
+                          reinterpret_cast<uintptr_t>(uv);
+    if (mis & 3u) return fail(VSR_E_ARG, "output not 4-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(stats) & 7u) != 0) return fail(VSR_E_ARG, "stats not 8-byte aligned");
+    if (n < 0 || n > (int64_t(1) << 31)) return fail(VSR_E_ARG, "n out of range");
+    if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
+    return hip_status(launch_aa_raster(map, v->width, v->height, fmt, rot_of(v->rot), setup, n, bins, bin_depth,
+                                       coverage, depth_pass, dominant, lost,
+                                       reinterpret_cast<unsigned long long*>(stats), no_skip, hipStream_t(stream),
+                                       kPrimParticles, uv),
+                      what);
+}
+
+int vsr_aa_particles(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t n, const void* bins,
+                     int32_t bin_depth, float* coverage, float* depth_pass, float* uv, uint32_t* dominant,
+                     uint32_t* lost, void* stream) {
+    return aa_particles_common(v, fmt, map, setup, n, bins, bin_depth, coverage, depth_pass, uv, dominant, lost,
+                               nullptr, 0, stream, "vsr_aa_particles");
+}
+
+int vsr_aa_particles_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t n,
+                           const void* bins, int32_t bin_depth, float* coverage, float* depth_pass, float* uv,
+                           uint32_t* dominant, uint32_t* lost, uint64_t* stats, int32_t no_skip, void* stream) {
+    if (!stats) return fail(VSR_E_ARG, "stats is NULL");
+    return aa_particles_common(v, fmt, map, setup, n, bins, bin_depth, coverage, depth_pass, uv, dominant, lost,
+                               stats, no_skip, stream, "vsr_aa_particles_stats");
+}
+
+static int wireframe_common(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const float* xyz,
+                            int64_t ntri, const void* bins, int32_t bin_depth, float* coverage, uint32_t* dominant,
+                            uint64_t* stats, void* stream, const char* what) {
+    int rc = check_view_buffers(v, fmt);
+    if (rc != VSR_OK) return rc;
+    if (!map || !setup || !bins || !coverage || !dominant || (ntri > 0 && !xyz) || !aligned(map) ||
+        !aligned(setup) || !aligned(bins))
+        return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    const uintptr_t mis = reinterpret_cast<uintptr_t>(coverage) | reinterpret_cast<uintptr_t>(dominant) |
+                          reinterpret_cast<uintptr_t>(xyz);
+    if (mis & 3u) return fail(VSR_E_ARG, "array not 4-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(stats) & 7u) != 0) return fail(VSR_E_ARG, "stats not 8-byte aligned");
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri out of range");
+    if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
+    return hip_status(launch_wire(map, v->width, v->height, fmt, rot_of(v->rot), setup, xyz, ntri, bins, bin_depth,
+                                  coverage, dominant, reinterpret_cast<unsigned long long*>(stats),
+                                  hipStream_t(stream)),
+                      what);
+}
+
+int vsr_aa_wireframe(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const float* xyz,
+                     int64_t ntri, const void* bins, int32_t bin_depth, float* coverage, uint32_t* dominant,
+                     void* stream) {
+    return wireframe_common(v, fmt, map, setup, xyz, ntri, bins, bin_depth, coverage, dominant, nullptr, stream,
+                            "vsr_aa_wireframe");
+}
+
+int vsr_aa_wireframe_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const float* xyz,
+                           int64_t ntri, const void* bins, int32_t bin_depth, float* coverage, uint32_t* dominant,
+                           uint64_t* stats, void* stream) {
+    if (!stats) return fail(VSR_E_ARG, "stats is NULL");
+    return wireframe_common(v, fmt, map, setup, xyz, ntri, bins, bin_depth, coverage, dominant, stats, stream,
+                            "vsr_aa_wireframe_stats");
 }
 
 int64_t vsr_render_bytes(int32_t width, int32_t height) {

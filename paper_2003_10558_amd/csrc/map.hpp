@@ -254,7 +254,10 @@ __device__ inline void tile_cap(float3 g, bool ok, float4& c0, float4& c1) {
 // is widened by the fringe the pixel step adds outside an edge: a pixel is
 // touched by a triangle when every edge value exceeds -1/(2 delta) (and the
 // miter value, whose cap grows by no more for radii up to pi/2), i.e. within
-// asin(1/(2 delta)) of each edge's half-sphere.
+// asin(1/(2 delta)) of each edge's half-sphere.  For wire frames the fringe
+// is 5/4 pixel: a line mask reaches 1/delta from the great circle and half a
+// pixel past the segment's cap, so within sqrt(1 + 1/4) < 5/4 pixel of the
+// segment (P.fringe holds the factor).
 template <bool kAA>
 __device__ inline void build_map_tile(const MapParams& P, void* map, int64_t ntiles, int64_t tile, int lane,
                                       float4& c0, float4& c1) {
@@ -270,7 +273,7 @@ __device__ inline void build_map_tile(const MapParams& P, void* map, int64_t nti
         float delta = ok ? pixel_delta(P, i, j, g) : 0.0f;
         float* dplane = reinterpret_cast<float*>(reinterpret_cast<char*>(map) + aa_delta_off(P.W, P.H, P.fmt));
         dplane[q] = delta;
-        fringe = wave_max(ok ? 0.5f / delta : 0.0f);
+        fringe = wave_max(ok ? P.fringe / delta : 0.0f);
     }
     if (P.fmt == VSR_MAP_OCT16) {
         uint32_t w = ok ? oct_encode(g) : kOctInvalid;

@@ -450,15 +450,80 @@ __global__ __launch_bounds__(64) void k_face_count(const uint32_t* __restrict__ 
     face_count[s * 64 + p] = c;
 }
 
-hipError_t launch_setup(const float* xyz, int64_t n, void* setup, hipStream_t st) {
+// Section 1.3 particles as primitives of the same setup: position P and
+// radius r (pr = float[4][n]).  The record holds no edge planes (zero
+// normals pass every edge test of the binner), the plane through P with
+// normal P_hat (where texture coordinates live and depth is measured), and
+// |P| as depth lower bound; the cap is the sphere's silhouette cone,
+// sin(rho) = r/|P|, with the exact half-angle sine in its last word.  A
+// particle with r <= 0 or containing O covers nothing.
+__global__ __launch_bounds__(256) void k_setup_particles(const float* __restrict__ pr, int64_t n,
+                                                         float4* __restrict__ rec_id, float4* __restrict__ cap_id,
+                                                         uint32_t* __restrict__ key, uint32_t* __restrict__ val,
+                                                         uint32_t* __restrict__ bucket) {
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    float3 P = f3(pr[0 * n + t], pr[1 * n + t], pr[2 * n + t]);
+    float r = pr[3 * n + t];
+    float d = sqrtf(dot3(P, P));
+    bool live = r > 0.0f && d > r;
+    float4 r0, r1, r2, r3, c0, c1;
+    uint32_t bkt = uint32_t(kNumBuckets);
+    float lb = __int_as_float(0x7F800000);
+    if (live) {
+        float3 Ph = scale3(P, 1.0f / d);
+        lb = d * (1.0f - 1.0f / 65536.0f);
+        r0 = make_float4(0.0f, 0.0f, 0.0f, Ph.x);
+        r1 = make_float4(0.0f, 0.0f, 0.0f, Ph.y);
+        r2 = make_float4(0.0f, 0.0f, 0.0f, Ph.z);
+        r3 = make_float4(d, lb, __uint_as_float(uint32_t(t)), 0.0f);
+        float s = fminf(1.0f, r / d);
+        float sh_rim = sinf(0.5f * asinf(s));
+        float rho = 2.0f * asinf(sh_rim);
+        rho = rho * (1.0f + kCapRelMargin) + kCapAbsMargin;
+        int L = 0;
+        if (rho < kHalfPi) {
+            float sh, chh;
+            sincosf(0.5f * rho, &sh, &chh);
+            c0 = make_float4(Ph.x, Ph.y, Ph.z, sh);
+            c1 = make_float4(chh, sinf(rho), 0.0f, sh_rim);
+            while (L < kMaxLevel && rho <= kQuarterPi / float(1 << (L + 1))) ++L;
+            if (rho > kQuarterPi) L = 0;
+            bkt = cell_of(Ph, L);
+        } else {
+            c0 = make_float4(Ph.x, Ph.y, Ph.z, 1.0f);
+            c1 = make_float4(0.0f, 1.0f, kCapWide, sh_rim);
+            bkt = uint32_t(level_base(0));
+        }
+    } else {
+        r0 = r1 = r2 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        r3 = make_float4(0.0f, lb, __uint_as_float(uint32_t(t)), 0.0f);
+        c0 = make_float4(0.0f, 0.0f, 1.0f, 0.0f);
+        c1 = make_float4(1.0f, 0.0f, kCapEmpty, 0.0f);
+    }
+    rec_id[4 * t + 0] = r0;
+    rec_id[4 * t + 1] = r1;
+    rec_id[4 * t + 2] = r2;
+    rec_id[4 * t + 3] = r3;
+    cap_id[2 * t + 0] = c0;
+    cap_id[2 * t + 1] = c1;
+    key[t] = __float_as_uint(lb);
+    val[t] = uint32_t(t);
+    bucket[t] = bkt;
+}
+
+// Setup of n primitives: `prims` writes the per-primitive records (id
+// order), then the nearest-first order, depth buckets and cap index are
+// built the same way for every kind of primitive.
+template <typename Prims>
+hipError_t launch_setup_common(int64_t n, void* setup, hipStream_t st, Prims prims) {
     SetupLayout L = setup_layout(n);
     char* base = reinterpret_cast<char*>(setup);
     auto U = [&](int64_t off) { return reinterpret_cast<uint32_t*>(base + off); };
     auto F4 = [&](int64_t off) { return reinterpret_cast<float4*>(base + off); };
     if (n > 0) {
         unsigned blocks = unsigned((n + 255) / 256);
-        hipLaunchKernelGGL(k_setup_tris, dim3(blocks), dim3(256), 0, st, xyz, n, F4(L.rec_id_off), F4(L.cap_id_off),
-                           U(L.key_a_off), U(L.val_a_off), U(L.bucket_off));
+        prims(blocks, F4(L.rec_id_off), F4(L.cap_id_off), U(L.key_a_off), U(L.val_a_off), U(L.bucket_off));
         bool in_b = false;
         hipError_t e = radix_sort(U(L.key_a_off), U(L.val_a_off), U(L.key_b_off), U(L.val_b_off), U(L.hist_off), n,
                                   32, &in_b, st);
@@ -488,6 +553,24 @@ hipError_t launch_setup(const float* xyz, int64_t n, void* setup, hipStream_t st
     }
     hipLaunchKernelGGL(k_face_count, dim3(kSlices), dim3(64), 0, st, U(L.cell_start_off), U(L.face_count_off));
     return hipGetLastError();
+}
+
+hipError_t launch_setup(const float* xyz, int64_t n, void* setup, hipStream_t st) {
+    return launch_setup_common(n, setup, st,
+                               [&](unsigned blocks, float4* rec, float4* cap, uint32_t* key, uint32_t* val,
+                                   uint32_t* bkt) {
+                                   hipLaunchKernelGGL(k_setup_tris, dim3(blocks), dim3(256), 0, st, xyz, n, rec, cap,
+                                                      key, val, bkt);
+                               });
+}
+
+hipError_t launch_setup_particles(const float* pr, int64_t n, void* setup, hipStream_t st) {
+    return launch_setup_common(n, setup, st,
+                               [&](unsigned blocks, float4* rec, float4* cap, uint32_t* key, uint32_t* val,
+                                   uint32_t* bkt) {
+                                   hipLaunchKernelGGL(k_setup_particles, dim3(blocks), dim3(256), 0, st, pr, n, rec,
+                                                      cap, key, val, bkt);
+                               });
 }
 
 }  // namespace vsr

@@ -4,6 +4,7 @@
 //   raster.hpp  conservative binning + rasterizer       (steps 3, 4)
 //   submit.hpp  batched views                           (step 5)
 //   resolve.hpp fragment data from barycentrics         (section 1.1.4)
-//   aa.hpp      aliasing-free coverage                  (sections 1.1.1, 1.1.2, 1.4)
+//   aa.hpp      aliasing-free coverage, particles       (sections 1.1.1, 1.1.2, 1.3, 1.4)
+//   wire.hpp    aliasing-free wire frame                (section 1.2)
 //   api.hpp     C ABI (include/vsr.h)
 #include "api.hpp"

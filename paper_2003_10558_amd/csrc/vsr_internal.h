@@ -112,7 +112,7 @@ struct MapParams {
     int32_t lens;       // map generator, VSR_LENS_*
     int32_t lens_n;     // screen array: number of screens
     int32_t distort;    // Universal: Brown-Conrady coefficients not all zero
-    int32_t pad_;
+    float fringe;       // AA maps: caps widened by asin(fringe / delta) (1/2: triangles, 5/4: lines)
     float lp[8];        // generator constants (set by the host, see make_map_params)
 };
 

@@ -143,6 +143,94 @@ def render_aa(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, bin_depth: int = D
     return frame
 
 
+@dataclass
+class WireFrame:
+    coverage: torch.Tensor    # float32 [H, W], largest line mask
+    dominant: torch.Tensor    # uint32 as int32 storage, [H, W]
+    map: torch.Tensor
+    bins: torch.Tensor
+    view_eff: object
+
+
+def render_wireframe(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, bin_depth: int = DEFAULT_BIN_DEPTH,
+                     bin_flags: int = 0, stream=None, frame: Optional[WireFrame] = None,
+                     stats: Optional[torch.Tensor] = None) -> WireFrame:
+    """Aliasing-free wire frame of the scene's triangle sides:
+    build_map (VSR_MAP_AA_LINES) -> bin -> vsr_aa_wireframe."""
+    dev = scene.device
+    H, W = view.height, view.width
+    if frame is None:
+        frame = WireFrame(torch.empty((H, W), dtype=torch.float32, device=dev),
+                          torch.empty((H, W), dtype=torch.int32, device=dev),
+                          _buffer(vsr.vsr_aa_map_bytes(W, H, fmt), dev),
+                          _buffer(vsr.vsr_bin_bytes(W, H, bin_depth), dev), None)
+    frame.view_eff = build_map(view, fmt, vsr.VSR_MAP_AA_LINES, frame.map, stream)
+    vsr.vsr_bin(view, fmt, frame.map, scene.setup, scene.ntri, bin_depth, bin_flags, frame.bins, stream)
+    if stats is None:
+        vsr.vsr_aa_wireframe(view, fmt, frame.map, scene.setup, scene.xyz, scene.ntri, frame.bins, bin_depth,
+                             frame.coverage, frame.dominant, stream)
+    else:
+        vsr.vsr_aa_wireframe_stats(view, fmt, frame.map, scene.setup, scene.xyz, scene.ntri, frame.bins, bin_depth,
+                                   frame.coverage, frame.dominant, stats, stream)
+    return frame
+
+
+class ParticleScene:
+    """Particles (float[4][n]: x, y, z, radius) resident on the GPU with their
+    setup (vsr_setup_particles)."""
+
+    def __init__(self, pr: np.ndarray | torch.Tensor, device="cuda", stream=None):
+        if isinstance(pr, np.ndarray):
+            pr = torch.from_numpy(np.ascontiguousarray(pr, dtype=np.float32))
+        self.pr = pr.to(device=device, dtype=torch.float32).contiguous()
+        assert self.pr.dim() == 2 and self.pr.shape[0] == 4
+        self.ntri = self.n = int(self.pr.shape[1])
+        self.device = self.pr.device
+        self.setup = _buffer(vsr.vsr_setup_bytes(self.n), self.device)
+        self.refresh(stream)
+
+    def refresh(self, stream=None) -> None:
+        vsr.vsr_setup_particles(self.pr, self.setup, stream)
+
+
+@dataclass
+class ParticleFrame:
+    coverage: torch.Tensor
+    depth_pass: torch.Tensor
+    uv: torch.Tensor          # float32 [2, H, W] texture-coordinate pass
+    dominant: torch.Tensor
+    lost: torch.Tensor
+    map: torch.Tensor
+    bins: torch.Tensor
+    view_eff: object
+
+
+def render_particles(scene: ParticleScene, view, fmt: int = vsr.VSR_MAP_F32, bin_depth: int = DEFAULT_BIN_DEPTH,
+                     bin_flags: int = 0, stream=None, frame: Optional[ParticleFrame] = None,
+                     stats: Optional[torch.Tensor] = None, no_skip: bool = False) -> ParticleFrame:
+    """Aliasing-free particles: build_map (VSR_MAP_AA) -> bin -> vsr_aa_particles."""
+    dev = scene.device
+    H, W = view.height, view.width
+    if frame is None:
+        frame = ParticleFrame(torch.empty((H, W), dtype=torch.float32, device=dev),
+                              torch.empty((H, W), dtype=torch.float32, device=dev),
+                              torch.empty((2, H, W), dtype=torch.float32, device=dev),
+                              torch.empty((H, W), dtype=torch.int32, device=dev),
+                              torch.empty(1, dtype=torch.int32, device=dev),
+                              _buffer(vsr.vsr_aa_map_bytes(W, H, fmt), dev),
+                              _buffer(vsr.vsr_bin_bytes(W, H, bin_depth), dev), None)
+    frame.view_eff = build_map(view, fmt, vsr.VSR_MAP_AA, frame.map, stream)
+    vsr.vsr_bin(view, fmt, frame.map, scene.setup, scene.n, bin_depth, bin_flags, frame.bins, stream)
+    if stats is None:
+        vsr.vsr_aa_particles(view, fmt, frame.map, scene.setup, scene.n, frame.bins, bin_depth, frame.coverage,
+                             frame.depth_pass, frame.uv, frame.dominant, frame.lost, stream)
+    else:
+        vsr.vsr_aa_particles_stats(view, fmt, frame.map, scene.setup, scene.n, frame.bins, bin_depth,
+                                   frame.coverage, frame.depth_pass, frame.uv, frame.dominant, frame.lost, stats,
+                                   no_skip, stream)
+    return frame
+
+
 class Batch:
     """Workspace + outputs for vsr_submit over a fixed list of (scene, view)."""
 

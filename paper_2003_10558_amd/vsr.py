@@ -19,6 +19,7 @@ VSR_OK, VSR_E_ARG, VSR_E_SPACE, VSR_E_RANGE, VSR_E_HIP = 0, -1, -2, -3, -4
 VSR_MAP_F32, VSR_MAP_OCT16 = 0, 1
 VSR_STRICT = 1
 VSR_MAP_AA = 2
+VSR_MAP_AA_LINES = 4
 VSR_LENS_UNIVERSAL, VSR_LENS_EQUIRECT, VSR_LENS_CUBE, VSR_LENS_SCREENS, VSR_LENS_VR, VSR_LENS_PANORAMA = range(6)
 VSR_BIN_ALL = 1
 VSR_BIN_BLOCKS, VSR_BIN_SUPERTILES = 2, 4
@@ -82,6 +83,14 @@ _lib.vsr_aa_map_bytes.restype = _i64
 _lib.vsr_aa_raster.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp, _vp]
 _lib.vsr_aa_raster_stats.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp,
                                      _vp, _i32, _vp]
+_lib.vsr_setup_particles.argtypes = [_vp, _i64, _vp, _i64, _vp]
+_lib.vsr_aa_particles.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
+                                  _vp]
+_lib.vsr_aa_particles_stats.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp,
+                                        _vp, _vp, _vp, _i32, _vp]
+_lib.vsr_aa_wireframe.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp]
+_lib.vsr_aa_wireframe_stats.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp,
+                                        _vp, _vp]
 _lib.vsr_submit_bytes.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32]
 _lib.vsr_submit_bytes.restype = _i64
 _lib.vsr_submit.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32, _vp, _i64, _vp]
@@ -100,7 +109,8 @@ for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_
 
 EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map", "vsr_build_map_lens", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin",
            "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_resolve", "vsr_aa_map_bytes",
-           "vsr_aa_raster", "vsr_aa_raster_stats", "vsr_submit_bytes",
+           "vsr_aa_raster", "vsr_aa_raster_stats", "vsr_setup_particles", "vsr_aa_particles",
+           "vsr_aa_particles_stats", "vsr_aa_wireframe", "vsr_aa_wireframe_stats", "vsr_submit_bytes",
            "vsr_submit_table_bytes", "vsr_submit_table_offset", "vsr_submit_table", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
 
 
@@ -261,6 +271,43 @@ def vsr_aa_raster_stats(view, fmt: int, map_buf, setup_buf, ntri: int, bins, bin
     _check(_lib.vsr_aa_raster_stats(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), ntri, _ptr(bins),
                                     bin_depth, _ptr(coverage), _ptr(depth_pass), _ptr(dominant), _ptr(lost),
                                     _ptr(stats), int(bool(no_skip)), _stream(stream)))
+
+
+def vsr_setup_particles(pr, setup_buf, stream=None) -> None:
+    assert pr.dim() == 2 and pr.shape[0] == 4 and pr.is_contiguous()
+    _check(_lib.vsr_setup_particles(_ptr(pr), int(pr.shape[1]), _ptr(setup_buf), _nbytes(setup_buf),
+                                    _stream(stream)))
+
+
+def vsr_aa_particles(view, fmt: int, map_buf, setup_buf, n: int, bins, bin_depth: int, coverage, depth_pass, uv,
+                     dominant, lost=None, stream=None) -> None:
+    v = make_view(view)
+    _check(_lib.vsr_aa_particles(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), n, _ptr(bins), bin_depth,
+                                 _ptr(coverage), _ptr(depth_pass), _ptr(uv), _ptr(dominant), _ptr(lost),
+                                 _stream(stream)))
+
+
+def vsr_aa_particles_stats(view, fmt: int, map_buf, setup_buf, n: int, bins, bin_depth: int, coverage, depth_pass,
+                           uv, dominant, lost, stats, no_skip: bool = False, stream=None) -> None:
+    v = make_view(view)
+    _check(_lib.vsr_aa_particles_stats(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), n, _ptr(bins),
+                                       bin_depth, _ptr(coverage), _ptr(depth_pass), _ptr(uv), _ptr(dominant),
+                                       _ptr(lost), _ptr(stats), int(bool(no_skip)), _stream(stream)))
+
+
+def vsr_aa_wireframe(view, fmt: int, map_buf, setup_buf, xyz, ntri: int, bins, bin_depth: int, coverage, dominant,
+                     stream=None) -> None:
+    v = make_view(view)
+    _check(_lib.vsr_aa_wireframe(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), _ptr(xyz), ntri, _ptr(bins),
+                                 bin_depth, _ptr(coverage), _ptr(dominant), _stream(stream)))
+
+
+def vsr_aa_wireframe_stats(view, fmt: int, map_buf, setup_buf, xyz, ntri: int, bins, bin_depth: int, coverage,
+                           dominant, stats, stream=None) -> None:
+    v = make_view(view)
+    _check(_lib.vsr_aa_wireframe_stats(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), _ptr(xyz), ntri,
+                                       _ptr(bins), bin_depth, _ptr(coverage), _ptr(dominant), _ptr(stats),
+                                       _stream(stream)))
 
 
 def vsr_submit_bytes(jobs, fmt: int, mode: int = 0, bin_depth: int = 1024) -> int:

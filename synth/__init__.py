@@ -259,6 +259,26 @@ def serve_scenes() -> List[np.ndarray]:
 # Pixel samples for parity at full size
 # ----------------------------------------------------------------------------
 
+def particles(n: int, seed: int, d_min: float = 1.0, d_max: float = 50.0,
+              ang_mean: float = 0.02, ang_sd: float = 0.005) -> np.ndarray:
+    """float32[4, n] spheres (x, y, z, radius): direction uniform on the
+    sphere, distance U(d_min, d_max), angular diameter ~N(ang_mean, ang_sd^2)
+    clipped at 1e-3 rad (the small-triangle recipe's angular size)."""
+    rng = np.random.default_rng(seed)
+    u = _unit_vectors(rng, n)
+    d = rng.uniform(d_min, d_max, size=n)
+    e = np.maximum(rng.normal(ang_mean, ang_sd, size=n), 1e-3)
+    out = np.empty((4, n))
+    out[0:3] = (u * d[:, None]).T
+    out[3] = d * np.sin(e / 2)
+    return out.astype(np.float32)
+
+
+def particles_1m() -> np.ndarray:
+    """10^6 particles, seed 9 (the 1080p particle workload)."""
+    return particles(1_000_000, 9)
+
+
 def vertex_attributes(n_tri: int, seed: int) -> np.ndarray:
     """Per-vertex data ``float32[3, 5, T]`` (vertex, attribute, triangle):
     attributes 0..2 a unit normal per vertex (a random direction per

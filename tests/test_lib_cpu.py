@@ -206,3 +206,31 @@ def test_lens_argument_errors(vsr):
     from paper_2003_10558_amd import pipeline
     with pytest.raises(ValueError):
         pipeline.Batch([(None, synth.View(64, 32, 0, 0, 1, 90, lens=vsr.VSR_LENS_EQUIRECT))])
+
+
+def test_primitive_argument_errors(vsr):
+    v = synth.View(64, 32, 0.3, 0.5, 0.9, 120.0)
+    B = _FakeBuf
+    with pytest.raises(vsr.VsrError) as e:
+        vsr._check(vsr._lib.vsr_setup_particles(None, 10, 256, 10 ** 9, None))
+    assert e.value.code == vsr.VSR_E_ARG
+    with pytest.raises(vsr.VsrError) as e:
+        vsr._check(vsr._lib.vsr_setup_particles(512, 1000, 256, 16, None))
+    assert e.value.code == vsr.VSR_E_SPACE
+    ok = dict(map_buf=B(256, 1), setup=B(512, 1), n=10, bins=B(768, 1), depth=64, cov=B(1024, 1), dp=B(2048, 1),
+              uv=B(4096, 1), dom=B(8192, 1), lost=None)
+    for c in [dict(map_buf=None), dict(cov=None), dict(uv=B(4098, 1)), dict(depth=0), dict(n=-1)]:
+        a = dict(ok)
+        a.update(c)
+        with pytest.raises(vsr.VsrError) as e:
+            vsr.vsr_aa_particles(v, 0, a["map_buf"], a["setup"], a["n"], a["bins"], a["depth"], a["cov"], a["dp"],
+                                 a["uv"], a["dom"], a["lost"], stream=0)
+        assert e.value.code == vsr.VSR_E_ARG, c
+    for c in [dict(map_buf=None), dict(xyz=None), dict(cov=B(1026, 1)), dict(depth=5000)]:
+        a = dict(map_buf=B(256, 1), setup=B(512, 1), xyz=B(1024, 1), bins=B(768, 1), depth=64, cov=B(2048, 1),
+                 dom=B(4096, 1))
+        a.update(c)
+        with pytest.raises(vsr.VsrError) as e:
+            vsr.vsr_aa_wireframe(v, 0, a["map_buf"], a["setup"], a["xyz"], 10, a["bins"], a["depth"], a["cov"],
+                                 a["dom"], stream=0)
+        assert e.value.code == vsr.VSR_E_ARG, c
