@@ -35,6 +35,8 @@ sys.path.insert(0, ROOT)
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: non-packed FP32 VALU
 PEAK_HBM = 8.0e12
 OPS_PER_AA_FRAGMENT = 36                     # 3 edge dots (9) + chord (6) + miter (1) + 4 steps (12) + 3 min + cmp + g.N (3) + div
+OPS_PER_WIRE_FRAGMENT = 46                   # 3 sides x (dot 3, |.| step 2, chord 6, cap step 2, min 1) + max/compare
+OPS_PER_PARTICLE_FRAGMENT = 28               # chord 6, cap step 2, g.N 3, rcp + mul 2, Y = X x N 6, two dots 6, 2 fma, compare
 OPS_PER_FRAGMENT = 20                        # 3 edge dots (9) + min3 + cmp + g.N (3) + rcp + mul + cmp64 + 2 sel
 BIN_BYTES_PER_TRI = 64                       # cap (16 B) + three edge normals (48 B), read once
 BIN_BYTES_PER_TILE = 36                      # tile cap (32 B) read, list length (4 B) written
@@ -335,6 +337,89 @@ def main():
             f"-> {lens_stats[name]['fps']:.0f} frames/s")
         del lf
 
+    # ---------------- wire frame (section 1.2) of the scene's triangle sides
+    wv = views[1]
+    wf = pipeline.render_wireframe(scene, wv, fmt=fmt, bin_depth=depth)
+    torch.cuda.synchronize()
+    w_map, w_bin, w_rast = [], [], []
+    for rep in range(3 if not args.profile else 2):
+        e0, ea, e1, e2 = ev(), ev(), ev(), ev()
+        e0.record(stream)
+        pipeline.build_map(wv, fmt, vsr.VSR_MAP_AA_LINES, wf.map)
+        ea.record(stream)
+        vsr.vsr_bin(wv, fmt, wf.map, scene.setup, scene.ntri, depth, 0, wf.bins)
+        e1.record(stream)
+        vsr.vsr_aa_wireframe(wv, fmt, wf.map, scene.setup, scene.xyz, scene.ntri, wf.bins, depth, wf.coverage,
+                             wf.dominant)
+        e2.record(stream)
+        e2.synchronize()
+        if rep:
+            w_map.append(e0.elapsed_time(ea))
+            w_bin.append(ea.elapsed_time(e1))
+            w_rast.append(e1.elapsed_time(e2))
+    wstats = torch.zeros(4, dtype=torch.int64, device=dev)
+    pipeline.render_wireframe(scene, wv, fmt=fmt, bin_depth=depth, frame=wf, stats=wstats)
+    torch.cuda.synchronize()
+    wire_evals, wire_frags = int(wstats[0].item()), int(wstats[1].item())
+    t_w = float(np.mean(w_rast)) * 1e-3
+    roofline_wire = {"bound": "alu", "achieved": OPS_PER_WIRE_FRAGMENT * wire_frags / t_w / 1e12,
+                     "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+                     "frac": OPS_PER_WIRE_FRAGMENT * wire_frags / t_w / PEAK_VALU_LANE_OPS,
+                     "traffic": traffic_from_profiles("k_wire<false>"), "kernel": "k_wire", "kernel_ms": t_w * 1e3,
+                     "fragments_per_launch": wire_frags, "ops_per_fragment": OPS_PER_WIRE_FRAGMENT,
+                     "mask_evaluations": wire_evals}
+    log(f"wire frame 1080p x 1M: map {np.mean(w_map):.3f} ms, bin {np.mean(w_bin):.3f} ms, raster "
+        f"{np.mean(w_rast):.3f} ms; {wire_frags} (pixel, triangle) pairs drawn, {wire_evals} evaluated; "
+        f"{roofline_wire['achieved']:.2f} T lane-ops/s ({roofline_wire['frac']:.3f} of VALU)")
+    del wf
+
+    # ---------------- particles (section 1.3): 10^6 spheres of the small-triangle angular size
+    t0 = time.time()
+    pscene = pipeline.ParticleScene(synth.particles_1m(), device=dev)
+    torch.cuda.synchronize()
+    log(f"particles: 10^6 generated and set up in {time.time() - t0:.1f}s")
+    pf = pipeline.render_particles(pscene, wv, fmt=fmt, bin_depth=depth)
+    torch.cuda.synchronize()
+    p_setup, p_map, p_bin, p_rast = [], [], [], []
+    for rep in range(3 if not args.profile else 2):
+        es, e0, ea, e1, e2 = ev(), ev(), ev(), ev(), ev()
+        es.record(stream)
+        pscene.refresh()
+        e0.record(stream)
+        pipeline.build_map(wv, fmt, vsr.VSR_MAP_AA, pf.map)
+        ea.record(stream)
+        vsr.vsr_bin(wv, fmt, pf.map, pscene.setup, pscene.n, depth, 0, pf.bins)
+        e1.record(stream)
+        vsr.vsr_aa_particles(wv, fmt, pf.map, pscene.setup, pscene.n, pf.bins, depth, pf.coverage, pf.depth_pass,
+                             pf.uv, pf.dominant, pf.lost)
+        e2.record(stream)
+        e2.synchronize()
+        if rep:
+            p_setup.append(es.elapsed_time(e0))
+            p_map.append(e0.elapsed_time(ea))
+            p_bin.append(ea.elapsed_time(e1))
+            p_rast.append(e1.elapsed_time(e2))
+    pstats = torch.zeros(4, dtype=torch.int64, device=dev)
+    pipeline.render_particles(pscene, wv, fmt=fmt, bin_depth=depth, frame=pf, stats=pstats, no_skip=True)
+    torch.cuda.synchronize()
+    part_frags = int(pstats[1].item())
+    pipeline.render_particles(pscene, wv, fmt=fmt, bin_depth=depth, frame=pf, stats=pstats)
+    torch.cuda.synchronize()
+    part_found, part_evals = int(pstats[1].item()), int(pstats[0].item())
+    part_lost = int(pf.lost.item())
+    t_p = float(np.mean(p_rast)) * 1e-3
+    roofline_particles = {"bound": "alu", "achieved": OPS_PER_PARTICLE_FRAGMENT * part_frags / t_p / 1e12,
+                          "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+                          "frac": OPS_PER_PARTICLE_FRAGMENT * part_frags / t_p / PEAK_VALU_LANE_OPS,
+                          "traffic": traffic_from_profiles("k_aa_raster<false, 1>"), "kernel": "k_aa_raster (particles)",
+                          "kernel_ms": t_p * 1e3, "fragments_per_launch": part_frags,
+                          "ops_per_fragment": OPS_PER_PARTICLE_FRAGMENT}
+    log(f"particles 1080p x 10^6: setup {np.mean(p_setup):.3f} ms, map {np.mean(p_map):.3f} ms, bin "
+        f"{np.mean(p_bin):.3f} ms, raster {np.mean(p_rast):.3f} ms; fragments {part_frags} (all depths), "
+        f"{part_found} found with skipping, {part_evals} evaluated, lost pixels {part_lost}; "
+        f"{roofline_particles['achieved']:.2f} T lane-ops/s ({roofline_particles['frac']:.3f} of VALU)")
+    del pf, pscene
+
     # ---------------- single-view fused path (vsr_build_map + vsr_render)
     ffr = pipeline.render_fused(scene, views[0], fmt=fmt)
     torch.cuda.synchronize()
@@ -571,6 +656,16 @@ def main():
                "mask_evaluations": float(np.mean(aa_tests)), "triangles_skipped": float(np.mean(aa_skipped))},
         "roofline_aa": roofline_aa,
         "lenses": lens_stats,
+        "wireframe": {"fps": 1e3 / (np.mean(w_map) + np.mean(w_bin) + np.mean(w_rast)),
+                      "map_ms": float(np.mean(w_map)), "bin_ms": float(np.mean(w_bin)),
+                      "raster_ms": float(np.mean(w_rast))},
+        "roofline_wire": roofline_wire,
+        "particles": {"fps": 1e3 / (np.mean(p_map) + np.mean(p_bin) + np.mean(p_rast)),
+                      "setup_ms": float(np.mean(p_setup)), "map_ms": float(np.mean(p_map)),
+                      "bin_ms": float(np.mean(p_bin)), "raster_ms": float(np.mean(p_rast)),
+                      "fragments_found_with_skipping": part_found, "mask_evaluations": part_evals,
+                      "lost_pixels": part_lost},
+        "roofline_particles": roofline_particles,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
