@@ -121,7 +121,7 @@ int64_t vsr_bin_bytes(int32_t width, int32_t height, int32_t bin_depth);
 int vsr_build_map(const vsr_view* v, int32_t fmt, uint32_t flags, void* map, int64_t map_bytes,
                   vsr_view* v_effective, void* stream);
 
-/* Other map generators (sections 2.2.2, 2.2.4, 2.2.7-2.2.9) and lens
+/* Other map generators (sections 2.2.2-2.2.4, 2.2.7-2.2.9) and lens
  * distortion (section 2.3).  A vsr_lens picks the generator; the view's
  * width, height and rotation always apply, its k, l, s, omega_deg and aov
  * only to VSR_LENS_UNIVERSAL.  Parameters (p[]):
@@ -143,6 +143,12 @@ int vsr_build_map(const vsr_view* v, int32_t fmt, uint32_t flags, void* map, int
  *                       1 + k1 + k2 = 0 is refused); left eye on the left.
  *   VSR_LENS_PANORAMA   p[0] = horizontal angle of view (0, 360] degrees of
  *                       a unit cylinder; its height follows from W/H.
+ *   VSR_LENS_DOME       p[0] = compression angle [-89, 90] degrees, p[1] =
+ *                       tilt in degrees, p[2] = view position offset in
+ *                       dome radii (-1, 1): full-dome fisheye (section
+ *                       2.2.3), zenith +y at the picture centre, 90 degrees
+ *                       + compression at the inscribed circle; pixels
+ *                       outside that circle have no direction.
  * The map has the same layout as vsr_build_map's (flags: VSR_STRICT for the
  * Universal parameters, VSR_MAP_AA), and every later step takes it
  * unchanged.  VSR_E_ARG for an unknown type or parameters outside the
@@ -153,6 +159,7 @@ int vsr_build_map(const vsr_view* v, int32_t fmt, uint32_t flags, void* map, int
 #define VSR_LENS_SCREENS 3
 #define VSR_LENS_VR 4
 #define VSR_LENS_PANORAMA 5
+#define VSR_LENS_DOME 6
 typedef struct {
     int32_t type, n;
     float p[8];

@@ -17,8 +17,8 @@
  *            step: 1 iff g > 0).
  *   depth    section 1.1.4 (hard normal N=(A-B)x(C-B); r = A.N / G.N).
  *   resolve  section 1.4 (depth-pass test: the nearest r wins).
- *   lens     sections 2.2.2, 2.2.4, 2.2.7-2.2.9 (curved panorama,
- *            equirectangular, cube, screen array and VR maps) and 2.3
+ *   lens     sections 2.2.2-2.2.4, 2.2.7-2.2.9 (curved panorama, full
+ *            dome, equirectangular, cube, screen array and VR maps) and 2.3
  *            (Brown-Conrady distortion of the Universal map's view
  *            coordinates).
  *   wire     section 1.2 (line step of a segment's great circle limited by
@@ -59,15 +59,16 @@
 
 /* Map generators: the Universal Perspective of section 2.1 (with the
  * Brown-Conrady distortion of section 2.3 when any coefficient is non-zero)
- * and the maps of section 2.2: equirectangular (2.2.4), cube (2.2.7),
- * multiple-screen array (2.2.8), virtual reality (2.2.9) and curved
- * panorama (2.2.2). */
+ * and the maps of section 2.2: curved panorama (2.2.2), full dome (2.2.3),
+ * equirectangular (2.2.4), cube (2.2.7), multiple-screen array (2.2.8) and
+ * virtual reality (2.2.9). */
 #define ORC_LENS_UNIVERSAL 0
 #define ORC_LENS_EQUIRECT 1
 #define ORC_LENS_CUBE 2
 #define ORC_LENS_SCREENS 3
 #define ORC_LENS_VR 4
 #define ORC_LENS_PANORAMA 5
+#define ORC_LENS_DOME 6
 
 typedef struct {
     int32_t width, height, aov;
@@ -215,7 +216,12 @@ static void lens_distort(const double *c, double *x, double *y)
  *   VR         lp[0] = vertical angle of view (degrees), lp[1] = IPD d in
  *              screen widths, lp[2], lp[3] = radial coefficients k1, k2;
  *   PANORAMA   lp[0] = horizontal angle of view (degrees) of a cylinder of
- *              unit radius whose height follows from the aspect ratio. */
+ *              unit radius whose height follows from the aspect ratio;
+ *   DOME       lp[0] = compression angle (degrees), lp[1] = tilt (degrees),
+ *              lp[2] = view position offset (in dome radii): a full-dome
+ *              fisheye whose angle from the zenith (+y) grows linearly to
+ *              90 degrees + compression at the rim; pixels outside the
+ *              inscribed circle have no direction. */
 int orc_lens_direction(const orc_view *v, double fs, double ft, double out[3], int32_t *seg)
 {
     const double a = (double)v->width / (double)v->height;
@@ -285,6 +291,25 @@ int orc_lens_direction(const orc_view *v, double fs, double ft, double out[3], i
         out[2] = 1.0 / tan(0.5 * p[0] * ORC_PI / 180.0);
         normalize3(out);
         *seg = eye > 0.0 ? 1 : 0;
+        return 1;
+    }
+    case ORC_LENS_DOME: { /* section 2.2.3, full dome */
+        double x = 2.0 * fs - 1.0, y = 1.0 - 2.0 * ft;
+        double R = sqrt(x * x + y * y);
+        if (R > 1.0) {
+            out[0] = out[1] = out[2] = 0.0;
+            return 0;
+        }
+        double span = (p[0] + 90.0) * ORC_PI / 180.0;
+        double th = R * span;
+        double sr = R > 0.0 ? sin(th) / R : span; /* limit of sin(theta)/R at R = 0 */
+        double d[3] = {x * sr, cos(th), y * sr + p[2]};
+        normalize3(d);
+        /* tilt about x, rows of the printed matrix applied to the row vector */
+        double t = p[1] * ORC_PI / 180.0, c = cos(t), s = sin(t);
+        out[0] = d[0];
+        out[1] = d[1] * c + d[2] * s;
+        out[2] = -d[1] * s + d[2] * c;
         return 1;
     }
     case ORC_LENS_PANORAMA: { /* section 2.2.2, curved panorama */

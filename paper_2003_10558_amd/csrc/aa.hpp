@@ -1,6 +1,9 @@
 // Aliasing-free coverage: pixel step with the global delta (section 1.1.1),
 // miter mask (section 1.1.2) and front-to-back combination of clipped
-// fragment masks (section 1.4).
+// fragment masks (section 1.4); the same kernel draws the particles of
+// section 1.3 (a particle's mask is the pixel step of its silhouette cap,
+// which is the miter value with the particle direction as centre; its
+// fragments also carry texture coordinates, combined like the depth).
 //
 // One 64-lane wavefront per 8x8 tile of a map built with VSR_MAP_AA, whose
 // tile caps are widened by the pixel step's fringe so that the ordinary

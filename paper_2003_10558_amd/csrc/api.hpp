@@ -172,6 +172,16 @@ int make_lens_params(const vsr_lens* lens, MapParams* P) {
         P->lp[0] = float(om * pi / 180.0 / (2.0 * W));
         break;
     }
+    case VSR_LENS_DOME: {
+        double comp = lens->p[0], tilt = lens->p[1] * pi / 180.0, off = lens->p[2];
+        if (!(comp >= -89.0 && comp <= 90.0)) return fail(VSR_E_ARG, "dome compression %g outside [-89, 90]", comp);
+        if (!(off > -1.0 && off < 1.0)) return fail(VSR_E_ARG, "dome offset %g outside (-1, 1)", off);
+        P->lp[0] = float((comp + 90.0) * pi / 180.0);
+        P->lp[1] = float(sin(tilt));
+        P->lp[2] = float(cos(tilt));
+        P->lp[3] = float(off);
+        break;
+    }
     default:
         return fail(VSR_E_ARG, "unknown lens type %d", lens->type);
     }

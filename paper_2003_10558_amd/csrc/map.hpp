@@ -164,6 +164,20 @@ __device__ inline bool pixel_direction(const MapParams& P, int i, int j, float3&
         out = normalized(x * f, y * f, P.lp[0]);
         return true;
     }
+    case VSR_LENS_DOME: {  // section 2.2.3: fisheye about the zenith +y, tilted about x
+        // outside the inscribed circle: exact integer test of R^2 > 1
+        const int64_t nx = 2 * i + 1 - P.W, ny = P.H - 2 * j - 1;
+        if (nx * nx * int64_t(P.H) * P.H + ny * ny * int64_t(P.W) * P.W > int64_t(P.W) * P.W * int64_t(P.H) * P.H)
+            return false;
+        float x = float(nx) / float(P.W), y = float(ny) / float(P.H);
+        float R = sqrtf(fmaf(x, x, y * y));
+        float sn, cs;
+        sincosf(R * P.lp[0], &sn, &cs);
+        float sr = R > 0.0f ? sn / R : P.lp[0];
+        float3 d = normalized(x * sr, cs, fmaf(y, sr, P.lp[3]));
+        out = f3(d.x, fmaf(d.y, P.lp[2], d.z * P.lp[1]), fmaf(-d.y, P.lp[1], d.z * P.lp[2]));
+        return true;
+    }
     case VSR_LENS_PANORAMA: {  // section 2.2.2: unit cylinder, height from the aspect ratio
         float x = float(2 * i + 1 - P.W) * P.lp[0], y = float(2 * j + 1 - P.H) * P.lp[0];
         float sn, cs;

@@ -20,7 +20,8 @@ VSR_MAP_F32, VSR_MAP_OCT16 = 0, 1
 VSR_STRICT = 1
 VSR_MAP_AA = 2
 VSR_MAP_AA_LINES = 4
-VSR_LENS_UNIVERSAL, VSR_LENS_EQUIRECT, VSR_LENS_CUBE, VSR_LENS_SCREENS, VSR_LENS_VR, VSR_LENS_PANORAMA = range(6)
+(VSR_LENS_UNIVERSAL, VSR_LENS_EQUIRECT, VSR_LENS_CUBE, VSR_LENS_SCREENS, VSR_LENS_VR, VSR_LENS_PANORAMA,
+ VSR_LENS_DOME) = range(7)
 VSR_BIN_ALL = 1
 VSR_BIN_BLOCKS, VSR_BIN_SUPERTILES = 2, 4
 VSR_NO_HIT = 0xFFFFFFFF

@@ -26,7 +26,7 @@ import numpy as np
 AOV_HORIZONTAL, AOV_DIAGONAL, AOV_VERTICAL, AOV_HORIZONTAL_4X3 = 0, 1, 2, 3
 
 
-LENS_UNIVERSAL, LENS_EQUIRECT, LENS_CUBE, LENS_SCREENS, LENS_VR, LENS_PANORAMA = 0, 1, 2, 3, 4, 5
+LENS_UNIVERSAL, LENS_EQUIRECT, LENS_CUBE, LENS_SCREENS, LENS_VR, LENS_PANORAMA, LENS_DOME = 0, 1, 2, 3, 4, 5, 6
 
 
 @dataclasses.dataclass

@@ -46,6 +46,8 @@ LENS_VIEWS = [
     ("vr", _v(160, 90, synth.LENS_VR, p=(100.0, 0.42, 0.22, 0.05), rot=synth.yaw_pitch_rotation(2.0, 0.1))),
     ("vr_odd", _v(97, 61, synth.LENS_VR, p=(90.0, 0.5, 0.0, 0.0))),
     ("panorama", _v(240, 60, synth.LENS_PANORAMA, p=(250.0,), rot=synth.yaw_pitch_rotation(0.2, -0.6))),
+    ("dome", _v(96, 96, synth.LENS_DOME, p=(20.0, 15.0, 0.2), rot=synth.yaw_pitch_rotation(0.3, 0.4))),
+    ("dome_ragged", _v(77, 51, synth.LENS_DOME, p=(-10.0, 0.0, 0.0))),
     ("distort_diag", _v(120, 80, synth.LENS_UNIVERSAL, p=(0.12, -0.03, 0.02, -0.01, 0.01, -0.02), k=0.4,
                         l=0.6, s=0.9, om=160.0, aov=1)),
     ("distort_kneg", _v(96, 96, synth.LENS_UNIVERSAL, p=(-0.1, 0.02, 0.0, 0.0, 0.0, 0.0), k=-0.6, l=1.0,
@@ -113,7 +115,7 @@ def test_lens_binning_is_exact(gpu, name):
         assert torch.equal(fr.tri_id, ref_ids) and torch.equal(fr.depth, ref_dep), (name, shape)
 
 
-@pytest.mark.parametrize("name", ["cube", "screens3", "vr", "equirect"])
+@pytest.mark.parametrize("name", ["cube", "screens3", "vr", "equirect", "dome"])
 def test_lens_aa_matches_oracle(gpu, name):
     """Aliasing-free frames on segmented maps: the delta plane takes no
     difference across cube faces, screens or eyes, on both sides."""
@@ -135,7 +137,8 @@ def test_lens_argument_errors_reach_no_kernel(gpu):
     buf = torch.empty(vsr.vsr_map_bytes(64, 32, 0), dtype=torch.uint8, device="cuda")
     for view in [_v(64, 32, 9), _v(64, 32, synth.LENS_SCREENS, 0, (60.0,)),
                  _v(64, 32, synth.LENS_SCREENS, 3, (180.0,)), _v(64, 32, synth.LENS_VR, p=(90.0, 0.5, -0.5, -0.5)),
-                 _v(64, 32, synth.LENS_PANORAMA, p=(400.0,))]:
+                 _v(64, 32, synth.LENS_PANORAMA, p=(400.0,)), _v(64, 32, synth.LENS_DOME, p=(95.0, 0.0, 0.0)),
+                 _v(64, 32, synth.LENS_DOME, p=(0.0, 0.0, 1.0))]:
         with pytest.raises(vsr.VsrError):
             pipeline.build_map(view, 0, 0, buf)
 

@@ -246,3 +246,51 @@ def test_delta_does_not_difference_across_cube_seams(oracle_lib):
             edge = oracle_lib.delta(v, f * F, j)
             inner = oracle_lib.delta(v, f * F + 1, j)
             assert edge == pytest.approx(inner, rel=0.08), (f, j, edge, inner)
+
+
+# ---------------------------------------------------------------- full dome
+
+def test_dome_is_an_equidistant_fisheye_about_the_zenith(oracle_lib):
+    """Full dome, no offset or tilt: the angle from the zenith (+y) grows
+    linearly with the distance from the picture centre, reaching 90 degrees
+    + compression at the inscribed circle, azimuth preserved; outside the
+    circle no direction."""
+    W = H = 64
+    for comp in (0.0, 30.0, -20.0):
+        v = synth.View(W, H, 0, 0, 0, 0, lens=synth.LENS_DOME, lens_p=(comp, 0.0, 0.0))
+        d, ok = oracle_lib.perspective_map(v)
+        for j in range(H):
+            for i in range(W):
+                x, y = 2 * (i + 0.5) / W - 1, 1 - 2 * (j + 0.5) / H
+                R = math.hypot(x, y)
+                assert ok[j, i] == (R <= 1.0)
+                if R > 1.0:
+                    continue
+                g = d[j, i]
+                assert math.acos(max(-1, min(1, g[1]))) == pytest.approx(R * math.radians(90 + comp), abs=1e-12)
+                if math.sin(R * math.radians(90 + comp)) > 1e-6:
+                    assert math.atan2(g[2], g[0]) == pytest.approx(math.atan2(y, x), abs=1e-9)
+
+
+def test_dome_offset_and_tilt(oracle_lib):
+    """The offset moves the viewpoint: the direction is the unit dome point
+    seen from -o along z; the tilt turns the whole map about x (a proper
+    rotation fixing x, recovered by SVD)."""
+    rng = np.random.default_rng(2)
+    base = synth.View(48, 48, 0, 0, 0, 0, lens=synth.LENS_DOME, lens_p=(10.0, 0.0, 0.0))
+    off = synth.View(48, 48, 0, 0, 0, 0, lens=synth.LENS_DOME, lens_p=(10.0, 0.0, 0.35))
+    tilt = synth.View(48, 48, 0, 0, 0, 0, lens=synth.LENS_DOME, lens_p=(10.0, 25.0, 0.0))
+    for _ in range(50):
+        fs, ft = rng.uniform(0.2, 0.8, size=2)
+        a, oka, _ = oracle_lib.lens_direction(base, fs, ft)
+        b, okb, _ = oracle_lib.lens_direction(off, fs, ft)
+        assert oka and okb
+        w = a + np.array([0.0, 0.0, 0.35])
+        assert np.allclose(b, w / np.linalg.norm(w), atol=1e-14)
+    da, oka = oracle_lib.perspective_map(base)
+    dt, okt = oracle_lib.perspective_map(tilt)
+    assert np.array_equal(oka, okt)
+    R, res = _kabsch(da[oka], dt[okt])
+    assert res < 1e-13 and np.linalg.det(R) == pytest.approx(1.0, abs=1e-12)
+    assert np.allclose(R @ [1.0, 0.0, 0.0], [1.0, 0.0, 0.0], atol=1e-13)
+    assert math.degrees(math.acos(R[1, 1])) == pytest.approx(25.0, abs=1e-9)
