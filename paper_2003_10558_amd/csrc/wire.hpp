@@ -15,10 +15,7 @@
 // edge normal e, lanes 8t + 3 + e the cap centre of side e and its constant
 // a, which they compute from the two end points (loaded by the triangle's
 // id from the vertex array), and pass its constant b to lane 8t + e; lane
-// 8t + 6 holds the record word with the id; lane 8t + 7 finds the sides
-// whose great circle passes farther from the tile than the widened tile
-// cap's radius (they cannot draw into the tile): the wave skips those sides,
-// and the triangle when no side is left.
+// 8t + 6 holds the record word with the id.
 #pragma once
 #include "aa.hpp"
 
@@ -82,24 +79,9 @@ __device__ inline void wire_tile(const WireArgs& A, int64_t tile, int lane, floa
     uint32_t dom = kNoHit;
     unsigned long long n_test = 0, n_frag = 0;
 
-    float4 tc0, tc1;
-    load_tile_cap(caps, tile, A.rot, tc0, tc1);
-    // sides of a triangle (normals n_e) that may draw into the tile: the
-    // widened tile cap meets the great circle's band only if |n.c| <= sin
-    // of its radius (wide or empty caps: every side)
-    auto sides_near = [&](float3 n0, float3 n1, float3 n2) -> uint32_t {
-        if (tc1.z != 0.0f) return 7u;
-        const float lim = tc1.y + 1e-6f;
-        const float3 c = f3(tc0.x, tc0.y, tc0.z);
-        return (fabsf(dot3(n0, c)) <= lim ? 1u : 0u) | (fabsf(dot3(n1, c)) <= lim ? 2u : 0u) |
-               (fabsf(dot3(n2, c)) <= lim ? 4u : 0u);
-    };
-    // the sides `near` of one triangle: normals (b in .w), caps (L, a), id
-    auto visit = [&](float4 n0, float4 n1, float4 n2, float4 k0, float4 k1, float4 k2, uint32_t id, uint32_t near) {
-        float m = 0.0f;
-        if (near & 1u) m = side_mask(n0, k0, g, delta);
-        if (near & 2u) m = fmaxf(m, side_mask(n1, k1, g, delta));
-        if (near & 4u) m = fmaxf(m, side_mask(n2, k2, g, delta));
+    // the three sides of one triangle: normals (b in .w), caps (L, a), id
+    auto visit = [&](float4 n0, float4 n1, float4 n2, float4 k0, float4 k1, float4 k2, uint32_t id) {
+        float m = fmaxf(fmaxf(side_mask(n0, k0, g, delta), side_mask(n1, k1, g, delta)), side_mask(n2, k2, g, delta));
         m = has_dir ? m : 0.0f;
         if (m > best || (m == best && m > 0.0f && id < dom)) {
             best = m;
@@ -123,6 +105,8 @@ __device__ inline void wire_tile(const WireArgs& A, int64_t tile, int lane, floa
         cap = make_float4(L.x, L.y, L.z, a);
     };
 
+    float4 tc0, tc1;
+    load_tile_cap(caps, tile, A.rot, tc0, tc1);
     const uint32_t count = counts[tile];
     if (count <= uint32_t(A.depth)) {
         const uint32_t* lst = lists + tile * A.depth;
@@ -140,11 +124,6 @@ __device__ inline void wire_tile(const WireArgs& A, int64_t tile, int lane, floa
                     side(rec, int(part) - 3, v, b);
                 } else if (part == 6u) {
                     v = rec[3];
-                } else {
-                    const float* rw = reinterpret_cast<const float*>(rec);
-                    uint32_t near = sides_near(f3(rw[0], rw[1], rw[2]), f3(rw[4], rw[5], rw[6]),
-                                               f3(rw[8], rw[9], rw[10]));
-                    v.x = __uint_as_float(near);
                 }
             }
             // b of side e travels from lane 8t + 3 + e to lane 8t + e
@@ -156,11 +135,10 @@ __device__ inline void wire_tile(const WireArgs& A, int64_t tile, int lane, floa
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            // triangles with at least one side near the tile
-            const uint32_t todo = pack_group_bits(__ballot(part == 7u && e < count && __float_as_uint(v.x) != 0u) >> 1);
-            for (uint32_t m = todo; m; m &= m - 1) {
-                const float4* w = stg + 8 * uint32_t(__ffs(m) - 1);
-                visit(w[0], w[1], w[2], w[3], w[4], w[5], __float_as_uint(w[6].z), __float_as_uint(w[7].x));
+            const uint32_t nt = min(8u, count - gi * 8u);
+            for (uint32_t t = 0; t < nt; ++t) {
+                const float4* w = stg + 8 * t;
+                visit(w[0], w[1], w[2], w[3], w[4], w[5], __float_as_uint(w[6].z));
             }
         }
     } else {
@@ -173,12 +151,10 @@ __device__ inline void wire_tile(const WireArgs& A, int64_t tile, int lane, floa
                 uint32_t rk = uint32_t(__builtin_amdgcn_readlane(int(rank), qb));
                 const float4* rec = S.rec + 4 * int64_t(rk);
                 float4 n0 = rec[0], n1 = rec[1], n2 = rec[2], k0, k1, k2;
-                const uint32_t near = sides_near(f3(n0.x, n0.y, n0.z), f3(n1.x, n1.y, n1.z), f3(n2.x, n2.y, n2.z));
-                if (!near) continue;
                 side(rec, 0, k0, n0.w);
                 side(rec, 1, k1, n1.w);
                 side(rec, 2, k2, n2.w);
-                visit(n0, n1, n2, k0, k1, k2, __float_as_uint(rec[3].z), near);
+                visit(n0, n1, n2, k0, k1, k2, __float_as_uint(rec[3].z));
             }
         });
     }
