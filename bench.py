@@ -349,8 +349,8 @@ def main():
         ea.record(stream)
         vsr.vsr_bin(wv, fmt, wf.map, scene.setup, scene.ntri, depth, 0, wf.bins)
         e1.record(stream)
-        vsr.vsr_aa_wireframe(wv, fmt, wf.map, scene.setup, scene.xyz, scene.ntri, wf.bins, depth, wf.coverage,
-                             wf.dominant)
+        vsr.vsr_aa_wireframe(wv, fmt, wf.map, scene.setup, scene.wire_caps(), scene.ntri, wf.bins, depth,
+                             wf.coverage, wf.dominant)
         e2.record(stream)
         e2.synchronize()
         if rep:

@@ -315,15 +315,25 @@ int vsr_aa_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const v
  *   map          built with VSR_MAP_AA_LINES (caps widened by 5/4 pixel:
  *                a side draws up to sqrt(5)/2 pixel from its segment);
  *                bins from vsr_bin on that map and the triangles' setup.
- *   xyz, ntri    the vertex array given to vsr_setup_tris.
+ *   wire, ntri   the side caps of the scene from vsr_setup_wire.
  *   coverage     device float[height][width]; dominant uint32[height][width]. */
-int vsr_aa_wireframe(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const float* xyz,
+int vsr_aa_wireframe(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const void* wire,
                      int64_t ntri, const void* bins, int32_t bin_depth, float* coverage, uint32_t* dominant,
                      void* stream);
+/* Bytes of the side-cap buffer of ntri triangles (64 per triangle).  <0 on
+ * bad input. */
+int64_t vsr_wire_bytes(int64_t ntri);
+/* Side caps of a scene for vsr_aa_wireframe, once per scene after
+ * vsr_setup_tris (again whenever the setup is redone): per triangle, in the
+ * setup's nearest-first order, each side's cap centre and the two
+ * constants of its pixel step, and the triangle id.
+ *   setup, xyz, ntri  the setup buffer and the vertex array given to it.
+ *   wire              device buffer of vsr_wire_bytes(ntri) bytes. */
+int vsr_setup_wire(const void* setup, const float* xyz, int64_t ntri, void* wire, int64_t wire_bytes, void* stream);
 /* Instrumented vsr_aa_wireframe: stats[4] of uint64 receive (pixels with a
  * direction x triangles tested, (pixel, triangle) pairs with a mask > 0, 0,
  * tiles). */
-int vsr_aa_wireframe_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const float* xyz,
+int vsr_aa_wireframe_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const void* wire,
                            int64_t ntri, const void* bins, int32_t bin_depth, float* coverage, uint32_t* dominant,
                            uint64_t* stats, void* stream);
 

@@ -409,38 +409,52 @@ int vsr_aa_particles_stats(const vsr_view* v, int32_t fmt, const void* map, cons
                                stats, no_skip, stream, "vsr_aa_particles_stats");
 }
 
-static int wireframe_common(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const float* xyz,
+int64_t vsr_wire_bytes(int64_t ntri) {
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return VSR_E_ARG;
+    return align256(ntri * 64 > 0 ? ntri * 64 : 256);
+}
+
+int vsr_setup_wire(const void* setup, const float* xyz, int64_t ntri, void* wire, int64_t wire_bytes, void* stream) {
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri %lld out of range", (long long)ntri);
+    if (!setup || !aligned(setup) || !wire || !aligned(wire) || (ntri > 0 && !xyz))
+        return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if ((reinterpret_cast<uintptr_t>(xyz) & 3u) != 0) return fail(VSR_E_ARG, "vertex array not 4-byte aligned");
+    if (wire_bytes < vsr_wire_bytes(ntri))
+        return fail(VSR_E_SPACE, "wire buffer %lld < %lld bytes", (long long)wire_bytes, (long long)vsr_wire_bytes(ntri));
+    return hip_status(launch_setup_wire(setup, xyz, ntri, wire, hipStream_t(stream)), "vsr_setup_wire");
+}
+
+static int wireframe_common(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const void* wire,
                             int64_t ntri, const void* bins, int32_t bin_depth, float* coverage, uint32_t* dominant,
                             uint64_t* stats, void* stream, const char* what) {
     int rc = check_view_buffers(v, fmt);
     if (rc != VSR_OK) return rc;
-    if (!map || !setup || !bins || !coverage || !dominant || (ntri > 0 && !xyz) || !aligned(map) ||
-        !aligned(setup) || !aligned(bins))
+    if (!map || !setup || !bins || !coverage || !dominant || !wire || !aligned(map) || !aligned(setup) ||
+        !aligned(bins) || !aligned(wire))
         return fail(VSR_E_ARG, "NULL or misaligned buffer");
-    const uintptr_t mis = reinterpret_cast<uintptr_t>(coverage) | reinterpret_cast<uintptr_t>(dominant) |
-                          reinterpret_cast<uintptr_t>(xyz);
+    const uintptr_t mis = reinterpret_cast<uintptr_t>(coverage) | reinterpret_cast<uintptr_t>(dominant);
     if (mis & 3u) return fail(VSR_E_ARG, "array not 4-byte aligned");
     if ((reinterpret_cast<uintptr_t>(stats) & 7u) != 0) return fail(VSR_E_ARG, "stats not 8-byte aligned");
     if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri out of range");
     if (bin_depth < 1 || bin_depth > kMaxDepth) return fail(VSR_E_ARG, "bin_depth %d outside 1..%d", bin_depth, kMaxDepth);
-    return hip_status(launch_wire(map, v->width, v->height, fmt, rot_of(v->rot), setup, xyz, ntri, bins, bin_depth,
+    return hip_status(launch_wire(map, v->width, v->height, fmt, rot_of(v->rot), setup, wire, ntri, bins, bin_depth,
                                   coverage, dominant, reinterpret_cast<unsigned long long*>(stats),
                                   hipStream_t(stream)),
                       what);
 }
 
-int vsr_aa_wireframe(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const float* xyz,
+int vsr_aa_wireframe(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const void* wire,
                      int64_t ntri, const void* bins, int32_t bin_depth, float* coverage, uint32_t* dominant,
                      void* stream) {
-    return wireframe_common(v, fmt, map, setup, xyz, ntri, bins, bin_depth, coverage, dominant, nullptr, stream,
+    return wireframe_common(v, fmt, map, setup, wire, ntri, bins, bin_depth, coverage, dominant, nullptr, stream,
                             "vsr_aa_wireframe");
 }
 
-int vsr_aa_wireframe_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const float* xyz,
+int vsr_aa_wireframe_stats(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const void* wire,
                            int64_t ntri, const void* bins, int32_t bin_depth, float* coverage, uint32_t* dominant,
                            uint64_t* stats, void* stream) {
     if (!stats) return fail(VSR_E_ARG, "stats is NULL");
-    return wireframe_common(v, fmt, map, setup, xyz, ntri, bins, bin_depth, coverage, dominant, stats, stream,
+    return wireframe_common(v, fmt, map, setup, wire, ntri, bins, bin_depth, coverage, dominant, stats, stream,
                             "vsr_aa_wireframe_stats");
 }
 

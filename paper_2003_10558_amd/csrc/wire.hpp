@@ -11,11 +11,12 @@
 // Lines do not hide each other: the pixel keeps the largest mask and the
 // triangle it came from (ties: the lower id).
 //
-// Records are staged eight triangles at a time: lanes 8t + e (e < 3) hold
-// edge normal e, lanes 8t + 3 + e the cap centre of side e and its constant
-// a, which they compute from the two end points (loaded by the triangle's
-// id from the vertex array), and pass its constant b to lane 8t + e; lane
-// 8t + 6 holds the record word with the id.
+// The sides' caps are prepared once per scene (vsr_setup_wire) into a
+// rank-ordered array beside the setup records, 64 bytes per triangle:
+// (L_0, a_0), (L_1, a_1), (L_2, a_2), (b_0, b_1, b_2, id).  Records are
+// staged eight triangles at a time: lanes 8t + e (e < 3) hold edge normal e
+// with b_e in its fourth word, lanes 8t + 3 + e side e's cap, lane 8t + 6
+// the word with the id.
 #pragma once
 #include "aa.hpp"
 
@@ -26,7 +27,7 @@ struct WireArgs {
     int64_t ntiles;
     int32_t fmt, depth, W, H, ntx;
     const void* setup;
-    const float* xyz;
+    const float4* wire;  // 4 per rank (vsr_setup_wire)
     int64_t n;
     const void* bins;
     float* cov;
@@ -92,18 +93,6 @@ __device__ inline void wire_tile(const WireArgs& A, int64_t tile, int lane, floa
             n_frag += __popcll(__ballot(m > 0.0f));
         }
     };
-    // side e of the triangle with record rec: cap (L, a) and b
-    auto side = [&](const float4* rec, int e, float4& cap, float& b) {
-        const uint32_t id = __float_as_uint(rec[3].z);
-        const int64_t n = A.n;
-        const int v0 = e, v1 = e == 2 ? 0 : e + 1;
-        float3 P = f3(A.xyz[(3 * v0 + 0) * n + id], A.xyz[(3 * v0 + 1) * n + id], A.xyz[(3 * v0 + 2) * n + id]);
-        float3 Q = f3(A.xyz[(3 * v1 + 0) * n + id], A.xyz[(3 * v1 + 1) * n + id], A.xyz[(3 * v1 + 2) * n + id]);
-        float3 L;
-        float a;
-        side_cap(P, Q, L, a, b);
-        cap = make_float4(L.x, L.y, L.z, a);
-    };
 
     float4 tc0, tc1;
     load_tile_cap(caps, tile, A.rot, tc0, tc1);
@@ -112,33 +101,33 @@ __device__ inline void wire_tile(const WireArgs& A, int64_t tile, int lane, floa
         const uint32_t* lst = lists + tile * A.depth;
         const uint32_t sub = uint32_t(lane) >> 3, part = uint32_t(lane) & 7u;
         const uint32_t ngroups = (count + 7u) >> 3;
-        for (uint32_t gi = 0; gi < ngroups; ++gi) {
-            const uint32_t e = gi * 8u + sub;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            float b = 0.0f;
+        // this lane's word of triangle `sub` of a group
+        auto fetch = [&](uint32_t e) {
+            float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
             if (e < count) {
-                const float4* rec = S.rec + 4 * int64_t(lst[e]);
+                const int64_t rk = lst[e];
                 if (part < 3u) {
-                    v = rec[part];
-                } else if (part < 6u) {
-                    side(rec, int(part) - 3, v, b);
-                } else if (part == 6u) {
-                    v = rec[3];
+                    w = S.rec[4 * rk + part];
+                    w.w = reinterpret_cast<const float*>(A.wire + 4 * rk + 3)[part];
+                } else if (part < 7u) {
+                    w = A.wire[4 * rk + (part - 3u)];
                 }
             }
-            // b of side e travels from lane 8t + 3 + e to lane 8t + e
-            const float bb_e = __shfl(b, int(lane & ~7) + 3 + int(part & 3u));
-            if (part < 3u) v.w = bb_e;
+            return w;
+        };
+        float4 v = fetch(sub);  // group 0; the next group is fetched while one is tested
+        for (uint32_t gi = 0; gi < ngroups; ++gi) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             stg[lane] = v;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (gi + 1 < ngroups) v = fetch((gi + 1) * 8u + sub);
             const uint32_t nt = min(8u, count - gi * 8u);
             for (uint32_t t = 0; t < nt; ++t) {
                 const float4* w = stg + 8 * t;
-                visit(w[0], w[1], w[2], w[3], w[4], w[5], __float_as_uint(w[6].z));
+                visit(w[0], w[1], w[2], w[3], w[4], w[5], __float_as_uint(w[6].w));
             }
         }
     } else {
@@ -150,11 +139,12 @@ __device__ inline void wire_tile(const WireArgs& A, int64_t tile, int lane, floa
                 msk &= msk - 1;
                 uint32_t rk = uint32_t(__builtin_amdgcn_readlane(int(rank), qb));
                 const float4* rec = S.rec + 4 * int64_t(rk);
-                float4 n0 = rec[0], n1 = rec[1], n2 = rec[2], k0, k1, k2;
-                side(rec, 0, k0, n0.w);
-                side(rec, 1, k1, n1.w);
-                side(rec, 2, k2, n2.w);
-                visit(n0, n1, n2, k0, k1, k2, __float_as_uint(rec[3].z));
+                const float4* wr = A.wire + 4 * int64_t(rk);
+                float4 n0 = rec[0], n1 = rec[1], n2 = rec[2], bs = wr[3];
+                n0.w = bs.x;
+                n1.w = bs.y;
+                n2.w = bs.z;
+                visit(n0, n1, n2, wr[0], wr[1], wr[2], __float_as_uint(bs.w));
             }
         });
     }
@@ -171,6 +161,35 @@ __device__ inline void wire_tile(const WireArgs& A, int64_t tile, int lane, floa
     }
 }
 
+// Side caps of every live triangle, rank order (once per scene, after the
+// setup): the end points are the triangle's vertices in id order.
+__global__ __launch_bounds__(256) void k_setup_wire(const float4* __restrict__ rec, const float* __restrict__ xyz,
+                                                    int64_t n, float4* __restrict__ wire) {
+    int64_t rk = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (rk >= n) return;
+    const uint32_t id = __float_as_uint(rec[4 * rk + 3].z);
+    float3 V[3];
+    for (int c = 0; c < 3; ++c) V[c] = f3(xyz[(3 * c + 0) * n + id], xyz[(3 * c + 1) * n + id], xyz[(3 * c + 2) * n + id]);
+    float b[3];
+    for (int e = 0; e < 3; ++e) {
+        float3 L;
+        float a;
+        side_cap(V[e], V[e == 2 ? 0 : e + 1], L, a, b[e]);
+        wire[4 * rk + e] = make_float4(L.x, L.y, L.z, a);
+    }
+    wire[4 * rk + 3] = make_float4(b[0], b[1], b[2], __uint_as_float(id));
+}
+
+hipError_t launch_setup_wire(const void* setup, const float* xyz, int64_t n, void* wire, hipStream_t st) {
+    if (n > 0) {
+        const float4* rec =
+            reinterpret_cast<const float4*>(static_cast<const char*>(setup) + setup_layout(n).rec_off);
+        hipLaunchKernelGGL(k_setup_wire, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, rec, xyz, n,
+                           reinterpret_cast<float4*>(wire));
+    }
+    return hipGetLastError();
+}
+
 template <bool kStats>
 __global__ __launch_bounds__(256) void k_wire(WireArgs A) {
     __shared__ float4 s_stage[4][64];
@@ -181,7 +200,7 @@ __global__ __launch_bounds__(256) void k_wire(WireArgs A) {
 }
 
 hipError_t launch_wire(const void* map, int32_t W, int32_t H, int32_t fmt, const Rot& R, const void* setup,
-                       const float* xyz, int64_t n, const void* bins, int32_t depth, float* cov, uint32_t* dom,
+                       const void* wire, int64_t n, const void* bins, int32_t depth, float* cov, uint32_t* dom,
                        unsigned long long* stats, hipStream_t st) {
     MapLayout ML = map_layout(W, H, fmt);
     WireArgs A;
@@ -193,7 +212,7 @@ hipError_t launch_wire(const void* map, int32_t W, int32_t H, int32_t fmt, const
     A.H = H;
     A.ntx = ML.ntx;
     A.setup = setup;
-    A.xyz = xyz;
+    A.wire = reinterpret_cast<const float4*>(wire);
     A.n = n;
     A.bins = bins;
     A.cov = cov;

@@ -39,11 +39,21 @@ class Scene:
         self.ntri = int(self.xyz.shape[1])
         self.device = self.xyz.device
         self.setup = _buffer(vsr.vsr_setup_bytes(self.ntri), self.device)
+        self.wire = None  # side caps for wire frames, made on first use
         self.refresh(stream)
 
     def refresh(self, stream=None) -> None:
         """Re-run the per-triangle setup (e.g. after the vertices moved)."""
         vsr.vsr_setup_tris(self.xyz, self.setup, stream)
+        if self.wire is not None:
+            vsr.vsr_setup_wire(self.setup, self.xyz, self.ntri, self.wire, stream)
+
+    def wire_caps(self, stream=None) -> torch.Tensor:
+        """The side caps of vsr_setup_wire (kept in step with refresh())."""
+        if self.wire is None:
+            self.wire = _buffer(vsr.vsr_wire_bytes(self.ntri), self.device)
+            vsr.vsr_setup_wire(self.setup, self.xyz, self.ntri, self.wire, stream)
+        return self.wire
 
 
 @dataclass
@@ -166,11 +176,12 @@ def render_wireframe(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, bin_depth: 
                           _buffer(vsr.vsr_bin_bytes(W, H, bin_depth), dev), None)
     frame.view_eff = build_map(view, fmt, vsr.VSR_MAP_AA_LINES, frame.map, stream)
     vsr.vsr_bin(view, fmt, frame.map, scene.setup, scene.ntri, bin_depth, bin_flags, frame.bins, stream)
+    wire = scene.wire_caps(stream)
     if stats is None:
-        vsr.vsr_aa_wireframe(view, fmt, frame.map, scene.setup, scene.xyz, scene.ntri, frame.bins, bin_depth,
+        vsr.vsr_aa_wireframe(view, fmt, frame.map, scene.setup, wire, scene.ntri, frame.bins, bin_depth,
                              frame.coverage, frame.dominant, stream)
     else:
-        vsr.vsr_aa_wireframe_stats(view, fmt, frame.map, scene.setup, scene.xyz, scene.ntri, frame.bins, bin_depth,
+        vsr.vsr_aa_wireframe_stats(view, fmt, frame.map, scene.setup, wire, scene.ntri, frame.bins, bin_depth,
                                    frame.coverage, frame.dominant, stats, stream)
     return frame
 

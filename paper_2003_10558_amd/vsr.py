@@ -89,6 +89,9 @@ _lib.vsr_aa_particles.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64
                                   _vp]
 _lib.vsr_aa_particles_stats.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp,
                                         _vp, _vp, _vp, _i32, _vp]
+_lib.vsr_wire_bytes.argtypes = [_i64]
+_lib.vsr_wire_bytes.restype = _i64
+_lib.vsr_setup_wire.argtypes = [_vp, _vp, _i64, _vp, _i64, _vp]
 _lib.vsr_aa_wireframe.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp]
 _lib.vsr_aa_wireframe_stats.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp,
                                         _vp, _vp]
@@ -111,7 +114,7 @@ for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_
 EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map", "vsr_build_map_lens", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin",
            "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_resolve", "vsr_aa_map_bytes",
            "vsr_aa_raster", "vsr_aa_raster_stats", "vsr_setup_particles", "vsr_aa_particles",
-           "vsr_aa_particles_stats", "vsr_aa_wireframe", "vsr_aa_wireframe_stats", "vsr_submit_bytes",
+           "vsr_aa_particles_stats", "vsr_wire_bytes", "vsr_setup_wire", "vsr_aa_wireframe", "vsr_aa_wireframe_stats", "vsr_submit_bytes",
            "vsr_submit_table_bytes", "vsr_submit_table_offset", "vsr_submit_table", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
 
 
@@ -296,17 +299,25 @@ def vsr_aa_particles_stats(view, fmt: int, map_buf, setup_buf, n: int, bins, bin
                                        _ptr(lost), _ptr(stats), int(bool(no_skip)), _stream(stream)))
 
 
-def vsr_aa_wireframe(view, fmt: int, map_buf, setup_buf, xyz, ntri: int, bins, bin_depth: int, coverage, dominant,
+def vsr_wire_bytes(ntri: int) -> int:
+    return _size(_lib.vsr_wire_bytes(ntri), "vsr_wire_bytes")
+
+
+def vsr_setup_wire(setup_buf, xyz, ntri: int, wire, stream=None) -> None:
+    _check(_lib.vsr_setup_wire(_ptr(setup_buf), _ptr(xyz), ntri, _ptr(wire), _nbytes(wire), _stream(stream)))
+
+
+def vsr_aa_wireframe(view, fmt: int, map_buf, setup_buf, wire, ntri: int, bins, bin_depth: int, coverage, dominant,
                      stream=None) -> None:
     v = make_view(view)
-    _check(_lib.vsr_aa_wireframe(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), _ptr(xyz), ntri, _ptr(bins),
+    _check(_lib.vsr_aa_wireframe(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), _ptr(wire), ntri, _ptr(bins),
                                  bin_depth, _ptr(coverage), _ptr(dominant), _stream(stream)))
 
 
-def vsr_aa_wireframe_stats(view, fmt: int, map_buf, setup_buf, xyz, ntri: int, bins, bin_depth: int, coverage,
+def vsr_aa_wireframe_stats(view, fmt: int, map_buf, setup_buf, wire, ntri: int, bins, bin_depth: int, coverage,
                            dominant, stats, stream=None) -> None:
     v = make_view(view)
-    _check(_lib.vsr_aa_wireframe_stats(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), _ptr(xyz), ntri,
+    _check(_lib.vsr_aa_wireframe_stats(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), _ptr(wire), ntri,
                                        _ptr(bins), bin_depth, _ptr(coverage), _ptr(dominant), _ptr(stats),
                                        _stream(stream)))
 

@@ -226,11 +226,15 @@ def test_primitive_argument_errors(vsr):
             vsr.vsr_aa_particles(v, 0, a["map_buf"], a["setup"], a["n"], a["bins"], a["depth"], a["cov"], a["dp"],
                                  a["uv"], a["dom"], a["lost"], stream=0)
         assert e.value.code == vsr.VSR_E_ARG, c
-    for c in [dict(map_buf=None), dict(xyz=None), dict(cov=B(1026, 1)), dict(depth=5000)]:
-        a = dict(map_buf=B(256, 1), setup=B(512, 1), xyz=B(1024, 1), bins=B(768, 1), depth=64, cov=B(2048, 1),
+    for c in [dict(map_buf=None), dict(wire=None), dict(wire=B(1040, 1)), dict(cov=B(1026, 1)), dict(depth=5000)]:
+        a = dict(map_buf=B(256, 1), setup=B(512, 1), wire=B(1024, 1), bins=B(768, 1), depth=64, cov=B(2048, 1),
                  dom=B(4096, 1))
         a.update(c)
         with pytest.raises(vsr.VsrError) as e:
-            vsr.vsr_aa_wireframe(v, 0, a["map_buf"], a["setup"], a["xyz"], 10, a["bins"], a["depth"], a["cov"],
+            vsr.vsr_aa_wireframe(v, 0, a["map_buf"], a["setup"], a["wire"], 10, a["bins"], a["depth"], a["cov"],
                                  a["dom"], stream=0)
         assert e.value.code == vsr.VSR_E_ARG, c
+    assert vsr.vsr_wire_bytes(1000) == 64000 and vsr.vsr_wire_bytes(0) == 256
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.vsr_setup_wire(B(256, 1), B(512, 1), 1000, B(1024, 100), stream=0)
+    assert e.value.code == vsr.VSR_E_SPACE
