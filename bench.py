@@ -236,24 +236,42 @@ def main():
     vattr = torch.from_numpy(synth.vertex_attributes(tris.shape[1], 21)).to(dev)
     bary_t = torch.empty((3, views[0].height, views[0].width), dtype=torch.float32, device=dev)
     attr_t = torch.empty((5, views[0].height, views[0].width), dtype=torch.float32, device=dev)
-    rl = []
-    for rep in range(4):
+    # the packed copy of vertices and data is made once per scene and data set
+    packed = torch.empty(vsr.vsr_resolve_pack_bytes(scene.ntri, 5), dtype=torch.uint8, device=dev)
+    pl = []
+    for rep in range(3):
         e0, e1 = ev(), ev()
         e0.record(stream)
-        vsr.vsr_resolve(v, fmt, frame.map, scene.xyz, scene.ntri, frame.tri_id, vattr, 5,
-                        vsr.VSR_RESOLVE_NORMALIZE3, bary_t, attr_t)
+        vsr.vsr_resolve_pack(scene.xyz, vattr, scene.ntri, 5, packed)
         e1.record(stream)
         e1.synchronize()
         if rep:
+            pl.append(e0.elapsed_time(e1))
+    pack_ms = float(np.mean(pl))
+    rl, gl = [], []
+    for rep in range(4):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record(stream)
+        vsr.vsr_resolve_packed(v, fmt, frame.map, packed, scene.ntri, 5, frame.tri_id,
+                               vsr.VSR_RESOLVE_NORMALIZE3, bary_t, attr_t)
+        e1.record(stream)
+        vsr.vsr_resolve(v, fmt, frame.map, scene.xyz, scene.ntri, frame.tri_id, vattr, 5,
+                        vsr.VSR_RESOLVE_NORMALIZE3, bary_t, attr_t)
+        e2.record(stream)
+        e2.synchronize()
+        if rep:
             rl.append(e0.elapsed_time(e1))
-    resolve_ms = float(np.mean(rl))
+            gl.append(e1.elapsed_time(e2))
+    resolve_ms, resolve_gather_ms = float(np.mean(rl)), float(np.mean(gl))
+    del packed
     ids_now = frame.tri_id.reshape(-1)
     winners = int(torch.unique(ids_now[ids_now != -1]).numel())
     P = views[0].width * views[0].height
     map_px = 12 if fmt == vsr.VSR_MAP_F32 else 4
     resolve_bytes = P * (map_px + 4 + 4 * (3 + 5)) + winners * (36 + 3 * 5 * 4)
-    log(f"resolve (barycentrics + 5 interpolated components): {resolve_ms:.3f} ms, {winners} distinct winners, "
-        f"{resolve_bytes / resolve_ms / 1e6:.0f} GB/s algorithmic")
+    log(f"resolve (barycentrics + 5 interpolated components): packed {resolve_ms:.3f} ms "
+        f"({resolve_bytes / resolve_ms / 1e6:.0f} GB/s algorithmic), from the arrays {resolve_gather_ms:.3f} ms, "
+        f"packing once per scene {pack_ms:.3f} ms; {winners} distinct winners")
     del bary_t, attr_t
 
     # ---------------- aliasing-free coverage (sections 1.1.1, 1.1.2, 1.4), plain per-view path
@@ -569,8 +587,9 @@ def main():
     roofline_resolve = {"bound": "hbm", "achieved": resolve_bytes / (resolve_ms * 1e-3) / 1e9,
                         "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                         "frac": resolve_bytes / (resolve_ms * 1e-3) / PEAK_HBM,
-                        "traffic": traffic_from_profiles("k_resolve"), "kernel": "k_resolve",
-                        "kernel_ms": resolve_ms, "algorithmic_bytes": resolve_bytes, "winners": winners}
+                        "traffic": traffic_from_profiles("k_resolve<true>"), "kernel": "k_resolve<true>",
+                        "kernel_ms": resolve_ms, "algorithmic_bytes": resolve_bytes, "winners": winners,
+                        "unpacked_ms": resolve_gather_ms, "pack_ms": pack_ms}
     # aliasing-free raster against the VALU peak: lane-ops per fragment (all depths)
     t_aa = float(np.mean(aa_rast)) * 1e-3
     achieved_aa = OPS_PER_AA_FRAGMENT * F_aa_mean / t_aa

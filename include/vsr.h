@@ -364,6 +364,22 @@ int vsr_aa_particles_stats(const vsr_view* v, int32_t fmt, const void* map, cons
                            const void* bins, int32_t bin_depth, float* coverage, float* depth_pass, float* uv,
                            uint32_t* dominant, uint32_t* lost, uint64_t* stats, int32_t no_skip, void* stream);
 
+/* Fragment data from a packed copy of the scene.  vsr_resolve gathers a
+ * winner's 9 coordinates and 3*nattr data values from rows of the [9][T] and
+ * [3][K][T] arrays, each in its own memory line; the packed form keeps one
+ * triangle's vertices and data in one row (A, B, C, then vertex v's
+ * component k at 9 + v*nattr + k; rows of (9 + 3*nattr) floats rounded up
+ * to a multiple of 4).  Pack once per scene and data set (again when
+ * either changes); vsr_resolve_packed gives the same images, bit for bit,
+ * as vsr_resolve on the arrays packed.
+ *   vsr_resolve_pack_bytes  bytes of the packed copy (<0 on bad input).
+ *   vsr_resolve_pack        xyz, vattr as for vsr_resolve -> packed. */
+int64_t vsr_resolve_pack_bytes(int64_t ntri, int32_t nattr);
+int vsr_resolve_pack(const float* xyz, const float* vattr, int64_t ntri, int32_t nattr, void* packed,
+                     int64_t packed_bytes, void* stream);
+int vsr_resolve_packed(const vsr_view* v, int32_t fmt, const void* map, const void* packed, int64_t ntri,
+                       int32_t nattr, const uint32_t* tri_id, uint32_t flags, float* bary, float* attr, void* stream);
+
 /* ------------------------------------------------------------- batches */
 
 /* One view of a batch (host memory).  setup/ntri name a resident scene

@@ -502,6 +502,46 @@ int vsr_resolve(const vsr_view* v, int32_t fmt, const void* map, const float* xy
                       "vsr_resolve");
 }
 
+int64_t vsr_resolve_pack_bytes(int64_t ntri, int32_t nattr) {
+    if (ntri < 0 || ntri > (int64_t(1) << 31) || nattr < 0 || nattr > 64) return VSR_E_ARG;
+    const int64_t b = ntri * int64_t(resolve_stride(nattr)) * 4;
+    return align256(b > 0 ? b : 256);
+}
+
+int vsr_resolve_pack(const float* xyz, const float* vattr, int64_t ntri, int32_t nattr, void* packed,
+                     int64_t packed_bytes, void* stream) {
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri out of range");
+    if (nattr < 0 || nattr > 64) return fail(VSR_E_ARG, "nattr %d outside 0..64", nattr);
+    if (!packed || !aligned(packed) || (ntri > 0 && (!xyz || (nattr > 0 && !vattr))))
+        return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if ((reinterpret_cast<uintptr_t>(xyz) | reinterpret_cast<uintptr_t>(vattr)) & 3u)
+        return fail(VSR_E_ARG, "buffer not 4-byte aligned");
+    const int64_t need = vsr_resolve_pack_bytes(ntri, nattr);
+    if (packed_bytes < need)
+        return fail(VSR_E_SPACE, "packed buffer %lld < %lld bytes", (long long)packed_bytes, (long long)need);
+    return hip_status(launch_resolve_pack(xyz, vattr, ntri, nattr, packed, hipStream_t(stream)), "vsr_resolve_pack");
+}
+
+int vsr_resolve_packed(const vsr_view* v, int32_t fmt, const void* map, const void* packed, int64_t ntri,
+                       int32_t nattr, const uint32_t* tri_id, uint32_t flags, float* bary, float* attr, void* stream) {
+    int rc = check_view_buffers(v, fmt);
+    if (rc != VSR_OK) return rc;
+    if (!map || !aligned(map) || !tri_id || !packed || !aligned(packed))
+        return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if (ntri < 0 || ntri > (int64_t(1) << 31)) return fail(VSR_E_ARG, "ntri out of range");
+    if (nattr < 0 || nattr > 64) return fail(VSR_E_ARG, "nattr %d outside 0..64", nattr);
+    if ((flags & VSR_RESOLVE_NORMALIZE3) && nattr < 3) return fail(VSR_E_ARG, "NORMALIZE3 needs nattr >= 3");
+    if ((flags & ~VSR_RESOLVE_NORMALIZE3) != 0) return fail(VSR_E_ARG, "unknown flags 0x%x", flags);
+    const uintptr_t mis = reinterpret_cast<uintptr_t>(tri_id) | reinterpret_cast<uintptr_t>(bary) |
+                          reinterpret_cast<uintptr_t>(attr);
+    if (mis & 3u) return fail(VSR_E_ARG, "buffer not 4-byte aligned");
+    if (!bary && !attr) return VSR_OK;
+    return hip_status(launch_resolve(map, v->width, v->height, fmt, rot_of(v->rot), nullptr, ntri, tri_id, nullptr,
+                                     nattr, (flags & VSR_RESOLVE_NORMALIZE3) != 0, bary, nattr > 0 ? attr : nullptr,
+                                     hipStream_t(stream), packed),
+                      "vsr_resolve_packed");
+}
+
 int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth) {
     if (!jobs || njobs < 1 || njobs > 4096) return VSR_E_ARG;
     if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return VSR_E_ARG;

@@ -11,7 +11,10 @@
 //
 // One 64-lane wavefront per 8x8 tile of the map, one lane per pixel; the
 // winner's vertices and data are gathered per pixel (neighbouring pixels
-// mostly share a winner, so the gathers hit in cache).
+// mostly share a winner, so the gathers hit in cache).  From the [9][T] and
+// [3][K][T] arrays one triangle's data spans 9 + 3K memory lines; the
+// packed form (vsr_resolve_pack, once per scene) stores each triangle's
+// vertices and data in one contiguous row instead.
 #pragma once
 #include "vsr_internal.h"
 
@@ -29,12 +32,19 @@ struct ResolveArgs {
     int32_t nattr, normalize3;
     float* bary;  // [3][H][W] or null
     float* attr;  // [nattr][H][W] or null
+    const float* packed;  // rows of `stride` floats per triangle, or null
+    int32_t stride, pad_;
 };
+
+// Floats per triangle row of the packed form: A, B, C (9), then vertex v's
+// component k at 9 + v*nattr + k; padded to whole float4.
+__host__ __device__ inline int32_t resolve_stride(int32_t nattr) { return (9 + 3 * nattr + 3) & ~3; }
 
 __device__ inline float3 vertex_of(const float* xyz, int64_t ntri, int64_t t, int v) {
     return f3(xyz[(3 * v + 0) * ntri + t], xyz[(3 * v + 1) * ntri + t], xyz[(3 * v + 2) * ntri + t]);
 }
 
+template <bool kPacked>
 __device__ inline void resolve_tile(const ResolveArgs& A, int64_t tile, int lane) {
     const int tx = int(tile % A.ntx), ty = int(tile / A.ntx);
     const int i = tx * kTile + (lane & (kTile - 1)), j = ty * kTile + (lane >> 3);
@@ -45,8 +55,18 @@ __device__ inline void resolve_tile(const ResolveArgs& A, int64_t tile, int lane
     float b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;
     bool hit = false;
     if (t != VSR_NO_HIT && int64_t(t) < A.ntri && (g.x != 0.0f || g.y != 0.0f || g.z != 0.0f)) {
-        const float3 a = vertex_of(A.xyz, A.ntri, t, 0), b = vertex_of(A.xyz, A.ntri, t, 1),
-                     c = vertex_of(A.xyz, A.ntri, t, 2);
+        float3 a, b, c;
+        if (kPacked) {  // rows start on 16-byte boundaries
+            const float4* row = reinterpret_cast<const float4*>(A.packed + int64_t(t) * A.stride);
+            const float4 r0 = row[0], r1 = row[1], r2 = row[2];
+            a = f3(r0.x, r0.y, r0.z);
+            b = f3(r0.w, r1.x, r1.y);
+            c = f3(r1.z, r1.w, r2.x);
+        } else {
+            a = vertex_of(A.xyz, A.ntri, t, 0);
+            b = vertex_of(A.xyz, A.ntri, t, 1);
+            c = vertex_of(A.xyz, A.ntri, t, 2);
+        }
         const float wa = dot3(g, cross3(b, sub3(c, b)));  // G.(B x C)
         const float wb = dot3(g, cross3(c, sub3(a, c)));  // G.(C x A)
         const float wc = dot3(g, cross3(a, sub3(b, a)));  // G.(A x B)
@@ -67,8 +87,17 @@ __device__ inline void resolve_tile(const ResolveArgs& A, int64_t tile, int lane
     const int64_t na = A.nattr, n = A.ntri;
     auto interp = [&](int k) -> float {
         if (!hit) return 0.0f;
-        const float fa = A.vattr[(0 * na + k) * n + t], fb = A.vattr[(1 * na + k) * n + t],
-                    fc = A.vattr[(2 * na + k) * n + t];
+        float fa, fb, fc;
+        if (kPacked) {
+            const float* row = A.packed + int64_t(t) * A.stride + 9;
+            fa = row[k];
+            fb = row[na + k];
+            fc = row[2 * na + k];
+        } else {
+            fa = A.vattr[(0 * na + k) * n + t];
+            fb = A.vattr[(1 * na + k) * n + t];
+            fc = A.vattr[(2 * na + k) * n + t];
+        }
         return fmaf(b2, fc, fmaf(b1, fb, b0 * fa));
     };
     int k0 = 0;
@@ -89,16 +118,38 @@ __device__ inline void resolve_tile(const ResolveArgs& A, int64_t tile, int lane
     for (int k = k0; k < A.nattr; ++k) A.attr[k * plane + o] = interp(k);
 }
 
+template <bool kPacked>
 __global__ __launch_bounds__(256) void k_resolve(ResolveArgs A) {
     const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
     if (tile >= A.ntiles) return;
-    resolve_tile(A, tile, threadIdx.x & 63);
+    resolve_tile<kPacked>(A, tile, threadIdx.x & 63);
 }
 
+// One thread per triangle: its vertices and data copied into one row.
+__global__ __launch_bounds__(256) void k_resolve_pack(const float* __restrict__ xyz, const float* __restrict__ vattr,
+                                                      int64_t n, int32_t nattr, int32_t stride,
+                                                      float* __restrict__ packed) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    float* row = packed + t * stride;
+    for (int q = 0; q < 9; ++q) row[q] = xyz[q * n + t];
+    for (int q = 0; q < 3 * nattr; ++q) row[9 + q] = vattr[q * n + t];
+    for (int q = 9 + 3 * nattr; q < stride; ++q) row[q] = 0.0f;
+}
+
+hipError_t launch_resolve_pack(const float* xyz, const float* vattr, int64_t n, int32_t nattr, void* packed,
+                               hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_resolve_pack, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, xyz, vattr, n, nattr,
+                           resolve_stride(nattr), reinterpret_cast<float*>(packed));
+    return hipGetLastError();
+}
+
+// packed (optional): rows from vsr_resolve_pack; then xyz and vattr are not read.
 hipError_t launch_resolve(const void* map, int32_t W, int32_t H, int32_t fmt, const Rot& R, const float* xyz,
                           int64_t ntri, const uint32_t* tri_id, const float* vattr, int32_t nattr, bool normalize3,
-                          float* bary, float* attr, hipStream_t st) {
+                          float* bary, float* attr, hipStream_t st, const void* packed = nullptr) {
     const MapLayout ML = map_layout(W, H, fmt);
     ResolveArgs A;
     A.map = map;
@@ -116,7 +167,13 @@ hipError_t launch_resolve(const void* map, int32_t W, int32_t H, int32_t fmt, co
     A.normalize3 = normalize3 ? 1 : 0;
     A.bary = bary;
     A.attr = attr;
-    hipLaunchKernelGGL(k_resolve, dim3(unsigned((ML.ntiles + 3) / 4)), dim3(256), 0, st, A);
+    A.packed = reinterpret_cast<const float*>(packed);
+    A.stride = resolve_stride(nattr);
+    A.pad_ = 0;
+    if (packed)
+        hipLaunchKernelGGL(k_resolve<true>, dim3(unsigned((ML.ntiles + 3) / 4)), dim3(256), 0, st, A);
+    else
+        hipLaunchKernelGGL(k_resolve<false>, dim3(unsigned((ML.ntiles + 3) / 4)), dim3(256), 0, st, A);
     return hipGetLastError();
 }
 

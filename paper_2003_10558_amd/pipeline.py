@@ -99,11 +99,34 @@ def render_fused(scene: Scene, view, fmt: int = vsr.VSR_MAP_F32, stream=None,
     return frame
 
 
+def pack_resolve(scene: Scene, vattr: Optional[torch.Tensor] = None, stream=None) -> Tuple[torch.Tensor, int]:
+    """Packed copy of the scene's vertices and per-vertex data [3, K, T] for
+    resolve(..., packed=...); returns (buffer, K)."""
+    dev = scene.device
+    nattr = 0 if vattr is None else int(vattr.shape[1])
+    if nattr:
+        vattr = vattr.to(device=dev, dtype=torch.float32).contiguous()
+        assert vattr.shape == (3, nattr, scene.ntri)
+    buf = _buffer(vsr.vsr_resolve_pack_bytes(scene.ntri, nattr), dev)
+    vsr.vsr_resolve_pack(scene.xyz, vattr, scene.ntri, nattr, buf, stream)
+    return buf, nattr
+
+
 def resolve(scene: Scene, view, frame: Frame, vattr: Optional[torch.Tensor] = None, normalize3: bool = False,
-            fmt: int = vsr.VSR_MAP_F32, stream=None) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+            fmt: int = vsr.VSR_MAP_F32, stream=None,
+            packed: Optional[Tuple[torch.Tensor, int]] = None) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
     """Fragment data of a rendered frame: barycentric weights [3, H, W] and,
     with per-vertex data ``vattr`` [3, K, T], the interpolated data [K, H, W]
-    (the first three normalised when ``normalize3``)."""
+    (the first three normalised when ``normalize3``).  With ``packed`` (from
+    pack_resolve) the packed copy is read instead of the arrays."""
+    if packed is not None:
+        buf, nattr = packed
+        dev = scene.device
+        bary = torch.empty((3, view.height, view.width), dtype=torch.float32, device=dev)
+        attr = torch.empty((nattr, view.height, view.width), dtype=torch.float32, device=dev) if nattr else None
+        vsr.vsr_resolve_packed(view, fmt, frame.map, buf, scene.ntri, nattr, frame.tri_id,
+                               vsr.VSR_RESOLVE_NORMALIZE3 if normalize3 else 0, bary, attr, stream)
+        return bary, attr
     dev = scene.device
     bary = torch.empty((3, view.height, view.width), dtype=torch.float32, device=dev)
     nattr = 0 if vattr is None else int(vattr.shape[1])

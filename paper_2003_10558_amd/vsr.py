@@ -95,6 +95,10 @@ _lib.vsr_setup_wire.argtypes = [_vp, _vp, _i64, _vp, _i64, _vp]
 _lib.vsr_aa_wireframe.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp]
 _lib.vsr_aa_wireframe_stats.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _vp, _i64, _vp, _i32, _vp, _vp,
                                         _vp, _vp]
+_lib.vsr_resolve_pack_bytes.argtypes = [_i64, _i32]
+_lib.vsr_resolve_pack_bytes.restype = _i64
+_lib.vsr_resolve_pack.argtypes = [_vp, _vp, _i64, _i32, _vp, _i64, _vp]
+_lib.vsr_resolve_packed.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _i32, _vp, _u32, _vp, _vp, _vp]
 _lib.vsr_submit_bytes.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32]
 _lib.vsr_submit_bytes.restype = _i64
 _lib.vsr_submit.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32, _vp, _i64, _vp]
@@ -112,7 +116,8 @@ for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map", "vsr_build_map_lens", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin",
-           "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_resolve", "vsr_aa_map_bytes",
+           "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_resolve", "vsr_resolve_pack_bytes", "vsr_resolve_pack",
+           "vsr_resolve_packed", "vsr_aa_map_bytes",
            "vsr_aa_raster", "vsr_aa_raster_stats", "vsr_setup_particles", "vsr_aa_particles",
            "vsr_aa_particles_stats", "vsr_wire_bytes", "vsr_setup_wire", "vsr_aa_wireframe", "vsr_aa_wireframe_stats", "vsr_submit_bytes",
            "vsr_submit_table_bytes", "vsr_submit_table_offset", "vsr_submit_table", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
@@ -256,6 +261,22 @@ def vsr_resolve(view, fmt: int, map_buf, xyz, ntri: int, tri_id, vattr, nattr: i
     v = make_view(view)
     _check(_lib.vsr_resolve(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(xyz), ntri, _ptr(tri_id), _ptr(vattr), nattr,
                             flags, _ptr(bary), _ptr(attr), _stream(stream)))
+
+
+def vsr_resolve_pack_bytes(ntri: int, nattr: int) -> int:
+    return _size(_lib.vsr_resolve_pack_bytes(ntri, nattr), "vsr_resolve_pack_bytes")
+
+
+def vsr_resolve_pack(xyz, vattr, ntri: int, nattr: int, packed, stream=None) -> None:
+    _check(_lib.vsr_resolve_pack(_ptr(xyz), _ptr(vattr), ntri, nattr, _ptr(packed), _nbytes(packed),
+                                 _stream(stream)))
+
+
+def vsr_resolve_packed(view, fmt: int, map_buf, packed, ntri: int, nattr: int, tri_id, flags: int, bary, attr,
+                       stream=None) -> None:
+    v = make_view(view)
+    _check(_lib.vsr_resolve_packed(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(packed), ntri, nattr, _ptr(tri_id),
+                                   flags, _ptr(bary), _ptr(attr), _stream(stream)))
 
 
 def vsr_aa_map_bytes(width: int, height: int, fmt: int = VSR_MAP_F32) -> int:

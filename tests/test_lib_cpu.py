@@ -155,6 +155,32 @@ def test_resolve_argument_errors(vsr):
         assert e.value.code == vsr.VSR_E_ARG, c
 
 
+def test_resolve_pack_sizes_and_argument_errors(vsr):
+    # rows of 9 + 3K floats rounded up to whole float4, the buffer to 256 bytes
+    for n, k, stride in [(1, 0, 12), (10, 1, 12), (1000, 5, 24), (7, 64, 204)]:
+        assert vsr.vsr_resolve_pack_bytes(n, k) == (n * stride * 4 + 255) // 256 * 256
+    assert vsr.vsr_resolve_pack_bytes(0, 3) == 256
+    for n, k in [(-1, 0), (5, -1), (5, 65)]:
+        with pytest.raises(vsr.VsrError):
+            vsr.vsr_resolve_pack_bytes(n, k)
+    with pytest.raises(vsr.VsrError) as e:   # too small for 1000 rows of 24 floats
+        vsr.vsr_resolve_pack(_FakeBuf(512, 1), _FakeBuf(1024, 1), 1000, 5, _FakeBuf(256, 4096), stream=0)
+    assert e.value.code == vsr.VSR_E_SPACE
+    with pytest.raises(vsr.VsrError) as e:   # data missing for K > 0
+        vsr.vsr_resolve_pack(_FakeBuf(512, 1), None, 10, 2, _FakeBuf(256, 4096), stream=0)
+    assert e.value.code == vsr.VSR_E_ARG
+    v = synth.View(64, 32, 0.3, 0.5, 0.9, 120.0)
+    for c in [dict(nattr=65), dict(nattr=2, flags=vsr.VSR_RESOLVE_NORMALIZE3), dict(flags=8),
+              dict(packed=None), dict(packed=_FakeBuf(300, 1)), dict(bary=_FakeBuf(4098, 1))]:
+        a = dict(map_buf=_FakeBuf(256, 1), packed=_FakeBuf(512, 1), ntri=10, tri_id=_FakeBuf(1024, 1), nattr=3,
+                 flags=0, bary=_FakeBuf(4096, 1), attr=_FakeBuf(8192, 1))
+        a.update(c)
+        with pytest.raises(vsr.VsrError) as e:
+            vsr.vsr_resolve_packed(v, 0, a["map_buf"], a["packed"], a["ntri"], a["nattr"], a["tri_id"],
+                                   a["flags"], a["bary"], a["attr"], stream=0)
+        assert e.value.code == vsr.VSR_E_ARG, c
+
+
 def test_aa_sizes_and_argument_errors(vsr):
     # the AA map appends one float of global delta per pixel to the map
     for w, h, fmt in [(256, 256, 0), (9, 9, 1), (1920, 1080, 0)]:
