@@ -65,9 +65,10 @@ extern "C" {
 #define VSR_BIN_ALL 1u /* list every live triangle in every tile (no culling) */
 /* Workgroup shape of the binner (the lists are the same either way):
  * candidates gathered once per 32x32-pixel block of 4x4 tiles, or once per
- * 16x16 super-tile of 2x2 tiles.  Neither flag: blocks when the list
- * capacity (bin_depth rounded up to a power of two, at least 64) is at most
- * 256 and the launch has at least 8192 blocks, super-tiles otherwise. */
+ * 16x16 super-tile of 2x2 tiles.  Blocks need a list capacity (bin_depth
+ * rounded up to a power of two, at least 64) of at most 256: above it
+ * super-tiles are used whatever the flags.  Neither flag: blocks when the
+ * launch has at least 8192 of them, super-tiles otherwise. */
 #define VSR_BIN_BLOCKS 2u
 #define VSR_BIN_SUPERTILES 4u
 

@@ -6,12 +6,13 @@
 //              owns the 2x2 tiles of quadrant w).  The block cap gathers the
 //              candidates once; each survivor is tested against the four
 //              quadrant (super-tile) caps and then the tiles of the
-//              quadrants it may meet.  Used when the LDS lists (16 x the
-//              list capacity) stay small.
+//              quadrants it may meet; survivors go straight to the output
+//              lists, which each wave sorts in place at the end.  For list
+//              capacities up to 256.
 //   bin_super  one 256-thread workgroup per 16x16 super-tile (2x2 tiles,
 //              wave w owns tile w), for deep lists.
-// Survivors are appended to the tiles' LDS lists with LDS atomics, and each
-// wave writes its tiles' lists with a counting sort by depth bucket.
+// bin_super appends survivors to LDS lists and each wave writes its tile's
+// list with a counting sort by depth bucket.
 #pragma once
 #include "gather.hpp"
 
@@ -103,14 +104,16 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs A) { bin_super(A, xcd_remap
 // ------------------------------------------------ 32x32 blocks ----------
 
 constexpr int kBlkTiles = 16;
+constexpr uint32_t kRing = 512;  // > 63 carried + 256 of one chunk
 
 struct BlockShared {
     SuperShared g;                // gathering state; g.sup = block cap
     float4 tcap[kBlkTiles][2];    // tile caps, tile 4q + (2 dy + dx) of quadrant q
     float4 qcap[4][2];            // quadrant (super-tile) caps, super-tile layout
     uint32_t tcnt[kBlkTiles];
-    uint32_t qn[4];               // survivors of the current chunk that may meet quadrant q ...
-    uint32_t ql[4][256];          // ... and their cell-ordered positions
+    uint32_t ttile[kBlkTiles];    // map tile of each slot (its output list)
+    uint32_t qn[4], qh[4];        // survivors filed for quadrant q so far, and tested so far ...
+    uint32_t ql[4][kRing];        // ... and a ring of their cell-ordered positions
 };
 
 // Tile (tx, ty) of slot t (quadrant t >> 2) of block b; false outside the map.
@@ -139,13 +142,61 @@ __device__ inline bool quad_may_see(float4 s0, float4 s1, float4 a, float ch_t, 
     return !(dot3(n0, c) < lim || dot3(n1, c) < lim || dot3(n2, c) < lim);
 }
 
+// In-place counting sort of one wave's list of cnt <= 256 ranks (global
+// memory written by this workgroup) by depth bucket: the wave holds the list
+// in registers while it counts, then scatters it back.
+__device__ inline void bucket_sort_inplace(uint32_t* list, uint32_t cnt_any, uint32_t* bk, int shift) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t cnt = __builtin_amdgcn_readfirstlane(cnt_any);
+    if (cnt < 2) return;
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t i = uint32_t(lane + 64 * k);
+        v[k] = 0u;
+        if (64u * k < cnt && i < cnt) v[k] = list[i];
+    }
+    reinterpret_cast<uint4*>(bk)[lane] = make_uint4(0u, 0u, 0u, 0u);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (64u * k < cnt && uint32_t(lane + 64 * k) < cnt) atomicAdd(&bk[v[k] >> shift], 1u);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint4 c4 = reinterpret_cast<const uint4*>(bk)[lane];
+    const uint32_t run = c4.x + c4.y + c4.z + c4.w;
+    uint32_t x = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    const uint32_t base = x - run;
+    __builtin_amdgcn_wave_barrier();
+    reinterpret_cast<uint4*>(bk)[lane] = make_uint4(base, base + c4.x, base + c4.x + c4.y, base + c4.x + c4.y + c4.z);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (64u * k < cnt && uint32_t(lane + 64 * k) < cnt) list[atomicAdd(&bk[v[k] >> shift], 1u)] = v[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The block shape needs list capacity <= 256 (see use_blocks).  Survivors
+// go straight to their tile's slots of the output lists (the first `depth`
+// appended; a tile with more is reported as overflowed), and each wave
+// sorts its tiles' lists in place at the end, so the workgroup's LDS holds
+// no lists: more workgroups fit on a CU.
 __device__ inline void bin_block(const BinArgs& A, int64_t b) {
-    extern __shared__ uint32_t lists[];  // kBlkTiles x lds_cap
     __shared__ BlockShared sh;
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const SceneView S = scene_view(A.setup, A.n);
-    const uint32_t lcap = uint32_t(A.lds_cap);
+    const uint32_t depth = uint32_t(A.depth);
+    char* bb = reinterpret_cast<char*>(A.bins);
+    uint32_t* const out = reinterpret_cast<uint32_t*>(bb + 256 + align256(A.ntiles * 4));
     const int nsx = (A.ntx + 1) / 2, nsy = (A.nty + 1) / 2, nbx = (A.ntx + 3) / 4;
     if (tid < kBlkTiles) {
         int64_t tile;
@@ -154,6 +205,7 @@ __device__ inline void bin_block(const BinArgs& A, int64_t b) {
         sh.tcap[tid][0] = c0;
         sh.tcap[tid][1] = c1;
         sh.tcnt[tid] = 0;
+        sh.ttile[tid] = uint32_t(tile);  // only used for tiles inside the map
     } else if (tid < kBlkTiles + 4) {
         const int q = tid - kBlkTiles;
         const int sx = 2 * int(b % nbx) + (q & 1), sy = 2 * int(b / nbx) + (q >> 1);
@@ -177,7 +229,7 @@ __device__ inline void bin_block(const BinArgs& A, int64_t b) {
             const int t = __ffs(mask) - 1;
             mask &= mask - 1;
             const uint32_t pos = atomicAdd(&sh.tcnt[t], 1u);
-            if (pos < lcap) lists[t * lcap + pos] = rank;
+            if (pos < depth) out[int64_t(sh.ttile[t]) * depth + pos] = rank;
         }
     };
     if (any && A.all) {
@@ -190,44 +242,43 @@ __device__ inline void bin_block(const BinArgs& A, int64_t b) {
         }
     } else if (any) {
         // Each chunk of survivors: every thread tests one survivor against
-        // the four quadrant caps and files it in the lists of the quadrants
-        // it may meet; then wave w tests quadrant w's list against its four
-        // tiles.  A wave owns its tiles' counters, so it appends with ballots.
-        if (tid < 4) sh.qn[tid] = 0;
+        // the four quadrant caps and files it in the rings of the quadrants
+        // it may meet; then wave w tests the whole waves (64 entries) of
+        // quadrant w's ring against its four tiles and carries the rest to
+        // the next chunk; what is left is tested at the end.  A wave owns
+        // its tiles' counters, so it appends with ballots.
+        if (tid < 4) {
+            sh.qn[tid] = 0;
+            sh.qh[tid] = 0;
+        }
         __syncthreads();
-        auto visit_chunk = [&](const uint32_t* chunk, uint32_t n) {
-            if (uint32_t(tid) < n) {
-                const uint32_t p = chunk[tid];
-                visit_record(S, true, p, [&](bool, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (quad_may_see(sh.qcap[q][0], sh.qcap[q][1], a, ch_t, n0, n1, n2))
-                            sh.ql[q][atomicAdd(&sh.qn[q], 1u)] = p;
-                });
-            }
-            __syncthreads();
-            const uint32_t m = sh.qn[w];
+        auto drain = [&](bool all) {
+            const uint32_t head = __builtin_amdgcn_readfirstlane(sh.qh[w]);
+            const uint32_t tail = __builtin_amdgcn_readfirstlane(sh.qn[w]);
+            const uint32_t m = all ? tail - head : (tail - head) & ~63u;
+            if (m == 0) return;
             float4 tc0[4], tc1[4];
-            uint32_t tn[4];  // the wave's tile counts, kept identical in every lane
+            uint32_t tn[4];   // the wave's tile counts, kept identical in every lane
+            uint32_t* tl[4];  // and their output lists
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
                 tc0[d] = sh.tcap[4 * w + d][0];
                 tc1[d] = sh.tcap[4 * w + d][1];
-                tn[d] = sh.tcnt[4 * w + d];
+                tn[d] = __builtin_amdgcn_readfirstlane(sh.tcnt[4 * w + d]);
+                tl[d] = out + int64_t(uint32_t(__builtin_amdgcn_readfirstlane(sh.ttile[4 * w + d]))) * depth;
             }
             for (uint32_t i0 = 0; i0 < m; i0 += 64) {
                 const bool v = i0 + uint32_t(lane) < m;
-                visit_record(S, v, v ? sh.ql[w][i0 + lane] : 0u,
+                visit_record(S, v, v ? sh.ql[w][(head + i0 + uint32_t(lane)) & (kRing - 1)] : 0u,
                              [&](bool valid, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t rank) {
 #pragma unroll
                                  for (int d = 0; d < 4; ++d) {
-                                     const int t = 4 * w + d;
                                      const bool on = valid && sub_may_see(tc0[d], tc1[d], a, ch_t, n0, n1, n2);
                                      const uint64_t bal = __ballot(on);
                                      const uint32_t pos = tn[d] + __builtin_amdgcn_mbcnt_hi(
                                                                       uint32_t(bal >> 32),
                                                                       __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
-                                     if (on && pos < lcap) lists[t * lcap + pos] = rank;
+                                     if (on && pos < depth) tl[d][pos] = rank;
                                      tn[d] += uint32_t(__popcll(bal));
                                  }
                              });
@@ -235,27 +286,37 @@ __device__ inline void bin_block(const BinArgs& A, int64_t b) {
             if (lane == 0) {
 #pragma unroll
                 for (int d = 0; d < 4; ++d) sh.tcnt[4 * w + d] = tn[d];
-                sh.qn[w] = 0;  // read by this wave only; the next chunk starts after a barrier
+                sh.qh[w] = head + m;  // read by this wave only, after the next barrier
             }
+        };
+        auto visit_chunk = [&](const uint32_t* chunk, uint32_t n) {
+            if (uint32_t(tid) < n) {
+                const uint32_t p = chunk[tid];
+                visit_record(S, true, p, [&](bool, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (quad_may_see(sh.qcap[q][0], sh.qcap[q][1], a, ch_t, n0, n1, n2))
+                            sh.ql[q][atomicAdd(&sh.qn[q], 1u) & (kRing - 1)] = p;
+                });
+            }
+            __syncthreads();
+            drain(false);
             __syncthreads();
         };
         gather_slices(sh.g, S, 0, kSlices, visit_chunk, [] {});
+        drain(true);
     }
     __syncthreads();
 
-    // wave w writes the lists of quadrant w's tiles
-    char* bb = reinterpret_cast<char*>(A.bins);
+    // wave w sorts the lists of quadrant w's tiles
     const int shift = bucket_shift(A.n);
     for (int d = 0; d < 4; ++d) {
         const int t = 4 * w + d;
         int64_t tile;
         if (!block_tile_of(b, t, A.ntx, A.nty, tile)) continue;
         const uint32_t cnt = sh.tcnt[t];
-        const bool keep = cnt <= uint32_t(A.depth);
-        if (keep) {
-            uint32_t* out = reinterpret_cast<uint32_t*>(bb + 256 + align256(A.ntiles * 4)) + tile * A.depth;
-            bucket_sort_wave(lists + t * lcap, cnt, sh.g.bk[w], shift, out);
-        }
+        const bool keep = cnt <= depth;
+        if (keep) bucket_sort_inplace(out + tile * depth, cnt, sh.g.bk[w], shift);
         if (lane == 0) {
             reinterpret_cast<uint32_t*>(bb + 256)[tile] = cnt;
             if (!keep) atomicAdd(A.status, 1u);
@@ -272,9 +333,10 @@ constexpr int32_t kBlockMaxCap = 256;
 constexpr int64_t kBlockMinGrid = 8192;
 
 inline bool use_blocks(int32_t lds_cap, int64_t nblk, uint32_t flags) {
+    if (lds_cap > kBlockMaxCap) return false;  // blocks sort lists of at most 256 in registers
     if (flags & VSR_BIN_BLOCKS) return true;
     if (flags & VSR_BIN_SUPERTILES) return false;
-    return lds_cap <= kBlockMaxCap && nblk >= kBlockMinGrid;
+    return nblk >= kBlockMinGrid;
 }
 
 __global__ __launch_bounds__(64) void k_zero_u32(uint32_t* p, int64_t n) {
@@ -309,7 +371,7 @@ hipError_t launch_bin(const void* map, int32_t W, int32_t H, int32_t fmt, const 
     A.rot = R;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(bins), int64_t(64));
     if (use_blocks(A.lds_cap, ML.nblk, flags))
-        hipLaunchKernelGGL(k_bin_block, dim3(unsigned(ML.nblk)), dim3(256), size_t(kBlkTiles) * A.lds_cap * 4, st, A);
+        hipLaunchKernelGGL(k_bin_block, dim3(unsigned(ML.nblk)), dim3(256), 0, st, A);
     else
         hipLaunchKernelGGL(k_bin, dim3(unsigned(bin_grid(ML.ntx, ML.nty))), dim3(256),
                            size_t(kSupTiles) * A.lds_cap * 4, st, A);

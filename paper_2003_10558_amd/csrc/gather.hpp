@@ -224,8 +224,9 @@ struct SuperShared {
     uint32_t flag[kSupTiles];
     uint32_t npass;
     uint32_t fc[kSlices * 64];  // per-slice (level, face) triangle counts
-    uint32_t bk[kSupTiles][kDepthBuckets];
+    alignas(16) uint32_t bk[kSupTiles][kDepthBuckets];  // rows read and written as uint4
 };
+static_assert(offsetof(SuperShared, bk) % 16 == 0, "bucket rows are 16-byte aligned");
 static_assert(kSupTiles * kDepthBuckets >= kGatherBlock, "survivor list fits in the bucket counters");
 
 // Exclusive scan of one value per thread over a 256-thread block.

@@ -348,7 +348,7 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
     } else {
         int32_t cap = bin_lds_cap(depth);
         if (use_blocks(cap, blks, shape))
-            hipLaunchKernelGGL(k_submit_bin_block, dim3(unsigned(blks)), dim3(256), size_t(kBlkTiles) * cap * 4, st,
+            hipLaunchKernelGGL(k_submit_bin_block, dim3(unsigned(blks)), dim3(256), 0, st,
                                table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
         else
             hipLaunchKernelGGL(k_submit_bin, dim3(unsigned(stiles)), dim3(256), size_t(kSupTiles) * cap * 4, st,
