@@ -571,9 +571,12 @@ def main():
     # triangle's 64-byte bin record and every tile cap once, write the lists)
     t_b = float(np.mean(binl)) * 1e-3
     bin_bytes = BIN_BYTES_PER_TRI * tris.shape[1] + BIN_BYTES_PER_TILE * ntiles + 4 * float(np.mean(entries))
+    # the library's automatic shape: 32x32 blocks from 2,560 blocks up (list capacity <= 256)
+    nblk = ((views[0].width + 31) // 32) * ((views[0].height + 31) // 32)
+    bin_kernel = "k_bin_block" if (nblk >= 2560 and max(64, 1 << (depth - 1).bit_length()) <= 256) else "k_bin"
     roofline = {"bound": "hbm", "achieved": bin_bytes / t_b / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": bin_bytes / t_b / PEAK_HBM, "traffic": traffic_from_profiles("k_bin"),
-                "kernel": "k_bin", "kernel_ms": t_b * 1e3, "algorithmic_bytes": bin_bytes,
+                "frac": bin_bytes / t_b / PEAK_HBM, "traffic": traffic_from_profiles(bin_kernel),
+                "kernel": bin_kernel, "kernel_ms": t_b * 1e3, "algorithmic_bytes": bin_bytes,
                 "list_entries": float(np.mean(entries))}
     # the rasterizer against the VALU peak: lane-ops per covered fragment
     t_r = float(np.mean(rast)) * 1e-3
@@ -604,7 +607,7 @@ def main():
     roofline_step = {"valu_frac": OPS_PER_FRAGMENT * F_mean / per_view_s / PEAK_VALU_LANE_OPS,
                      "hbm_frac": frame_bytes / per_view_s / PEAK_HBM, "per_view_us": per_view_s * 1e6}
     log(f"roofline: k_aa_raster {roofline_aa['achieved']:.2f} T lane-ops/s ({roofline_aa['frac']:.3f} of VALU)")
-    log(f"roofline: k_bin {roofline['achieved']:.0f} GB/s ({roofline['frac']:.3f} of HBM), k_raster "
+    log(f"roofline: {roofline['kernel']} {roofline['achieved']:.0f} GB/s ({roofline['frac']:.3f} of HBM), k_raster "
         f"{roofline_raster['achieved']:.2f} T lane-ops/s ({roofline_raster['frac']:.3f} of VALU), step per view "
         f"{roofline_step['valu_frac']:.3f} VALU / {roofline_step['hbm_frac']:.3f} HBM")
 

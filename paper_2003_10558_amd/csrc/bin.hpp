@@ -63,19 +63,16 @@ __device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
             if (r < A.n && S.cap[2 * r + 1].z != kCapEmpty) append(live_mask, uint32_t(r));
         }
     } else if (any) {
-        float4 tc0[kSupTiles], tc1[kSupTiles];
-#pragma unroll
-        for (int q = 0; q < kSupTiles; ++q) {
-            tc0[q] = sh.cap[q][0];
-            tc1[q] = sh.cap[q][1];
-        }
         auto visit = [&](bool valid, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t rank) {
             uint32_t mask = 0;
+            // the tile caps are read from LDS here rather than held in 32
+            // registers across the gathering loop
+            asm volatile("" ::: "memory");
             if (valid) {
 #pragma unroll
                 for (int q = 0; q < kSupTiles; ++q)
                     if ((live_mask >> q) & 1u)
-                        if (sub_may_see(tc0[q], tc1[q], a, ch_t, n0, n1, n2)) mask |= 1u << q;
+                        if (sub_may_see(sh.cap[q][0], sh.cap[q][1], a, ch_t, n0, n1, n2)) mask |= 1u << q;
             }
             if (mask) append(mask, rank);
         };
@@ -104,7 +101,7 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs A) { bin_super(A, xcd_remap
 // ------------------------------------------------ 32x32 blocks ----------
 
 constexpr int kBlkTiles = 16;
-constexpr uint32_t kRing = 512;  // > 63 carried + 256 of one chunk
+constexpr uint32_t kQueue = 320;  // >= 63 carried + 256 of one chunk
 
 struct BlockShared {
     SuperShared g;                // gathering state; g.sup = block cap
@@ -112,8 +109,8 @@ struct BlockShared {
     float4 qcap[4][2];            // quadrant (super-tile) caps, super-tile layout
     uint32_t tcnt[kBlkTiles];
     uint32_t ttile[kBlkTiles];    // map tile of each slot (its output list)
-    uint32_t qn[4], qh[4];        // survivors filed for quadrant q so far, and tested so far ...
-    uint32_t ql[4][kRing];        // ... and a ring of their cell-ordered positions
+    uint32_t qn[4];               // survivors filed for quadrant q and not yet tested ...
+    uint32_t ql[4][kQueue];       // ... and their cell-ordered positions
 };
 
 // Tile (tx, ty) of slot t (quadrant t >> 2) of block b; false outside the map.
@@ -242,38 +239,35 @@ __device__ inline void bin_block(const BinArgs& A, int64_t b) {
         }
     } else if (any) {
         // Each chunk of survivors: every thread tests one survivor against
-        // the four quadrant caps and files it in the rings of the quadrants
+        // the four quadrant caps and files it in the queues of the quadrants
         // it may meet; then wave w tests the whole waves (64 entries) of
-        // quadrant w's ring against its four tiles and carries the rest to
-        // the next chunk; what is left is tested at the end.  A wave owns
-        // its tiles' counters, so it appends with ballots.
-        if (tid < 4) {
-            sh.qn[tid] = 0;
-            sh.qh[tid] = 0;
-        }
+        // quadrant w's queue against its four tiles and moves the rest to
+        // the front, for the next chunk; what is left is tested at the end.
+        // A wave owns its tiles' counters, so it appends with ballots.
+        if (tid < 4) sh.qn[tid] = 0;
         __syncthreads();
         auto drain = [&](bool all) {
-            const uint32_t head = __builtin_amdgcn_readfirstlane(sh.qh[w]);
-            const uint32_t tail = __builtin_amdgcn_readfirstlane(sh.qn[w]);
-            const uint32_t m = all ? tail - head : (tail - head) & ~63u;
+            const uint32_t nq = __builtin_amdgcn_readfirstlane(sh.qn[w]);
+            const uint32_t m = all ? nq : nq & ~63u;
             if (m == 0) return;
-            float4 tc0[4], tc1[4];
             uint32_t tn[4];   // the wave's tile counts, kept identical in every lane
             uint32_t* tl[4];  // and their output lists
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
-                tc0[d] = sh.tcap[4 * w + d][0];
-                tc1[d] = sh.tcap[4 * w + d][1];
                 tn[d] = __builtin_amdgcn_readfirstlane(sh.tcnt[4 * w + d]);
                 tl[d] = out + int64_t(uint32_t(__builtin_amdgcn_readfirstlane(sh.ttile[4 * w + d]))) * depth;
             }
             for (uint32_t i0 = 0; i0 < m; i0 += 64) {
+                // the tile caps are read from LDS where they are used rather
+                // than held in 32 registers across the loop
+                asm volatile("" ::: "memory");
                 const bool v = i0 + uint32_t(lane) < m;
-                visit_record(S, v, v ? sh.ql[w][(head + i0 + uint32_t(lane)) & (kRing - 1)] : 0u,
+                visit_record(S, v, v ? sh.ql[w][i0 + uint32_t(lane)] : 0u,
                              [&](bool valid, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t rank) {
 #pragma unroll
                                  for (int d = 0; d < 4; ++d) {
-                                     const bool on = valid && sub_may_see(tc0[d], tc1[d], a, ch_t, n0, n1, n2);
+                                     const bool on = valid && sub_may_see(sh.tcap[4 * w + d][0], sh.tcap[4 * w + d][1],
+                                                                          a, ch_t, n0, n1, n2);
                                      const uint64_t bal = __ballot(on);
                                      const uint32_t pos = tn[d] + __builtin_amdgcn_mbcnt_hi(
                                                                       uint32_t(bal >> 32),
@@ -283,10 +277,16 @@ __device__ inline void bin_block(const BinArgs& A, int64_t b) {
                                  }
                              });
             }
+            // fewer than 64 left (none at the end): to the front of the queue
+            const uint32_t left = nq - m;
+            const uint32_t keep = uint32_t(lane) < left ? sh.ql[w][m + uint32_t(lane)] : 0u;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (uint32_t(lane) < left) sh.ql[w][lane] = keep;
             if (lane == 0) {
 #pragma unroll
                 for (int d = 0; d < 4; ++d) sh.tcnt[4 * w + d] = tn[d];
-                sh.qh[w] = head + m;  // read by this wave only, after the next barrier
+                sh.qn[w] = left;  // appended to after the next barrier
             }
         };
         auto visit_chunk = [&](const uint32_t* chunk, uint32_t n) {
@@ -296,7 +296,7 @@ __device__ inline void bin_block(const BinArgs& A, int64_t b) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
                         if (quad_may_see(sh.qcap[q][0], sh.qcap[q][1], a, ch_t, n0, n1, n2))
-                            sh.ql[q][atomicAdd(&sh.qn[q], 1u) & (kRing - 1)] = p;
+                            sh.ql[q][atomicAdd(&sh.qn[q], 1u)] = p;
                 });
             }
             __syncthreads();
@@ -327,10 +327,13 @@ __device__ inline void bin_block(const BinArgs& A, int64_t b) {
 __global__ __launch_bounds__(256) void k_bin_block(BinArgs A) { bin_block(A, xcd_remap(blockIdx.x, gridDim.x)); }
 
 // Automatic binner shape: 32x32 blocks for list capacities up to
-// kBlockMaxCap and launches of at least kBlockMinGrid blocks (a single small
-// view leaves too few workgroups for the longer block-sized ones).
+// kBlockMaxCap and launches of at least kBlockMinGrid blocks.  Below that a
+// block's longer candidate stream leaves the chip under-filled (the slowest
+// blocks set the launch time): on the 1M-triangle scene the shapes tie at
+// 1600x900 and 1920x1080 (1,450 and 2,040 blocks), blocks take 0.81x the
+// super-tiles' time at 2560x1440 and 0.67x at 3840x2160.
 constexpr int32_t kBlockMaxCap = 256;
-constexpr int64_t kBlockMinGrid = 8192;
+constexpr int64_t kBlockMinGrid = 2560;
 
 inline bool use_blocks(int32_t lds_cap, int64_t nblk, uint32_t flags) {
     if (lds_cap > kBlockMaxCap) return false;  // blocks sort lists of at most 256 in registers

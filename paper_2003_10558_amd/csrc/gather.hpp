@@ -225,8 +225,12 @@ struct SuperShared {
     uint32_t npass;
     uint32_t fc[kSlices * 64];  // per-slice (level, face) triangle counts
     alignas(16) uint32_t bk[kSupTiles][kDepthBuckets];  // rows read and written as uint4
+    alignas(16) uint16_t mark[kGatherBlock];            // row starts (row + 1) in one window of candidates
+    uint32_t carry;                                     // row holding the window's first candidate
 };
-static_assert(offsetof(SuperShared, bk) % 16 == 0, "bucket rows are 16-byte aligned");
+static_assert(offsetof(SuperShared, bk) % 16 == 0 && offsetof(SuperShared, mark) % 16 == 0,
+              "rows read and written as uint4 are 16-byte aligned");
+static_assert(kGatherPer == 4 && kGatherBlock == 4 * 256, "a thread reads its window marks as one uint2");
 static_assert(kSupTiles * kDepthBuckets >= kGatherBlock, "survivor list fits in the bucket counters");
 
 // Exclusive scan of one value per thread over a 256-thread block.
@@ -341,6 +345,7 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
     const float3 cs = f3(sup0.x, sup0.y, sup0.z);
     const float sh_s = sup1.x, ch_s = sup1.y;
     const bool wide = sup1.w != 0.0f;
+    reinterpret_cast<uint2*>(sh.mark)[tid] = make_uint2(0u, 0u);
     if (tid < 64) {
         // rows of pair `tid`, slice-major over the slices that have triangles
         const int iu0 = sh.rect[tid][0], iu1 = sh.rect[tid][1], iv0 = sh.rect[tid][2], iv1 = sh.rect[tid][3];
@@ -363,6 +368,7 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
     __syncthreads();
     const uint32_t nrows_all = sh.ppre[64];
     uint32_t* const pass_list = &sh.bk[0][0];  // free while gathering
+    const int lane = tid & 63, w = tid >> 6;
     for (uint32_t rb = 0; rb < nrows_all; rb += 256) {
         const uint32_t nb = min(256u, nrows_all - rb);
         uint32_t len = 0;
@@ -395,22 +401,43 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
             // stage 1: the super-tile cap test on up to kGatherPer candidates
             // per thread, their loads all in flight together; survivors are
             // compacted into pass_list
+            // Thread t takes candidates k0 + 4t .. k0 + 4t + 3.  Their rows:
+            // the row holding k0, and a mark (row + 1) where each later
+            // non-empty row of the window starts; a running maximum over
+            // the marks gives every candidate its row.
+            if (uint32_t(tid) < nb && len > 0) {
+                if (pre <= k0 && k0 - pre < len)
+                    sh.carry = uint32_t(tid);
+                else if (pre > k0 && pre - k0 < uint32_t(kGatherBlock))
+                    sh.mark[pre - k0] = uint16_t(tid + 1);
+            }
+            __syncthreads();
+            const uint2 m2 = reinterpret_cast<const uint2*>(sh.mark)[tid];
+            reinterpret_cast<uint2*>(sh.mark)[tid] = make_uint2(0u, 0u);  // only this thread reads them
+            uint32_t mk[kGatherPer] = {m2.x & 0xFFFFu, m2.x >> 16, m2.y & 0xFFFFu, m2.y >> 16};
+#pragma unroll
+            for (int u = 1; u < kGatherPer; ++u) mk[u] = max(mk[u], mk[u - 1]);
+            uint32_t x = mk[kGatherPer - 1];
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o, 64);
+                if (lane >= o) x = max(x, y);
+            }
+            if (lane == 63) sh.wsum[w] = x;
+            __syncthreads();
+            uint32_t before = __shfl_up(x, 1, 64);
+            if (lane == 0) before = 0u;
+            for (int q = 0; q < w; ++q) before = max(before, sh.wsum[q]);
+            before = max(before, sh.carry + 1u);
             uint32_t pos[kGatherPer];
             float4 a[kGatherPer];
 #pragma unroll
             for (int u = 0; u < kGatherPer; ++u) {
-                const uint32_t k = k0 + uint32_t(u * 256 + tid);
+                const uint32_t k = k0 + uint32_t(kGatherPer * tid + u);
                 pos[u] = 0xFFFFFFFFu;
                 if (k < total) {
-                    int lo = 0, hi = int(nb) - 1;  // row holding candidate k
-                    while (lo < hi) {
-                        int mid = (lo + hi + 1) >> 1;
-                        if (sh.pre[mid] <= k)
-                            lo = mid;
-                        else
-                            hi = mid - 1;
-                    }
-                    pos[u] = sh.rb[lo] + (k - sh.pre[lo]);
+                    const uint32_t row = max(before, mk[u]) - 1u;
+                    pos[u] = sh.rb[row] + (k - sh.pre[row]);
                 }
             }
 #pragma unroll
