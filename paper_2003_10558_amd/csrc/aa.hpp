@@ -292,7 +292,7 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
         }
     };
 
-    const uint32_t count = counts[tile];
+    const uint32_t count = __builtin_amdgcn_readfirstlane(counts[tile]);  // uniform: scalar loop bounds
     if (count <= uint32_t(A.depth)) {
         const uint32_t* lst = lists + tile * A.depth;
         const uint32_t sub = uint32_t(lane) >> 3, part = uint32_t(lane) & 7u;

@@ -126,7 +126,7 @@ __device__ inline void raster_tile(const RasterArgs& A, int64_t tile, int lane) 
     float3 g = load_dir(A.map, A.fmt, A.ntiles, tile, lane, A.rot);
     bool has_dir = inside && (g.x != 0.0f || g.y != 0.0f || g.z != 0.0f);
     uint64_t best = kKeyEmpty;
-    uint32_t count = counts[tile];
+    const uint32_t count = __builtin_amdgcn_readfirstlane(counts[tile]);  // uniform: scalar loop bounds
     unsigned long long n_tri = 0, n_cov = 0;
     if (count <= uint32_t(A.depth)) {
         __shared__ float4 s_stage[4][64];

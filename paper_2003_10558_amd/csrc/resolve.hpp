@@ -126,23 +126,36 @@ __global__ __launch_bounds__(256) void k_resolve(ResolveArgs A) {
     resolve_tile<kPacked>(A, tile, threadIdx.x & 63);
 }
 
-// One thread per triangle: its vertices and data copied into one row.
+// 64 triangles per 256-thread workgroup, transposed through LDS: the
+// [9][T] and [3][K][T] arrays are read along T and the rows written
+// contiguously, so both sides stay coalesced.
+constexpr int kPackTris = 64;
+
 __global__ __launch_bounds__(256) void k_resolve_pack(const float* __restrict__ xyz, const float* __restrict__ vattr,
                                                       int64_t n, int32_t nattr, int32_t stride,
                                                       float* __restrict__ packed) {
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    float* row = packed + t * stride;
-    for (int q = 0; q < 9; ++q) row[q] = xyz[q * n + t];
-    for (int q = 0; q < 3 * nattr; ++q) row[9 + q] = vattr[q * n + t];
-    for (int q = 9 + 3 * nattr; q < stride; ++q) row[q] = 0.0f;
+    extern __shared__ float rows[];  // kPackTris x stride
+    const int64_t t0 = int64_t(blockIdx.x) * kPackTris;
+    const int nt = int(min(int64_t(kPackTris), n - t0));
+    const int nq = 9 + 3 * nattr;
+    for (int i = threadIdx.x; i < stride * kPackTris; i += 256) {
+        const int q = i / kPackTris, tl = i % kPackTris;
+        float v = 0.0f;
+        if (tl < nt && q < nq) v = q < 9 ? xyz[int64_t(q) * n + t0 + tl] : vattr[int64_t(q - 9) * n + t0 + tl];
+        rows[tl * stride + q] = v;
+    }
+    __syncthreads();
+    float* out = packed + t0 * stride;
+    for (int i = threadIdx.x; i < nt * stride; i += 256) out[i] = rows[i];
 }
 
 hipError_t launch_resolve_pack(const float* xyz, const float* vattr, int64_t n, int32_t nattr, void* packed,
                                hipStream_t st) {
+    const int32_t stride = resolve_stride(nattr);
     if (n > 0)
-        hipLaunchKernelGGL(k_resolve_pack, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, xyz, vattr, n, nattr,
-                           resolve_stride(nattr), reinterpret_cast<float*>(packed));
+        hipLaunchKernelGGL(k_resolve_pack, dim3(unsigned((n + kPackTris - 1) / kPackTris)), dim3(256),
+                           size_t(kPackTris) * stride * 4, st, xyz, vattr, n, nattr, stride,
+                           reinterpret_cast<float*>(packed));
     return hipGetLastError();
 }
 

@@ -96,7 +96,7 @@ __device__ inline void wire_tile(const WireArgs& A, int64_t tile, int lane, floa
 
     float4 tc0, tc1;
     load_tile_cap(caps, tile, A.rot, tc0, tc1);
-    const uint32_t count = counts[tile];
+    const uint32_t count = __builtin_amdgcn_readfirstlane(counts[tile]);  // uniform: scalar loop bounds
     if (count <= uint32_t(A.depth)) {
         const uint32_t* lst = lists + tile * A.depth;
         const uint32_t sub = uint32_t(lane) >> 3, part = uint32_t(lane) & 7u;
