@@ -129,6 +129,47 @@ def test_binning_is_exact_random_views(gpu, seed):
             assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
 
 
+def _bin_lists(gpu, scene, view, depth, flags):
+    """Per-tile counts, lists ([ntiles, depth] u32) and overflow count of one binning."""
+    torch, pipeline, vsr = gpu
+    fr = pipeline.render(scene, view, bin_depth=depth, bin_flags=flags)
+    torch.cuda.synchronize()
+    ntiles = ((view.width + 7) // 8) * ((view.height + 7) // 8)
+    raw = fr.bins.cpu().numpy()
+    counts = raw[256:256 + 4 * ntiles].view(np.uint32).copy()
+    off = 256 + (ntiles * 4 + 255) // 256 * 256
+    lists = raw[off:off + ntiles * depth * 4].view(np.uint32).reshape(ntiles, depth).copy()
+    return counts, lists, vsr.vsr_bin_overflow(fr.bins)
+
+
+def test_bin_lists_identical_across_shapes(gpu):
+    """The 32x32-block and 16x16-super-tile binners give every tile the same
+    count and, where the list fits, the same ranks in depth-bucket order: at
+    depths 1, 2, 63-65 and at depths taken from the tiles' own counts, so
+    that some lists are exactly full (kept) and the next longer ones
+    overflow (counted)."""
+    view = synth.View(200, 150, -0.4, 0.3, 0.9, 300.0, 0, synth.yaw_pitch_rotation(1.0, 0.3))
+    torch, pipeline, vsr = gpu
+    scene = pipeline.Scene(synth.scene(20000, 5))
+    shift = 0
+    while (256 << shift) < scene.ntri:
+        shift += 1
+    full, _, ovf_full = _bin_lists(gpu, scene, view, 2048, 4)
+    assert ovf_full == 0
+    seen = np.unique(full[(full > 0) & (full <= 256)])
+    _say(f"[bin-lists] counts: max {int(full.max())}, {seen.size} distinct values <= 256")
+    depths = sorted({1, 2, 63, 64, 65} | {int(seen[0]), int(seen[len(seen) // 2]), int(seen[-1])})
+    for depth in depths:
+        cb, lb, ob = _bin_lists(gpu, scene, view, depth, 2)
+        cs, ls, os_ = _bin_lists(gpu, scene, view, depth, 4)
+        assert np.array_equal(cb, full) and np.array_equal(cs, full), depth
+        assert ob == os_ == int(np.sum(full > depth)), depth
+        for t in np.flatnonzero((full > 0) & (full <= depth)):
+            a, b = lb[t, :full[t]], ls[t, :full[t]]
+            assert np.array_equal(np.sort(a), np.sort(b)), (depth, t)
+            assert np.all(np.diff(a >> shift) >= 0) and np.all(np.diff(b >> shift) >= 0), (depth, t)
+
+
 RAGGED = [
     (1, 1, 0), (7, 5, 0), (8, 8, 1), (9, 9, 2), (37, 23, 3), (129, 65, 0), (255, 257, 1),
 ]

@@ -38,6 +38,9 @@ def gpu():
 
 
 def _dirs(view, pix):
+    if getattr(view, "lens", synth.LENS_UNIVERSAL) != synth.LENS_UNIVERSAL:
+        d, ok = oracle.perspective_map(view)
+        return np.where(ok.reshape(-1)[pix, None], d.reshape(-1, 3)[pix], 0.0)
     out = np.zeros((len(pix), 3))
     for q, p in enumerate(pix):
         x, y = oracle.view_coord(int(p) % view.width, int(p) // view.width, view.width, view.height, view.aov)
@@ -130,3 +133,20 @@ def test_resolve_packed_identical(gpu, nattr, normalize3):
         assert torch.equal(b0, b1)
         assert (a0 is None and a1 is None) or torch.equal(a0, a1)
         _say(f"[resolve-packed] {view.width}x{view.height} x {tris.shape[1]}, K={nattr}: identical")
+
+
+LENS_VIEWS = {
+    "equirect": synth.View(160, 80, 0, 0, 1, 90, 0, synth.yaw_pitch_rotation(0.7, 0.3), lens=synth.LENS_EQUIRECT),
+    "cube": synth.View(6 * 24, 24, 0, 0, 1, 90, 0, synth.yaw_pitch_rotation(-0.4, 0.9), lens=synth.LENS_CUBE),
+    "dome": synth.View(96, 96, 0, 0, 1, 90, 0, synth.yaw_pitch_rotation(0.3, 0.4), lens=synth.LENS_DOME,
+                       lens_p=(20.0, 15.0, 0.2)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(LENS_VIEWS))
+def test_resolve_lens_maps(gpu, name):
+    """Fragment data on maps of other generators: the step reads only the
+    map's directions, so the same parity holds on every pixel with one."""
+    view = LENS_VIEWS[name]
+    pix = np.arange(view.width * view.height)
+    _check(gpu, view, synth.scene(1500, 41), pix, 43, name)
