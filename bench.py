@@ -663,6 +663,9 @@ def main():
         "covered_fragments_per_frame": F_mean,
         "processed_fragments_per_frame": float(np.mean(F_proc)),
         "executed_tests_per_frame": float(np.mean(tests_proc)),
+        # the same per-frame counts at the batched throughput
+        "covered_fragments_per_s": F_mean * views_per_s,
+        "executed_tests_per_s": float(np.mean(tests_proc)) * views_per_s,
         "overflowed_tiles_plain": overflow,
         "fused_fps": 1e3 / fused_ms,
         "batched_fused_fps": len(views) / fsubmit_ms * 1e3,
