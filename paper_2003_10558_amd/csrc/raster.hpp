@@ -86,7 +86,8 @@ __device__ inline bool raster_list(const uint32_t* lst, uint32_t count, const fl
             if (early_exit) {
                 // every pixel already beats the depth lower bound of this
                 // triangle's bucket, which bounds every triangle still to come
-                float lb = __builtin_amdgcn_readfirstlane(stg[4 * t8 + 3].w);
+                // (the builtin takes an int: pass the bits, not the value)
+                const float lb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(stg[4 * t8 + 3].w)));
                 uint32_t worst = wave_max_u32_dpp(has_dir ? uint32_t(best >> 32) : 0u);
                 if (lb > __uint_as_float(worst)) {
                     done = true;
