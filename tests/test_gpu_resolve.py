@@ -135,6 +135,24 @@ def test_resolve_packed_identical(gpu, nattr, normalize3):
         _say(f"[resolve-packed] {view.width}x{view.height} x {tris.shape[1]}, K={nattr}: identical")
 
 
+def test_resolve_packed_widest_rows(gpu):
+    """64 data components per vertex (rows of 204 floats, the largest the
+    packing transposes through LDS) on a scene whose size is not a multiple
+    of the packing block: the packed path equals the arrays bit for bit."""
+    torch, pipeline, vsr = gpu
+    view = synth.View(64, 48, 0.2, 0.5, 0.9, 140.0, 0, synth.yaw_pitch_rotation(0.2, 0.1))
+    tris = synth.scene(1001, 47)
+    scene = pipeline.Scene(tris)
+    fr = pipeline.render(scene, view)
+    rng = np.random.default_rng(48)
+    vattr = torch.from_numpy(rng.standard_normal((3, 64, tris.shape[1])).astype(np.float32))
+    b0, a0 = pipeline.resolve(scene, view, fr, vattr)
+    b1, a1 = pipeline.resolve(scene, view, fr, vattr, packed=pipeline.pack_resolve(scene, vattr))
+    torch.cuda.synchronize()
+    assert torch.equal(b0, b1) and torch.equal(a0, a1)
+    assert int((pipeline.ids_u32(fr.tri_id) != 0xFFFFFFFF).sum()) > 100
+
+
 LENS_VIEWS = {
     "equirect": synth.View(160, 80, 0, 0, 1, 90, 0, synth.yaw_pitch_rotation(0.7, 0.3), lens=synth.LENS_EQUIRECT),
     "cube": synth.View(6 * 24, 24, 0, 0, 1, 90, 0, synth.yaw_pitch_rotation(-0.4, 0.9), lens=synth.LENS_CUBE),
