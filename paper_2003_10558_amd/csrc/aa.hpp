@@ -76,12 +76,15 @@ struct FragList {
 
     // The loops are unrolled with constant indices (the list stays in
     // registers); a step that no lane of the wave needs is branched over.
-    __device__ inline void insert(float rr, uint32_t ii, float mm, float uu = 0.0f, float ww = 0.0f) {
+    // ub (wave-uniform) >= every lane's cnt: slots past it are empty in the
+    // whole wave and are not visited.
+    __device__ inline void insert(float rr, uint32_t ii, float mm, int ub, float uu = 0.0f, float ww = 0.0f) {
         if (!frag_less(rr, ii, rsat, idsat)) return;  // behind the saturated prefix: zero share
         float cr = rr, cm = mm, cu = uu, cw = ww;
         uint32_t ci = ii;
 #pragma unroll
         for (int k = 0; k < kAAFrags; ++k) {
+            if (k > ub) break;
             if (k < cnt) {
                 if (frag_less(cr, ci, r[k], id[k])) {
                     float tr = r[k], tm = m[k];
@@ -117,6 +120,7 @@ struct FragList {
         int keep = cnt;
 #pragma unroll
         for (int k = 0; k < kAAFrags; ++k) {
+            if (k > ub) break;
             if (k < keep) {
                 if (m[k] >= 1.0f - mb) {
                     rsat = r[k];
@@ -180,7 +184,7 @@ __device__ inline float2 miter_consts(float sh) {
 // One triangle against the lane's pixel: inserts its fragment, if any.
 // c0 = (S, -), c1 = (a, b, -, -).
 __device__ inline bool aa_rec(float4 r0, float4 r1, float4 r2, float4 r3, float4 c0, float4 c1, float3 g, float delta,
-                              FragList<false>& L) {
+                              FragList<false>& L, int ub) {
     float e0 = fmaf(r0.z, g.z, fmaf(r0.y, g.y, r0.x * g.x));
     float e1 = fmaf(r1.z, g.z, fmaf(r1.y, g.y, r1.x * g.x));
     float e2 = fmaf(r2.z, g.z, fmaf(r2.y, g.y, r2.x * g.x));
@@ -191,7 +195,7 @@ __device__ inline bool aa_rec(float4 r0, float4 r1, float4 r2, float4 r3, float4
     if (m > 0.0f) {
         float dn = fmaf(r2.w, g.z, fmaf(r1.w, g.y, r0.w * g.x));
         if (dn > 0.0f) {
-            L.insert(r3.x * __builtin_amdgcn_rcpf(dn), __float_as_uint(r3.z), m);
+            L.insert(r3.x * __builtin_amdgcn_rcpf(dn), __float_as_uint(r3.z), m, ub);
             return true;
         }
     }
@@ -212,7 +216,7 @@ __device__ inline float4 particle_axes(float3 Ph, float sh) {
 // the miter constants c1 = (a, b), depth on the particle's plane, texture
 // coordinates from the axes ax = (X, scale).
 __device__ inline bool part_rec(float4 r0, float4 r1, float4 r2, float4 r3, float4 c0, float4 c1, float4 ax, float3 g,
-                                float delta, FragList<true>& L) {
+                                float delta, FragList<true>& L, int ub) {
     float dx = g.x - c0.x, dy = g.y - c0.y, dz = g.z - c0.z;
     float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     float m = gpstep(fmaf(-q, c1.y, c1.x), delta);
@@ -223,7 +227,7 @@ __device__ inline bool part_rec(float4 r0, float4 r1, float4 r2, float4 r3, floa
             const float3 X = f3(ax.x, ax.y, ax.z);
             const float3 Y = cross3(X, N);
             float u = fmaf(dot3(g, X), ax.w, 0.5f), w = fmaf(dot3(g, Y), ax.w, 0.5f);
-            L.insert(r3.x * __builtin_amdgcn_rcpf(dn), __float_as_uint(r3.z), m, u, w);
+            L.insert(r3.x * __builtin_amdgcn_rcpf(dn), __float_as_uint(r3.z), m, ub, u, w);
             return true;
         }
     }
@@ -281,11 +285,13 @@ __device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* 
         return plane_min_depth(N, d, tcen, tcr, tsr, twide) * (1.0f - 1e-4f) > rmax;
     };
     auto visit = [&](float4 r0, float4 r1, float4 r2, float4 r3, float4 c0, float4 c1, float4 ax) {
+        // the longest list of the wave bounds every lane's insertion (all lanes here)
+        const int ub = int(wave_max_u32_dpp(uint32_t(L.cnt)));
         bool f;
         if constexpr (kPart)
-            f = has_dir && part_rec(r0, r1, r2, r3, c0, c1, ax, g, delta, L);
+            f = has_dir && part_rec(r0, r1, r2, r3, c0, c1, ax, g, delta, L, ub);
         else
-            f = has_dir && aa_rec(r0, r1, r2, r3, c0, c1, g, delta, L);
+            f = has_dir && aa_rec(r0, r1, r2, r3, c0, c1, g, delta, L, ub);
         if (kStats) {
             ++n_test;
             n_frag += __popcll(__ballot(f));
