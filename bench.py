@@ -571,9 +571,9 @@ def main():
     # triangle's 64-byte bin record and every tile cap once, write the lists)
     t_b = float(np.mean(binl)) * 1e-3
     bin_bytes = BIN_BYTES_PER_TRI * tris.shape[1] + BIN_BYTES_PER_TILE * ntiles + 4 * float(np.mean(entries))
-    # the library's automatic shape: 32x32 blocks from 2,000 blocks up (list capacity <= 256)
+    # the library's automatic shape: 32x32 blocks from 2,560 blocks up (list capacity <= 256)
     nblk = ((views[0].width + 31) // 32) * ((views[0].height + 31) // 32)
-    bin_kernel = "k_bin_block" if (nblk >= 2000 and max(64, 1 << (depth - 1).bit_length()) <= 256) else "k_bin"
+    bin_kernel = "k_bin_block" if (nblk >= 2560 and max(64, 1 << (depth - 1).bit_length()) <= 256) else "k_bin"
     roofline = {"bound": "hbm", "achieved": bin_bytes / t_b / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                 "frac": bin_bytes / t_b / PEAK_HBM, "traffic": traffic_from_profiles(bin_kernel),
                 "kernel": bin_kernel, "kernel_ms": t_b * 1e3, "algorithmic_bytes": bin_bytes,

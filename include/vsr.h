@@ -68,7 +68,7 @@ extern "C" {
  * 16x16 super-tile of 2x2 tiles.  Blocks need a list capacity (bin_depth
  * rounded up to a power of two, at least 64) of at most 256: above it
  * super-tiles are used whatever the flags.  Neither flag: blocks when the
- * launch has at least 2000 of them, super-tiles otherwise. */
+ * launch has at least 2560 of them, super-tiles otherwise. */
 #define VSR_BIN_BLOCKS 2u
 #define VSR_BIN_SUPERTILES 4u
 

@@ -329,13 +329,11 @@ __global__ __launch_bounds__(256) void k_bin_block(BinArgs A) { bin_block(A, xcd
 // Automatic binner shape: 32x32 blocks for list capacities up to
 // kBlockMaxCap and launches of at least kBlockMinGrid blocks.  Below that a
 // block's longer candidate stream leaves the chip under-filled (the slowest
-// blocks set the launch time): on the 1M-triangle scene super-tiles win up
-// to 1280x720, the shapes tie at 1600x900 (1,450 blocks), at 1920x1080
-// (2,040 blocks) blocks take 0.90x the super-tiles' time averaged over four
-// lenses (1.02x on a single 180-degree view), 0.81x at 2560x1440 and 0.67x
-// at 3840x2160.
+// blocks set the launch time): on the 1M-triangle scene the shapes tie at
+// 1600x900 and 1920x1080 (1,450 and 2,040 blocks), blocks take 0.81x the
+// super-tiles' time at 2560x1440 and 0.67x at 3840x2160.
 constexpr int32_t kBlockMaxCap = 256;
-constexpr int64_t kBlockMinGrid = 2000;
+constexpr int64_t kBlockMinGrid = 2560;
 
 inline bool use_blocks(int32_t lds_cap, int64_t nblk, uint32_t flags) {
     if (lds_cap > kBlockMaxCap) return false;  // blocks sort lists of at most 256 in registers
