@@ -330,7 +330,9 @@ __global__ __launch_bounds__(256) void k_bin_block(BinArgs A) { bin_block(A, xcd
 // kBlockMaxCap and launches of at least kBlockMinGrid blocks.  Below that a
 // block's longer candidate stream leaves the chip under-filled (the slowest
 // blocks set the launch time): on the 1M-triangle scene the shapes tie at
-// 1600x900 and 1920x1080 (1,450 and 2,040 blocks), blocks take 0.81x the
+// 1600x900 and 1920x1080 (1,450 and 2,040 blocks; at 1920x1080 blocks are
+// 0.90x over four perspective lenses but a 2048x1024 equirectangular map,
+// whose polar blocks gather far more, takes 1.35x), blocks take 0.81x the
 // super-tiles' time at 2560x1440 and 0.67x at 3840x2160.
 constexpr int32_t kBlockMaxCap = 256;
 constexpr int64_t kBlockMinGrid = 2560;
