@@ -471,38 +471,41 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
 }
 
 // Counting sort of one wave's list (ranks) by depth bucket into `out`.
-__device__ inline void bucket_sort_wave(const uint32_t* in, uint32_t cnt, uint32_t* bk, int shift, uint32_t* out) {
+__device__ inline void bucket_sort_wave(const uint32_t* in, uint32_t cnt_any, uint32_t* bk, int shift, uint32_t* out) {
     const int lane = threadIdx.x & 63;
-    for (int q = lane; q < kDepthBuckets; q += 64) bk[q] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    for (uint32_t i = lane; i < cnt; i += 64) atomicAdd(&bk[in[i] >> shift], 1u);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    uint32_t c4[4], run = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        c4[q] = bk[4 * lane + q];
-        run += c4[q];
+    const uint32_t cnt = __builtin_amdgcn_readfirstlane(cnt_any);  // wave-uniform: scalar loop control
+    if (cnt < 2u) {
+        if (cnt == 1u && lane == 0) out[0] = in[0];
+        return;
     }
+    reinterpret_cast<uint4*>(bk)[lane] = make_uint4(0u, 0u, 0u, 0u);  // 16-byte aligned rows of 256
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t i0 = 0; i0 < cnt; i0 += 64) {
+        const uint32_t i = i0 + uint32_t(lane);
+        if (i < cnt) atomicAdd(&bk[in[i] >> shift], 1u);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint4 c4 = reinterpret_cast<const uint4*>(bk)[lane];
+    const uint32_t run = c4.x + c4.y + c4.z + c4.w;
     uint32_t x = run;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         uint32_t y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
-    uint32_t base = x - run;
+    const uint32_t base = x - run;
     __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        bk[4 * lane + q] = base;
-        base += c4[q];
-    }
+    reinterpret_cast<uint4*>(bk)[lane] = make_uint4(base, base + c4.x, base + c4.x + c4.y, base + c4.x + c4.y + c4.z);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t i = lane; i < cnt; i += 64) {
-        uint32_t r = in[i];
-        out[atomicAdd(&bk[r >> shift], 1u)] = r;
+    for (uint32_t i0 = 0; i0 < cnt; i0 += 64) {
+        const uint32_t i = i0 + uint32_t(lane);
+        if (i < cnt) {
+            const uint32_t r = in[i];
+            out[atomicAdd(&bk[r >> shift], 1u)] = r;
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
