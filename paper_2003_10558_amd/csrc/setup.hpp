@@ -253,7 +253,8 @@ __global__ __launch_bounds__(256) void k_setup_tris(const float* __restrict__ xy
 
 // ------------------------------------------------ stable LSD radix sort --
 // Blocks of kSortBlock consecutive keys; per pass: per-block digit
-// histogram, one exclusive scan over (digit, block), stable scatter.
+// histogram, exclusive scans over blocks per digit (and over the digit
+// totals, inside the scatter), stable scatter.
 
 __global__ __launch_bounds__(kSortThreads) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                           uint32_t* __restrict__ hist, int64_t nblocks) {
@@ -296,29 +297,29 @@ __global__ __launch_bounds__(256) void k_rs_scan_rows(uint32_t* __restrict__ his
     if (threadIdx.x == 255) tot[blockIdx.x] = part[255];
 }
 
-// Exclusive scan of the 256 digit totals, in place.
-__global__ __launch_bounds__(256) void k_rs_scan_tot(uint32_t* __restrict__ tot) {
-    __shared__ uint32_t part[256];
-    part[threadIdx.x] = tot[threadIdx.x];
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        uint32_t v = threadIdx.x >= unsigned(o) ? part[threadIdx.x - o] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    tot[threadIdx.x] = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0u;
-}
-
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                              const uint32_t* __restrict__ vin,
                                                              uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              int64_t n, int shift, const uint32_t* __restrict__ offs,
-                                                             int64_t nblocks, const uint32_t* __restrict__ base_of) {
+                                                             int64_t nblocks, const uint32_t* __restrict__ tot) {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[kSortThreads / 64][256];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    run[tid] = base_of[tid] + offs[int64_t(tid) * nblocks + blockIdx.x];
+    // first position of digit tid: exclusive scan of the 256 digit totals
+    // (every workgroup scans them itself: no separate launch)
+    uint32_t x = tot[tid];
+    const uint32_t own = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wcnt[0][wave] = x;
+    __syncthreads();
+    uint32_t first = x - own;
+    for (int q = 0; q < wave; ++q) first += wcnt[0][q];
+    __syncthreads();
+    run[tid] = first + offs[int64_t(tid) * nblocks + blockIdx.x];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int64_t base = int64_t(blockIdx.x) * kSortBlock;
     for (int r = 0; r < kSortItems; ++r) {
@@ -362,7 +363,6 @@ static hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t*
         uint32_t* tot = hist + 256 * nb;
         hipLaunchKernelGGL(k_rs_hist, dim3(unsigned(nb)), dim3(kSortThreads), 0, st, ki, n, shift, hist, nb);
         hipLaunchKernelGGL(k_rs_scan_rows, dim3(256), dim3(256), 0, st, hist, nb, tot);
-        hipLaunchKernelGGL(k_rs_scan_tot, dim3(1), dim3(256), 0, st, tot);
         hipLaunchKernelGGL(k_rs_scatter, dim3(unsigned(nb)), dim3(kSortThreads), 0, st, ki, vi, ko, vo, n, shift,
                            hist, nb, tot);
         b = !b;
@@ -372,29 +372,23 @@ static hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t*
 }
 
 // Permute records and caps into nearest-first order; prepare the cell sort.
-// Eight lanes per rank (four record words, two cap words, the keys), so a
-// gathered 64-byte record is read by one instruction.
 __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ order_ids, int64_t n,
                                                  const float4* __restrict__ rec_id, const float4* __restrict__ cap_id,
                                                  const uint32_t* __restrict__ bucket, float4* __restrict__ rec,
                                                  float4* __restrict__ cap, uint32_t* __restrict__ order,
                                                  uint32_t* __restrict__ key2, uint32_t* __restrict__ val2) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t r = i >> 3;
-    const int part = int(i & 7);
+    int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const uint32_t id = order_ids[r];
-    if (part < 4) {
-        rec[4 * r + part] = rec_id[4 * int64_t(id) + part];
-    } else if (part < 6) {
-        cap[2 * r + (part - 4)] = cap_id[2 * int64_t(id) + (part - 4)];
-    } else if (part == 6) {
-        order[r] = id;
-        const uint32_t b = bucket[id];
-        key2[r] = b == uint32_t(kNumBuckets) ? uint32_t(kIndexKeys)
-                                             : uint32_t(int64_t(slice_of(n, r)) * kNumBuckets + b);
-        val2[r] = uint32_t(r);
-    }
+    uint32_t id = order_ids[r];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rec[4 * r + q] = rec_id[4 * int64_t(id) + q];
+    cap[2 * r + 0] = cap_id[2 * int64_t(id) + 0];
+    cap[2 * r + 1] = cap_id[2 * int64_t(id) + 1];
+    order[r] = id;
+    uint32_t b = bucket[id];
+    key2[r] = b == uint32_t(kNumBuckets) ? uint32_t(kIndexKeys)
+                                         : uint32_t(int64_t(slice_of(n, r)) * kNumBuckets + b);
+    val2[r] = uint32_t(r);
 }
 
 // Depth buckets: ranks are grouped into 2^bucket_shift(n) consecutive ranks
@@ -409,26 +403,22 @@ __global__ __launch_bounds__(256) void k_bucket_lb(float4* __restrict__ rec, int
 }
 
 // Cell-ordered copies: cell_list[k] = rank of the k-th entry and its
-// binning record (cap + edge normals).  Four lanes per entry: the cap, and
-// one edge normal each.
+// binning record (cap + edge normals).
 __global__ __launch_bounds__(256) void k_cell_records(const uint32_t* __restrict__ ranks, int64_t n,
                                                       const float4* __restrict__ rec, const float4* __restrict__ cap,
                                                       uint32_t* __restrict__ cell_list, float4* __restrict__ bincap,
                                                       float4* __restrict__ binnrm) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t k = i >> 2;
-    const int part = int(i & 3);
+    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const uint32_t r = ranks[k];
-    if (part == 0) {
-        cell_list[k] = r;
-        const float4 c0 = cap[2 * int64_t(r)];
-        const float c1z = cap[2 * int64_t(r) + 1].z;
-        bincap[k] = make_float4(c0.x, c0.y, c0.z, c1z == kCapWide ? kBinWide : c0.w);
-    } else {
-        const float4 e = rec[4 * int64_t(r) + (part - 1)];
-        binnrm[3 * k + (part - 1)] = make_float4(e.x, e.y, e.z, part == 1 ? __uint_as_float(r) : 0.0f);
-    }
+    uint32_t r = ranks[k];
+    cell_list[k] = r;
+    float4 c0 = cap[2 * int64_t(r)], c1 = cap[2 * int64_t(r) + 1];
+    float4 r0 = rec[4 * int64_t(r)], r1 = rec[4 * int64_t(r) + 1], r2 = rec[4 * int64_t(r) + 2];
+    float sh = (c1.z == kCapWide) ? kBinWide : c0.w;
+    bincap[k] = make_float4(c0.x, c0.y, c0.z, sh);
+    binnrm[3 * k + 0] = make_float4(r0.x, r0.y, r0.z, __uint_as_float(r));
+    binnrm[3 * k + 1] = make_float4(r1.x, r1.y, r1.z, 0.0f);
+    binnrm[3 * k + 2] = make_float4(r2.x, r2.y, r2.z, 0.0f);
 }
 
 // cell_start[b] = first position whose index key is >= b (lower bound).
@@ -542,8 +532,7 @@ hipError_t launch_setup_common(int64_t n, void* setup, hipStream_t st, Prims pri
         // the cell sort writes into the pair not holding ids
         uint32_t* k2 = in_b ? U(L.key_a_off) : U(L.key_b_off);
         uint32_t* v2 = in_b ? U(L.val_a_off) : U(L.val_b_off);
-        hipLaunchKernelGGL(k_permute, dim3(unsigned((8 * n + 255) / 256)), dim3(256), 0, st, ids, n,
-                           F4(L.rec_id_off), F4(L.cap_id_off),
+        hipLaunchKernelGGL(k_permute, dim3(blocks), dim3(256), 0, st, ids, n, F4(L.rec_id_off), F4(L.cap_id_off),
                            U(L.bucket_off), F4(L.rec_off), F4(L.cap_off), U(L.order_off), k2, v2);
         hipLaunchKernelGGL(k_bucket_lb, dim3(blocks), dim3(256), 0, st, F4(L.rec_off), n, bucket_shift(n));
         // ids are no longer needed: the other pair is free scratch
@@ -554,8 +543,7 @@ hipError_t launch_setup_common(int64_t n, void* setup, hipStream_t st, Prims pri
         if (e != hipSuccess) return e;
         uint32_t* sk = in3 ? k3 : k2;
         uint32_t* sv = in3 ? v3 : v2;
-        hipLaunchKernelGGL(k_cell_records, dim3(unsigned((4 * n + 255) / 256)), dim3(256), 0, st, sv, n,
-                           F4(L.rec_off), F4(L.cap_off),
+        hipLaunchKernelGGL(k_cell_records, dim3(blocks), dim3(256), 0, st, sv, n, F4(L.rec_off), F4(L.cap_off),
                            U(L.cell_list_off), F4(L.bincap_off), F4(L.binnrm_off));
         hipLaunchKernelGGL(k_cell_start, dim3(unsigned((kIndexKeys + 1 + 255) / 256)), dim3(256), 0, st, sk, n,
                            U(L.cell_start_off));
