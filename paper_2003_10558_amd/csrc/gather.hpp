@@ -13,9 +13,10 @@
 // Two gatherers share this machinery:
 //   gather_candidates  one wavefront, one tile (the rasterizer's fallback
 //                      for tiles whose bin overflowed);
-//   gather_slices      one 256-thread workgroup, one 16x16 super-tile of four
-//                      tiles, a range of depth slices, candidates streamed
-//                      through all threads (binning and the fused renderer).
+//   gather_slices      one 256-thread workgroup, one gathering cap (a 16x16
+//                      super-tile or a 32x32 block), a range of depth
+//                      slices, candidates streamed through all threads
+//                      (both binner shapes and the fused renderer).
 #pragma once
 #include "vsr_internal.h"
 
@@ -332,7 +333,8 @@ __device__ inline void visit_record(const SceneView& S, bool valid, uint32_t p, 
 // Streams the candidates of depth slices [s0, s1) through the test against
 // the gathering cap sh.sup.  The rows of every (level, face, slice) are
 // flattened into one list so that their cell ranges load and scan in one
-// pass.  visit_chunk(list, n) is called by every thread for each chunk of
+// pass; each window of kGatherBlock candidates finds its rows from marks at
+// the row starts and a block max-scan.  visit_chunk(list, n) is called by every thread for each chunk of
 // at most 256 survivors (cell-ordered positions list[0..n)); it tests the
 // caller's tiles and appends.  chunk_end() runs after each such call, by all
 // threads (a point where the caller may synchronise).  All threads of the
