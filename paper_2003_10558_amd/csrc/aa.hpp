@@ -49,6 +49,18 @@ struct AAArgs {
     unsigned long long* stats;      // optional: tests, fragments inserted, triangles skipped, tiles
     int32_t no_skip;                // instrumented variant only: test every listed triangle
     Rot rot;
+
+    __device__ inline void globalize() {
+        map = to_global(map);
+        setup = to_global(setup);
+        bins = to_global(bins);
+        cov = to_global(cov);
+        dpass = to_global(dpass);
+        dom = to_global(dom);
+        uv = to_global(uv);
+        lost = to_global(lost);
+        stats = to_global(stats);
+    }
 };
 
 __device__ inline bool frag_less(float ra, uint32_t ia, float rb, uint32_t ib) {
@@ -249,7 +261,9 @@ __device__ inline float plane_min_depth(float3 N, float d, float3 c, float cr, f
 constexpr int kPrimTriangles = 0, kPrimParticles = 1;
 
 template <bool kStats, int kPrim>
-__device__ inline void aa_tile(const AAArgs& A, int64_t tile, int lane, float4* stg) {
+__device__ inline void aa_tile(const AAArgs& A0, int64_t tile, int lane, float4* stg) {
+    AAArgs A = A0;
+    A.globalize();
     constexpr bool kPart = kPrim == kPrimParticles;
     const float4* caps = map_caps(A.map, A.ntiles, A.fmt);
     SceneView S = scene_view(A.setup, A.n);

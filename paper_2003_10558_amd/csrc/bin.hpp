@@ -28,9 +28,18 @@ struct BinArgs {
     void* bins;
     uint32_t* status;  // overflowed-tile counter
     Rot rot;           // camera -> world
+
+    __device__ inline void globalize() {
+        map = to_global(map);
+        setup = to_global(setup);
+        bins = to_global(bins);
+        status = to_global(status);
+    }
 };
 
-__device__ inline void bin_super(const BinArgs& A, int64_t sidx) {
+__device__ inline void bin_super(const BinArgs& A0, int64_t sidx) {
+    BinArgs A = A0;
+    A.globalize();
     extern __shared__ uint32_t lists[];  // kSupTiles x lds_cap
     __shared__ SuperShared sh;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -186,7 +195,9 @@ __device__ inline void bucket_sort_inplace(uint32_t* list, uint32_t cnt_any, uin
 // appended; a tile with more is reported as overflowed), and each wave
 // sorts its tiles' lists in place at the end, so the workgroup's LDS holds
 // no lists: more workgroups fit on a CU.
-__device__ inline void bin_block(const BinArgs& A, int64_t b) {
+__device__ inline void bin_block(const BinArgs& A0, int64_t b) {
+    BinArgs A = A0;
+    A.globalize();
     __shared__ BlockShared sh;
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);

@@ -32,9 +32,19 @@ struct FusedArgs {
     uint32_t* tri_id;
     float* depth;
     Rot rot;            // camera -> world
+
+    __device__ inline void globalize() {
+        map = to_global(map);
+        setup = to_global(setup);
+        scratch = to_global(scratch);
+        tri_id = to_global(tri_id);
+        depth = to_global(depth);
+    }
 };
 
-__device__ inline void fused_super(const FusedArgs& A, int64_t sidx) {
+__device__ inline void fused_super(const FusedArgs& A0, int64_t sidx) {
+    FusedArgs A = A0;
+    A.globalize();
     __shared__ uint32_t lists[kSupTiles][kFusedCap];
     __shared__ SuperShared sh;
     __shared__ float4 stage[kSupTiles][64];

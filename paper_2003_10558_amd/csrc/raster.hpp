@@ -31,6 +31,15 @@ struct RasterArgs {
     unsigned long long* stats;  // instrumented variant only: tests, covered, triangles, tiles
     int32_t no_early_exit;      // instrumented variant only: process whole lists
     Rot rot;                    // camera -> world
+
+    __device__ inline void globalize() {
+        map = to_global(map);
+        setup = to_global(setup);
+        bins = to_global(bins);
+        tri_id = to_global(tri_id);
+        out_depth = to_global(out_depth);
+        stats = to_global(stats);
+    }
 };
 
 // One triangle (record r0..r3) against the lane's pixel; returns whether it
@@ -114,7 +123,9 @@ __device__ inline bool raster_list(const uint32_t* lst, uint32_t count, const fl
 }
 
 template <bool kStats>
-__device__ inline void raster_tile(const RasterArgs& A, int64_t tile, int lane) {
+__device__ inline void raster_tile(const RasterArgs& A0, int64_t tile, int lane) {
+    RasterArgs A = A0;
+    A.globalize();
     const float4* caps = map_caps(A.map, A.ntiles, A.fmt);
     SceneView S = scene_view(A.setup, A.n);
     const char* bb = reinterpret_cast<const char*>(A.bins);

@@ -34,6 +34,16 @@ struct ResolveArgs {
     float* attr;  // [nattr][H][W] or null
     const float* packed;  // rows of `stride` floats per triangle, or null
     int32_t stride, pad_;
+
+    __device__ inline void globalize() {
+        map = to_global(map);
+        xyz = to_global(xyz);
+        tri_id = to_global(tri_id);
+        vattr = to_global(vattr);
+        bary = to_global(bary);
+        attr = to_global(attr);
+        packed = to_global(packed);
+    }
 };
 
 // Floats per triangle row of the packed form: A, B, C (9), then vertex v's
@@ -45,7 +55,9 @@ __device__ inline float3 vertex_of(const float* xyz, int64_t ntri, int64_t t, in
 }
 
 template <bool kPacked>
-__device__ inline void resolve_tile(const ResolveArgs& A, int64_t tile, int lane) {
+__device__ inline void resolve_tile(const ResolveArgs& A0, int64_t tile, int lane) {
+    ResolveArgs A = A0;
+    A.globalize();
     const int tx = int(tile % A.ntx), ty = int(tile / A.ntx);
     const int i = tx * kTile + (lane & (kTile - 1)), j = ty * kTile + (lane >> 3);
     if (i >= A.W || j >= A.H) return;

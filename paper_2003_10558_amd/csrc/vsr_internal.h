@@ -22,6 +22,17 @@ constexpr float kPi = 3.14159265358979323846f;
 constexpr float kQuarterPi = 0.785398163397448310f;
 constexpr float kHalfPi = 1.57079632679489662f;
 constexpr uint32_t kNoHit = VSR_NO_HIT;
+// Buffers reach the kernels through argument structs, job tables or void*,
+// so the compiler sees generic pointers and emits flat loads and stores.  A
+// flat operation also counts as an LDS operation: every wait for LDS data
+// would then wait for outstanding global loads too (a prefetch would stall
+// the next LDS read).  All buffers of the library are global device memory;
+// this cast says so.
+template <typename T>
+__device__ inline T* to_global(T* p) {
+    return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+
 // Initial z-buffer key: depth +inf in the high word, id NO_HIT in the low word.
 constexpr uint64_t kKeyEmpty = (uint64_t(0x7F800000u) << 32) | uint64_t(kNoHit);
 

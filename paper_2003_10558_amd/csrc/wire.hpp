@@ -34,6 +34,16 @@ struct WireArgs {
     uint32_t* dom;
     unsigned long long* stats;  // optional: mask evaluations, (pixel, triangle) pairs with a mask > 0, tiles
     Rot rot;
+
+    __device__ inline void globalize() {
+        map = to_global(map);
+        setup = to_global(setup);
+        wire = to_global(wire);
+        bins = to_global(bins);
+        cov = to_global(cov);
+        dom = to_global(dom);
+        stats = to_global(stats);
+    }
 };
 
 // Centre of the cap around side P->Q and its constants: value at g =
@@ -61,7 +71,9 @@ __device__ inline float side_mask(float4 n, float4 cap, float3 g, float delta) {
 }
 
 template <bool kStats>
-__device__ inline void wire_tile(const WireArgs& A, int64_t tile, int lane, float4* stg) {
+__device__ inline void wire_tile(const WireArgs& A0, int64_t tile, int lane, float4* stg) {
+    WireArgs A = A0;
+    A.globalize();
     const float4* caps = map_caps(A.map, A.ntiles, A.fmt);
     SceneView S = scene_view(A.setup, A.n);
     const char* bb = reinterpret_cast<const char*>(A.bins);
