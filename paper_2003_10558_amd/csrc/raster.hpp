@@ -91,7 +91,9 @@ __device__ inline bool raster_list(const uint32_t* lst, uint32_t count, const fl
             rk = e < count ? lst[e] : 0u;
         }
         const uint32_t nt = min(16u, count - gi * 16u);
-        for (uint32_t t8 = 0; t8 < nt; t8 += 8) {
+        // the early exit is checked every 4 triangles (1080p x 1M: 6% faster
+        // than every 8; every 2 gains nothing more, every 16 loses 15%)
+        for (uint32_t t8 = 0; t8 < nt; t8 += 4) {
             if (early_exit) {
                 // every pixel already beats the depth lower bound of this
                 // triangle's bucket, which bounds every triangle still to come
@@ -104,7 +106,7 @@ __device__ inline bool raster_list(const uint32_t* lst, uint32_t count, const fl
                 }
             }
 #pragma unroll
-            for (uint32_t u = 0; u < 8; ++u) {
+            for (uint32_t u = 0; u < 4; ++u) {
                 const uint32_t t = t8 + u;
                 if (t < nt) {
                     float4 c0 = stg[4 * t], c1 = stg[4 * t + 1], c2 = stg[4 * t + 2], c3 = stg[4 * t + 3];
