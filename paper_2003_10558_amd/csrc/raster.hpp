@@ -99,8 +99,8 @@ __device__ inline bool raster_list(const uint32_t* lst, uint32_t count, const fl
                 // triangle's bucket, which bounds every triangle still to come
                 // (the builtin takes an int: pass the bits, not the value)
                 const float lb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(stg[4 * t8 + 3].w)));
-                uint32_t worst = wave_max_u32_dpp(has_dir ? uint32_t(best >> 32) : 0u);
-                if (lb > __uint_as_float(worst)) {
+                const bool below = !has_dir || __uint_as_float(uint32_t(best >> 32)) < lb;
+                if (__ballot(!below) == 0) {
                     done = true;
                     break;
                 }
