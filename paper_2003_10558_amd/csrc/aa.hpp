@@ -424,7 +424,8 @@ template <bool kStats, int kPrim>
 __global__ __launch_bounds__(256) void k_aa_raster(AAArgs A) {
     __shared__ float4 s_stage[4][64];
     int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
+    // workgroups of 4 consecutive tiles, ntx tiles per row
+    int64_t tile = band_remap(blockIdx.x, gridDim.x, max(int64_t(1), int64_t(A.ntx) * kBandPx / (4 * kTile))) * 4 + w;
     if (tile >= A.ntiles) return;
     aa_tile<kStats, kPrim>(A, tile, threadIdx.x & 63, s_stage[w]);
 }

@@ -105,7 +105,10 @@ __device__ inline void bin_super(const BinArgs& A0, int64_t sidx) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_bin(BinArgs A) { bin_super(A, xcd_remap(blockIdx.x, gridDim.x)); }
+__global__ __launch_bounds__(256) void k_bin(BinArgs A) {
+    const int64_t nsx = (A.ntx + 1) / 2;  // super-tiles per row
+    bin_super(A, band_remap(blockIdx.x, gridDim.x, max(int64_t(1), nsx * kBandPx / (2 * kTile))));
+}
 
 // ------------------------------------------------ 32x32 blocks ----------
 

@@ -149,7 +149,10 @@ __device__ inline void fused_super(const FusedArgs& A0, int64_t sidx) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_fused(FusedArgs A) { fused_super(A, xcd_remap(blockIdx.x, gridDim.x)); }
+__global__ __launch_bounds__(256) void k_fused(FusedArgs A) {
+    const int64_t nsx = (A.ntx + 1) / 2;  // super-tiles per row
+    fused_super(A, band_remap(blockIdx.x, gridDim.x, max(int64_t(1), nsx * kBandPx / (2 * kTile))));
+}
 
 inline int64_t fused_scratch_bytes(int32_t W, int32_t H) {
     return align256(map_layout(W, H, VSR_MAP_F32).ntiles * int64_t(kFusedCap) * 4);

@@ -181,7 +181,8 @@ __device__ inline void raster_tile(const RasterArgs& A0, int64_t tile, int lane)
 template <bool kStats>
 __global__ __launch_bounds__(256) void k_raster(RasterArgs A) {
     int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
+    // workgroups of 4 consecutive tiles, ntx tiles per row
+    int64_t tile = band_remap(blockIdx.x, gridDim.x, max(int64_t(1), int64_t(A.ntx) * kBandPx / (4 * kTile))) * 4 + w;
     if (tile >= A.ntiles) return;
     raster_tile<kStats>(A, tile, threadIdx.x & 63);
 }

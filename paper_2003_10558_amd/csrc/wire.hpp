@@ -206,7 +206,8 @@ template <bool kStats>
 __global__ __launch_bounds__(256) void k_wire(WireArgs A) {
     __shared__ float4 s_stage[4][64];
     int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
+    // workgroups of 4 consecutive tiles, ntx tiles per row
+    int64_t tile = band_remap(blockIdx.x, gridDim.x, max(int64_t(1), int64_t(A.ntx) * kBandPx / (4 * kTile))) * 4 + w;
     if (tile >= A.ntiles) return;
     wire_tile<kStats>(A, tile, threadIdx.x & 63, s_stage[w]);
 }
