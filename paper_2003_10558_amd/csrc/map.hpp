@@ -247,20 +247,26 @@ __device__ inline void tile_cap(float3 g, bool ok, float4& c0, float4& c1) {
         c1 = make_float4(0.f, 1.f, kCapWide, 0.f);
         return;
     }
-    float3 c = f3(sx / len, sy / len, sz / len);
+    const float il = 1.0f / len;
+    float3 c = f3(sx * il, sy * il, sz * il);
     float3 d = sub3(g, c);
     float ch2 = wave_max(ok ? d.x * d.x + d.y * d.y + d.z * d.z : 0.f);
-    float rho = 2.0f * asinf(fminf(1.0f, 0.5f * sqrtf(ch2)));
-    rho = rho * (1.0f + kCapRelMargin) + kCapAbsMargin;
-    if (!(rho < kHalfPi)) {
+    // Half radius a = asin(h), h = half the largest chord, widened by the
+    // margins to a + delta, delta = a kCapRelMargin + kCapAbsMargin / 2.
+    // No transcendental: asin(h) <= (pi/2) h bounds delta, and
+    // sin(a + delta) <= h + cos(a) delta, so the cap is at least as wide as
+    // the margins ask.
+    const float h = fminf(1.0f, 0.5f * sqrtf(ch2));
+    const float delta = kHalfPi * h * kCapRelMargin + 0.5f * kCapAbsMargin;
+    const float sh = fmaf(sqrtf(fmaxf(0.0f, 1.0f - h * h)), delta, h) * (1.0f + 1e-7f);
+    if (!(sh < 0.70710678f)) {  // radius >= pi/2
         c0 = make_float4(c.x, c.y, c.z, 1.f);
         c1 = make_float4(0.f, 1.f, kCapWide, 0.f);
         return;
     }
-    float sh, chh;
-    sincosf(0.5f * rho, &sh, &chh);
+    const float chh = sqrtf(1.0f - sh * sh);
     c0 = make_float4(c.x, c.y, c.z, sh);
-    c1 = make_float4(chh, sinf(rho), 0.f, 0.f);
+    c1 = make_float4(chh, 2.0f * sh * chh, 0.f, 0.f);
 }
 
 // Directions and cap of one tile (one wave); the cap is also returned.
