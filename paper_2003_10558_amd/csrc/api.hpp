@@ -108,6 +108,8 @@ int make_map_params(const vsr_view* v, int32_t fmt, uint32_t flags, MapParams* P
         double hyp = sqrt(W * W + H * H);
         P->xden_lo = P->yden_lo = float(hyp - double(P->xden));
     }
+    P->rxden = P->ryden = float(1.0 / (double(P->xden) + double(P->xden_lo)));
+    P->rc = float(1.0 / (l * (1.0 - s) + s));
     for (int q = 0; q < 9; ++q) P->rot[q] = v->rot[q];
     P->lens = VSR_LENS_UNIVERSAL;
     P->lens_n = 1;

@@ -61,8 +61,12 @@ __device__ inline void lens_distort(const float* c, float& x, float& y) {
 // false when the pixel is outside the projection's domain.
 __device__ inline bool universal_direction(const MapParams& P, int i, int j, float3& out) {
     float nx = float((2 * i + 1 - P.W) * P.xmul), ny = float((2 * j + 1 - P.H) * P.xmul);
-    float x = nx / P.xden;
-    float y = ny / P.yden;
+    // the per-view divisions are products with rounded reciprocals and the
+    // per-pixel ones hardware reciprocals (about 1 ulp each, far inside the
+    // map's accuracy bound of 1e-6 rad; the double-float path below takes
+    // the exact residuals of whatever x and y hold)
+    float x = nx * P.rxden;
+    float y = ny * P.ryden;
     if (P.distort) lens_distort(P.lp, x, y);
     float R = sqrtf(fmaf(x, x, P.l * (y * y)));
     float theta;
@@ -71,8 +75,8 @@ __device__ inline bool universal_direction(const MapParams& P, int i, int j, flo
     } else if (P.kind < 0) {
         // sin(k Omega/2) R in double-float: x, y, R^2, R and the product
         // (the rounding residuals of x and y are known only undistorted)
-        float xl = P.distort ? 0.0f : (fmaf(-x, P.xden, nx) - x * P.xden_lo) / P.xden;
-        float yl = P.distort ? 0.0f : (fmaf(-y, P.yden, ny) - y * P.yden_lo) / P.yden;
+        float xl = P.distort ? 0.0f : (fmaf(-x, P.xden, nx) - x * P.xden_lo) * P.rxden;
+        float yl = P.distort ? 0.0f : (fmaf(-y, P.yden, ny) - y * P.yden_lo) * P.ryden;
         float xx = x * x, xxe = fmaf(x, x, -xx) + 2.0f * x * xl;
         float yy = y * y, yye = fmaf(y, y, -yy) + 2.0f * y * yl;
         float ly = P.l * yy, lye = fmaf(P.l, yy, -ly) + P.l * yye;
@@ -80,7 +84,7 @@ __device__ inline bool universal_direction(const MapParams& P, int i, int j, flo
         two_sum(xx, ly, Xh, Xe);
         Xe += xxe + lye;
         float Rh = sqrtf(Xh);
-        float Rl = Rh > 0.0f ? (fmaf(-Rh, Rh, Xh) + Xe) / (2.0f * Rh) : 0.0f;
+        float Rl = Rh > 0.0f ? (fmaf(-Rh, Rh, Xh) + Xe) * (0.5f * __builtin_amdgcn_rcpf(Rh)) : 0.0f;
         float qh = P.kt * Rh;
         float ql = fmaf(P.kt, Rh, -qh) + P.kt * Rl + P.kt_lo * Rh;
         float s, e;
@@ -93,9 +97,9 @@ __device__ inline bool universal_direction(const MapParams& P, int i, int j, flo
     }
     float sn, cs;
     sincosf(theta, &sn, &cs);
-    float sig = R > 0.0f ? sn / R : P.sig0;
-    float v0 = x * sig, v1 = (y * sig) / P.c, v2 = cs;
-    float inv = 1.0f / sqrtf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
+    float sig = R > 0.0f ? sn * __builtin_amdgcn_rcpf(R) : P.sig0;
+    float v0 = x * sig, v1 = (y * sig) * P.rc, v2 = cs;
+    float inv = __builtin_amdgcn_rsqf(fmaf(v0, v0, fmaf(v1, v1, v2 * v2)));
     out = f3(v0 * inv, v1 * inv, v2 * inv);
     return true;
 }

@@ -112,6 +112,7 @@ struct MapParams {
     int32_t xmul;       // x = (2i+1-W) * xmul / xden, y = (2j+1-H) * xmul / yden
     float xden, yden;   // denominators (rounded) ...
     float xden_lo, yden_lo;  // ... and their rounding residuals
+    float rxden, ryden;      // 1 / the exact denominators, rounded
     float k;            // projection type k (divisor of the arc functions)
     float half;         // Omega / 2 in radians
     float kt;           // tan(k*Omega/2) (k>0) or sin(k*Omega/2) (k<0)
@@ -119,6 +120,7 @@ struct MapParams {
     float sig0;         // limit of sin(theta)/R at R = 0
     float l;            // cylindricity
     float c;            // anamorphic divisor l*(1-s)+s
+    float rc;           // 1 / (l*(1-s)+s), rounded
     float rot[9];
     int32_t lens;       // map generator, VSR_LENS_*
     int32_t lens_n;     // screen array: number of screens
