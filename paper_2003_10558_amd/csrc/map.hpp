@@ -194,28 +194,60 @@ __device__ inline bool pixel_direction(const MapParams& P, int i, int j, float3&
     }
 }
 
-// Derivative of the camera-frame map along one pixel axis at (i, j): central
-// difference of the two neighbours, one-sided where a neighbour is outside
-// the picture, has no direction or lies in another segment of the picture
-// (cube face, screen, eye: not adjacent on the sphere), zero when neither
-// counts.
-__device__ inline float3 map_derivative(const MapParams& P, int i, int j, int di, int dj, float3 g) {
-    float3 gp, gm;
-    const int ip = i + di, jp = j + dj, im = i - di, jm = j - dj;
-    const int seg = pixel_segment(P, i);
-    bool okp = ip < P.W && jp < P.H && pixel_segment(P, ip) == seg && pixel_direction(P, ip, jp, gp);
-    bool okm = im >= 0 && jm >= 0 && pixel_segment(P, im) == seg && pixel_direction(P, im, jm, gm);
+// Derivative of the camera-frame map along one pixel axis at a pixel with
+// direction g: central difference of the two neighbours gp (next) and gm
+// (previous), one-sided where a neighbour is outside the picture, has no
+// direction or lies in another segment of the picture (cube face, screen,
+// eye: not adjacent on the sphere), zero when neither counts (okp, okm say
+// which count).
+__device__ inline float3 central_diff(float3 gp, bool okp, float3 gm, bool okm, float3 g) {
     if (okp && okm) return f3(0.5f * (gp.x - gm.x), 0.5f * (gp.y - gm.y), 0.5f * (gp.z - gm.z));
     if (okp) return sub3(gp, g);
     if (okm) return sub3(g, gm);
     return f3(0.f, 0.f, 0.f);
 }
 
-// Section 1.1.1 global delta: the reciprocal of the largest component of
-// fwidth(G) = |dG/di| + |dG/dj| (+inf when the map does not vary).
-__device__ inline float pixel_delta(const MapParams& P, int i, int j, float3 g) {
-    float3 a = map_derivative(P, i, j, 1, 0, g), b = map_derivative(P, i, j, 0, 1, g);
-    float f = fmaxf(fabsf(a.x) + fabsf(b.x), fmaxf(fabsf(a.y) + fabsf(b.y), fabsf(a.z) + fabsf(b.z)));
+// Direction g and flag ok of lane `inner` when `use_inner`, else ge and oke
+// of lane `ring` (all lanes of the wave call it together).
+__device__ inline void neighbour(bool use_inner, int inner, int ring, float3 g, bool ok, float3 ge, bool oke,
+                                 float3& gn, bool& okn) {
+    const float3 a = f3(__shfl(g.x, inner, 64), __shfl(g.y, inner, 64), __shfl(g.z, inner, 64));
+    const float3 b = f3(__shfl(ge.x, ring, 64), __shfl(ge.y, ring, 64), __shfl(ge.z, ring, 64));
+    const int oa = __shfl(int(ok), inner, 64), ob = __shfl(int(oke), ring, 64);
+    gn = use_inner ? a : b;
+    okn = (use_inner ? oa : ob) != 0;
+}
+
+// Section 1.1.1 global delta of the lane's pixel (i, j) in 8x8 tile (tx, ty):
+// the reciprocal of the largest component of fwidth(G) = |dG/di| + |dG/dj|
+// (+inf when the map does not vary; 0 for a pixel without direction).  The
+// four neighbours' directions inside the tile are those the neighbouring
+// lanes hold (the same evaluation, so the same bits); the 32 pixels around
+// the tile take one more evaluation by lanes 0..31 (right, left, lower,
+// upper side, 8 each).  All lanes of the wave call it together.
+__device__ inline float tile_pixel_delta(const MapParams& P, int tx, int ty, int i, int j, int lane, float3 g,
+                                         bool ok) {
+    const int x = lane & (kTile - 1), y = lane >> 3;
+    float3 ge = f3(0.f, 0.f, 0.f);
+    bool oke = false;
+    if (lane < 4 * kTile) {
+        const int side = lane >> 3, q = lane & (kTile - 1);
+        const int ie = side == 0 ? tx * kTile + kTile : (side == 1 ? tx * kTile - 1 : tx * kTile + q);
+        const int je = side < 2 ? ty * kTile + q : (side == 2 ? ty * kTile + kTile : ty * kTile - 1);
+        if (ie >= 0 && ie < P.W && je >= 0 && je < P.H) oke = pixel_direction(P, ie, je, ge);
+    }
+    float3 gr, gl, gd, gu;
+    bool okr, okl, okd, oku;
+    neighbour(x < kTile - 1, (lane + 1) & 63, y, g, ok, ge, oke, gr, okr);
+    neighbour(x > 0, (lane + 63) & 63, kTile + y, g, ok, ge, oke, gl, okl);
+    neighbour(y < kTile - 1, (lane + kTile) & 63, 2 * kTile + x, g, ok, ge, oke, gd, okd);
+    neighbour(y > 0, (lane + 64 - kTile) & 63, 3 * kTile + x, g, ok, ge, oke, gu, oku);
+    if (!ok) return 0.0f;
+    const int seg = pixel_segment(P, i);
+    okr = okr && pixel_segment(P, i + 1) == seg;
+    okl = okl && pixel_segment(P, i - 1) == seg;
+    const float3 a = central_diff(gr, okr, gl, okl, g), b = central_diff(gd, okd, gu, oku, g);
+    const float f = fmaxf(fabsf(a.x) + fabsf(b.x), fmaxf(fabsf(a.y) + fabsf(b.y), fabsf(a.z) + fabsf(b.z)));
     return f > 0.0f ? 1.0f / f : __int_as_float(0x7F800000);
 }
 
@@ -294,7 +326,7 @@ __device__ inline void build_map_tile(const MapParams& P, void* map, int64_t nti
     int64_t q = tile * kTilePix + lane;
     float fringe = 0.0f;
     if (kAA) {
-        float delta = ok ? pixel_delta(P, i, j, g) : 0.0f;
+        float delta = tile_pixel_delta(P, tx, ty, i, j, lane, g, ok);
         float* dplane = reinterpret_cast<float*>(reinterpret_cast<char*>(map) + aa_delta_off(P.W, P.H, P.fmt));
         dplane[q] = delta;
         fringe = wave_max(ok ? P.fringe / delta : 0.0f);
