@@ -251,20 +251,26 @@ __device__ inline float tile_pixel_delta(const MapParams& P, int tx, int ty, int
     return f > 0.0f ? 1.0f / f : __int_as_float(0x7F800000);
 }
 
-// Widens a tile cap by beta radians (a cap reaching pi/2 becomes wide).
-__device__ inline void dilate_cap(float4& c0, float4& c1, float beta) {
+// Widens a tile cap by the angle asin(f) of a fringe f (sine of the angle),
+// times 1 + 1e-3, plus 1e-6 rad (a cap reaching pi/2 becomes wide).  No
+// transcendental: asin(f) <= f / sqrt(1 - f^2), and with half radius a and
+// half widening b, sin(a + b) <= sin(a) + cos(a) b.
+__device__ inline void dilate_cap(float4& c0, float4& c1, float f) {
     if (c1.z == kCapEmpty || c1.z == kCapWide) return;
-    float rho = 2.0f * asinf(fminf(1.0f, c0.w)) + beta;
-    if (!(rho < kHalfPi)) {
+    float sh = 1.0f;
+    if (f < 0.5f) {
+        const float b = 0.5f * (f * __builtin_amdgcn_rsqf(1.0f - f * f) * (1.0f + 2e-3f) + 1e-6f);
+        sh = fmaf(c1.x, b, c0.w) * (1.0f + 1e-7f);
+    }
+    if (!(sh < 0.70710678f)) {  // radius >= pi/2
         c0.w = 1.f;
         c1 = make_float4(0.f, 1.f, kCapWide, 0.f);
         return;
     }
-    float sh, chh;
-    sincosf(0.5f * rho, &sh, &chh);
+    const float chh = sqrtf(1.0f - sh * sh);
     c0.w = sh;
     c1.x = chh;
-    c1.y = sinf(rho);
+    c1.y = 2.0f * sh * chh;
 }
 
 // Cap of the directions held by the lanes with ok=true (wave-uniform result).
@@ -344,7 +350,7 @@ __device__ inline void build_map_tile(const MapParams& P, void* map, int64_t nti
         p[2 * plane + q] = g.z;
     }
     tile_cap(g, ok, c0, c1);
-    if (kAA) dilate_cap(c0, c1, asinf(fminf(1.0f, fringe)) * (1.0f + 1e-3f) + 1e-6f);
+    if (kAA) dilate_cap(c0, c1, fringe);
     if (lane == 0) {
         MapLayout L = map_layout(P.W, P.H, P.fmt);
         float4* caps = reinterpret_cast<float4*>(reinterpret_cast<char*>(map) + L.caps_off);

@@ -4,9 +4,12 @@ Binning is exact only if every cap the map stores contains the directions
 of all of its pixels, with the safety margin the binner's FP32 tests rely
 on.  This checks that property directly, in FP64 on the host, for the
 Universal Perspective lenses of the benchmark and the other map generators
-(section 2.2), on ragged sizes, for both map formats: every pixel direction
-lies at least half the absolute margin inside its tile cap, every tile cap
-inside its super-tile cap and every super-tile cap inside its block cap.
+(section 2.2), on ragged sizes, for both map formats and for plain,
+aliasing-free and wire-frame maps: every pixel direction, widened by its
+fringe (aliasing-free maps: asin(1/(2 delta)) for triangles, asin(5/(4
+delta)) for lines, delta the pixel's global delta of section 1.1.1), lies at
+least half the absolute margin inside its tile cap, every tile cap inside
+its super-tile cap and every super-tile cap inside its block cap.
 """
 import math
 import sys
@@ -20,8 +23,9 @@ pytestmark = pytest.mark.gpu
 
 CAP_WIDE, CAP_EMPTY = 1.0, 2.0
 # Tile caps are widened by 2e-5 rad in radius (plus 1e-6 relative): a pixel
-# must sit at least half of that inside in chord length.
+# (with its fringe) must sit at least half of that inside.
 TILE_INSIDE = 1e-5
+FRINGE = {"plain": 0.0, "aa": 0.5, "lines": 1.25}
 
 
 def _say(msg):
@@ -100,13 +104,16 @@ def _check_children(parent0, parent1, child0, child1, nx, ny, what):
 @pytest.mark.parametrize("name", ["k1_90", "k0.5_180", "k0_180", "k-0.5_180", "k-0.9_300", "equirect", "cube",
                                   "screens3", "vr", "panorama", "distorted"])
 @pytest.mark.parametrize("fmt", [0, 1], ids=["f32", "oct16"])
-def test_caps_contain_their_pixels(gpu, name, fmt):
+@pytest.mark.parametrize("kind", ["plain", "aa", "lines"])
+def test_caps_contain_their_pixels(gpu, name, fmt, kind):
     torch, pipeline, vsr = gpu
     view = _views(vsr)[name]
-    _say(f"[caps] {name} fmt={fmt} {view.width}x{view.height}")
+    _say(f"[caps] {name} fmt={fmt} {kind} {view.width}x{view.height}")
     W, H = view.width, view.height
-    buf = torch.empty(vsr.vsr_map_bytes(W, H, fmt), dtype=torch.uint8, device="cuda")
-    pipeline.build_map(view, fmt, 0, buf)
+    flags = {"plain": 0, "aa": vsr.VSR_MAP_AA, "lines": vsr.VSR_MAP_AA_LINES}[kind]
+    nbytes = vsr.vsr_map_bytes(W, H, fmt) if kind == "plain" else vsr.vsr_aa_map_bytes(W, H, fmt)
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    pipeline.build_map(view, fmt, flags, buf)
     dirs = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     vsr.vsr_map_unpack(view, fmt, buf, dirs)  # identity rotation: camera frame, as the caps are stored
     torch.cuda.synchronize()
@@ -120,6 +127,7 @@ def test_caps_contain_their_pixels(gpu, name, fmt):
     caps_off = _align(ntiles * 64 * (12 if fmt == 0 else 4))
     sups_off = caps_off + _align(ntiles * 32)
     blks_off = sups_off + _align(nsx * nsy * 32)
+    delta_off = blks_off + _align(nbx * nby * 32)  # aliasing-free maps: one float per pixel, tile-major
 
     def caps_at(off, n):
         a = raw[off:off + 32 * n].view(np.float32).astype(np.float64).reshape(n, 2, 4)
@@ -147,10 +155,18 @@ def test_caps_contain_their_pixels(gpu, name, fmt):
     assert np.all(np.abs(np.linalg.norm(c, axis=1) - 1.0) < 1e-6)
     assert np.all(np.abs(sh * sh + chh * chh - 1.0) < 1e-6)
     assert np.all(srho >= np.sin(_rho(sh)) - 1e-7)
-    chord = np.linalg.norm(tg[narrow] - c[:, None, :], axis=-1)
-    chord = np.where(valid[narrow], chord, 0.0)
-    worst = (chord - (2.0 * sh)[:, None]).max()
-    assert worst <= -TILE_INSIDE, f"a pixel lies {worst:.3g} from its tile cap's rim"
+    cu = c / np.linalg.norm(c, axis=1, keepdims=True)
+    chord = np.linalg.norm(tg[narrow] - cu[:, None, :], axis=-1)
+    ang = 2.0 * np.arcsin(np.minimum(1.0, 0.5 * chord))
+    if kind != "plain":
+        delta = raw[delta_off:delta_off + 4 * 64 * ntiles].view(np.float32).astype(np.float64).reshape(ntiles, 64)
+        d = delta[narrow]
+        assert np.all(d[valid[narrow]] > 0.0)
+        with np.errstate(divide="ignore"):
+            ang = ang + np.arcsin(np.minimum(1.0, np.where(np.isinf(d), 0.0, FRINGE[kind] / d)))
+    ang = np.where(valid[narrow], ang, 0.0)
+    worst = (ang - _rho(sh)[:, None]).max()
+    assert worst <= -TILE_INSIDE, f"a pixel lies {worst:.3g} rad from its tile cap's rim"
 
     _check_children(s0, s1, t0, t1, ntx, nty, "tile")
     _check_children(b0, b1, s0, s1, nsx, nsy, "super")
