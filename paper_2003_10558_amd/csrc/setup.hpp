@@ -297,13 +297,20 @@ __global__ __launch_bounds__(256) void k_rs_scan_rows(uint32_t* __restrict__ his
     if (threadIdx.x == 255) tot[blockIdx.x] = part[255];
 }
 
+// Stable scatter of one block: each element's rank within its digit comes
+// from ballots (8 rounds of 256 in input order), the block is then staged in
+// LDS sorted by digit, and written out so that consecutive threads store
+// consecutive positions of one digit's run (one coalesced segment per digit
+// instead of one 4-byte store per element).
 __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                              const uint32_t* __restrict__ vin,
                                                              uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              int64_t n, int shift, const uint32_t* __restrict__ offs,
                                                              int64_t nblocks, const uint32_t* __restrict__ tot) {
-    __shared__ uint32_t run[256];
+    __shared__ uint32_t gbase[256];  // output position of this block's first element of each digit
+    __shared__ uint32_t lrun[256];   // block-local count of each digit, then its first slot in the stage
     __shared__ uint32_t wcnt[kSortThreads / 64][256];
+    __shared__ uint32_t sk[kSortBlock], sv[kSortBlock];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     // first position of digit tid: exclusive scan of the 256 digit totals
     // (every workgroup scans them itself: no separate launch)
@@ -319,36 +326,76 @@ __global__ __launch_bounds__(kSortThreads) void k_rs_scatter(const uint32_t* __r
     uint32_t first = x - own;
     for (int q = 0; q < wave; ++q) first += wcnt[0][q];
     __syncthreads();
-    run[tid] = first + offs[int64_t(tid) * nblocks + blockIdx.x];
+    gbase[tid] = first + offs[int64_t(tid) * nblocks + blockIdx.x];
+    lrun[tid] = 0;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int64_t base = int64_t(blockIdx.x) * kSortBlock;
+    const int64_t base = int64_t(blockIdx.x) * kSortBlock;
+    uint32_t kk[kSortItems], vv[kSortItems], pos[kSortItems];
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][tid] = 0;
         __syncthreads();
-        int64_t i = base + r * kSortThreads + tid;
-        bool valid = i < n;
-        uint32_t k = valid ? kin[i] : 0u, v = valid ? vin[i] : 0u;
-        uint32_t dg = (k >> shift) & 255u;
+        const int64_t i = base + r * kSortThreads + tid;
+        const bool valid = i < n;
+        const uint32_t k = valid ? kin[i] : 0u, v = valid ? vin[i] : 0u;
+        const uint32_t dg = (k >> shift) & 255u;
         uint64_t same = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
             uint64_t m = __ballot((dg >> bit) & 1u);
             same &= ((dg >> bit) & 1u) ? m : ~m;
         }
-        uint32_t rank = (uint32_t)__popcll(same & lt);
+        const uint32_t rank = (uint32_t)__popcll(same & lt);
         if (valid && rank == 0) wcnt[wave][dg] = (uint32_t)__popcll(same);
         __syncthreads();
+        uint32_t p = 0xFFFFFFFFu;  // rank within the digit over the block so far
         if (valid) {
-            uint32_t pos = run[dg] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][dg];
-            kout[pos] = k;
-            vout[pos] = v;
+            p = lrun[dg] + rank;
+            for (int w = 0; w < wave; ++w) p += wcnt[w][dg];
         }
+        kk[r] = k;
+        vv[r] = v;
+        pos[r] = p;
         __syncthreads();
         uint32_t add = 0;
         for (int w = 0; w < kSortThreads / 64; ++w) add += wcnt[w][tid];
-        run[tid] += add;
-        __syncthreads();
+        lrun[tid] += add;
+    }
+    __syncthreads();
+    // first stage slot of each digit: exclusive scan of the block's counts
+    const uint32_t c = lrun[tid];
+    x = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wcnt[0][wave] = x;
+    __syncthreads();
+    uint32_t start = x - c;
+    for (int q = 0; q < wave; ++q) start += wcnt[0][q];
+    lrun[tid] = start;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        if (pos[r] != 0xFFFFFFFFu) {
+            const uint32_t q = lrun[(kk[r] >> shift) & 255u] + pos[r];
+            sk[q] = kk[r];
+            sv[q] = vv[r];
+        }
+    }
+    __syncthreads();
+    const uint32_t nvalid = uint32_t(min(int64_t(kSortBlock), n - base));
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint32_t q = uint32_t(r * kSortThreads + tid);
+        if (q < nvalid) {
+            const uint32_t k = sk[q];
+            const uint32_t d = (k >> shift) & 255u;
+            const uint32_t o = gbase[d] + (q - lrun[d]);
+            kout[o] = k;
+            vout[o] = sv[q];
+        }
     }
 }
 
