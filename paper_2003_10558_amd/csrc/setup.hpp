@@ -419,7 +419,12 @@ static hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t*
 }
 
 // Permute records and caps into nearest-first order; prepare the cell sort.
-__global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ order_ids, int64_t n,
+// Depth buckets: ranks are grouped into 2^bucket_shift(n) consecutive ranks
+// (at most 256 buckets).  Every record's fourth word of r3 receives the depth
+// lower bound of the first rank of its bucket, which bounds the lower bound
+// of every triangle in that bucket and in all later ones; the permutation
+// writes it with the record (read from the bucket's first source record).
+__global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ order_ids, int64_t n, int shift,
                                                  const float4* __restrict__ rec_id, const float4* __restrict__ cap_id,
                                                  const uint32_t* __restrict__ bucket, float4* __restrict__ rec,
                                                  float4* __restrict__ cap, uint32_t* __restrict__ order,
@@ -427,8 +432,12 @@ __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ or
     int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n) return;
     uint32_t id = order_ids[r];
+    const uint32_t first_id = order_ids[(r >> shift) << shift];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) rec[4 * r + q] = rec_id[4 * int64_t(id) + q];
+    for (int q = 0; q < 3; ++q) rec[4 * r + q] = rec_id[4 * int64_t(id) + q];
+    float4 r3 = rec_id[4 * int64_t(id) + 3];
+    r3.w = rec_id[4 * int64_t(first_id) + 3].y;
+    rec[4 * r + 3] = r3;
     cap[2 * r + 0] = cap_id[2 * int64_t(id) + 0];
     cap[2 * r + 1] = cap_id[2 * int64_t(id) + 1];
     order[r] = id;
@@ -436,17 +445,6 @@ __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ or
     key2[r] = b == uint32_t(kNumBuckets) ? uint32_t(kIndexKeys)
                                          : uint32_t(int64_t(slice_of(n, r)) * kNumBuckets + b);
     val2[r] = uint32_t(r);
-}
-
-// Depth buckets: ranks are grouped into 2^bucket_shift(n) consecutive ranks
-// (at most 256 buckets).  Every record's fourth word of r3 receives the depth
-// lower bound of the first rank of its bucket, which bounds the lower bound
-// of every triangle in that bucket and in all later ones.
-__global__ __launch_bounds__(256) void k_bucket_lb(float4* __restrict__ rec, int64_t n, int shift) {
-    int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    int64_t first = (r >> shift) << shift;
-    rec[4 * r + 3].w = rec[4 * first + 3].y;
 }
 
 // Cell-ordered copies: cell_list[k] = rank of the k-th entry and its
@@ -579,9 +577,8 @@ hipError_t launch_setup_common(int64_t n, void* setup, hipStream_t st, Prims pri
         // the cell sort writes into the pair not holding ids
         uint32_t* k2 = in_b ? U(L.key_a_off) : U(L.key_b_off);
         uint32_t* v2 = in_b ? U(L.val_a_off) : U(L.val_b_off);
-        hipLaunchKernelGGL(k_permute, dim3(blocks), dim3(256), 0, st, ids, n, F4(L.rec_id_off), F4(L.cap_id_off),
-                           U(L.bucket_off), F4(L.rec_off), F4(L.cap_off), U(L.order_off), k2, v2);
-        hipLaunchKernelGGL(k_bucket_lb, dim3(blocks), dim3(256), 0, st, F4(L.rec_off), n, bucket_shift(n));
+        hipLaunchKernelGGL(k_permute, dim3(blocks), dim3(256), 0, st, ids, n, bucket_shift(n), F4(L.rec_id_off),
+                           F4(L.cap_id_off), U(L.bucket_off), F4(L.rec_off), F4(L.cap_off), U(L.order_off), k2, v2);
         // ids are no longer needed: the other pair is free scratch
         uint32_t* k3 = in_b ? U(L.key_b_off) : U(L.key_a_off);
         uint32_t* v3 = in_b ? U(L.val_b_off) : U(L.val_a_off);
