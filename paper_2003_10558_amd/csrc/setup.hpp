@@ -449,12 +449,9 @@ __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ or
 
 // Cell-ordered copies: cell_list[k] = rank of the k-th entry and its
 // binning record (cap + edge normals).
-__global__ __launch_bounds__(256) void k_cell_records(const uint32_t* __restrict__ ranks, int64_t n,
-                                                      const float4* __restrict__ rec, const float4* __restrict__ cap,
-                                                      uint32_t* __restrict__ cell_list, float4* __restrict__ bincap,
-                                                      float4* __restrict__ binnrm) {
-    int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+__device__ inline void cell_record(int64_t k, const uint32_t* __restrict__ ranks, const float4* __restrict__ rec,
+                                   const float4* __restrict__ cap, uint32_t* __restrict__ cell_list,
+                                   float4* __restrict__ bincap, float4* __restrict__ binnrm) {
     uint32_t r = ranks[k];
     cell_list[k] = r;
     float4 c0 = cap[2 * int64_t(r)], c1 = cap[2 * int64_t(r) + 1];
@@ -467,10 +464,8 @@ __global__ __launch_bounds__(256) void k_cell_records(const uint32_t* __restrict
 }
 
 // cell_start[b] = first position whose index key is >= b (lower bound).
-__global__ __launch_bounds__(256) void k_cell_start(const uint32_t* __restrict__ sorted_bucket, int64_t n,
-                                                    uint32_t* __restrict__ cell_start) {
-    int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (b > kIndexKeys) return;
+__device__ inline void cell_start_of(int64_t b, const uint32_t* __restrict__ sorted_bucket, int64_t n,
+                                     uint32_t* __restrict__ cell_start) {
     int64_t lo = 0, hi = n;
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
@@ -480,6 +475,26 @@ __global__ __launch_bounds__(256) void k_cell_start(const uint32_t* __restrict__
             hi = mid;
     }
     cell_start[b] = uint32_t(lo);
+}
+
+constexpr unsigned kCellStartBlocks = unsigned((kIndexKeys + 1 + 255) / 256);
+
+// The cap index from the cell-sorted pairs, in one launch: workgroups
+// [0, kCellStartBlocks) find the cell starts (latency-bound binary
+// searches), the rest gather the cell-ordered binning records (bandwidth-
+// bound), so the two overlap.
+__global__ __launch_bounds__(256) void k_cell_index(const uint32_t* __restrict__ sorted_bucket,
+                                                    const uint32_t* __restrict__ ranks, int64_t n,
+                                                    const float4* __restrict__ rec, const float4* __restrict__ cap,
+                                                    uint32_t* __restrict__ cell_start, uint32_t* __restrict__ cell_list,
+                                                    float4* __restrict__ bincap, float4* __restrict__ binnrm) {
+    if (blockIdx.x < kCellStartBlocks) {
+        const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+        if (b <= kIndexKeys) cell_start_of(b, sorted_bucket, n, cell_start);
+    } else {
+        const int64_t k = int64_t(blockIdx.x - kCellStartBlocks) * blockDim.x + threadIdx.x;
+        if (k < n) cell_record(k, ranks, rec, cap, cell_list, bincap, binnrm);
+    }
 }
 
 // Triangles of slice s on cube face `face` of level L (p = L*6 + face).
@@ -587,13 +602,13 @@ hipError_t launch_setup_common(int64_t n, void* setup, hipStream_t st, Prims pri
         if (e != hipSuccess) return e;
         uint32_t* sk = in3 ? k3 : k2;
         uint32_t* sv = in3 ? v3 : v2;
-        hipLaunchKernelGGL(k_cell_records, dim3(blocks), dim3(256), 0, st, sv, n, F4(L.rec_off), F4(L.cap_off),
-                           U(L.cell_list_off), F4(L.bincap_off), F4(L.binnrm_off));
-        hipLaunchKernelGGL(k_cell_start, dim3(unsigned((kIndexKeys + 1 + 255) / 256)), dim3(256), 0, st, sk, n,
-                           U(L.cell_start_off));
+        hipLaunchKernelGGL(k_cell_index, dim3(kCellStartBlocks + blocks), dim3(256), 0, st, sk, sv, n, F4(L.rec_off),
+                           F4(L.cap_off), U(L.cell_start_off), U(L.cell_list_off), F4(L.bincap_off),
+                           F4(L.binnrm_off));
     } else {
-        hipLaunchKernelGGL(k_cell_start, dim3(unsigned((kIndexKeys + 1 + 255) / 256)), dim3(256), 0, st,
-                           U(L.key_a_off), int64_t(0), U(L.cell_start_off));
+        hipLaunchKernelGGL(k_cell_index, dim3(kCellStartBlocks), dim3(256), 0, st, U(L.key_a_off), U(L.val_a_off),
+                           int64_t(0), F4(L.rec_off), F4(L.cap_off), U(L.cell_start_off), U(L.cell_list_off),
+                           F4(L.bincap_off), F4(L.binnrm_off));
     }
     hipLaunchKernelGGL(k_face_count, dim3(kSlices), dim3(64), 0, st, U(L.cell_start_off), U(L.face_count_off));
     return hipGetLastError();
