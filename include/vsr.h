@@ -17,8 +17,10 @@
  * Conventions shared by every call
  *   - All buffer pointers are DEVICE pointers owned by the caller.  The
  *     library never allocates or frees device memory and keeps no device
- *     state between calls.  Buffer sizes come from the vsr_*_bytes()
- *     functions; buffers must be 256-byte aligned.
+ *     state between calls (the one exception is the scratch array of
+ *     vsr_render_noalloc, part of the loaded code object).  Buffer sizes
+ *     come from the vsr_*_bytes() functions; buffers must be 256-byte
+ *     aligned.
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
  *     Every call only enqueues work on it and returns; results are ready
  *     when the stream is synchronised.
@@ -230,6 +232,22 @@ int64_t vsr_render_bytes(int32_t width, int32_t height);
  *   scratch  device buffer of vsr_render_bytes(width, height) bytes. */
 int vsr_render(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri, void* scratch,
                int64_t scratch_bytes, uint32_t* tri_id, float* depth, void* stream);
+
+/* vsr_render for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernel and images as vsr_render, with its list scratch taken from a
+ * device array the library holds (VSR_NOALLOC_MAX_TILES x 4 KiB = 128 MiB
+ * on every GPU that loads the library, until the process ends) instead of a
+ * caller buffer.  The call allocates nothing.  Views of more than
+ * VSR_NOALLOC_MAX_TILES tiles of 8x8 pixels (1920x1080 has 32,400) are
+ * refused with VSR_E_SPACE.  All calls on one GPU share its array and the
+ * array keeps the last call's contents: calls that overlap in time on one GPU
+ * (other streams, other threads) race on it and may give wrong images;
+ * serialise them.  The current device must be the device of `stream`.
+ * Other arguments and errors as vsr_render. */
+#define VSR_NOALLOC_MAX_TILES 32768
+int vsr_render_noalloc(const vsr_view* v, int32_t fmt, const void* map, const void* setup, int64_t ntri,
+                       uint32_t* tri_id, float* depth, void* stream);
 
 /* Step 6 — fragment data from barycentric coordinates (section 1.1.4,
  * second half).  For every pixel whose tri_id names a triangle: the

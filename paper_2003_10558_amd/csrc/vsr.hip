@@ -10,4 +10,6 @@
 //   aa.hpp      aliasing-free coverage, particles       (sections 1.1.1, 1.1.2, 1.3, 1.4)
 //   wire.hpp    aliasing-free wire frame                (section 1.2)
 //   api.hpp     C ABI (include/vsr.h)
+//   noalloc.hpp vsr_render with a library-held scratch array
 #include "api.hpp"
+#include "noalloc.hpp"

@@ -78,6 +78,7 @@ _lib.vsr_raster_stats.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64
 _lib.vsr_render_bytes.argtypes = [_i32, _i32]
 _lib.vsr_render_bytes.restype = _i64
 _lib.vsr_render.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp]
+_lib.vsr_render_noalloc.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _vp, _vp]
 _lib.vsr_resolve.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i64, _vp, _vp, _i32, _u32, _vp, _vp, _vp]
 _lib.vsr_aa_map_bytes.argtypes = [_i32, _i32, _i32]
 _lib.vsr_aa_map_bytes.restype = _i64
@@ -111,12 +112,12 @@ _lib.vsr_bin_overflow.argtypes = [_vp, _i32, ctypes.POINTER(_i64)]
 _lib.vsr_strerror.argtypes = [ctypes.c_int]
 _lib.vsr_strerror.restype = ctypes.c_char_p
 _lib.vsr_last_error.restype = ctypes.c_char_p
-for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_raster", "vsr_raster_stats", "vsr_render", "vsr_submit", "vsr_submit_table",
-           "vsr_bin_overflow"):
+for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_raster", "vsr_raster_stats", "vsr_render", "vsr_render_noalloc", "vsr_submit",
+           "vsr_submit_table", "vsr_bin_overflow"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map", "vsr_build_map_lens", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin",
-           "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_resolve", "vsr_resolve_pack_bytes", "vsr_resolve_pack",
+           "vsr_raster", "vsr_raster_stats", "vsr_render_bytes", "vsr_render", "vsr_render_noalloc", "vsr_resolve", "vsr_resolve_pack_bytes", "vsr_resolve_pack",
            "vsr_resolve_packed", "vsr_aa_map_bytes",
            "vsr_aa_raster", "vsr_aa_raster_stats", "vsr_setup_particles", "vsr_aa_particles",
            "vsr_aa_particles_stats", "vsr_wire_bytes", "vsr_setup_wire", "vsr_aa_wireframe", "vsr_aa_wireframe_stats", "vsr_submit_bytes",
@@ -254,6 +255,12 @@ def vsr_render(view, fmt: int, map_buf, setup_buf, ntri: int, scratch, tri_id, d
     v = make_view(view)
     _check(_lib.vsr_render(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), ntri, _ptr(scratch),
                            _nbytes(scratch), _ptr(tri_id), _ptr(depth), _stream(stream)))
+
+
+def vsr_render_noalloc(view, fmt: int, map_buf, setup_buf, ntri: int, tri_id, depth, stream=None) -> None:
+    v = make_view(view)
+    _check(_lib.vsr_render_noalloc(ctypes.byref(v), fmt, _ptr(map_buf), _ptr(setup_buf), ntri, _ptr(tri_id),
+                                   _ptr(depth), _stream(stream)))
 
 
 def vsr_resolve(view, fmt: int, map_buf, xyz, ntri: int, tri_id, vattr, nattr: int, flags: int, bary, attr,

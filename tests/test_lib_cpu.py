@@ -111,6 +111,20 @@ def test_argument_errors(vsr):
     assert vsr.vsr_strerror(vsr.VSR_E_SPACE) == "buffer too small"
 
 
+def test_noalloc_refuses_views_beyond_its_array(vsr):
+    # 2048x1088 = 34,816 tiles > 32,768: refused before any device call
+    big = synth.View(2048, 1088, 0.5, 0.5, 1.0, 180.0)
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.vsr_render_noalloc(big, 0, _FakeBuf(256, 1), _FakeBuf(512, 1), 10, _FakeBuf(1024, 1), _FakeBuf(2048, 1),
+                               stream=0)
+    assert e.value.code == vsr.VSR_E_SPACE
+    assert "32768 tiles" in vsr.vsr_last_error()
+    with pytest.raises(vsr.VsrError) as e:
+        vsr.vsr_render_noalloc(synth.View(64, 32, 0.3, 0.5, 0.9, 120.0), 0, _FakeBuf(256, 1), None, 10,
+                               _FakeBuf(1024, 1), _FakeBuf(2048, 1), stream=0)
+    assert e.value.code == vsr.VSR_E_ARG
+
+
 def test_submit_argument_errors(vsr):
     jobs = (vsr.vsr_job * 1)()
     jobs[0].view = vsr.make_view(synth.View(64, 32, 0.3, 0.5, 0.9, 120.0))
