@@ -14,6 +14,9 @@ Per-pixel flags returned by :func:`render`:
                FP32.
   FLAG_DEPTH   best and second-best covered depths differ by <= 2e-5 * r.
   FLAG_INVALID the pixel has no view direction (outside the projection).
+  FLAG_DOMAIN  the pixel lies within 1e-6 of the projection's domain edge
+               (k < 0, |sin(k*Omega/2)*R| within 1e-6 of 1): it may have a
+               direction in one precision and none in another.
 """
 from __future__ import annotations
 
@@ -31,7 +34,7 @@ _SRC = os.path.join(_HERE, "vsr_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 NO_HIT = 0xFFFFFFFF
-FLAG_EDGE, FLAG_DEPTH, FLAG_INVALID = 1, 2, 4
+FLAG_EDGE, FLAG_DEPTH, FLAG_INVALID, FLAG_DOMAIN = 1, 2, 4, 8
 
 _lock = threading.Lock()
 _lib = None

@@ -56,6 +56,7 @@
 #define ORC_FLAG_EDGE 1u    /* within the 1e-6 rad band of a competing edge */
 #define ORC_FLAG_DEPTH 2u   /* best and second-best depth within 2e-5 rel.  */
 #define ORC_FLAG_INVALID 4u /* pixel has no view direction                   */
+#define ORC_FLAG_DOMAIN 8u  /* within 1e-6 of the projection's domain edge  */
 
 /* Map generators: the Universal Perspective of section 2.1 (with the
  * Brown-Conrady distortion of section 2.3 when any coefficient is non-zero)
@@ -577,7 +578,7 @@ static void render_pixel(const orc_job *jb, int64_t q)
     if (!ok)
         f |= ORC_FLAG_INVALID;
     if (orc_domain_edge(jb->v, i, j))
-        f |= ORC_FLAG_EDGE;
+        f |= ORC_FLAG_DOMAIN;
     if (band_any || (band_min < INFINITY && (best_id == ORC_NO_HIT || band_min <= best * (1.0 + 1e-5))))
         f |= ORC_FLAG_EDGE;
     if (best_id != ORC_NO_HIT && second < INFINITY && second - best <= 2e-5 * best)

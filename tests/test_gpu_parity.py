@@ -73,7 +73,7 @@ def test_map_matches_oracle(gpu, name, view):
     if diff.any():
         js, is_ = np.nonzero(diff)
         for j, i in zip(js[:50], is_[:50]):
-            assert oracle.render(view, np.zeros((9, 0), np.float32), np.array([j * view.width + i])).flags[0] & 1
+            assert oracle.render(view, np.zeros((9, 0), np.float32), np.array([j * view.width + i])).flags[0] & oracle.FLAG_DOMAIN
     both = gok & ok
     err = _angle(g[both], ref[both])
     _say(f"[map] {name}: max angular error {err.max():.3e} rad, p99 {np.quantile(err, 0.99):.3e}")
