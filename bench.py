@@ -24,7 +24,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -181,21 +180,48 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # ---------------- measured roofline denominators (the library's own
+    # calibration kernels): streaming copy of 1 GiB, FP32 FMA chains
+    csrc_t = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    cdst_t = torch.empty_like(csrc_t)
+    cb = []
+    for rep in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        vsr.vsr_calib_copy(csrc_t, cdst_t)
+        e1.record()
+        e1.synchronize()
+        if rep:
+            cb.append(e0.elapsed_time(e1))
+    copy_gbps = 2 * csrc_t.numel() * 4 / (float(np.median(cb)) * 1e-3) / 1e9
+    del csrc_t, cdst_t
+    fma_out = torch.empty(256 * 32 * 64, dtype=torch.float32, device=dev)  # 32 waves per CU
+    fma_iters = 4096
+    cf = []
+    for rep in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        vsr.vsr_calib_fma(fma_out, fma_iters)
+        e1.record()
+        e1.synchronize()
+        if rep:
+            cf.append(e0.elapsed_time(e1))
+    fma_rate = fma_out.numel() * 8 * fma_iters / (float(np.median(cf)) * 1e-3) / 1e12
+    del fma_out
+    calib = {"hbm_GBps": copy_gbps, "hbm_sheet_GBps": PEAK_HBM / 1e9, "hbm_kernel": "k_calib_copy (1 GiB read + "
+             "1 GiB written per launch, median of 5)", "valu_T_lane_fma_per_s": fma_rate,
+             "valu_sheet_T_lane_ops_per_s": PEAK_VALU_LANE_OPS / 1e12,
+             "valu_kernel": "k_calib_fma (524,288 threads x 8 chains x 4096 FMAs, median of 5)"}
+    log(f"measured peaks: copy {copy_gbps:.0f} GB/s (sheet {PEAK_HBM / 1e9:.0f}), FP32 FMA {fma_rate:.2f} T lane-ops/s "
+        f"(sheet {PEAK_VALU_LANE_OPS / 1e12:.2f})")
+
     t0 = time.time()
     tris = synth.scene_1m()
     log(f"scene: {tris.shape[1]} triangles generated in {time.time() - t0:.1f}s")
     scene = pipeline.Scene(tris, device=dev)
     torch.cuda.synchronize()
 
-    sweep = synth.views_1080p_sweep()
-    rng = np.random.default_rng(1234)
-    views = []
-    for q in range(args.views):
-        base = sweep[q % 4]
-        yaw = 2 * math.pi * (q // 4) / max(1, args.views // 4)
-        pitch = math.asin(rng.uniform(-0.5, 0.5))
-        views.append(synth.View(base.width, base.height, base.k, base.l, base.s, base.omega_deg, base.aov,
-                                synth.yaw_pitch_rotation(yaw, pitch)))
+    views = synth.views_1080p_batch(args.views)
 
     stream = torch.cuda.current_stream()
 
@@ -266,9 +292,8 @@ def main():
     del packed
     ids_now = frame.tri_id.reshape(-1)
     winners = int(torch.unique(ids_now[ids_now != -1]).numel())
-    P = views[0].width * views[0].height
-    map_px = 12 if fmt == vsr.VSR_MAP_F32 else 4
-    resolve_bytes = P * (map_px + 4 + 4 * (3 + 5)) + winners * (36 + 3 * 5 * 4)
+    P_r = views[0].width * views[0].height
+    resolve_bytes = P_r * ((12 if fmt == vsr.VSR_MAP_F32 else 4) + 4 + 4 * (3 + 5)) + winners * (36 + 3 * 5 * 4)
     log(f"resolve (barycentrics + 5 interpolated components): packed {resolve_ms:.3f} ms "
         f"({resolve_bytes / resolve_ms / 1e6:.0f} GB/s algorithmic), from the arrays {resolve_gather_ms:.3f} ms, "
         f"packing once per scene {pack_ms:.3f} ms; {winners} distinct winners")
@@ -477,20 +502,40 @@ def main():
         scene.refresh()
         batch.submit()
     torch.cuda.synchronize()
+    # the library records four events per step between its stages (maps |
+    # binner | rasterizer), on the stream its kernels run on
+    stage_ev = [[ev() for _ in range(4)] for _ in range(args.steps)]
+    for evs in stage_ev:
+        for e in evs:
+            e.record(stream)  # creates the events before the library records them
     e_start, e_end = ev(), ev()
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     e_start.record(stream)
-    for _ in range(args.steps):
+    for k in range(args.steps):
         scene.refresh()
-        batch.submit()
+        batch.submit(events=stage_ev[k])
     e_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
     step_ms = e_start.elapsed_time(e_end) / args.steps
     views_per_s = len(views) / (step_ms / 1e3)
+    stage_map_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in stage_ev]))
+    stage_bin_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in stage_ev]))
+    stage_raster_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in stage_ev]))
     log(f"batched step (setup + {len(views)} views): {step_ms:.3f} ms -> {views_per_s:.1f} views/s "
-        f"(wall {wall:.3f}s for {args.steps} steps)")
+        f"(wall {wall:.3f}s for {args.steps} steps); stages: maps {stage_map_ms:.3f} ms, binner "
+        f"{stage_bin_ms:.3f} ms, rasterizer {stage_raster_ms:.3f} ms")
+    # outside the timed region: one view of the batch equals the plain path,
+    # bit for bit (ids and depth), at the benchmark's own size and settings
+    chk = views[5 % len(views)]
+    ref_frame = pipeline.render(scene, chk, fmt=fmt, bin_depth=depth)
+    torch.cuda.synchronize()
+    b_ids, b_dep = batch.outputs[5 % len(views)]
+    batched_equals_plain = bool(torch.equal(b_ids, ref_frame.tri_id) and
+                                torch.equal(b_dep.view(torch.int32), ref_frame.depth.view(torch.int32)))
+    log(f"batched view {5 % len(views)} == plain render: {batched_equals_plain}")
+    del ref_frame
 
     # batched without setup, and setup alone
     e0, e1 = ev(), ev()
@@ -525,6 +570,32 @@ def main():
     log(f"submit, {len(views)} distinct lenses: {dsubmit_ms:.3f} ms ({len(views) / dsubmit_ms * 1e3:.1f} views/s); "
         f"the benchmark batch shares {n_lens} lens maps")
     del dbatch
+    # the same step with 16x16 bin tiles (lists per super-tile, culled per
+    # tile by the rasterizer)
+    tbatch = pipeline.Batch([(scene, v) for v in views], fmt=fmt,
+                            mode=vsr.VSR_SUBMIT_BINNED | vsr.VSR_SUBMIT_BIN_TILE16, bin_depth=max(depth, 512))
+    tbatch.submit()
+    torch.cuda.synchronize()
+    t16_ev = [[ev() for _ in range(4)] for _ in range(args.steps)]
+    for evs in t16_ev:
+        for e in evs:
+            e.record(stream)
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    for k in range(args.steps):
+        scene.refresh()
+        tbatch.submit(events=t16_ev[k])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t16_step_ms = e0.elapsed_time(e1) / args.steps
+    t16_bin_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in t16_ev]))
+    t16_raster_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in t16_ev]))
+    t16_same = all(torch.equal(a[0], b[0]) and torch.equal(a[1].view(torch.int32), b[1].view(torch.int32))
+                   for a, b in zip(tbatch.outputs, batch.outputs))
+    log(f"batched step, 16x16 bin tiles: {t16_step_ms:.3f} ms ({len(views) / t16_step_ms * 1e3:.1f} views/s); "
+        f"binner {t16_bin_ms:.3f} ms, rasterizer {t16_raster_ms:.3f} ms; overflowed "
+        f"{vsr.vsr_bin_overflow(tbatch.workspace, True)}; images identical to 8x8 bins: {t16_same}")
+    del tbatch
     # the fused depth-sliced batch on the same views
     fbatch = pipeline.Batch([(scene, v) for v in views], fmt=fmt, mode=vsr.VSR_SUBMIT_FUSED)
     fbatch.submit()
@@ -567,17 +638,46 @@ def main():
         del sc, srv
 
     # ---------------- rooflines
-    # dominant kernel of the step: the binner (HBM-bound ideal: read every
-    # triangle's 64-byte bin record and every tile cap once, write the lists)
+    P = views[0].width * views[0].height
+    map_px = 12 if fmt == vsr.VSR_MAP_F32 else 4
+    # bytes per frame with the scene resident: map read, the raw vertices
+    # (36 B per triangle) read, ids and depth written
+    frame_bytes = map_px * P + 36 * tris.shape[1] + 8 * P
+    # dominant kernel of the headline step: the batched binner; its launch
+    # covers len(views) frames, timed live between the library's stage
+    # events over the timed steps
+    nblk_all = len(views) * (((views[0].width + 31) // 32) * ((views[0].height + 31) // 32))
+    sub_bin_kernel = ("k_submit_bin_block" if (nblk_all >= 2560 and max(64, 1 << (depth - 1).bit_length()) <= 256)
+                      else "k_submit_bin")
+    t_sb = stage_bin_ms * 1e-3
+    roofline = {"bound": "hbm", "achieved": frame_bytes * len(views) / t_sb / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "frac": frame_bytes * len(views) / t_sb / PEAK_HBM,
+                "traffic": traffic_from_profiles(sub_bin_kernel), "kernel": sub_bin_kernel,
+                "kernel_ms": stage_bin_ms, "frames_per_launch": len(views),
+                "algorithmic_bytes": frame_bytes * len(views), "bytes_per_frame": frame_bytes,
+                "measured_peak": calib["hbm_GBps"], "frac_of_measured": frame_bytes * len(views) / t_sb / 1e9 /
+                calib["hbm_GBps"]}
+    # the batched rasterizer against the VALU peak: 20 lane-ops per covered
+    # fragment of every frame of the launch
+    t_sr = stage_raster_ms * 1e-3
+    roofline_submit_raster = {"bound": "alu", "achieved": OPS_PER_FRAGMENT * F_mean * len(views) / t_sr / 1e12,
+                              "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+                              "frac": OPS_PER_FRAGMENT * F_mean * len(views) / t_sr / PEAK_VALU_LANE_OPS,
+                              "kernel": "k_submit_raster", "kernel_ms": stage_raster_ms,
+                              "fragments_per_launch": F_mean * len(views), "ops_per_fragment": OPS_PER_FRAGMENT,
+                              "measured_peak": calib["valu_T_lane_fma_per_s"],
+                              "traffic": traffic_from_profiles("k_submit_raster")}
+    # the plain path's binner (16x16 super-tiles at one 1080p view) with its
+    # own HBM ideal: read every triangle's 64-byte bin record and every tile
+    # cap once, write the lists
     t_b = float(np.mean(binl)) * 1e-3
     bin_bytes = BIN_BYTES_PER_TRI * tris.shape[1] + BIN_BYTES_PER_TILE * ntiles + 4 * float(np.mean(entries))
-    # the library's automatic shape: 32x32 blocks from 2,560 blocks up (list capacity <= 256)
     nblk = ((views[0].width + 31) // 32) * ((views[0].height + 31) // 32)
     bin_kernel = "k_bin_block" if (nblk >= 2560 and max(64, 1 << (depth - 1).bit_length()) <= 256) else "k_bin"
-    roofline = {"bound": "hbm", "achieved": bin_bytes / t_b / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": bin_bytes / t_b / PEAK_HBM, "traffic": traffic_from_profiles(bin_kernel),
-                "kernel": bin_kernel, "kernel_ms": t_b * 1e3, "algorithmic_bytes": bin_bytes,
-                "list_entries": float(np.mean(entries))}
+    roofline_plain_bin = {"bound": "hbm", "achieved": bin_bytes / t_b / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                          "frac": bin_bytes / t_b / PEAK_HBM, "traffic": traffic_from_profiles(bin_kernel),
+                          "kernel": bin_kernel, "kernel_ms": t_b * 1e3, "algorithmic_bytes": bin_bytes,
+                          "list_entries": float(np.mean(entries))}
     # the rasterizer against the VALU peak: lane-ops per covered fragment
     t_r = float(np.mean(rast)) * 1e-3
     achieved = OPS_PER_FRAGMENT * F_mean / t_r
@@ -601,14 +701,23 @@ def main():
                    "traffic": traffic_from_profiles("k_aa_raster<false>"), "kernel": "k_aa_raster",
                    "kernel_ms": t_aa * 1e3, "fragments_per_launch": F_aa_mean,
                    "ops_per_fragment": OPS_PER_AA_FRAGMENT}
-    # the whole batched step per view: covered-fragment work and frame bytes
-    per_view_s = submit_ms * 1e-3 / len(views)
-    frame_bytes = (12 if fmt == vsr.VSR_MAP_F32 else 4) * 2073600 + 68 * tris.shape[1] + 8 * 2073600
+    # the whole batched step (setup included) per view: covered-fragment
+    # work and frame bytes
+    per_view_s = step_ms * 1e-3 / len(views)
     roofline_step = {"valu_frac": OPS_PER_FRAGMENT * F_mean / per_view_s / PEAK_VALU_LANE_OPS,
-                     "hbm_frac": frame_bytes / per_view_s / PEAK_HBM, "per_view_us": per_view_s * 1e6}
+                     "hbm_frac": frame_bytes / per_view_s / PEAK_HBM, "per_view_us": per_view_s * 1e6,
+                     "valu_frac_of_measured": OPS_PER_FRAGMENT * F_mean / per_view_s / 1e12 /
+                     calib["valu_T_lane_fma_per_s"],
+                     "hbm_frac_of_measured": frame_bytes / per_view_s / 1e9 / calib["hbm_GBps"],
+                     "per_view_us_stages": {"setup": setup_ms * 1e3 / len(views),
+                                            "maps": stage_map_ms * 1e3 / len(views),
+                                            "binner": stage_bin_ms * 1e3 / len(views),
+                                            "rasterizer": stage_raster_ms * 1e3 / len(views)}}
     log(f"roofline: k_aa_raster {roofline_aa['achieved']:.2f} T lane-ops/s ({roofline_aa['frac']:.3f} of VALU)")
-    log(f"roofline: {roofline['kernel']} {roofline['achieved']:.0f} GB/s ({roofline['frac']:.3f} of HBM), k_raster "
-        f"{roofline_raster['achieved']:.2f} T lane-ops/s ({roofline_raster['frac']:.3f} of VALU), step per view "
+    log(f"roofline: {roofline['kernel']} {roofline['achieved']:.0f} GB/s ({roofline['frac']:.3f} of HBM, "
+        f"{roofline['frac_of_measured']:.3f} of the measured copy rate), k_submit_raster "
+        f"{roofline_submit_raster['achieved']:.2f} T lane-ops/s ({roofline_submit_raster['frac']:.3f} of VALU), "
+        f"plain k_raster {roofline_raster['frac']:.3f} of VALU, step per view "
         f"{roofline_step['valu_frac']:.3f} VALU / {roofline_step['hbm_frac']:.3f} HBM")
 
     # ---------------- CPU baseline: the FP64 oracle on a bounded sample
@@ -669,9 +778,16 @@ def main():
         "overflowed_tiles_plain": overflow,
         "fused_fps": 1e3 / fused_ms,
         "batched_fused_fps": len(views) / fsubmit_ms * 1e3,
+        "batched_tile16": {"fps_with_setup": len(views) / t16_step_ms * 1e3, "binner_ms": t16_bin_ms,
+                           "rasterizer_ms": t16_raster_ms, "identical_images": t16_same},
         "serving": serve_stats,
         "roofline": roofline,
+        "roofline_submit_raster": roofline_submit_raster,
+        "roofline_plain_bin": roofline_plain_bin,
         "roofline_raster": roofline_raster,
+        "measured_peaks": calib,
+        "batched_equals_plain": batched_equals_plain,
+        "stage_ms": {"maps": stage_map_ms, "binner": stage_bin_ms, "rasterizer": stage_raster_ms},
         "roofline_step": roofline_step,
         "roofline_resolve": roofline_resolve,
         "resolve_ms": resolve_ms,

@@ -73,10 +73,20 @@ extern "C" {
  * launch has at least 2560 of them, super-tiles otherwise. */
 #define VSR_BIN_BLOCKS 2u
 #define VSR_BIN_SUPERTILES 4u
+/* Bin tile edge 16 instead of 8: one list per 16x16 super-tile (2x2 tiles),
+ * of the triangles that may meet the super-tile, written once in
+ * depth-bucket order (fewer, longer lists: about half the entries at
+ * 1080p x 1M).  vsr_raster reads the tile edge from the bin buffer and
+ * keeps, for each 8x8 tile, the entries that pass the 8x8 binner's own tile
+ * test, so images are identical either way.  A list longer than bin_depth
+ * overflows as a whole super-tile.  With 16x16 lists the 32x32-block shape
+ * takes list capacities up to 1024. */
+#define VSR_BIN_TILE16 8u
 
 #define VSR_NO_HIT 0xFFFFFFFFu /* tri_id of a pixel that nothing covers */
 
-/* Edge of the square pixel tiles that maps, bins and the rasterizer use. */
+/* Edge of the square pixel tiles that maps and the rasterizer use (bins:
+ * VSR_TILE, or 16 with VSR_BIN_TILE16). */
 #define VSR_TILE 8
 
 /* One view request (host memory).
@@ -434,6 +444,16 @@ int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
 int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth, void* workspace,
                int64_t ws_bytes, void* stream);
 
+/* Instrumented vsr_submit (same work, same images) that also records the
+ * caller's HIP events (hipEvent_t passed as void*) on `stream` between its
+ * stages: events[0] before the maps, events[1] before the binner (mode
+ * VSR_SUBMIT_BINNED) or the fused kernel, events[2] before the rasterizer
+ * (binned) or after the fused kernel, events[3] after the last kernel, so
+ * that hipEventElapsedTime gives each stage's time on the stream.  nevents
+ * must be 4.  For measurement. */
+int vsr_submit_timed(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth,
+                     void* workspace, int64_t ws_bytes, void* const* events, int32_t nevents, void* stream);
+
 /* Graph-friendly batches.  A caller that replays one captured vsr_submit
  * with new view parameters (same sizes, same scenes' triangle counts) writes
  * the job table itself between replays:
@@ -448,12 +468,24 @@ int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, in
  * over the blocks of all jobs. */
 #define VSR_SUBMIT_BIN_BLOCKS 0x200
 #define VSR_SUBMIT_BIN_SUPERTILES 0x400
+/* 16x16 bin tiles for a binned submit (see VSR_BIN_TILE16). */
+#define VSR_SUBMIT_BIN_TILE16 0x800
 int64_t vsr_submit_table_bytes(int32_t njobs);
 int64_t vsr_submit_table_offset(void);
 int vsr_submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth,
                      const void* workspace, void* host_table, int64_t host_table_bytes);
 
 /* ---------------------------------------------------------- diagnostics */
+
+/* Roofline calibration (measurement only; not part of the method).
+ * vsr_calib_copy copies nbytes (a multiple of 16) from src to dst with a
+ * streaming kernel (one pass: 2 x nbytes of HBM traffic), to measure the
+ * attainable HBM bandwidth.  vsr_calib_fma runs nthreads (a multiple of
+ * 256) threads of 8 independent FP32 FMA chains of iters rounds each
+ * (nthreads x 8 x iters lane-FMAs) and writes one float per thread to
+ * out[nthreads], to measure the attainable non-packed FP32 VALU rate. */
+int vsr_calib_copy(const void* src, void* dst, int64_t nbytes, void* stream);
+int vsr_calib_fma(float* out, int64_t nthreads, int32_t iters, void* stream);
 
 /* Host call after the stream has synchronised: number of overflowed tiles
  * recorded in a bin buffer (or submit workspace).  Reads device memory with

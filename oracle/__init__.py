@@ -40,8 +40,21 @@ _lock = threading.Lock()
 _lib = None
 
 
+def build_sanitized(out: str) -> str:
+    """Compile the oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every report fatal) into ``out``; a process loads it in place of the
+    normal build when ORACLE_LIB names it (and libasan is preloaded)."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-fno-fast-math", "-Wall", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-fno-omit-frame-pointer", "-o", out, _SRC, "-lm", "-lpthread"])
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no fast-math, no FP contraction)."""
+    """Compile the oracle with gcc (-O2, no fast-math, no FP contraction).
+    With ORACLE_LIB set, that library is used as it is."""
+    if os.environ.get("ORACLE_LIB"):
+        return os.environ["ORACLE_LIB"]
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
@@ -61,9 +74,10 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            path = os.environ.get("ORACLE_LIB") or _LIB
+            if path == _LIB and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
                 build(force=True)
-            lib = ctypes.CDLL(_LIB)
+            lib = ctypes.CDLL(path)
             dp = ctypes.POINTER(ctypes.c_double)
             lib.orc_limits.argtypes = [dp, dp, dp, dp]
             lib.orc_view_coord.argtypes = [ctypes.c_int32] * 5 + [dp, dp]

@@ -1,10 +1,12 @@
-"""Autotuner: picks the batched-submit mode and bin depth per scene and
-view-size class by timing the candidates on the GPU, with a JSON cache.
+"""Autotuner: picks the batched-submit mode, bin tile size (8x8 or 16x16
+lists) and bin depth per scene and view-size class by timing the candidates
+on the GPU, with a JSON cache.
 
-The choice only affects speed: every mode and depth gives bit-identical
-images.  A (scene, size class) key is the scene's triangle count, a hash of
-a sample of its vertices and the power-of-two class of the views' mean
-pixel count.
+The choice only affects speed: every mode, tile size and depth gives
+bit-identical images.  A (scene, size class) key is the scene's triangle
+count, a hash of a sample of its vertices and the power-of-two class of the
+views' mean pixel count.  A choice is (mode, bin_depth), where mode carries
+VSR_SUBMIT_BIN_TILE16 for 16x16 bin tiles.
 """
 from __future__ import annotations
 
@@ -18,10 +20,20 @@ import torch
 
 from . import pipeline, vsr
 
+_T16 = vsr.VSR_SUBMIT_BINNED | vsr.VSR_SUBMIT_BIN_TILE16
 CANDIDATES: Tuple[Tuple[int, int], ...] = (
     (vsr.VSR_SUBMIT_BINNED, 256), (vsr.VSR_SUBMIT_BINNED, 512), (vsr.VSR_SUBMIT_BINNED, 1024),
-    (vsr.VSR_SUBMIT_BINNED, 2048), (vsr.VSR_SUBMIT_FUSED, 1024),
+    (vsr.VSR_SUBMIT_BINNED, 2048), (_T16, 256), (_T16, 512), (_T16, 1024), (_T16, 2048),
+    (vsr.VSR_SUBMIT_FUSED, 1024),
 )
+
+
+def describe(choice: Tuple[int, int]) -> dict:
+    """Readable form of a (mode, bin_depth) choice."""
+    mode, depth = choice
+    if mode & 0xFF == vsr.VSR_SUBMIT_FUSED:
+        return {"mode": "fused", "tile": 8, "bin_depth": None}
+    return {"mode": "binned", "tile": 16 if mode & vsr.VSR_SUBMIT_BIN_TILE16 else 8, "bin_depth": int(depth)}
 
 
 def scene_key(scene: pipeline.Scene) -> str:

@@ -312,7 +312,10 @@ __device__ inline void aa_tile(const AAArgs& A0, int64_t tile, int lane, float4*
         }
     };
 
-    const uint32_t count = __builtin_amdgcn_readfirstlane(counts[tile]);  // uniform: scalar loop bounds
+    // 16x16 bin tiles (VSR_BIN_TILE16) are not read here: every tile then
+    // gathers its own candidates, as an overflowed one does
+    const bool b16 = reinterpret_cast<const uint32_t*>(bb)[kBinHdrTile] == 16u;
+    const uint32_t count = b16 ? uint32_t(A.depth) + 1u : __builtin_amdgcn_readfirstlane(counts[tile]);
     if (count <= uint32_t(A.depth)) {
         const uint32_t* lst = lists + tile * A.depth;
         const uint32_t sub = uint32_t(lane) >> 3, part = uint32_t(lane) & 7u;

@@ -8,6 +8,7 @@
 
 #include "aa.hpp"
 #include "bin.hpp"
+#include "calib.hpp"
 #include "fused.hpp"
 #include "map.hpp"
 #include "raster.hpp"
@@ -547,7 +548,7 @@ int vsr_resolve_packed(const vsr_view* v, int32_t fmt, const void* map, const vo
 int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth) {
     if (!jobs || njobs < 1 || njobs > 4096) return VSR_E_ARG;
     if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return VSR_E_ARG;
-    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES);
+    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES | VSR_SUBMIT_BIN_TILE16);
     if (mode != VSR_SUBMIT_BINNED && mode != VSR_SUBMIT_FUSED) return VSR_E_ARG;
     if (mode == VSR_SUBMIT_BINNED && (bin_depth < 1 || bin_depth > kMaxDepth)) return VSR_E_ARG;
     for (int32_t q = 0; q < njobs; ++q) {
@@ -569,7 +570,7 @@ int vsr_submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mo
     if (!jobs || njobs < 1 || njobs > 4096) return fail(VSR_E_ARG, "njobs %d outside 1..4096", njobs);
     if (!workspace || !aligned(workspace) || !host_table) return fail(VSR_E_ARG, "NULL or misaligned buffer");
     if (host_table_bytes < submit_table_bytes(njobs)) return fail(VSR_E_SPACE, "host table too small");
-    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES);
+    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES | VSR_SUBMIT_BIN_TILE16);
     for (int32_t q = 0; q < njobs; ++q) {
         MapParams P;
         int rc = make_map_params(&jobs[q].view, fmt, 0, &P, nullptr);
@@ -579,15 +580,16 @@ int vsr_submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mo
     return VSR_OK;
 }
 
-int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth, void* workspace,
-               int64_t ws_bytes, void* stream) {
+static int submit_common(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth,
+                         void* workspace, int64_t ws_bytes, hipEvent_t* ev, void* stream, const char* what) {
     const bool table_ready = (mode & VSR_SUBMIT_TABLE_READY) != 0;
     uint32_t shape = 0;
     if (mode & VSR_SUBMIT_BIN_BLOCKS) shape |= VSR_BIN_BLOCKS;
     if (mode & VSR_SUBMIT_BIN_SUPERTILES) shape |= VSR_BIN_SUPERTILES;
+    if (mode & VSR_SUBMIT_BIN_TILE16) shape |= VSR_BIN_TILE16;
     if (shape == (VSR_BIN_BLOCKS | VSR_BIN_SUPERTILES))
         return fail(VSR_E_ARG, "VSR_SUBMIT_BIN_BLOCKS and VSR_SUBMIT_BIN_SUPERTILES together");
-    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES);
+    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES | VSR_SUBMIT_BIN_TILE16);
     if (!jobs || njobs < 1 || njobs > 4096) return fail(VSR_E_ARG, "njobs %d outside 1..4096", njobs);
     if (mode != VSR_SUBMIT_BINNED && mode != VSR_SUBMIT_FUSED) return fail(VSR_E_ARG, "unknown submit mode %d", mode);
     if (mode == VSR_SUBMIT_BINNED && (bin_depth < 1 || bin_depth > kMaxDepth))
@@ -606,8 +608,38 @@ int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, in
     int64_t need = submit_bytes(jobs, njobs, fmt, mode, bin_depth);
     if (ws_bytes < need) return fail(VSR_E_SPACE, "workspace %lld < %lld bytes", (long long)ws_bytes, (long long)need);
     return hip_status(
-        launch_submit(jobs, njobs, fmt, mode, bin_depth, workspace, table_ready, shape, hipStream_t(stream)),
-                      "vsr_submit");
+        launch_submit(jobs, njobs, fmt, mode, bin_depth, workspace, table_ready, shape, hipStream_t(stream), ev),
+                      what);
+}
+
+int vsr_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth, void* workspace,
+               int64_t ws_bytes, void* stream) {
+    return submit_common(jobs, njobs, fmt, mode, bin_depth, workspace, ws_bytes, nullptr, stream, "vsr_submit");
+}
+
+int vsr_submit_timed(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth,
+                     void* workspace, int64_t ws_bytes, void* const* events, int32_t nevents, void* stream) {
+    if (!events || nevents != 4) return fail(VSR_E_ARG, "vsr_submit_timed needs 4 events, got %d", nevents);
+    hipEvent_t ev[4];
+    for (int q = 0; q < 4; ++q) {
+        if (!events[q]) return fail(VSR_E_ARG, "event %d is NULL", q);
+        ev[q] = reinterpret_cast<hipEvent_t>(events[q]);
+    }
+    return submit_common(jobs, njobs, fmt, mode, bin_depth, workspace, ws_bytes, ev, stream, "vsr_submit_timed");
+}
+
+int vsr_calib_copy(const void* src, void* dst, int64_t nbytes, void* stream) {
+    if (!src || !dst || !aligned(src) || !aligned(dst)) return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if (nbytes < 16 || (nbytes & 15)) return fail(VSR_E_ARG, "nbytes %lld not a positive multiple of 16", (long long)nbytes);
+    return hip_status(launch_calib_copy(src, dst, nbytes, hipStream_t(stream)), "vsr_calib_copy");
+}
+
+int vsr_calib_fma(float* out, int64_t nthreads, int32_t iters, void* stream) {
+    if (!out || (reinterpret_cast<uintptr_t>(out) & 3u)) return fail(VSR_E_ARG, "NULL or misaligned buffer");
+    if (nthreads < 256 || (nthreads & 255) || nthreads / 256 > 0x7FFFFFFF)
+        return fail(VSR_E_ARG, "nthreads %lld not a positive multiple of 256", (long long)nthreads);
+    if (iters < 1) return fail(VSR_E_ARG, "iters %d < 1", iters);
+    return hip_status(launch_calib_fma(out, nthreads, iters, hipStream_t(stream)), "vsr_calib_fma");
 }
 
 int vsr_bin_overflow(const void* bins_or_ws, int32_t is_workspace, int64_t* overflowed_tiles) {

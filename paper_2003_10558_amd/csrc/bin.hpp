@@ -13,6 +13,12 @@
 //              wave w owns tile w), for deep lists.
 // bin_super appends survivors to LDS lists and each wave writes its tile's
 // list with a counting sort by depth bucket.
+//
+// With 16x16 bin tiles (BinArgs::tile16) there is one list per super-tile:
+// the survivors that may meet the super-tile (its cap and edge planes,
+// quad_may_see), appended to LDS and written once, in depth-bucket order.
+// The rasterizer then keeps, for each 8x8 tile, the entries that pass the
+// 8x8 binner's own tile test, so each tile sees exactly that binner's list.
 #pragma once
 #include "gather.hpp"
 
@@ -23,6 +29,7 @@ struct BinArgs {
     int64_t ntiles;
     int32_t fmt, depth, lds_cap, all;
     int32_t ntx, nty;
+    int32_t tile16, pad;  // tile16: one list per 16x16 super-tile instead of per 8x8 tile
     const void* setup;
     int64_t n;
     void* bins;
@@ -108,6 +115,64 @@ __device__ inline void bin_super(const BinArgs& A0, int64_t sidx) {
 __global__ __launch_bounds__(256) void k_bin(BinArgs A) {
     const int64_t nsx = (A.ntx + 1) / 2;  // super-tiles per row
     bin_super(A, band_remap(blockIdx.x, gridDim.x, max(int64_t(1), nsx * kBandPx / (2 * kTile))));
+}
+
+// quad_may_see is defined with the 32x32 blocks below.
+__device__ inline bool quad_may_see(float4 s0, float4 s1, float4 a, float ch_t, float3 n0, float3 n1, float3 n2);
+
+// One 16x16 bin tile per workgroup: the gather survivors that may meet the
+// super-tile go to one LDS list, which wave 0 writes in depth-bucket order.
+__device__ inline void bin_super16(const BinArgs& A0, int64_t sidx) {
+    BinArgs A = A0;
+    A.globalize();
+    extern __shared__ uint32_t lists[];  // lds_cap
+    __shared__ SuperShared sh;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int64_t tile;
+    int tx, ty;
+    const bool present = super_tile_of(sidx, w, A.ntx, A.nty, tile, tx, ty);
+    super_setup(sh, map_caps(A.map, A.ntiles, A.fmt), map_sups(A.map, A.ntiles, A.fmt), A.rot,
+                scene_view(A.setup, A.n).face_count, present, tile, sidx);
+    const bool any = sh.sup[1].z != 0.0f;
+    const SceneView S = scene_view(A.setup, A.n);
+    const uint32_t lcap = uint32_t(A.lds_cap);
+    auto append = [&](uint32_t rank) {
+        const uint32_t pos = atomicAdd(&sh.cnt[0], 1u);
+        if (pos < lcap) lists[pos] = rank;
+    };
+    if (any && A.all) {
+        for (int64_t k0 = 0; k0 < A.n; k0 += 256) {
+            int64_t r = k0 + tid;
+            if (r < A.n && S.cap[2 * r + 1].z != kCapEmpty) append(uint32_t(r));
+        }
+    } else if (any) {
+        const float4 s0 = sh.sup[0], s1 = sh.sup[1];
+        gather_slices(sh, S, 0, kSlices, [&](const uint32_t* chunk, uint32_t n) {
+            const bool valid = uint32_t(threadIdx.x) < n;
+            visit_record(S, valid, valid ? chunk[threadIdx.x] : 0u,
+                         [&](bool v, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t rank) {
+                             if (v && quad_may_see(s0, s1, a, ch_t, n0, n1, n2)) append(rank);
+                         });
+        }, [] {});
+    }
+    __syncthreads();
+    if (w == 0) {
+        const uint32_t cnt = sh.cnt[0];
+        const bool keep = cnt <= uint32_t(A.depth);
+        char* bb = reinterpret_cast<char*>(A.bins);
+        uint32_t* out = reinterpret_cast<uint32_t*>(bb + 256 + align256(A.ntiles * 4)) + sidx * A.depth;
+        if (keep) bucket_sort_wave(lists, cnt, sh.bk[0], bucket_shift(A.n), out);
+        if (lane == 0) {
+            reinterpret_cast<uint32_t*>(bb + 256)[sidx] = cnt;
+            if (!keep) atomicAdd(A.status, 1u);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bin16(BinArgs A) {
+    const int64_t nsx = (A.ntx + 1) / 2;
+    bin_super16(A, band_remap(blockIdx.x, gridDim.x, max(int64_t(1), nsx * kBandPx / (2 * kTile))));
 }
 
 // ------------------------------------------------ 32x32 blocks ----------
@@ -340,6 +405,86 @@ __device__ inline void bin_block(const BinArgs& A0, int64_t b) {
 
 __global__ __launch_bounds__(256) void k_bin_block(BinArgs A) { bin_block(A, xcd_remap(blockIdx.x, gridDim.x)); }
 
+struct Block16Shared {
+    SuperShared g;      // gathering state; g.sup = block cap
+    float4 qcap[4][2];  // quadrant (super-tile) caps, super-tile layout
+    uint32_t qn[4];     // entries appended to quadrant q's list
+};
+
+// 16x16 bin tiles from 32x32 blocks: the block cap gathers the candidates
+// once; every survivor is tested against the four quadrant (super-tile)
+// caps and appended to the LDS list of each quadrant it may meet; at the
+// end wave w writes quadrant w's list once, in depth-bucket order.
+__device__ inline void bin_block16(const BinArgs& A0, int64_t b) {
+    BinArgs A = A0;
+    A.globalize();
+    extern __shared__ uint32_t qlist[];  // 4 x lds_cap
+    __shared__ Block16Shared sh;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const SceneView S = scene_view(A.setup, A.n);
+    const uint32_t lcap = uint32_t(A.lds_cap);
+    const int nsx = (A.ntx + 1) / 2, nsy = (A.nty + 1) / 2, nbx = (A.ntx + 3) / 4;
+    if (tid < 4) {
+        const int q = tid;
+        const int sx = 2 * int(b % nbx) + (q & 1), sy = 2 * int(b / nbx) + (q >> 1);
+        float4 s0 = make_float4(0.f, 0.f, 1.f, 1.f), s1 = make_float4(1.f, 0.f, 0.f, 0.f);  // no pixel
+        if (sx < nsx && sy < nsy) load_tile_cap(map_sups(A.map, A.ntiles, A.fmt), int64_t(sy) * nsx + sx, A.rot, s0, s1);
+        sh.qcap[q][0] = s0;
+        sh.qcap[q][1] = s1;
+        sh.qn[q] = 0;
+    } else if (tid == 4) {
+        float4 s0, s1;
+        load_tile_cap(map_blks(A.map, A.ntiles, A.fmt, A.ntx, A.nty), b, A.rot, s0, s1);
+        sh.g.sup[0] = s0;
+        sh.g.sup[1] = s1;
+    }
+    for (int q = tid; q < kSlices * 64; q += 256) sh.g.fc[q] = S.face_count[q];
+    __syncthreads();
+    setup_rects(sh.g);
+    const bool any = sh.g.sup[1].z != 0.0f;
+    auto append = [&](int q, uint32_t rank) {
+        const uint32_t pos = atomicAdd(&sh.qn[q], 1u);
+        if (pos < lcap) qlist[q * lcap + pos] = rank;
+    };
+    if (any && A.all) {
+        for (int64_t k0 = 0; k0 < A.n; k0 += 256) {
+            int64_t r = k0 + tid;
+            if (r < A.n && S.cap[2 * r + 1].z != kCapEmpty)
+                for (int q = 0; q < 4; ++q)
+                    if (sh.qcap[q][1].z != 0.0f) append(q, uint32_t(r));
+        }
+    } else if (any) {
+        gather_slices(sh.g, S, 0, kSlices, [&](const uint32_t* chunk, uint32_t n) {
+            if (uint32_t(tid) < n) {
+                visit_record(S, true, chunk[tid],
+                             [&](bool, float4 a, float ch_t, float3 n0, float3 n1, float3 n2, uint32_t rank) {
+#pragma unroll
+                                 for (int q = 0; q < 4; ++q)
+                                     if (quad_may_see(sh.qcap[q][0], sh.qcap[q][1], a, ch_t, n0, n1, n2))
+                                         append(q, rank);
+                             });
+            }
+        }, [] {});
+    }
+    __syncthreads();
+    const int sx = 2 * int(b % nbx) + (w & 1), sy = 2 * int(b / nbx) + (w >> 1);
+    if (sx < nsx && sy < nsy) {
+        const int64_t sidx = int64_t(sy) * nsx + sx;
+        const uint32_t cnt = sh.qn[w];
+        const bool keep = cnt <= uint32_t(A.depth);
+        char* bb = reinterpret_cast<char*>(A.bins);
+        uint32_t* out = reinterpret_cast<uint32_t*>(bb + 256 + align256(A.ntiles * 4)) + sidx * A.depth;
+        if (keep) bucket_sort_wave(qlist + w * lcap, cnt, sh.g.bk[w], bucket_shift(A.n), out);
+        if (lane == 0) {
+            reinterpret_cast<uint32_t*>(bb + 256)[sidx] = cnt;
+            if (!keep) atomicAdd(A.status, 1u);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bin_block16(BinArgs A) { bin_block16(A, xcd_remap(blockIdx.x, gridDim.x)); }
+
 // Automatic binner shape: 32x32 blocks for list capacities up to
 // kBlockMaxCap and launches of at least kBlockMinGrid blocks.  Below that a
 // block's longer candidate stream leaves the chip under-filled (the slowest
@@ -349,10 +494,12 @@ __global__ __launch_bounds__(256) void k_bin_block(BinArgs A) { bin_block(A, xcd
 // whose polar blocks gather far more, takes 1.35x), blocks take 0.81x the
 // super-tiles' time at 2560x1440 and 0.67x at 3840x2160.
 constexpr int32_t kBlockMaxCap = 256;
+constexpr int32_t kBlock16MaxCap = 1024;  // four LDS lists of this many entries
 constexpr int64_t kBlockMinGrid = 2560;
 
-inline bool use_blocks(int32_t lds_cap, int64_t nblk, uint32_t flags) {
-    if (lds_cap > kBlockMaxCap) return false;  // blocks sort lists of at most 256 in registers
+inline bool use_blocks(int32_t lds_cap, int64_t nblk, uint32_t flags, bool tile16 = false) {
+    // 8x8 lists: blocks sort lists of at most 256 in registers
+    if (lds_cap > (tile16 ? kBlock16MaxCap : kBlockMaxCap)) return false;
     if (flags & VSR_BIN_BLOCKS) return true;
     if (flags & VSR_BIN_SUPERTILES) return false;
     return nblk >= kBlockMinGrid;
@@ -361,6 +508,13 @@ inline bool use_blocks(int32_t lds_cap, int64_t nblk, uint32_t flags) {
 __global__ __launch_bounds__(64) void k_zero_u32(uint32_t* p, int64_t n) {
     int64_t i = int64_t(blockIdx.x) * 64 + threadIdx.x;
     if (i < n) p[i] = 0u;
+}
+
+// Status header of a bin buffer: word 0 counts overflowed lists, word 1
+// records the bin tile edge (8 or 16) for the rasterizer.
+constexpr int kBinHdrTile = 1;
+__global__ __launch_bounds__(64) void k_bins_header(uint32_t* hdr, uint32_t tile) {
+    hdr[threadIdx.x] = threadIdx.x == kBinHdrTile ? tile : 0u;
 }
 
 inline int32_t bin_lds_cap(int32_t depth) {
@@ -388,12 +542,22 @@ hipError_t launch_bin(const void* map, int32_t W, int32_t H, int32_t fmt, const 
     A.bins = bins;
     A.status = reinterpret_cast<uint32_t*>(bins);
     A.rot = R;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(bins), int64_t(64));
-    if (use_blocks(A.lds_cap, ML.nblk, flags))
+    A.tile16 = (flags & VSR_BIN_TILE16) ? 1 : 0;
+    A.pad = 0;
+    hipLaunchKernelGGL(k_bins_header, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(bins),
+                       uint32_t(A.tile16 ? 16 : 8));
+    if (A.tile16) {
+        if (use_blocks(A.lds_cap, ML.nblk, flags, true))
+            hipLaunchKernelGGL(k_bin_block16, dim3(unsigned(ML.nblk)), dim3(256), size_t(4) * A.lds_cap * 4, st, A);
+        else
+            hipLaunchKernelGGL(k_bin16, dim3(unsigned(bin_grid(ML.ntx, ML.nty))), dim3(256), size_t(A.lds_cap) * 4,
+                               st, A);
+    } else if (use_blocks(A.lds_cap, ML.nblk, flags)) {
         hipLaunchKernelGGL(k_bin_block, dim3(unsigned(ML.nblk)), dim3(256), 0, st, A);
-    else
+    } else {
         hipLaunchKernelGGL(k_bin, dim3(unsigned(bin_grid(ML.ntx, ML.nty))), dim3(256),
                            size_t(kSupTiles) * A.lds_cap * 4, st, A);
+    }
     return hipGetLastError();
 }
 

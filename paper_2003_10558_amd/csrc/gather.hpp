@@ -54,31 +54,39 @@ __device__ inline SceneView scene_view(const void* setup, int64_t n) {
 // lies on the plane through O on which p_u = u p_a; the centre is then within
 // alpha of that plane, |cu - u ca| <= sa sqrt(1 + u^2), i.e.
 //   f(u) = (ca^2 - sa^2) u^2 - 2 ca cu u + cu^2 - sa^2 <= 0.
-// The hull of {u in [-1, 1] : f(u) <= 0}, evaluated in FP64 so that rounding
-// stays far below the cap margins; false when empty.
-__device__ inline bool axis_range(float ca_f, float cu_f, float sa_f, float& lo, float& hi) {
-    const double ca = ca_f, cu = cu_f, sa = sa_f;
-    const double den = ca * ca - sa * sa;
-    const double disc = ca * ca + cu * cu - sa * sa;  // discriminant of f / (4 sa^2)
-    double a = -1.0, b = 1.0;
-    if (disc > 0.0 && fabs(den) > 1e-8) {
-        const double root = sa * sqrt(disc), mid = ca * cu;
-        double r1 = (mid - root) / den, r2 = (mid + root) / den;
-        if (den > 0.0) {  // f <= 0 between the roots r1 <= r2
-            a = fmax(r1 - 1e-7 * (1.0 + fabs(r1)), -1.0);
-            b = fmin(r2 + 1e-7 * (1.0 + fabs(r2)), 1.0);
+// The hull of {u in [-1, 1] : f(u) <= 0} in FP32, each root widened by a
+// bound on its rounding error (u = 2^-24; den = ca^2 - sa^2 and
+// disc = ca^2 + cu^2 - sa^2 carry at most 3u (ca^2 + sa^2) and 9u, the
+// numerator mid +- root 2u (|mid| + root) plus the square root's
+// 9u sa / (2 sqrt(disc)); four times their effect on r = (mid +- root)/den,
+// plus 1e-6 (1 + |r|)); the full range when |den| < 1e-5 or the roots
+// are not real; false when empty.
+__device__ inline bool axis_range(float ca, float cu, float sa, float& lo, float& hi) {
+    const float den = ca * ca - sa * sa;
+    const float disc = ca * ca + cu * cu - sa * sa;  // discriminant of f / (4 sa^2)
+    float a = -1.0f, b = 1.0f;
+    if (disc > 0.0f && fabsf(den) > 1e-5f) {
+        const float sq = sqrtf(disc);
+        const float root = sa * sq, mid = ca * cu;
+        const float r1 = (mid - root) / den, r2 = (mid + root) / den;
+        const float ad = fabsf(den), w2 = ca * ca + sa * sa;
+        const float e0 = (8.0f * kUlp * (fabsf(mid) + root) + 20.0f * kUlp * sa / sq) / ad;
+        const float m1 = e0 + 12.0f * kUlp * fabsf(r1) * w2 / ad + 1e-6f * (1.0f + fabsf(r1));
+        const float m2 = e0 + 12.0f * kUlp * fabsf(r2) * w2 / ad + 1e-6f * (1.0f + fabsf(r2));
+        if (den > 0.0f) {  // f <= 0 between the roots r1 <= r2
+            a = fmaxf(r1 - m1, -1.0f);
+            b = fminf(r2 + m2, 1.0f);
             if (a > b) return false;
         } else {  // f <= 0 outside (r2, r1)
-            r2 += 1e-7 * (1.0 + fabs(r2));
-            r1 -= 1e-7 * (1.0 + fabs(r1));
-            const bool left = r2 >= -1.0, right = r1 <= 1.0;
+            const float hi2 = r2 + m2, lo1 = r1 - m1;
+            const bool left = hi2 >= -1.0f, right = lo1 <= 1.0f;
             if (!left && !right) return false;
-            if (!right) b = fmin(r2, 1.0);
-            if (!left) a = fmax(r1, -1.0);
+            if (!right) b = fminf(hi2, 1.0f);
+            if (!left) a = fmaxf(lo1, -1.0f);
         }
     }
-    lo = float(a);
-    hi = float(b);
+    lo = a;
+    hi = b;
     return true;
 }
 

@@ -30,6 +30,7 @@ struct RasterArgs {
     float* out_depth;
     unsigned long long* stats;  // instrumented variant only: tests, covered, triangles, tiles
     int32_t no_early_exit;      // instrumented variant only: process whole lists
+    int32_t bin_tile;           // 8 or 16: edge of the bin tiles; 0: read it from the bin buffer's header
     Rot rot;                    // camera -> world
 
     __device__ inline void globalize() {
@@ -124,6 +125,69 @@ __device__ inline bool raster_list(const uint32_t* lst, uint32_t count, const fl
     return done;
 }
 
+// Rasterizes the entries of a 16x16 bin tile's list that may meet this 8x8
+// tile.  Lane l takes entry l of each 64-entry chunk, loads its cap and
+// record and keeps it when sub_may_see passes for the tile's cap (the test
+// the 8x8 binner applies, on the same binning cap and normals, so the
+// survivors are that binner's list for the tile, in the same depth-bucket
+// order); the survivors' records are compacted into LDS (stg: 256 float4)
+// and tested as in raster_list, with the same early exit.
+template <bool kStats>
+__device__ inline void raster_list_cull(const uint32_t* lst, uint32_t count, const SceneView& S, float4 tc0,
+                                        float4 tc1, float3 g, bool has_dir, uint64_t& best, float4* stg,
+                                        bool early_exit, unsigned long long& n_tri, unsigned long long& n_cov) {
+    const int lane = threadIdx.x & 63;
+    bool done = false;
+    for (uint32_t c0 = 0; c0 < count && !done; c0 += 64) {
+        const uint32_t e = c0 + uint32_t(lane);
+        const bool valid = e < count;
+        const uint32_t rank = valid ? lst[e] : lst[c0];
+        const float4 cp0 = S.cap[2 * int64_t(rank)], cp1 = S.cap[2 * int64_t(rank) + 1];
+        const float4* r = S.rec + 4 * int64_t(rank);
+        const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+        const float4 a = make_float4(cp0.x, cp0.y, cp0.z, (cp1.z == kCapWide) ? kBinWide : cp0.w);
+        const bool pass = valid && sub_may_see(tc0, tc1, a, bin_cos_half(a), f3(r0.x, r0.y, r0.z),
+                                               f3(r1.x, r1.y, r1.z), f3(r2.x, r2.y, r2.z));
+        const uint64_t bal = __ballot(pass);
+        const uint32_t ns = uint32_t(__popcll(bal));
+        if (pass) {
+            const uint32_t pos =
+                __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
+            stg[4 * pos] = r0;
+            stg[4 * pos + 1] = r1;
+            stg[4 * pos + 2] = r2;
+            stg[4 * pos + 3] = r3;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t t8 = 0; t8 < ns; t8 += 4) {
+            if (early_exit) {
+                const float lb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(stg[4 * t8 + 3].w)));
+                const bool below = !has_dir || __uint_as_float(uint32_t(best >> 32)) < lb;
+                if (__ballot(!below) == 0) {
+                    done = true;
+                    break;
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t t = t8 + u;
+                if (t < ns) {
+                    float4 c0v = stg[4 * t], c1v = stg[4 * t + 1], c2v = stg[4 * t + 2], c3v = stg[4 * t + 3];
+                    bool cov = raster_rec(c0v, c1v, c2v, c3v, g, best);
+                    if (kStats) {
+                        n_tri += 1;
+                        n_cov += __popcll(__ballot(cov));
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 template <bool kStats>
 __device__ inline void raster_tile(const RasterArgs& A0, int64_t tile, int lane) {
     RasterArgs A = A0;
@@ -140,10 +204,18 @@ __device__ inline void raster_tile(const RasterArgs& A0, int64_t tile, int lane)
     float3 g = load_dir(A.map, A.fmt, A.ntiles, tile, lane, A.rot);
     bool has_dir = inside && (g.x != 0.0f || g.y != 0.0f || g.z != 0.0f);
     uint64_t best = kKeyEmpty;
-    const uint32_t count = __builtin_amdgcn_readfirstlane(counts[tile]);  // uniform: scalar loop bounds
+    // bin tile edge: from the bin buffer's header unless the caller gives it
+    const bool b16 = A.bin_tile == 16 || (A.bin_tile == 0 && reinterpret_cast<const uint32_t*>(bb)[kBinHdrTile] == 16u);
+    const int64_t list_idx = b16 ? int64_t(ty >> 1) * ((A.ntx + 1) >> 1) + (tx >> 1) : tile;
+    const uint32_t count = __builtin_amdgcn_readfirstlane(counts[list_idx]);  // uniform: scalar loop bounds
     unsigned long long n_tri = 0, n_cov = 0;
-    if (count <= uint32_t(A.depth)) {
-        __shared__ float4 s_stage[4][64];
+    __shared__ float4 s_stage[4][256];
+    if (count <= uint32_t(A.depth) && b16) {
+        float4 tc0, tc1;
+        load_tile_cap(caps, tile, A.rot, tc0, tc1);
+        raster_list_cull<kStats>(lists + list_idx * A.depth, count, S, tc0, tc1, g, has_dir, best,
+                                 s_stage[threadIdx.x >> 6], !(kStats && A.no_early_exit), n_tri, n_cov);
+    } else if (count <= uint32_t(A.depth)) {
         raster_list<kStats>(lists + tile * A.depth, count, S.rec, g, has_dir, best, s_stage[threadIdx.x >> 6],
                             !(kStats && A.no_early_exit), n_tri, n_cov);
     } else {
@@ -207,6 +279,7 @@ hipError_t launch_raster(const void* map, int32_t W, int32_t H, int32_t fmt, con
     A.out_depth = out_depth;
     A.stats = stats;
     A.no_early_exit = no_early_exit;
+    A.bin_tile = 0;
     A.rot = R;
     int64_t blocks = (ML.ntiles + 3) / 4;
     if (stats) {

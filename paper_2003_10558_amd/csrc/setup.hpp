@@ -69,90 +69,91 @@ __device__ inline uint32_t cell_of(float3 s, int L) {
 // (r = d / (G.N) >= d), but for a triangle seen at an angle the rays that
 // cover it meet its plane much further out: r >= d / cos(theta), theta the
 // angle from the plane normal to the nearest direction of the triangle's
-// cone.  Evaluated in FP64 from the values the rasterizer uses:
-//   - covered directions satisfy the stored FP32 edge tests, so they lie in
-//     the exact vertex cone dilated by eta_i per edge (the stored normal's
-//     deviation from the exact one plus the FP32 dot-product rounding, 8
-//     ulp); near a corner of angle alpha the dilation reaches
-//     eta / sin(alpha / 2), doubled for margin;
-//   - the FP32 depth d * rcp(G.N) is at least (1 - 3 ulp) r / (1 + 8 ulp r/d)
-//     (G.N carries at most 8 ulp of absolute rounding, |G| <= 1 + 2e-6);
-// and the result is widened by 1e-5 and rounded down to FP32.  Never below
-// the plane-distance bound d (1 - 2^-16).
-__device__ inline double dnorm3(double x, double y, double z) { return sqrt(x * x + y * y + z * z); }
-
-struct D3 {
-    double x, y, z;
-};
-__device__ inline D3 d3(float3 v) { return D3{double(v.x), double(v.y), double(v.z)}; }
-__device__ inline D3 dsub(D3 a, D3 b) { return D3{a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ inline D3 dscale(D3 a, double s) { return D3{a.x * s, a.y * s, a.z * s}; }
-__device__ inline double ddot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ inline D3 dcross(D3 a, D3 b) { return D3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
-__device__ inline double dlen(D3 a) { return dnorm3(a.x, a.y, a.z); }
-__device__ inline D3 dunit(D3 a) { return dscale(a, 1.0 / dlen(a)); }
-
-// Angle from unit p to the minor arc between unit directions u and v.
-__device__ inline double arc_distance(D3 p, D3 u, D3 v) {
-    D3 n = dcross(u, v);
-    const double ln = dlen(n);
-    double best = fmin(acos(fmin(1.0, fmax(-1.0, ddot(p, u)))), acos(fmin(1.0, fmax(-1.0, ddot(p, v)))));
-    if (ln > 0.0) {
-        n = dscale(n, 1.0 / ln);
-        const double sp = ddot(p, n);
-        const D3 q = dsub(p, dscale(n, sp));  // projection onto the arc's great circle
-        if (ddot(dcross(u, q), n) >= 0.0 && ddot(dcross(q, v), n) >= 0.0)
-            best = fmin(best, asin(fmin(1.0, fabs(sp))));
-    }
-    return best;
-}
-
+// cone.  Evaluated in FP32 from the values the rasterizer uses, with every
+// rounding bounded and added on the safe side (u = 2^-24):
+//   - a stored edge normal n_i = P x (Q - P), rounded and normalised in FP32,
+//     deviates from the exact unit normal of the cone's edge by at most
+//     (5.25 K + 4) u rad, K = max(|P|, |Q|) |Q - P| / |P x Q| (one rounding
+//     of Q - P, three per cross-product component, four for the
+//     normalisation); with the FP32 rounding of the rasterizer's n_i . G
+//     (8 u) each edge is trusted to eta = (16 K + 32) u, twice that sum;
+//   - covered directions then lie in the cone dilated by eta per edge,
+//     which near a corner of angle alpha reaches eta / sin(alpha/2),
+//     doubled: eta_c = 2 eta / s_min, with sin(alpha/2) bounded below both
+//     from the cosine, sqrt((1 - cos alpha)/2), and from the sine,
+//     sin(alpha)/2, of the two stored normals that meet there;
+//   - cos(theta) is bounded above without angles: the largest of u.v over
+//     the vertex directions v and, for each edge whose great circle has the
+//     projection of u inside the edge (tested with a 1e-5 allowance, so a
+//     borderline edge is counted: its value never falls below the true
+//     maximum), sqrt(1 - (u.n_i)^2); plus eta (the edge planes' error),
+//     eta_c (the dilation: cos(theta - eta_c) <= cos(theta) + eta_c) and
+//     4e-6 for the rounding of these dots, clamped to [cos 1.5, 1];
+//   - the FP32 depth d * rcp(G.N) is at least (1 - 3u) r / (1 + 8u r/d)
+//     (G.N carries at most 8u of absolute rounding, |G| <= 1 + 2e-6);
+// the result is widened by 1e-5 and by 16u for its own rounding.  Never
+// below the plane-distance bound d (1 - 2^-16), which is also returned when
+// an edge is too ill-conditioned (K u > 1e-3) or a corner too sharp
+// (sin(alpha/2) <= 1e-4) for the bound to say more.
 __device__ inline float depth_lb(float3 A, float3 B, float3 C, float4 r0, float4 r1, float4 r2, float dist,
                                  float sigma) {
     const float base = dist * (1.0f - 1.0f / 65536.0f);
-    const double eps = 1.0 / 16777216.0;
-    const D3 a = dunit(d3(A)), b = dunit(d3(B)), c = dunit(d3(C));
-    // exact unit edge normals of the vertex cone, oriented inward
-    const D3 stored[3] = {D3{r0.x, r0.y, r0.z}, D3{r1.x, r1.y, r1.z}, D3{r2.x, r2.y, r2.z}};
-    const D3 ex[3] = {dcross(d3(A), d3(B)), dcross(d3(B), d3(C)), dcross(d3(C), d3(A))};
-    double eta = 0.0;
+    const float3 V[3] = {A, B, C};
+    const float3 nrm[3] = {f3(r0.x, r0.y, r0.z), f3(r1.x, r1.y, r1.z), f3(r2.x, r2.y, r2.z)};
+    float eta = 0.0f;
     for (int i = 0; i < 3; ++i) {
-        const double l = dlen(ex[i]);
-        if (!(l > 0.0)) return base;
-        const D3 e = dscale(ex[i], double(sigma) / l);
-        eta = fmax(eta, dlen(dsub(stored[i], e)) + 8.0 * eps * (1.0 + dlen(stored[i])));
+        const float3 P = V[i], Q = V[(i + 1) % 3];
+        const float3 D = sub3(Q, P);
+        const float3 X = cross3(P, D);
+        const float lx = sqrtf(dot3(X, X));
+        if (!(lx > 0.0f)) return base;
+        const float K = fmaxf(sqrtf(dot3(P, P)), sqrtf(dot3(Q, Q))) * sqrtf(dot3(D, D)) / lx;
+        if (!(K * kUlp < 1e-3f)) return base;
+        eta = fmaxf(eta, (16.0f * K + 32.0f) * kUlp);
     }
-    // smallest spherical angle of the triangle
-    const D3 v[3] = {a, b, c};
-    double smin = 1.0;
-    for (int i = 0; i < 3; ++i) {
-        const D3 p = v[i], q = v[(i + 1) % 3], r = v[(i + 2) % 3];
-        D3 tq = dsub(q, dscale(p, ddot(q, p))), tr = dsub(r, dscale(p, ddot(r, p)));
-        const double lq = dlen(tq), lr = dlen(tr);
-        if (!(lq > 0.0 && lr > 0.0)) return base;
-        const double ca = fmin(1.0, fmax(-1.0, ddot(tq, tr) / (lq * lr)));
-        smin = fmin(smin, sqrt(fmax(0.0, 0.5 * (1.0 - ca))));  // sin(alpha/2)
+    // smallest corner: A between edges CA (2) and AB (0), B between 0 and 1,
+    // C between 1 and 2; the inward normals meet at pi - alpha
+    float smin = 1.0f;
+    for (int k = 0; k < 3; ++k) {
+        const float3 ni = nrm[(k + 2) % 3], nj = nrm[k];
+        const float c = dot3(ni, nj);  // -cos(alpha)
+        const float s_cos = sqrtf(fmaxf(0.0f, 0.5f * (1.0f + c) - (eta + 4.0f * kUlp)));
+        const float3 x = cross3(ni, nj);
+        const float s_sin = 0.5f * (sqrtf(dot3(x, x)) - 2.0f * eta - 8.0f * kUlp);
+        smin = fminf(smin, fmaxf(s_cos, s_sin));
     }
-    if (!(smin > 1e-9)) return base;
-    const double eta_eff = 2.0 * eta / smin;
-    // angle from the stored plane normal to the cone
-    const D3 nh = D3{r0.w, r1.w, r2.w};
-    const double lnh = dlen(nh);
-    const D3 u = dscale(nh, 1.0 / lnh);
-    double theta = 0.0;
+    if (!(smin > 1e-4f)) return base;
+    const float eta_c = 2.0f * eta / smin;
+    // unit direction of the stored plane normal
+    const float3 nh = f3(r0.w, r1.w, r2.w);
+    const float lnh = sqrtf(dot3(nh, nh));
+    const float3 u = scale3(nh, 1.0f / lnh);
     bool inside = true;
     for (int i = 0; i < 3; ++i)
-        if (ddot(dscale(ex[i], double(sigma)), u) < 0.0) inside = false;
-    if (!inside) theta = fmin(arc_distance(u, a, b), fmin(arc_distance(u, b, c), arc_distance(u, c, a)));
-    theta = fmax(0.0, theta - eta_eff);
-    if (!(theta < 1.5)) theta = 1.5;  // keep cos well away from 0; still a valid bound
-    const double dd = double(dist);
-    const double L = dd / (lnh * (1.0 + 2e-6) * cos(theta));
-    double lb = (1.0 - 3.0 * eps) * L / (1.0 + 8.0 * eps * L / dd);
-    lb *= 1.0 - 1e-5;
-    float f = float(lb);
-    if (double(f) > lb) f = __uint_as_float(__float_as_uint(f) - 1u);  // round down
-    return fmaxf(f, base);
+        if (dot3(nrm[i], u) < -(eta_c + 8.0f * kUlp)) inside = false;
+    float cmax = 1.0f;
+    if (!inside) {
+        float3 v[3];
+        cmax = -1.0f;
+        for (int i = 0; i < 3; ++i) {
+            v[i] = scale3(V[i], 1.0f / sqrtf(dot3(V[i], V[i])));
+            cmax = fmaxf(cmax, dot3(u, v[i]));
+        }
+        for (int i = 0; i < 3; ++i) {
+            const float3 p = v[i], q = v[(i + 1) % 3];
+            const float3 so = scale3(nrm[i], sigma);  // along p x q
+            const float x = dot3(nrm[i], u);
+            const float3 w = sub3(u, scale3(nrm[i], x));  // projection on the great circle
+            if (dot3(cross3(p, w), so) >= -1e-5f && dot3(cross3(w, q), so) >= -1e-5f)
+                cmax = fmaxf(cmax, sqrtf(fmaxf(0.0f, 1.0f - x * x)));
+        }
+        cmax += eta + eta_c + 4e-6f;
+    }
+    const float cos_up = fminf(1.0f, fmaxf(cmax, 0.0707372f));  // cos(1.5) = 0.07073720...
+    const float L = dist / (lnh * (1.0f + 2e-6f) * cos_up);
+    float lb = L * (1.0f - 3.0f * kUlp) / (1.0f + 8.0f * kUlp * L / dist);
+    lb *= (1.0f - 1e-5f) * (1.0f - 16.0f * kUlp);
+    return fmaxf(lb, base);
 }
 
 __global__ __launch_bounds__(256) void k_setup_tris(const float* __restrict__ xyz, int64_t n,

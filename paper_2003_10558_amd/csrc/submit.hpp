@@ -137,12 +137,62 @@ __global__ __launch_bounds__(256) void k_submit_bin_block(const JobDesc* __restr
     A.all = 0;
     A.ntx = J.ntx;
     A.nty = J.nty;
+    A.tile16 = 0;
+    A.pad = 0;
     A.setup = J.setup;
     A.n = J.ntri;
     A.bins = J.bins;
     A.status = status;
     A.rot = rot_of(J.P.rot);
     bin_block(A, t - J.blk_off);
+}
+
+__global__ __launch_bounds__(256) void k_submit_bin_block16(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
+                                                      int32_t depth, int32_t lds_cap, uint32_t* status) {
+    int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    int jb = find_off<&JobDesc::blk_off>(T, njobs, t);
+    const JobDesc& J = T[jb];
+    BinArgs A;
+    A.map = J.map;
+    A.ntiles = J.ntiles;
+    A.fmt = fmt;
+    A.depth = depth;
+    A.lds_cap = lds_cap;
+    A.all = 0;
+    A.ntx = J.ntx;
+    A.nty = J.nty;
+    A.tile16 = 1;
+    A.pad = 0;
+    A.setup = J.setup;
+    A.n = J.ntri;
+    A.bins = J.bins;
+    A.status = status;
+    A.rot = rot_of(J.P.rot);
+    bin_block16(A, t - J.blk_off);
+}
+
+__global__ __launch_bounds__(256) void k_submit_bin16(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
+                                                      int32_t depth, int32_t lds_cap, uint32_t* status) {
+    int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    int jb = find_job_super(T, njobs, t);
+    const JobDesc& J = T[jb];
+    BinArgs A;
+    A.map = J.map;
+    A.ntiles = J.ntiles;
+    A.fmt = fmt;
+    A.depth = depth;
+    A.lds_cap = lds_cap;
+    A.all = 0;
+    A.ntx = J.ntx;
+    A.nty = J.nty;
+    A.tile16 = 1;
+    A.pad = 0;
+    A.setup = J.setup;
+    A.n = J.ntri;
+    A.bins = J.bins;
+    A.status = status;
+    A.rot = rot_of(J.P.rot);
+    bin_super16(A, t - J.stile_off);
 }
 
 __global__ __launch_bounds__(64) void k_submit_block_caps(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
@@ -167,6 +217,8 @@ __global__ __launch_bounds__(256) void k_submit_bin(const JobDesc* __restrict__ 
     A.all = 0;
     A.ntx = J.ntx;
     A.nty = J.nty;
+    A.tile16 = 0;
+    A.pad = 0;
     A.setup = J.setup;
     A.n = J.ntri;
     A.bins = J.bins;
@@ -176,7 +228,7 @@ __global__ __launch_bounds__(256) void k_submit_bin(const JobDesc* __restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
-                                                       int32_t depth, int64_t total) {
+                                                       int32_t depth, int64_t total, int32_t bin_tile) {
     int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     int64_t t = xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
     if (t >= total) return;
@@ -198,6 +250,7 @@ __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict
     A.out_depth = J.depth;
     A.stats = nullptr;
     A.no_early_exit = 0;
+    A.bin_tile = bin_tile;
     A.rot = rot_of(J.P.rot);
     raster_tile<false>(A, t - J.tile_off, threadIdx.x & 63);
 }
@@ -317,8 +370,11 @@ void submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode,
 
 int64_t submit_table_offset() { return ws_layout(1).table_off; }
 
+// ev (optional): four events recorded on st before the maps, before the
+// binner (or the fused kernel), before the rasterizer and after the last
+// kernel, for timing the stages.
 hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t depth, void* ws,
-                         bool table_ready, uint32_t shape, hipStream_t st) {
+                         bool table_ready, uint32_t shape, hipStream_t st, hipEvent_t* ev = nullptr) {
     WsLayout W = ws_layout(njobs);
     char* base = reinterpret_cast<char*>(ws);
     JobDesc* table = reinterpret_cast<JobDesc*>(base + W.table_off);
@@ -339,23 +395,35 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
             hipLaunchKernelGGL(k_write_jobs, dim3(1), dim3(kJobChunk), 0, st, chunk, table);
         }
     }
+    if (ev) (void)hipEventRecord(ev[0], st);
     if (mtiles > 0) hipLaunchKernelGGL(k_submit_map, dim3(unsigned(mtiles)), dim3(256), 0, st, table, njobs);
     if (mblks > 0)
         hipLaunchKernelGGL(k_submit_block_caps, dim3(unsigned((mblks + 63) / 64)), dim3(64), 0, st, table, njobs, fmt,
                            mblks);
+    if (ev) (void)hipEventRecord(ev[1], st);
     if (mode == VSR_SUBMIT_FUSED) {
         hipLaunchKernelGGL(k_submit_fused, dim3(unsigned(stiles)), dim3(256), 0, st, table, njobs, fmt);
+        if (ev) (void)hipEventRecord(ev[2], st);
     } else {
         int32_t cap = bin_lds_cap(depth);
-        if (use_blocks(cap, blks, shape))
+        const bool t16 = (shape & VSR_BIN_TILE16) != 0;
+        if (t16 && use_blocks(cap, blks, shape, true))
+            hipLaunchKernelGGL(k_submit_bin_block16, dim3(unsigned(blks)), dim3(256), size_t(4) * cap * 4, st,
+                               table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
+        else if (t16)
+            hipLaunchKernelGGL(k_submit_bin16, dim3(unsigned(stiles)), dim3(256), size_t(cap) * 4, st,
+                               table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
+        else if (use_blocks(cap, blks, shape))
             hipLaunchKernelGGL(k_submit_bin_block, dim3(unsigned(blks)), dim3(256), 0, st,
                                table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
         else
             hipLaunchKernelGGL(k_submit_bin, dim3(unsigned(stiles)), dim3(256), size_t(kSupTiles) * cap * 4, st,
                                table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
+        if (ev) (void)hipEventRecord(ev[2], st);
         hipLaunchKernelGGL(k_submit_raster, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, fmt,
-                           depth, tiles);
+                           depth, tiles, int32_t(t16 ? 16 : 8));
     }
+    if (ev) (void)hipEventRecord(ev[3], st);
     return hipGetLastError();
 }
 

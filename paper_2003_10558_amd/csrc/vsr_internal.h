@@ -199,6 +199,10 @@ __device__ inline float3 sub3(float3 a, float3 b) { return f3(a.x - b.x, a.y - b
 __device__ inline float3 add3(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
 __device__ inline float3 scale3(float3 a, float s) { return f3(a.x * s, a.y * s, a.z * s); }
 __device__ inline float dot3(float3 a, float3 b) { return fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)); }
+// Unit roundoff of FP32, 2^-24: the bound on the relative error of one
+// rounded operation, in the error budgets of conservative tests.
+constexpr float kUlp = 5.9604645e-8f;
+
 // Cross product with separately rounded products (no contraction).
 __device__ inline float3 cross3(float3 a, float3 b) {
     return f3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);

@@ -282,8 +282,13 @@ class Batch:
                                    for (s, v), o in zip(self.items, self.outputs)])
         self.workspace = _buffer(vsr.vsr_submit_bytes(self.jobs, fmt, mode, bin_depth), dev)
 
-    def submit(self, stream=None) -> List[Tuple[torch.Tensor, torch.Tensor]]:
-        vsr.vsr_submit(self.jobs, self.fmt, self.mode, self.bin_depth, self.workspace, stream)
+    def submit(self, stream=None, events=None) -> List[Tuple[torch.Tensor, torch.Tensor]]:
+        """One vsr_submit; with ``events`` (four torch.cuda.Event) the stage
+        boundaries are recorded on the stream (vsr_submit_timed)."""
+        if events is None:
+            vsr.vsr_submit(self.jobs, self.fmt, self.mode, self.bin_depth, self.workspace, stream)
+        else:
+            vsr.vsr_submit_timed(self.jobs, self.fmt, self.mode, self.bin_depth, self.workspace, events, stream)
         return self.outputs
 
 

@@ -61,6 +61,11 @@ class ServeStats:
     max_inflight_bytes: int = 0
     budget_bytes: int = 0
     pixels: int = 0
+    batch_size_hist: dict = field(default_factory=dict)    # batch size -> batches
+    queue_depth_hist: dict = field(default_factory=dict)   # requests waiting at an admission -> admissions
+    queue_wait_hist_ms: dict = field(default_factory=dict)  # upper edge of the wait bin (ms) -> requests
+    overlapped_batches: int = 0   # batches whose device interval intersects another batch's
+    max_concurrent_batches: int = 0
     extra: dict = field(default_factory=dict)
 
     def as_dict(self) -> dict:
@@ -106,7 +111,10 @@ class Server:
         inflight: List[tuple] = []   # (event, slot, reqs, bytes, batch)
         used = 0
         st = ServeStats(offered=len(requests), budget_bytes=self.budget)
-        batch_sizes = []
+        batch_sizes, queue_depths = [], []
+        intervals = []  # (start event, end event) per batch: its device interval
+        ref_ev = torch.cuda.Event(enable_timing=True)
+        ref_ev.record(self.streams[0])
         t0 = time.perf_counter()
         while pending or queue or inflight:
             now = time.perf_counter() - t0
@@ -135,6 +143,7 @@ class Server:
             # admit
             admitted_any = False
             while free_slots and queue:
+                queue_depths.append(len(queue))
                 mode, depth = self.mode_for_scene(queue[0].scene)
                 reqs, nbytes = [], 0
                 rest = collections.deque()
@@ -161,9 +170,12 @@ class Server:
                 with torch.cuda.stream(stream):
                     batch = pipeline.Batch([(self.scenes[r.scene], r.view) for r in reqs], fmt=self.fmt,
                                            mode=mode, bin_depth=depth)
+                    ev0 = torch.cuda.Event(enable_timing=True)
+                    ev0.record(stream)
                     batch.submit(stream)
-                    ev = torch.cuda.Event()
+                    ev = torch.cuda.Event(enable_timing=True)
                     ev.record(stream)
+                intervals.append((ev0, ev))
                 for r in reqs:
                     r.admitted = tadm
                 used += nbytes
@@ -177,6 +189,31 @@ class Server:
                 elif pending:
                     time.sleep(min(1e-3, max(0.0, pending[0].arrival - (time.perf_counter() - t0))))
         wall = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        # device intervals of the batches (ms after the reference event); a
+        # batch overlaps when another batch's interval intersects its own
+        iv = np.array([(ref_ev.elapsed_time(a), ref_ev.elapsed_time(b)) for a, b in intervals]).reshape(-1, 2)
+        if len(iv):
+            order = np.argsort(iv[:, 0])
+            iv = iv[order]
+            over = np.zeros(len(iv), bool)
+            end_max, end_arg = -np.inf, -1
+            for k in range(len(iv)):
+                if iv[k, 0] < end_max:
+                    over[k] = True
+                    over[end_arg] = True
+                if iv[k, 1] > end_max:
+                    end_max, end_arg = iv[k, 1], k
+            st.overlapped_batches = int(over.sum())
+            ev_t = np.concatenate([np.stack([iv[:, 0], np.ones(len(iv))], 1), np.stack([iv[:, 1], -np.ones(len(iv))], 1)])
+            ev_t = ev_t[np.lexsort((ev_t[:, 1], ev_t[:, 0]))]
+            st.max_concurrent_batches = int(np.max(np.cumsum(ev_t[:, 1])))
+        st.batch_size_hist = {int(k): int(v) for k, v in zip(*np.unique(batch_sizes, return_counts=True))} \
+            if batch_sizes else {}
+        qd_edges = [0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 1 << 30]
+        qd = np.histogram(queue_depths, bins=qd_edges)[0] if queue_depths else np.zeros(len(qd_edges) - 1, int)
+        st.queue_depth_hist = {f"{qd_edges[k]}-{qd_edges[k + 1] - 1}" if k + 2 < len(qd_edges) else
+                               f">={qd_edges[k]}": int(qd[k]) for k in range(len(qd))}
         done = [r for r in requests if not r.dropped and not math.isnan(r.done)]
         st.completed = len(done)
         st.dropped = sum(1 for r in requests if r.dropped)
@@ -190,6 +227,10 @@ class Server:
             st.p50_ms, st.p99_ms, st.mean_ms = (float(np.percentile(lat, 50)), float(np.percentile(lat, 99)),
                                                 float(lat.mean()))
             st.queue_p50_ms, st.queue_p99_ms = float(np.percentile(qd, 50)), float(np.percentile(qd, 99))
+            w_edges = [0.0, 0.1, 0.2, 0.5, 1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0, np.inf]
+            wh = np.histogram(qd, bins=w_edges)[0]
+            st.queue_wait_hist_ms = {(f"<{w_edges[k + 1]:g}" if np.isfinite(w_edges[k + 1]) else f">={w_edges[k]:g}"):
+                                     int(wh[k]) for k in range(len(wh))}
             last = max(r.done for r in done)
             first = min(r.arrival for r in requests)
             st.views_per_s = st.completed / max(1e-9, last - first)

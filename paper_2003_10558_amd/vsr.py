@@ -23,11 +23,11 @@ VSR_MAP_AA_LINES = 4
 (VSR_LENS_UNIVERSAL, VSR_LENS_EQUIRECT, VSR_LENS_CUBE, VSR_LENS_SCREENS, VSR_LENS_VR, VSR_LENS_PANORAMA,
  VSR_LENS_DOME) = range(7)
 VSR_BIN_ALL = 1
-VSR_BIN_BLOCKS, VSR_BIN_SUPERTILES = 2, 4
+VSR_BIN_BLOCKS, VSR_BIN_SUPERTILES, VSR_BIN_TILE16 = 2, 4, 8
 VSR_NO_HIT = 0xFFFFFFFF
 VSR_SUBMIT_BINNED, VSR_SUBMIT_FUSED = 0, 1
 VSR_SUBMIT_TABLE_READY = 0x100
-VSR_SUBMIT_BIN_BLOCKS, VSR_SUBMIT_BIN_SUPERTILES = 0x200, 0x400
+VSR_SUBMIT_BIN_BLOCKS, VSR_SUBMIT_BIN_SUPERTILES, VSR_SUBMIT_BIN_TILE16 = 0x200, 0x400, 0x800
 VSR_TILE = 8
 VSR_RESOLVE_NORMALIZE3 = 1
 VSR_AOV_HORIZONTAL, VSR_AOV_DIAGONAL, VSR_AOV_VERTICAL, VSR_AOV_HORIZONTAL_4X3 = 0, 1, 2, 3
@@ -103,17 +103,21 @@ _lib.vsr_resolve_packed.argtypes = [ctypes.POINTER(vsr_view), _i32, _vp, _vp, _i
 _lib.vsr_submit_bytes.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32]
 _lib.vsr_submit_bytes.restype = _i64
 _lib.vsr_submit.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32, _vp, _i64, _vp]
+_lib.vsr_submit_timed.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32, _vp, _i64,
+                                  ctypes.POINTER(ctypes.c_void_p), _i32, _vp]
 _lib.vsr_submit_table_bytes.argtypes = [_i32]
 _lib.vsr_submit_table_bytes.restype = _i64
 _lib.vsr_submit_table_offset.argtypes = []
 _lib.vsr_submit_table_offset.restype = _i64
 _lib.vsr_submit_table.argtypes = [ctypes.POINTER(vsr_job), _i32, _i32, _i32, _i32, _vp, _vp, _i64]
 _lib.vsr_bin_overflow.argtypes = [_vp, _i32, ctypes.POINTER(_i64)]
+_lib.vsr_calib_copy.argtypes = [_vp, _vp, _i64, _vp]
+_lib.vsr_calib_fma.argtypes = [_vp, _i64, _i32, _vp]
 _lib.vsr_strerror.argtypes = [ctypes.c_int]
 _lib.vsr_strerror.restype = ctypes.c_char_p
 _lib.vsr_last_error.restype = ctypes.c_char_p
 for _f in ("vsr_build_map", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin", "vsr_raster", "vsr_raster_stats", "vsr_render", "vsr_render_noalloc", "vsr_submit",
-           "vsr_submit_table", "vsr_bin_overflow"):
+           "vsr_submit_timed", "vsr_submit_table", "vsr_bin_overflow", "vsr_calib_copy", "vsr_calib_fma"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map", "vsr_build_map_lens", "vsr_map_unpack", "vsr_setup_tris", "vsr_bin",
@@ -121,7 +125,8 @@ EXPORTS = ("vsr_map_bytes", "vsr_setup_bytes", "vsr_bin_bytes", "vsr_build_map",
            "vsr_resolve_packed", "vsr_aa_map_bytes",
            "vsr_aa_raster", "vsr_aa_raster_stats", "vsr_setup_particles", "vsr_aa_particles",
            "vsr_aa_particles_stats", "vsr_wire_bytes", "vsr_setup_wire", "vsr_aa_wireframe", "vsr_aa_wireframe_stats", "vsr_submit_bytes",
-           "vsr_submit_table_bytes", "vsr_submit_table_offset", "vsr_submit_table", "vsr_submit", "vsr_bin_overflow", "vsr_strerror", "vsr_last_error")
+           "vsr_submit_table_bytes", "vsr_submit_table_offset", "vsr_submit_table", "vsr_submit", "vsr_submit_timed", "vsr_bin_overflow", "vsr_calib_copy", "vsr_calib_fma",
+           "vsr_strerror", "vsr_last_error")
 
 
 def _check(rc: int) -> None:
@@ -359,6 +364,15 @@ def vsr_submit(jobs, fmt: int, mode: int, bin_depth: int, workspace, stream=None
                            _stream(stream)))
 
 
+def vsr_submit_timed(jobs, fmt: int, mode: int, bin_depth: int, workspace, events, stream=None) -> None:
+    """events: four recorded-once torch.cuda.Event objects (or raw hipEvent_t
+    handles) that the library records between the stages."""
+    handles = [int(e.cuda_event) if hasattr(e, "cuda_event") else int(e) for e in events]
+    arr = (ctypes.c_void_p * len(handles))(*handles)
+    _check(_lib.vsr_submit_timed(jobs, len(jobs), fmt, mode, bin_depth, _ptr(workspace), _nbytes(workspace), arr,
+                                 len(handles), _stream(stream)))
+
+
 def vsr_submit_table_bytes(njobs: int) -> int:
     return _size(_lib.vsr_submit_table_bytes(njobs), "vsr_submit_table_bytes")
 
@@ -378,6 +392,14 @@ def vsr_bin_overflow(bins_or_ws, is_workspace: bool = False) -> int:
     out = ctypes.c_int64(0)
     _check(_lib.vsr_bin_overflow(_ptr(bins_or_ws), int(bool(is_workspace)), ctypes.byref(out)))
     return int(out.value)
+
+
+def vsr_calib_copy(src, dst, stream=None) -> None:
+    _check(_lib.vsr_calib_copy(_ptr(src), _ptr(dst), min(_nbytes(src), _nbytes(dst)) // 16 * 16, _stream(stream)))
+
+
+def vsr_calib_fma(out, iters: int, stream=None) -> None:
+    _check(_lib.vsr_calib_fma(_ptr(out), int(out.numel()), int(iters), _stream(stream)))
 
 
 def vsr_strerror(code: int) -> str:

@@ -76,6 +76,22 @@ def views_1080p_sweep() -> List[View]:
     return out
 
 
+def views_1080p_batch(n: int = 64) -> List[View]:
+    """The benchmark's batch: view q has the lens of views_1080p_sweep()[q % 4]
+    (4 distinct lenses), yaw 2 pi (q // 4) / (n // 4) and pitch asin(U[-0.5,
+    0.5]) (seed 1234)."""
+    sweep = views_1080p_sweep()
+    rng = np.random.default_rng(1234)
+    out = []
+    for q in range(n):
+        base = sweep[q % 4]
+        yaw = 2 * math.pi * (q // 4) / max(1, n // 4)
+        pitch = math.asin(rng.uniform(-0.5, 0.5))
+        out.append(View(base.width, base.height, base.k, base.l, base.s, base.omega_deg, base.aov,
+                        yaw_pitch_rotation(yaw, pitch)))
+    return out
+
+
 def view_4k() -> View:
     """3840x2160 map with the 256x256 case's lens parameters."""
     return View(3840, 2160, 0.32, 0.62, 0.86, 270.0)

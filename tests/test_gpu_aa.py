@@ -132,7 +132,8 @@ def test_aa_overflow_and_binner_paths_identical(gpu):
     base = pipeline.render_aa(scene, view, bin_depth=256)
     torch.cuda.synchronize()
     ref = [base.coverage.clone(), base.depth_pass.clone(), base.dominant.clone()]
-    for depth, flags in [(4, 0), (256, vsr.VSR_BIN_BLOCKS), (256, vsr.VSR_BIN_SUPERTILES), (256, vsr.VSR_BIN_ALL)]:
+    for depth, flags in [(4, 0), (256, vsr.VSR_BIN_BLOCKS), (256, vsr.VSR_BIN_SUPERTILES), (256, vsr.VSR_BIN_ALL),
+                         (256, vsr.VSR_BIN_TILE16)]:
         fr = pipeline.render_aa(scene, view, bin_depth=depth, bin_flags=flags)
         torch.cuda.synchronize()
         if depth == 4:

@@ -109,7 +109,8 @@ def test_lens_binning_is_exact(gpu, name):
     ref = pipeline.render(scene, view, bin_depth=2048, bin_flags=vsr.VSR_BIN_ALL)
     torch.cuda.synchronize()
     ref_ids, ref_dep = ref.tri_id.clone(), ref.depth.clone()
-    for depth, shape in ((1024, 0), (256, vsr.VSR_BIN_BLOCKS), (256, vsr.VSR_BIN_SUPERTILES)):
+    for depth, shape in ((1024, 0), (256, vsr.VSR_BIN_BLOCKS), (256, vsr.VSR_BIN_SUPERTILES),
+                         (512, vsr.VSR_BIN_TILE16 | vsr.VSR_BIN_BLOCKS), (512, vsr.VSR_BIN_TILE16 | vsr.VSR_BIN_SUPERTILES)):
         fr = pipeline.render(scene, view, bin_depth=depth, bin_flags=shape)
         torch.cuda.synchronize()
         assert torch.equal(fr.tri_id, ref_ids) and torch.equal(fr.depth, ref_dep), (name, shape)

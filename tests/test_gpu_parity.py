@@ -108,7 +108,8 @@ def test_binning_is_exact(gpu):
         _say(f"[bin-exact] {name}")
         b_ids, b_dep, ovf = _render(gpu, tris, view, depth=2048, flags=1)
         assert ovf == 0
-        for depth, shape in ((1024, 0), (256, 2), (256, 4)):  # automatic, 32x32 blocks, 16x16 super-tiles
+        # automatic, 32x32 blocks, 16x16 super-tiles; then the same with 16x16 bin tiles
+        for depth, shape in ((1024, 0), (256, 2), (256, 4), (1024, 8), (256, 8 | 2), (512, 8 | 2), (256, 8 | 4)):
             a_ids, a_dep, _ = _render(gpu, tris, view, depth=depth, flags=shape)
             assert np.array_equal(a_ids, b_ids), shape
             assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32)), shape
@@ -123,7 +124,7 @@ def test_binning_is_exact_random_views(gpu, seed):
     for v in views:
         b_ids, b_dep, ovf = _render(gpu, tris, v, depth=2048, flags=1)
         assert ovf == 0
-        for shape in (2, 4):  # 32x32 blocks, 16x16 super-tiles
+        for shape in (2, 4, 8 | 2, 8 | 4):  # 32x32 blocks, 16x16 super-tiles; 8x8 or 16x16 bin tiles
             a_ids, a_dep, _ = _render(gpu, tris, v, depth=256, flags=shape)
             assert np.array_equal(a_ids, b_ids), (v.k, v.omega_deg, shape)
             assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
@@ -218,18 +219,52 @@ def test_winding_and_antipode(gpu):
     assert np.array_equal(a != 0xFFFFFFFF, ref.id != 0xFFFFFFFF)
 
 
-def test_overflow_falls_back(gpu):
+@pytest.mark.parametrize("flags", [0, 8], ids=["tile8", "tile16"])
+def test_overflow_falls_back(gpu, flags):
     """A tiny bin depth overflows; the rasterizer gathers itself: same bits."""
     view, tris = synth.view_small(), synth.scene_small()
-    _say("[overflow] depth 4 vs 1024")
+    _say(f"[overflow] depth 4 vs 1024, bin flags {flags}")
     a_ids, a_dep, ovf_a = _render(gpu, tris, view, depth=1024)
-    b_ids, b_dep, ovf_b = _render(gpu, tris, view, depth=4)
+    b_ids, b_dep, ovf_b = _render(gpu, tris, view, depth=4, flags=flags)
     assert ovf_a == 0 and ovf_b > 0
     assert np.array_equal(a_ids, b_ids)
     assert np.array_equal(a_dep.view(np.uint32), b_dep.view(np.uint32))
 
 
-def test_early_exit_is_exact(gpu):
+def test_tile16_lists_are_the_union_of_tile_lists(gpu):
+    """A 16x16 bin tile's list holds every triangle of its four 8x8 tiles'
+    lists (same depth-bucket order), and nothing the rasterizer's tile test
+    then drops makes a difference: same images on both binner shapes."""
+    view = synth.View(200, 150, -0.4, 0.3, 0.9, 300.0, 0, synth.yaw_pitch_rotation(1.0, 0.3))
+    torch, pipeline, vsr = gpu
+    scene = pipeline.Scene(synth.scene(20000, 5))
+    shift = 0
+    while (256 << shift) < scene.ntri:
+        shift += 1
+    t8, l8, _ = _bin_lists(gpu, scene, view, 2048, 4)
+    ntx = (view.width + 7) // 8
+    nty = (view.height + 7) // 8
+    nsx = (ntx + 1) // 2
+    nsup = nsx * ((nty + 1) // 2)
+    for shape in (2, 4):
+        c16, l16, o16 = _bin_lists(gpu, scene, view, 1024, 8 | shape)
+        assert o16 == int(np.sum(c16[:nsup] > 1024))  # overflowed lists are counted, not written
+        for t in range(ntx * nty):
+            tx, ty = t % ntx, t // ntx
+            s_idx = (ty // 2) * nsx + tx // 2
+            if c16[s_idx] > 1024:
+                continue
+            sup = set(l16[s_idx, :c16[s_idx]].tolist())
+            assert set(l8[t, :t8[t]].tolist()) <= sup, (shape, t)
+        for s_idx in range(nsup):
+            if c16[s_idx] <= 1024:
+                lst = l16[s_idx, :c16[s_idx]]
+                assert np.all(np.diff(lst >> shift) >= 0), (shape, s_idx)
+    _say(f"[tile16] lists: {int(t8.sum())} 8x8 entries, {int(c16[:nsup].sum())} 16x16 entries, {o16} overflowed")
+
+
+@pytest.mark.parametrize("bin_flags", [0, 8], ids=["tile8", "tile16"])
+def test_early_exit_is_exact(gpu, bin_flags):
     """The nearest-first early exit (stop once every pixel beats the depth
     lower bound of the current bucket) skips only triangles that cannot win:
     same bits as testing every listed triangle, on the 1920x1080 frames of
@@ -237,8 +272,14 @@ def test_early_exit_is_exact(gpu):
     torch, pipeline, vsr = gpu
     scene = pipeline.Scene(synth.scene_1m())
     stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+    ref8 = None
     for q, view in enumerate(synth.views_1080p_sweep()):
-        fr = pipeline.render(scene, view)
+        fr = pipeline.render(scene, view, bin_flags=bin_flags)
+        if bin_flags:
+            ref8 = pipeline.render(scene, view)
+            torch.cuda.synchronize()
+            assert torch.equal(ref8.tri_id, fr.tri_id) and torch.equal(ref8.depth.view(torch.int32),
+                                                                       fr.depth.view(torch.int32)), q
         ids = torch.empty_like(fr.tri_id)
         dep = torch.empty_like(fr.depth)
         vsr.vsr_raster_stats(view, 0, fr.map, scene.setup, scene.ntri, fr.bins, pipeline.DEFAULT_BIN_DEPTH, ids, dep,
@@ -249,7 +290,77 @@ def test_early_exit_is_exact(gpu):
         _say(f"[early-exit] view {q}: identical with every listed triangle tested")
 
 
-@pytest.mark.parametrize("mode", [0x200, 0x400, 1], ids=["binned-blocks", "binned-supertiles", "fused"])
+def _cone_min_depth(tris):
+    """FP64 smallest ray-plane depth d / (g . N_hat) over the unit directions g
+    of each triangle's vertex cone: d / cos(theta), theta the angle from the
+    plane's unit normal (facing away from O) to the cone (0 inside it; else
+    to the nearest vertex direction or edge arc)."""
+    a = tris[0:3].T.astype(np.float64)
+    b = tris[3:6].T.astype(np.float64)
+    c = tris[6:9].T.astype(np.float64)
+    n = np.cross(a - b, c - b)
+    d = np.einsum("ij,ij->i", a, n)
+    u = n * np.sign(d)[:, None] / np.linalg.norm(n, axis=1, keepdims=True)
+    dist = np.abs(d) / np.linalg.norm(n, axis=1)
+    sig = np.sign(np.einsum("ij,ij->i", a, np.cross(b, c)))
+    v = [x / np.linalg.norm(x, axis=1, keepdims=True) for x in (a, b, c)]
+    cos_t = np.max([np.einsum("ij,ij->i", u, x) for x in v], axis=0)
+    inside = np.ones(len(a), bool)
+    for p, q in ((v[0], v[1]), (v[1], v[2]), (v[2], v[0])):
+        e = np.cross(p, q) * sig[:, None]
+        e /= np.linalg.norm(e, axis=1, keepdims=True)
+        x = np.einsum("ij,ij->i", e, u)
+        inside &= x >= 0
+        w = u - e * x[:, None]
+        pq = np.cross(p, q)
+        within = (np.einsum("ij,ij->i", np.cross(p, w), pq) >= 0) & (np.einsum("ij,ij->i", np.cross(w, q), pq) >= 0)
+        cos_t = np.where(within, np.maximum(cos_t, np.sqrt(np.maximum(0.0, 1.0 - x * x))), cos_t)
+    cos_t = np.where(inside, 1.0, cos_t)
+    return dist / cos_t
+
+
+def test_depth_lower_bound_below_cone_minimum(gpu):
+    """The FP32 depth lower bound of every live triangle (64-byte setup
+    record, word 13, rank order) is at most the FP64 smallest depth over its
+    vertex cone, and close to it: on shell, small, grazing and sliver
+    triangles."""
+    torch, pipeline, vsr = gpu
+    rng = np.random.default_rng(77)
+    shell = synth.scene(4000, 78)
+    small = synth.small_triangles(4000, 79)
+    # grazing: planes passing 1e-3..1e-1 from O relative to their size
+    cen = rng.normal(size=(2000, 3)) * 5
+    t1 = rng.normal(size=(2000, 3))
+    t1 -= cen * (np.einsum("ij,ij->i", t1, cen) / np.einsum("ij,ij->i", cen, cen))[:, None]
+    t2 = np.cross(cen, t1)
+    t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+    t2 /= np.linalg.norm(t2, axis=1, keepdims=True)
+    off = cen * 10 ** rng.uniform(-3, -1, size=(2000, 1))
+    ga, gb, gc = cen + off, cen + 2 * t1 + off * 0.5, cen - 2 * t1 + 3 * t2
+    grazing = np.concatenate([ga.T, gb.T, gc.T]).astype(np.float32)
+    # slivers: one vertex 1e-3..1e-2 off the opposite edge
+    sa = rng.normal(size=(2000, 3)) * 4
+    sb = sa + rng.normal(size=(2000, 3))
+    sc = 0.5 * (sa + sb) + rng.normal(size=(2000, 3)) * 10 ** rng.uniform(-3, -2, size=(2000, 1))
+    sliver = np.concatenate([sa.T, sb.T, sc.T]).astype(np.float32)
+    tris = np.ascontiguousarray(np.concatenate([shell, small, grazing, sliver], axis=1))
+    scene = pipeline.Scene(tris)
+    torch.cuda.synchronize()
+    n = tris.shape[1]
+    rec = scene.setup[256:256 + 64 * n].cpu().numpy().view(np.float32).reshape(n, 16)
+    tid = rec[:, 14].view(np.uint32)
+    lb = rec[:, 13].astype(np.float64)
+    live = np.isfinite(lb)
+    rmin = _cone_min_depth(tris)[tid[live]]
+    ratio = lb[live] / rmin
+    _say(f"[depth-lb] {int(live.sum())} live of {n}: lb / cone minimum max {ratio.max():.9f}, "
+         f"median {np.median(ratio):.6f}, min {ratio.min():.3e}")
+    assert np.all(ratio <= 1.0)
+    assert np.median(ratio) > 0.9999
+
+
+@pytest.mark.parametrize("mode", [0x200, 0x400, 0xA00, 0xC00, 1],
+                         ids=["binned-blocks", "binned-supertiles", "tile16-blocks", "tile16-supertiles", "fused"])
 def test_submit_matches_single_views(gpu, mode):
     torch, pipeline, vsr = gpu
     tris = synth.scene(3000, 23)

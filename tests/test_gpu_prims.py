@@ -124,7 +124,8 @@ def test_wireframe_binning_paths_identical(gpu):
     ref = pipeline.render_wireframe(scene, view, bin_depth=256)
     torch.cuda.synchronize()
     rc, rd = ref.coverage.clone(), ref.dominant.clone()
-    for depth, flags in [(4, 0), (256, vsr.VSR_BIN_BLOCKS), (256, vsr.VSR_BIN_SUPERTILES), (256, vsr.VSR_BIN_ALL)]:
+    for depth, flags in [(4, 0), (256, vsr.VSR_BIN_BLOCKS), (256, vsr.VSR_BIN_SUPERTILES), (256, vsr.VSR_BIN_ALL),
+                         (256, vsr.VSR_BIN_TILE16)]:
         fr = pipeline.render_wireframe(scene, view, bin_depth=depth, bin_flags=flags)
         torch.cuda.synchronize()
         assert torch.equal(fr.coverage, rc) and torch.equal(fr.dominant, rd), (depth, flags)
@@ -162,7 +163,8 @@ def test_particles_binning_paths_identical(gpu):
     ref = pipeline.render_particles(scene, view, bin_depth=256)
     torch.cuda.synchronize()
     base = [ref.coverage.clone(), ref.depth_pass.clone(), ref.uv.clone(), ref.dominant.clone()]
-    for depth, flags in [(4, 0), (256, vsr.VSR_BIN_BLOCKS), (256, vsr.VSR_BIN_SUPERTILES), (256, vsr.VSR_BIN_ALL)]:
+    for depth, flags in [(4, 0), (256, vsr.VSR_BIN_BLOCKS), (256, vsr.VSR_BIN_SUPERTILES), (256, vsr.VSR_BIN_ALL),
+                         (256, vsr.VSR_BIN_TILE16)]:
         fr = pipeline.render_particles(scene, view, bin_depth=depth, bin_flags=flags)
         torch.cuda.synchronize()
         for a, b in zip(base, [fr.coverage, fr.depth_pass, fr.uv, fr.dominant]):

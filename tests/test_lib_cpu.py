@@ -278,3 +278,26 @@ def test_primitive_argument_errors(vsr):
     with pytest.raises(vsr.VsrError) as e:
         vsr.vsr_setup_wire(B(256, 1), B(512, 1), 1000, B(1024, 100), stream=0)
     assert e.value.code == vsr.VSR_E_SPACE
+
+
+def test_device_code_has_no_fp64(tmp_path):
+    """FP64 stays off the GPU: the gfx950 assembly of the whole library has
+    no double-precision instruction (v_*_f64) and no packed FP32 one."""
+    import shutil
+    import subprocess
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not os.path.exists(hipcc) and shutil.which("hipcc") is None:
+        pytest.skip("hipcc not available")
+    import importlib
+    b = importlib.import_module("paper_2003_10558_amd.build")
+    out = tmp_path / "vsr.s"
+    flags = [f for f in b.HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
+    res = subprocess.run([hipcc] + flags + ["--cuda-device-only", "-S", "-o", str(out), b.SRC],
+                         capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr[-2000:]
+    asm = out.read_text()
+    assert asm.count("v_fma_f32") > 100
+    f64 = re.findall(r"\bv_[a-z0-9_]*_f64\b", asm)
+    pk = re.findall(r"\bv_pk_(?:fma|mul|add)_f32\b", asm)
+    assert not f64, sorted(set(f64))
+    assert not pk, sorted(set(pk))
