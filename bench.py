@@ -149,7 +149,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: no CPU leg, fewer passes")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="headline batch with 8x8 bin tiles at --bin-depth instead of the autotuner's choice")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()
@@ -496,8 +498,20 @@ def main():
     log(f"covered fragments per frame (k sweep): {F_all}; processed with early exit: {F_proc}; "
         f"tests executed: {tests_proc}")
 
-    # ---------------- batched: setup + one submit of all views per step
-    batch = pipeline.Batch([(scene, v) for v in views], fmt=fmt, mode=vsr.VSR_SUBMIT_BINNED, bin_depth=depth)
+    # ---------------- batched: setup + one submit of all views per step, in
+    # the submit mode, bin tile size and bin depth the autotuner picks for
+    # this scene and view size (timed over its candidates before the run)
+    from paper_2003_10558_amd import autotune
+    tuner = autotune.Tuner(None, reps=3)
+    if args.no_tune:
+        choice = (vsr.VSR_SUBMIT_BINNED, depth)
+        tuner_ms = None
+    else:
+        choice = tuner.choose(scene, views, fmt)
+        tuner_ms = next(iter(tuner.cache.values()))["ms"]
+    tuned = autotune.describe(choice)
+    log(f"autotuner: {tuned} (candidates, ms per submit: {tuner_ms})")
+    batch = pipeline.Batch([(scene, v) for v in views], fmt=fmt, mode=choice[0], bin_depth=choice[1])
     for _ in range(args.warmup):
         scene.refresh()
         batch.submit()
@@ -570,10 +584,12 @@ def main():
     log(f"submit, {len(views)} distinct lenses: {dsubmit_ms:.3f} ms ({len(views) / dsubmit_ms * 1e3:.1f} views/s); "
         f"the benchmark batch shares {n_lens} lens maps")
     del dbatch
-    # the same step with 16x16 bin tiles (lists per super-tile, culled per
-    # tile by the rasterizer)
+    # the same step with the other bin tile size (8x8 lists, or 16x16 lists
+    # culled per tile by the rasterizer), at the 8x8 default depth or 512
+    other16 = tuned["tile"] == 8
     tbatch = pipeline.Batch([(scene, v) for v in views], fmt=fmt,
-                            mode=vsr.VSR_SUBMIT_BINNED | vsr.VSR_SUBMIT_BIN_TILE16, bin_depth=max(depth, 512))
+                            mode=vsr.VSR_SUBMIT_BINNED | (vsr.VSR_SUBMIT_BIN_TILE16 if other16 else 0),
+                            bin_depth=512 if other16 else depth)
     tbatch.submit()
     torch.cuda.synchronize()
     t16_ev = [[ev() for _ in range(4)] for _ in range(args.steps)]
@@ -592,7 +608,8 @@ def main():
     t16_raster_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in t16_ev]))
     t16_same = all(torch.equal(a[0], b[0]) and torch.equal(a[1].view(torch.int32), b[1].view(torch.int32))
                    for a, b in zip(tbatch.outputs, batch.outputs))
-    log(f"batched step, 16x16 bin tiles: {t16_step_ms:.3f} ms ({len(views) / t16_step_ms * 1e3:.1f} views/s); "
+    log(f"batched step, {16 if other16 else 8}x{16 if other16 else 8} bin tiles: {t16_step_ms:.3f} ms "
+        f"({len(views) / t16_step_ms * 1e3:.1f} views/s); "
         f"binner {t16_bin_ms:.3f} ms, rasterizer {t16_raster_ms:.3f} ms; overflowed "
         f"{vsr.vsr_bin_overflow(tbatch.workspace, True)}; images identical to 8x8 bins: {t16_same}")
     del tbatch
@@ -622,8 +639,13 @@ def main():
         reqs = serve.make_requests(len(sc), rate_hz=args.serve_rate, duration_s=args.serve_seconds,
                                    seed=synth.SERVE_ARRIVAL_SEED, view_seed=synth.SERVE_ARRIVAL_SEED + 100,
                                    resolutions=synth.SERVE_RESOLUTIONS)
+        # the autotuner's (mode, bin tile, depth) per resident scene, timed on
+        # 16 request-like views (mixed resolutions) of that scene
+        sample_views = synth.random_views(16, 777, resolutions=synth.SERVE_RESOLUTIONS)
+        serve_choice = {q: tuner.choose(sc[q], sample_views, fmt) for q in range(len(sc))}
+        log(f"serving: autotuned per scene {[autotune.describe(serve_choice[q]) for q in range(len(sc))]}")
         srv = serve.Server(sc, streams=3, max_batch=32, hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)),
-                           mode_for_scene=lambda s: (vsr.VSR_SUBMIT_FUSED, depth))
+                           mode_for_scene=lambda s: serve_choice[s])
         warm = serve.make_requests(len(sc), rate_hz=200.0, duration_s=0.1, seed=99, view_seed=98,
                                    resolutions=synth.SERVE_RESOLUTIONS)
         srv.run(warm)
@@ -631,10 +653,13 @@ def main():
         serve_stats = st.as_dict()
         serve_stats.update({"rate_hz": args.serve_rate, "duration_s": args.serve_seconds,
                             "scenes": [int(t.shape[1]) for t in sc_np],
+                            "mode_per_scene": [autotune.describe(serve_choice[q]) for q in range(len(sc))],
                             "resolutions": [list(r) for r in synth.SERVE_RESOLUTIONS]})
         log(f"serving: offered {st.offered} at {args.serve_rate:.0f}/s for {args.serve_seconds}s: completed "
             f"{st.completed}, dropped {st.dropped}, {st.views_per_s:.1f} views/s, p50 {st.p50_ms:.1f} ms, "
-            f"p99 {st.p99_ms:.1f} ms, mean batch {st.mean_batch:.1f}")
+            f"p99 {st.p99_ms:.1f} ms, mean batch {st.mean_batch:.1f}, overlapped batches {st.overlapped_batches} of "
+            f"{st.batches} (at most {st.max_concurrent_batches} at once); batch sizes {st.batch_size_hist}; "
+            f"queue depth at admission {st.queue_depth_hist}; queue wait (ms) {st.queue_wait_hist_ms}")
         del sc, srv
 
     # ---------------- rooflines
@@ -647,8 +672,13 @@ def main():
     # covers len(views) frames, timed live between the library's stage
     # events over the timed steps
     nblk_all = len(views) * (((views[0].width + 31) // 32) * ((views[0].height + 31) // 32))
-    sub_bin_kernel = ("k_submit_bin_block" if (nblk_all >= 2560 and max(64, 1 << (depth - 1).bit_length()) <= 256)
-                      else "k_submit_bin")
+    cap_all = max(64, 1 << (choice[1] - 1).bit_length())
+    if tuned["mode"] == "fused":
+        sub_bin_kernel = "k_submit_fused"
+    elif tuned["tile"] == 16:
+        sub_bin_kernel = "k_submit_bin_block16" if (nblk_all >= 2560 and cap_all <= 1024) else "k_submit_bin16"
+    else:
+        sub_bin_kernel = "k_submit_bin_block" if (nblk_all >= 2560 and cap_all <= 256) else "k_submit_bin"
     t_sb = stage_bin_ms * 1e-3
     roofline = {"bound": "hbm", "achieved": frame_bytes * len(views) / t_sb / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s", "frac": frame_bytes * len(views) / t_sb / PEAK_HBM,
@@ -663,10 +693,12 @@ def main():
     roofline_submit_raster = {"bound": "alu", "achieved": OPS_PER_FRAGMENT * F_mean * len(views) / t_sr / 1e12,
                               "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "T lane-ops/s",
                               "frac": OPS_PER_FRAGMENT * F_mean * len(views) / t_sr / PEAK_VALU_LANE_OPS,
-                              "kernel": "k_submit_raster", "kernel_ms": stage_raster_ms,
+                              "kernel": "k_submit_raster16" if tuned["tile"] == 16 else "k_submit_raster",
+                              "kernel_ms": stage_raster_ms,
                               "fragments_per_launch": F_mean * len(views), "ops_per_fragment": OPS_PER_FRAGMENT,
                               "measured_peak": calib["valu_T_lane_fma_per_s"],
-                              "traffic": traffic_from_profiles("k_submit_raster")}
+                              "traffic": traffic_from_profiles("k_submit_raster16" if tuned["tile"] == 16
+                                                               else "k_submit_raster")}
     # the plain path's binner (16x16 super-tiles at one 1080p view) with its
     # own HBM ideal: read every triangle's 64-byte bin record and every tile
     # cap once, write the lists
@@ -760,7 +792,9 @@ def main():
         "config": {"workload": "1920x1080 Universal Perspective views (k in {1@90deg, 0.5, 0, -0.5 @180deg}, "
                                "l=0.5, s=1, varied yaw/pitch) of 1,000,000 small triangles (angular edge "
                                "~N(0.02,0.005^2) rad, distance U(1,50)) + radius-100 icosphere, seed 1",
-                   "views_per_step": len(views), "triangles": int(tris.shape[1]), "bin_depth": depth,
+                   "views_per_step": len(views), "triangles": int(tris.shape[1]),
+                   "submit_mode": tuned["mode"], "bin_tile": tuned["tile"], "bin_depth": tuned["bin_depth"],
+                   "chosen_by": "autotuner" if not args.no_tune else "fixed (--no-tune)",
                    "step": "vsr_setup_tris + vsr_submit(all views)"},
         "batched_fps_with_setup": views_per_s,
         "batched_fps": len(views) / submit_ms * 1e3,
@@ -778,8 +812,11 @@ def main():
         "overflowed_tiles_plain": overflow,
         "fused_fps": 1e3 / fused_ms,
         "batched_fused_fps": len(views) / fsubmit_ms * 1e3,
-        "batched_tile16": {"fps_with_setup": len(views) / t16_step_ms * 1e3, "binner_ms": t16_bin_ms,
-                           "rasterizer_ms": t16_raster_ms, "identical_images": t16_same},
+        "batched_other_tile": {"tile": 16 if other16 else 8, "fps_with_setup": len(views) / t16_step_ms * 1e3,
+                               "binner_ms": t16_bin_ms, "rasterizer_ms": t16_raster_ms,
+                               "identical_images": t16_same},
+        "autotuned": tuned,
+        "autotuner_ms_per_submit": tuner_ms,
         "serving": serve_stats,
         "roofline": roofline,
         "roofline_submit_raster": roofline_submit_raster,

@@ -406,9 +406,9 @@ __device__ inline void bin_block(const BinArgs& A0, int64_t b) {
 __global__ __launch_bounds__(256) void k_bin_block(BinArgs A) { bin_block(A, xcd_remap(blockIdx.x, gridDim.x)); }
 
 struct Block16Shared {
-    SuperShared g;      // gathering state; g.sup = block cap
-    float4 qcap[4][2];  // quadrant (super-tile) caps, super-tile layout
-    uint32_t qn[4];     // entries appended to quadrant q's list
+    SuperShared g;                // gathering state; g.sup = block cap
+    float4 qcap[4][2];            // quadrant (super-tile) caps, super-tile layout
+    uint32_t qn[4];               // entries appended to quadrant q's list
 };
 
 // 16x16 bin tiles from 32x32 blocks: the block cap gathers the candidates

@@ -25,6 +25,7 @@ namespace vsr {
 struct SceneView {
     const float4* rec;         // 4 x float4 per triangle, nearest-first (rank) order
     const float4* cap;         // 2 x float4 per triangle, rank order
+    const float4* rcap;        // binning cap (as bincap) per triangle, rank order
     const uint32_t* cell_list; // ranks sorted by (slice, cell)
     const uint32_t* cell_start;
     const float4* bincap;      // cell-ordered caps: centre, sine of half radius (kBinWide: wide)
@@ -39,6 +40,7 @@ __device__ inline SceneView scene_view(const void* setup, int64_t n) {
     SceneView s;
     s.rec = reinterpret_cast<const float4*>(b + L.rec_off);
     s.cap = reinterpret_cast<const float4*>(b + L.cap_off);
+    s.rcap = reinterpret_cast<const float4*>(b + L.rcap_off);
     s.cell_list = reinterpret_cast<const uint32_t*>(b + L.cell_list_off);
     s.cell_start = reinterpret_cast<const uint32_t*>(b + L.cell_start_off);
     s.bincap = reinterpret_cast<const float4*>(b + L.bincap_off);

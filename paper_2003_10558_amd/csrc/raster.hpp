@@ -22,7 +22,7 @@ namespace vsr {
 struct RasterArgs {
     const void* map;
     int64_t ntiles;
-    int32_t fmt, depth, W, H, ntx, pad;
+    int32_t fmt, depth, W, H, ntx, nty;
     const void* setup;
     int64_t n;
     const void* bins;
@@ -30,7 +30,6 @@ struct RasterArgs {
     float* out_depth;
     unsigned long long* stats;  // instrumented variant only: tests, covered, triangles, tiles
     int32_t no_early_exit;      // instrumented variant only: process whole lists
-    int32_t bin_tile;           // 8 or 16: edge of the bin tiles; 0: read it from the bin buffer's header
     Rot rot;                    // camera -> world
 
     __device__ inline void globalize() {
@@ -125,69 +124,6 @@ __device__ inline bool raster_list(const uint32_t* lst, uint32_t count, const fl
     return done;
 }
 
-// Rasterizes the entries of a 16x16 bin tile's list that may meet this 8x8
-// tile.  Lane l takes entry l of each 64-entry chunk, loads its cap and
-// record and keeps it when sub_may_see passes for the tile's cap (the test
-// the 8x8 binner applies, on the same binning cap and normals, so the
-// survivors are that binner's list for the tile, in the same depth-bucket
-// order); the survivors' records are compacted into LDS (stg: 256 float4)
-// and tested as in raster_list, with the same early exit.
-template <bool kStats>
-__device__ inline void raster_list_cull(const uint32_t* lst, uint32_t count, const SceneView& S, float4 tc0,
-                                        float4 tc1, float3 g, bool has_dir, uint64_t& best, float4* stg,
-                                        bool early_exit, unsigned long long& n_tri, unsigned long long& n_cov) {
-    const int lane = threadIdx.x & 63;
-    bool done = false;
-    for (uint32_t c0 = 0; c0 < count && !done; c0 += 64) {
-        const uint32_t e = c0 + uint32_t(lane);
-        const bool valid = e < count;
-        const uint32_t rank = valid ? lst[e] : lst[c0];
-        const float4 cp0 = S.cap[2 * int64_t(rank)], cp1 = S.cap[2 * int64_t(rank) + 1];
-        const float4* r = S.rec + 4 * int64_t(rank);
-        const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-        const float4 a = make_float4(cp0.x, cp0.y, cp0.z, (cp1.z == kCapWide) ? kBinWide : cp0.w);
-        const bool pass = valid && sub_may_see(tc0, tc1, a, bin_cos_half(a), f3(r0.x, r0.y, r0.z),
-                                               f3(r1.x, r1.y, r1.z), f3(r2.x, r2.y, r2.z));
-        const uint64_t bal = __ballot(pass);
-        const uint32_t ns = uint32_t(__popcll(bal));
-        if (pass) {
-            const uint32_t pos =
-                __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
-            stg[4 * pos] = r0;
-            stg[4 * pos + 1] = r1;
-            stg[4 * pos + 2] = r2;
-            stg[4 * pos + 3] = r3;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (uint32_t t8 = 0; t8 < ns; t8 += 4) {
-            if (early_exit) {
-                const float lb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(stg[4 * t8 + 3].w)));
-                const bool below = !has_dir || __uint_as_float(uint32_t(best >> 32)) < lb;
-                if (__ballot(!below) == 0) {
-                    done = true;
-                    break;
-                }
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < 4; ++u) {
-                const uint32_t t = t8 + u;
-                if (t < ns) {
-                    float4 c0v = stg[4 * t], c1v = stg[4 * t + 1], c2v = stg[4 * t + 2], c3v = stg[4 * t + 3];
-                    bool cov = raster_rec(c0v, c1v, c2v, c3v, g, best);
-                    if (kStats) {
-                        n_tri += 1;
-                        n_cov += __popcll(__ballot(cov));
-                    }
-                }
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    }
-}
-
 template <bool kStats>
 __device__ inline void raster_tile(const RasterArgs& A0, int64_t tile, int lane) {
     RasterArgs A = A0;
@@ -204,18 +140,10 @@ __device__ inline void raster_tile(const RasterArgs& A0, int64_t tile, int lane)
     float3 g = load_dir(A.map, A.fmt, A.ntiles, tile, lane, A.rot);
     bool has_dir = inside && (g.x != 0.0f || g.y != 0.0f || g.z != 0.0f);
     uint64_t best = kKeyEmpty;
-    // bin tile edge: from the bin buffer's header unless the caller gives it
-    const bool b16 = A.bin_tile == 16 || (A.bin_tile == 0 && reinterpret_cast<const uint32_t*>(bb)[kBinHdrTile] == 16u);
-    const int64_t list_idx = b16 ? int64_t(ty >> 1) * ((A.ntx + 1) >> 1) + (tx >> 1) : tile;
-    const uint32_t count = __builtin_amdgcn_readfirstlane(counts[list_idx]);  // uniform: scalar loop bounds
+    const uint32_t count = __builtin_amdgcn_readfirstlane(counts[tile]);  // uniform: scalar loop bounds
     unsigned long long n_tri = 0, n_cov = 0;
-    __shared__ float4 s_stage[4][256];
-    if (count <= uint32_t(A.depth) && b16) {
-        float4 tc0, tc1;
-        load_tile_cap(caps, tile, A.rot, tc0, tc1);
-        raster_list_cull<kStats>(lists + list_idx * A.depth, count, S, tc0, tc1, g, has_dir, best,
-                                 s_stage[threadIdx.x >> 6], !(kStats && A.no_early_exit), n_tri, n_cov);
-    } else if (count <= uint32_t(A.depth)) {
+    if (count <= uint32_t(A.depth)) {
+        __shared__ float4 s_stage[4][64];
         raster_list<kStats>(lists + tile * A.depth, count, S.rec, g, has_dir, best, s_stage[threadIdx.x >> 6],
                             !(kStats && A.no_early_exit), n_tri, n_cov);
     } else {
@@ -250,11 +178,149 @@ __device__ inline void raster_tile(const RasterArgs& A0, int64_t tile, int lane)
     }
 }
 
+// ------------------------------------------------ 16x16 bin tiles ------
+// One 256-thread workgroup per 16x16 super-tile, wave w on its tile w (2x2),
+// so the four waves read the same list entries (the later ones from cache).
+// Each wave walks the super-tile's list in chunks of 64: lane l takes entry
+// l, with its binning cap (rank order) and record, and keeps it when
+// sub_may_see passes for the tile's cap — the test the 8x8 binner applies,
+// on the same cap and normals, so the survivors are that binner's list for
+// the tile, in the same depth-bucket order.  Survivors' records are
+// compacted into LDS and tested as in raster_list (same early exit).  A
+// chunk is loaded only when the previous one did not end the tile: most
+// tiles stop within the first 64 entries, so loading the next chunk ahead
+// would mostly fetch entries nobody tests (measured: 32% slower).
+template <bool kStats>
+__device__ inline void raster_list_cull(const uint32_t* lst, uint32_t count, const SceneView& S, float4 tc0,
+                                        float4 tc1, float3 g, bool has_dir, uint64_t& best, float4* stg,
+                                        bool early_exit, unsigned long long& n_tri, unsigned long long& n_cov) {
+    const int lane = threadIdx.x & 63;
+    for (uint32_t c0 = 0; c0 < count; c0 += 64) {
+        const bool valid = c0 + uint32_t(lane) < count;
+        const uint32_t rank = lst[min(c0 + uint32_t(lane), count - 1u)];
+        const float4 a = S.rcap[rank];
+        const float4* rp = S.rec + 4 * int64_t(rank);
+        const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
+        const bool pass = valid && sub_may_see(tc0, tc1, a, bin_cos_half(a), f3(r0.x, r0.y, r0.z),
+                                               f3(r1.x, r1.y, r1.z), f3(r2.x, r2.y, r2.z));
+        const uint64_t bal = __ballot(pass);
+        const uint32_t ns = uint32_t(__popcll(bal));
+        if (pass) {
+            const uint32_t pos =
+                __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
+            stg[4 * pos] = r0;
+            stg[4 * pos + 1] = r1;
+            stg[4 * pos + 2] = r2;
+            stg[4 * pos + 3] = r3;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        bool done = false;
+        for (uint32_t t8 = 0; t8 < ns; t8 += 4) {
+            if (early_exit) {
+                const float lb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(stg[4 * t8 + 3].w)));
+                const bool below = !has_dir || __uint_as_float(uint32_t(best >> 32)) < lb;
+                if (__ballot(!below) == 0) {
+                    done = true;
+                    break;
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t t = t8 + u;
+                if (t < ns) {
+                    float4 c0v = stg[4 * t], c1v = stg[4 * t + 1], c2v = stg[4 * t + 2], c3v = stg[4 * t + 3];
+                    bool cov = raster_rec(c0v, c1v, c2v, c3v, g, best);
+                    if (kStats) {
+                        n_tri += 1;
+                        n_cov += __popcll(__ballot(cov));
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (done) break;
+    }
+}
+
+template <bool kStats>
+__device__ inline void raster_super16(const RasterArgs& A0, int64_t sidx) {
+    RasterArgs A = A0;
+    A.globalize();
+    __shared__ float4 s_stage[4][256];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int64_t tile;
+    int tx, ty;
+    if (!super_tile_of(sidx, w, A.ntx, A.nty, tile, tx, ty)) return;
+    const float4* caps = map_caps(A.map, A.ntiles, A.fmt);
+    SceneView S = scene_view(A.setup, A.n);
+    const char* bb = reinterpret_cast<const char*>(A.bins);
+    const uint32_t* counts = reinterpret_cast<const uint32_t*>(bb + 256);
+    const uint32_t* lists = reinterpret_cast<const uint32_t*>(bb + 256 + align256(A.ntiles * 4));
+    const int i = tx * kTile + (lane & (kTile - 1)), j = ty * kTile + (lane >> 3);
+    const bool inside = i < A.W && j < A.H;
+    const float3 g = load_dir(A.map, A.fmt, A.ntiles, tile, lane, A.rot);
+    const bool has_dir = inside && (g.x != 0.0f || g.y != 0.0f || g.z != 0.0f);
+    float4 tc0, tc1;
+    load_tile_cap(caps, tile, A.rot, tc0, tc1);
+    uint64_t best = kKeyEmpty;
+    unsigned long long n_tri = 0, n_cov = 0;
+    const uint32_t count = __builtin_amdgcn_readfirstlane(counts[sidx]);
+    if (count <= uint32_t(A.depth)) {
+        if (count > 0 && tc1.z != kCapEmpty)
+            raster_list_cull<kStats>(lists + sidx * A.depth, count, S, tc0, tc1, g, has_dir, best, s_stage[w],
+                                     !(kStats && A.no_early_exit), n_tri, n_cov);
+    } else {
+        // overflowed list: the tile gathers its own candidates
+        gather_candidates(S, tc0, tc1, lane, [&](uint32_t rank, bool valid) {
+            bool pass = valid && candidate_test(S, rank, tc0, tc1);
+            uint64_t mm = __ballot(pass);
+            while (mm) {
+                int q = __ffsll((unsigned long long)mm) - 1;
+                mm &= mm - 1;
+                uint32_t rk = uint32_t(__builtin_amdgcn_readlane(int(rank), q));
+                bool cov = raster_one(S.rec, rk, g, best);
+                if (kStats) {
+                    n_tri += 1;
+                    n_cov += __popcll(__ballot(cov));
+                }
+            }
+        });
+    }
+    const unsigned long long npix = kStats ? (unsigned long long)__popcll(__ballot(has_dir)) : 0ull;
+    if (kStats && lane == 0) {
+        atomicAdd(&A.stats[0], n_tri * npix);
+        atomicAdd(&A.stats[1], n_cov);
+        atomicAdd(&A.stats[2], n_tri);
+        atomicAdd(&A.stats[3], 1ull);
+    }
+    if (inside) {
+        int64_t o = int64_t(j) * A.W + i;
+        A.tri_id[o] = uint32_t(best & 0xFFFFFFFFull);
+        A.out_depth[o] = __uint_as_float(uint32_t(best >> 32));
+    }
+}
+
+// Plain rasterizer: the bin buffer's header says whether its lists are per
+// 8x8 tile (workgroups of 4 consecutive tiles) or per 16x16 super-tile (one
+// workgroup per super-tile); the grid covers the larger of the two counts.
 template <bool kStats>
 __global__ __launch_bounds__(256) void k_raster(RasterArgs A) {
+    const bool b16 = reinterpret_cast<const uint32_t*>(A.bins)[kBinHdrTile] == 16u;
+    if (b16) {
+        const int64_t nsx = (A.ntx + 1) / 2, nsup = nsx * ((A.nty + 1) / 2);
+        if (int64_t(blockIdx.x) >= nsup) return;
+        raster_super16<kStats>(A, band_remap(blockIdx.x, nsup, max(int64_t(1), nsx * kBandPx / (2 * kTile))));
+        return;
+    }
+    const int64_t nwg = (A.ntiles + 3) / 4;
+    if (int64_t(blockIdx.x) >= nwg) return;
     int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     // workgroups of 4 consecutive tiles, ntx tiles per row
-    int64_t tile = band_remap(blockIdx.x, gridDim.x, max(int64_t(1), int64_t(A.ntx) * kBandPx / (4 * kTile))) * 4 + w;
+    int64_t tile = band_remap(blockIdx.x, nwg, max(int64_t(1), int64_t(A.ntx) * kBandPx / (4 * kTile))) * 4 + w;
     if (tile >= A.ntiles) return;
     raster_tile<kStats>(A, tile, threadIdx.x & 63);
 }
@@ -271,7 +337,7 @@ hipError_t launch_raster(const void* map, int32_t W, int32_t H, int32_t fmt, con
     A.W = W;
     A.H = H;
     A.ntx = ML.ntx;
-    A.pad = 0;
+    A.nty = ML.nty;
     A.setup = setup;
     A.n = n;
     A.bins = bins;
@@ -279,9 +345,9 @@ hipError_t launch_raster(const void* map, int32_t W, int32_t H, int32_t fmt, con
     A.out_depth = out_depth;
     A.stats = stats;
     A.no_early_exit = no_early_exit;
-    A.bin_tile = 0;
     A.rot = R;
-    int64_t blocks = (ML.ntiles + 3) / 4;
+    // 4 tiles per workgroup (8x8 lists) or one super-tile (16x16 lists)
+    int64_t blocks = std::max((ML.ntiles + 3) / 4, int64_t((ML.ntx + 1) / 2) * ((ML.nty + 1) / 2));
     if (stats) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(stats), int64_t(8));
         hipLaunchKernelGGL(k_raster<true>, dim3(unsigned(blocks)), dim3(256), 0, st, A);

@@ -428,8 +428,9 @@ static hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t*
 __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ order_ids, int64_t n, int shift,
                                                  const float4* __restrict__ rec_id, const float4* __restrict__ cap_id,
                                                  const uint32_t* __restrict__ bucket, float4* __restrict__ rec,
-                                                 float4* __restrict__ cap, uint32_t* __restrict__ order,
-                                                 uint32_t* __restrict__ key2, uint32_t* __restrict__ val2) {
+                                                 float4* __restrict__ cap, float4* __restrict__ rcap,
+                                                 uint32_t* __restrict__ order, uint32_t* __restrict__ key2,
+                                                 uint32_t* __restrict__ val2) {
     int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n) return;
     uint32_t id = order_ids[r];
@@ -439,8 +440,11 @@ __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ or
     float4 r3 = rec_id[4 * int64_t(id) + 3];
     r3.w = rec_id[4 * int64_t(first_id) + 3].y;
     rec[4 * r + 3] = r3;
-    cap[2 * r + 0] = cap_id[2 * int64_t(id) + 0];
-    cap[2 * r + 1] = cap_id[2 * int64_t(id) + 1];
+    const float4 c0 = cap_id[2 * int64_t(id) + 0], c1 = cap_id[2 * int64_t(id) + 1];
+    cap[2 * r + 0] = c0;
+    cap[2 * r + 1] = c1;
+    // the binning cap (as in the cell-ordered copy), in rank order
+    rcap[r] = make_float4(c0.x, c0.y, c0.z, (c1.z == kCapWide) ? kBinWide : c0.w);
     order[r] = id;
     uint32_t b = bucket[id];
     key2[r] = b == uint32_t(kNumBuckets) ? uint32_t(kIndexKeys)
@@ -594,7 +598,8 @@ hipError_t launch_setup_common(int64_t n, void* setup, hipStream_t st, Prims pri
         uint32_t* k2 = in_b ? U(L.key_a_off) : U(L.key_b_off);
         uint32_t* v2 = in_b ? U(L.val_a_off) : U(L.val_b_off);
         hipLaunchKernelGGL(k_permute, dim3(blocks), dim3(256), 0, st, ids, n, bucket_shift(n), F4(L.rec_id_off),
-                           F4(L.cap_id_off), U(L.bucket_off), F4(L.rec_off), F4(L.cap_off), U(L.order_off), k2, v2);
+                           F4(L.cap_id_off), U(L.bucket_off), F4(L.rec_off), F4(L.cap_off), F4(L.rcap_off),
+                           U(L.order_off), k2, v2);
         // ids are no longer needed: the other pair is free scratch
         uint32_t* k3 = in_b ? U(L.key_b_off) : U(L.key_a_off);
         uint32_t* v3 = in_b ? U(L.val_b_off) : U(L.val_a_off);

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_submit_bin(const JobDesc* __restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
-                                                       int32_t depth, int64_t total, int32_t bin_tile) {
+                                                       int32_t depth, int64_t total) {
     int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     int64_t t = xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
     if (t >= total) return;
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict
     A.W = J.P.W;
     A.H = J.P.H;
     A.ntx = J.P.ntx;
-    A.pad = 0;
+    A.nty = J.P.nty;
     A.setup = J.setup;
     A.n = J.ntri;
     A.bins = J.bins;
@@ -250,9 +250,34 @@ __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict
     A.out_depth = J.depth;
     A.stats = nullptr;
     A.no_early_exit = 0;
-    A.bin_tile = bin_tile;
     A.rot = rot_of(J.P.rot);
     raster_tile<false>(A, t - J.tile_off, threadIdx.x & 63);
+}
+
+// 16x16 bin tiles: one workgroup per super-tile of every job
+__global__ __launch_bounds__(256) void k_submit_raster16(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
+                                                         int32_t depth) {
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int jb = find_job_super(T, njobs, t);
+    const JobDesc& J = T[jb];
+    RasterArgs A;
+    A.map = J.map;
+    A.ntiles = J.ntiles;
+    A.fmt = fmt;
+    A.depth = depth;
+    A.W = J.P.W;
+    A.H = J.P.H;
+    A.ntx = J.P.ntx;
+    A.nty = J.P.nty;
+    A.setup = J.setup;
+    A.n = J.ntri;
+    A.bins = J.bins;
+    A.tri_id = J.tri_id;
+    A.out_depth = J.depth;
+    A.stats = nullptr;
+    A.no_early_exit = 0;
+    A.rot = rot_of(J.P.rot);
+    raster_super16<false>(A, t - J.stile_off);
 }
 
 __global__ __launch_bounds__(256) void k_submit_fused(const JobDesc* __restrict__ T, int njobs, int32_t fmt) {
@@ -420,8 +445,11 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
             hipLaunchKernelGGL(k_submit_bin, dim3(unsigned(stiles)), dim3(256), size_t(kSupTiles) * cap * 4, st,
                                table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
         if (ev) (void)hipEventRecord(ev[2], st);
-        hipLaunchKernelGGL(k_submit_raster, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, fmt,
-                           depth, tiles, int32_t(t16 ? 16 : 8));
+        if (t16)
+            hipLaunchKernelGGL(k_submit_raster16, dim3(unsigned(stiles)), dim3(256), 0, st, table, njobs, fmt, depth);
+        else
+            hipLaunchKernelGGL(k_submit_raster, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, fmt,
+                               depth, tiles);
     }
     if (ev) (void)hipEventRecord(ev[3], st);
     return hipGetLastError();

@@ -133,7 +133,8 @@ struct MapParams {
 struct SetupLayout {
     int64_t n;
     int64_t nblocks;    // radix-sort blocks
-    int64_t rec_off, cap_off, cell_list_off, cell_start_off, order_off, bincap_off, binnrm_off, face_count_off;
+    int64_t rec_off, cap_off, rcap_off, cell_list_off, cell_start_off, order_off, bincap_off, binnrm_off,
+        face_count_off;
     int64_t rec_id_off, cap_id_off, key_a_off, val_a_off, key_b_off, val_b_off, bucket_off, hist_off;
     int64_t bytes;
 };
@@ -149,6 +150,7 @@ __host__ __device__ inline SetupLayout setup_layout(int64_t n) {
     int64_t o = 256;
     s.rec_off = o;        o += align256(n * 64);
     s.cap_off = o;        o += align256(n * 32);
+    s.rcap_off = o;       o += align256(n * 16);
     s.cell_list_off = o;  o += align256(n * 4);
     s.cell_start_off = o; o += align256((kIndexKeys + 1) * 4);
     s.face_count_off = o; o += align256(int64_t(kSlices) * 64 * 4);

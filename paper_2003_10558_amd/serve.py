@@ -108,11 +108,11 @@ class Server:
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         queue: collections.deque = collections.deque()
         free_slots = list(range(len(self.streams)))
-        inflight: List[tuple] = []   # (event, slot, reqs, bytes, batch)
+        inflight: List[tuple] = []   # (end event, slot, reqs, bytes, batch, start event)
         used = 0
         st = ServeStats(offered=len(requests), budget_bytes=self.budget)
         batch_sizes, queue_depths = [], []
-        intervals = []  # (start event, end event) per batch: its device interval
+        intervals = []  # (start, end) in ms after ref_ev per batch: its device interval
         ref_ev = torch.cuda.Event(enable_timing=True)
         ref_ev.record(self.streams[0])
         t0 = time.perf_counter()
@@ -123,8 +123,10 @@ class Server:
             # retire finished batches
             still = []
             for item in inflight:
-                ev, slot, reqs, nbytes, batch = item
+                ev, slot, reqs, nbytes, batch, ev0 = item
                 if ev.query():
+                    # device interval of the batch (the events are released here)
+                    intervals.append((ref_ev.elapsed_time(ev0), ref_ev.elapsed_time(ev)))
                     tdone = time.perf_counter() - t0
                     for q, r in enumerate(reqs):
                         r.done = tdone
@@ -175,12 +177,12 @@ class Server:
                     batch.submit(stream)
                     ev = torch.cuda.Event(enable_timing=True)
                     ev.record(stream)
-                intervals.append((ev0, ev))
+
                 for r in reqs:
                     r.admitted = tadm
                 used += nbytes
                 st.max_inflight_bytes = max(st.max_inflight_bytes, used)
-                inflight.append((ev, slot, reqs, nbytes, batch))
+                inflight.append((ev, slot, reqs, nbytes, batch, ev0))
                 batch_sizes.append(len(reqs))
                 admitted_any = True
             if not admitted_any:
@@ -192,7 +194,7 @@ class Server:
         torch.cuda.synchronize()
         # device intervals of the batches (ms after the reference event); a
         # batch overlaps when another batch's interval intersects its own
-        iv = np.array([(ref_ev.elapsed_time(a), ref_ev.elapsed_time(b)) for a, b in intervals]).reshape(-1, 2)
+        iv = np.array(intervals, dtype=np.float64).reshape(-1, 2)
         if len(iv):
             order = np.argsort(iv[:, 0])
             iv = iv[order]

@@ -102,22 +102,38 @@ def _dir(view, p):
     return view.rot_matrix() @ g
 
 
-def test_batched_64_views_500k(gpu):
+def test_batched_64_views_500k(gpu, tmp_path):
+    """64 mixed views of the 500k shell scene in one submit, in the mode, bin
+    tile size and depth the autotuner picks for them, and in every binned
+    variant (8x8 and 16x16 bin tiles) and the fused one: each view identical
+    to rendering it alone, sampled parity against the oracle."""
     torch, pipeline, vsr = gpu
+    from paper_2003_10558_amd import autotune
     tris = synth.scene_500k()
     scene = pipeline.Scene(tris)
     views = synth.random_views(64, 3)
-    _say("[batch64] fused submit of 64 mixed views")
-    batch = pipeline.Batch([(scene, v) for v in views], mode=vsr.VSR_SUBMIT_FUSED)
-    outs = batch.submit()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    batch.submit()
-    t1.record()
-    torch.cuda.synchronize()
-    _say(f"[batch64] fused submit {t0.elapsed_time(t1):.2f} ms for 64 views")
+    tuner = autotune.Tuner(str(tmp_path / "tune.json"), reps=2)
+    choice = tuner.choose(scene, views)
+    _say(f"[batch64] autotuner: {autotune.describe(choice)}; candidates (ms) {next(iter(tuner.cache.values()))['ms']}")
+    variants = [choice, (vsr.VSR_SUBMIT_BINNED, 1024), (vsr.VSR_SUBMIT_BINNED | vsr.VSR_SUBMIT_BIN_TILE16, 1024),
+                (vsr.VSR_SUBMIT_FUSED, 1024)]
+    results = []
+    for mode, depth in variants:
+        batch = pipeline.Batch([(scene, v) for v in views], mode=mode, bin_depth=depth)
+        outs = batch.submit()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        batch.submit()
+        t1.record()
+        torch.cuda.synchronize()
+        _say(f"[batch64] {autotune.describe((mode, depth))}: {t0.elapsed_time(t1):.2f} ms for 64 views")
+        results.append([(pipeline.ids_u32(i), d.cpu().numpy().view(np.uint32).copy()) for i, d in outs])
+    for r in results[1:]:
+        for (ai, ad), (bi, bd) in zip(results[0], r):
+            assert np.array_equal(ai, bi) and np.array_equal(ad, bd)
+    outs = batch.outputs
     # identical to rendering each view alone (binned path, large depth) on a few views
     for q in (0, 17, 42):
         v = views[q]

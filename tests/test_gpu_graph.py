@@ -34,7 +34,8 @@ def _views(seed):
     return vs
 
 
-@pytest.mark.parametrize("mode", [0x200, 0x400, 1], ids=["binned-blocks", "binned-supertiles", "fused"])
+@pytest.mark.parametrize("mode", [0x200, 0x400, 0xA00, 0xC00, 1],
+                         ids=["binned-blocks", "binned-supertiles", "tile16-blocks", "tile16-supertiles", "fused"])
 def test_graph_replays_match_eager(env, mode):
     torch, pipeline, vsr, autotune, scene = env
     g = pipeline.GraphBatch([(scene, v) for v in _views(1)], mode=mode, bin_depth=512)

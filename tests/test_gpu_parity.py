@@ -233,8 +233,8 @@ def test_overflow_falls_back(gpu, flags):
 
 def test_tile16_lists_are_the_union_of_tile_lists(gpu):
     """A 16x16 bin tile's list holds every triangle of its four 8x8 tiles'
-    lists (same depth-bucket order), and nothing the rasterizer's tile test
-    then drops makes a difference: same images on both binner shapes."""
+    lists, in depth-bucket order, on both binner shapes (the rasterizer
+    keeps each tile's share with the 8x8 binner's own test)."""
     view = synth.View(200, 150, -0.4, 0.3, 0.9, 300.0, 0, synth.yaw_pitch_rotation(1.0, 0.3))
     torch, pipeline, vsr = gpu
     scene = pipeline.Scene(synth.scene(20000, 5))
@@ -419,7 +419,7 @@ def test_map_is_orientation_free(gpu, fmt):
         assert st.ok(), st.notes
 
 
-@pytest.mark.parametrize("mode", [0x200, 0x400, 1], ids=["binned-blocks", "binned-supertiles", "fused"])
+@pytest.mark.parametrize("mode", [0x200, 0x400, 0xA00, 1], ids=["binned-blocks", "binned-supertiles", "tile16", "fused"])
 def test_submit_shares_lens_maps(gpu, mode):
     """A batch whose views repeat lenses in several orientations (maps built
     once per lens) renders every view exactly as alone."""
