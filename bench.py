@@ -537,9 +537,68 @@ def main():
     stage_map_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in stage_ev]))
     stage_bin_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in stage_ev]))
     stage_raster_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in stage_ev]))
-    log(f"batched step (setup + {len(views)} views): {step_ms:.3f} ms -> {views_per_s:.1f} views/s "
+    log(f"batched step, serial (setup + {len(views)} views): {step_ms:.3f} ms -> {views_per_s:.1f} views/s "
         f"(wall {wall:.3f}s for {args.steps} steps); stages: maps {stage_map_ms:.3f} ms, binner "
         f"{stage_bin_ms:.3f} ms, rasterizer {stage_raster_ms:.3f} ms")
+    serial = {"ms_per_step": step_ms, "views_per_s": views_per_s, "stage_ms": {
+        "maps": stage_map_ms, "binner": stage_bin_ms, "rasterizer": stage_raster_ms}}
+
+    # ---------------- the headline: the same steps pipelined.  Every step
+    # still runs its full setup and its submit inside the timed region, but
+    # the setup of step k+1 runs on a second stream while step k renders (two
+    # setup buffers of the scene and two batches alternate), so the setup's
+    # short, latency-bound kernels fill the chip beside the binner and the
+    # rasterizer.  A step's submit waits for its own setup; a setup waits for
+    # the submit that last read its buffer.
+    scene_b = pipeline.Scene(scene.xyz, device=dev)
+    batch_b = pipeline.Batch([(scene_b, v) for v in views], fmt=fmt, mode=choice[0], bin_depth=choice[1])
+    p_scenes, p_batches = [scene, scene_b], [batch, batch_b]
+    s_setup = torch.cuda.Stream(device=dev)
+
+    def pipelined(nsteps, stage=None, start=None):
+        done = [None, None]
+        if start is not None:
+            s_setup.wait_event(start)
+        for k in range(nsteps):
+            q = k % 2
+            with torch.cuda.stream(s_setup):
+                if done[q] is not None:
+                    s_setup.wait_event(done[q])
+                p_scenes[q].refresh(s_setup)
+                ready = torch.cuda.Event()
+                ready.record(s_setup)
+            stream.wait_event(ready)
+            p_batches[q].submit(stream, events=None if stage is None else stage[k])
+            fin = torch.cuda.Event()
+            fin.record(stream)
+            done[q] = fin
+
+    pipelined(max(2, args.warmup))
+    torch.cuda.synchronize()
+    stage_ev = [[ev() for _ in range(4)] for _ in range(args.steps)]
+    for evs in stage_ev:
+        for e in evs:
+            e.record(stream)
+    e_start, e_end = ev(), ev()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e_start.record(stream)
+    pipelined(args.steps, stage_ev, e_start)
+    e_end.record(stream)  # after the last submit, which waited for the last setup
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    step_ms = e_start.elapsed_time(e_end) / args.steps
+    views_per_s = len(views) / (step_ms / 1e3)
+    stage_map_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in stage_ev]))
+    stage_bin_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in stage_ev]))
+    stage_raster_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in stage_ev]))
+    pipelined_same = all(torch.equal(a[0], b[0]) and torch.equal(a[1].view(torch.int32), b[1].view(torch.int32))
+                         for a, b in zip(batch.outputs, batch_b.outputs))
+    log(f"batched step, setup pipelined with the previous step's rendering: {step_ms:.3f} ms -> {views_per_s:.1f} "
+        f"views/s (wall {wall:.3f}s for {args.steps} steps); stages: maps {stage_map_ms:.3f} ms, binner "
+        f"{stage_bin_ms:.3f} ms, rasterizer {stage_raster_ms:.3f} ms; both buffers' images identical: "
+        f"{pipelined_same}")
+    del batch_b, scene_b
     # outside the timed region: one view of the batch equals the plain path,
     # bit for bit (ids and depth), at the benchmark's own size and settings
     chk = views[5 % len(views)]
@@ -795,8 +854,11 @@ def main():
                    "views_per_step": len(views), "triangles": int(tris.shape[1]),
                    "submit_mode": tuned["mode"], "bin_tile": tuned["tile"], "bin_depth": tuned["bin_depth"],
                    "chosen_by": "autotuner" if not args.no_tune else "fixed (--no-tune)",
-                   "step": "vsr_setup_tris + vsr_submit(all views)"},
+                   "step": "vsr_setup_tris + vsr_submit(all views); the setup of the next step overlaps "
+                           "this step's submit on a second stream"},
         "batched_fps_with_setup": views_per_s,
+        "batched_serial": serial,
+        "pipelined_buffers_identical": pipelined_same,
         "batched_fps": len(views) / submit_ms * 1e3,
         "batched_fps_distinct_lenses": len(views) / dsubmit_ms * 1e3,
         "lens_maps_per_step": n_lens,

@@ -186,7 +186,8 @@ __device__ inline void raster_tile(const RasterArgs& A0, int64_t tile, int lane)
 // sub_may_see passes for the tile's cap — the test the 8x8 binner applies,
 // on the same cap and normals, so the survivors are that binner's list for
 // the tile, in the same depth-bucket order.  Survivors' records are
-// compacted into LDS and tested as in raster_list (same early exit).  A
+// compacted into LDS (word k of survivor p at stg[64 k + p]) and tested as
+// in raster_list (same early exit).  A
 // chunk is loaded only when the previous one did not end the tile: most
 // tiles stop within the first 64 entries, so loading the next chunk ahead
 // would mostly fetch entries nobody tests (measured: 32% slower).
@@ -196,6 +197,13 @@ __device__ inline void raster_list_cull(const uint32_t* lst, uint32_t count, con
                                         bool early_exit, unsigned long long& n_tri, unsigned long long& n_cov) {
     const int lane = threadIdx.x & 63;
     for (uint32_t c0 = 0; c0 < count; c0 += 64) {
+        if (c0 > 0 && early_exit) {
+            // before loading a chunk: every pixel may already beat the bucket
+            // bound of its first entry, which bounds all that follow
+            const uint32_t r0k = __builtin_amdgcn_readfirstlane(lst[c0]);
+            const float lb0 = S.rec[4 * int64_t(r0k) + 3].w;
+            if (__ballot(has_dir && !(__uint_as_float(uint32_t(best >> 32)) < lb0)) == 0) break;
+        }
         const bool valid = c0 + uint32_t(lane) < count;
         const uint32_t rank = lst[min(c0 + uint32_t(lane), count - 1u)];
         const float4 a = S.rcap[rank];
@@ -206,12 +214,14 @@ __device__ inline void raster_list_cull(const uint32_t* lst, uint32_t count, con
         const uint64_t bal = __ballot(pass);
         const uint32_t ns = uint32_t(__popcll(bal));
         if (pass) {
+            // word k of survivor p at stg[64 k + p]: consecutive lanes write
+            // consecutive 16-byte slots (no bank conflicts)
             const uint32_t pos =
                 __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
-            stg[4 * pos] = r0;
-            stg[4 * pos + 1] = r1;
-            stg[4 * pos + 2] = r2;
-            stg[4 * pos + 3] = r3;
+            stg[pos] = r0;
+            stg[64 + pos] = r1;
+            stg[128 + pos] = r2;
+            stg[192 + pos] = r3;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -219,7 +229,7 @@ __device__ inline void raster_list_cull(const uint32_t* lst, uint32_t count, con
         bool done = false;
         for (uint32_t t8 = 0; t8 < ns; t8 += 4) {
             if (early_exit) {
-                const float lb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(stg[4 * t8 + 3].w)));
+                const float lb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(stg[192 + t8].w)));
                 const bool below = !has_dir || __uint_as_float(uint32_t(best >> 32)) < lb;
                 if (__ballot(!below) == 0) {
                     done = true;
@@ -230,7 +240,7 @@ __device__ inline void raster_list_cull(const uint32_t* lst, uint32_t count, con
             for (uint32_t u = 0; u < 4; ++u) {
                 const uint32_t t = t8 + u;
                 if (t < ns) {
-                    float4 c0v = stg[4 * t], c1v = stg[4 * t + 1], c2v = stg[4 * t + 2], c3v = stg[4 * t + 3];
+                    float4 c0v = stg[t], c1v = stg[64 + t], c2v = stg[128 + t], c3v = stg[192 + t];
                     bool cov = raster_rec(c0v, c1v, c2v, c3v, g, best);
                     if (kStats) {
                         n_tri += 1;
