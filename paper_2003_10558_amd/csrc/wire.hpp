@@ -176,13 +176,16 @@ __device__ inline void wire_tile(const WireArgs& A0, int64_t tile, int lane, flo
     }
 }
 
-// Side caps of every live triangle, rank order (once per scene, after the
-// setup): the end points are the triangle's vertices in id order.
-__global__ __launch_bounds__(256) void k_setup_wire(const float4* __restrict__ rec, const float* __restrict__ xyz,
-                                                    int64_t n, float4* __restrict__ wire) {
-    int64_t rk = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (rk >= n) return;
-    const uint32_t id = __float_as_uint(rec[4 * rk + 3].z);
+// Side caps of every triangle, stored in rank order (once per scene, after
+// the setup): one thread per triangle id, so the [9][n] vertex rows are
+// read coalesced, and each thread writes its 64-byte entry at the
+// triangle's rank (one whole line).
+__global__ __launch_bounds__(256) void k_setup_wire(const uint32_t* __restrict__ rank_of,
+                                                    const float* __restrict__ xyz, int64_t n,
+                                                    float4* __restrict__ wire) {
+    const int64_t id = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const int64_t rk = rank_of[id];
     float3 V[3];
     for (int c = 0; c < 3; ++c) V[c] = f3(xyz[(3 * c + 0) * n + id], xyz[(3 * c + 1) * n + id], xyz[(3 * c + 2) * n + id]);
     float b[3];
@@ -192,14 +195,14 @@ __global__ __launch_bounds__(256) void k_setup_wire(const float4* __restrict__ r
         side_cap(V[e], V[e == 2 ? 0 : e + 1], L, a, b[e]);
         wire[4 * rk + e] = make_float4(L.x, L.y, L.z, a);
     }
-    wire[4 * rk + 3] = make_float4(b[0], b[1], b[2], __uint_as_float(id));
+    wire[4 * rk + 3] = make_float4(b[0], b[1], b[2], __uint_as_float(uint32_t(id)));
 }
 
 hipError_t launch_setup_wire(const void* setup, const float* xyz, int64_t n, void* wire, hipStream_t st) {
     if (n > 0) {
-        const float4* rec =
-            reinterpret_cast<const float4*>(static_cast<const char*>(setup) + setup_layout(n).rec_off);
-        hipLaunchKernelGGL(k_setup_wire, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, rec, xyz, n,
+        const uint32_t* rank_of =
+            reinterpret_cast<const uint32_t*>(static_cast<const char*>(setup) + setup_layout(n).rank_of_off);
+        hipLaunchKernelGGL(k_setup_wire, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, rank_of, xyz, n,
                            reinterpret_cast<float4*>(wire));
     }
     return hipGetLastError();
