@@ -99,8 +99,11 @@ def summarize(dirs):
             for row in csv.DictReader(open(f)):
                 name = row["Kernel_Name"].split("(")[0].replace("void ", "").strip()
                 key = (name, row["Counter_Name"])
-                counters.setdefault(key, {}).setdefault(row.get("Dispatch_Id", ""), 0.0)
-                counters[key][row.get("Dispatch_Id", "")] += float(row["Counter_Value"])
+                # rows of one dispatch add up; a counter taken in several runs
+                # (one directory each) keeps one entry per run and dispatch
+                disp = (f, row.get("Dispatch_Id", ""))
+                counters.setdefault(key, {}).setdefault(disp, 0.0)
+                counters[key][disp] += float(row["Counter_Value"])
     print(f"source {source_hash()}")
     for f in stats:
         rows = list(csv.DictReader(open(f)))
@@ -127,11 +130,22 @@ def summarize(dirs):
                             for c in cnames if (n, c) in mean)
             vals = vals.replace("fetch_size", "fetch_kib").replace("write_size", "write_kib")
             nd = max(len(counters[(n, c)]) for c in cnames if (n, c) in counters)
-            if (n, "SQ_INSTS_VALU") in mean and (n, "GRBM_GUI_ACTIVE") in mean:
-                # wave-level VALU issue slots: one per CU per cycle; the GRBM
-                # busy count is summed over the 8 XCDs
-                util = mean[(n, "SQ_INSTS_VALU")] / (256 * mean[(n, "GRBM_GUI_ACTIVE")] / 8)
-                vals += f" valu_issue_util {util:.3f}"
+            if (n, "GRBM_GUI_ACTIVE") in mean:
+                # busy fractions: SQ_ACTIVE_INST_VALU counts one quad-cycle
+                # per wave64 VALU instruction on its SIMD (4 SIMDs per CU) and
+                # SQ_ACTIVE_INST_VALU2 the quad-cycles in which a SIMD issued
+                # two, so their difference is the SIMD quad-cycles with VALU
+                # issue; SQ_LDS_IDX_ACTIVE counts cycles per CU; the GRBM busy
+                # count is summed over the 8 XCDs.  The FMA calibration kernel
+                # reads valu_busy 0.89 at 89% of the lane peak.
+                cu_cycles = 256 * mean[(n, "GRBM_GUI_ACTIVE")] / 8
+                if (n, "SQ_ACTIVE_INST_VALU") in mean:
+                    v2 = mean.get((n, "SQ_ACTIVE_INST_VALU2"), 0.0)
+                    vals += f" valu_busy {(mean[(n, 'SQ_ACTIVE_INST_VALU')] - v2) / cu_cycles:.3f}"
+                    if (n, "SQ_ACTIVE_INST_VALU2") in mean:
+                        vals += f" valu_dual_frac {v2 / max(1.0, mean[(n, 'SQ_ACTIVE_INST_VALU')]):.3f}"
+                if (n, "SQ_LDS_IDX_ACTIVE") in mean:
+                    vals += f" lds_busy {mean[(n, 'SQ_LDS_IDX_ACTIVE')] / cu_cycles:.3f}"
             print(f"kernel {n.replace(' ', '')} dispatches {nd} {vals}")
 
 
