@@ -129,7 +129,7 @@ def summarize(dirs):
             vals = " ".join(f"{c.lower() if c in ('FETCH_SIZE', 'WRITE_SIZE') else c} {mean[(n, c)]:.6g}"
                             for c in cnames if (n, c) in mean)
             vals = vals.replace("fetch_size", "fetch_kib").replace("write_size", "write_kib")
-            nd = max(len(counters[(n, c)]) for c in cnames if (n, c) in counters)
+            nd = max(len({d for _, d in counters[(n, c)]}) for c in cnames if (n, c) in counters)
             if (n, "GRBM_GUI_ACTIVE") in mean:
                 # busy fractions: SQ_ACTIVE_INST_VALU counts one quad-cycle
                 # per wave64 VALU instruction on its SIMD (4 SIMDs per CU) and
@@ -686,6 +686,28 @@ def main():
         f"binner {t16_bin_ms:.3f} ms, rasterizer {t16_raster_ms:.3f} ms; overflowed "
         f"{vsr.vsr_bin_overflow(tbatch.workspace, True)}; images identical to 8x8 bins: {t16_same}")
     del tbatch
+    # the tuned step with the persistent rasterizer (work counters) in place
+    # of one workgroup per tile group: same images, measured beside it
+    pbatch = pipeline.Batch([(scene, v) for v in views], fmt=fmt, mode=choice[0] | vsr.VSR_SUBMIT_PERSISTENT,
+                            bin_depth=choice[1])
+    pbatch.submit()
+    torch.cuda.synchronize()
+    p_ev = [[ev() for _ in range(4)] for _ in range(args.steps)]
+    for evs in p_ev:
+        for e in evs:
+            e.record(stream)
+    torch.cuda.synchronize()
+    for k in range(args.steps):
+        pbatch.submit(events=p_ev[k])
+    torch.cuda.synchronize()
+    p_raster_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in p_ev]))
+    p_same = all(torch.equal(a[0], b[0]) and torch.equal(a[1].view(torch.int32), b[1].view(torch.int32))
+                 for a, b in zip(pbatch.outputs, batch.outputs))
+    grid_raster_ms = serial["stage_ms"]["rasterizer"]
+    log(f"persistent rasterizer: {p_raster_ms:.3f} ms against {grid_raster_ms:.3f} ms for the per-tile grid; "
+        f"images identical: {p_same}")
+    persistent = {"rasterizer_ms": p_raster_ms, "grid_rasterizer_ms": grid_raster_ms, "identical_images": p_same}
+    del pbatch
     # the fused depth-sliced batch on the same views
     fbatch = pipeline.Batch([(scene, v) for v in views], fmt=fmt, mode=vsr.VSR_SUBMIT_FUSED)
     fbatch.submit()
@@ -888,6 +910,7 @@ def main():
         "overflowed_tiles_plain": overflow,
         "fused_fps": 1e3 / fused_ms,
         "batched_fused_fps": len(views) / fsubmit_ms * 1e3,
+        "batched_persistent": persistent,
         "batched_other_tile": {"tile": 16 if other16 else 8, "fps_with_setup": len(views) / t16_step_ms * 1e3,
                                "binner_ms": t16_bin_ms, "rasterizer_ms": t16_raster_ms,
                                "identical_images": t16_same},

@@ -470,6 +470,12 @@ int vsr_submit_timed(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mo
 #define VSR_SUBMIT_BIN_SUPERTILES 0x400
 /* 16x16 bin tiles for a binned submit (see VSR_BIN_TILE16). */
 #define VSR_SUBMIT_BIN_TILE16 0x800
+/* Binned submit: the rasterizer runs as a persistent grid (about as many
+ * workgroups as the device holds at once) whose waves take tiles from work
+ * counters kept in the workspace header, instead of one workgroup per four
+ * tiles or per super-tile.  Same images; only the schedule differs.  No
+ * effect on VSR_SUBMIT_FUSED. */
+#define VSR_SUBMIT_PERSISTENT 0x1000
 int64_t vsr_submit_table_bytes(int32_t njobs);
 int64_t vsr_submit_table_offset(void);
 int vsr_submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth,

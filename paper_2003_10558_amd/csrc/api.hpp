@@ -548,7 +548,8 @@ int vsr_resolve_packed(const vsr_view* v, int32_t fmt, const void* map, const vo
 int64_t vsr_submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mode, int32_t bin_depth) {
     if (!jobs || njobs < 1 || njobs > 4096) return VSR_E_ARG;
     if (fmt != VSR_MAP_F32 && fmt != VSR_MAP_OCT16) return VSR_E_ARG;
-    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES | VSR_SUBMIT_BIN_TILE16);
+    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES | VSR_SUBMIT_BIN_TILE16 |
+              VSR_SUBMIT_PERSISTENT);
     if (mode != VSR_SUBMIT_BINNED && mode != VSR_SUBMIT_FUSED) return VSR_E_ARG;
     if (mode == VSR_SUBMIT_BINNED && (bin_depth < 1 || bin_depth > kMaxDepth)) return VSR_E_ARG;
     for (int32_t q = 0; q < njobs; ++q) {
@@ -570,7 +571,8 @@ int vsr_submit_table(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mo
     if (!jobs || njobs < 1 || njobs > 4096) return fail(VSR_E_ARG, "njobs %d outside 1..4096", njobs);
     if (!workspace || !aligned(workspace) || !host_table) return fail(VSR_E_ARG, "NULL or misaligned buffer");
     if (host_table_bytes < submit_table_bytes(njobs)) return fail(VSR_E_SPACE, "host table too small");
-    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES | VSR_SUBMIT_BIN_TILE16);
+    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES | VSR_SUBMIT_BIN_TILE16 |
+              VSR_SUBMIT_PERSISTENT);
     for (int32_t q = 0; q < njobs; ++q) {
         MapParams P;
         int rc = make_map_params(&jobs[q].view, fmt, 0, &P, nullptr);
@@ -587,9 +589,11 @@ static int submit_common(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
     if (mode & VSR_SUBMIT_BIN_BLOCKS) shape |= VSR_BIN_BLOCKS;
     if (mode & VSR_SUBMIT_BIN_SUPERTILES) shape |= VSR_BIN_SUPERTILES;
     if (mode & VSR_SUBMIT_BIN_TILE16) shape |= VSR_BIN_TILE16;
-    if (shape == (VSR_BIN_BLOCKS | VSR_BIN_SUPERTILES))
+    if (mode & VSR_SUBMIT_PERSISTENT) shape |= kShapePersistent;
+    if ((shape & ~kShapePersistent) == (VSR_BIN_BLOCKS | VSR_BIN_SUPERTILES))
         return fail(VSR_E_ARG, "VSR_SUBMIT_BIN_BLOCKS and VSR_SUBMIT_BIN_SUPERTILES together");
-    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES | VSR_SUBMIT_BIN_TILE16);
+    mode &= ~(VSR_SUBMIT_TABLE_READY | VSR_SUBMIT_BIN_BLOCKS | VSR_SUBMIT_BIN_SUPERTILES | VSR_SUBMIT_BIN_TILE16 |
+              VSR_SUBMIT_PERSISTENT);
     if (!jobs || njobs < 1 || njobs > 4096) return fail(VSR_E_ARG, "njobs %d outside 1..4096", njobs);
     if (mode != VSR_SUBMIT_BINNED && mode != VSR_SUBMIT_FUSED) return fail(VSR_E_ARG, "unknown submit mode %d", mode);
     if (mode == VSR_SUBMIT_BINNED && (bin_depth < 1 || bin_depth > kMaxDepth))

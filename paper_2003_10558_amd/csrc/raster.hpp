@@ -256,12 +256,10 @@ __device__ inline void raster_list_cull(const uint32_t* lst, uint32_t count, con
 }
 
 template <bool kStats>
-__device__ inline void raster_super16(const RasterArgs& A0, int64_t sidx) {
+__device__ inline void raster_quad16(const RasterArgs& A0, int64_t sidx, int w, float4* stg) {
     RasterArgs A = A0;
     A.globalize();
-    __shared__ float4 s_stage[4][256];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = threadIdx.x & 63;
     int64_t tile;
     int tx, ty;
     if (!super_tile_of(sidx, w, A.ntx, A.nty, tile, tx, ty)) return;
@@ -281,7 +279,7 @@ __device__ inline void raster_super16(const RasterArgs& A0, int64_t sidx) {
     const uint32_t count = __builtin_amdgcn_readfirstlane(counts[sidx]);
     if (count <= uint32_t(A.depth)) {
         if (count > 0 && tc1.z != kCapEmpty)
-            raster_list_cull<kStats>(lists + sidx * A.depth, count, S, tc0, tc1, g, has_dir, best, s_stage[w],
+            raster_list_cull<kStats>(lists + sidx * A.depth, count, S, tc0, tc1, g, has_dir, best, stg,
                                      !(kStats && A.no_early_exit), n_tri, n_cov);
     } else {
         // overflowed list: the tile gathers its own candidates
@@ -312,6 +310,14 @@ __device__ inline void raster_super16(const RasterArgs& A0, int64_t sidx) {
         A.tri_id[o] = uint32_t(best & 0xFFFFFFFFull);
         A.out_depth[o] = __uint_as_float(uint32_t(best >> 32));
     }
+}
+
+// Wave w of the workgroup on tile w of super-tile sidx.
+template <bool kStats>
+__device__ inline void raster_super16(const RasterArgs& A, int64_t sidx) {
+    __shared__ float4 s_stage[4][256];
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    raster_quad16<kStats>(A, sidx, w, s_stage[w]);
 }
 
 // Plain rasterizer: the bin buffer's header says whether its lists are per

@@ -20,6 +20,7 @@
 #include <array>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "fused.hpp"
@@ -59,13 +60,19 @@ __global__ void k_write_jobs(JobChunk c, JobDesc* table) {
     if (q < c.count) table[c.first + q] = c.d[q];
 }
 
+// Work counters of the persistent rasterizers, 64 bytes apart.
+constexpr int kWorkRanges = 8;
+
+// Workspace: 256-byte status header (word 0: overflowed tiles), the work
+// counters, the job table, then the jobs' maps and bins.
 struct WsLayout {
-    int64_t table_off, data_off, bytes;
+    int64_t ctr_off, table_off, data_off, bytes;
 };
 
 static WsLayout ws_layout(int32_t njobs) {
     WsLayout w;
-    w.table_off = 256;
+    w.ctr_off = 256;
+    w.table_off = w.ctr_off + int64_t(kWorkRanges) * 64;
     w.data_off = w.table_off + align256(int64_t(njobs) * int64_t(sizeof(JobDesc)));
     w.bytes = w.data_off;
     return w;
@@ -280,6 +287,128 @@ __global__ __launch_bounds__(256) void k_submit_raster16(const JobDesc* __restri
     raster_super16<false>(A, t - J.stile_off);
 }
 
+// Persistent rasterizers (VSR_SUBMIT_PERSISTENT): a grid of about as many
+// workgroups as are resident at once; each wave takes runs of kWorkChunk
+// work items (an 8x8 tile; with 16x16 lists a (super-tile, quadrant) pair,
+// the four quadrants of a super-tile being consecutive items) from work
+// counters until none are left.  The items are split into kWorkRanges
+// contiguous ranges with a counter each; range r belongs to XCD r mod kXcds
+// (workgroup b runs on XCD b mod kXcds), and a wave visits every range once,
+// its XCD's first, so neighbouring tiles, which share triangles, meet in one
+// L2.  Within a range the items come in increasing order, so a wave finds
+// each item's job by walking forward from the last one (a binary search
+// only after a move).  The counters sit in the workspace (zeroed by the
+// submit); the per-tile work is the grid kernels', so the images are the
+// same.  Measured slower than the grid kernels on 64 1080p views (the
+// vector memory counter covers loads and stores alike, so the first load
+// wait of each tile also waits for the previous tile's output stores, and
+// the loop needs more registers); kept as a measured alternative.
+constexpr int kXcds = 8;
+constexpr uint32_t kShapePersistent = 0x10000u;
+constexpr int kPersistentWgPerCu = 8;
+constexpr uint32_t kWorkChunk = 16;
+
+// Compute units of the current device (cached per device).
+static int device_cus() {
+    static std::mutex mu;
+    static std::map<int, int> cus;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cus.find(dev);
+    if (it != cus.end()) return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+    cus.emplace(dev, n);
+    return n;
+}
+
+template <int64_t JobDesc::*Off>
+__device__ inline int advance_job(const JobDesc* __restrict__ T, int njobs, int jb, int64_t t) {
+    if (jb < 0 || t < T[jb].*Off) return find_off<Off>(T, njobs, t);
+    while (jb + 1 < njobs && T[jb + 1].*Off <= t) ++jb;
+    return jb;
+}
+
+// Next run of up to kWorkChunk items [t, t_end) for the calling wave;
+// false when it has visited every range.  j counts the ranges visited (the
+// wave's j-th range is its XCD's, then the next XCD's, ... starting at the
+// wave's own slot k0); jb is reset on a move.
+__device__ inline bool next_items(uint32_t* __restrict__ ctr, int64_t items, int xcd, int k0, int& j, int& jb,
+                                  int64_t& t, int64_t& t_end) {
+    constexpr int kPer = kWorkRanges / kXcds;
+    const int64_t per = (items + kWorkRanges - 1) / kWorkRanges;
+    while (j < kWorkRanges) {
+        const int r = (xcd + j / kPer) % kXcds + kXcds * ((k0 + j) % kPer);
+        uint32_t i = 0;
+        if ((threadIdx.x & 63) == 0) i = atomicAdd(&ctr[16 * r], kWorkChunk);
+        i = __builtin_amdgcn_readfirstlane(i);
+        const int64_t end = min(int64_t(r + 1) * per, items);
+        t = int64_t(r) * per + int64_t(i);
+        if (int64_t(i) < per && t < end) {
+            t_end = min(t + int64_t(kWorkChunk), end);
+            return true;
+        }
+        ++j;
+        jb = -1;
+    }
+    return false;
+}
+
+__device__ inline RasterArgs submit_raster_args(const JobDesc& J, int32_t fmt, int32_t depth) {
+    RasterArgs A;
+    A.map = J.map;
+    A.ntiles = J.ntiles;
+    A.fmt = fmt;
+    A.depth = depth;
+    A.W = J.P.W;
+    A.H = J.P.H;
+    A.ntx = J.P.ntx;
+    A.nty = J.P.nty;
+    A.setup = J.setup;
+    A.n = J.ntri;
+    A.bins = J.bins;
+    A.tri_id = J.tri_id;
+    A.out_depth = J.depth;
+    A.stats = nullptr;
+    A.no_early_exit = 0;
+    A.rot = rot_of(J.P.rot);
+    return A;
+}
+
+__global__ __launch_bounds__(256) void k_submit_raster_p(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
+                                                         int32_t depth, int64_t items, uint32_t* __restrict__ ctr) {
+    const int xcd = int(blockIdx.x % kXcds);
+    const int k0 = int((blockIdx.x / kXcds) * 4 + (threadIdx.x >> 6)) % (kWorkRanges / kXcds);
+    int j = 0, jb = -1;
+    int64_t t0, t1;
+    while (next_items(ctr, items, xcd, k0, j, jb, t0, t1)) {
+        for (int64_t t = t0; t < t1; ++t) {
+            jb = advance_job<&JobDesc::tile_off>(T, njobs, jb, t);
+            const JobDesc& J = T[jb];
+            raster_tile<false>(submit_raster_args(J, fmt, depth), t - J.tile_off, threadIdx.x & 63);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_submit_raster16_p(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
+                                                           int32_t depth, int64_t items, uint32_t* __restrict__ ctr) {
+    __shared__ float4 s_stage[4][256];
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int xcd = int(blockIdx.x % kXcds);
+    const int k0 = int((blockIdx.x / kXcds) * 4 + (threadIdx.x >> 6)) % (kWorkRanges / kXcds);
+    int j = 0, jb = -1;
+    int64_t t0, t1;
+    while (next_items(ctr, items, xcd, k0, j, jb, t0, t1)) {
+        for (int64_t t = t0; t < t1; ++t) {
+            const int64_t sidx = t >> 2;
+            jb = advance_job<&JobDesc::stile_off>(T, njobs, jb, sidx);
+            const JobDesc& J = T[jb];
+            raster_quad16<false>(submit_raster_args(J, fmt, depth), sidx - J.stile_off, int(t & 3), s_stage[w]);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_submit_fused(const JobDesc* __restrict__ T, int njobs, int32_t fmt) {
     int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     int jb = find_job_super(T, njobs, t);
@@ -445,11 +574,26 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
             hipLaunchKernelGGL(k_submit_bin, dim3(unsigned(stiles)), dim3(256), size_t(kSupTiles) * cap * 4, st,
                                table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
         if (ev) (void)hipEventRecord(ev[2], st);
-        if (t16)
+        if (shape & kShapePersistent) {
+            // as many workgroups as are resident at once, at most one wave
+            // per item
+            const int64_t items = t16 ? 4 * stiles : tiles;
+            const int64_t wgs = std::min(int64_t(device_cus()) * kPersistentWgPerCu, (items + 3) / 4);
+            uint32_t* ctr = reinterpret_cast<uint32_t*>(base + W.ctr_off);
+            hipLaunchKernelGGL(k_zero_u32, dim3(unsigned(kWorkRanges * 16 / 64)), dim3(64), 0, st, ctr,
+                               int64_t(kWorkRanges) * 16);
+            if (t16)
+                hipLaunchKernelGGL(k_submit_raster16_p, dim3(unsigned(wgs)), dim3(256), 0, st, table, njobs, fmt,
+                                   depth, items, ctr);
+            else
+                hipLaunchKernelGGL(k_submit_raster_p, dim3(unsigned(wgs)), dim3(256), 0, st, table, njobs, fmt,
+                                   depth, items, ctr);
+        } else if (t16) {
             hipLaunchKernelGGL(k_submit_raster16, dim3(unsigned(stiles)), dim3(256), 0, st, table, njobs, fmt, depth);
-        else
+        } else {
             hipLaunchKernelGGL(k_submit_raster, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, fmt,
                                depth, tiles);
+        }
     }
     if (ev) (void)hipEventRecord(ev[3], st);
     return hipGetLastError();

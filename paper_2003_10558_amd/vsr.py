@@ -28,6 +28,7 @@ VSR_NO_HIT = 0xFFFFFFFF
 VSR_SUBMIT_BINNED, VSR_SUBMIT_FUSED = 0, 1
 VSR_SUBMIT_TABLE_READY = 0x100
 VSR_SUBMIT_BIN_BLOCKS, VSR_SUBMIT_BIN_SUPERTILES, VSR_SUBMIT_BIN_TILE16 = 0x200, 0x400, 0x800
+VSR_SUBMIT_PERSISTENT = 0x1000
 VSR_TILE = 8
 VSR_RESOLVE_NORMALIZE3 = 1
 VSR_AOV_HORIZONTAL, VSR_AOV_DIAGONAL, VSR_AOV_VERTICAL, VSR_AOV_HORIZONTAL_4X3 = 0, 1, 2, 3

@@ -23,7 +23,7 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU only" in r.stderr and r.stdout == ""
 
 
-def _write_csvs(tmp_path, fetch_kib, write_kib, valu, grbm):
+def _write_csvs(tmp_path, fetch_kib, write_kib, valu, valu2, lds, grbm):
     kt = tmp_path / "kt"
     kt.mkdir()
     (kt / "run_kernel_stats.csv").write_text(
@@ -36,13 +36,23 @@ def _write_csvs(tmp_path, fetch_kib, write_kib, valu, grbm):
             f'1,"{NEG}",FETCH_SIZE,{0.5 * calib_kib}', f'1,"{NEG}",WRITE_SIZE,{calib_kib}']
     for d in (2, 3):  # two dispatches of the binner, averaged
         rows += [f'{d},"{BIN}",FETCH_SIZE,{fetch_kib[d - 2]}', f'{d},"{BIN}",WRITE_SIZE,{write_kib}',
-                 f'{d},"{BIN}",SQ_INSTS_VALU,{valu}', f'{d},"{BIN}",GRBM_GUI_ACTIVE,{grbm}']
+                 f'{d},"{BIN}",SQ_ACTIVE_INST_VALU,{valu}', f'{d},"{BIN}",SQ_ACTIVE_INST_VALU2,{valu2}',
+                 f'{d},"{BIN}",GRBM_GUI_ACTIVE,{grbm}']
     (pmc / "run_counter_collection.csv").write_text("\n".join(rows) + "\n")
+    # a second counter run of the same program: GRBM_GUI_ACTIVE again (the
+    # two runs' values are averaged, not added) beside the LDS counter
+    pmc2 = pmc / "second"
+    pmc2.mkdir()
+    rows = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+    for d in (2, 3):
+        rows += [f'{d},"{BIN}",SQ_LDS_IDX_ACTIVE,{lds}', f'{d},"{BIN}",GRBM_GUI_ACTIVE,{grbm}']
+    (pmc2 / "run_counter_collection.csv").write_text("\n".join(rows) + "\n")
     return kt, pmc
 
 
 def test_summary_and_traffic(tmp_path, capsys, monkeypatch):
-    kt, pmc = _write_csvs(tmp_path, fetch_kib=(900.0, 1100.0), write_kib=200.0, valu=6.4e6, grbm=1.0e6)
+    kt, pmc = _write_csvs(tmp_path, fetch_kib=(900.0, 1100.0), write_kib=200.0, valu=6.4e6, valu2=0.4e6,
+                          lds=3.2e6, grbm=1.0e6)
     bench.summarize([str(kt), str(pmc)])
     out = capsys.readouterr().out
     lines = out.splitlines()
@@ -54,8 +64,11 @@ def test_summary_and_traffic(tmp_path, capsys, monkeypatch):
     kern = [ln for ln in lines if ln.startswith("kernel vsr::k_bin")][0].split()
     vals = dict(zip(kern[2::2], kern[3::2]))
     assert vals["dispatches"] == "2" and float(vals["fetch_kib"]) == 1000.0 and float(vals["write_kib"]) == 200.0
-    # 6.4e6 wave instructions over 256 CUs x 1e6 / 8 busy cycles per XCD
-    assert float(vals["valu_issue_util"]) == pytest.approx(6.4e6 / (256 * 1.0e6 / 8))
+    # SIMD quad-cycles with VALU issue (6.4e6 - 0.4e6 dual) over 256 CUs x
+    # 1e6 / 8 busy cycles per XCD; LDS cycles over the same
+    assert float(vals["valu_busy"]) == pytest.approx(6.0e6 / (256 * 1.0e6 / 8), abs=1e-3)
+    assert float(vals["lds_busy"]) == pytest.approx(3.2e6 / (256 * 1.0e6 / 8), abs=1e-3)
+    assert float(vals["GRBM_GUI_ACTIVE"]) == pytest.approx(1.0e6)
 
     prof = tmp_path / "profiles"
     prof.mkdir()

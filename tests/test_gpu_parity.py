@@ -359,8 +359,9 @@ def test_depth_lower_bound_below_cone_minimum(gpu):
     assert np.median(ratio) > 0.9999
 
 
-@pytest.mark.parametrize("mode", [0x200, 0x400, 0xA00, 0xC00, 1],
-                         ids=["binned-blocks", "binned-supertiles", "tile16-blocks", "tile16-supertiles", "fused"])
+@pytest.mark.parametrize("mode", [0x200, 0x400, 0xA00, 0xC00, 0x1200, 0x1A00, 1],
+                         ids=["binned-blocks", "binned-supertiles", "tile16-blocks", "tile16-supertiles",
+                              "persistent", "persistent-tile16", "fused"])
 def test_submit_matches_single_views(gpu, mode):
     torch, pipeline, vsr = gpu
     tris = synth.scene(3000, 23)
