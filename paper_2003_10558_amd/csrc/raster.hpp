@@ -69,16 +69,18 @@ __device__ inline bool raster_one(const float4* __restrict__ rec, uint32_t rank,
 // lane's pixel (all lanes of the wave call it with the same list).  With
 // early_exit, stops once every pixel with a direction holds a depth below
 // the current triangle's bucket bound.  Returns true when it stopped early.
+// pre0/pre1 are lst[sub] and lst[16 + sub] (sub = lane / 4) when the
+// caller loaded them already (each only read where below count).
 template <bool kStats>
 __device__ inline bool raster_list(const uint32_t* lst, uint32_t count, const float4* __restrict__ rec, float3 g,
                                    bool has_dir, uint64_t& best, float4* stg, bool early_exit,
-                                   unsigned long long& n_tri, unsigned long long& n_cov) {
+                                   unsigned long long& n_tri, unsigned long long& n_cov, const uint32_t* pre = nullptr) {
     const int lane = threadIdx.x & 63;
     const uint32_t ngroups = (count + 15u) >> 4;
     const uint32_t sub = uint32_t(lane) >> 2, part = uint32_t(lane) & 3u;
-    uint32_t rk = sub < count ? lst[sub] : 0u;
+    uint32_t rk = sub < count ? (pre ? pre[0] : lst[sub]) : 0u;
     float4 v = rec[4 * int64_t(rk) + part];
-    rk = 16u + sub < count ? lst[16u + sub] : 0u;
+    rk = 16u + sub < count ? (pre ? pre[1] : lst[16u + sub]) : 0u;
     bool done = false;
     for (uint32_t gi = 0; gi < ngroups && !done; ++gi) {
         stg[lane] = v;
@@ -140,12 +142,18 @@ __device__ inline void raster_tile(const RasterArgs& A0, int64_t tile, int lane)
     float3 g = load_dir(A.map, A.fmt, A.ntiles, tile, lane, A.rot);
     bool has_dir = inside && (g.x != 0.0f || g.y != 0.0f || g.z != 0.0f);
     uint64_t best = kKeyEmpty;
+    // the first list words are requested together with the count (in
+    // bounds whatever the count; used only below it), one round trip less
+    const uint32_t* lst = lists + tile * A.depth;
+    const uint32_t dm = uint32_t(A.depth) - 1u, sub = uint32_t(lane) >> 2;
+    const uint32_t pre[2] = {lst[min(sub, dm)], lst[min(16u + sub, dm)]};
     const uint32_t count = __builtin_amdgcn_readfirstlane(counts[tile]);  // uniform: scalar loop bounds
+    asm volatile("" ::"v"(pre[0]), "v"(pre[1]), "s"(count));  // in flight together
     unsigned long long n_tri = 0, n_cov = 0;
     if (count <= uint32_t(A.depth)) {
         __shared__ float4 s_stage[4][64];
-        raster_list<kStats>(lists + tile * A.depth, count, S.rec, g, has_dir, best, s_stage[threadIdx.x >> 6],
-                            !(kStats && A.no_early_exit), n_tri, n_cov);
+        raster_list<kStats>(lst, count, S.rec, g, has_dir, best, s_stage[threadIdx.x >> 6],
+                            !(kStats && A.no_early_exit), n_tri, n_cov, pre);
     } else {
         float4 tc0, tc1;
         load_tile_cap(caps, tile, A.rot, tc0, tc1);
@@ -194,7 +202,9 @@ __device__ inline void raster_tile(const RasterArgs& A0, int64_t tile, int lane)
 template <bool kStats>
 __device__ inline void raster_list_cull(const uint32_t* lst, uint32_t count, const SceneView& S, float4 tc0,
                                         float4 tc1, float3 g, bool has_dir, uint64_t& best, float4* stg,
-                                        bool early_exit, unsigned long long& n_tri, unsigned long long& n_cov) {
+                                        bool early_exit, unsigned long long& n_tri, unsigned long long& n_cov,
+                                        uint32_t pre) {
+    // pre: lst[lane], loaded by the caller with the count (read below it only)
     const int lane = threadIdx.x & 63;
     for (uint32_t c0 = 0; c0 < count; c0 += 64) {
         if (c0 > 0 && early_exit) {
@@ -205,7 +215,7 @@ __device__ inline void raster_list_cull(const uint32_t* lst, uint32_t count, con
             if (__ballot(has_dir && !(__uint_as_float(uint32_t(best >> 32)) < lb0)) == 0) break;
         }
         const bool valid = c0 + uint32_t(lane) < count;
-        const uint32_t rank = lst[min(c0 + uint32_t(lane), count - 1u)];
+        const uint32_t rank = c0 == 0 ? (valid ? pre : 0u) : lst[min(c0 + uint32_t(lane), count - 1u)];
         const float4 a = S.rcap[rank];
         const float4* rp = S.rec + 4 * int64_t(rank);
         const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
@@ -276,11 +286,18 @@ __device__ inline void raster_quad16(const RasterArgs& A0, int64_t sidx, int w, 
     load_tile_cap(caps, tile, A.rot, tc0, tc1);
     uint64_t best = kKeyEmpty;
     unsigned long long n_tri = 0, n_cov = 0;
+    // the first 64 list words are requested together with the count (in
+    // bounds whatever the count; used only below it), one round trip less
+    const uint32_t* lst = lists + sidx * A.depth;
+    const uint32_t pre = lst[min(uint32_t(lane), uint32_t(A.depth) - 1u)];
     const uint32_t count = __builtin_amdgcn_readfirstlane(counts[sidx]);
+    // both in flight together (the compiler would sink the list load into
+    // the branch that uses it, after the count has arrived)
+    asm volatile("" ::"v"(pre), "s"(count));
     if (count <= uint32_t(A.depth)) {
         if (count > 0 && tc1.z != kCapEmpty)
-            raster_list_cull<kStats>(lists + sidx * A.depth, count, S, tc0, tc1, g, has_dir, best, stg,
-                                     !(kStats && A.no_early_exit), n_tri, n_cov);
+            raster_list_cull<kStats>(lst, count, S, tc0, tc1, g, has_dir, best, stg, !(kStats && A.no_early_exit),
+                                     n_tri, n_cov, pre);
     } else {
         // overflowed list: the tile gathers its own candidates
         gather_candidates(S, tc0, tc1, lane, [&](uint32_t rank, bool valid) {
