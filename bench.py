@@ -559,33 +559,27 @@ def main():
 
     # ---------------- the headline: the same steps pipelined.  Every step
     # still runs its full setup and its submit inside the timed region, but
-    # the setup of step k+1 runs on a second stream while step k renders (two
-    # setup buffers of the scene and two batches alternate), so the setup's
-    # short, latency-bound kernels fill the chip beside the binner and the
-    # rasterizer.  A step's submit waits for its own setup; a setup waits for
-    # the submit that last read its buffer.
+    # consecutive steps alternate between two streams (two setup buffers of
+    # the scene and two batches), so step k+1's setup, and the start of its
+    # submit, run beside step k's rendering: the setup's short,
+    # latency-bound kernels and the stage boundaries fill the chip.  On each
+    # stream a step's submit follows its own setup, and a setup follows the
+    # submit that last read its buffer.
     scene_b = pipeline.Scene(scene.xyz, device=dev)
     batch_b = pipeline.Batch([(scene_b, v) for v in views], fmt=fmt, mode=choice[0], bin_depth=choice[1])
     p_scenes, p_batches = [scene, scene_b], [batch, batch_b]
-    s_setup = torch.cuda.Stream(device=dev)
+    p_streams = [stream, torch.cuda.Stream(device=dev)]
 
     def pipelined(nsteps, stage=None, start=None):
-        done = [None, None]
         if start is not None:
-            s_setup.wait_event(start)
+            p_streams[1].wait_event(start)
         for k in range(nsteps):
             q = k % 2
-            with torch.cuda.stream(s_setup):
-                if done[q] is not None:
-                    s_setup.wait_event(done[q])
-                p_scenes[q].refresh(s_setup)
-                ready = torch.cuda.Event()
-                ready.record(s_setup)
-            stream.wait_event(ready)
-            p_batches[q].submit(stream, events=None if stage is None else stage[k])
-            fin = torch.cuda.Event()
-            fin.record(stream)
-            done[q] = fin
+            p_scenes[q].refresh(p_streams[q])
+            p_batches[q].submit(p_streams[q], events=None if stage is None else stage[k])
+        joined = torch.cuda.Event()
+        joined.record(p_streams[1])
+        stream.wait_event(joined)
 
     pipelined(max(2, args.warmup))
     torch.cuda.synchronize()
@@ -598,7 +592,7 @@ def main():
     t_wall = time.perf_counter()
     e_start.record(stream)
     pipelined(args.steps, stage_ev, e_start)
-    e_end.record(stream)  # after the last submit, which waited for the last setup
+    e_end.record(stream)  # after both streams' last submits
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
     step_ms = e_start.elapsed_time(e_end) / args.steps
@@ -890,8 +884,8 @@ def main():
                    "views_per_step": len(views), "triangles": int(tris.shape[1]),
                    "submit_mode": tuned["mode"], "bin_tile": tuned["tile"], "bin_depth": tuned["bin_depth"],
                    "chosen_by": "autotuner" if not args.no_tune else "fixed (--no-tune)",
-                   "step": "vsr_setup_tris + vsr_submit(all views); the setup of the next step overlaps "
-                           "this step's submit on a second stream"},
+                   "step": "vsr_setup_tris + vsr_submit(all views); consecutive steps alternate between two "
+                           "streams, so the next step's setup overlaps this step's rendering"},
         "batched_fps_with_setup": views_per_s,
         "batched_serial": serial,
         "pipelined_buffers_identical": pipelined_same,

@@ -128,10 +128,10 @@ __device__ inline void fused_super(const FusedArgs& A0, int64_t sidx) {
         }
         if (!done) {
             // every later triangle has a depth lower bound >= that of the
-            // first rank of the next group
+            // first rank of the next group, floored to its sort key
             const int64_t nb = slice_begin(A.n, s1);
             if (nb < A.n) {
-                float next_lb = S.rec[4 * nb + 3].y;
+                float next_lb = depth_key_floor(S.rec[4 * nb + 3].y);
                 uint32_t worst = wave_max_u32_dpp(has_dir ? uint32_t(best >> 32) : 0u);
                 if (next_lb > __uint_as_float(worst)) done = true;
             }

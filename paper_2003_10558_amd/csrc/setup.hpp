@@ -13,8 +13,8 @@
 //   - the smallest-circle cap of section 1.1.2 (bounding cap of the
 //     spherical triangle) and the cube-map cell of its centre at the level
 //     matching its radius.
-// Then a stable LSD radix sort orders triangles by depth lower bound (ties
-// keep id order), records are permuted into that order, and a second
+// Then a stable LSD radix sort orders triangles by depth lower bound (its
+// top 24 bits; ties keep id order), records are permuted into that order, and a second
 // stable radix sort groups them by (depth slice, cell) so that every cell's
 // list is itself nearest first.  cell_start[key] is the first entry of
 // index key `key`; face_count[s][level*6+face] counts a slice's triangles
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_setup_tris(const float* __restrict__ xy
     rec_id[4 * t + 3] = r3;
     cap_id[2 * t + 0] = c0;
     cap_id[2 * t + 1] = c1;
-    key[t] = __float_as_uint(lb);  // non-negative floats sort like their bits
+    key[t] = depth_key(lb);
     val[t] = uint32_t(t);
     bucket[t] = bkt;
 }
@@ -422,9 +422,10 @@ static hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t*
 // Permute records and caps into nearest-first order; prepare the cell sort.
 // Depth buckets: ranks are grouped into 2^bucket_shift(n) consecutive ranks
 // (at most 256 buckets).  Every record's fourth word of r3 receives the depth
-// lower bound of the first rank of its bucket, which bounds the lower bound
-// of every triangle in that bucket and in all later ones; the permutation
-// writes it with the record (read from the bucket's first source record).
+// lower bound of the first rank of its bucket, floored to its sort key
+// (depth_key_floor), which bounds the lower bound of every triangle in that
+// bucket and in all later ones; the permutation writes it with the record
+// (read from the bucket's first source record).
 __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ order_ids, int64_t n, int shift,
                                                  const float4* __restrict__ rec_id, const float4* __restrict__ cap_id,
                                                  const uint32_t* __restrict__ bucket, float4* __restrict__ rec,
@@ -438,7 +439,7 @@ __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ or
 #pragma unroll
     for (int q = 0; q < 3; ++q) rec[4 * r + q] = rec_id[4 * int64_t(id) + q];
     float4 r3 = rec_id[4 * int64_t(id) + 3];
-    r3.w = rec_id[4 * int64_t(first_id) + 3].y;
+    r3.w = depth_key_floor(rec_id[4 * int64_t(first_id) + 3].y);
     rec[4 * r + 3] = r3;
     const float4 c0 = cap_id[2 * int64_t(id) + 0], c1 = cap_id[2 * int64_t(id) + 1];
     cap[2 * r + 0] = c0;
@@ -573,7 +574,7 @@ __global__ __launch_bounds__(256) void k_setup_particles(const float* __restrict
     rec_id[4 * t + 3] = r3;
     cap_id[2 * t + 0] = c0;
     cap_id[2 * t + 1] = c1;
-    key[t] = __float_as_uint(lb);
+    key[t] = depth_key(lb);
     val[t] = uint32_t(t);
     bucket[t] = bkt;
 }
@@ -592,7 +593,7 @@ hipError_t launch_setup_common(int64_t n, void* setup, hipStream_t st, Prims pri
         prims(blocks, F4(L.rec_id_off), F4(L.cap_id_off), U(L.key_a_off), U(L.val_a_off), U(L.bucket_off));
         bool in_b = false;
         hipError_t e = radix_sort(U(L.key_a_off), U(L.val_a_off), U(L.key_b_off), U(L.val_b_off), U(L.hist_off), n,
-                                  32, &in_b, st);
+                                  kDepthKeyBits, &in_b, st);
         if (e != hipSuccess) return e;
         uint32_t* ids = in_b ? U(L.val_b_off) : U(L.val_a_off);
         // the cell sort writes into the pair not holding ids

@@ -202,6 +202,17 @@ __device__ inline float3 sub3(float3 a, float3 b) { return f3(a.x - b.x, a.y - b
 __device__ inline float3 add3(float3 a, float3 b) { return f3(a.x + b.x, a.y + b.y, a.z + b.z); }
 __device__ inline float3 scale3(float3 a, float s) { return f3(a.x * s, a.y * s, a.z * s); }
 __device__ inline float dot3(float3 a, float3 b) { return fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)); }
+// Nearest-first order: triangles are sorted by the top kDepthKeyBits bits
+// of their (non-negative) depth lower bound, whose bits order like the
+// values.  Ranks with equal keys keep id order, so a bound valid for a rank
+// and every later rank is the first rank's lower bound with the dropped low
+// bits cleared (depth_key_floor), not its lower bound itself.
+constexpr int kDepthKeyBits = 24;
+__device__ inline uint32_t depth_key(float lb) { return __float_as_uint(lb) >> (32 - kDepthKeyBits); }
+__device__ inline float depth_key_floor(float lb) {
+    return __uint_as_float(__float_as_uint(lb) & ~((1u << (32 - kDepthKeyBits)) - 1u));
+}
+
 // Unit roundoff of FP32, 2^-24: the bound on the relative error of one
 // rounded operation, in the error budgets of conservative tests.
 constexpr float kUlp = 5.9604645e-8f;
