@@ -342,34 +342,43 @@ __device__ inline void raster_quad16(const RasterArgs& A0, int64_t sidx, int w, 
 // depth-bucket order; they are compacted into LDS as above and tested with
 // the early exit taken when both pixels of every lane beat the bound.
 
-// One triangle (record r0..r3) against the lane's two pixels; the arithmetic
+// Pixels of a lane when a wave covers NP 8x8 tiles: pixel p lies in tile p.
+template <int NP>
+struct LanePix {
+    float3 g[NP];
+    bool dir[NP];
+    uint64_t best[NP];
+};
+
+// One triangle (record r0..r3) against the lane's NP pixels; the arithmetic
 // for each pixel is raster_rec's, so the images are the same bit for bit.
-// Returns the number of the two pixels it covers (for the statistics).
-__device__ inline int raster_rec2(float4 r0, float4 r1, float4 r2, float4 r3, float3 ga, float3 gb,
-                                  uint64_t& best_a, uint64_t& best_b) {
-    const float a0 = fmaf(r0.z, ga.z, fmaf(r0.y, ga.y, r0.x * ga.x));
-    const float a1 = fmaf(r1.z, ga.z, fmaf(r1.y, ga.y, r1.x * ga.x));
-    const float a2 = fmaf(r2.z, ga.z, fmaf(r2.y, ga.y, r2.x * ga.x));
-    const float b0 = fmaf(r0.z, gb.z, fmaf(r0.y, gb.y, r0.x * gb.x));
-    const float b1 = fmaf(r1.z, gb.z, fmaf(r1.y, gb.y, r1.x * gb.x));
-    const float b2 = fmaf(r2.z, gb.z, fmaf(r2.y, gb.y, r2.x * gb.x));
-    const bool in_a = fminf(a0, fminf(a1, a2)) > 0.0f, in_b = fminf(b0, fminf(b1, b2)) > 0.0f;
-    int cov = 0;
-    if (in_a || in_b) {
-        const float dna = fmaf(r2.w, ga.z, fmaf(r1.w, ga.y, r0.w * ga.x));
-        const float dnb = fmaf(r2.w, gb.z, fmaf(r1.w, gb.y, r0.w * gb.x));
+// Returns the mask of the pixels it covers (for the statistics).
+template <int NP>
+__device__ inline uint32_t raster_rec_n(float4 r0, float4 r1, float4 r2, float4 r3, LanePix<NP>& P) {
+    bool in[NP];
+    bool any = false;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const float3 g = P.g[p];
+        const float e0 = fmaf(r0.z, g.z, fmaf(r0.y, g.y, r0.x * g.x));
+        const float e1 = fmaf(r1.z, g.z, fmaf(r1.y, g.y, r1.x * g.x));
+        const float e2 = fmaf(r2.z, g.z, fmaf(r2.y, g.y, r2.x * g.x));
+        in[p] = fminf(e0, fminf(e1, e2)) > 0.0f;
+        any |= in[p];
+    }
+    uint32_t cov = 0;
+    if (any) {
         const uint64_t idk = uint64_t(__float_as_uint(r3.z));
-        if (in_a && dna > 0.0f) {
-            const float rr = r3.x * __builtin_amdgcn_rcpf(dna);
-            const uint64_t key = (uint64_t(__float_as_uint(rr)) << 32) | idk;
-            best_a = key < best_a ? key : best_a;
-            cov += 1;
-        }
-        if (in_b && dnb > 0.0f) {
-            const float rr = r3.x * __builtin_amdgcn_rcpf(dnb);
-            const uint64_t key = (uint64_t(__float_as_uint(rr)) << 32) | idk;
-            best_b = key < best_b ? key : best_b;
-            cov += 1;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const float3 g = P.g[p];
+            const float dn = fmaf(r2.w, g.z, fmaf(r1.w, g.y, r0.w * g.x));
+            if (in[p] && dn > 0.0f) {
+                const float rr = r3.x * __builtin_amdgcn_rcpf(dn);
+                const uint64_t key = (uint64_t(__float_as_uint(rr)) << 32) | idk;
+                P.best[p] = key < P.best[p] ? key : P.best[p];
+                cov |= 1u << p;
+            }
         }
     }
     return cov;
@@ -377,17 +386,19 @@ __device__ inline int raster_rec2(float4 r0, float4 r1, float4 r2, float4 r3, fl
 
 // Can a later triangle with depth lower bound lb still win a pixel of the
 // lane?  (Pixels without a direction never wait.)
-__device__ inline bool pair_open(bool dir_a, bool dir_b, uint64_t best_a, uint64_t best_b, float lb) {
-    return (dir_a && !(__uint_as_float(uint32_t(best_a >> 32)) < lb)) ||
-           (dir_b && !(__uint_as_float(uint32_t(best_b >> 32)) < lb));
+template <int NP>
+__device__ inline bool lane_open(const LanePix<NP>& P, float lb) {
+    bool open = false;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) open |= P.dir[p] && !(__uint_as_float(uint32_t(P.best[p] >> 32)) < lb);
+    return open;
 }
 
-template <bool kStats>
-__device__ inline void raster_list_cull2(const uint32_t* lst, uint32_t count, const SceneView& S, float4 ta0,
-                                         float4 ta1, float4 tb0, float4 tb1, float3 ga, float3 gb, bool dir_a,
-                                         bool dir_b, uint64_t& best_a, uint64_t& best_b, float4* stg,
-                                         bool early_exit, unsigned long long& n_tri, unsigned long long& n_cov,
-                                         uint32_t pre) {
+template <bool kStats, int NP>
+__device__ inline void raster_list_cull_n(const uint32_t* lst, uint32_t count, const SceneView& S,
+                                          const float4 (&tc0)[NP], const float4 (&tc1)[NP], LanePix<NP>& P,
+                                          float4* stg, bool early_exit, unsigned long long& n_tri,
+                                          unsigned long long& n_cov, uint32_t pre) {
     // pre: lst[lane], loaded by the caller with the count (read below it only)
     const int lane = threadIdx.x & 63;
     for (uint32_t c0 = 0; c0 < count; c0 += 64) {
@@ -396,7 +407,7 @@ __device__ inline void raster_list_cull2(const uint32_t* lst, uint32_t count, co
             // bound of its first entry, which bounds all that follow
             const uint32_t r0k = __builtin_amdgcn_readfirstlane(lst[c0]);
             const float lb0 = S.rec[4 * int64_t(r0k) + 3].w;
-            if (__ballot(pair_open(dir_a, dir_b, best_a, best_b, lb0)) == 0) break;
+            if (__ballot(lane_open(P, lb0)) == 0) break;
         }
         const bool valid = c0 + uint32_t(lane) < count;
         const uint32_t rank = c0 == 0 ? (valid ? pre : 0u) : lst[min(c0 + uint32_t(lane), count - 1u)];
@@ -405,8 +416,10 @@ __device__ inline void raster_list_cull2(const uint32_t* lst, uint32_t count, co
         const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
         const float ch = bin_cos_half(a);
         const float3 n0 = f3(r0.x, r0.y, r0.z), n1 = f3(r1.x, r1.y, r1.z), n2 = f3(r2.x, r2.y, r2.z);
-        const bool pass =
-            valid && (sub_may_see(ta0, ta1, a, ch, n0, n1, n2) || sub_may_see(tb0, tb1, a, ch, n0, n1, n2));
+        bool pass = false;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) pass |= sub_may_see(tc0[p], tc1[p], a, ch, n0, n1, n2);
+        pass = pass && valid;
         const uint64_t bal = __ballot(pass);
         const uint32_t ns = uint32_t(__popcll(bal));
         if (pass) {
@@ -424,7 +437,7 @@ __device__ inline void raster_list_cull2(const uint32_t* lst, uint32_t count, co
         for (uint32_t t8 = 0; t8 < ns; t8 += 4) {
             if (early_exit) {
                 const float lb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(stg[192 + t8].w)));
-                if (__ballot(pair_open(dir_a, dir_b, best_a, best_b, lb)) == 0) {
+                if (__ballot(lane_open(P, lb)) == 0) {
                     done = true;
                     break;
                 }
@@ -433,11 +446,11 @@ __device__ inline void raster_list_cull2(const uint32_t* lst, uint32_t count, co
             for (uint32_t u = 0; u < 4; ++u) {
                 const uint32_t t = t8 + u;
                 if (t < ns) {
-                    const int cov = raster_rec2(stg[t], stg[64 + t], stg[128 + t], stg[192 + t], ga, gb, best_a,
-                                                best_b);
+                    const uint32_t cov = raster_rec_n<NP>(stg[t], stg[64 + t], stg[128 + t], stg[192 + t], P);
                     if (kStats) {
                         n_tri += 1;
-                        n_cov += __popcll(__ballot(cov & 1)) + __popcll(__ballot(cov >> 1));
+#pragma unroll
+                        for (int p = 0; p < NP; ++p) n_cov += __popcll(__ballot((cov >> p) & 1u));
                     }
                 }
             }
@@ -469,73 +482,89 @@ __device__ inline void raster_gather_tile(const SceneView& S, float4 tc0, float4
     });
 }
 
-// Strip `half` (0 top, 1 bottom) of super-tile sidx, one wave; stg is the
-// wave's 4 KB of LDS.
-template <bool kStats>
-__device__ inline void raster_strip16(const RasterArgs& A0, int64_t sidx, int half, float4* stg) {
+// Grid kernels with 16x16 lists: each wave takes kStripTiles 8x8 tiles of a
+// super-tile (its `part`-th row for 2, all four for 4); stg is the wave's
+// 4 KB of LDS.
+constexpr int kStripTiles = 2;
+
+template <bool kStats, int NP>
+__device__ inline void raster_multi16(const RasterArgs& A0, int64_t sidx, int part, float4* stg) {
     RasterArgs A = A0;
     A.globalize();
     const int lane = threadIdx.x & 63;
-    int64_t tile_a;
-    int tx, ty;
-    if (!super_tile_of(sidx, 2 * half, A.ntx, A.nty, tile_a, tx, ty)) return;
-    const bool has_b = tx + 1 < A.ntx;
-    const int64_t tile_b = tile_a + 1;
     const float4* caps = map_caps(A.map, A.ntiles, A.fmt);
     SceneView S = scene_view(A.setup, A.n);
     const char* bb = reinterpret_cast<const char*>(A.bins);
     const uint32_t* counts = reinterpret_cast<const uint32_t*>(bb + 256);
     const uint32_t* lists = reinterpret_cast<const uint32_t*>(bb + 256 + align256(A.ntiles * 4));
-    const int ia = tx * kTile + (lane & (kTile - 1)), ib = ia + kTile, j = ty * kTile + (lane >> 3);
-    const bool in_a = ia < A.W && j < A.H, in_b = has_b && ib < A.W && j < A.H;
-    const float3 ga = load_dir(A.map, A.fmt, A.ntiles, tile_a, lane, A.rot);
-    const float3 gb = has_b ? load_dir(A.map, A.fmt, A.ntiles, tile_b, lane, A.rot) : f3(0.0f, 0.0f, 0.0f);
-    const bool dir_a = in_a && (ga.x != 0.0f || ga.y != 0.0f || ga.z != 0.0f);
-    const bool dir_b = in_b && (gb.x != 0.0f || gb.y != 0.0f || gb.z != 0.0f);
-    float4 ta0, ta1, tb0 = empty_cap0(), tb1 = empty_cap1();
-    load_tile_cap(caps, tile_a, A.rot, ta0, ta1);
-    if (has_b) load_tile_cap(caps, tile_b, A.rot, tb0, tb1);
-    uint64_t best_a = kKeyEmpty, best_b = kKeyEmpty;
+    LanePix<NP> P;
+    float4 tc0[NP], tc1[NP];
+    int64_t tile[NP];
+    int px[NP], py[NP];
+    bool inside[NP], has[NP], any_tile = false;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        int tx, ty;
+        const int q = NP == 4 ? p : 2 * part + p;  // quadrant of the super-tile
+        has[p] = super_tile_of(sidx, q, A.ntx, A.nty, tile[p], tx, ty);
+        px[p] = tx * kTile + (lane & (kTile - 1));
+        py[p] = ty * kTile + (lane >> 3);
+        inside[p] = has[p] && px[p] < A.W && py[p] < A.H;
+        P.g[p] = has[p] ? load_dir(A.map, A.fmt, A.ntiles, tile[p], lane, A.rot) : f3(0.0f, 0.0f, 0.0f);
+        P.dir[p] = inside[p] && (P.g[p].x != 0.0f || P.g[p].y != 0.0f || P.g[p].z != 0.0f);
+        P.best[p] = kKeyEmpty;
+        tc0[p] = empty_cap0();
+        tc1[p] = empty_cap1();
+        if (has[p]) load_tile_cap(caps, tile[p], A.rot, tc0[p], tc1[p]);
+        any_tile |= has[p];
+    }
+    if (!any_tile) return;
     unsigned long long n_tri = 0, n_cov = 0;
     const uint32_t* lst = lists + sidx * A.depth;
     const uint32_t pre = lst[min(uint32_t(lane), uint32_t(A.depth) - 1u)];
     const uint32_t count = __builtin_amdgcn_readfirstlane(counts[sidx]);
     asm volatile("" ::"v"(pre), "s"(count));  // in flight together
+    unsigned long long npix = 0;
+    if (kStats) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) npix += __popcll(__ballot(P.dir[p]));
+    }
     if (count <= uint32_t(A.depth)) {
-        if (count > 0 && (ta1.z != kCapEmpty || tb1.z != kCapEmpty))
-            raster_list_cull2<kStats>(lst, count, S, ta0, ta1, tb0, tb1, ga, gb, dir_a, dir_b, best_a, best_b, stg,
-                                      !(kStats && A.no_early_exit), n_tri, n_cov, pre);
+        bool live = false;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) live |= tc1[p].z != kCapEmpty;
+        if (count > 0 && live)
+            raster_list_cull_n<kStats, NP>(lst, count, S, tc0, tc1, P, stg, !(kStats && A.no_early_exit), n_tri,
+                                           n_cov, pre);
+        if (kStats && lane == 0) atomicAdd(&A.stats[0], n_tri * npix);
     } else {
-        raster_gather_tile<kStats>(S, ta0, ta1, ga, lane, best_a, n_tri, n_cov);
-        unsigned long long n_tri_b = 0;
-        raster_gather_tile<kStats>(S, tb0, tb1, gb, lane, best_b, n_tri_b, n_cov);
-        if (kStats) {
-            // each tile counts its own tests
-            const unsigned long long pa = __popcll(__ballot(dir_a)), pb = __popcll(__ballot(dir_b));
-            if (lane == 0) {
-                atomicAdd(&A.stats[0], n_tri * pa + n_tri_b * pb);
-                atomicAdd(&A.stats[2], n_tri + n_tri_b);
+        // each tile gathers and counts its own candidates
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            unsigned long long nt = 0;
+            raster_gather_tile<kStats>(S, tc0[p], tc1[p], P.g[p], lane, P.best[p], nt, n_cov);
+            if (kStats) {
+                const unsigned long long pp = __popcll(__ballot(P.dir[p]));
+                if (lane == 0) atomicAdd(&A.stats[0], nt * pp);
+                n_tri += nt;
             }
-            n_tri = 0;
         }
     }
-    const unsigned long long npix =
-        kStats ? (unsigned long long)(__popcll(__ballot(dir_a)) + __popcll(__ballot(dir_b))) : 0ull;
     if (kStats && lane == 0) {
-        atomicAdd(&A.stats[0], n_tri * npix);
+        unsigned long long ntiles = 0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) ntiles += has[p] ? 1ull : 0ull;
         atomicAdd(&A.stats[1], n_cov);
         atomicAdd(&A.stats[2], n_tri);
-        atomicAdd(&A.stats[3], has_b ? 2ull : 1ull);
+        atomicAdd(&A.stats[3], ntiles);
     }
-    if (in_a) {
-        const int64_t o = int64_t(j) * A.W + ia;
-        A.tri_id[o] = uint32_t(best_a & 0xFFFFFFFFull);
-        A.out_depth[o] = __uint_as_float(uint32_t(best_a >> 32));
-    }
-    if (in_b) {
-        const int64_t o = int64_t(j) * A.W + ib;
-        A.tri_id[o] = uint32_t(best_b & 0xFFFFFFFFull);
-        A.out_depth[o] = __uint_as_float(uint32_t(best_b >> 32));
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        if (inside[p]) {
+            const int64_t o = int64_t(py[p]) * A.W + px[p];
+            A.tri_id[o] = uint32_t(P.best[p] & 0xFFFFFFFFull);
+            A.out_depth[o] = __uint_as_float(uint32_t(P.best[p] >> 32));
+        }
     }
 }
 
@@ -546,14 +575,15 @@ template <bool kStats>
 __global__ __launch_bounds__(256) void k_raster(RasterArgs A) {
     const bool b16 = reinterpret_cast<const uint32_t*>(A.bins)[kBinHdrTile] == 16u;
     if (b16) {
-        // two super-tiles per workgroup, two waves (strips) each
+        // kStripTiles super-tiles per workgroup, 4 / kStripTiles waves each
+        constexpr int kWps = 4 / kStripTiles;
         __shared__ float4 s_stage16[4][256];
         const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
         const int64_t nsx = (A.ntx + 1) / 2, nsup = nsx * ((A.nty + 1) / 2);
-        const int64_t s = 2 * int64_t(blockIdx.x) + (w >> 1);
+        const int64_t s = kStripTiles * int64_t(blockIdx.x) + w / kWps;
         if (s >= nsup) return;
-        raster_strip16<kStats>(A, band_remap(s, nsup, max(int64_t(1), nsx * kBandPx / (2 * kTile))), w & 1,
-                               s_stage16[w]);
+        raster_multi16<kStats, kStripTiles>(A, band_remap(s, nsup, max(int64_t(1), nsx * kBandPx / (2 * kTile))),
+                                            w % kWps, s_stage16[w]);
         return;
     }
     const int64_t nwg = (A.ntiles + 3) / 4;
@@ -586,8 +616,9 @@ hipError_t launch_raster(const void* map, int32_t W, int32_t H, int32_t fmt, con
     A.stats = stats;
     A.no_early_exit = no_early_exit;
     A.rot = R;
-    // 4 tiles per workgroup (8x8 lists) or two super-tiles (16x16 lists)
-    int64_t blocks = std::max((ML.ntiles + 3) / 4, (int64_t((ML.ntx + 1) / 2) * ((ML.nty + 1) / 2) + 1) / 2);
+    // 4 tiles per workgroup (8x8 lists) or kStripTiles super-tiles (16x16 lists)
+    const int64_t nsup = int64_t((ML.ntx + 1) / 2) * ((ML.nty + 1) / 2);
+    int64_t blocks = std::max((ML.ntiles + 3) / 4, (nsup + kStripTiles - 1) / kStripTiles);
     if (stats) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(stats), int64_t(8));
         hipLaunchKernelGGL(k_raster<true>, dim3(unsigned(blocks)), dim3(256), 0, st, A);

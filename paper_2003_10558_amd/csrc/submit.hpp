@@ -261,13 +261,14 @@ __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict
     raster_tile<false>(A, t - J.tile_off, threadIdx.x & 63);
 }
 
-// 16x16 bin tiles: two super-tiles of the jobs' concatenated range per
-// workgroup, one wave per 16x8 strip
+// 16x16 bin tiles: kStripTiles super-tiles of the jobs' concatenated range
+// per workgroup, each wave on kStripTiles of a super-tile's 8x8 tiles
 __global__ __launch_bounds__(256) void k_submit_raster16(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
                                                          int32_t depth, int64_t total) {
+    constexpr int kWps = 4 / kStripTiles;
     __shared__ float4 s_stage16[4][256];
     const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    const int64_t t = 2 * xcd_remap(blockIdx.x, gridDim.x) + (w >> 1);
+    const int64_t t = kStripTiles * xcd_remap(blockIdx.x, gridDim.x) + w / kWps;
     if (t >= total) return;
     const int jb = find_job_super(T, njobs, t);
     const JobDesc& J = T[jb];
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(256) void k_submit_raster16(const JobDesc* __restri
     A.stats = nullptr;
     A.no_early_exit = 0;
     A.rot = rot_of(J.P.rot);
-    raster_strip16<false>(A, t - J.stile_off, w & 1, s_stage16[w]);
+    raster_multi16<false, kStripTiles>(A, t - J.stile_off, w % kWps, s_stage16[w]);
 }
 
 // Persistent rasterizers (VSR_SUBMIT_PERSISTENT): a grid of about as many
@@ -593,8 +594,8 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
                 hipLaunchKernelGGL(k_submit_raster_p, dim3(unsigned(wgs)), dim3(256), 0, st, table, njobs, fmt,
                                    depth, items, ctr);
         } else if (t16) {
-            hipLaunchKernelGGL(k_submit_raster16, dim3(unsigned((stiles + 1) / 2)), dim3(256), 0, st, table, njobs,
-                               fmt, depth, stiles);
+            hipLaunchKernelGGL(k_submit_raster16, dim3(unsigned((stiles + kStripTiles - 1) / kStripTiles)), dim3(256),
+                               0, st, table, njobs, fmt, depth, stiles);
         } else {
             hipLaunchKernelGGL(k_submit_raster, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, fmt,
                                depth, tiles);
