@@ -202,18 +202,17 @@ __device__ inline bool block_tile_of(int64_t b, int t, int ntx, int nty, int64_t
 
 // May a triangle meet a pixel of the super-tile with cap (s0, s1) (super-tile
 // layout)?  Same conservative tests as sub_may_see.
+// Without branches, as sub_may_see.
 __device__ inline bool quad_may_see(float4 s0, float4 s1, float4 a, float ch_t, float3 n0, float3 n1, float3 n2) {
-    if (s1.z == 0.0f) return false;  // no pixel with a direction
-    if (s1.w != 0.0f) return true;   // wide
-    if (a.w < kBinWide) {
-        float dx = s0.x - a.x, dy = s0.y - a.y, dz = s0.z - a.z;
-        float chord2 = dx * dx + dy * dy + dz * dz;
-        float sm = s0.w * ch_t + s1.y * a.w;
-        if (chord2 > 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f) return false;
-    }
-    float3 c = f3(s0.x, s0.y, s0.z);
-    float lim = -2.0f * s1.x * s1.y - 1e-6f;  // -sin(rho)
-    return !(dot3(n0, c) < lim || dot3(n1, c) < lim || dot3(n2, c) < lim);
+    const float dx = s0.x - a.x, dy = s0.y - a.y, dz = s0.z - a.z;
+    const float chord2 = dx * dx + dy * dy + dz * dz;
+    const float sm = s0.w * ch_t + s1.y * a.w;
+    const bool apart = (a.w < kBinWide) & (chord2 > 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f);
+    const float3 c = f3(s0.x, s0.y, s0.z);
+    const float lim = -2.0f * s1.x * s1.y - 1e-6f;  // -sin(rho)
+    const bool outside = (dot3(n0, c) < lim) | (dot3(n1, c) < lim) | (dot3(n2, c) < lim);
+    // s1.z == 0: no pixel with a direction; s1.w != 0: wide
+    return (s1.z != 0.0f) & ((s1.w != 0.0f) | !(apart | outside));
 }
 
 // In-place counting sort of one wave's list of cnt <= 256 ranks (global

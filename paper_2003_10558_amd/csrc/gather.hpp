@@ -180,17 +180,38 @@ __device__ inline float bin_cos_half(float4 a) { return __builtin_amdgcn_sqrtf(f
 // May a triangle (binning record a, ch_t = bin_cos_half(a), unit edge
 // normals) cover a pixel of the tile with cap (c0, c1)?  Never false for a
 // pair the rasterizer's FP32 test could cover.
+// Written without branches (every lane evaluates every test and the
+// results combine bitwise): in the binners' candidate loops, whose lanes
+// hold different triangles, the short-circuit form's exec-mask branches
+// cost 13% of the 16x16 block binner's time.
 __device__ inline bool sub_may_see(float4 c0, float4 c1, float4 a, float ch_t, float3 n0, float3 n1, float3 n2) {
+    const float dx = c0.x - a.x, dy = c0.y - a.y, dz = c0.z - a.z;
+    const float chord2 = dx * dx + dy * dy + dz * dz;
+    const float sm = c0.w * ch_t + c1.x * a.w;  // sin((rho_tile + rho_tri)/2)
+    // caps apart (not for a useless triangle cap)
+    const bool apart = (a.w < kBinWide) & (chord2 > 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f);
+    const float3 c = f3(c0.x, c0.y, c0.z);
+    const float lim = -c1.y - 1e-6f;
+    // the tile cap wholly outside one edge plane
+    const bool outside = (dot3(n0, c) < lim) | (dot3(n1, c) < lim) | (dot3(n2, c) < lim);
+    return (c1.z != kCapEmpty) & ((c1.z == kCapWide) | !(apart | outside));
+}
+
+// sub_may_see with early returns (the same decision): in the rasterizers'
+// cull, which tests each entry against one or two tiles only, skipping the
+// plane tests of lanes whose caps are apart is 4% faster.
+__device__ inline bool sub_may_see_lazy(float4 c0, float4 c1, float4 a, float ch_t, float3 n0, float3 n1,
+                                        float3 n2) {
     if (c1.z == kCapEmpty) return false;
     if (c1.z == kCapWide) return true;
     if (a.w < kBinWide) {
-        float dx = c0.x - a.x, dy = c0.y - a.y, dz = c0.z - a.z;
-        float chord2 = dx * dx + dy * dy + dz * dz;
-        float sm = c0.w * ch_t + c1.x * a.w;  // sin((rho_tile + rho_tri)/2)
+        const float dx = c0.x - a.x, dy = c0.y - a.y, dz = c0.z - a.z;
+        const float chord2 = dx * dx + dy * dy + dz * dz;
+        const float sm = c0.w * ch_t + c1.x * a.w;
         if (chord2 > 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f) return false;
     }
-    float3 c = f3(c0.x, c0.y, c0.z);
-    float lim = -c1.y - 1e-6f;
+    const float3 c = f3(c0.x, c0.y, c0.z);
+    const float lim = -c1.y - 1e-6f;
     return !(dot3(n0, c) < lim || dot3(n1, c) < lim || dot3(n2, c) < lim);
 }
 

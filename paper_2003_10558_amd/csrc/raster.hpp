@@ -219,7 +219,7 @@ __device__ inline void raster_list_cull(const uint32_t* lst, uint32_t count, con
         const float4 a = S.rcap[rank];
         const float4* rp = S.rec + 4 * int64_t(rank);
         const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2], r3 = rp[3];
-        const bool pass = valid && sub_may_see(tc0, tc1, a, bin_cos_half(a), f3(r0.x, r0.y, r0.z),
+        const bool pass = valid && sub_may_see_lazy(tc0, tc1, a, bin_cos_half(a), f3(r0.x, r0.y, r0.z),
                                                f3(r1.x, r1.y, r1.z), f3(r2.x, r2.y, r2.z));
         const uint64_t bal = __ballot(pass);
         const uint32_t ns = uint32_t(__popcll(bal));
@@ -418,7 +418,7 @@ __device__ inline void raster_list_cull_n(const uint32_t* lst, uint32_t count, c
         const float3 n0 = f3(r0.x, r0.y, r0.z), n1 = f3(r1.x, r1.y, r1.z), n2 = f3(r2.x, r2.y, r2.z);
         bool pass = false;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) pass |= sub_may_see(tc0[p], tc1[p], a, ch, n0, n1, n2);
+        for (int p = 0; p < NP; ++p) pass |= sub_may_see_lazy(tc0[p], tc1[p], a, ch, n0, n1, n2);
         pass = pass && valid;
         const uint64_t bal = __ballot(pass);
         const uint32_t ns = uint32_t(__popcll(bal));
