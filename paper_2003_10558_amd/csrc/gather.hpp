@@ -502,14 +502,12 @@ __device__ inline void gather_slices(SuperShared& sh, const SceneView& S, int s0
                 a[u] = (pos[u] != 0xFFFFFFFFu) ? S.bincap[pos[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int u = 0; u < kGatherPer; ++u) {
-                if (pos[u] == 0xFFFFFFFFu) continue;
-                bool pass = true;
-                if (!wide && a[u].w < kBinWide) {
-                    float dx = cs.x - a[u].x, dy = cs.y - a[u].y, dz = cs.z - a[u].z;
-                    float chord2 = dx * dx + dy * dy + dz * dz;
-                    float sm = sh_s * bin_cos_half(a[u]) + ch_s * a[u].w;
-                    pass = chord2 <= 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f;
-                }
+                // evaluated by every lane, combined bitwise (no branches)
+                const float dx = cs.x - a[u].x, dy = cs.y - a[u].y, dz = cs.z - a[u].z;
+                const float chord2 = dx * dx + dy * dy + dz * dz;
+                const float sm = sh_s * bin_cos_half(a[u]) + ch_s * a[u].w;
+                const bool near = chord2 <= 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f;
+                const bool pass = (pos[u] != 0xFFFFFFFFu) & (wide | !(a[u].w < kBinWide) | near);
                 if (pass) pass_list[atomicAdd(&sh.npass, 1u)] = pos[u];
             }
             __syncthreads();
