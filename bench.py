@@ -164,7 +164,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3: no CPU leg, fewer passes")
     ap.add_argument("--no-tune", action="store_true",
-                    help="headline batch with 8x8 bin tiles at --bin-depth instead of the autotuner's choice")
+                    help="headline batch with 16x16 bin tiles at depth 512 (the autotuner's usual pick on this "
+                         "workload) without timing the candidates")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
@@ -518,7 +519,8 @@ def main():
     from paper_2003_10558_amd import autotune
     tuner = autotune.Tuner(None, reps=3)
     if args.no_tune:
-        choice = (vsr.VSR_SUBMIT_BINNED, depth)
+        # what the tuner picks on the benchmark workload
+        choice = (vsr.VSR_SUBMIT_BINNED | vsr.VSR_SUBMIT_BIN_TILE16, 512)
         tuner_ms = None
     else:
         choice = tuner.choose(scene, views, fmt)
@@ -581,31 +583,41 @@ def main():
         joined.record(p_streams[1])
         stream.wait_event(joined)
 
-    pipelined(max(2, args.warmup))
-    torch.cuda.synchronize()
-    stage_ev = [[ev() for _ in range(4)] for _ in range(args.steps)]
-    for evs in stage_ev:
-        for e in evs:
-            e.record(stream)
-    e_start, e_end = ev(), ev()
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    e_start.record(stream)
-    pipelined(args.steps, stage_ev, e_start)
-    e_end.record(stream)  # after both streams' last submits
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    step_ms = e_start.elapsed_time(e_end) / args.steps
-    views_per_s = len(views) / (step_ms / 1e3)
-    stage_map_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in stage_ev]))
-    stage_bin_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in stage_ev]))
-    stage_raster_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in stage_ev]))
-    pipelined_same = all(torch.equal(a[0], b[0]) and torch.equal(a[1].view(torch.int32), b[1].view(torch.int32))
-                         for a, b in zip(batch.outputs, batch_b.outputs))
-    log(f"batched step, setup pipelined with the previous step's rendering: {step_ms:.3f} ms -> {views_per_s:.1f} "
-        f"views/s (wall {wall:.3f}s for {args.steps} steps); stages: maps {stage_map_ms:.3f} ms, binner "
-        f"{stage_bin_ms:.3f} ms, rasterizer {stage_raster_ms:.3f} ms; both buffers' images identical: "
-        f"{pipelined_same}")
+    p_stage = None
+    if args.profile:
+        # a profiled run's kernel trace is compared with the serial step's
+        # kernel times, so it holds no concurrent steps
+        step_ms, views_per_s, pipelined_same = serial["ms_per_step"], serial["views_per_s"], None
+        log("profile run: the pipelined leg is skipped")
+    else:
+        pipelined(max(2, args.warmup))
+        torch.cuda.synchronize()
+        p_ev = [[ev() for _ in range(4)] for _ in range(args.steps)]
+        for evs in p_ev:
+            for e in evs:
+                e.record(stream)
+        e_start, e_end = ev(), ev()
+        torch.cuda.synchronize()
+        t_wall = time.perf_counter()
+        e_start.record(stream)
+        pipelined(args.steps, p_ev, e_start)
+        e_end.record(stream)  # after both streams' last submits
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_wall
+        step_ms = e_start.elapsed_time(e_end) / args.steps
+        views_per_s = len(views) / (step_ms / 1e3)
+        # stage intervals on each step's stream: they include the other
+        # stream's work running beside them, so the kernel rooflines use the
+        # serial step's stage times
+        p_stage = {"maps": float(np.mean([e[0].elapsed_time(e[1]) for e in p_ev])),
+                   "binner": float(np.mean([e[1].elapsed_time(e[2]) for e in p_ev])),
+                   "rasterizer": float(np.mean([e[2].elapsed_time(e[3]) for e in p_ev]))}
+        pipelined_same = all(torch.equal(a[0], b[0]) and torch.equal(a[1].view(torch.int32), b[1].view(torch.int32))
+                             for a, b in zip(batch.outputs, batch_b.outputs))
+        log(f"batched step, steps alternating two streams: {step_ms:.3f} ms -> {views_per_s:.1f} views/s (wall "
+            f"{wall:.3f}s for {args.steps} steps); stage intervals (with the other stream's work beside them): "
+            f"maps {p_stage['maps']:.3f} ms, binner {p_stage['binner']:.3f} ms, rasterizer "
+            f"{p_stage['rasterizer']:.3f} ms; both buffers' images identical: {pipelined_same}")
     del batch_b, scene_b
     # outside the timed region: one view of the batch equals the plain path,
     # bit for bit (ids and depth), at the benchmark's own size and settings
@@ -918,6 +930,7 @@ def main():
         "measured_peaks": calib,
         "batched_equals_plain": batched_equals_plain,
         "stage_ms": {"maps": stage_map_ms, "binner": stage_bin_ms, "rasterizer": stage_raster_ms},
+        "pipelined_stage_intervals_ms": p_stage,
         "roofline_step": roofline_step,
         "roofline_resolve": roofline_resolve,
         "resolve_ms": resolve_ms,
