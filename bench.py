@@ -168,6 +168,8 @@ def main():
                          "workload) without timing the candidates")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-burst-seconds", type=float, default=3.0,
+                    help="after the serving run, the same server at 2x the rate for this long (0: skip)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -664,7 +666,7 @@ def main():
         f"the benchmark batch shares {n_lens} lens maps")
     del dbatch
     # the same step with the other bin tile size (8x8 lists, or 16x16 lists
-    # culled per tile by the rasterizer), at the 8x8 default depth or 512
+    # culled per 16x8 strip by the rasterizer), at the 8x8 default depth or 512
     other16 = tuned["tile"] == 8
     tbatch = pipeline.Batch([(scene, v) for v in views], fmt=fmt,
                             mode=vsr.VSR_SUBMIT_BINNED | (vsr.VSR_SUBMIT_BIN_TILE16 if other16 else 0),
@@ -761,6 +763,22 @@ def main():
             f"p99 {st.p99_ms:.1f} ms, mean batch {st.mean_batch:.1f}, overlapped batches {st.overlapped_batches} of "
             f"{st.batches} (at most {st.max_concurrent_batches} at once); batch sizes {st.batch_size_hist}; "
             f"queue depth at admission {st.queue_depth_hist}; queue wait (ms) {st.queue_wait_hist_ms}")
+        # the same server under a burst at 2x the rate: more requests arrive
+        # while batches run, so admission forms larger batches
+        if args.serve_burst_seconds > 0:
+            breqs = serve.make_requests(len(sc), rate_hz=2 * args.serve_rate, duration_s=args.serve_burst_seconds,
+                                        seed=synth.SERVE_ARRIVAL_SEED + 1, view_seed=synth.SERVE_ARRIVAL_SEED + 101,
+                                        resolutions=synth.SERVE_RESOLUTIONS)
+            bt = srv.run(breqs)
+            serve_stats["burst"] = {k: v for k, v in bt.as_dict().items()
+                                    if k in ("offered", "completed", "dropped", "views_per_s", "p50_ms", "p99_ms",
+                                             "queue_p50_ms", "queue_p99_ms", "batches", "mean_batch",
+                                             "batch_size_hist", "overlapped_batches", "max_concurrent_batches")}
+            serve_stats["burst"].update({"rate_hz": 2 * args.serve_rate, "duration_s": args.serve_burst_seconds})
+            log(f"serving burst: offered {bt.offered} at {2 * args.serve_rate:.0f}/s for "
+                f"{args.serve_burst_seconds}s: completed {bt.completed}, {bt.views_per_s:.1f} views/s, p50 "
+                f"{bt.p50_ms:.1f} ms, p99 {bt.p99_ms:.1f} ms, mean batch {bt.mean_batch:.1f}, batch sizes "
+                f"{bt.batch_size_hist}")
         del sc, srv
 
     # ---------------- rooflines
