@@ -349,8 +349,9 @@ int vsr_aa_raster_stats(const vsr_view* v, int32_t fmt, const void* map, const v
 int vsr_aa_wireframe(const vsr_view* v, int32_t fmt, const void* map, const void* setup, const void* wire,
                      int64_t ntri, const void* bins, int32_t bin_depth, float* coverage, uint32_t* dominant,
                      void* stream);
-/* Bytes of the side-cap buffer of ntri triangles (64 per triangle).  <0 on
- * bad input. */
+/* Bytes of the side-cap buffer of ntri triangles: 64 per triangle of caps
+ * (rounded up to 256), then 4 per triangle of scratch for vsr_setup_wire
+ * (rounded up to 256).  <0 on bad input. */
 int64_t vsr_wire_bytes(int64_t ntri);
 /* Side caps of a scene for vsr_aa_wireframe, once per scene after
  * vsr_setup_tris (again whenever the setup is redone): per triangle, in the

@@ -414,7 +414,7 @@ int vsr_aa_particles_stats(const vsr_view* v, int32_t fmt, const void* map, cons
 
 int64_t vsr_wire_bytes(int64_t ntri) {
     if (ntri < 0 || ntri > (int64_t(1) << 31)) return VSR_E_ARG;
-    return align256(ntri * 64 > 0 ? ntri * 64 : 256);
+    return wire_total_bytes(ntri);
 }
 
 int vsr_setup_wire(const void* setup, const float* xyz, int64_t ntri, void* wire, int64_t wire_bytes, void* stream) {

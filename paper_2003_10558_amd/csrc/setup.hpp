@@ -430,8 +430,8 @@ __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ or
                                                  const float4* __restrict__ rec_id, const float4* __restrict__ cap_id,
                                                  const uint32_t* __restrict__ bucket, float4* __restrict__ rec,
                                                  float4* __restrict__ cap, float4* __restrict__ rcap,
-                                                 uint32_t* __restrict__ order, uint32_t* __restrict__ rank_of,
-                                                 uint32_t* __restrict__ key2, uint32_t* __restrict__ val2) {
+                                                 uint32_t* __restrict__ order, uint32_t* __restrict__ key2,
+                                                 uint32_t* __restrict__ val2) {
     int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= n) return;
     uint32_t id = order_ids[r];
@@ -447,7 +447,6 @@ __global__ __launch_bounds__(256) void k_permute(const uint32_t* __restrict__ or
     // the binning cap (as in the cell-ordered copy), in rank order
     rcap[r] = make_float4(c0.x, c0.y, c0.z, (c1.z == kCapWide) ? kBinWide : c0.w);
     order[r] = id;
-    rank_of[id] = uint32_t(r);
     uint32_t b = bucket[id];
     key2[r] = b == uint32_t(kNumBuckets) ? uint32_t(kIndexKeys)
                                          : uint32_t(int64_t(slice_of(n, r)) * kNumBuckets + b);
@@ -601,7 +600,7 @@ hipError_t launch_setup_common(int64_t n, void* setup, hipStream_t st, Prims pri
         uint32_t* v2 = in_b ? U(L.val_a_off) : U(L.val_b_off);
         hipLaunchKernelGGL(k_permute, dim3(blocks), dim3(256), 0, st, ids, n, bucket_shift(n), F4(L.rec_id_off),
                            F4(L.cap_id_off), U(L.bucket_off), F4(L.rec_off), F4(L.cap_off), F4(L.rcap_off),
-                           U(L.order_off), U(L.rank_of_off), k2, v2);
+                           U(L.order_off), k2, v2);
         // ids are no longer needed: the other pair is free scratch
         uint32_t* k3 = in_b ? U(L.key_b_off) : U(L.key_a_off);
         uint32_t* v3 = in_b ? U(L.val_b_off) : U(L.val_a_off);

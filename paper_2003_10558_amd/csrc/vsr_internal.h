@@ -133,8 +133,8 @@ struct MapParams {
 struct SetupLayout {
     int64_t n;
     int64_t nblocks;    // radix-sort blocks
-    int64_t rec_off, cap_off, rcap_off, cell_list_off, cell_start_off, order_off, rank_of_off, bincap_off,
-        binnrm_off, face_count_off;
+    int64_t rec_off, cap_off, rcap_off, cell_list_off, cell_start_off, order_off, bincap_off, binnrm_off,
+        face_count_off;
     int64_t rec_id_off, cap_id_off, key_a_off, val_a_off, key_b_off, val_b_off, bucket_off, hist_off;
     int64_t bytes;
 };
@@ -155,7 +155,6 @@ __host__ __device__ inline SetupLayout setup_layout(int64_t n) {
     s.cell_start_off = o; o += align256((kIndexKeys + 1) * 4);
     s.face_count_off = o; o += align256(int64_t(kSlices) * 64 * 4);
     s.order_off = o;      o += align256(n * 4);
-    s.rank_of_off = o;    o += align256(n * 4);
     s.bincap_off = o;     o += align256(n * 16);
     s.binnrm_off = o;     o += align256(n * 48);
     s.rec_id_off = o;     o += align256(n * 64);

@@ -177,9 +177,18 @@ __device__ inline void wire_tile(const WireArgs& A0, int64_t tile, int lane, flo
 }
 
 // Side caps of every triangle, stored in rank order (once per scene, after
-// the setup): one thread per triangle id, so the [9][n] vertex rows are
-// read coalesced, and each thread writes its 64-byte entry at the
-// triangle's rank (one whole line).
+// the setup).  First the rank of every id is scattered into the scratch tail
+// of the wire buffer (rank_of[order[r]] = r); then one thread per triangle
+// id reads the [9][n] vertex rows coalesced and writes its 64-byte entry at
+// the triangle's rank (one whole line).  The scatter lives here rather than
+// in the setup, which runs for every frame of a changing scene and would pay
+// for it whether wire frames are drawn or not.
+__global__ __launch_bounds__(256) void k_wire_rank(const uint32_t* __restrict__ order, int64_t n,
+                                                   uint32_t* __restrict__ rank_of) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r < n) rank_of[order[r]] = uint32_t(r);
+}
+
 __global__ __launch_bounds__(256) void k_setup_wire(const uint32_t* __restrict__ rank_of,
                                                     const float* __restrict__ xyz, int64_t n,
                                                     float4* __restrict__ wire) {
@@ -198,11 +207,19 @@ __global__ __launch_bounds__(256) void k_setup_wire(const uint32_t* __restrict__
     wire[4 * rk + 3] = make_float4(b[0], b[1], b[2], __uint_as_float(uint32_t(id)));
 }
 
+// Bytes of the side caps (64 per triangle) and of the scratch tail (4 per
+// triangle) of a wire buffer.
+inline int64_t wire_caps_bytes(int64_t n) { return align256(n * 64 > 0 ? n * 64 : 256); }
+inline int64_t wire_total_bytes(int64_t n) { return wire_caps_bytes(n) + align256(n * 4 > 0 ? n * 4 : 256); }
+
 hipError_t launch_setup_wire(const void* setup, const float* xyz, int64_t n, void* wire, hipStream_t st) {
     if (n > 0) {
-        const uint32_t* rank_of =
-            reinterpret_cast<const uint32_t*>(static_cast<const char*>(setup) + setup_layout(n).rank_of_off);
-        hipLaunchKernelGGL(k_setup_wire, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, rank_of, xyz, n,
+        const uint32_t* order =
+            reinterpret_cast<const uint32_t*>(static_cast<const char*>(setup) + setup_layout(n).order_off);
+        uint32_t* rank_of = reinterpret_cast<uint32_t*>(static_cast<char*>(wire) + wire_caps_bytes(n));
+        const unsigned blocks = unsigned((n + 255) / 256);
+        hipLaunchKernelGGL(k_wire_rank, dim3(blocks), dim3(256), 0, st, order, n, rank_of);
+        hipLaunchKernelGGL(k_setup_wire, dim3(blocks), dim3(256), 0, st, rank_of, xyz, n,
                            reinterpret_cast<float4*>(wire));
     }
     return hipGetLastError();

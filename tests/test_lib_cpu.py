@@ -274,7 +274,7 @@ def test_primitive_argument_errors(vsr):
             vsr.vsr_aa_wireframe(v, 0, a["map_buf"], a["setup"], a["wire"], 10, a["bins"], a["depth"], a["cov"],
                                  a["dom"], stream=0)
         assert e.value.code == vsr.VSR_E_ARG, c
-    assert vsr.vsr_wire_bytes(1000) == 64000 and vsr.vsr_wire_bytes(0) == 256
+    assert vsr.vsr_wire_bytes(1000) == 64000 + 4096 and vsr.vsr_wire_bytes(0) == 512
     with pytest.raises(vsr.VsrError) as e:
         vsr.vsr_setup_wire(B(256, 1), B(512, 1), 1000, B(1024, 100), stream=0)
     assert e.value.code == vsr.VSR_E_SPACE
