@@ -11,7 +11,11 @@ icosphere in one binned vsr_submit (bin depth 256, automatic binner shape:
   * one view per lens matches the FP64 oracle on the stratified sample
     (every pixel of 64 random 16x16 tiles + 16,384 random pixels) under
     the parity rule (ids bit-exact outside the flagged pixels, depth within
-    1e-5 relative).
+    1e-5 relative);
+  * the configuration the autotuner picks for the benchmark (16x16 bin
+    tiles at depth 512), alone and run as the benchmark runs it (steps with
+    their setup alternating between two streams, two scene buffers), gives
+    all 64 images of the 8x8 batch bit for bit.
 """
 import sys
 
@@ -75,3 +79,40 @@ def test_batched_view_oracle_sample(batch, q):
     _say("[bench-batch] " + st.line())
     assert st.ok(), st.notes
     assert st.hits > 0.9 * st.pixels
+
+
+def _same(torch, outs_a, outs_b):
+    return [q for q, (a, b) in enumerate(zip(outs_a, outs_b))
+            if not (torch.equal(a[0], b[0]) and torch.equal(a[1].view(torch.int32), b[1].view(torch.int32)))]
+
+
+def test_tile16_batch_equals_tile8_batch(batch):
+    torch, pipeline, vsr, tris, scene, views, outs = batch
+    b16 = pipeline.Batch([(scene, v) for v in views], mode=vsr.VSR_SUBMIT_BINNED | vsr.VSR_SUBMIT_BIN_TILE16,
+                         bin_depth=512)
+    o16 = b16.submit()
+    torch.cuda.synchronize()
+    bad = _same(torch, outs, o16)
+    _say(f"[bench-batch] 16x16 tiles, depth 512: {64 - len(bad)} of 64 views identical to the 8x8 batch; "
+         f"overflowed tiles {vsr.vsr_bin_overflow(b16.workspace, True)}")
+    assert not bad, bad
+
+
+def test_two_stream_steps_equal_one_batch(batch):
+    """Steps alternating between two streams, each refreshing its own scene
+    buffer before its submit, while the other stream's step runs."""
+    torch, pipeline, vsr, tris, scene, views, outs = batch
+    mode = vsr.VSR_SUBMIT_BINNED | vsr.VSR_SUBMIT_BIN_TILE16
+    scenes = [pipeline.Scene(scene.xyz), pipeline.Scene(scene.xyz)]
+    batches = [pipeline.Batch([(s, v) for v in views], mode=mode, bin_depth=512) for s in scenes]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for k in range(6):
+        q = k % 2
+        scenes[q].refresh(streams[q])
+        batches[q].submit(streams[q])
+    torch.cuda.synchronize()
+    for q in range(2):
+        bad = _same(torch, outs, batches[q].outputs)
+        _say(f"[bench-batch] two-stream steps, buffer {q}: {64 - len(bad)} of 64 views identical")
+        assert not bad, bad

@@ -290,6 +290,34 @@ def test_early_exit_is_exact(gpu, bin_flags):
         _say(f"[early-exit] view {q}: identical with every listed triangle tested")
 
 
+def test_fragment_counts_agree_across_bin_tiles(gpu):
+    """With every listed triangle tested, the covered (pixel, triangle) pairs
+    counted by the instrumented rasterizer are a property of the frame alone:
+    8x8 lists (a wave per tile) and 16x16 lists (a wave per 16x8 strip, two
+    pixels per lane, each triangle tested on both) count the same number, over
+    every tile of the frame; the 16x16 form executes more tests per covered
+    pair, never fewer."""
+    torch, pipeline, vsr = gpu
+    scene = pipeline.Scene(synth.scene_1m())
+    view = synth.views_1080p_sweep()[1]
+    ntiles = ((view.width + 7) // 8) * ((view.height + 7) // 8)
+    got = {}
+    for name, flags, depth in (("tile8", 0, 256), ("tile16", vsr.VSR_BIN_TILE16, 512)):
+        fr = pipeline.render(scene, view, bin_depth=depth, bin_flags=flags)
+        stats = torch.zeros(8, dtype=torch.int64, device="cuda")
+        ids, dep = torch.empty_like(fr.tri_id), torch.empty_like(fr.depth)
+        vsr.vsr_raster_stats(view, 0, fr.map, scene.setup, scene.ntri, fr.bins, depth, ids, dep, stats,
+                             no_early_exit=True)
+        torch.cuda.synchronize()
+        assert torch.equal(ids, fr.tri_id) and torch.equal(dep.view(torch.int32), fr.depth.view(torch.int32))
+        got[name] = [int(x) for x in stats[:4].cpu()]
+        _say(f"[fragments] {name}: tests {got[name][0]}, covered {got[name][1]}, triangles {got[name][2]}, "
+             f"tiles {got[name][3]}")
+    assert got["tile8"][1] == got["tile16"][1] > 0
+    assert got["tile8"][3] == got["tile16"][3] == ntiles
+    assert got["tile16"][0] >= got["tile16"][1] and got["tile8"][0] >= got["tile8"][1]
+
+
 def _cone_min_depth(tris):
     """FP64 smallest ray-plane depth d / (g . N_hat) over the unit directions g
     of each triangle's vertex cone: d / cos(theta), theta the angle from the
