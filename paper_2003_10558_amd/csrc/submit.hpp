@@ -130,10 +130,23 @@ __device__ inline int find_off(const JobDesc* __restrict__ T, int njobs, int64_t
     return lo;
 }
 
+// Per-job range sizes when every job has the same tile grid (0 otherwise):
+// then a global index maps to its job by one division instead of a binary
+// search over the table, whose dependent loads open every workgroup.
+struct JobGrid {
+    int64_t tiles, stiles, blks;
+};
+
+template <int64_t JobDesc::*Off>
+__device__ inline int job_of(const JobDesc* __restrict__ T, int njobs, int64_t per_job, int64_t t) {
+    if (per_job > 0) return int(t / per_job);
+    return find_off<Off>(T, njobs, t);
+}
+
 __global__ __launch_bounds__(256) void k_submit_bin_block(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
-                                                          int32_t depth, int32_t lds_cap, uint32_t* status) {
+                                                          int32_t depth, int32_t lds_cap, uint32_t* status, JobGrid G) {
     int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    int jb = find_off<&JobDesc::blk_off>(T, njobs, t);
+    int jb = job_of<&JobDesc::blk_off>(T, njobs, G.blks, t);
     const JobDesc& J = T[jb];
     BinArgs A;
     A.map = J.map;
@@ -155,9 +168,9 @@ __global__ __launch_bounds__(256) void k_submit_bin_block(const JobDesc* __restr
 }
 
 __global__ __launch_bounds__(256) void k_submit_bin_block16(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
-                                                      int32_t depth, int32_t lds_cap, uint32_t* status) {
+                                                      int32_t depth, int32_t lds_cap, uint32_t* status, JobGrid G) {
     int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    int jb = find_off<&JobDesc::blk_off>(T, njobs, t);
+    int jb = job_of<&JobDesc::blk_off>(T, njobs, G.blks, t);
     const JobDesc& J = T[jb];
     BinArgs A;
     A.map = J.map;
@@ -179,9 +192,9 @@ __global__ __launch_bounds__(256) void k_submit_bin_block16(const JobDesc* __res
 }
 
 __global__ __launch_bounds__(256) void k_submit_bin16(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
-                                                      int32_t depth, int32_t lds_cap, uint32_t* status) {
+                                                      int32_t depth, int32_t lds_cap, uint32_t* status, JobGrid G) {
     int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    int jb = find_job_super(T, njobs, t);
+    int jb = job_of<&JobDesc::stile_off>(T, njobs, G.stiles, t);
     const JobDesc& J = T[jb];
     BinArgs A;
     A.map = J.map;
@@ -211,9 +224,9 @@ __global__ __launch_bounds__(64) void k_submit_block_caps(const JobDesc* __restr
 }
 
 __global__ __launch_bounds__(256) void k_submit_bin(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
-                                                    int32_t depth, int32_t lds_cap, uint32_t* status) {
+                                                    int32_t depth, int32_t lds_cap, uint32_t* status, JobGrid G) {
     int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    int jb = find_job_super(T, njobs, t);
+    int jb = job_of<&JobDesc::stile_off>(T, njobs, G.stiles, t);
     const JobDesc& J = T[jb];
     BinArgs A;
     A.map = J.map;
@@ -235,11 +248,11 @@ __global__ __launch_bounds__(256) void k_submit_bin(const JobDesc* __restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
-                                                       int32_t depth, int64_t total) {
+                                                       int32_t depth, int64_t total, JobGrid G) {
     int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     int64_t t = xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
     if (t >= total) return;
-    int jb = find_job(T, njobs, t);
+    int jb = job_of<&JobDesc::tile_off>(T, njobs, G.tiles, t);
     const JobDesc& J = T[jb];
     RasterArgs A;
     A.map = J.map;
@@ -264,13 +277,13 @@ __global__ __launch_bounds__(256) void k_submit_raster(const JobDesc* __restrict
 // 16x16 bin tiles: kStripTiles super-tiles of the jobs' concatenated range
 // per workgroup, each wave on kStripTiles of a super-tile's 8x8 tiles
 __global__ __launch_bounds__(256) void k_submit_raster16(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
-                                                         int32_t depth, int64_t total) {
+                                                         int32_t depth, int64_t total, JobGrid G) {
     constexpr int kWps = 4 / kStripTiles;
     __shared__ float4 s_stage16[4][256];
     const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int64_t t = kStripTiles * xcd_remap(blockIdx.x, gridDim.x) + w / kWps;
     if (t >= total) return;
-    const int jb = find_job_super(T, njobs, t);
+    const int jb = job_of<&JobDesc::stile_off>(T, njobs, G.stiles, t);
     const JobDesc& J = T[jb];
     RasterArgs A;
     A.map = J.map;
@@ -414,9 +427,9 @@ __global__ __launch_bounds__(256) void k_submit_raster16_p(const JobDesc* __rest
     }
 }
 
-__global__ __launch_bounds__(256) void k_submit_fused(const JobDesc* __restrict__ T, int njobs, int32_t fmt) {
+__global__ __launch_bounds__(256) void k_submit_fused(const JobDesc* __restrict__ T, int njobs, int32_t fmt, JobGrid G) {
     int64_t t = xcd_remap(blockIdx.x, gridDim.x);
-    int jb = find_job_super(T, njobs, t);
+    int jb = job_of<&JobDesc::stile_off>(T, njobs, G.stiles, t);
     const JobDesc& J = T[jb];
     FusedArgs A;
     A.map = J.map;
@@ -543,6 +556,14 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
     // sized here fit any table written for jobs of the same sizes
     build_table(jobs, njobs, fmt, mode, depth, ws, !table_ready, host.data(), &tiles, &stiles, &mtiles, &blks,
                 &mblks);
+    JobGrid G = {0, 0, 0};
+    bool same = true;
+    for (int32_t q = 1; q < njobs; ++q) same = same && host[q].ntx == host[0].ntx && host[q].nty == host[0].nty;
+    if (same) {
+        G.tiles = host[0].ntiles;
+        G.stiles = bin_grid(host[0].ntx, host[0].nty);
+        G.blks = blks / njobs;
+    }
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ws), int64_t(64));
     if (!table_ready) {
         // descriptors travel as kernel arguments: no host-memory copy
@@ -561,23 +582,23 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
                            mblks);
     if (ev) (void)hipEventRecord(ev[1], st);
     if (mode == VSR_SUBMIT_FUSED) {
-        hipLaunchKernelGGL(k_submit_fused, dim3(unsigned(stiles)), dim3(256), 0, st, table, njobs, fmt);
+        hipLaunchKernelGGL(k_submit_fused, dim3(unsigned(stiles)), dim3(256), 0, st, table, njobs, fmt, G);
         if (ev) (void)hipEventRecord(ev[2], st);
     } else {
         int32_t cap = bin_lds_cap(depth);
         const bool t16 = (shape & VSR_BIN_TILE16) != 0;
         if (t16 && use_blocks(cap, blks, shape, true))
             hipLaunchKernelGGL(k_submit_bin_block16, dim3(unsigned(blks)), dim3(256), size_t(4) * cap * 4, st,
-                               table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
+                               table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws), G);
         else if (t16)
             hipLaunchKernelGGL(k_submit_bin16, dim3(unsigned(stiles)), dim3(256), size_t(cap) * 4, st,
-                               table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
+                               table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws), G);
         else if (use_blocks(cap, blks, shape))
             hipLaunchKernelGGL(k_submit_bin_block, dim3(unsigned(blks)), dim3(256), 0, st,
-                               table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
+                               table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws), G);
         else
             hipLaunchKernelGGL(k_submit_bin, dim3(unsigned(stiles)), dim3(256), size_t(kSupTiles) * cap * 4, st,
-                               table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws));
+                               table, njobs, fmt, depth, cap, reinterpret_cast<uint32_t*>(ws), G);
         if (ev) (void)hipEventRecord(ev[2], st);
         if (shape & kShapePersistent) {
             // as many workgroups as are resident at once, at most one wave
@@ -595,10 +616,10 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
                                    depth, items, ctr);
         } else if (t16) {
             hipLaunchKernelGGL(k_submit_raster16, dim3(unsigned((stiles + kStripTiles - 1) / kStripTiles)), dim3(256),
-                               0, st, table, njobs, fmt, depth, stiles);
+                               0, st, table, njobs, fmt, depth, stiles, G);
         } else {
             hipLaunchKernelGGL(k_submit_raster, dim3(unsigned((tiles + 3) / 4)), dim3(256), 0, st, table, njobs, fmt,
-                               depth, tiles);
+                               depth, tiles, G);
         }
     }
     if (ev) (void)hipEventRecord(ev[3], st);
