@@ -91,30 +91,6 @@ int64_t submit_bytes(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_t mo
     return b;
 }
 
-__device__ inline int find_job(const JobDesc* __restrict__ T, int njobs, int64_t t) {
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (T[mid].tile_off <= t)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
-__device__ inline int find_job_super(const JobDesc* __restrict__ T, int njobs, int64_t t) {
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (T[mid].stile_off <= t)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
 // Last job whose range offset (member Off) is <= t.  Jobs with empty
 // ranges share the next job's offset and are never returned for t < total.
 template <int64_t JobDesc::*Off>
