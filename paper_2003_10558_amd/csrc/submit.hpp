@@ -10,8 +10,9 @@
 // The job table lives in the workspace; it is written by a small kernel whose
 // arguments carry the descriptors (no host-memory copy, so a caller may
 // capture the whole submit in a HIP graph).  Each kernel maps its global
-// tile (or super-tile) index to (job, local index) with a uniform binary
-// search over the jobs' offsets and runs the per-tile device function of the
+// tile (or super-tile) index to (job, local index), by one division when all
+// jobs share one tile grid and otherwise with a uniform binary search over
+// the jobs' offsets, and runs the per-tile device function of the
 // single-view path, so a batched job's images are bit-identical to
 // rendering that view alone.
 
