@@ -89,10 +89,11 @@ def _render(gpu, tris, view, fmt=0, depth=1024, flags=0):
     return pipeline.ids_u32(fr.tri_id), fr.depth.cpu().numpy(), vsr.vsr_bin_overflow(fr.bins)
 
 
-def test_small_full_frame(gpu):
+@pytest.mark.parametrize("flags", [0, 8], ids=["tile8", "tile16"])
+def test_small_full_frame(gpu, flags):
     view, tris = synth.view_small(), synth.scene_small()
-    _say("[raster] 256x256 full frame vs oracle")
-    ids, dep, ovf = _render(gpu, tris, view)
+    _say(f"[raster] 256x256 full frame vs oracle, bin flags {flags}")
+    ids, dep, ovf = _render(gpu, tris, view, flags=flags)
     ref = oracle.render(view, tris)
     st = compare(view, tris, ids, dep, ref)
     _say("[raster] " + st.line() + " " + "; ".join(st.notes))
@@ -176,14 +177,17 @@ RAGGED = [
 ]
 
 
+@pytest.mark.parametrize("flags", [0, 8], ids=["tile8", "tile16"])
 @pytest.mark.parametrize("w,h,aov", RAGGED)
-def test_ragged_sizes(gpu, w, h, aov):
+def test_ragged_sizes(gpu, w, h, aov, flags):
+    """Odd sizes: partial 8x8 tiles, and with 16x16 bin tiles partial strips
+    and super-tiles (a strip whose right tile lies outside the image)."""
     rng = np.random.default_rng(w * 1000 + h)
     view = synth.View(w, h, float(rng.uniform(-1, 1)), float(rng.uniform(0, 1)), float(rng.uniform(0.8, 1)),
                       float(rng.uniform(60, 360)), aov, synth.yaw_pitch_rotation(rng.uniform(0, 6), rng.uniform(-1, 1)))
     tris = synth.scene(400, w + h)
-    _say(f"[ragged] {w}x{h} aov={aov} k={view.k:.3f}")
-    ids, dep, _ = _render(gpu, tris, view)
+    _say(f"[ragged] {w}x{h} aov={aov} k={view.k:.3f} bin flags {flags}")
+    ids, dep, _ = _render(gpu, tris, view, flags=flags)
     st = compare(view, tris, ids, dep, oracle.render(view, tris))
     _say("[ragged] " + st.line())
     assert st.ok(), st.notes
@@ -192,8 +196,9 @@ def test_ragged_sizes(gpu, w, h, aov):
 def test_empty_and_degenerate(gpu):
     view = synth.View(64, 48, 0.2, 0.5, 0.9, 200.0)
     _say("[edge] empty scene")
-    ids, dep, _ = _render(gpu, np.zeros((9, 0), np.float32), view)
-    assert np.all(ids == 0xFFFFFFFF) and np.all(np.isinf(dep))
+    for flags in (0, 8):
+        ids, dep, _ = _render(gpu, np.zeros((9, 0), np.float32), view, flags=flags)
+        assert np.all(ids == 0xFFFFFFFF) and np.all(np.isinf(dep)), flags
     _say("[edge] degenerate triangles")
     t1 = [1, 0, 0, 0, 1, 0, 1, 1, 0]          # plane through O
     t2 = [1, 2, 3, 1, 2, 3, -1, 0, 2]         # two equal vertices
