@@ -61,8 +61,9 @@ __global__ void k_write_jobs(JobChunk c, JobDesc* table) {
     if (q < c.count) table[c.first + q] = c.d[q];
 }
 
-// Work counters of the persistent rasterizers, 64 bytes apart.
-constexpr int kWorkRanges = 8;
+// XCDs of the chip: workgroup b of a launch runs on XCD b mod kXcds.  The
+// persistent rasterizers keep one work counter per XCD, 64 bytes apart.
+constexpr int kXcds = 8;
 
 // Workspace: 256-byte status header (word 0: overflowed tiles), the work
 // counters, the job table, then the jobs' maps and bins.
@@ -73,7 +74,7 @@ struct WsLayout {
 static WsLayout ws_layout(int32_t njobs) {
     WsLayout w;
     w.ctr_off = 256;
-    w.table_off = w.ctr_off + int64_t(kWorkRanges) * 64;
+    w.table_off = w.ctr_off + int64_t(kXcds) * 64;
     w.data_off = w.table_off + align256(int64_t(njobs) * int64_t(sizeof(JobDesc)));
     w.bytes = w.data_off;
     return w;
@@ -286,11 +287,10 @@ __global__ __launch_bounds__(256) void k_submit_raster16(const JobDesc* __restri
 // workgroups as are resident at once; each wave takes runs of kWorkChunk
 // work items (an 8x8 tile; with 16x16 lists a (super-tile, quadrant) pair,
 // the four quadrants of a super-tile being consecutive items) from work
-// counters until none are left.  The items are split into kWorkRanges
-// contiguous ranges with a counter each; range r belongs to XCD r mod kXcds
-// (workgroup b runs on XCD b mod kXcds), and a wave visits every range once,
-// its XCD's first, so neighbouring tiles, which share triangles, meet in one
-// L2.  Within a range the items come in increasing order, so a wave finds
+// counters until none are left.  The items are split into kXcds contiguous
+// ranges with a counter each; range r belongs to XCD r, and a wave visits
+// every range once, its XCD's first, so neighbouring tiles, which share
+// triangles, meet in one L2.  Within a range the items come in increasing order, so a wave finds
 // each item's job by walking forward from the last one (a binary search
 // only after a move).  The counters sit in the workspace (zeroed by the
 // submit); the per-tile work is the grid kernels', so the images are the
@@ -298,7 +298,6 @@ __global__ __launch_bounds__(256) void k_submit_raster16(const JobDesc* __restri
 // vector memory counter covers loads and stores alike, so the first load
 // wait of each tile also waits for the previous tile's output stores, and
 // the loop needs more registers); kept as a measured alternative.
-constexpr int kXcds = 8;
 constexpr uint32_t kShapePersistent = 0x10000u;
 constexpr int kPersistentWgPerCu = 8;
 constexpr uint32_t kWorkChunk = 16;
@@ -326,15 +325,14 @@ __device__ inline int advance_job(const JobDesc* __restrict__ T, int njobs, int 
 }
 
 // Next run of up to kWorkChunk items [t, t_end) for the calling wave;
-// false when it has visited every range.  j counts the ranges visited (the
-// wave's j-th range is its XCD's, then the next XCD's, ... starting at the
-// wave's own slot k0); jb is reset on a move.
-__device__ inline bool next_items(uint32_t* __restrict__ ctr, int64_t items, int xcd, int k0, int& j, int& jb,
-                                  int64_t& t, int64_t& t_end) {
-    constexpr int kPer = kWorkRanges / kXcds;
-    const int64_t per = (items + kWorkRanges - 1) / kWorkRanges;
-    while (j < kWorkRanges) {
-        const int r = (xcd + j / kPer) % kXcds + kXcds * ((k0 + j) % kPer);
+// false when it has found every range used up.  j counts the ranges it has
+// left behind (its XCD's first, then the next XCD's, ...); jb is reset on a
+// move.
+__device__ inline bool next_items(uint32_t* __restrict__ ctr, int64_t items, int xcd, int& j, int& jb, int64_t& t,
+                                  int64_t& t_end) {
+    const int64_t per = (items + kXcds - 1) / kXcds;
+    while (j < kXcds) {
+        const int r = (xcd + j) % kXcds;
         uint32_t i = 0;
         if ((threadIdx.x & 63) == 0) i = atomicAdd(&ctr[16 * r], kWorkChunk);
         i = __builtin_amdgcn_readfirstlane(i);
@@ -374,10 +372,9 @@ __device__ inline RasterArgs submit_raster_args(const JobDesc& J, int32_t fmt, i
 __global__ __launch_bounds__(256) void k_submit_raster_p(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
                                                          int32_t depth, int64_t items, uint32_t* __restrict__ ctr) {
     const int xcd = int(blockIdx.x % kXcds);
-    const int k0 = int((blockIdx.x / kXcds) * 4 + (threadIdx.x >> 6)) % (kWorkRanges / kXcds);
     int j = 0, jb = -1;
     int64_t t0, t1;
-    while (next_items(ctr, items, xcd, k0, j, jb, t0, t1)) {
+    while (next_items(ctr, items, xcd, j, jb, t0, t1)) {
         for (int64_t t = t0; t < t1; ++t) {
             jb = advance_job<&JobDesc::tile_off>(T, njobs, jb, t);
             const JobDesc& J = T[jb];
@@ -391,10 +388,9 @@ __global__ __launch_bounds__(256) void k_submit_raster16_p(const JobDesc* __rest
     __shared__ float4 s_stage[4][256];
     const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int xcd = int(blockIdx.x % kXcds);
-    const int k0 = int((blockIdx.x / kXcds) * 4 + (threadIdx.x >> 6)) % (kWorkRanges / kXcds);
     int j = 0, jb = -1;
     int64_t t0, t1;
-    while (next_items(ctr, items, xcd, k0, j, jb, t0, t1)) {
+    while (next_items(ctr, items, xcd, j, jb, t0, t1)) {
         for (int64_t t = t0; t < t1; ++t) {
             const int64_t sidx = t >> 2;
             jb = advance_job<&JobDesc::stile_off>(T, njobs, jb, sidx);
@@ -583,8 +579,8 @@ hipError_t launch_submit(const vsr_job* jobs, int32_t njobs, int32_t fmt, int32_
             const int64_t items = t16 ? 4 * stiles : tiles;
             const int64_t wgs = std::min(int64_t(device_cus()) * kPersistentWgPerCu, (items + 3) / 4);
             uint32_t* ctr = reinterpret_cast<uint32_t*>(base + W.ctr_off);
-            hipLaunchKernelGGL(k_zero_u32, dim3(unsigned(kWorkRanges * 16 / 64)), dim3(64), 0, st, ctr,
-                               int64_t(kWorkRanges) * 16);
+            hipLaunchKernelGGL(k_zero_u32, dim3(unsigned(kXcds * 16 / 64)), dim3(64), 0, st, ctr,
+                               int64_t(kXcds) * 16);
             if (t16)
                 hipLaunchKernelGGL(k_submit_raster16_p, dim3(unsigned(wgs)), dim3(256), 0, st, table, njobs, fmt,
                                    depth, items, ctr);
