@@ -882,7 +882,9 @@ def main():
         oracle.build(force=False)
         v = views[1]
         cores = os.cpu_count() or 1
-        probe = synth.pixel_sample(v.width, v.height, seed=7, n_tiles=0, n_pixels=64)
+        # a probe long enough that thread start-up does not inflate the
+        # per-pixel time the sample is sized from
+        probe = synth.pixel_sample(v.width, v.height, seed=7, n_tiles=0, n_pixels=512)
         t0 = time.perf_counter()
         oracle.render(v, tris, probe, threads=cores)
         t_probe = time.perf_counter() - t0
