@@ -355,19 +355,28 @@ struct LanePix {
 // One triangle (record r0..r3) against the lane's NP pixels; the arithmetic
 // for each pixel is raster_rec's, so the images are the same bit for bit.
 // Returns the mask of the pixels it covers (for the statistics).
+// Only the tiles whose bit is set in the wave-uniform mask `live` are
+// tested: the others are done (every pixel already beats the depth bound of
+// the current group, which bounds this triangle).
 template <int NP>
-__device__ inline uint32_t raster_rec_n(float4 r0, float4 r1, float4 r2, float4 r3, LanePix<NP>& P) {
-    bool in[NP];
-    bool any = false;
+__device__ inline uint32_t raster_rec_n(float4 r0, float4 r1, float4 r2, float4 r3, LanePix<NP>& P, uint32_t live) {
+    // smallest edge value per pixel (-1: not tested), kept as values rather
+    // than flags so that a skipped tile costs one move
+    float em[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        const float3 g = P.g[p];
-        const float e0 = fmaf(r0.z, g.z, fmaf(r0.y, g.y, r0.x * g.x));
-        const float e1 = fmaf(r1.z, g.z, fmaf(r1.y, g.y, r1.x * g.x));
-        const float e2 = fmaf(r2.z, g.z, fmaf(r2.y, g.y, r2.x * g.x));
-        in[p] = fminf(e0, fminf(e1, e2)) > 0.0f;
-        any |= in[p];
+        em[p] = -1.0f;
+        if (live & (1u << p)) {
+            const float3 g = P.g[p];
+            const float e0 = fmaf(r0.z, g.z, fmaf(r0.y, g.y, r0.x * g.x));
+            const float e1 = fmaf(r1.z, g.z, fmaf(r1.y, g.y, r1.x * g.x));
+            const float e2 = fmaf(r2.z, g.z, fmaf(r2.y, g.y, r2.x * g.x));
+            em[p] = fminf(e0, fminf(e1, e2));
+        }
     }
+    bool any = false;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) any |= em[p] > 0.0f;
     uint32_t cov = 0;
     if (any) {
         const uint64_t idk = uint64_t(__float_as_uint(r3.z));
@@ -375,7 +384,7 @@ __device__ inline uint32_t raster_rec_n(float4 r0, float4 r1, float4 r2, float4 
         for (int p = 0; p < NP; ++p) {
             const float3 g = P.g[p];
             const float dn = fmaf(r2.w, g.z, fmaf(r1.w, g.y, r0.w * g.x));
-            if (in[p] && dn > 0.0f) {
+            if ((em[p] > 0.0f) & (dn > 0.0f)) {
                 const float rr = r3.x * __builtin_amdgcn_rcpf(dn);
                 const uint64_t key = (uint64_t(__float_as_uint(rr)) << 32) | idk;
                 P.best[p] = key < P.best[p] ? key : P.best[p];
@@ -437,9 +446,15 @@ __device__ inline void raster_list_cull_n(const uint32_t* lst, uint32_t count, c
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         bool done = false;
         for (uint32_t t8 = 0; t8 < ns; t8 += 4) {
+            // tiles whose pixels may still change (all without the exit)
+            uint32_t live = (1u << NP) - 1u;
             if (early_exit) {
                 const float lb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(stg[192 + t8].w)));
-                if (__ballot(lane_open(P, lb)) == 0) {
+                live = 0;
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    live |= __ballot(P.dir[p] && !(__uint_as_float(uint32_t(P.best[p] >> 32)) < lb)) ? 1u << p : 0u;
+                if (live == 0) {
                     done = true;
                     break;
                 }
@@ -448,7 +463,8 @@ __device__ inline void raster_list_cull_n(const uint32_t* lst, uint32_t count, c
             for (uint32_t u = 0; u < 4; ++u) {
                 const uint32_t t = t8 + u;
                 if (t < ns) {
-                    const uint32_t cov = raster_rec_n<NP>(stg[t], stg[64 + t], stg[128 + t], stg[192 + t], P);
+                    const uint32_t cov =
+                        raster_rec_n<NP>(stg[t], stg[64 + t], stg[128 + t], stg[192 + t], P, live);
                     if (kStats) {
                         n_tri += 1;
 #pragma unroll
