@@ -210,7 +210,8 @@ __device__ inline bool quad_may_see(float4 s0, float4 s1, float4 a, float ch_t, 
     const bool apart = (a.w < kBinWide) & (chord2 > 4.0f * sm * sm * (1.0f + 1e-6f) + 1e-12f);
     const float3 c = f3(s0.x, s0.y, s0.z);
     const float lim = -2.0f * s1.x * s1.y - 1e-6f;  // -sin(rho)
-    const bool outside = (dot3(n0, c) < lim) | (dot3(n1, c) < lim) | (dot3(n2, c) < lim);
+    const float d0 = dot3(n0, c), d1 = dot3(n1, c), d2 = dot3(n2, c);
+    const bool outside = (d0 < lim) | (d1 < lim) | (d2 < lim);
     // s1.z == 0: no pixel with a direction; s1.w != 0: wide
     return (s1.z != 0.0f) & ((s1.w != 0.0f) | !(apart | outside));
 }

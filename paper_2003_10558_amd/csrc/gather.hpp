@@ -193,7 +193,8 @@ __device__ inline bool sub_may_see(float4 c0, float4 c1, float4 a, float ch_t, f
     const float3 c = f3(c0.x, c0.y, c0.z);
     const float lim = -c1.y - 1e-6f;
     // the tile cap wholly outside one edge plane
-    const bool outside = (dot3(n0, c) < lim) | (dot3(n1, c) < lim) | (dot3(n2, c) < lim);
+    const float d0 = dot3(n0, c), d1 = dot3(n1, c), d2 = dot3(n2, c);
+    const bool outside = (d0 < lim) | (d1 < lim) | (d2 < lim);
     return (c1.z != kCapEmpty) & ((c1.z == kCapWide) | !(apart | outside));
 }
 
