@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void k_submit_bin_block(const JobDesc* __restr
     bin_block(A, t - J.blk_off);
 }
 
-__global__ __launch_bounds__(256) void k_submit_bin_block16(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
+__global__ __launch_bounds__(256) VSR_BLOCK16_WAVES void k_submit_bin_block16(const JobDesc* __restrict__ T, int njobs, int32_t fmt,
                                                       int32_t depth, int32_t lds_cap, uint32_t* status, JobGrid G) {
     int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     int jb = job_of<&JobDesc::blk_off>(T, njobs, G.blks, t);
