@@ -473,7 +473,7 @@ def main():
     roofline_particles = {"bound": "alu", "achieved": OPS_PER_PARTICLE_FRAGMENT * part_frags / t_p / 1e12,
                           "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "T lane-ops/s",
                           "frac": OPS_PER_PARTICLE_FRAGMENT * part_frags / t_p / PEAK_VALU_LANE_OPS,
-                          "traffic": traffic_from_profiles("k_aa_raster<false, 1>"), "kernel": "k_aa_raster (particles)",
+                          "traffic": traffic_from_profiles("k_aa_raster<false,1>"), "kernel": "k_aa_raster (particles)",
                           "kernel_ms": t_p * 1e3, "fragments_per_launch": part_frags,
                           "ops_per_fragment": OPS_PER_PARTICLE_FRAGMENT}
     log(f"particles 1080p x 10^6: setup {np.mean(p_setup):.3f} ms, map {np.mean(p_map):.3f} ms, bin "
@@ -852,7 +852,7 @@ def main():
     achieved_aa = OPS_PER_AA_FRAGMENT * F_aa_mean / t_aa
     roofline_aa = {"bound": "alu", "achieved": achieved_aa / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12,
                    "unit": "T lane-ops/s", "frac": achieved_aa / PEAK_VALU_LANE_OPS,
-                   "traffic": traffic_from_profiles("k_aa_raster<false>"), "kernel": "k_aa_raster",
+                   "traffic": traffic_from_profiles("k_aa_raster<false,0>"), "kernel": "k_aa_raster",
                    "kernel_ms": t_aa * 1e3, "fragments_per_launch": F_aa_mean,
                    "ops_per_fragment": OPS_PER_AA_FRAGMENT}
     # the whole batched step (setup included) per view: covered-fragment

@@ -85,3 +85,18 @@ def test_summary_and_traffic(tmp_path, capsys, monkeypatch):
     assert bench.traffic_from_profiles("k_bin") is None
     os.remove(prof / "traffic_1080p_1m.txt")
     assert bench.traffic_from_profiles("k_bin") is None
+
+
+def test_roofline_kernels_are_named_as_profiled():
+    """Every kernel whose traffic the bench looks up by a literal name, and
+    the benchmark batch's binner and rasterizer, are spelled as the committed
+    traffic summary spells them (template arguments without spaces), so a
+    roofline's traffic is null only when the profile is stale."""
+    import re
+    src = open(os.path.join(os.path.dirname(bench.__file__), "bench.py")).read()
+    asked = set(re.findall(r'traffic_from_profiles\("([^"]+)"', src))
+    asked |= {"k_submit_bin_block16", "k_submit_raster16"}
+    path = os.path.join(bench.PROFILES, "traffic_1080p_1m.txt")
+    rows = {ln.split()[1] for ln in open(path) if ln.startswith("kernel ")}
+    missing = sorted(k for k in asked if "vsr::" + k not in rows)
+    assert asked and not missing, missing
