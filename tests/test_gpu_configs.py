@@ -1,12 +1,13 @@
 """GPU parity at the full sizes of the dense workloads.
 
 * 3840x2160 view (k=0.32, l=0.62, s=0.86, 270 deg) of 4,000,000 shell
-  triangles + radius-10 icosphere: FP32 map sampled parity, and the
+  triangles + radius-10 icosphere: FP32 map parity on the stratified sample
+  (every pixel of 64 random 16x16 tiles + 16,384 random pixels), and the
   octahedral 2xfp16 map tier with its angular error and coverage-mismatch
   fraction against the FP64 oracle (reported, bounded).
 * 64 views of mixed resolution and random parameters of a 500,000-triangle
   shell scene in one batched submit: every view identical to rendering it
-  alone, sampled parity against the oracle on several views.
+  alone, parity against the oracle on the stratified sample of four views.
 """
 import sys
 
@@ -63,7 +64,8 @@ def test_4k_4m_fp32_sampled(gpu, scene_4m):
     torch.cuda.synchronize()
     _say(f"[4k] fused render {t0.elapsed_time(t1):.2f} ms")
     ids, dep = pipeline.ids_u32(fr.tri_id), fr.depth.cpu().numpy()
-    pix = synth.pixel_sample(view.width, view.height, seed=300, n_tiles=4, n_pixels=1024)
+    pix = synth.pixel_sample(view.width, view.height, seed=300)
+    _say(f"[4k] oracle on {len(pix)} sampled pixels x {tris.shape[1]} triangles")
     ref = oracle.render(view, tris, pix)
     st = compare(view, tris, ids, dep, ref, pix)
     _say("[4k] " + st.line() + " " + "; ".join(st.notes))
@@ -141,10 +143,10 @@ def test_batched_64_views_500k(gpu, tmp_path):
         torch.cuda.synchronize()
         assert np.array_equal(pipeline.ids_u32(outs[q][0]), pipeline.ids_u32(fr.tri_id)), q
         assert np.array_equal(outs[q][1].cpu().numpy().view(np.uint32), fr.depth.cpu().numpy().view(np.uint32)), q
-    # oracle parity on sampled pixels of four views
+    # oracle parity on the stratified sample of four views
     for q in (1, 8, 33, 63):
         v = views[q]
-        pix = synth.pixel_sample(v.width, v.height, seed=400 + q, n_tiles=2, n_pixels=512)
+        pix = synth.pixel_sample(v.width, v.height, seed=400 + q)
         ref = oracle.render(v, tris, pix)
         st = compare(v, tris, pipeline.ids_u32(outs[q][0]), outs[q][1].cpu().numpy(), ref, pix)
         _say(f"[batch64] view {q} {v.width}x{v.height} k={v.k:.2f} om={v.omega_deg:.0f}: " + st.line())
