@@ -523,14 +523,15 @@ def test_oct16_tier_small(gpu):
 
 @pytest.mark.parametrize("q", [0, 1, 2, 3])
 def test_1080p_1m_sampled(gpu, q):
-    """1920x1080 view of 1M small triangles + radius-100 icosphere, sampled
-    pixels (64 random 16x16 tiles + random pixels) against the oracle."""
+    """1920x1080 view of 1M small triangles + radius-100 icosphere on the
+    stratified sample (every pixel of 64 random 16x16 tiles + 16,384 random
+    pixels) against the oracle."""
     torch, pipeline, vsr = gpu
     view = synth.views_1080p_sweep()[q]
     tris = _scene_1m()
     _say(f"[1080p] k={view.k} omega={view.omega_deg}")
     ids, dep, ovf = _render(gpu, tris, view)
-    pix = synth.pixel_sample(view.width, view.height, seed=100 + q, n_tiles=8, n_pixels=2048)
+    pix = synth.pixel_sample(view.width, view.height, seed=100 + q)
     ref = oracle.render(view, tris, pix)
     st = compare(view, tris, ids, dep, ref, pix)
     _say(f"[1080p] k={view.k}: " + st.line() + f" overflow={ovf} " + "; ".join(st.notes))
